@@ -1,0 +1,367 @@
+"""Oracle: Dey--Mittra cut fractions (TEST INFRASTRUCTURE ONLY).
+
+Definitions followed
+--------------------
+* Sec. 2 (discussion after eq. farInt): when a face or edge is cut by the
+  perfect conductor, its area / length is replaced by the portion lying
+  *outside* the conductor; the diagonal matrices of eq. discWaveBDM hold
+  these portions divided by the vacuum area h^2 / length h.
+* Sec. 5.1 (text after eq. divBInt, eq. divBDM): the cell volume fraction is
+  the volume of the cell outside the conductor divided by h^3.
+
+Conventions (this project's readings, stated once):
+* cell (i,j,k) is [ih,(i+1)h] x [jh,(j+1)h] x [kh,(k+1)h]; the domain box
+  [0,Nx h] x [0,Ny h] x [0,Nz h] is bounded by perfectly conducting walls;
+  a face or edge lying in a wall has fraction 0;
+* the cavity interior Omega is open and the conductor closed, so a face that
+  only touches Omega along a curve has area fraction 0;
+* a computed fraction below ZERO_FRACTION (1e-12, far below any fraction
+  a resolved boundary produces and above the rounding error of the area and
+  volume formulas, ~1e-13) is rounding noise of a tangency and is set to 0.
+
+Array layout: numpy arrays indexed [k, j, i] (x fastest), shapes
+    ax (Nz, Ny, Nx+1)   ay (Nz, Ny+1, Nx)   az (Nz+1, Ny, Nx)
+    lx (Nz+1, Ny+1, Nx) ly (Nz+1, Ny, Nx+1) lz (Nz, Ny+1, Nx+1)
+    v  (Nz, Ny, Nx)
+
+Every routine here is the plain definition: the area of a rectangle inside a
+disk is the integral of the chord length (integrated piece by piece with the
+antiderivative of sqrt(rho^2 - t^2)), a volume is the integral of the
+cross-section area (SciPy adaptive quadrature with the kinks as
+breakpoints).  Pinned in tests against: measure sums (plane sums of areas
+equal the disk area, line sums of lengths equal the chord, the volume sum
+equals the ball volume), direct 2-D / 3-D SciPy quadrature of the
+indicator on individual faces and cells, the octahedral symmetry of a
+node-centred sphere, and the component counts and smallest area fraction
+printed in the paper's sphere benchmark (Sec. 6.1, Table tab:invPerf).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+from scipy import integrate
+
+# ---------------------------------------------------------------------------
+# 1-D / 2-D primitives (unit-free)
+# ---------------------------------------------------------------------------
+
+
+def _arc_primitive(t: float, rho: float) -> float:
+    """Antiderivative of sqrt(rho^2 - t^2) on [-rho, rho]."""
+    t = min(max(t, -rho), rho)
+    return 0.5 * (t * math.sqrt(max(rho * rho - t * t, 0.0))
+                  + rho * rho * math.asin(t / rho))
+
+
+def disk_rect_area(rho: float, y0: float, y1: float, z0: float, z1: float) -> float:
+    """Area of {(y,z) in [y0,y1]x[z0,z1] : y^2 + z^2 < rho^2}.
+
+    Written as the integral over y of the chord length
+    |[z0,z1] intersect (-s(y), s(y))|, s(y) = sqrt(rho^2 - y^2).  Between
+    the breakpoints (y = +-rho and the y where s(y) = |z0| or |z1|) each end
+    of the chord is either a rectangle side or the circle, so each piece is
+    integrated exactly.
+    """
+    if rho <= 0.0:
+        return 0.0
+    lo, hi = max(y0, -rho), min(y1, rho)
+    if hi <= lo:
+        return 0.0
+    cuts = {lo, hi}
+    for z in (z0, z1):
+        if abs(z) < rho:
+            w = math.sqrt(rho * rho - z * z)
+            for c in (-w, w):
+                if lo < c < hi:
+                    cuts.add(c)
+    pts = sorted(cuts)
+    total = 0.0
+    for a, b in zip(pts[:-1], pts[1:]):
+        m = 0.5 * (a + b)
+        s = math.sqrt(max(rho * rho - m * m, 0.0))
+        top_arc = s < z1
+        bot_arc = -s > z0
+        top = s if top_arc else z1
+        bot = -s if bot_arc else z0
+        if top <= bot:
+            continue
+        arc = _arc_primitive(b, rho) - _arc_primitive(a, rho)
+        upper = arc if top_arc else z1 * (b - a)
+        lower = -arc if bot_arc else z0 * (b - a)
+        total += upper - lower
+    return total
+
+
+def interval_overlap(a0: float, a1: float, b0: float, b1: float) -> float:
+    """Length of [a0,a1] intersect (b0,b1)."""
+    return max(0.0, min(a1, b1) - max(a0, b0))
+
+
+# ---------------------------------------------------------------------------
+# Geometries.  Each offers, in physical units:
+#   edge_len(axis, lo, hi, p)       length of {p + t e_axis, t in [lo,hi]} in Omega
+#   face_area(axis, c, lo2, hi2)    area of the axis-normal face at coordinate c
+#                                   over the rectangle lo2..hi2 (other two axes
+#                                   in increasing order)
+#   cell_vol(lo3, hi3)              volume of the box in Omega
+#   classify(lo3, hi3)              1 box inside Omega, 0 disjoint, -1 cut
+# ---------------------------------------------------------------------------
+
+_OTHER = {0: (1, 2), 1: (0, 2), 2: (0, 1)}
+
+ZERO_FRACTION = 1e-12
+
+
+def _clean(x: float) -> float:
+    return x if x >= ZERO_FRACTION else 0.0
+
+
+@dataclass
+class Box:
+    """The whole domain box is the cavity (only the walls conduct)."""
+
+    def classify(self, lo, hi):
+        return 1
+
+    def edge_len(self, axis, lo, hi, p):
+        return hi - lo
+
+    def face_area(self, axis, c, lo2, hi2):
+        return (hi2[0] - lo2[0]) * (hi2[1] - lo2[1])
+
+    def cell_vol(self, lo3, hi3):
+        return float(np.prod(np.subtract(hi3, lo3)))
+
+
+@dataclass
+class Ellipsoid:
+    """Open axis-aligned ellipsoid sum(((x_a - c_a)/s_a)^2) < 1.
+
+    A sphere is the case s_x = s_y = s_z = R.  Each quantity is computed in
+    the scaled coordinates u_a = (x_a - c_a)/s_a, where Omega is the unit
+    ball, and mapped back with the Jacobian of the scaling.
+    """
+
+    center: tuple
+    semi: tuple
+
+    def _u(self, a, x):
+        return (x - self.center[a]) / self.semi[a]
+
+    def classify(self, lo, hi):
+        ulo = [self._u(a, lo[a]) for a in range(3)]
+        uhi = [self._u(a, hi[a]) for a in range(3)]
+        far = sum(max(abs(ulo[a]), abs(uhi[a])) ** 2 for a in range(3))
+        if far < 1.0:
+            return 1
+        near = 0.0
+        for a in range(3):
+            if ulo[a] > 0.0:
+                near += ulo[a] ** 2
+            elif uhi[a] < 0.0:
+                near += uhi[a] ** 2
+        if near >= 1.0:
+            return 0
+        return -1
+
+    def edge_len(self, axis, lo, hi, p):
+        d2 = sum(self._u(a, p[a]) ** 2 for a in range(3) if a != axis)
+        if d2 >= 1.0:
+            return 0.0
+        s = math.sqrt(1.0 - d2) * self.semi[axis]
+        c = self.center[axis]
+        return interval_overlap(lo, hi, c - s, c + s)
+
+    def _section_area_u(self, axis, uc, ulo2, uhi2):
+        rho2 = 1.0 - uc * uc
+        if rho2 <= 0.0:
+            return 0.0
+        return disk_rect_area(math.sqrt(rho2), ulo2[0], uhi2[0], ulo2[1], uhi2[1])
+
+    def face_area(self, axis, c, lo2, hi2):
+        b, d = _OTHER[axis]
+        ulo2 = (self._u(b, lo2[0]), self._u(d, lo2[1]))
+        uhi2 = (self._u(b, hi2[0]), self._u(d, hi2[1]))
+        return (self._section_area_u(axis, self._u(axis, c), ulo2, uhi2)
+                * self.semi[b] * self.semi[d])
+
+    def cell_vol(self, lo3, hi3):
+        ulo = [self._u(a, lo3[a]) for a in range(3)]
+        uhi = [self._u(a, hi3[a]) for a in range(3)]
+        # kinks of the x-section area: where the section radius
+        # rho(ux) = sqrt(1-ux^2) equals a distance to a side line or corner
+        dists = [abs(ulo[1]), abs(uhi[1]), abs(ulo[2]), abs(uhi[2])]
+        dists += [math.hypot(y, z) for y in (ulo[1], uhi[1]) for z in (ulo[2], uhi[2])]
+        dists.append(0.0)
+        pts = set()
+        for d in dists:
+            if d < 1.0:
+                r = math.sqrt(1.0 - d * d)
+                for q in (-r, r):
+                    if ulo[0] < q < uhi[0]:
+                        pts.add(q)
+
+        def area(ux):
+            return self._section_area_u(0, ux, (ulo[1], ulo[2]), (uhi[1], uhi[2]))
+
+        val, _ = integrate.quad(area, ulo[0], uhi[0], points=sorted(pts) or None,
+                                epsabs=1e-17, epsrel=1e-13, limit=400)
+        return val * self.semi[0] * self.semi[1] * self.semi[2]
+
+
+def sphere(center=(0.5, 0.5, 0.5), radius=0.45) -> Ellipsoid:
+    return Ellipsoid(tuple(center), (radius, radius, radius))
+
+
+# ---------------------------------------------------------------------------
+# Fraction arrays on the Yee grid
+# ---------------------------------------------------------------------------
+
+FACE_SHAPES = {
+    "ax": lambda n: (n[2], n[1], n[0] + 1),
+    "ay": lambda n: (n[2], n[1] + 1, n[0]),
+    "az": lambda n: (n[2] + 1, n[1], n[0]),
+}
+EDGE_SHAPES = {
+    "lx": lambda n: (n[2] + 1, n[1] + 1, n[0]),
+    "ly": lambda n: (n[2] + 1, n[1], n[0] + 1),
+    "lz": lambda n: (n[2], n[1] + 1, n[0] + 1),
+}
+
+
+def face_fraction(geom, n, h, axis, i, j, k) -> float:
+    """Area fraction of the axis-normal face with low corner node (i,j,k)."""
+    idx = (i, j, k)
+    if idx[axis] == 0 or idx[axis] == n[axis]:
+        return 0.0  # face lies in a conducting wall of the domain
+    b, d = _OTHER[axis]
+    c = idx[axis] * h
+    lo2 = (idx[b] * h, idx[d] * h)
+    hi2 = ((idx[b] + 1) * h, (idx[d] + 1) * h)
+    lo3 = [x * h for x in idx]
+    hi3 = list(lo3)
+    hi3[b] += h
+    hi3[d] += h
+    cls = geom.classify(lo3, hi3)
+    if cls == 1:
+        return 1.0
+    if cls == 0:
+        return 0.0
+    return _clean(geom.face_area(axis, c, lo2, hi2) / (h * h))
+
+
+def edge_fraction(geom, n, h, axis, i, j, k) -> float:
+    """Length fraction of the axis-directed edge starting at node (i,j,k)."""
+    idx = (i, j, k)
+    for a in _OTHER[axis]:
+        if idx[a] == 0 or idx[a] == n[a]:
+            return 0.0  # edge lies in a conducting wall of the domain
+    p = [x * h for x in idx]
+    lo = idx[axis] * h
+    return _clean(geom.edge_len(axis, lo, lo + h, p) / h)
+
+
+def cell_fraction(geom, n, h, i, j, k) -> float:
+    lo3 = [i * h, j * h, k * h]
+    hi3 = [(i + 1) * h, (j + 1) * h, (k + 1) * h]
+    cls = geom.classify(lo3, hi3)
+    if cls == 1:
+        return 1.0
+    if cls == 0:
+        return 0.0
+    return _clean(geom.cell_vol(lo3, hi3) / h ** 3)
+
+
+def _classify_all(geom, lo, hi):
+    """Vectorised ``classify`` over arrays of boxes (lo, hi: (m, 3))."""
+    if isinstance(geom, Box):
+        return np.ones(lo.shape[0], dtype=int)
+    if isinstance(geom, Ellipsoid):
+        c = np.asarray(geom.center)
+        s = np.asarray(geom.semi)
+        ulo = (lo - c) / s
+        uhi = (hi - c) / s
+        far = np.sum(np.maximum(abs(ulo), abs(uhi)) ** 2, axis=1)
+        near = np.sum(np.where(ulo > 0, ulo, np.where(uhi < 0, uhi, 0.0)) ** 2, axis=1)
+        return np.where(far < 1.0, 1, np.where(near >= 1.0, 0, -1))
+    return np.array([geom.classify(a, b) for a, b in zip(lo, hi)])
+
+
+def _family(shape):
+    k, j, i = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]),
+                          np.arange(shape[2]), indexing="ij")
+    return np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)
+
+
+def face_fractions(geom, n, h, axis) -> np.ndarray:
+    """Area fractions of all axis-normal faces (array [k, j, i])."""
+    n = tuple(int(x) for x in n)
+    shape = FACE_SHAPES[("ax", "ay", "az")[axis]](n)
+    idx = _family(shape)
+    b, d = _OTHER[axis]
+    lo = idx * h
+    hi = lo.copy()
+    hi[:, b] += h
+    hi[:, d] += h
+    cls = _classify_all(geom, lo.astype(float), hi.astype(float)).astype(float)
+    wall = (idx[:, axis] == 0) | (idx[:, axis] == n[axis])
+    cls[wall] = 0.0
+    out = cls.copy()
+    for m in np.flatnonzero(cls < 0):
+        i, j, k = (int(x) for x in idx[m])
+        out[m] = face_fraction(geom, n, h, axis, i, j, k)
+    return out.reshape(shape)
+
+
+def edge_fractions(geom, n, h, axis) -> np.ndarray:
+    n = tuple(int(x) for x in n)
+    shape = EDGE_SHAPES[("lx", "ly", "lz")[axis]](n)
+    out = np.zeros(shape)
+    for (k, j, i), _ in np.ndenumerate(out):
+        out[k, j, i] = edge_fraction(geom, n, h, axis, i, j, k)
+    return out
+
+
+def cell_fractions(geom, n, h) -> np.ndarray:
+    n = tuple(int(x) for x in n)
+    shape = (n[2], n[1], n[0])
+    idx = _family(shape)
+    lo = (idx * h).astype(float)
+    cls = _classify_all(geom, lo, lo + h).astype(float)
+    out = cls.copy()
+    for m in np.flatnonzero(cls < 0):
+        i, j, k = (int(x) for x in idx[m])
+        out[m] = cell_fraction(geom, n, h, i, j, k)
+    return out.reshape(shape)
+
+
+def fractions(geom, n, h) -> dict:
+    """All seven fraction arrays of the grid n = (Nx, Ny, Nz), cell size h."""
+    out = {}
+    for axis, name in enumerate(("ax", "ay", "az")):
+        out[name] = face_fractions(geom, n, h, axis)
+    for axis, name in enumerate(("lx", "ly", "lz")):
+        out[name] = edge_fractions(geom, n, h, axis)
+    out["v"] = cell_fractions(geom, n, h)
+    return out
+
+
+def count_active_faces(geom, n, h) -> int:
+    """Number of faces with a > 0, decided by classification alone (a face
+    whose closed rectangle meets the open cavity has positive area)."""
+    n = tuple(int(x) for x in n)
+    total = 0
+    for axis in range(3):
+        shape = FACE_SHAPES[("ax", "ay", "az")[axis]](n)
+        idx = _family(shape)
+        b, d = _OTHER[axis]
+        lo = (idx * h).astype(float)
+        hi = lo.copy()
+        hi[:, b] += h
+        hi[:, d] += h
+        cls = _classify_all(geom, lo, hi)
+        wall = (idx[:, axis] == 0) | (idx[:, axis] == n[axis])
+        total += int(np.sum((cls != 0) & ~wall))
+    return total

@@ -1,0 +1,62 @@
+"""Pins of the oracle V-cycle definition.
+
+The paper's multigrid (Sec. 6) is algebraic; this project's geometric V-cycle
+is a reading.  What mathematics fixes about it, and is checked here: the
+V-cycle operator is symmetric (reverse smoothing order, R = P^T / 8), a
+one-level cycle is the exact inverse, it contracts the error at an SPD shift,
+and the coarse fractions obtained by summation are the geometric fractions
+of the coarse grid.
+"""
+import numpy as np
+import pytest
+
+from oracle import geometry as geo, multigrid as mg
+
+
+@pytest.fixture(scope="module")
+def sphere16_frac():
+    n, h = (16, 16, 16), 1.0 / 16
+    return geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), n, h), n, h
+
+
+@pytest.mark.parametrize("sigma", [5.0, 36.0])
+def test_vcycle_is_symmetric(sphere16_frac, sigma):
+    fr, n, h = sphere16_frac
+    vc = mg.VCycle(fr, n, h, sigma, 3)
+    rng = np.random.default_rng(1)
+    m = vc.levels[0].op.act.size
+    u, v = rng.standard_normal(m), rng.standard_normal(m)
+    lhs, rhs = u @ vc.apply_active(v), v @ vc.apply_active(u)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_one_level_is_exact_inverse(sphere16_frac):
+    fr, n, h = mg.coarsen_fractions(sphere16_frac[0]), (8, 8, 8), 1.0 / 8
+    vc = mg.VCycle(fr, n, h, 5.0, 1)
+    op = vc.levels[0].op
+    f = np.random.default_rng(2).standard_normal(op.act.size)
+    x = vc.apply_active(f)
+    assert np.linalg.norm(op.M_a @ x - f) < 1e-12 * np.linalg.norm(f)
+
+
+def test_vcycle_contracts(sphere16_frac):
+    """Stationary iteration x += B (f - M x) at sigma = 5 (SPD): the residual
+    falls by at least 3x per cycle (the paper's AMG rates were 0.21-0.27)."""
+    fr, n, h = sphere16_frac
+    vc = mg.VCycle(fr, n, h, 5.0, 3)
+    op = vc.levels[0].op
+    f = np.random.default_rng(3).standard_normal(op.act.size)
+    x = np.zeros_like(f)
+    r0 = np.linalg.norm(f)
+    for _ in range(6):
+        x += vc.apply_active(f - op.M_a @ x)
+    rate = (np.linalg.norm(f - op.M_a @ x) / r0) ** (1 / 6)
+    assert rate < 0.33
+
+
+def test_coarse_fractions_are_geometric(sphere16_frac):
+    fr, n, h = sphere16_frac
+    coarse = mg.coarsen_fractions(fr)
+    direct = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), (8, 8, 8), 2 * h)
+    for s in coarse:
+        assert np.max(abs(coarse[s] - direct[s])) < 1e-13
