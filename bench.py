@@ -1,0 +1,175 @@
+#!/usr/bin/env python
+"""Benchmark: seconds per eigenpair at rho <= 1e-10, and V-cycle kernel bandwidth.
+
+Workload (one step = one whole eigensolve): sphere of radius 0.45 centred in
+the unit cube, 128^3 cells (h = 1/128), Dey--Mittra fractions from the
+analytic sphere, shift sigma = 36 (just below the lowest TM mode), the 6
+lowest nonzero eigenpairs of K b = lambda A b to rho <= 1e-10; block
+Krylov--Schur on P_DM M^-1 A, each M solve by FP64 flexible GMRES with a
+5-level V-cycle preconditioner.  The headline form runs the V-cycle in FP32
+(FP64 outer solve, orthogonalisation, Rayleigh quotients and residuals);
+the plain FP64 form is timed beside it.  Inputs are synthetic (analytic
+geometry); setup (fractions, hierarchy, coarsest factorisation) is outside
+the timed region and reported separately.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 128
+R = 0.45
+SIGMA = 36.0
+K_EIG = 6
+LEVELS = 5
+TOL = 1e-10
+SEED = 1301
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per cell (3 face unknowns) of the FP32 kernels: every
+# array the kernel must read or write, each counted once.
+#   residual r = f - M x : x(3) f(3) coef(7) r(3)       = 16 words
+#   apply   y = M x      : x(3) coef(7) y(3)            = 13 words
+#   red-black sweep (6 class updates): x(3) f(3) coef(7) read, x(3) written = 16 words
+BYTES_PER_CELL = {"residual": 16 * 4, "apply": 13 * 4, "sweep": 16 * 4}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--skip-fp64", action="store_true", help="do not time the plain FP64 form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline():
+    """The oracle (block shift-invert Lanczos + Jacobi-CG, projection by CG)
+    on a bounded sample of the workload: the same sphere at 32^3, k = 6,
+    rho <= 1e-10, on one host thread.  Scaled to the 128^3 workload by the
+    ratio of active faces (linear: a lower bound, since the oracle's CG
+    iteration count grows with resolution)."""
+    import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_limits
+
+    from oracle import eigs as oeigs, geometry as geo, operators as ops
+    n = 32
+    with threadpool_limits(1):
+        fr = geo.fractions(geo.sphere((0.5, 0.5, 0.5), R), (n, n, n), 1.0 / n)
+        op = ops.build(fr, (n, n, n), 1.0 / n, 5.0)
+        t0 = time.perf_counter()
+        lam, _, info = oeigs.lanczos_eigs(op, K_EIG, sigma_o=5.0, block=4, tol=TOL)
+        dt = time.perf_counter() - t0
+    return dict(sample_seconds=dt, sample_active_faces=int(op.act.size), lam=lam.tolist(),
+                max_residual=float(np.max(info["residuals"])))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the data-parallel sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1301_3794_amd import dm
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    op = dm.Operator(dm.sphere((0.5, 0.5, 0.5), R), (N, N, N), 1.0 / N, SIGMA, levels=LEVELS)
+    setup_s = time.perf_counter() - t0
+    lay = op.layout(0)
+
+    def solve(mode):
+        out = op.eigs(K_EIG, sigma=SIGMA, tol=TOL, seed=SEED, solve_mode=mode,
+                      verbose=int(args.verbose))
+        if out["status"] != 0:
+            raise RuntimeError(f"eigensolve did not converge: {out}")
+        return out
+
+    for _ in range(args.warmup):
+        solve(dm.SOLVE_FGMRES_MG32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for _ in range(args.steps):
+        outs.append(solve(dm.SOLVE_FGMRES_MG32))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1000.0 * dt / args.steps
+    value = dt / args.steps / K_EIG
+    main_out = outs[-1]
+
+    forms = {"fp32mg": dict(s_per_eigenpair=value, lam=main_out["lam"].tolist(),
+                            max_residual=main_out["max_residual"],
+                            inner_iterations=main_out["inner_iterations"],
+                            outer_iterations=main_out["outer_iterations"])}
+    if not args.skip_fp64:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o64 = solve(dm.SOLVE_FGMRES_MG64)
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - t1
+        forms["fp64"] = dict(s_per_eigenpair=d64 / K_EIG, lam=o64["lam"].tolist(),
+                             max_residual=o64["max_residual"],
+                             inner_iterations=o64["inner_iterations"],
+                             outer_iterations=o64["outer_iterations"],
+                             rel_diff_vs_fp32mg=float(np.max(abs(o64["lam"] - main_out["lam"]) / o64["lam"])))
+    golden = os.path.join(ROOT, "tests", "golden", "sphere128_oracle.json")
+    if os.path.exists(golden):
+        ref = np.array(json.load(open(golden))["lam"][:K_EIG])
+        for f in forms.values():
+            f["rel_err_vs_oracle"] = (abs(np.array(f["lam"]) - ref) / ref).tolist()
+
+    # roofline of the dominant kernel: the FP32 red-black sweep on the finest level
+    ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=50)
+    cells = N ** 3
+    achieved = BYTES_PER_CELL["sweep"] * cells / (ms_sweep * 1e-3) / 1e9
+    ms_vc = op.time_kernel(dm.KERNEL_VCYCLE, prec=32, level=0, reps=20)
+    ms_res = op.time_kernel(dm.KERNEL_RESIDUAL, prec=32, level=0, reps=50)
+    roofline = {"bound": "hbm", "kernel": "red-black sweep (6 class updates), FP32, 128^3",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "ms_per_launch": ms_sweep, "bytes_per_launch": BYTES_PER_CELL["sweep"] * cells,
+                "vcycle_ms": ms_vc, "residual_ms": ms_res,
+                "residual_GBps": BYTES_PER_CELL["residual"] * cells / (ms_res * 1e-3) / 1e9}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline()
+        scale = lay["active_faces"] / cb["sample_active_faces"]
+        cpu = {"value": cb["sample_seconds"] / K_EIG * scale, "unit": "s/eigenpair", "cores": 1,
+               "kind": "oracle",
+               "sample": (f"oracle eigensolve of the same sphere at 32^3 (k={K_EIG}, rho<=1e-10, "
+                          f"{cb['sample_seconds']:.1f} s, {cb['sample_active_faces']} active faces), "
+                          f"scaled x{scale:.1f} by active faces to 128^3 (lower bound)")}
+
+    line = {
+        "metric": "s per eigenpair at 1e-10 residual (FP64 vs FP32-MG vs learned); V-cycle HBM GB/s",
+        "value": value, "unit": "s/eigenpair", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32 V-cycle / f64 outer",
+        "data": "synthetic (analytic sphere geometry)",
+        "config": {"workload": "sphere R=0.45, 128^3 cells, sigma=36, k=6, 5-level V-cycle, FP32-MG FGMRES",
+                   "grid": [N, N, N], "active_faces": lay["active_faces"], "k": K_EIG,
+                   "sigma": SIGMA, "levels": LEVELS, "tol": TOL, "setup_s": setup_s},
+        "forms": forms,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    op.close()
+
+
+if __name__ == "__main__":
+    main()

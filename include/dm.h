@@ -1,0 +1,286 @@
+/*
+ * dm.h -- C ABI of the MI355X Dey--Mittra cut-cell cavity eigensolver.
+ *
+ * Problem (Bauer, Werner & Cary, arXiv:1301.3794): find the lowest
+ * electromagnetic eigenpairs k^2, b of a perfectly conducting cavity on the
+ * Yee mesh with Dey--Mittra cut cells, i.e. the smallest lambda > 0 of the
+ * symmetric pencil  K b = lambda A b,  K = C L C^T  (Sec. 2, eq. discWaveBDM
+ * multiplied by A).  The work is the shift-and-invert Krylov iteration of
+ * eq. fullMat:  T = P_DM M^-1 A  with
+ *      M    = C L C^T + A D^T V^-1 D A - sigma A          (eq. discLaplDM)
+ *      P_DM = I - D^T (D A D^T)^-1 D A                     (eq. proj)
+ * M is inverted by a multigrid-preconditioned Krylov solve (Sec. 6); every
+ * step of that runs in this library's HIP kernels on the GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: Nx x Ny x Nz cubic cells of size h (Sec. 6, cubic cells), cell
+ * (i,j,k) = [ih,(i+1)h] x [jh,(j+1)h] x [kh,(k+1)h].  Face b_x[i,j,k] is the
+ * x = ih face of cell (i,j,k); edge e_x[i,j,k] runs from node (i,j,k) in +x.
+ *
+ * Field layout ("padded SoA"): every per-face, per-edge or per-cell array of
+ * a grid level is one contiguous block of P = (Nx+2)(Ny+2)(Nz+2) elements;
+ * element (i,j,k), -1 <= i <= Nx (same for j, k), sits at
+ *      (i+1) + (Nx+2) * ((j+1) + (Ny+2) * (k+1)).
+ * A face vector is three such blocks back to back (b_x, b_y, b_z): 3P
+ * elements.  Entries of inactive faces (area fraction 0) and of the padding
+ * are zero on input and are returned zero.  A cell vector is one block.
+ * dm_field_layout() returns the sizes.  Fraction arrays (dm_get_fractions,
+ * user fractions) are seven blocks in the order ax, ay, az, lx, ly, lz, v.
+ *
+ * Memory: pointers named *_dev are device pointers of the op's GPU (e.g.
+ * torch tensor data), owned by the caller, contiguous, aligned to 8 bytes;
+ * the library keeps no pointer after a call returns.  *_host are host
+ * pointers.  The library owns the dm_op and all internal device buffers.
+ *
+ * Streams: `stream` is a hipStream_t passed as void*; NULL means the op's
+ * own stream.  Calls enqueue their work on that stream and return after it
+ * has completed (every entry point synchronises before returning), so
+ * caller buffers may be reused at once.  One dm_op must not be used from two
+ * host threads at the same time.
+ *
+ * Errors: 0 on success, a negative DM_E* code on error (the op is left
+ * usable unless DM_EHIP), a positive code for a warning with a usable
+ * partial result.  dm_strerror() names every code; dm_last_error_message()
+ * gives the detail of the last error of the calling thread.
+ */
+#ifndef DM_H
+#define DM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DM_OK               0
+#define DM_NOT_CONVERGED    1    /* warning: iteration limit hit; partial result */
+#define DM_EINVAL          (-1)  /* bad argument (size, pointer, option) */
+#define DM_ENOMEM          (-2)  /* device or host allocation failed */
+#define DM_EHIP            (-3)  /* HIP runtime error (detail in message) */
+#define DM_ESINGULAR       (-4)  /* coarsest operator singular: sigma hits a
+                                    coarse eigenvalue; choose another shift */
+#define DM_EBREAKDOWN      (-5)  /* Krylov breakdown (e.g. zero start vector) */
+#define DM_ENAN            (-6)  /* NaN/Inf met in an iterate or residual */
+#define DM_ENODEVICE       (-7)  /* no HIP device available */
+
+/* ---- geometry ---------------------------------------------------------- */
+#define DM_GEOM_BOX          0   /* the domain box itself is the cavity */
+#define DM_GEOM_ELLIPSOID    1   /* open axis-aligned ellipsoid (sphere: equal axes) */
+#define DM_GEOM_ELLIPTIC_BOR 2   /* body of revolution about the line x=axis_xy[0],
+                                    y=axis_xy[1]: beam tube, n_cells elliptic cells,
+                                    beam tube (see fields below) */
+#define DM_GEOM_USER         3   /* caller-supplied fractions */
+
+#define DM_BC_PEC 0              /* perfect electric conductor wall */
+#define DM_BC_PMC 1              /* perfect magnetic conductor symmetry plane */
+
+typedef struct {
+    int kind;                    /* DM_GEOM_* */
+    double center[3];            /* ellipsoid centre */
+    double semi_axes[3];         /* ellipsoid semi-axes (sphere: all = R) */
+    /* DM_GEOM_ELLIPTIC_BOR: radius profile r(z) of n_cells cells of length
+       cell_length, each an elliptic arc from r_iris (cell ends) to r_equator
+       (cell middle); tubes of radius r_iris and length tube_length on both
+       sides; the structure starts at z = z_start and the end plates are
+       perfect conductors. */
+    double axis_xy[2];
+    double z_start;
+    int n_cells;
+    double r_equator, r_iris, cell_length, tube_length;
+    /* DM_GEOM_USER: 7 host blocks (ax, ay, az, lx, ly, lz, v) in the padded
+       layout of level 0, copied at build time. */
+    const double *user_fractions_host;
+    /* boundary type of the low side x=0, y=0, z=0 of the domain (the high
+       sides are always perfect electric conductors).  A PMC plane is a
+       symmetry plane of the cavity (Sec. 6.3, quarter cavity). */
+    int bc_lo[3];
+    /* face neglect (Sec. 3): faces with area fraction below a_min are
+       removed together with the edges around them; 0 keeps every cut face
+       (the paper's choice for all its timing runs). */
+    double a_min;
+} dm_geometry;
+
+/* ---- options ----------------------------------------------------------- */
+typedef struct {
+    int levels;          /* multigrid levels, 0 = halve while every dimension is
+                            even, the largest exceeds 8 and the smallest is >= 4 */
+    int nu_pre;          /* red-black sweeps before coarse correction (2) */
+    int nu_post;         /* red-black sweeps after (2) */
+    int fgmres_restart;  /* FGMRES restart length (30) */
+    int verbose;         /* 0 silent, 1 per-solve lines on stderr */
+} dm_options;
+
+/* Fills `opt` with the defaults listed above. */
+void dm_default_options(dm_options *opt);
+
+typedef struct dm_op dm_op;   /* opaque, owned by the library */
+
+/* Builds the operator hierarchy on the current HIP device.
+ *   geom   geometry description (host); copied.
+ *   dims   Nx, Ny, Nz >= 2, each divisible by 2^(levels-1).
+ *   h      cell size (> 0).
+ *   sigma  shift of M (k^2 units, Sec. 4.1 eq. shiftInv); must not be an
+ *          eigenvalue of the coarsest operator.
+ *   opt    NULL for defaults.
+ *   out    receives the new op.
+ * Computes the cut fractions of every level on the host (coarse fractions
+ * are exact sums of fine ones), uploads them in FP64 and FP32, and factors
+ * the coarsest vector and scalar operators densely in FP64.
+ * Errors: DM_EINVAL, DM_ENOMEM, DM_EHIP, DM_ENODEVICE, DM_ESINGULAR. */
+int dm_build_operator(const dm_geometry *geom, const int dims[3], double h,
+                      double sigma, const dm_options *opt, dm_op **out);
+
+/* Releases the op and all its device memory.  NULL is ignored. */
+void dm_destroy(dm_op *op);
+
+/* Changes sigma (re-factors the coarsest level).  Errors: DM_ESINGULAR. */
+int dm_set_shift(dm_op *op, double sigma);
+
+/* Cut fractions on the host, without a GPU (setup step of build).
+ *   out_host  7 * P doubles (level-0 padded layout, order ax..v).
+ * Same values dm_build_operator uploads.  Errors: DM_EINVAL. */
+int dm_compute_fractions(const dm_geometry *geom, const int dims[3], double h,
+                         double *out_host);
+
+/* Sizes of level `level`: out[0..2] = Nx, Ny, Nz of that level, out[3] = P
+ * (elements per block), out[4] = number of active faces, out[5] = number of
+ * active cells, out[6] = number of levels.  Errors: DM_EINVAL. */
+int dm_field_layout(const dm_op *op, int level, int64_t out[7]);
+
+/* Copies the fractions of `level` (7 * P doubles, order ax..v; v holds the
+ * volume fraction, not its inverse). */
+int dm_get_fractions(const dm_op *op, int level, double *out_host);
+
+/* ---- operator applications (parity hooks and building blocks) ---------- */
+#define DM_APPLY_M   0   /* y = M x = C L C^T x + A D^T V^-1 D A x - sigma A x  (eq. discLaplDM) */
+#define DM_APPLY_K   1   /* y = K x = C L C^T x                               (eq. discWaveBDM times A) */
+#define DM_APPLY_A   2   /* y = A x */
+#define DM_APPLY_DA  3   /* cells: y = D A x   (eq. divBInt without V^-1) */
+#define DM_APPLY_DT  4   /* faces: y = D^T x for a cell vector x (minus the gradient, eq. gradPhi) */
+#define DM_APPLY_S   5   /* cells: y = D A D^T x  (scalar Laplacian of eq. proj) */
+
+/* prec: 64 (double) or 32 (float) for M/K/A; DA/DT/S are FP64 only.
+ * x_dev, y_dev: face or cell vectors of `level` in the padded layout. */
+int dm_apply(dm_op *op, int which, int prec, int level, const void *x_dev,
+             void *y_dev, void *stream);
+
+/* r = f - M x on `level` (prec 64 or 32). */
+int dm_residual(dm_op *op, int prec, int level, const void *f_dev,
+                const void *x_dev, void *r_dev, void *stream);
+
+/* n_sweeps red-black Gauss--Seidel sweeps of M x = f on `level`, in place on
+ * x.  One sweep updates the six classes (component, colour (i+j+k) mod 2)
+ * in the order (x,0)(x,1)(y,0)(y,1)(z,0)(z,1); reverse != 0 uses the
+ * reverse order (post-smoothing).  prec 64 or 32. */
+int dm_smooth(dm_op *op, int prec, int level, int n_sweeps, int reverse,
+              const void *f_dev, void *x_dev, void *stream);
+
+/* Staggered transfers between `level` and `level`+1 (prec 64 or 32).
+ * Prolongation P: linear along the face normal, constant across it,
+ * inactive faces of either level dropped.  Restriction R = P^T / 8.
+ *   dm_restrict:    f_coarse = R r_fine
+ *   dm_prolong_add: x_fine  += P x_coarse */
+int dm_restrict(dm_op *op, int prec, int level, const void *r_fine_dev,
+                void *f_coarse_dev, void *stream);
+int dm_prolong_add(dm_op *op, int prec, int level, const void *x_coarse_dev,
+                   void *x_fine_dev, void *stream);
+
+/* One multigrid V-cycle x = B f for M on level 0, zero initial guess:
+ * nu_pre sweeps, residual, restriction, recursion, prolongation, nu_post
+ * reverse sweeps; exact dense FP64 solve on the coarsest level.  prec 64
+ * (all FP64) or 32 (FP32 smoothing/transfers, FP64 coarsest solve). */
+int dm_vcycle(dm_op *op, int prec, const void *f_dev, void *x_dev, void *stream);
+
+/* Divergence projection b_out = P_DM b (eq. proj); the scalar system
+ * D A D^T psi = D A b is solved by CG preconditioned with a cell-centred
+ * multigrid V-cycle until ||D A D^T psi - D A b||_2 <= rtol ||b||_A / h, a
+ * bound on the scale of the field (not of its divergence), so nearly
+ * divergence-free input costs few iterations.  FP64.  b and b_out may alias. */
+int dm_project(dm_op *op, const double *b_dev, double *out_dev, double rtol,
+               void *stream);
+
+/* ---- linear solve of M x = f (Sec. 6: the inner inversion) -------------- */
+#define DM_SOLVE_PCG64        0  /* CG + FP64 V-cycle (M must be SPD: sigma below
+                                    the lowest eigenvalue of (K+G, A)) */
+#define DM_SOLVE_FGMRES_MG64  1  /* flexible GMRES, FP64 V-cycle preconditioner */
+#define DM_SOLVE_FGMRES_MG32  2  /* flexible GMRES (FP64), FP32 V-cycle */
+
+typedef struct {
+    int iterations;          /* preconditioner applications */
+    int restarts;
+    double rel_residual;     /* ||f - M x||_2 / ||f||_2, recomputed in FP64 */
+    double seconds;
+} dm_solve_info;
+
+/* x = M^-1 f to ||f - M x|| <= rtol ||f||, starting from x = 0.  FP64 in
+ * and out.  Returns DM_NOT_CONVERGED if maxit preconditioner applications
+ * did not reach rtol (x holds the best iterate). */
+int dm_solve(dm_op *op, int mode, const double *f_dev, double *x_dev,
+             double rtol, int maxit, dm_solve_info *info, void *stream);
+
+/* ---- eigensolve (Sec. 4.1, Sec. 5.2 eq. fullMat) ------------------------ */
+typedef struct {
+    int solve_mode;      /* DM_SOLVE_* used for M^-1 (default FGMRES_MG64) */
+    double inner_rtol;   /* relative tolerance of each M solve (1e-11) */
+    double proj_rtol;    /* tolerance of each projection, see dm_project (1e-13) */
+    int block;           /* block size of the Krylov--Schur iteration (4) */
+    int max_basis;       /* basis size before a thick restart (40) */
+    int max_restarts;    /* (20) */
+    int verbose;
+} dm_eig_options;
+
+void dm_default_eig_options(dm_eig_options *opt);
+
+typedef struct {
+    int n_converged;
+    int outer_iterations;    /* block applications of T */
+    int restarts;
+    int inner_iterations;    /* total preconditioner applications in M solves */
+    int projection_iterations;
+    double max_residual;     /* max over returned pairs of rho (below) */
+    double seconds;
+} dm_eig_info;
+
+/* The k smallest eigenvalues lambda > 0 of K b = lambda A b, by block
+ * Krylov--Schur in the A-inner product (eq. bInner) on T = P_DM M^-1 A with
+ * shift sigma, stopping when every pair has
+ *     rho = ||K b - lambda A b||_{A^-1} / (lambda ||b||_A) <= tol.
+ *   sigma        shift (M is re-factored if it differs from the op's).
+ *   seed         start block: N(0,1) on active faces from a counter-based
+ *                generator keyed by seed.
+ *   lambda_host  k doubles, ascending.
+ *   vecs_dev     NULL or k face vectors (k * 3P doubles), A-orthonormal.
+ *   residuals_host  NULL or k doubles (rho of each pair).
+ * Returns DM_NOT_CONVERGED with info->n_converged if max_restarts is hit. */
+int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed,
+            const dm_eig_options *opt, double *lambda_host, double *vecs_dev,
+            double *residuals_host, dm_eig_info *info, void *stream);
+
+/* ---- measurement -------------------------------------------------------- */
+#define DM_KERNEL_APPLY     0  /* y = M x on `level` */
+#define DM_KERNEL_RESIDUAL  1  /* r = f - M x on `level` */
+#define DM_KERNEL_SMOOTH    2  /* one class update: component x, colour 0 */
+#define DM_KERNEL_SWEEP     3  /* the six class updates of one red-black sweep */
+#define DM_KERNEL_RESTRICT  4  /* `level` -> `level`+1 */
+#define DM_KERNEL_PROLONG   5  /* `level`+1 -> `level` */
+#define DM_KERNEL_VCYCLE    6  /* one whole V-cycle (level must be 0) */
+
+/* Average duration of one launch of `kernel` (prec 64 or 32) on seeded
+ * N(0,1) data in library-owned buffers: 2 untimed launches, then `reps`
+ * launches bracketed by HIP events on the op's stream.  Writes the
+ * milliseconds per launch.  Used for roofline figures; touches no caller
+ * memory.  Errors: DM_EINVAL, DM_ENOMEM, DM_EHIP. */
+int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps,
+                   double *ms_per_launch);
+
+/* ---- diagnostics -------------------------------------------------------- */
+const char *dm_strerror(int code);
+const char *dm_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DM_H */

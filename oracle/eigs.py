@@ -141,14 +141,18 @@ def _a_orthonormalize(W, a, basis=None):
 
 
 def lanczos_eigs(op, k, sigma_o=0.0, block=4, tol=1e-10, max_blocks=60, seed=1301,
-                 cg_tol=1e-13, proj_tol=1e-13, precond=None, maxiter=100000, log=None):
+                 cg_tol=1e-13, proj_tol=1e-13, precond=None, maxiter=100000, log=None,
+                 project=True):
     """k smallest nonzero eigenpairs of (K, A) by shift-and-invert block Lanczos.
 
     ``sigma_o`` must keep M = K + G - sigma_o A positive definite (below both
     the lowest electromagnetic eigenvalue and the lowest nonzero eigenvalue
     of (S, V)); sigma_o = 0 is always safe because K + G has a trivial null
     space (Sec. 4.3, text after eq. hodge).  ``precond`` is an optional SPD
-    preconditioner for M (default Jacobi).
+    preconditioner for M (default Jacobi).  With ``project=False`` the
+    projection P_DM is skipped: the Krylov basis then also holds gradient
+    modes b = D^T psi, which Rayleigh--Ritz on (K, A) maps to lambda = 0 and
+    discards (eq. hodge: K D^T = 0), so the returned pairs are the same.
 
     Returns (lam, B, info) with B A-orthonormal columns.
     """
@@ -158,7 +162,7 @@ def lanczos_eigs(op, k, sigma_o=0.0, block=4, tol=1e-10, max_blocks=60, seed=130
     if precond is None:
         dinv = 1.0 / M.diagonal()
         precond = lambda r: dinv * r  # noqa: E731
-    proj = Projector(op, tol=proj_tol)
+    proj = Projector(op, tol=proj_tol) if project else (lambda b: b)
     rng = np.random.default_rng(seed)
     V0 = rng.standard_normal((n, block))
     V0 = np.column_stack([proj(V0[:, c]) for c in range(block)])

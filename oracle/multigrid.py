@@ -98,6 +98,8 @@ class Level:
             for c in (0, 1):
                 sel = fid[col == c]
                 self.classes[(axis, c)] = sel[self.active[sel]]
+        # the rows of M of each class (the same numbers as M[ids], kept once)
+        self.class_rows = {key: self.M[ids].tocsr() for key, ids in self.classes.items()}
 
 
 class VCycle:
@@ -129,7 +131,7 @@ class VCycle:
     def _smooth(self, L, x, f, order):
         for cls in order:
             ids = L.classes[cls]
-            r = f[ids] - L.M[ids] @ x
+            r = f[ids] - L.class_rows[cls] @ x
             x[ids] += r * L.dinv[ids]
 
     def cycle(self, lev, f):

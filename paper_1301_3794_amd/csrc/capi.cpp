@@ -1,0 +1,512 @@
+// extern "C" entry points of dm.h: argument checks, error mapping, stream
+// handling.  Every entry point synchronises its stream before returning.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "geometry.h"
+#include "op.h"
+
+namespace dm {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const DmError &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const HipError &e) {
+        set_error(std::string(hipGetErrorString(e.e)) + " in " + e.where);
+        return DM_EHIP;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return DM_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return DM_EINVAL;
+    }
+}
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+hipStream_t stream_of(dm_op *op, void *stream) {
+    return stream ? (hipStream_t)stream : op->stream;
+}
+
+// run `f` on the op's device, then synchronise and surface launch errors
+template <class F>
+int on_device(dm_op *op, void *stream, F &&f) {
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(op->device));
+        hipStream_t s = stream_of(op, stream);
+        const int rc = f(s);
+        DM_HIP(hipGetLastError());
+        DM_HIP(hipStreamSynchronize(s));
+        return rc;
+    });
+}
+
+bool valid_geometry(const dm_geometry *g, std::string &why) {
+    if (!g) {
+        why = "geometry is NULL";
+        return false;
+    }
+    if (g->kind < DM_GEOM_BOX || g->kind > DM_GEOM_USER) {
+        why = "unknown geometry kind";
+        return false;
+    }
+    if (g->kind == DM_GEOM_ELLIPSOID)
+        for (int a = 0; a < 3; ++a)
+            if (!(g->semi_axes[a] > 0.0)) {
+                why = "ellipsoid semi-axes must be positive";
+                return false;
+            }
+    if (g->kind == DM_GEOM_USER && !g->user_fractions_host) {
+        why = "user geometry without fractions";
+        return false;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (g->bc_lo[a] != DM_BC_PEC && g->bc_lo[a] != DM_BC_PMC) {
+            why = "bc_lo must be DM_BC_PEC or DM_BC_PMC";
+            return false;
+        }
+    if (g->bc_lo[0] == DM_BC_PMC || g->bc_lo[1] == DM_BC_PMC || g->bc_lo[2] == DM_BC_PMC) {
+        why = "PMC symmetry planes are not supported by this build";
+        return false;
+    }
+    if (!(g->a_min >= 0.0 && g->a_min < 1.0)) {
+        why = "a_min must be in [0, 1)";
+        return false;
+    }
+    return true;
+}
+
+int auto_levels(const int d[3]) {
+    int l = 1, n[3] = {d[0], d[1], d[2]};
+    while (n[0] % 2 == 0 && n[1] % 2 == 0 && n[2] % 2 == 0 &&
+           std::max(n[0], std::max(n[1], n[2])) > 8 && std::min(n[0], std::min(n[1], n[2])) >= 4) {
+        for (int a = 0; a < 3; ++a) n[a] /= 2;
+        ++l;
+    }
+    return l;
+}
+
+}  // namespace
+}  // namespace dm
+
+using namespace dm;
+
+
+static void free_op(dm_op *op) {
+    if (!op) return;
+    hipSetDevice(op->device);
+    if (op->stream) hipStreamSynchronize(op->stream);
+    for (void *p : op->allocs) hipFree(p);
+    if (op->hres) hipHostFree(op->hres);
+    if (op->stream) hipStreamDestroy(op->stream);
+    delete op;
+}
+
+extern "C" {
+
+void dm_default_options(dm_options *opt) {
+    if (!opt) return;
+    opt->levels = 0;
+    opt->nu_pre = 2;
+    opt->nu_post = 2;
+    opt->fgmres_restart = 30;
+    opt->verbose = 0;
+}
+
+void dm_default_eig_options(dm_eig_options *opt) {
+    if (!opt) return;
+    opt->solve_mode = DM_SOLVE_FGMRES_MG64;
+    opt->inner_rtol = 1e-11;
+    opt->proj_rtol = 1e-13;
+    opt->block = 4;
+    opt->max_basis = 40;
+    opt->max_restarts = 20;
+    opt->verbose = 0;
+}
+
+const char *dm_strerror(int code) {
+    switch (code) {
+        case DM_OK: return "success";
+        case DM_NOT_CONVERGED: return "iteration limit reached before the tolerance (partial result)";
+        case DM_EINVAL: return "invalid argument";
+        case DM_ENOMEM: return "out of memory";
+        case DM_EHIP: return "HIP runtime error";
+        case DM_ESINGULAR: return "coarsest operator singular at this shift";
+        case DM_EBREAKDOWN: return "Krylov breakdown";
+        case DM_ENAN: return "NaN or Inf encountered";
+        case DM_ENODEVICE: return "no HIP device available";
+        default: return "unknown status code";
+    }
+}
+
+const char *dm_last_error_message(void) { return dm::g_last_error.c_str(); }
+
+int dm_compute_fractions(const dm_geometry *geom, const int dims[3], double h, double *out_host) {
+    return guarded([&]() -> int {
+        std::string why;
+        if (!valid_geometry(geom, why)) return fail(DM_EINVAL, why);
+        if (!dims || dims[0] < 2 || dims[1] < 2 || dims[2] < 2) return fail(DM_EINVAL, "dims must be >= 2");
+        if (!(h > 0.0)) return fail(DM_EINVAL, "h must be positive");
+        if (!out_host) return fail(DM_EINVAL, "out_host is NULL");
+        if (geom->kind == DM_GEOM_USER) return fail(DM_EINVAL, "user geometry has no computed fractions");
+        Grid g = make_grid(dims[0], dims[1], dims[2], h);
+        std::unique_ptr<Body> body = make_body(*geom);
+        if (!body) return fail(DM_EINVAL, "geometry kind not available");
+        std::vector<double> fr;
+        compute_fractions(*body, g, geom->bc_lo, fr);
+        neglect_faces(g, geom->a_min, fr);
+        std::memcpy(out_host, fr.data(), fr.size() * sizeof(double));
+        return DM_OK;
+    });
+}
+
+int dm_build_operator(const dm_geometry *geom, const int dims[3], double h, double sigma,
+                      const dm_options *opt, dm_op **out) {
+    if (!out) return fail(DM_EINVAL, "out is NULL");
+    *out = nullptr;
+    dm_op *op = nullptr;
+    const int rc = guarded([&]() -> int {
+        std::string why;
+        if (!valid_geometry(geom, why)) return fail(DM_EINVAL, why);
+        if (!dims || dims[0] < 2 || dims[1] < 2 || dims[2] < 2) return fail(DM_EINVAL, "dims must be >= 2");
+        if (!(h > 0.0) || !std::isfinite(h)) return fail(DM_EINVAL, "h must be positive");
+        if (!std::isfinite(sigma)) return fail(DM_EINVAL, "sigma must be finite");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(DM_ENODEVICE, "no HIP device");
+        op = new dm_op();
+        op->geom = *geom;
+        for (int a = 0; a < 3; ++a) op->dims[a] = dims[a];
+        op->h = h;
+        op->sigma = sigma;
+        if (opt) op->opt = *opt;
+        else dm_default_options(&op->opt);
+        if (op->opt.levels <= 0) op->opt.levels = auto_levels(dims);
+        if (op->opt.nu_pre < 0 || op->opt.nu_post < 0 || op->opt.fgmres_restart < 1 ||
+            op->opt.fgmres_restart > kMaxDots - 2)
+            return fail(DM_EINVAL, "bad smoothing or restart option");
+        const int div = 1 << (op->opt.levels - 1);
+        for (int a = 0; a < 3; ++a)
+            if (dims[a] % div != 0 || dims[a] / div < 1)
+                return fail(DM_EINVAL, "dims not divisible by 2^(levels-1)");
+        DM_HIP(hipGetDevice(&op->device));
+        DM_HIP(hipStreamCreate(&op->stream));
+        build_hierarchy(op, geom->user_fractions_host);
+        factor_coarse(op);
+        DM_HIP(hipStreamSynchronize(op->stream));
+        return DM_OK;
+    });
+    if (rc != DM_OK) {
+        free_op(op);
+        return rc;
+    }
+    *out = op;
+    return DM_OK;
+}
+
+void dm_destroy(dm_op *op) { free_op(op); }
+
+int dm_set_shift(dm_op *op, double sigma) {
+    if (!op) return fail(DM_EINVAL, "op is NULL");
+    if (!std::isfinite(sigma)) return fail(DM_EINVAL, "sigma must be finite");
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(op->device));
+        const double old = op->sigma;
+        op->sigma = sigma;
+        try {
+            factor_coarse(op);
+        } catch (...) {
+            op->sigma = old;
+            factor_coarse(op);
+            throw;
+        }
+        return DM_OK;
+    });
+}
+
+int dm_field_layout(const dm_op *op, int level, int64_t out[7]) {
+    if (!op || !out) return fail(DM_EINVAL, "NULL argument");
+    if (level < 0 || level >= op->nlev()) return fail(DM_EINVAL, "level out of range");
+    const Level &L = op->lv[level];
+    out[0] = L.g.nx;
+    out[1] = L.g.ny;
+    out[2] = L.g.nz;
+    out[3] = L.g.P;
+    out[4] = L.n_act_faces;
+    out[5] = L.n_act_cells;
+    out[6] = op->nlev();
+    return DM_OK;
+}
+
+int dm_get_fractions(const dm_op *op, int level, double *out_host) {
+    if (!op || !out_host) return fail(DM_EINVAL, "NULL argument");
+    if (level < 0 || level >= op->nlev()) return fail(DM_EINVAL, "level out of range");
+    std::memcpy(out_host, op->frac[level].data(), op->frac[level].size() * sizeof(double));
+    return DM_OK;
+}
+
+int dm_apply(dm_op *op, int which, int prec, int level, const void *x, void *y, void *stream) {
+    if (!op || !x || !y) return fail(DM_EINVAL, "NULL argument");
+    if (level < 0 || level >= op->nlev()) return fail(DM_EINVAL, "level out of range");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    if (which < DM_APPLY_M || which > DM_APPLY_S) return fail(DM_EINVAL, "unknown operator");
+    if (which >= DM_APPLY_DA && prec != 64) return fail(DM_EINVAL, "scalar operators are FP64 only");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        const Level &L = op->lv[level];
+        switch (which) {
+            case DM_APPLY_M:
+            case DM_APPLY_K: {
+                const int kind = which == DM_APPLY_M ? AK_M : AK_K;
+                if (prec == 64)
+                    launch_apply<double>(L.g, L.coef64, op->sigma, kind, nullptr, (const double *)x, (double *)y, s);
+                else
+                    launch_apply<float>(L.g, L.coef32, (float)op->sigma, kind, nullptr, (const float *)x, (float *)y, s);
+                break;
+            }
+            case DM_APPLY_A:
+                if (prec == 64) launch_apply_A_t<double>(L.g, L.coef64, (const double *)x, (double *)y, s);
+                else launch_apply_A_t<float>(L.g, L.coef32, (const float *)x, (float *)y, s);
+                break;
+            case DM_APPLY_DA:
+                launch_div_DA(L.g, L.coef64, (const double *)x, (double *)y, s);
+                break;
+            case DM_APPLY_DT:
+                // y = D^T x on active faces: grad_sub with zero input and scale -1
+                DM_HIP(hipMemsetAsync(y, 0, 3 * L.g.P * sizeof(double), s));
+                launch_grad_sub(L.g, L.coef64, (const double *)x, (double *)y, (double *)y, -1.0, s);
+                break;
+            case DM_APPLY_S:
+                launch_s_apply(L.g, L.coef64, 1.0 / (L.g.h * L.g.h), 0, nullptr, (const double *)x, (double *)y, s);
+                break;
+        }
+        return DM_OK;
+    });
+}
+
+int dm_residual(dm_op *op, int prec, int level, const void *f, const void *x, void *r, void *stream) {
+    if (!op || !f || !x || !r) return fail(DM_EINVAL, "NULL argument");
+    if (level < 0 || level >= op->nlev()) return fail(DM_EINVAL, "level out of range");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        const Level &L = op->lv[level];
+        if (prec == 64)
+            launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, (const double *)f, (const double *)x, (double *)r, s);
+        else
+            launch_apply<float>(L.g, L.coef32, (float)op->sigma, AK_RESID, (const float *)f, (const float *)x, (float *)r, s);
+        return DM_OK;
+    });
+}
+
+int dm_smooth(dm_op *op, int prec, int level, int n_sweeps, int reverse, const void *f, void *x,
+              void *stream) {
+    if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
+    if (level < 0 || level >= op->nlev()) return fail(DM_EINVAL, "level out of range");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    if (n_sweeps < 0) return fail(DM_EINVAL, "n_sweeps must be >= 0");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        const Level &L = op->lv[level];
+        for (int it = 0; it < n_sweeps; ++it)
+            for (int q = 0; q < 6; ++q) {
+                const int cls = reverse ? 5 - q : q;
+                const int comp = cls / 2, col = cls % 2;
+                if (prec == 64)
+                    launch_smooth<double>(L.g, L.coef64, op->sigma, comp, col, (const double *)f, (double *)x, s);
+                else
+                    launch_smooth<float>(L.g, L.coef32, (float)op->sigma, comp, col, (const float *)f, (float *)x, s);
+            }
+        return DM_OK;
+    });
+}
+
+int dm_restrict(dm_op *op, int prec, int level, const void *r, void *fc, void *stream) {
+    if (!op || !r || !fc) return fail(DM_EINVAL, "NULL argument");
+    if (level < 0 || level + 1 >= op->nlev()) return fail(DM_EINVAL, "level out of range");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        const Level &F = op->lv[level], &C = op->lv[level + 1];
+        if (prec == 64) launch_restrict<double>(F.g, C.g, C.coef64, (const double *)r, (double *)fc, s);
+        else launch_restrict<float>(F.g, C.g, C.coef32, (const float *)r, (float *)fc, s);
+        return DM_OK;
+    });
+}
+
+int dm_prolong_add(dm_op *op, int prec, int level, const void *xc, void *x, void *stream) {
+    if (!op || !xc || !x) return fail(DM_EINVAL, "NULL argument");
+    if (level < 0 || level + 1 >= op->nlev()) return fail(DM_EINVAL, "level out of range");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        const Level &F = op->lv[level], &C = op->lv[level + 1];
+        if (prec == 64) launch_prolong_add<double>(F.g, C.g, F.coef64, (const double *)xc, (double *)x, s);
+        else launch_prolong_add<float>(F.g, C.g, F.coef32, (const float *)xc, (float *)x, s);
+        return DM_OK;
+    });
+}
+
+int dm_vcycle(dm_op *op, int prec, const void *f, void *x, void *stream) {
+    if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        if (prec == 64) vcycle<double>(op, 0, (const double *)f, (double *)x, s);
+        else vcycle<float>(op, 0, (const float *)f, (float *)x, s);
+        return DM_OK;
+    });
+}
+
+int dm_project(dm_op *op, const double *b, double *out, double rtol, void *stream) {
+    if (!op || !b || !out) return fail(DM_EINVAL, "NULL argument");
+    if (!(rtol > 0.0)) return fail(DM_EINVAL, "rtol must be positive");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        return project(op, b, out, rtol, 2000, s, nullptr);
+    });
+}
+
+int dm_solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
+             dm_solve_info *info, void *stream) {
+    if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
+    if (mode < DM_SOLVE_PCG64 || mode > DM_SOLVE_FGMRES_MG32) return fail(DM_EINVAL, "unknown solve mode");
+    if (!(rtol > 0.0) || maxit < 1) return fail(DM_EINVAL, "rtol must be positive and maxit >= 1");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        return solve(op, mode, f, x, rtol, maxit, info, s);
+    });
+}
+
+int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed, const dm_eig_options *opt,
+            double *lambda_host, double *vecs_dev, double *residuals_host, dm_eig_info *info,
+            void *stream) {
+    if (!op || !lambda_host) return fail(DM_EINVAL, "NULL argument");
+    if (k < 1) return fail(DM_EINVAL, "k must be >= 1");
+    if (!(tol > 0.0)) return fail(DM_EINVAL, "tol must be positive");
+    dm_eig_options o;
+    if (opt) o = *opt;
+    else dm_default_eig_options(&o);
+    if (o.block < 1 || o.max_restarts < 0 || !(o.inner_rtol > 0) || !(o.proj_rtol > 0) ||
+        o.solve_mode < DM_SOLVE_PCG64 || o.solve_mode > DM_SOLVE_FGMRES_MG32)
+        return fail(DM_EINVAL, "bad eig options");
+    if (sigma != op->sigma) {
+        const int rc = dm_set_shift(op, sigma);
+        if (rc != DM_OK) return rc;
+    }
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        return eigs(op, k, tol, seed, o, lambda_host, vecs_dev, residuals_host, info, s);
+    });
+}
+
+int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double *ms_per_launch) {
+    if (!op || !ms_per_launch) return fail(DM_EINVAL, "NULL argument");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    if (kernel < DM_KERNEL_APPLY || kernel > DM_KERNEL_VCYCLE) return fail(DM_EINVAL, "unknown kernel");
+    if (reps < 1) return fail(DM_EINVAL, "reps must be >= 1");
+    const bool pair = kernel == DM_KERNEL_RESTRICT || kernel == DM_KERNEL_PROLONG;
+    if (level < 0 || level >= op->nlev() || (pair && level + 1 >= op->nlev()) ||
+        (kernel == DM_KERNEL_VCYCLE && level != 0))
+        return fail(DM_EINVAL, "level out of range for this kernel");
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(op->device));
+        hipStream_t s = op->stream;
+        const Level &L = op->lv[level];
+        const int64_t n = 3 * L.g.P;
+        const int64_t nc = pair ? 3 * op->lv[level + 1].g.P : 0;
+        const size_t es = prec == 64 ? sizeof(double) : sizeof(float);
+        std::vector<void *> tmp;
+        auto alloc = [&](int64_t cnt) {
+            void *p = nullptr;
+            DM_HIP(hipMalloc(&p, std::max<int64_t>(cnt, 1) * es));
+            tmp.push_back(p);
+            return p;
+        };
+        int rc = DM_OK;
+        try {
+            void *x = alloc(n), *f = alloc(n), *y = alloc(n), *c = alloc(std::max(nc, (int64_t)1));
+            double *g64 = nullptr;
+            DM_HIP(hipMalloc((void **)&g64, n * sizeof(double)));
+            tmp.push_back(g64);
+            // seeded data on the active faces of `level` (mask = its area fractions)
+            std::vector<double> m(n);
+            for (int64_t p = 0; p < n; ++p) m[p] = op->frac[level][p] > 0.0 ? 1.0 : 0.0;
+            double *mask = nullptr;
+            DM_HIP(hipMalloc((void **)&mask, n * sizeof(double)));
+            tmp.push_back(mask);
+            DM_HIP(hipMemcpyAsync(mask, m.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+            for (int q = 0; q < 2; ++q) {
+                launch_randn(n, 97 + q, 0, mask, g64, s);
+                void *dst = q == 0 ? x : f;
+                if (prec == 64) launch_copy(n, g64, (double *)dst, s);
+                else launch_cast<double, float>(g64, (float *)dst, n, s);
+            }
+            DM_HIP(hipMemsetAsync(y, 0, n * es, s));
+            DM_HIP(hipMemsetAsync(c, 0, std::max(nc, (int64_t)1) * es, s));
+            auto launch = [&]() {
+                const Level &C = op->lv[std::min(level + 1, op->nlev() - 1)];
+                switch (kernel) {
+                    case DM_KERNEL_APPLY:
+                    case DM_KERNEL_RESIDUAL: {
+                        const int kind = kernel == DM_KERNEL_APPLY ? AK_M : AK_RESID;
+                        if (prec == 64) launch_apply<double>(L.g, L.coef64, op->sigma, kind, (double *)f, (double *)x, (double *)y, s);
+                        else launch_apply<float>(L.g, L.coef32, (float)op->sigma, kind, (float *)f, (float *)x, (float *)y, s);
+                        break;
+                    }
+                    case DM_KERNEL_SMOOTH:
+                    case DM_KERNEL_SWEEP:
+                        for (int q = 0; q < (kernel == DM_KERNEL_SMOOTH ? 1 : 6); ++q) {
+                            if (prec == 64) launch_smooth<double>(L.g, L.coef64, op->sigma, q / 2, q % 2, (double *)f, (double *)x, s);
+                            else launch_smooth<float>(L.g, L.coef32, (float)op->sigma, q / 2, q % 2, (float *)f, (float *)x, s);
+                        }
+                        break;
+                    case DM_KERNEL_RESTRICT:
+                        if (prec == 64) launch_restrict<double>(L.g, C.g, C.coef64, (double *)x, (double *)c, s);
+                        else launch_restrict<float>(L.g, C.g, C.coef32, (float *)x, (float *)c, s);
+                        break;
+                    case DM_KERNEL_PROLONG:
+                        if (prec == 64) launch_prolong_add<double>(L.g, C.g, L.coef64, (double *)c, (double *)y, s);
+                        else launch_prolong_add<float>(L.g, C.g, L.coef32, (float *)c, (float *)y, s);
+                        break;
+                    case DM_KERNEL_VCYCLE:
+                        if (prec == 64) vcycle<double>(op, 0, (double *)f, (double *)y, s);
+                        else vcycle<float>(op, 0, (float *)f, (float *)y, s);
+                        break;
+                }
+            };
+            launch();
+            launch();
+            hipEvent_t e0, e1;
+            DM_HIP(hipEventCreate(&e0));
+            DM_HIP(hipEventCreate(&e1));
+            DM_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) launch();
+            DM_HIP(hipEventRecord(e1, s));
+            DM_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            DM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            DM_HIP(hipGetLastError());
+            *ms_per_launch = (double)ms / reps;
+        } catch (...) {
+            hipStreamSynchronize(s);
+            for (void *p : tmp) hipFree(p);
+            throw;
+        }
+        DM_HIP(hipStreamSynchronize(s));
+        for (void *p : tmp) hipFree(p);
+        return rc;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Internal declarations of the Dey--Mittra eigensolver library.
+//
+// Field layout: padded SoA blocks of P = (Nx+2)(Ny+2)(Nz+2) elements, element
+// (i,j,k) at (i+1) + sy (j+1) + sz (k+1), x fastest; a face vector is the
+// three blocks b_x, b_y, b_z back to back.  Coefficient blocks per level:
+// ax ay az (face area fractions), lx ly lz (edge length fractions), vinv
+// (1 / cell volume fraction, 0 for cells outside the cavity).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dm.h"
+
+namespace dm {
+
+struct Grid {
+    int nx, ny, nz;
+    int sy;        // j stride = nx + 2
+    int64_t sz;    // k stride = (nx+2)(ny+2)
+    int64_t P;     // elements per block
+    double h;
+};
+
+inline Grid make_grid(int nx, int ny, int nz, double h) {
+    Grid g;
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.sy = nx + 2;
+    g.sz = (int64_t)(nx + 2) * (ny + 2);
+    g.P = g.sz * (nz + 2);
+    g.h = h;
+    return g;
+}
+
+__host__ __device__ inline int64_t pidx(const Grid &g, int i, int j, int k) {
+    return (int64_t)(i + 1) + (int64_t)(j + 1) * g.sy + (int64_t)(k + 1) * g.sz;
+}
+
+enum { CAX = 0, CAY, CAZ, CLX, CLY, CLZ, CVINV, NCOEF };
+
+template <class T>
+struct Coefs {
+    const T *ax, *ay, *az, *lx, *ly, *lz, *vinv;
+};
+
+template <class T>
+inline Coefs<T> coefs_of(const T *base, int64_t P) {
+    Coefs<T> c;
+    c.ax = base; c.ay = base + P; c.az = base + 2 * P;
+    c.lx = base + 3 * P; c.ly = base + 4 * P; c.lz = base + 5 * P;
+    c.vinv = base + 6 * P;
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Stencil rows of M (Sec. 2 eq. farInt for C L C^T, Sec. 5.1 eq. divBInt for
+// the grad-div part), without the 1/h^2 factor and without -sigma a x.
+// Shared by the GPU kernels and by the host assembly of the coarsest matrix.
+// ---------------------------------------------------------------------------
+
+// flux divergence of cell q (times vinv, no 1/h)
+template <class T>
+__host__ __device__ inline T cell_div(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+                                      int64_t q, int64_t dy, int64_t dz) {
+    return c.vinv[q] * (c.ax[q + 1] * X[q + 1] - c.ax[q] * X[q] + c.ay[q + dy] * Y[q + dy] -
+                        c.ay[q] * Y[q] + c.az[q + dz] * Z[q + dz] - c.az[q] * Z[q]);
+}
+
+template <class T, bool GD>
+__host__ __device__ inline T row_x(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+                                   int64_t p, int64_t dy, int64_t dz) {
+    const T wy0 = c.ly[p] * (X[p] - X[p - dz] - Z[p] + Z[p - 1]);
+    const T wyz = c.ly[p + dz] * (X[p + dz] - X[p] - Z[p + dz] + Z[p + dz - 1]);
+    const T wz0 = c.lz[p] * (Y[p] - Y[p - 1] - X[p] + X[p - dy]);
+    const T wzy = c.lz[p + dy] * (Y[p + dy] - Y[p + dy - 1] - X[p + dy] + X[p]);
+    T s = wy0 - wyz + wzy - wz0;
+    if (GD) s += c.ax[p] * (cell_div(c, X, Y, Z, p - 1, dy, dz) - cell_div(c, X, Y, Z, p, dy, dz));
+    return s;
+}
+
+template <class T, bool GD>
+__host__ __device__ inline T row_y(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+                                   int64_t p, int64_t dy, int64_t dz) {
+    const T wx0 = c.lx[p] * (Z[p] - Z[p - dy] - Y[p] + Y[p - dz]);
+    const T wxz = c.lx[p + dz] * (Z[p + dz] - Z[p + dz - dy] - Y[p + dz] + Y[p]);
+    const T wz0 = c.lz[p] * (Y[p] - Y[p - 1] - X[p] + X[p - dy]);
+    const T wzx = c.lz[p + 1] * (Y[p + 1] - Y[p] - X[p + 1] + X[p + 1 - dy]);
+    T s = -wx0 + wxz + wz0 - wzx;
+    if (GD) s += c.ay[p] * (cell_div(c, X, Y, Z, p - dy, dy, dz) - cell_div(c, X, Y, Z, p, dy, dz));
+    return s;
+}
+
+template <class T, bool GD>
+__host__ __device__ inline T row_z(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+                                   int64_t p, int64_t dy, int64_t dz) {
+    const T wx0 = c.lx[p] * (Z[p] - Z[p - dy] - Y[p] + Y[p - dz]);
+    const T wxy = c.lx[p + dy] * (Z[p + dy] - Z[p] - Y[p + dy] + Y[p + dy - dz]);
+    const T wy0 = c.ly[p] * (X[p] - X[p - dz] - Z[p] + Z[p - 1]);
+    const T wyx = c.ly[p + 1] * (X[p + 1] - X[p + 1 - dz] - Z[p + 1] + Z[p]);
+    T s = wx0 - wxy - wy0 + wyx;
+    if (GD) s += c.az[p] * (cell_div(c, X, Y, Z, p - dz, dy, dz) - cell_div(c, X, Y, Z, p, dy, dz));
+    return s;
+}
+
+// diagonal of M (with 1/h^2 and shift): d/dx_f of the row of face f
+template <class T>
+__host__ __device__ inline T diag_of(const Coefs<T> &c, int comp, int64_t p, int64_t dy,
+                                     int64_t dz, T inv_h2, T sigma) {
+    if (comp == 0)
+        return inv_h2 * (c.ly[p] + c.ly[p + dz] + c.lz[p] + c.lz[p + dy] +
+                         c.ax[p] * c.ax[p] * (c.vinv[p - 1] + c.vinv[p])) - sigma * c.ax[p];
+    if (comp == 1)
+        return inv_h2 * (c.lx[p] + c.lx[p + dz] + c.lz[p] + c.lz[p + 1] +
+                         c.ay[p] * c.ay[p] * (c.vinv[p - dy] + c.vinv[p])) - sigma * c.ay[p];
+    return inv_h2 * (c.lx[p] + c.lx[p + dy] + c.ly[p] + c.ly[p + 1] +
+                     c.az[p] * c.az[p] * (c.vinv[p - dz] + c.vinv[p])) - sigma * c.az[p];
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All take a stream; none synchronise.
+// ---------------------------------------------------------------------------
+enum ApplyKind { AK_M = 0, AK_K = 1, AK_RESID = 2 };
+
+template <class T>
+void launch_apply(const Grid &g, const T *coef, T sigma, int kind, const T *f, const T *x, T *y,
+                  hipStream_t s);
+template <class T>
+void launch_smooth(const Grid &g, const T *coef, T sigma, int comp, int colour, const T *f, T *x,
+                   hipStream_t s);
+template <class T>
+void launch_restrict(const Grid &gf, const Grid &gc, const T *coef_c, const T *r, T *fc,
+                     hipStream_t s);
+template <class T>
+void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T *xc, T *x,
+                        hipStream_t s);
+template <class TI, class TO>
+void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s);
+template <class T>
+void launch_coarse_solve(int n, const double *inv, const int64_t *idx, const T *f, T *x,
+                         hipStream_t s);
+void launch_apply_A(const Grid &g, const double *coef, const double *x, double *y, hipStream_t s);
+template <class T>
+void launch_apply_A_t(const Grid &g, const T *coef, const T *x, T *y, hipStream_t s);
+
+// scalar (cell-centred) Laplacian S = D A D^T with per-level weight `w`
+void launch_div_DA(const Grid &g, const double *coef, const double *b, double *gout,
+                   hipStream_t s);
+void launch_grad_sub(const Grid &g, const double *coef, const double *psi, double *b_in,
+                     double *b_out, double scale, hipStream_t s);
+void launch_s_apply(const Grid &g, const double *coef, double w, int resid, const double *f,
+                    const double *x, double *y, hipStream_t s);
+void launch_s_smooth(const Grid &g, const double *coef, double w, int colour, const double *f,
+                     double *x, hipStream_t s);
+void launch_s_restrict(const Grid &gf, const Grid &gc, const double *coef_c, const double *r,
+                       double *fc, hipStream_t s);
+void launch_s_prolong_add(const Grid &gf, const Grid &gc, const double *coef_f,
+                          const double *xc, double *x, hipStream_t s);
+
+// BLAS-1 style FP64 helpers on flat arrays
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+void launch_scale(int64_t n, double a, double *x, hipStream_t s);
+void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
+// out[i] = sum_n V_i[n] w[n] (wt[n]) for i < nv; V_i = V + i*ld; results left in
+// device buffer `dout` (nv doubles); `part` scratch of nv * kReduceBlocks doubles
+constexpr int kReduceBlocks = 512;
+void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
+                 int64_t n, double *part, double *dout, hipStream_t s);
+// y -= sum_i c[i] V_i  (c on device)  or  y = sum_i c[i] V_i when overwrite
+void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
+                  int overwrite, hipStream_t s);
+// fused Gram--Schmidt step (nv <= 32): w -= sum c_i V_i, then dout[0..nv-1] =
+// V_i . w and dout[nv] = |w|^2 (device results)
+void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
+                            int64_t n, double *part, double *dout, hipStream_t s);
+// out = scale * (w - sum c_i V_i)
+void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,
+                        double scale, double *out, int64_t n, hipStream_t s);
+// masked shift: x[n] -= scale * val[0] where mask[n] != 0 (val on device)
+void launch_sub_masked(int64_t n, const double *mask, const double *val, double scale, double *x,
+                       hipStream_t s);
+void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, double *x,
+                  hipStream_t s);
+void launch_mask_mul(int64_t n, const double *mask, double *x, hipStream_t s);
+
+}  // namespace dm

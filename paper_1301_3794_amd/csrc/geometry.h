@@ -1,0 +1,34 @@
+// Host-side cavity geometries and cut-fraction arrays (setup step).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "dm_internal.h"
+
+namespace dm {
+
+// A cavity interior Omega (open set).  Coordinates are physical; the grid
+// origin is 0.  Every method answers for the closed box / segment / face given.
+struct Body {
+    virtual ~Body() {}
+    // 1: the closed box lies in Omega; 0: it does not meet Omega; -1: cut
+    virtual int classify(const double *lo, const double *hi) const = 0;
+    // length of {p + t e_axis : t in [lo, hi]} inside Omega
+    virtual double edge_len(int axis, double lo, double hi, const double *p) const = 0;
+    // area inside Omega of the axis-normal face at coordinate c over
+    // [lo2[0],hi2[0]] x [lo2[1],hi2[1]] (other two axes in increasing order)
+    virtual double face_area(int axis, double c, const double *lo2, const double *hi2) const = 0;
+    // volume inside Omega of the box [lo, hi]
+    virtual double cell_vol(const double *lo, const double *hi) const = 0;
+};
+
+std::unique_ptr<Body> make_body(const dm_geometry &g);
+double disk_rect_area(double rho, double x0, double x1, double y0, double y1);
+void compute_fractions(const Body &body, const Grid &g, const int bc_lo[3],
+                       std::vector<double> &out);
+void neglect_faces(const Grid &g, double a_min, std::vector<double> &fr);
+void coarsen_fractions(const Grid &gf, const std::vector<double> &ff, const Grid &gc,
+                       std::vector<double> &fc);
+
+}  // namespace dm

@@ -1,0 +1,680 @@
+// HIP kernels of the Dey--Mittra eigensolver (gfx950, wave64).
+//
+// Stencil kernels map one thread to one cell (i,j,k); the cell owns its three
+// low faces b_x[i,j,k], b_y[i,j,k], b_z[i,j,k].  Blocks are remapped so that
+// each of the 8 XCDs (which receive workgroups round-robin) works on one
+// contiguous slab of the grid and keeps its stencil neighbours in its own L2.
+// The stencil path is memory bound: no MFMA here.
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+
+#include "dm_internal.h"
+
+namespace dm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kXcd = 8;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// grid of `n` work items in blocks of kThreads, padded to a multiple of 8 blocks
+inline dim3 xcd_grid(int64_t n) {
+    int64_t nb = ceil_div(n, kThreads);
+    int64_t per = ceil_div(nb, kXcd);
+    return dim3((unsigned)(per * kXcd));
+}
+
+// logical block of this workgroup: XCD x gets blocks [x*per, (x+1)*per)
+__device__ inline int64_t xcd_item() {
+    const int64_t per = gridDim.x / kXcd;
+    const int64_t b = blockIdx.x;
+    const int64_t logical = (b % kXcd) * per + b / kXcd;
+    return logical * kThreads + threadIdx.x;
+}
+
+__device__ inline bool cell_of(const Grid &g, int64_t t, int &i, int &j, int &k) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    if (t >= n) return false;
+    i = (int)(t % g.nx);
+    const int64_t r = t / g.nx;
+    j = (int)(r % g.ny);
+    k = (int)(r / g.ny);
+    return true;
+}
+
+template <class T>
+__device__ inline T inv_h2_of(const Grid &g) {
+    return (T)(1.0 / (g.h * g.h));
+}
+
+// ---------------------------------------------------------------------------
+// y = M x, y = K x, or r = f - M x
+// ---------------------------------------------------------------------------
+template <class T, int KIND>
+__global__ void __launch_bounds__(kThreads)
+k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restrict__ x,
+        T *__restrict__ y) {
+    int i, j, k;
+    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    const int64_t p = pidx(g, i, j, k);
+    const T *X = x, *Y = x + P, *Z = x + 2 * P;
+    const T ih2 = inv_h2_of<T>(g);
+    T yx, yy, yz;
+    if (KIND == AK_K) {
+        yx = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
+        yy = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
+        yz = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
+    } else {
+        yx = ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
+        yy = ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
+        yz = ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
+        if (KIND == AK_RESID) {
+            yx = f[p] - yx;
+            yy = f[P + p] - yy;
+            yz = f[2 * P + p] - yz;
+        }
+    }
+    y[p] = c.ax[p] != T(0) ? yx : T(0);
+    y[P + p] = c.ay[p] != T(0) ? yy : T(0);
+    y[2 * P + p] = c.az[p] != T(0) ? yz : T(0);
+}
+
+// y = A x
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+k_apply_A(Grid g, Coefs<T> c, const T *__restrict__ x, T *__restrict__ y) {
+    int i, j, k;
+    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    const int64_t P = g.P, p = pidx(g, i, j, k);
+    y[p] = c.ax[p] * x[p];
+    y[P + p] = c.ay[p] * x[P + p];
+    y[2 * P + p] = c.az[p] * x[2 * P + p];
+}
+
+// ---------------------------------------------------------------------------
+// Red-black Gauss--Seidel: one (component, colour) class, colour = (i+j+k)&1.
+// Threads cover half the cells of each row: i = 2*ih + ((j+k+colour)&1).
+// ---------------------------------------------------------------------------
+template <class T, int COMP>
+__global__ void __launch_bounds__(kThreads)
+k_smooth(Grid g, Coefs<T> c, T sigma, int colour, const T *__restrict__ f, T *__restrict__ x) {
+    const int nxh = (g.nx + 1) >> 1;
+    const int64_t t = xcd_item();
+    if (t >= (int64_t)nxh * g.ny * g.nz) return;
+    const int ih = (int)(t % nxh);
+    const int64_t r = t / nxh;
+    const int j = (int)(r % g.ny), k = (int)(r / g.ny);
+    const int i = 2 * ih + ((j + k + colour) & 1);
+    if (i >= g.nx) return;
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    const int64_t p = pidx(g, i, j, k);
+    T *X = x, *Y = x + P, *Z = x + 2 * P;
+    const T ih2 = inv_h2_of<T>(g);
+    const T *a = COMP == 0 ? c.ax : (COMP == 1 ? c.ay : c.az);
+    T *xc = COMP == 0 ? X : (COMP == 1 ? Y : Z);
+    if (a[p] == T(0)) return;
+    T row;
+    if (COMP == 0) row = row_x<T, true>(c, X, Y, Z, p, dy, dz);
+    else if (COMP == 1) row = row_y<T, true>(c, X, Y, Z, p, dy, dz);
+    else row = row_z<T, true>(c, X, Y, Z, p, dy, dz);
+    row = ih2 * row - sigma * a[p] * xc[p];
+    const T d = diag_of<T>(c, COMP, p, dy, dz, ih2, sigma);
+    xc[p] += (f[COMP * P + p] - row) / d;
+}
+
+// ---------------------------------------------------------------------------
+// Staggered transfers.  P: linear along the normal, constant across; R = P^T/8.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict__ fc) {
+    int I, J, K;
+    if (!cell_of(gc, xcd_item(), I, J, K)) return;
+    const int64_t Pf = gf.P, Pc = gc.P, fy = gf.sy, fz = gf.sz;
+    const int64_t pc = pidx(gc, I, J, K);
+    const T *RX = r, *RY = r + Pf, *RZ = r + 2 * Pf;
+    const int64_t q = pidx(gf, 2 * I, 2 * J, 2 * K);
+    T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            // x: tangential offsets in y (a) and z (b)
+            const int64_t qx = q + a * fy + b * fz;
+            sx += RX[qx] + T(0.5) * (RX[qx - 1] + RX[qx + 1]);
+            const int64_t qy = q + a + b * fz;
+            sy += RY[qy] + T(0.5) * (RY[qy - fy] + RY[qy + fy]);
+            const int64_t qz = q + a + b * fy;
+            sz += RZ[qz] + T(0.5) * (RZ[qz - fz] + RZ[qz + fz]);
+        }
+    const T e = T(0.125);
+    fc[pc] = cc.ax[pc] != T(0) ? e * sx : T(0);
+    fc[Pc + pc] = cc.ay[pc] != T(0) ? e * sy : T(0);
+    fc[2 * Pc + pc] = cc.az[pc] != T(0) ? e * sz : T(0);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, const T *__restrict__ xc, T *__restrict__ x) {
+    int i, j, k;
+    if (!cell_of(gf, xcd_item(), i, j, k)) return;
+    const int64_t Pf = gf.P, Pc = gc.P, cy = gc.sy, cz = gc.sz;
+    const int64_t p = pidx(gf, i, j, k);
+    const int64_t q = pidx(gc, i >> 1, j >> 1, k >> 1);
+    const T *CX = xc, *CY = xc + Pc, *CZ = xc + 2 * Pc;
+    if (cf.ax[p] != T(0)) x[p] += (i & 1) ? T(0.5) * (CX[q] + CX[q + 1]) : CX[q];
+    if (cf.ay[p] != T(0)) x[Pf + p] += (j & 1) ? T(0.5) * (CY[q] + CY[q + cy]) : CY[q];
+    if (cf.az[p] != T(0)) x[2 * Pf + p] += (k & 1) ? T(0.5) * (CZ[q] + CZ[q + cz]) : CZ[q];
+}
+
+template <class TI, class TO>
+__global__ void k_cast(const TI *__restrict__ in, TO *__restrict__ out, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads)
+        out[e] = (TO)in[e];
+}
+
+// Coarsest level: x[idx[r]] = sum_c inv[r, c] f[idx[c]] (FP64 arithmetic)
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+k_coarse_solve(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx,
+               const T *__restrict__ f, T *__restrict__ x) {
+    const int row = blockIdx.x;
+    double s = 0.0;
+    for (int col = threadIdx.x; col < n; col += kThreads)
+        s += inv[(int64_t)row * n + col] * (double)f[idx[col]];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double sh[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) t += sh[w];
+        x[idx[row]] = (T)t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scalar problem: g = D A b, b -= D^T psi, S = D A D^T (weight w per level)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+k_div_DA(Grid g, Coefs<double> c, const double *__restrict__ b, double *__restrict__ out) {
+    int i, j, k;
+    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    const int64_t P = g.P, dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
+    const double *X = b, *Y = b + P, *Z = b + 2 * P;
+    const double s = c.ax[p + 1] * X[p + 1] - c.ax[p] * X[p] + c.ay[p + dy] * Y[p + dy] -
+                     c.ay[p] * Y[p] + c.az[p + dz] * Z[p + dz] - c.az[p] * Z[p];
+    out[p] = c.vinv[p] != 0.0 ? s / g.h : 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_grad_sub(Grid g, Coefs<double> c, const double *__restrict__ psi, const double *bin,
+           double *bout, double scale) {
+    int i, j, k;
+    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    const int64_t P = g.P, dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
+    const double s = scale / g.h;
+    const double pp = psi[p];
+    bout[p] = c.ax[p] != 0.0 ? bin[p] - s * (psi[p - 1] - pp) : 0.0;
+    bout[P + p] = c.ay[p] != 0.0 ? bin[P + p] - s * (psi[p - dy] - pp) : 0.0;
+    bout[2 * P + p] = c.az[p] != 0.0 ? bin[2 * P + p] - s * (psi[p - dz] - pp) : 0.0;
+}
+
+__device__ inline double s_row(const Coefs<double> &c, const double *x, int64_t p, int64_t dy,
+                               int64_t dz) {
+    const double xp = x[p];
+    return c.ax[p] * (xp - x[p - 1]) + c.ax[p + 1] * (xp - x[p + 1]) +
+           c.ay[p] * (xp - x[p - dy]) + c.ay[p + dy] * (xp - x[p + dy]) +
+           c.az[p] * (xp - x[p - dz]) + c.az[p + dz] * (xp - x[p + dz]);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_s_apply(Grid g, Coefs<double> c, double w, int resid, const double *__restrict__ f,
+          const double *__restrict__ x, double *__restrict__ y) {
+    int i, j, k;
+    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    const int64_t p = pidx(g, i, j, k);
+    double v = w * s_row(c, x, p, g.sy, g.sz);
+    if (resid) v = f[p] - v;
+    y[p] = c.vinv[p] != 0.0 ? v : 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_s_smooth(Grid g, Coefs<double> c, double w, int colour, const double *__restrict__ f,
+           double *__restrict__ x) {
+    const int nxh = (g.nx + 1) >> 1;
+    const int64_t t = xcd_item();
+    if (t >= (int64_t)nxh * g.ny * g.nz) return;
+    const int ih = (int)(t % nxh);
+    const int64_t r = t / nxh;
+    const int j = (int)(r % g.ny), k = (int)(r / g.ny);
+    const int i = 2 * ih + ((j + k + colour) & 1);
+    if (i >= g.nx) return;
+    const int64_t dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
+    if (c.vinv[p] == 0.0) return;
+    const double d = w * (c.ax[p] + c.ax[p + 1] + c.ay[p] + c.ay[p + dy] + c.az[p] + c.az[p + dz]);
+    if (d == 0.0) return;
+    x[p] += (f[p] - w * s_row(c, x, p, dy, dz)) / d;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_s_restrict(Grid gf, Grid gc, Coefs<double> cc, const double *__restrict__ r,
+             double *__restrict__ fc) {
+    int I, J, K;
+    if (!cell_of(gc, xcd_item(), I, J, K)) return;
+    const int64_t pc = pidx(gc, I, J, K), q = pidx(gf, 2 * I, 2 * J, 2 * K);
+    const int64_t fy = gf.sy, fz = gf.sz;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) s += r[q + a * fy + b * fz] + r[q + 1 + a * fy + b * fz];
+    fc[pc] = cc.vinv[pc] != 0.0 ? 0.125 * s : 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_s_prolong_add(Grid gf, Grid gc, Coefs<double> cf, const double *__restrict__ xc,
+                double *__restrict__ x) {
+    int i, j, k;
+    if (!cell_of(gf, xcd_item(), i, j, k)) return;
+    const int64_t p = pidx(gf, i, j, k);
+    if (cf.vinv[p] != 0.0) x[p] += xc[pidx(gc, i >> 1, j >> 1, k >> 1)];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 vector helpers
+// ---------------------------------------------------------------------------
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b,
+                        double *__restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads)
+        y[e] = a * x[e] + b * y[e];
+}
+
+__global__ void k_axpy(int64_t n, double a, const double *__restrict__ x, double *__restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads)
+        y[e] += a * x[e];
+}
+
+__global__ void k_scale(int64_t n, double a, double *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads)
+        x[e] *= a;
+}
+
+constexpr int kChunk = 8;  // vectors reduced per pass of k_mdot
+
+__global__ void __launch_bounds__(kThreads)
+k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
+       const double *__restrict__ wt, int64_t n, double *__restrict__ part) {
+    __shared__ double sh[kThreads / 64][kChunk];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < nv; c0 += kChunk) {
+        const int cn = min(kChunk, nv - c0);
+        double acc[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) acc[q] = 0.0;
+        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+             e += (int64_t)gridDim.x * kThreads) {
+            double wv = w[e];
+            if (wt) wv *= wt[e];
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q)
+                if (q < cn) acc[q] += V[(int64_t)(c0 + q) * ld + e] * wv;
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            double v = acc[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) sh[wave][q] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < cn) {
+            double s = 0.0;
+            for (int u = 0; u < kThreads / 64; ++u) s += sh[u][threadIdx.x];
+            part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_mdot_final(int nblk, const double *__restrict__ part, double *__restrict__ out) {
+    const int v = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(int64_t)v * nblk + b];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double sh[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int u = 0; u < kThreads / 64; ++u) t += sh[u];
+        out[v] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
+        double *__restrict__ y, int64_t n, int overwrite) {
+    __shared__ double cs[256];
+    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads) {
+        double s = 0.0;
+        for (int q = 0; q < nv; ++q) s += cs[q] * V[(int64_t)q * ld + e];
+        y[e] = overwrite ? s : y[e] - s;
+    }
+}
+
+// Fused Gram--Schmidt step for nv <= kFuseMax basis vectors:
+//   w' = w - sum_i c_i V_i      (written back to w)
+//   part: dots V_i . w' (rows 0..nv-1) and |w'|^2 (row nv)
+// One read of the basis serves both the update and the dots.
+constexpr int kFuseMax = 32;
+
+__global__ void __launch_bounds__(kThreads)
+k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
+                  double *__restrict__ w, int64_t n, double *__restrict__ part) {
+    __shared__ double cs[kFuseMax];
+    __shared__ double sh[kThreads / 64][kFuseMax + 1];
+    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
+    __syncthreads();
+    double acc[kFuseMax + 1];
+#pragma unroll
+    for (int q = 0; q <= kFuseMax; ++q) acc[q] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads) {
+        double vv[kFuseMax];
+        double s = w[e];
+#pragma unroll
+        for (int q = 0; q < kFuseMax; ++q)
+            if (q < nv) {
+                vv[q] = V[(int64_t)q * ld + e];
+                s -= cs[q] * vv[q];
+            }
+        w[e] = s;
+#pragma unroll
+        for (int q = 0; q < kFuseMax; ++q)
+            if (q < nv) acc[q] += vv[q] * s;
+        acc[kFuseMax] += s * s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q <= kFuseMax; ++q) {
+        if (q < nv || q == kFuseMax) {
+            double v = acc[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) sh[wave][q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= nv) {
+        const int q = threadIdx.x < nv ? threadIdx.x : kFuseMax;
+        double s = 0.0;
+        for (int u = 0; u < kThreads / 64; ++u) s += sh[u][q];
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// out = scale * (w - sum_i c_i V_i)
+__global__ void __launch_bounds__(kThreads)
+k_maxpy_scale(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
+              const double *__restrict__ w, double scale, double *__restrict__ out, int64_t n) {
+    __shared__ double cs[256];
+    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads) {
+        double s = w[e];
+        for (int q = 0; q < nv; ++q) s -= cs[q] * V[(int64_t)q * ld + e];
+        out[e] = scale * s;
+    }
+}
+
+__global__ void k_sub_masked(int64_t n, const double *__restrict__ mask,
+                             const double *__restrict__ val, double scale, double *__restrict__ x) {
+    const double m = val[0] * scale;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads)
+        if (mask[e] != 0.0) x[e] -= m;
+}
+
+__global__ void k_mask_mul(int64_t n, const double *__restrict__ mask, double *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads)
+        if (mask[e] == 0.0) x[e] = 0.0;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) used as a counter-based hash:
+// the value for counter c is the generator's output after c+1 steps from seed.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_randn(int64_t n, uint64_t seed, int64_t offset, const double *__restrict__ mask,
+                        double *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kThreads) {
+        if (mask[e] == 0.0) {
+            x[e] = 0.0;
+            continue;
+        }
+        const uint64_t c = 2 * (uint64_t)(e + offset);
+        const double u1 = ((double)(splitmix64_at(seed, c) >> 11) + 1.0) * 0x1.0p-53;
+        const double u2 = (double)(splitmix64_at(seed, c + 1) >> 11) * 0x1.0p-53;
+        x[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+inline dim3 flat_grid(int64_t n) {
+    int64_t nb = ceil_div(n, kThreads);
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    return dim3((unsigned)nb);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <class T>
+void launch_apply(const Grid &g, const T *coef, T sigma, int kind, const T *f, const T *x, T *y,
+                  hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    Coefs<T> c = coefs_of(coef, g.P);
+    if (kind == AK_M)
+        hipLaunchKernelGGL((k_apply<T, AK_M>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma, f, x, y);
+    else if (kind == AK_K)
+        hipLaunchKernelGGL((k_apply<T, AK_K>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma, f, x, y);
+    else
+        hipLaunchKernelGGL((k_apply<T, AK_RESID>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma, f, x, y);
+}
+
+template <class T>
+void launch_apply_A_t(const Grid &g, const T *coef, const T *x, T *y, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL((k_apply_A<T>), xcd_grid(n), dim3(kThreads), 0, s, g, coefs_of(coef, g.P), x, y);
+}
+
+void launch_apply_A(const Grid &g, const double *coef, const double *x, double *y, hipStream_t s) {
+    launch_apply_A_t<double>(g, coef, x, y, s);
+}
+
+template <class T>
+void launch_smooth(const Grid &g, const T *coef, T sigma, int comp, int colour, const T *f, T *x,
+                   hipStream_t s) {
+    const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
+    Coefs<T> c = coefs_of(coef, g.P);
+    if (comp == 0)
+        hipLaunchKernelGGL((k_smooth<T, 0>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma, colour, f, x);
+    else if (comp == 1)
+        hipLaunchKernelGGL((k_smooth<T, 1>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma, colour, f, x);
+    else
+        hipLaunchKernelGGL((k_smooth<T, 2>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma, colour, f, x);
+}
+
+template <class T>
+void launch_restrict(const Grid &gf, const Grid &gc, const T *coef_c, const T *r, T *fc,
+                     hipStream_t s) {
+    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+    hipLaunchKernelGGL((k_restrict<T>), xcd_grid(n), dim3(kThreads), 0, s, gf, gc,
+                       coefs_of(coef_c, gc.P), r, fc);
+}
+
+template <class T>
+void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T *xc, T *x,
+                        hipStream_t s) {
+    const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
+    hipLaunchKernelGGL((k_prolong_add<T>), xcd_grid(n), dim3(kThreads), 0, s, gf, gc,
+                       coefs_of(coef_f, gf.P), xc, x);
+}
+
+template <class TI, class TO>
+void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_cast<TI, TO>), flat_grid(n), dim3(kThreads), 0, s, in, out, n);
+}
+
+template <class T>
+void launch_coarse_solve(int n, const double *inv, const int64_t *idx, const T *f, T *x,
+                         hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(n), dim3(kThreads), 0, s, n, inv, idx, f, x);
+}
+
+void launch_div_DA(const Grid &g, const double *coef, const double *b, double *gout,
+                   hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_div_DA, xcd_grid(n), dim3(kThreads), 0, s, g, coefs_of(coef, g.P), b, gout);
+}
+
+void launch_grad_sub(const Grid &g, const double *coef, const double *psi, double *b_in,
+                     double *b_out, double scale, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_grad_sub, xcd_grid(n), dim3(kThreads), 0, s, g, coefs_of(coef, g.P), psi,
+                       (const double *)b_in, b_out, scale);
+}
+
+void launch_s_apply(const Grid &g, const double *coef, double w, int resid, const double *f,
+                    const double *x, double *y, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_s_apply, xcd_grid(n), dim3(kThreads), 0, s, g, coefs_of(coef, g.P), w,
+                       resid, f, x, y);
+}
+
+void launch_s_smooth(const Grid &g, const double *coef, double w, int colour, const double *f,
+                     double *x, hipStream_t s) {
+    const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
+    hipLaunchKernelGGL(k_s_smooth, xcd_grid(n), dim3(kThreads), 0, s, g, coefs_of(coef, g.P), w,
+                       colour, f, x);
+}
+
+void launch_s_restrict(const Grid &gf, const Grid &gc, const double *coef_c, const double *r,
+                       double *fc, hipStream_t s) {
+    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+    hipLaunchKernelGGL(k_s_restrict, xcd_grid(n), dim3(kThreads), 0, s, gf, gc,
+                       coefs_of(coef_c, gc.P), r, fc);
+}
+
+void launch_s_prolong_add(const Grid &gf, const Grid &gc, const double *coef_f,
+                          const double *xc, double *x, hipStream_t s) {
+    const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
+    hipLaunchKernelGGL(k_s_prolong_add, xcd_grid(n), dim3(kThreads), 0, s, gf, gc,
+                       coefs_of(coef_f, gf.P), xc, x);
+}
+
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, flat_grid(n), dim3(kThreads), 0, s, n, a, x, y);
+}
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, flat_grid(n), dim3(kThreads), 0, s, n, a, x, b, y);
+}
+void launch_scale(int64_t n, double a, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale, flat_grid(n), dim3(kThreads), 0, s, n, a, x);
+}
+void launch_copy(int64_t n, const double *x, double *y, hipStream_t s) {
+    hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+}
+
+void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
+                 int64_t n, double *part, double *dout, hipStream_t s) {
+    if (nv <= 0) return;
+    if (nv > 256) throw std::runtime_error("launch_mdot: more than 256 vectors");
+    hipLaunchKernelGGL(k_mdot, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part);
+    hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kThreads), 0, s, (int)kReduceBlocks,
+                       (const double *)part, dout);
+}
+
+void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
+                  int overwrite, hipStream_t s) {
+    if (nv <= 0 && !overwrite) return;
+    if (nv > 256) throw std::runtime_error("launch_maxpy: more than 256 vectors");
+    hipLaunchKernelGGL(k_maxpy, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, y, n, overwrite);
+}
+
+void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
+                            int64_t n, double *part, double *dout, hipStream_t s) {
+    if (nv < 1 || nv > kFuseMax) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
+    hipLaunchKernelGGL(k_maxpy_mdot_norm, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, c, w, n, part);
+    hipLaunchKernelGGL(k_mdot_final, dim3(nv + 1), dim3(kThreads), 0, s, (int)kReduceBlocks,
+                       (const double *)part, dout);
+}
+
+void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,
+                        double scale, double *out, int64_t n, hipStream_t s) {
+    if (nv < 0 || nv > 256) throw std::runtime_error("launch_maxpy_scale: nv out of range");
+    hipLaunchKernelGGL(k_maxpy_scale, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, w, scale, out, n);
+}
+
+void launch_sub_masked(int64_t n, const double *mask, const double *val, double scale, double *x,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_masked, flat_grid(n), dim3(kThreads), 0, s, n, mask, val, scale, x);
+}
+
+void launch_mask_mul(int64_t n, const double *mask, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_mul, flat_grid(n), dim3(kThreads), 0, s, n, mask, x);
+}
+
+void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, double *x,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_randn, flat_grid(n), dim3(kThreads), 0, s, n, seed, offset, mask, x);
+}
+
+// explicit instantiations
+template void launch_apply<double>(const Grid &, const double *, double, int, const double *,
+                                   const double *, double *, hipStream_t);
+template void launch_apply<float>(const Grid &, const float *, float, int, const float *,
+                                  const float *, float *, hipStream_t);
+template void launch_apply_A_t<float>(const Grid &, const float *, const float *, float *, hipStream_t);
+template void launch_apply_A_t<double>(const Grid &, const double *, const double *, double *, hipStream_t);
+template void launch_smooth<double>(const Grid &, const double *, double, int, int, const double *,
+                                    double *, hipStream_t);
+template void launch_smooth<float>(const Grid &, const float *, float, int, int, const float *,
+                                   float *, hipStream_t);
+template void launch_restrict<double>(const Grid &, const Grid &, const double *, const double *,
+                                      double *, hipStream_t);
+template void launch_restrict<float>(const Grid &, const Grid &, const float *, const float *,
+                                     float *, hipStream_t);
+template void launch_prolong_add<double>(const Grid &, const Grid &, const double *, const double *,
+                                         double *, hipStream_t);
+template void launch_prolong_add<float>(const Grid &, const Grid &, const float *, const float *,
+                                        float *, hipStream_t);
+template void launch_cast<double, float>(const double *, float *, int64_t, hipStream_t);
+template void launch_cast<float, double>(const float *, double *, int64_t, hipStream_t);
+template void launch_coarse_solve<double>(int, const double *, const int64_t *, const double *,
+                                          double *, hipStream_t);
+template void launch_coarse_solve<float>(int, const double *, const int64_t *, const float *,
+                                         float *, hipStream_t);
+
+}  // namespace dm

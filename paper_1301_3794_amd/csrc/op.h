@@ -1,0 +1,117 @@
+// The operator object behind the C ABI: level hierarchy, device buffers,
+// coarsest-level dense inverses and Krylov workspaces.
+#pragma once
+
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "dm_internal.h"
+
+namespace dm {
+
+struct Level {
+    Grid g;
+    double *coef64 = nullptr;  // 7P: ax ay az lx ly lz vinv
+    float *coef32 = nullptr;   // same, FP32
+    double sweight = 0.0;      // weight of the scalar Laplacian on this level
+    double *x64 = nullptr, *f64 = nullptr, *r64 = nullptr;  // 3P each
+    float *x32 = nullptr, *f32 = nullptr, *r32 = nullptr;   // 3P each
+    double *sx = nullptr, *sf = nullptr, *sr = nullptr;     // P each (scalar MG)
+    int64_t n_act_faces = 0, n_act_cells = 0;
+};
+
+// thread-local error reporting
+void set_error(const std::string &msg);
+
+struct HipError {
+    hipError_t e;
+    std::string where;
+};
+
+#define DM_HIP(call)                                                        \
+    do {                                                                    \
+        hipError_t e__ = (call);                                            \
+        if (e__ != hipSuccess) throw ::dm::HipError{e__, #call};            \
+    } while (0)
+
+struct DmError {
+    int code;
+    std::string msg;
+};
+
+}  // namespace dm
+
+struct dm_op {
+    dm_geometry geom{};
+    int dims[3] = {0, 0, 0};
+    double h = 0.0, sigma = 0.0;
+    dm_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<dm::Level> lv;
+    std::vector<std::vector<double>> frac;  // host fractions per level (7P, v not vinv)
+    // coarsest vector level: dense FP64 inverse over active faces
+    int nc = 0;
+    double *cinv = nullptr;
+    int64_t *cidx = nullptr;
+    // coarsest scalar level
+    int ns = 0;
+    double *sinv = nullptr;
+    int64_t *sidx = nullptr;
+    bool s_floating = true;
+    // level-0 masks
+    double *fmask = nullptr;  // 3P, 1 on active faces
+    double *cmask = nullptr;  // P, 1 on active cells
+    // reductions
+    double *part = nullptr;   // kReduceBlocks * kMaxDots
+    double *dres = nullptr;   // kMaxDots device results
+    double *hres = nullptr;   // kMaxDots pinned host results
+    // Krylov workspaces (allocated on first use)
+    int fg_m = 0;
+    double *fg_V = nullptr, *fg_Z = nullptr, *fg_w = nullptr, *dcoef = nullptr;
+    float *fg_f32 = nullptr, *fg_x32 = nullptr;
+    double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
+    double *pj_g = nullptr, *pj_psi = nullptr, *pj_r = nullptr, *pj_z = nullptr,
+           *pj_p = nullptr, *pj_q = nullptr;
+    int eg_cap = 0;
+    double *eg_V = nullptr, *eg_W = nullptr, *eg_T = nullptr;
+    std::vector<void *> allocs;  // everything to free
+    int last_proj_iters = 0;
+
+    template <class T>
+    T *dalloc(size_t count) {
+        void *p = nullptr;
+        DM_HIP(hipMalloc(&p, count * sizeof(T) + 256));
+        allocs.push_back(p);
+        DM_HIP(hipMemsetAsync(p, 0, count * sizeof(T) + 256, stream));
+        return (T *)p;
+    }
+    int nlev() const { return (int)lv.size(); }
+    int64_t n0() const { return 3 * lv[0].g.P; }
+};
+
+namespace dm {
+
+constexpr int kMaxDots = 256;
+
+// op.cpp
+void build_hierarchy(dm_op *op, const double *user_frac);
+void factor_coarse(dm_op *op);
+double host_dot_sync(dm_op *op, hipStream_t s);
+
+// solver.cpp
+template <class T>
+void vcycle(dm_op *op, int level, const T *f, T *x, hipStream_t s);
+void svcycle(dm_op *op, int level, const double *f, double *x, hipStream_t s);
+// device dots; results copied to op->hres (synchronises the stream)
+void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const double *wt,
+          int64_t n, hipStream_t s);
+int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hipStream_t s,
+            int *iters);
+int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
+          dm_solve_info *info, hipStream_t s);
+int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt, double *lam,
+         double *vecs, double *res, dm_eig_info *info, hipStream_t s);
+
+}  // namespace dm

@@ -1,0 +1,661 @@
+// Host-driven solvers over the HIP kernels:
+//  * V-cycles for M (FP64 or FP32) and for the scalar Laplacian S = D A D^T;
+//  * the divergence projection P_DM (eq. proj) by multigrid-preconditioned CG;
+//  * FGMRES (FP64, right-preconditioned by a V-cycle of either precision) and
+//    PCG for M x = f (Sec. 6: the inner inversions);
+//  * block Krylov--Schur on T = P_DM M^-1 A in the A-inner product
+//    (eqs. fullMat, bInner) with Rayleigh quotients and residuals on (K, A).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+
+#include "op.h"
+
+namespace dm {
+
+namespace {
+
+template <class T>
+struct Prec;
+template <>
+struct Prec<double> {
+    static const double *coef(const Level &L) { return L.coef64; }
+    static double *x(Level &L) { return L.x64; }
+    static double *f(Level &L) { return L.f64; }
+    static double *r(Level &L) { return L.r64; }
+};
+template <>
+struct Prec<float> {
+    static const float *coef(const Level &L) { return L.coef32; }
+    static float *x(Level &L) { return L.x32; }
+    static float *f(Level &L) { return L.f32; }
+    static float *r(Level &L) { return L.r32; }
+};
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Symmetric eigendecomposition of a small dense matrix by cyclic Jacobi
+// rotations.  a: n x n row-major (destroyed); w: eigenvalues; v: columns.
+void jacobi_eig(std::vector<double> a, int n, std::vector<double> &w, std::vector<double> &v) {
+    v.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double x = a[(size_t)i * n + j] * a[(size_t)i * n + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-32 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+                    a[(size_t)k * n + p] = c * akp - s * akq;
+                    a[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+                    a[(size_t)p * n + k] = c * apk - s * aqk;
+                    a[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+                    v[(size_t)k * n + p] = c * vkp - s * vkq;
+                    v[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
+}
+
+double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n,
+            hipStream_t s) {
+    dots(op, 1, x, 0, y, wt, n, s);
+    return op->hres[0];
+}
+
+void to_device_coef(dm_op *op, const double *h, int nv, hipStream_t s) {
+    DM_HIP(hipMemcpyAsync(op->dcoef, h, nv * sizeof(double), hipMemcpyHostToDevice, s));
+}
+
+// x -= mean of x over active cells (device-side, no host sync)
+void demean_cells(dm_op *op, double *x, hipStream_t s) {
+    const Level &L = op->lv[0];
+    launch_mdot(1, x, 0, op->cmask, nullptr, L.g.P, op->part, op->dres, s);
+    launch_sub_masked(L.g.P, op->cmask, op->dres, 1.0 / (double)std::max<int64_t>(1, L.n_act_cells), x, s);
+}
+
+void ensure_krylov(dm_op *op) {
+    const int64_t n = op->n0();
+    if (!op->fg_V) {
+        const int m = op->opt.fgmres_restart;
+        op->fg_m = m;
+        // at least 3 vectors: PCG borrows r, z, p from this block
+        op->fg_V = op->dalloc<double>((size_t)std::max(m + 1, 3) * n);
+        op->fg_Z = op->dalloc<double>((size_t)m * n);
+        op->fg_w = op->dalloc<double>(n);
+        op->fg_f32 = op->dalloc<float>(n);
+        op->fg_x32 = op->dalloc<float>(n);
+        op->dcoef = op->dalloc<double>(kMaxDots);
+    }
+}
+
+void ensure_proj(dm_op *op) {
+    if (!op->pj_g) {
+        const int64_t P = op->lv[0].g.P;
+        op->pj_g = op->dalloc<double>(P);
+        op->pj_psi = op->dalloc<double>(P);
+        op->pj_r = op->dalloc<double>(P);
+        op->pj_z = op->dalloc<double>(P);
+        op->pj_p = op->dalloc<double>(P);
+        op->pj_q = op->dalloc<double>(P);
+    }
+}
+
+void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s) {
+    const int64_t n = op->n0();
+    if (mode == DM_SOLVE_FGMRES_MG32) {
+        launch_cast<double, float>(v, op->fg_f32, n, s);
+        vcycle<float>(op, 0, op->fg_f32, op->fg_x32, s);
+        launch_cast<float, double>(op->fg_x32, z, n, s);
+    } else {
+        vcycle<double>(op, 0, v, z, s);
+    }
+}
+
+int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
+           dm_solve_info *info, hipStream_t s) {
+    ensure_krylov(op);
+    const Level &L = op->lv[0];
+    const int64_t n = op->n0();
+    const int m = op->fg_m;
+    double *V = op->fg_V, *Z = op->fg_Z, *w = op->fg_w;
+    DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    const double bnorm = std::sqrt(dot1(op, f, f, nullptr, n, s));
+    int total = 0, restarts = 0;
+    double rel = 0.0;
+    if (bnorm == 0.0) {
+        if (info) *info = dm_solve_info{0, 0, 0.0, 0.0};
+        return DM_OK;
+    }
+    if (!std::isfinite(bnorm)) throw DmError{DM_ENAN, "right-hand side is not finite"};
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1);
+    bool conv = false;
+    while (true) {
+        if (total == 0) launch_copy(n, f, V, s);
+        else launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, V, s);
+        const double beta = std::sqrt(dot1(op, V, V, nullptr, n, s));
+        if (!std::isfinite(beta)) throw DmError{DM_ENAN, "FGMRES residual is not finite"};
+        rel = beta / bnorm;
+        if (beta <= rtol * bnorm) {
+            conv = true;
+            break;
+        }
+        if (total >= maxit) break;
+        launch_scale(n, 1.0 / beta, V, s);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        std::fill(H.begin(), H.end(), 0.0);
+        int j = 0;
+        for (; j < m;) {
+            double *vj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n;
+            precondition(op, mode, vj, zj, s);
+            launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, zj, w, s);
+            // classical Gram--Schmidt twice, in three passes over the basis:
+            // (1) h = V^T w; (2) w -= V h fused with h2 = V^T w, |w|^2;
+            // (3) v_{j+1} = (w - V h2) / |w - V h2|, the norm from Pythagoras
+            // (h2 is the tiny re-orthogonalisation correction)
+            dots(op, j + 1, V, n, w, nullptr, n, s);
+            std::copy(op->hres, op->hres + j + 1, h.begin());
+            to_device_coef(op, h.data(), j + 1, s);
+            double wn2;
+            if (j + 1 <= 32) {
+                launch_maxpy_mdot_norm(j + 1, V, n, op->dcoef, w, n, op->part, op->dres, s);
+                DM_HIP(hipMemcpyAsync(op->hres, op->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+                DM_HIP(hipStreamSynchronize(s));
+                std::copy(op->hres, op->hres + j + 1, h2.begin());
+                wn2 = op->hres[j + 1];
+            } else {
+                launch_maxpy(j + 1, V, n, op->dcoef, w, n, 0, s);
+                dots(op, j + 1, V, n, w, nullptr, n, s);
+                std::copy(op->hres, op->hres + j + 1, h2.begin());
+                wn2 = dot1(op, w, w, nullptr, n, s);
+            }
+            double c2 = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                h[i] += h2[i];
+                c2 += h2[i] * h2[i];
+            }
+            const double hn = std::sqrt(std::max(wn2 - c2, 0.0));
+            if (!std::isfinite(hn)) throw DmError{DM_ENAN, "FGMRES iterate is not finite"};
+            to_device_coef(op, h2.data(), j + 1, s);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            const double r = std::hypot(a, b);
+            cs[j] = r > 0 ? a / r : 1.0;
+            sn[j] = r > 0 ? b / r : 0.0;
+            H[(size_t)j * m + j] = r;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            ++j;
+            if (hn > 0.0) launch_maxpy_scale(j, V, n, op->dcoef, w, 1.0 / hn, V + (int64_t)j * n, n, s);
+            if (std::fabs(g[j]) <= rtol * bnorm || total >= maxit || hn == 0.0) break;
+        }
+        for (int i = j - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int c = i + 1; c < j; ++c) t -= H[(size_t)i * m + c] * y[c];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i < j; ++i) h[i] = -y[i];
+        to_device_coef(op, h.data(), j, s);
+        launch_maxpy(j, Z, n, op->dcoef, x, n, 0, s);
+        ++restarts;
+    }
+    if (info) {
+        info->iterations = total;
+        info->restarts = restarts > 0 ? restarts - 1 : 0;
+        info->rel_residual = rel;
+    }
+    return conv ? DM_OK : DM_NOT_CONVERGED;
+}
+
+int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_info *info,
+        hipStream_t s) {
+    ensure_krylov(op);
+    const Level &L = op->lv[0];
+    const int64_t n = op->n0();
+    double *r = op->fg_V, *z = op->fg_V + n, *p = op->fg_V + 2 * n, *q = op->fg_w;
+    DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    const double bnorm = std::sqrt(dot1(op, f, f, nullptr, n, s));
+    if (bnorm == 0.0) {
+        if (info) *info = dm_solve_info{0, 0, 0.0, 0.0};
+        return DM_OK;
+    }
+    launch_copy(n, f, r, s);
+    vcycle<double>(op, 0, r, z, s);
+    launch_copy(n, z, p, s);
+    double rz = dot1(op, r, z, nullptr, n, s);
+    int it = 0;
+    double rel = 1.0;
+    bool conv = false;
+    while (it < maxit) {
+        launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, p, q, s);
+        const double pq = dot1(op, p, q, nullptr, n, s);
+        if (!(pq > 0.0)) throw DmError{pq == pq ? DM_EBREAKDOWN : DM_ENAN,
+                                       "PCG: operator not positive definite at this shift"};
+        const double alpha = rz / pq;
+        launch_axpy(n, alpha, p, x, s);
+        launch_axpy(n, -alpha, q, r, s);
+        ++it;
+        rel = std::sqrt(dot1(op, r, r, nullptr, n, s)) / bnorm;
+        if (!std::isfinite(rel)) throw DmError{DM_ENAN, "PCG residual is not finite"};
+        if (rel <= rtol) {
+            conv = true;
+            break;
+        }
+        vcycle<double>(op, 0, r, z, s);
+        const double rz2 = dot1(op, r, z, nullptr, n, s);
+        launch_axpby(n, 1.0, z, rz2 / rz, p, s);
+        rz = rz2;
+    }
+    // true residual
+    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, r, s);
+    rel = std::sqrt(dot1(op, r, r, nullptr, n, s)) / bnorm;
+    if (info) {
+        info->iterations = it;
+        info->restarts = 0;
+        info->rel_residual = rel;
+    }
+    return conv ? DM_OK : DM_NOT_CONVERGED;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const double *wt,
+          int64_t n, hipStream_t s) {
+    launch_mdot(nv, V, ld, w, wt, n, op->part, op->dres, s);
+    DM_HIP(hipMemcpyAsync(op->hres, op->dres, nv * sizeof(double), hipMemcpyDeviceToHost, s));
+    DM_HIP(hipStreamSynchronize(s));
+}
+
+template <class T>
+void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
+    Level &L = op->lv[l];
+    const Grid &g = L.g;
+    const T sig = (T)op->sigma;
+    DM_HIP(hipMemsetAsync(x, 0, 3 * g.P * sizeof(T), s));
+    if (l == op->nlev() - 1) {
+        launch_coarse_solve<T>(op->nc, op->cinv, op->cidx, f, x, s);
+        return;
+    }
+    const T *c = Prec<T>::coef(L);
+    for (int it = 0; it < op->opt.nu_pre; ++it)
+        for (int comp = 0; comp < 3; ++comp)
+            for (int col = 0; col < 2; ++col) launch_smooth<T>(g, c, sig, comp, col, f, x, s);
+    T *r = Prec<T>::r(L);
+    launch_apply<T>(g, c, sig, AK_RESID, f, x, r, s);
+    Level &C = op->lv[l + 1];
+    T *fc = Prec<T>::f(C), *xc = Prec<T>::x(C);
+    launch_restrict<T>(g, C.g, Prec<T>::coef(C), r, fc, s);
+    vcycle<T>(op, l + 1, fc, xc, s);
+    launch_prolong_add<T>(g, C.g, c, xc, x, s);
+    for (int it = 0; it < op->opt.nu_post; ++it)
+        for (int comp = 2; comp >= 0; --comp)
+            for (int col = 1; col >= 0; --col) launch_smooth<T>(g, c, sig, comp, col, f, x, s);
+}
+
+template void vcycle<double>(dm_op *, int, const double *, double *, hipStream_t);
+template void vcycle<float>(dm_op *, int, const float *, float *, hipStream_t);
+
+void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
+    Level &L = op->lv[l];
+    const Grid &g = L.g;
+    DM_HIP(hipMemsetAsync(x, 0, g.P * sizeof(double), s));
+    if (l == op->nlev() - 1) {
+        launch_coarse_solve<double>(op->ns, op->sinv, op->sidx, f, x, s);
+        return;
+    }
+    for (int it = 0; it < op->opt.nu_pre; ++it)
+        for (int col = 0; col < 2; ++col) launch_s_smooth(g, L.coef64, L.sweight, col, f, x, s);
+    launch_s_apply(g, L.coef64, L.sweight, 1, f, x, L.sr, s);
+    Level &C = op->lv[l + 1];
+    launch_s_restrict(g, C.g, C.coef64, L.sr, C.sf, s);
+    svcycle(op, l + 1, C.sf, C.sx, s);
+    launch_s_prolong_add(g, C.g, L.coef64, C.sx, x, s);
+    for (int it = 0; it < op->opt.nu_post; ++it)
+        for (int col = 1; col >= 0; --col) launch_s_smooth(g, L.coef64, L.sweight, col, f, x, s);
+}
+
+int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hipStream_t s,
+            int *iters) {
+    ensure_proj(op);
+    const Level &L = op->lv[0];
+    const Grid &g = L.g;
+    const int64_t P = g.P;
+    double *gv = op->pj_g, *psi = op->pj_psi, *r = op->pj_r, *z = op->pj_z, *p = op->pj_p,
+           *q = op->pj_q;
+    launch_div_DA(g, L.coef64, b, gv, s);
+    if (op->s_floating) demean_cells(op, gv, s);
+    const double gnorm = std::sqrt(dot1(op, gv, gv, nullptr, P, s));
+    // Stop on the scale of the field, not of its divergence: the gradient
+    // left in the output is then at most ~rtol of |b|_A, however nearly
+    // divergence-free b already was (the usual case inside the eigensolve).
+    const double stop = rtol * std::sqrt(dot1(op, b, b, L.coef64, op->n0(), s)) / g.h;
+    DM_HIP(hipMemsetAsync(psi, 0, P * sizeof(double), s));
+    int it = 0;
+    if (!std::isfinite(gnorm)) throw DmError{DM_ENAN, "projection input is not finite"};
+    if (gnorm > stop) {
+        launch_copy(P, gv, r, s);
+        svcycle(op, 0, r, z, s);
+        if (op->s_floating) demean_cells(op, z, s);
+        launch_copy(P, z, p, s);
+        double rz = dot1(op, r, z, nullptr, P, s);
+        while (it < maxit) {
+            launch_s_apply(g, L.coef64, L.sweight, 0, nullptr, p, q, s);
+            const double pq = dot1(op, p, q, nullptr, P, s);
+            if (!(pq > 0.0)) break;
+            const double alpha = rz / pq;
+            launch_axpy(P, alpha, p, psi, s);
+            launch_axpy(P, -alpha, q, r, s);
+            ++it;
+            const double rn = std::sqrt(dot1(op, r, r, nullptr, P, s));
+            if (rn <= stop) break;
+            svcycle(op, 0, r, z, s);
+            if (op->s_floating) demean_cells(op, z, s);
+            const double rz2 = dot1(op, r, z, nullptr, P, s);
+            launch_axpby(P, 1.0, z, rz2 / rz, p, s);
+            rz = rz2;
+        }
+    }
+    launch_grad_sub(g, L.coef64, psi, const_cast<double *>(b), out, 1.0, s);
+    if (iters) *iters = it;
+    op->last_proj_iters = it;
+    return DM_OK;
+}
+
+int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
+          dm_solve_info *info, hipStream_t s) {
+    const double t0 = now_s();
+    int rc;
+    if (mode == DM_SOLVE_PCG64) rc = pcg(op, f, x, rtol, maxit, info, s);
+    else rc = fgmres(op, mode, f, x, rtol, maxit, info, s);
+    DM_HIP(hipStreamSynchronize(s));
+    if (info) info->seconds = now_s() - t0;
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Block Krylov--Schur (symmetric) on T = P_DM M^-1 A, A-inner product.
+// ---------------------------------------------------------------------------
+int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt, double *lam,
+         double *vecs, double *res_out, dm_eig_info *info, hipStream_t s) {
+    const double t0 = now_s();
+    const Level &L = op->lv[0];
+    const int64_t n = op->n0();
+    const int b = std::max(1, opt.block);
+    int m = std::max(opt.max_basis, k + 2 * b);
+    m = (m + b - 1) / b * b;                 // basis columns that get expanded
+    const int keep_max = std::min(m - b, ((k + b + b - 1) / b) * b);
+    const int cap = m + b + keep_max;
+    if (cap > kMaxDots) throw DmError{DM_EINVAL, "eigs: basis too large"};
+    if (op->eg_cap < cap) {
+        op->eg_V = op->dalloc<double>((size_t)cap * n);
+        op->eg_W = op->dalloc<double>((size_t)b * n);
+        op->eg_T = op->dalloc<double>((size_t)3 * n);
+        op->eg_cap = cap;
+    }
+    ensure_krylov(op);
+    double *V = op->eg_V, *W = op->eg_W, *t1 = op->eg_T, *t2 = op->eg_T + n, *t3 = op->eg_T + 2 * n;
+    double *SCR = V + (size_t)(m + b) * n;   // room for keep_max Ritz vectors
+    const double *a = L.coef64;              // ax|ay|az: the A weights of a face vector
+    // 1/a on active faces (weight of the A^-1 norm)
+    double *ainv = t3;
+    {
+        std::vector<double> hv(n);
+        const std::vector<double> &fr = op->frac[0];
+        for (int64_t p = 0; p < n; ++p) hv[p] = fr[p] > 0.0 ? 1.0 / fr[p] : 0.0;
+        DM_HIP(hipMemcpyAsync(ainv, hv.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+        DM_HIP(hipStreamSynchronize(s));
+    }
+    int inner_its = 0, proj_its = 0, outer = 0, restarts = 0;
+    dm_solve_info sinfo;
+    auto A_normalize = [&](double *v) -> double {
+        const double nrm = std::sqrt(dot1(op, v, v, a, n, s));
+        if (nrm > 0) launch_scale(n, 1.0 / nrm, v, s);
+        return nrm;
+    };
+    // orthogonalise v against `cnt` A-orthonormal columns starting at B, twice;
+    // accumulates the coefficients into coef (size cnt)
+    std::vector<double> hc(cap);
+    auto orth = [&](const double *B, int cnt, double *v, double *coef) {
+        if (cnt <= 0) return;
+        for (int pass = 0; pass < 2; ++pass) {
+            dots(op, cnt, B, n, v, a, n, s);
+            std::copy(op->hres, op->hres + cnt, hc.begin());
+            if (coef)
+                for (int i = 0; i < cnt; ++i) coef[i] += hc[i];
+            to_device_coef(op, hc.data(), cnt, s);
+            launch_maxpy(cnt, B, n, op->dcoef, v, n, 0, s);
+        }
+    };
+    int pj;
+    // G = V^T K V of the basis, kept on the host: one K apply and one
+    // multi-dot per new basis vector; thick restarts transform it in place.
+    std::vector<double> GK((size_t)cap * cap, 0.0);
+    auto Gat = [&](int r, int c) -> double & { return GK[(size_t)r * cap + c]; };
+    auto add_gk = [&](int q) {
+        launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, V + (size_t)q * n, t2, s);
+        dots(op, q + 1, V, n, t2, nullptr, n, s);
+        for (int i = 0; i <= q; ++i) Gat(i, q) = Gat(q, i) = op->hres[i];
+    };
+    // start block
+    for (int c = 0; c < b; ++c) {
+        double *v = V + (size_t)c * n;
+        launch_randn(n, seed, (int64_t)c * n, op->fmask, v, s);
+        project(op, v, v, opt.proj_rtol, 1000, s, &pj);
+        proj_its += pj;
+        orth(V, c, v, nullptr);
+        if (!(A_normalize(v) > 0)) throw DmError{DM_EBREAKDOWN, "eigs: zero start vector"};
+        add_gk(c);
+    }
+    const int HR = m + b;  // rows of H
+    std::vector<double> H((size_t)HR * m, 0.0);
+    auto Hat = [&](int r, int c) -> double & { return H[(size_t)r * m + c]; };
+    int cur = b;           // basis vectors present
+    std::vector<double> theta, Y, mu, Z, lam_h(k), res_h(k, INFINITY);
+    std::vector<int> wanted(k);
+    std::vector<double> coef(cap);
+    int status = DM_NOT_CONVERGED;
+    int nconv = 0;
+    while (true) {
+        // ---- expand by one block: W = T V_last, orthogonalise, append
+        {
+            const int j0 = cur - b;
+            for (int c = 0; c < b; ++c) {
+                double *w = W + (size_t)c * n;
+                launch_apply_A(L.g, L.coef64, V + (size_t)(j0 + c) * n, t1, s);
+                const int rc = solve(op, opt.solve_mode, t1, w, opt.inner_rtol, 2000, &sinfo, s);
+                if (rc < 0) return rc;
+                inner_its += sinfo.iterations;
+                project(op, w, w, opt.proj_rtol, 1000, s, &pj);
+                proj_its += pj;
+            }
+            ++outer;
+            for (int c = 0; c < b; ++c) {
+                double *v = V + (size_t)(cur + c) * n;
+                launch_copy(n, W + (size_t)c * n, v, s);
+                std::fill(coef.begin(), coef.end(), 0.0);
+                orth(V, cur + c, v, coef.data());
+                for (int i = 0; i < cur + c; ++i) Hat(i, j0 + c) += coef[i];
+                const double nrm = A_normalize(v);
+                if (!std::isfinite(nrm)) throw DmError{DM_ENAN, "eigs: basis vector not finite"};
+                Hat(cur + c, j0 + c) = nrm;
+                if (nrm <= 1e-300) throw DmError{DM_EBREAKDOWN, "eigs: Krylov breakdown"};
+                add_gk(cur + c);
+            }
+            cur += b;
+        }
+        const bool full = cur >= m + b;
+        if (cur - b < k) continue;
+        // ---- Krylov--Schur Ritz vectors of T (restarts): the expanded columns
+        const int mm = cur - b;
+        std::vector<double> Hs((size_t)mm * mm);
+        for (int i = 0; i < mm; ++i)
+            for (int j = 0; j < mm; ++j) Hs[(size_t)i * mm + j] = 0.5 * (Hat(i, j) + Hat(j, i));
+        jacobi_eig(Hs, mm, theta, Y);
+        std::vector<int> order(mm);
+        for (int i = 0; i < mm; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return theta[x] > theta[y]; });
+        // ---- Rayleigh--Ritz on (K, A) over the whole basis (answers): the
+        // basis is A-orthonormal, so the projected pencil is (V^T K V, I)
+        const int nb = cur;
+        {
+            std::vector<double> Gs((size_t)nb * nb);
+            double gmax = 0.0;
+            for (int i = 0; i < nb; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    Gs[(size_t)i * nb + j] = 0.5 * (Gat(i, j) + Gat(j, i));
+                    gmax = std::max(gmax, std::fabs(Gs[(size_t)i * nb + j]));
+                }
+            jacobi_eig(Gs, nb, mu, Z);
+            std::vector<int> ord(nb);
+            for (int i = 0; i < nb; ++i) ord[i] = i;
+            std::sort(ord.begin(), ord.end(), [&](int x, int y) { return mu[x] < mu[y]; });
+            int w = 0;
+            for (int i = 0; i < nb && w < k; ++i)
+                if (mu[ord[i]] > 1e-10 * gmax) wanted[w++] = ord[i];
+            // fewer than k nonzero Rayleigh quotients: keep the lowest ones
+            for (int i = 0; w < k && i < nb; ++i)
+                if (!(mu[ord[i]] > 1e-10 * gmax)) wanted[w++] = ord[i];
+        }
+        // ---- explicit residuals of the k wanted Ritz pairs on (K, A)
+        nconv = 0;
+        double maxres = 0.0;
+        std::vector<double> yk(std::max(mm, nb));
+        for (int i = 0; i < k; ++i) {
+            for (int r = 0; r < nb; ++r) yk[r] = Z[(size_t)r * nb + wanted[i]];
+            to_device_coef(op, yk.data(), nb, s);
+            double *bi = SCR + (size_t)(i % std::max(1, keep_max)) * n;
+            launch_maxpy(nb, V, n, op->dcoef, t1, n, 1, s);  // t1 = V y
+            launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, t1, t2, s);
+            const double bKb = dot1(op, t1, t2, nullptr, n, s);
+            const double bAb = dot1(op, t1, t1, a, n, s);
+            const double lr = bKb / bAb;
+            // t2 = K b - lr A b
+            launch_apply_A(L.g, L.coef64, t1, bi, s);
+            launch_axpy(n, -lr, bi, t2, s);
+            const double rr = dot1(op, t2, t2, ainv, n, s);
+            const double rho = std::sqrt(rr) / (std::fabs(lr) * std::sqrt(bAb));
+            lam_h[i] = lr;
+            res_h[i] = rho;
+            maxres = std::max(maxres, rho);
+            if (rho <= tol) ++nconv;
+        }
+        if (opt.verbose)
+            fprintf(stderr, "[dm_eigs] outer %d restart %d dim %d: max rho %.3e, %d/%d converged\n",
+                    outer, restarts, mm, maxres, nconv, k);
+        if (nconv == k) status = DM_OK;
+        if (nconv == k || (full && restarts >= opt.max_restarts)) {
+            // outputs: Ritz vectors of the k wanted pairs, sorted by lambda
+            std::vector<int> idx(k);
+            for (int i = 0; i < k; ++i) idx[i] = i;
+            std::sort(idx.begin(), idx.end(), [&](int x, int y) { return lam_h[x] < lam_h[y]; });
+            for (int q = 0; q < k; ++q) {
+                const int i = idx[q];
+                lam[q] = lam_h[i];
+                if (res_out) res_out[q] = res_h[i];
+                if (vecs) {
+                    for (int r = 0; r < nb; ++r) yk[r] = Z[(size_t)r * nb + wanted[i]];
+                    to_device_coef(op, yk.data(), nb, s);
+                    launch_maxpy(nb, V, n, op->dcoef, vecs + (size_t)q * n, n, 1, s);
+                }
+            }
+            if (info) {
+                info->n_converged = nconv;
+                info->outer_iterations = outer;
+                info->restarts = restarts;
+                info->inner_iterations = inner_its;
+                info->projection_iterations = proj_its;
+                double mr = 0;
+                for (int i = 0; i < k; ++i) mr = std::max(mr, res_h[i]);
+                info->max_residual = mr;
+            }
+            break;
+        }
+        if (!full) continue;
+        // ---- thick restart: keep the keep_max leading Ritz vectors
+        const int keep = keep_max;
+        for (int i = 0; i < keep; ++i) {
+            for (int r = 0; r < mm; ++r) yk[r] = Y[(size_t)r * mm + order[i]];
+            to_device_coef(op, yk.data(), mm, s);
+            launch_maxpy(mm, V, n, op->dcoef, SCR + (size_t)i * n, n, 1, s);
+        }
+        std::vector<double> Bc((size_t)b * keep, 0.0);  // coupling of the last block
+        for (int r = 0; r < b; ++r)
+            for (int i = 0; i < keep; ++i) {
+                double sacc = 0.0;
+                for (int c = 0; c < mm; ++c) sacc += Hat(mm + r, c) * Y[(size_t)c * mm + order[i]];
+                Bc[(size_t)r * keep + i] = sacc;
+            }
+        DM_HIP(hipMemcpyAsync(V, SCR, (size_t)keep * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        DM_HIP(hipMemcpyAsync(V + (size_t)keep * n, V + (size_t)mm * n, (size_t)b * n * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+        std::fill(H.begin(), H.end(), 0.0);
+        for (int i = 0; i < keep; ++i) Hat(i, i) = theta[order[i]];
+        for (int r = 0; r < b; ++r)
+            for (int i = 0; i < keep; ++i) Hat(keep + r, i) = Bc[(size_t)r * keep + i];
+        // V^T K V of the new basis: Q^T G Q with Q = diag(Y_keep, I_b)
+        {
+            const int nn = keep + b, no = mm + b;
+            std::vector<double> Q((size_t)no * nn, 0.0);
+            for (int r = 0; r < mm; ++r)
+                for (int i = 0; i < keep; ++i) Q[(size_t)r * nn + i] = Y[(size_t)r * mm + order[i]];
+            for (int r = 0; r < b; ++r) Q[(size_t)(mm + r) * nn + keep + r] = 1.0;
+            std::vector<double> GQ((size_t)no * nn, 0.0), Gn((size_t)nn * nn, 0.0);
+            for (int r = 0; r < no; ++r)
+                for (int c = 0; c < no; ++c) {
+                    const double g = Gat(r, c);
+                    if (g == 0.0) continue;
+                    for (int j = 0; j < nn; ++j) GQ[(size_t)r * nn + j] += g * Q[(size_t)c * nn + j];
+                }
+            for (int r = 0; r < no; ++r)
+                for (int i = 0; i < nn; ++i) {
+                    const double q = Q[(size_t)r * nn + i];
+                    if (q == 0.0) continue;
+                    for (int j = 0; j < nn; ++j) Gn[(size_t)i * nn + j] += q * GQ[(size_t)r * nn + j];
+                }
+            std::fill(GK.begin(), GK.end(), 0.0);
+            for (int i = 0; i < nn; ++i)
+                for (int j = 0; j < nn; ++j) Gat(i, j) = Gn[(size_t)i * nn + j];
+        }
+        cur = keep + b;
+        ++restarts;
+    }
+    DM_HIP(hipStreamSynchronize(s));
+    if (info) info->seconds = now_s() - t0;
+    return status;
+}
+
+}  // namespace dm

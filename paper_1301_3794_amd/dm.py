@@ -1,0 +1,353 @@
+"""ctypes binding of the C ABI in ``include/dm.h``.
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Device buffers are torch tensors (PyTorch supplies device memory and
+streams); the library is loaded from this package directory and its absence
+is an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdm.so")
+
+DM_OK = 0
+DM_NOT_CONVERGED = 1
+DM_EINVAL, DM_ENOMEM, DM_EHIP, DM_ESINGULAR, DM_EBREAKDOWN, DM_ENAN, DM_ENODEVICE = range(-1, -8, -1)
+
+GEOM_BOX, GEOM_ELLIPSOID, GEOM_ELLIPTIC_BOR, GEOM_USER = 0, 1, 2, 3
+BC_PEC, BC_PMC = 0, 1
+APPLY_M, APPLY_K, APPLY_A, APPLY_DA, APPLY_DT, APPLY_S = range(6)
+SOLVE_PCG64, SOLVE_FGMRES_MG64, SOLVE_FGMRES_MG32 = range(3)
+
+EXPORTS = (
+    "dm_default_options", "dm_build_operator", "dm_destroy", "dm_set_shift",
+    "dm_compute_fractions", "dm_field_layout", "dm_get_fractions", "dm_apply",
+    "dm_residual", "dm_smooth", "dm_restrict", "dm_prolong_add", "dm_vcycle",
+    "dm_project", "dm_solve", "dm_default_eig_options", "dm_eigs", "dm_strerror",
+    "dm_last_error_message", "dm_time_kernel",
+)
+KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_SMOOTH, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE = range(7)
+
+
+class DMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("center", ctypes.c_double * 3),
+        ("semi_axes", ctypes.c_double * 3),
+        ("axis_xy", ctypes.c_double * 2),
+        ("z_start", ctypes.c_double),
+        ("n_cells", ctypes.c_int),
+        ("r_equator", ctypes.c_double),
+        ("r_iris", ctypes.c_double),
+        ("cell_length", ctypes.c_double),
+        ("tube_length", ctypes.c_double),
+        ("user_fractions_host", ctypes.POINTER(ctypes.c_double)),
+        ("bc_lo", ctypes.c_int * 3),
+        ("a_min", ctypes.c_double),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
+                ("fgmres_restart", ctypes.c_int), ("verbose", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class EigOptions(ctypes.Structure):
+    _fields_ = [("solve_mode", ctypes.c_int), ("inner_rtol", ctypes.c_double),
+                ("proj_rtol", ctypes.c_double), ("block", ctypes.c_int),
+                ("max_basis", ctypes.c_int), ("max_restarts", ctypes.c_int),
+                ("verbose", ctypes.c_int)]
+
+
+class EigInfo(ctypes.Structure):
+    _fields_ = [("n_converged", ctypes.c_int), ("outer_iterations", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("inner_iterations", ctypes.c_int),
+                ("projection_iterations", ctypes.c_int), ("max_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libdm.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1301_3794_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.dm_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.dm_default_options.restype = None
+    L.dm_build_operator.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(ctypes.c_int), d, d,
+                                    ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.dm_destroy.argtypes = [vp]
+    L.dm_destroy.restype = None
+    L.dm_set_shift.argtypes = [vp, d]
+    L.dm_compute_fractions.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(ctypes.c_int), d, dp]
+    L.dm_field_layout.argtypes = [vp, i, ctypes.POINTER(i64)]
+    L.dm_get_fractions.argtypes = [vp, i, dp]
+    L.dm_apply.argtypes = [vp, i, i, i, vp, vp, vp]
+    L.dm_residual.argtypes = [vp, i, i, vp, vp, vp, vp]
+    L.dm_smooth.argtypes = [vp, i, i, i, i, vp, vp, vp]
+    L.dm_restrict.argtypes = [vp, i, i, vp, vp, vp]
+    L.dm_prolong_add.argtypes = [vp, i, i, vp, vp, vp]
+    L.dm_vcycle.argtypes = [vp, i, vp, vp, vp]
+    L.dm_project.argtypes = [vp, vp, vp, d, vp]
+    L.dm_solve.argtypes = [vp, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
+    L.dm_default_eig_options.argtypes = [ctypes.POINTER(EigOptions)]
+    L.dm_default_eig_options.restype = None
+    L.dm_eigs.argtypes = [vp, i, d, d, ctypes.c_uint64, ctypes.POINTER(EigOptions), dp, vp, dp,
+                          ctypes.POINTER(EigInfo), vp]
+    L.dm_time_kernel.argtypes = [vp, i, i, i, i, dp]
+    L.dm_strerror.argtypes = [i]
+    L.dm_strerror.restype = ctypes.c_char_p
+    L.dm_last_error_message.argtypes = []
+    L.dm_last_error_message.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc, allow_warning=False):
+    if rc == DM_OK or (allow_warning and rc > 0):
+        return rc
+    L = lib()
+    raise DMError(rc, f"{L.dm_strerror(rc).decode()}: {L.dm_last_error_message().decode()}")
+
+
+# ---------------------------------------------------------------------------
+# geometry helpers
+# ---------------------------------------------------------------------------
+
+def box(bc_lo=(BC_PEC,) * 3, a_min=0.0) -> Geometry:
+    g = Geometry()
+    g.kind = GEOM_BOX
+    g.bc_lo[:] = list(bc_lo)
+    g.a_min = a_min
+    return g
+
+
+def ellipsoid(center, semi_axes, a_min=0.0) -> Geometry:
+    g = Geometry()
+    g.kind = GEOM_ELLIPSOID
+    g.center[:] = list(center)
+    g.semi_axes[:] = list(semi_axes)
+    g.a_min = a_min
+    return g
+
+
+def sphere(center=(0.5, 0.5, 0.5), radius=0.45, a_min=0.0) -> Geometry:
+    return ellipsoid(center, (radius,) * 3, a_min)
+
+
+def elliptic_bor(axis_xy, z_start, n_cells, r_equator, r_iris, cell_length, tube_length,
+                 bc_lo=(BC_PEC,) * 3, a_min=0.0) -> Geometry:
+    g = Geometry()
+    g.kind = GEOM_ELLIPTIC_BOR
+    g.axis_xy[:] = list(axis_xy)
+    g.z_start = z_start
+    g.n_cells = n_cells
+    g.r_equator, g.r_iris = r_equator, r_iris
+    g.cell_length, g.tube_length = cell_length, tube_length
+    g.bc_lo[:] = list(bc_lo)
+    g.a_min = a_min
+    return g
+
+
+def user_fractions(frac7: np.ndarray, bc_lo=(BC_PEC,) * 3) -> Geometry:
+    """Geometry from caller fractions: a (7, P) float64 array (ax..v) in the
+    padded layout of level 0.  The array must outlive the build call."""
+    g = Geometry()
+    g.kind = GEOM_USER
+    arr = np.ascontiguousarray(frac7, dtype=np.float64)
+    g._keep = arr
+    g.user_fractions_host = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    g.bc_lo[:] = list(bc_lo)
+    return g
+
+
+def padded_size(dims):
+    return (dims[0] + 2) * (dims[1] + 2) * (dims[2] + 2)
+
+
+def compute_fractions(geom: Geometry, dims, h) -> np.ndarray:
+    """Host-side fractions (no GPU): (7, P) array ax ay az lx ly lz v."""
+    P = padded_size(dims)
+    out = np.zeros(7 * P)
+    d = (ctypes.c_int * 3)(*dims)
+    _check(lib().dm_compute_fractions(ctypes.byref(geom), d, float(h),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(7, P)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+# ---------------------------------------------------------------------------
+# operator
+# ---------------------------------------------------------------------------
+
+class Operator:
+    """A built operator hierarchy (``dm_build_operator``)."""
+
+    def __init__(self, geom: Geometry, dims, h, sigma, levels=0, nu_pre=2, nu_post=2,
+                 fgmres_restart=30, verbose=0):
+        L = lib()
+        opt = Options()
+        L.dm_default_options(ctypes.byref(opt))
+        opt.levels, opt.nu_pre, opt.nu_post = levels, nu_pre, nu_post
+        opt.fgmres_restart, opt.verbose = fgmres_restart, verbose
+        self._op = ctypes.c_void_p()
+        self.dims = tuple(int(x) for x in dims)
+        self.h = float(h)
+        self._geom = geom
+        d = (ctypes.c_int * 3)(*self.dims)
+        _check(L.dm_build_operator(ctypes.byref(geom), d, self.h, float(sigma), ctypes.byref(opt),
+                                   ctypes.byref(self._op)))
+        self.sigma = float(sigma)
+
+    def close(self):
+        if self._op:
+            lib().dm_destroy(self._op)
+            self._op = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- layout
+    def layout(self, level=0):
+        out = (ctypes.c_int64 * 7)()
+        _check(lib().dm_field_layout(self._op, level, out))
+        return dict(dims=(out[0], out[1], out[2]), P=out[3], active_faces=out[4],
+                    active_cells=out[5], levels=out[6])
+
+    @property
+    def levels(self):
+        return self.layout(0)["levels"]
+
+    def fractions(self, level=0) -> np.ndarray:
+        P = self.layout(level)["P"]
+        out = np.zeros(7 * P)
+        _check(lib().dm_get_fractions(self._op, level,
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(7, P)
+
+    def set_shift(self, sigma):
+        _check(lib().dm_set_shift(self._op, float(sigma)))
+        self.sigma = float(sigma)
+
+    # -- device tensors
+    def face_tensor(self, level=0, dtype=None, device="cuda"):
+        import torch
+        return torch.zeros(3 * self.layout(level)["P"], dtype=dtype or torch.float64, device=device)
+
+    def cell_tensor(self, level=0, device="cuda"):
+        import torch
+        return torch.zeros(self.layout(level)["P"], dtype=torch.float64, device=device)
+
+    @staticmethod
+    def _prec(t):
+        import torch
+        return 64 if t.dtype == torch.float64 else 32
+
+    def apply(self, which, x, y, level=0, stream=None):
+        _check(lib().dm_apply(self._op, which, self._prec(x), level, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def residual(self, f, x, r, level=0, stream=None):
+        _check(lib().dm_residual(self._op, self._prec(x), level, _ptr(f), _ptr(x), _ptr(r), _stream(stream)))
+        return r
+
+    def smooth(self, f, x, sweeps=1, reverse=False, level=0, stream=None):
+        _check(lib().dm_smooth(self._op, self._prec(x), level, sweeps, int(bool(reverse)), _ptr(f), _ptr(x),
+                               _stream(stream)))
+        return x
+
+    def restrict(self, r, fc, level=0, stream=None):
+        _check(lib().dm_restrict(self._op, self._prec(r), level, _ptr(r), _ptr(fc), _stream(stream)))
+        return fc
+
+    def prolong_add(self, xc, x, level=0, stream=None):
+        _check(lib().dm_prolong_add(self._op, self._prec(x), level, _ptr(xc), _ptr(x), _stream(stream)))
+        return x
+
+    def vcycle(self, f, x, stream=None):
+        _check(lib().dm_vcycle(self._op, self._prec(f), _ptr(f), _ptr(x), _stream(stream)))
+        return x
+
+    def project(self, b, out, rtol=1e-13, stream=None):
+        _check(lib().dm_project(self._op, _ptr(b), _ptr(out), float(rtol), _stream(stream)))
+        return out
+
+    def solve(self, f, x, mode=SOLVE_FGMRES_MG64, rtol=1e-10, maxit=500, stream=None):
+        info = SolveInfo()
+        rc = _check(lib().dm_solve(self._op, mode, _ptr(f), _ptr(x), float(rtol), int(maxit),
+                                   ctypes.byref(info), _stream(stream)), allow_warning=True)
+        return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
+                    rel_residual=info.rel_residual, seconds=info.seconds)
+
+    def time_kernel(self, kernel, prec=32, level=0, reps=50):
+        """Milliseconds per launch of a library kernel (HIP events)."""
+        ms = ctypes.c_double()
+        _check(lib().dm_time_kernel(self._op, kernel, prec, level, reps, ctypes.byref(ms)))
+        return ms.value
+
+    def eigs(self, k, sigma=None, tol=1e-10, seed=1301, vecs=None, solve_mode=SOLVE_FGMRES_MG64,
+             inner_rtol=1e-11, proj_rtol=1e-13, block=4, max_basis=40, max_restarts=20,
+             verbose=0, stream=None):
+        L = lib()
+        o = EigOptions()
+        L.dm_default_eig_options(ctypes.byref(o))
+        o.solve_mode, o.inner_rtol, o.proj_rtol = solve_mode, inner_rtol, proj_rtol
+        o.block, o.max_basis, o.max_restarts, o.verbose = block, max_basis, max_restarts, verbose
+        lam = np.zeros(k)
+        res = np.zeros(k)
+        info = EigInfo()
+        sig = self.sigma if sigma is None else float(sigma)
+        rc = _check(L.dm_eigs(self._op, int(k), sig, float(tol), ctypes.c_uint64(seed), ctypes.byref(o),
+                              lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              _ptr(vecs) if vecs is not None else None,
+                              res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              ctypes.byref(info), _stream(stream)), allow_warning=True)
+        self.sigma = sig
+        return dict(status=rc, lam=lam, residuals=res, n_converged=info.n_converged,
+                    outer_iterations=info.outer_iterations, restarts=info.restarts,
+                    inner_iterations=info.inner_iterations,
+                    projection_iterations=info.projection_iterations,
+                    max_residual=info.max_residual, seconds=info.seconds)
