@@ -140,6 +140,62 @@ def _a_orthonormalize(W, a, basis=None):
     return W
 
 
+def augmented_eigs(op, k, sigma_o=0.0, block=4, tol=1e-10, max_blocks=60, seed=1301,
+                   cg_tol=1e-12, precond=None, maxiter=100000, div_tol=1e-6, log=None):
+    """k smallest electromagnetic eigenpairs via the augmented pencil.
+
+    Sec. 5.1 (after eq. discLaplBDM): every eigenpair of (K, A) with
+    lambda > 0 is an eigenpair of the grad-div augmented pencil (K + G, A),
+    whose remaining eigenpairs are the gradient modes (D A b != 0).  So:
+    block Lanczos with full re-orthogonalisation on M^-1 A (M = K + G -
+    sigma_o A SPD, no projection), Rayleigh--Ritz on (K + G, A), and keep the
+    Ritz pairs whose divergence ||V^-1/2 D A b|| / ||b||_A is below div_tol.
+    Used where the projection's CG would be too slow (large grids); pinned
+    against ``lanczos_eigs`` and dense eigh on small grids.
+    """
+    M = op.M_a if op.sigma == sigma_o else op.with_shift(sigma_o).M_a
+    KG = (op.K_a + op.G_a).tocsr()
+    a = op.a_a
+    n = a.size
+    if precond is None:
+        dinv = 1.0 / M.diagonal()
+        precond = lambda r: dinv * r  # noqa: E731
+    rng = np.random.default_rng(seed)
+    V = _a_orthonormalize(rng.standard_normal((n, block)), a)
+    KV = KG @ V
+    n_solves = cg_its = 0
+    lam = B = res = None
+    for it in range(max_blocks):
+        last = V[:, -block:]
+        W = np.empty_like(last)
+        for c in range(block):
+            W[:, c], its = pcg(lambda p: M @ p, a * last[:, c], cg_tol, maxiter, precond=precond)
+            n_solves += 1
+            cg_its += its
+        W = _a_orthonormalize(W, a, V)
+        V = np.hstack([V, W])
+        KV = np.hstack([KV, KG @ W])
+        H = V.T @ KV
+        theta, Y = np.linalg.eigh(0.5 * (H + H.T))
+        em = []
+        for c in np.argsort(theta):
+            b = V @ Y[:, c]
+            if div_residual(op, b) < div_tol:
+                em.append((theta[c], b))
+            if len(em) == k:
+                break
+        if len(em) < k:
+            continue
+        lam = np.array([e[0] for e in em])
+        B = np.column_stack([e[1] for e in em])
+        res = np.array([eig_residual(op, lam[c], B[:, c]) for c in range(k)])
+        if log:
+            log(f"augmented block {it}: dim {V.shape[1]} max res {res.max():.3e}")
+        if res.max() <= tol:
+            break
+    return lam, B, dict(n_solves=n_solves, cg_iters=cg_its, dim=V.shape[1], residuals=res)
+
+
 def lanczos_eigs(op, k, sigma_o=0.0, block=4, tol=1e-10, max_blocks=60, seed=1301,
                  cg_tol=1e-13, proj_tol=1e-13, precond=None, maxiter=100000, log=None,
                  project=True):

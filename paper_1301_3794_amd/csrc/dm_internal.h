@@ -167,7 +167,7 @@ void launch_scale(int64_t n, double a, double *x, hipStream_t s);
 void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
 // out[i] = sum_n V_i[n] w[n] (wt[n]) for i < nv; V_i = V + i*ld; results left in
 // device buffer `dout` (nv doubles); `part` scratch of nv * kReduceBlocks doubles
-constexpr int kReduceBlocks = 512;
+constexpr int kReduceBlocks = 1024;
 void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
                  int64_t n, double *part, double *dout, hipStream_t s);
 // y -= sum_i c[i] V_i  (c on device)  or  y = sum_i c[i] V_i when overwrite

@@ -310,24 +310,62 @@ __global__ void k_scale(int64_t n, double a, double *__restrict__ x) {
 
 constexpr int kChunk = 8;  // vectors reduced per pass of k_mdot
 
+// Reductions and multi-axpys stream long FP64 vectors: they read pairs of
+// doubles (16-byte loads) when every pointer is 16-byte aligned and the
+// length / stride are even (VEC = 2), else single doubles (VEC = 1).
+template <int VEC>
+struct Vec;
+template <>
+struct Vec<1> {
+    using T = double;
+    __device__ static T ld(const double *p, int64_t e) { return p[e]; }
+    __device__ static void st(double *p, int64_t e, T v) { p[e] = v; }
+    __device__ static double dot(T a, T b) { return a * b; }
+    __device__ static T fma(double c, T a, T b) { return b + c * a; }
+    __device__ static T mul(T a, T b) { return a * b; }
+    __device__ static T scale(double c, T a) { return c * a; }
+    __device__ static T zero() { return 0.0; }
+};
+template <>
+struct Vec<2> {
+    using T = double2;
+    __device__ static T ld(const double *p, int64_t e) { return reinterpret_cast<const double2 *>(p)[e]; }
+    __device__ static void st(double *p, int64_t e, T v) { reinterpret_cast<double2 *>(p)[e] = v; }
+    __device__ static double dot(T a, T b) { return a.x * b.x + a.y * b.y; }
+    __device__ static T fma(double c, T a, T b) { return make_double2(b.x + c * a.x, b.y + c * a.y); }
+    __device__ static T mul(T a, T b) { return make_double2(a.x * b.x, a.y * b.y); }
+    __device__ static T scale(double c, T a) { return make_double2(c * a.x, c * a.y); }
+    __device__ static T zero() { return make_double2(0.0, 0.0); }
+};
+
+// part[i][block] = partial sums of V_i . (w * wt) over the block's elements
+template <int VEC>
 __global__ void __launch_bounds__(kThreads)
 k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
        const double *__restrict__ wt, int64_t n, double *__restrict__ part) {
-    __shared__ double sh[kThreads / 64][kChunk];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    using O = Vec<VEC>;
+    const int64_t nvec = n / VEC, ldv = ld / VEC;
     for (int c0 = 0; c0 < nv; c0 += kChunk) {
         const int cn = min(kChunk, nv - c0);
         double acc[kChunk];
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) acc[q] = 0.0;
-        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
              e += (int64_t)gridDim.x * kThreads) {
-            double wv = w[e];
-            if (wt) wv *= wt[e];
+            typename O::T wv = O::ld(w, e);
+            if (wt) wv = O::mul(wv, O::ld(wt, e));
 #pragma unroll
             for (int q = 0; q < kChunk; ++q)
-                if (q < cn) acc[q] += V[(int64_t)(c0 + q) * ld + e] * wv;
+                if (q < cn) acc[q] += O::dot(O::ld(V + (int64_t)(c0 + q) * ldv * VEC, e), wv);
         }
+        if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double wv = w[n - 1] * (wt ? wt[n - 1] : 1.0);
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q)
+                if (q < cn) acc[q] += V[(int64_t)(c0 + q) * ld + n - 1] * wv;
+        }
+        __shared__ double sh[kThreads / 64][kChunk];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) {
             double v = acc[q];
@@ -336,9 +374,56 @@ k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restric
         }
         __syncthreads();
         if (threadIdx.x < cn) {
-            double s = 0.0;
-            for (int u = 0; u < kThreads / 64; ++u) s += sh[u][threadIdx.x];
-            part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+            double t = 0.0;
+            for (int u = 0; u < kThreads / 64; ++u) t += sh[u][threadIdx.x];
+            part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// part rows 0..nv-1: V_i . w; row nv: |w|^2  (chunks of kChunk vectors)
+template <int VEC>
+__global__ void __launch_bounds__(kThreads)
+k_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
+            int64_t n, double *__restrict__ part) {
+    using O = Vec<VEC>;
+    const int64_t nvec = n / VEC, ldv = ld / VEC;
+    __shared__ double sh[kThreads / 64][kChunk + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < nv; c0 += kChunk) {
+        const int cn = min(kChunk, nv - c0);
+        const bool last = c0 + kChunk >= nv;
+        double acc[kChunk + 1];
+#pragma unroll
+        for (int q = 0; q <= kChunk; ++q) acc[q] = 0.0;
+        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
+             e += (int64_t)gridDim.x * kThreads) {
+            const typename O::T wv = O::ld(w, e);
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q)
+                if (q < cn) acc[q] += O::dot(O::ld(V + (int64_t)(c0 + q) * ldv * VEC, e), wv);
+            if (last) acc[kChunk] += O::dot(wv, wv);
+        }
+        if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double wv = w[n - 1];
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q)
+                if (q < cn) acc[q] += V[(int64_t)(c0 + q) * ld + n - 1] * wv;
+            if (last) acc[kChunk] += wv * wv;
+        }
+#pragma unroll
+        for (int q = 0; q <= kChunk; ++q) {
+            double v = acc[q];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) sh[wave][q] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < cn || (last && threadIdx.x == cn)) {
+            const int q = threadIdx.x < cn ? threadIdx.x : kChunk;
+            double t = 0.0;
+            for (int u = 0; u < kThreads / 64; ++u) t += sh[u][q];
+            part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
         }
         __syncthreads();
     }
@@ -360,82 +445,95 @@ k_mdot_final(int nblk, const double *__restrict__ part, double *__restrict__ out
     }
 }
 
+// y = sum_i c_i V_i (overwrite) or y -= sum_i c_i V_i; w: optional input
+// (out = scale * (w - sum c_i V_i) when w != nullptr)
+template <int VEC>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
-        double *__restrict__ y, int64_t n, int overwrite) {
+        const double *w, double scale, double *y, int64_t n, int overwrite) {
+    using O = Vec<VEC>;
     __shared__ double cs[256];
     for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
     __syncthreads();
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+    const int64_t nvec = n / VEC, ldv = ld / VEC;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
          e += (int64_t)gridDim.x * kThreads) {
+        typename O::T s = O::zero();
+        for (int q = 0; q < nv; ++q) s = O::fma(cs[q], O::ld(V + (int64_t)q * ldv * VEC, e), s);
+        typename O::T r;
+        if (w) r = O::scale(scale, O::fma(-1.0, s, O::ld(w, e)));
+        else if (overwrite) r = s;
+        else r = O::fma(-1.0, s, O::ld(y, e));
+        O::st(y, e, r);
+    }
+    if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         double s = 0.0;
-        for (int q = 0; q < nv; ++q) s += cs[q] * V[(int64_t)q * ld + e];
-        y[e] = overwrite ? s : y[e] - s;
+        for (int q = 0; q < nv; ++q) s += cs[q] * V[(int64_t)q * ld + n - 1];
+        y[n - 1] = w ? scale * (w[n - 1] - s) : (overwrite ? s : y[n - 1] - s);
     }
 }
 
-// Fused Gram--Schmidt step for nv <= kFuseMax basis vectors:
+// Fused Gram--Schmidt step for nv <= MAXV basis vectors:
 //   w' = w - sum_i c_i V_i      (written back to w)
-//   part: dots V_i . w' (rows 0..nv-1) and |w'|^2 (row nv)
-// One read of the basis serves both the update and the dots.
+//   part rows 0..nv-1: V_i . w', row nv: |w'|^2
+// One read of the basis (held in registers) serves the update and the dots.
 constexpr int kFuseMax = 32;
 
+template <int VEC, int MAXV>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
                   double *__restrict__ w, int64_t n, double *__restrict__ part) {
-    __shared__ double cs[kFuseMax];
-    __shared__ double sh[kThreads / 64][kFuseMax + 1];
+    using O = Vec<VEC>;
+    __shared__ double cs[MAXV];
     for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
     __syncthreads();
-    double acc[kFuseMax + 1];
+    double acc[MAXV + 1];
 #pragma unroll
-    for (int q = 0; q <= kFuseMax; ++q) acc[q] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
+    for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
+    const int64_t nvec = n / VEC, ldv = ld / VEC;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
          e += (int64_t)gridDim.x * kThreads) {
-        double vv[kFuseMax];
-        double s = w[e];
+        typename O::T vv[MAXV];
+        typename O::T s = O::ld(w, e);
 #pragma unroll
-        for (int q = 0; q < kFuseMax; ++q)
+        for (int q = 0; q < MAXV; ++q)
             if (q < nv) {
-                vv[q] = V[(int64_t)q * ld + e];
-                s -= cs[q] * vv[q];
+                vv[q] = O::ld(V + (int64_t)q * ldv * VEC, e);
+                s = O::fma(-cs[q], vv[q], s);
             }
-        w[e] = s;
+        O::st(w, e, s);
 #pragma unroll
-        for (int q = 0; q < kFuseMax; ++q)
-            if (q < nv) acc[q] += vv[q] * s;
-        acc[kFuseMax] += s * s;
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) acc[q] += O::dot(vv[q], s);
+        acc[MAXV] += O::dot(s, s);
     }
+    if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double t = w[n - 1];
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) t -= cs[q] * V[(int64_t)q * ld + n - 1];
+        w[n - 1] = t;
+#pragma unroll
+        for (int q = 0; q < MAXV; ++q)
+            if (q < nv) acc[q] += V[(int64_t)q * ld + n - 1] * t;
+        acc[MAXV] += t * t;
+    }
+    __shared__ double sh[kThreads / 64][MAXV + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q <= kFuseMax; ++q) {
-        if (q < nv || q == kFuseMax) {
+    for (int q = 0; q <= MAXV; ++q) {
+        if (q < nv || q == MAXV) {
             double v = acc[q];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
             if (lane == 0) sh[wave][q] = v;
         }
     }
     __syncthreads();
-    if (threadIdx.x <= nv) {
-        const int q = threadIdx.x < nv ? threadIdx.x : kFuseMax;
-        double s = 0.0;
-        for (int u = 0; u < kThreads / 64; ++u) s += sh[u][q];
-        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
-    }
-}
-
-// out = scale * (w - sum_i c_i V_i)
-__global__ void __launch_bounds__(kThreads)
-k_maxpy_scale(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
-              const double *__restrict__ w, double scale, double *__restrict__ out, int64_t n) {
-    __shared__ double cs[256];
-    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
-    __syncthreads();
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * kThreads) {
-        double s = w[e];
-        for (int q = 0; q < nv; ++q) s -= cs[q] * V[(int64_t)q * ld + e];
-        out[e] = scale * s;
+    if (threadIdx.x <= nv) {  // row nv carries |w'|^2
+        const int q = threadIdx.x < nv ? threadIdx.x : MAXV;
+        double t = 0.0;
+        for (int u = 0; u < kThreads / 64; ++u) t += sh[u][q];
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -607,11 +705,24 @@ void launch_copy(int64_t n, const double *x, double *y, hipStream_t s) {
     hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
 }
 
+namespace {
+inline bool vec2_ok(int64_t n, int64_t ld, std::initializer_list<const void *> ptrs) {
+    if ((n & 1) && ld != 0) return false;
+    if (ld & 1) return false;
+    for (const void *p : ptrs)
+        if (p && ((uintptr_t)p & 15)) return false;
+    return true;
+}
+}  // namespace
+
 void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
                  int64_t n, double *part, double *dout, hipStream_t s) {
     if (nv <= 0) return;
     if (nv > 256) throw std::runtime_error("launch_mdot: more than 256 vectors");
-    hipLaunchKernelGGL(k_mdot, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part);
+    if (vec2_ok(n, ld, {V, w, wt}))
+        hipLaunchKernelGGL(k_mdot<2>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part);
+    else
+        hipLaunchKernelGGL(k_mdot<1>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part);
     hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout);
 }
@@ -620,13 +731,32 @@ void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *
                   int overwrite, hipStream_t s) {
     if (nv <= 0 && !overwrite) return;
     if (nv > 256) throw std::runtime_error("launch_maxpy: more than 256 vectors");
-    hipLaunchKernelGGL(k_maxpy, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, y, n, overwrite);
+    if (vec2_ok(n, ld, {V, y}))
+        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c,
+                           (const double *)nullptr, 1.0, y, n, overwrite);
+    else
+        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c,
+                           (const double *)nullptr, 1.0, y, n, overwrite);
 }
 
 void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
                             int64_t n, double *part, double *dout, hipStream_t s) {
     if (nv < 1 || nv > kFuseMax) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
-    hipLaunchKernelGGL(k_maxpy_mdot_norm, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, c, w, n, part);
+    const bool v2 = vec2_ok(n, ld, {V, w});
+    const dim3 g(kReduceBlocks), b(kThreads);
+    if (nv <= 8) {
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8>), g, b, 0, s, nv, V, ld, c, w, n, part);
+    } else if (nv <= 16) {
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16>), g, b, 0, s, nv, V, ld, c, w, n, part);
+    } else {
+        // too many vectors to hold in registers: update w, then a second
+        // pass for the dots (the basis is read twice)
+        launch_maxpy(nv, V, ld, c, w, n, 0, s);
+        if (v2) hipLaunchKernelGGL((k_mdot_norm<2>), g, b, 0, s, nv, V, ld, (const double *)w, n, part);
+        else hipLaunchKernelGGL((k_mdot_norm<1>), g, b, 0, s, nv, V, ld, (const double *)w, n, part);
+    }
     hipLaunchKernelGGL(k_mdot_final, dim3(nv + 1), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout);
 }
@@ -634,7 +764,12 @@ void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c
 void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,
                         double scale, double *out, int64_t n, hipStream_t s) {
     if (nv < 0 || nv > 256) throw std::runtime_error("launch_maxpy_scale: nv out of range");
-    hipLaunchKernelGGL(k_maxpy_scale, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, w, scale, out, n);
+    if (vec2_ok(n, ld, {V, w, out}))
+        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c, w, scale,
+                           out, n, 0);
+    else
+        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, w, scale,
+                           out, n, 0);
 }
 
 void launch_sub_masked(int64_t n, const double *mask, const double *val, double scale, double *x,

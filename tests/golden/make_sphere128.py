@@ -2,9 +2,10 @@
 
 Sphere of radius 0.45 centred in the unit cube, 128^3 cells (h = 1/128);
 the 8 smallest nonzero eigenvalues of (K, A) (TM11 x3 and TM21 x5) by the
-oracle's block shift-invert Lanczos at the SPD shift 5, inner CG
-preconditioned by the oracle V-cycle (5 levels), no projection (gradient
-modes fall out of the Rayleigh--Ritz on (K, A)).  Calls only ``oracle/``.
+oracle's block shift-invert Lanczos on the augmented pencil (K + G, A) at
+the SPD shift 5, inner CG preconditioned by the oracle V-cycle (5 levels),
+electromagnetic pairs picked by their vanishing divergence.  Calls only
+``oracle/``.
 
 Run: python tests/golden/make_sphere128.py   (about an hour on 8 cores)
 """
@@ -29,9 +30,9 @@ def main():
     vc = mg.VCycle(fr, n, h, sig, 5)
     op = vc.levels[0].op
     print(f"operators {time.time() - t0:.0f}s, active faces {op.act.size}", flush=True)
-    lam, B, info = eigs.lanczos_eigs(op, 8, sigma_o=sig, block=4, tol=1e-11, max_blocks=60,
-                                     cg_tol=1e-12, precond=vc.apply_active, project=False,
-                                     log=lambda s: print(f"{time.time() - t0:.0f}s {s}", flush=True))
+    lam, B, info = eigs.augmented_eigs(op, 8, sigma_o=sig, block=4, tol=1e-11, max_blocks=60,
+                                       cg_tol=1e-12, precond=vc.apply_active,
+                                       log=lambda s: print(f"{time.time() - t0:.0f}s {s}", flush=True))
     div = [eigs.div_residual(op, B[:, c]) for c in range(B.shape[1])]
     out = dict(config="sphere R=0.45 centred in the unit cube, 128^3 cells, h=1/128",
                lam=[float(x) for x in lam], residuals=[float(x) for x in info["residuals"]],

@@ -53,6 +53,18 @@ def test_dense_vs_lanczos_sphere_8():
     assert np.max(abs(G - np.eye(6))) < 1e-12
 
 
+def test_augmented_route_matches_dense_sphere_8():
+    """Sec. 5.1: the EM pairs of (K + G, A), selected by zero divergence, are
+    the nonzero pairs of (K, A)."""
+    n, h = (8, 8, 8), 1.0 / 8
+    fr = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), n, h)
+    op = ops.build(fr, n, h, 5.0)
+    w, _ = eigs.dense_eigs(op, 6)
+    lam, B, info = eigs.augmented_eigs(op, 6, sigma_o=5.0, block=4, tol=1e-11)
+    assert np.max(abs(lam - w) / w) < 1e-12
+    assert info["residuals"].max() <= 1e-11
+
+
 def test_sphere_tm11_second_order_convergence():
     """Sec. 6.2 / Fig. fig:freqErr3d: with every cut face kept the
     Dey--Mittra frequencies converge at second order.  TM_11 of a sphere of
