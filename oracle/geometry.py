@@ -215,6 +215,167 @@ def sphere(center=(0.5, 0.5, 0.5), radius=0.45) -> Ellipsoid:
     return Ellipsoid(tuple(center), (radius, radius, radius))
 
 
+@dataclass
+class EllipticCells:
+    """Open body of revolution about the z-line through (ax, ay): a tube of
+    radius r_iris and length `tube`, `ncell` cells whose radius rises along
+    an elliptic arc from r_iris at both cell ends to r_eq at the cell middle,
+    and a second tube; conducting end plates at z0 and z0 + 2 tube + ncell L.
+    (A synthetic stand-in for the multi-cell accelerator cavity of Sec. 6.3,
+    whose real profile the paper does not give.)"""
+
+    axis: tuple
+    z0: float
+    ncell: int
+    r_eq: float
+    r_iris: float
+    L: float
+    tube: float
+
+    @property
+    def z_end(self):
+        return self.z0 + 2 * self.tube + self.ncell * self.L
+
+    def centres(self):
+        c0 = self.z0 + self.tube
+        return [c0 + (m + 0.5) * self.L for m in range(self.ncell)]
+
+    def junctions(self):
+        c0 = self.z0 + self.tube
+        return [self.z0, self.z_end] + [c0 + m * self.L for m in range(self.ncell + 1)]
+
+    def radius(self, z):
+        if not (self.z0 < z < self.z_end):
+            return 0.0
+        for zc in self.centres():
+            t = (z - zc) / (0.5 * self.L)
+            if abs(t) < 1.0:
+                return self.r_iris + (self.r_eq - self.r_iris) * math.sqrt(1.0 - t * t)
+        return self.r_iris
+
+    def above(self, R):
+        """Intervals of z where radius(z) > R (R >= 0)."""
+        out = []
+        c0 = self.z0 + self.tube
+        if R < self.r_iris:
+            return [(self.z0, self.z_end)]
+        if R >= self.r_eq:
+            return out
+        t = (R - self.r_iris) / (self.r_eq - self.r_iris)
+        half = 0.5 * self.L * math.sqrt(1.0 - t * t)
+        for zc in self.centres():
+            out.append((zc - half, zc + half))
+        return out
+
+    def crossings(self, R):
+        """z where radius(z) passes through R."""
+        pts = []
+        for a, b in self.above(R):
+            pts += [a, b]
+        return pts
+
+    def _rlim(self, z):
+        """radius(z), with the tube radius as the limit at the end plates"""
+        if z <= self.z0 or z >= self.z_end:
+            return self.r_iris
+        return self.radius(z)
+
+    def _rmin_rmax(self, zlo, zhi):
+        """Bounds of radius(z) over [zlo, zhi] intersect (z0, z_end): the
+        profile is monotone between a junction and the next cell middle."""
+        a, b = max(zlo, self.z0), min(zhi, self.z_end)
+        zs = [a, b] + [z for z in self.junctions() if a < z < b]
+        rs = [self._rlim(z) for z in zs]
+        rmax = max(rs + [self.r_eq for zc in self.centres() if a < zc < b])
+        return min(rs), rmax
+
+    def classify(self, lo, hi):
+        ax, ay = self.axis
+        dx = [lo[0] - ax, hi[0] - ax]
+        dy = [lo[1] - ay, hi[1] - ay]
+        far = math.sqrt(max(d * d for d in dx) + max(d * d for d in dy))
+        nx = 0.0 if dx[0] <= 0.0 <= dx[1] else min(abs(dx[0]), abs(dx[1]))
+        ny = 0.0 if dy[0] <= 0.0 <= dy[1] else min(abs(dy[0]), abs(dy[1]))
+        near = math.hypot(nx, ny)
+        if hi[2] <= self.z0 or lo[2] >= self.z_end:
+            return 0
+        rmin, rmax = self._rmin_rmax(lo[2], hi[2])
+        if near >= rmax:
+            return 0
+        if far < rmin and lo[2] > self.z0 and hi[2] < self.z_end:
+            return 1
+        return -1
+
+    def edge_len(self, axis, lo, hi, p):
+        ax, ay = self.axis
+        if axis == 2:
+            rho = math.hypot(p[0] - ax, p[1] - ay)
+            return sum(interval_overlap(lo, hi, a, b) for a, b in self.above(rho))
+        r = self.radius(p[2])
+        other = p[1] - ay if axis == 0 else p[0] - ax
+        if r <= abs(other):
+            return 0.0
+        s = math.sqrt(r * r - other * other)
+        c = ax if axis == 0 else ay
+        return interval_overlap(lo, hi, c - s, c + s)
+
+    def face_area(self, axis, c, lo2, hi2):
+        ax, ay = self.axis
+        if axis == 2:
+            return disk_rect_area(self.radius(c), lo2[0] - ax, hi2[0] - ax, lo2[1] - ay, hi2[1] - ay)
+        # x-face (axis 0): coordinates (y, z); y-face (axis 1): (x, z)
+        d = c - (ax if axis == 0 else ay)
+        cen = ay if axis == 0 else ax
+        t0, t1 = lo2[0] - cen, hi2[0] - cen
+        zlo, zhi = lo2[1], hi2[1]
+
+        def chord(z):
+            r = self.radius(z)
+            if r <= abs(d):
+                return 0.0
+            s = math.sqrt(r * r - d * d)
+            return interval_overlap(t0, t1, -s, s)
+
+        pts = set(z for z in self.junctions() if zlo < z < zhi)
+        for R in (abs(d), math.hypot(d, t0), math.hypot(d, t1)):
+            pts.update(z for z in self.crossings(R) if zlo < z < zhi)
+        val, _ = integrate.quad(chord, zlo, zhi, points=sorted(pts) or None,
+                                epsabs=1e-17, epsrel=1e-13, limit=400)
+        return val
+
+    def cell_vol(self, lo3, hi3):
+        ax, ay = self.axis
+        x0, x1, y0, y1 = lo3[0] - ax, hi3[0] - ax, lo3[1] - ay, hi3[1] - ay
+        zlo, zhi = lo3[2], hi3[2]
+
+        def area(z):
+            return disk_rect_area(self.radius(z), x0, x1, y0, y1)
+
+        dists = {abs(x0), abs(x1), abs(y0), abs(y1)}
+        dists.update(math.hypot(x, y) for x in (x0, x1) for y in (y0, y1))
+        pts = set(z for z in self.junctions() if zlo < z < zhi)
+        for R in dists:
+            pts.update(z for z in self.crossings(R) if zlo < z < zhi)
+        val, _ = integrate.quad(area, zlo, zhi, points=sorted(pts) or None,
+                                epsabs=1e-17, epsrel=1e-13, limit=400)
+        return val
+
+
+def nine_cell(axis=(0.0, 0.0), z0=0.0, ncell=9, r_eq=0.103, r_iris=0.035, L=0.115, tube=0.1):
+    """The synthetic 9-cell elliptic cavity (equator 0.103, iris 0.035, cells
+    0.115 long, 0.1 end tubes)."""
+    return EllipticCells(tuple(axis), z0, ncell, r_eq, r_iris, L, tube)
+
+
+def bor_volume(g: EllipticCells):
+    """Exact volume of the body: pi * integral of r(z)^2."""
+    v = 2 * g.tube * math.pi * g.r_iris ** 2
+    a, b = g.r_iris, g.r_eq - g.r_iris
+    # one cell: integral over the length L of (a + b sqrt(1-t^2))^2 with z = t L/2
+    cell = 0.5 * g.L * (2 * a * a + math.pi * a * b + (4.0 / 3.0) * b * b)
+    return v + g.ncell * math.pi * cell
+
+
 # ---------------------------------------------------------------------------
 # Fraction arrays on the Yee grid
 # ---------------------------------------------------------------------------

@@ -83,15 +83,20 @@ bool valid_geometry(const dm_geometry *g, std::string &why) {
             why = "bc_lo must be DM_BC_PEC or DM_BC_PMC";
             return false;
         }
-    if (g->bc_lo[0] == DM_BC_PMC || g->bc_lo[1] == DM_BC_PMC || g->bc_lo[2] == DM_BC_PMC) {
-        why = "PMC symmetry planes are not supported by this build";
-        return false;
-    }
     if (!(g->a_min >= 0.0 && g->a_min < 1.0)) {
         why = "a_min must be in [0, 1)";
         return false;
     }
     return true;
+}
+
+// PMC planes: refresh the ghost layer of a caller face / cell vector that a
+// kernel reads across the plane (writes the caller's padding only)
+void fill_ghosts(const Level &L, int prec, const void *v, bool cells, hipStream_t s) {
+    if (!L.g.pmc) return;
+    if (cells) launch_mirror_cells(L.g, (double *)v, s);
+    else if (prec == 64) launch_mirror_faces<double>(L.g, (double *)v, s);
+    else launch_mirror_faces<float>(L.g, (float *)v, s);
 }
 
 int auto_levels(const int d[3]) {
@@ -167,12 +172,16 @@ int dm_compute_fractions(const dm_geometry *geom, const int dims[3], double h, d
         if (!(h > 0.0)) return fail(DM_EINVAL, "h must be positive");
         if (!out_host) return fail(DM_EINVAL, "out_host is NULL");
         if (geom->kind == DM_GEOM_USER) return fail(DM_EINVAL, "user geometry has no computed fractions");
-        Grid g = make_grid(dims[0], dims[1], dims[2], h);
+        int pmc = 0;
+        for (int a = 0; a < 3; ++a)
+            if (geom->bc_lo[a] == DM_BC_PMC) pmc |= 1 << a;
+        Grid g = make_grid(dims[0], dims[1], dims[2], h, pmc);
         std::unique_ptr<Body> body = make_body(*geom);
         if (!body) return fail(DM_EINVAL, "geometry kind not available");
         std::vector<double> fr;
         compute_fractions(*body, g, geom->bc_lo, fr);
         neglect_faces(g, geom->a_min, fr);
+        mirror_fraction_ghosts(g, fr);
         std::memcpy(out_host, fr.data(), fr.size() * sizeof(double));
         return DM_OK;
     });
@@ -270,6 +279,7 @@ int dm_apply(dm_op *op, int which, int prec, int level, const void *x, void *y, 
     if (which >= DM_APPLY_DA && prec != 64) return fail(DM_EINVAL, "scalar operators are FP64 only");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         const Level &L = op->lv[level];
+        fill_ghosts(L, prec, x, which == DM_APPLY_DT || which == DM_APPLY_S, s);
         switch (which) {
             case DM_APPLY_M:
             case DM_APPLY_K: {
@@ -306,6 +316,7 @@ int dm_residual(dm_op *op, int prec, int level, const void *f, const void *x, vo
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         const Level &L = op->lv[level];
+        fill_ghosts(L, prec, x, false, s);
         if (prec == 64)
             launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, (const double *)f, (const double *)x, (double *)r, s);
         else
@@ -322,6 +333,7 @@ int dm_smooth(dm_op *op, int prec, int level, int n_sweeps, int reverse, const v
     if (n_sweeps < 0) return fail(DM_EINVAL, "n_sweeps must be >= 0");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         const Level &L = op->lv[level];
+        fill_ghosts(L, prec, x, false, s);
         for (int it = 0; it < n_sweeps; ++it)
             for (int q = 0; q < 6; ++q) {
                 const int cls = reverse ? 5 - q : q;
@@ -341,6 +353,7 @@ int dm_restrict(dm_op *op, int prec, int level, const void *r, void *fc, void *s
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         const Level &F = op->lv[level], &C = op->lv[level + 1];
+        fill_ghosts(F, prec, r, false, s);
         if (prec == 64) launch_restrict<double>(F.g, C.g, C.coef64, (const double *)r, (double *)fc, s);
         else launch_restrict<float>(F.g, C.g, C.coef32, (const float *)r, (float *)fc, s);
         return DM_OK;
@@ -353,6 +366,7 @@ int dm_prolong_add(dm_op *op, int prec, int level, const void *xc, void *x, void
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         const Level &F = op->lv[level], &C = op->lv[level + 1];
+        fill_ghosts(F, prec, x, false, s);
         if (prec == 64) launch_prolong_add<double>(F.g, C.g, F.coef64, (const double *)xc, (double *)x, s);
         else launch_prolong_add<float>(F.g, C.g, F.coef32, (const float *)xc, (float *)x, s);
         return DM_OK;
@@ -363,6 +377,7 @@ int dm_vcycle(dm_op *op, int prec, const void *f, void *x, void *stream) {
     if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
     return on_device(op, stream, [&](hipStream_t s) -> int {
+        fill_ghosts(op->lv[0], prec, f, false, s);
         if (prec == 64) vcycle<double>(op, 0, (const double *)f, (double *)x, s);
         else vcycle<float>(op, 0, (const float *)f, (float *)x, s);
         return DM_OK;
@@ -373,6 +388,7 @@ int dm_project(dm_op *op, const double *b, double *out, double rtol, void *strea
     if (!op || !b || !out) return fail(DM_EINVAL, "NULL argument");
     if (!(rtol > 0.0)) return fail(DM_EINVAL, "rtol must be positive");
     return on_device(op, stream, [&](hipStream_t s) -> int {
+        fill_ghosts(op->lv[0], 64, b, false, s);
         return project(op, b, out, rtol, 2000, s, nullptr);
     });
 }
@@ -383,6 +399,7 @@ int dm_solve(dm_op *op, int mode, const double *f, double *x, double rtol, int m
     if (mode < DM_SOLVE_PCG64 || mode > DM_SOLVE_FGMRES_MG32) return fail(DM_EINVAL, "unknown solve mode");
     if (!(rtol > 0.0) || maxit < 1) return fail(DM_EINVAL, "rtol must be positive and maxit >= 1");
     return on_device(op, stream, [&](hipStream_t s) -> int {
+        fill_ghosts(op->lv[0], 64, f, false, s);
         return solve(op, mode, f, x, rtol, maxit, info, s);
     });
 }

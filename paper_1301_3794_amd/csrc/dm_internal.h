@@ -24,20 +24,117 @@ struct Grid {
     int64_t sz;    // k stride = (nx+2)(ny+2)
     int64_t P;     // elements per block
     double h;
+    int pmc;       // bit a set: the low side of axis a is a PMC symmetry plane
 };
 
-inline Grid make_grid(int nx, int ny, int nz, double h) {
+inline Grid make_grid(int nx, int ny, int nz, double h, int pmc = 0) {
     Grid g;
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.sy = nx + 2;
     g.sz = (int64_t)(nx + 2) * (ny + 2);
     g.P = g.sz * (nz + 2);
     g.h = h;
+    g.pmc = pmc;
     return g;
 }
 
 __host__ __device__ inline int64_t pidx(const Grid &g, int i, int j, int k) {
     return (int64_t)(i + 1) + (int64_t)(j + 1) * g.sy + (int64_t)(k + 1) * g.sz;
+}
+
+// ---------------------------------------------------------------------------
+// PMC symmetry planes (quarter-cavity runs, Sec. 6.3).  A low-side plane of
+// axis a is a node plane; the field continues across it as a mirror image:
+// the face component normal to a is even (ghost at -1 = value at +1), the
+// tangential components and cell scalars are odd (ghost at -1 = -value at 0).
+// The padding layer holds these ghosts, so the stencil rows below evaluate
+// the full-cavity operator on the symmetric field.  Every kernel that writes
+// a vector also writes the ghost images of what it owns.
+// ---------------------------------------------------------------------------
+
+// Ghost images of face component `comp` owned by cell (i,j,k): up to 7
+// (offset, sign) pairs (both planes and their corner).  Returns the count.
+__host__ __device__ inline int face_images(const Grid &g, int comp, int i, int j, int k,
+                                           int64_t off[7], signed char sgn[7]) {
+    int64_t o1[3];
+    signed char s1[3];
+    int na = 0;
+    const int idx[3] = {i, j, k};
+    const int64_t stride[3] = {1, g.sy, g.sz};
+    for (int a = 0; a < 3; ++a) {
+        if (!((g.pmc >> a) & 1)) continue;
+        if (comp == a && idx[a] == 1) { o1[na] = -2 * stride[a]; s1[na] = 1; ++na; }
+        else if (comp != a && idx[a] == 0) { o1[na] = -stride[a]; s1[na] = -1; ++na; }
+    }
+    int cnt = 0;
+    for (int m = 1; m < (1 << na); ++m) {
+        int64_t o = 0;
+        int s = 1;
+        for (int b = 0; b < na; ++b)
+            if ((m >> b) & 1) { o += o1[b]; s *= s1[b]; }
+        off[cnt] = o;
+        sgn[cnt] = (signed char)s;
+        ++cnt;
+    }
+    return cnt;
+}
+
+// Ghost images of a cell scalar (odd across every PMC plane) at (i,j,k).
+__host__ __device__ inline int cell_images(const Grid &g, int i, int j, int k, int64_t off[7],
+                                           signed char sgn[7]) {
+    int64_t o1[3];
+    int na = 0;
+    const int idx[3] = {i, j, k};
+    const int64_t stride[3] = {1, g.sy, g.sz};
+    for (int a = 0; a < 3; ++a)
+        if (((g.pmc >> a) & 1) && idx[a] == 0) o1[na++] = -stride[a];
+    int cnt = 0;
+    for (int m = 1; m < (1 << na); ++m) {
+        int64_t o = 0;
+        int s = 1;
+        for (int b = 0; b < na; ++b)
+            if ((m >> b) & 1) { o += o1[b]; s = -s; }
+        off[cnt] = o;
+        sgn[cnt] = (signed char)s;
+        ++cnt;
+    }
+    return cnt;
+}
+
+template <class T>
+__host__ __device__ inline void put_face(const Grid &g, T *arr, int comp, int i, int j, int k,
+                                         int64_t p, T v) {
+    arr[p] = v;
+    if (g.pmc) {
+        int64_t off[7];
+        signed char sg[7];
+        const int n = face_images(g, comp, i, j, k, off, sg);
+        for (int q = 0; q < n; ++q) arr[p + off[q]] = sg[q] > 0 ? v : -v;
+    }
+}
+
+template <class T>
+__host__ __device__ inline void put_cell(const Grid &g, T *arr, int i, int j, int k, int64_t p, T v) {
+    arr[p] = v;
+    if (g.pmc) {
+        int64_t off[7];
+        signed char sg[7];
+        const int n = cell_images(g, i, j, k, off, sg);
+        for (int q = 0; q < n; ++q) arr[p + off[q]] = sg[q] > 0 ? v : -v;
+    }
+}
+
+// extra diagonal of the curl-curl row from the odd mirror of a tangential
+// component on a PMC plane (the edge in the plane sees the value twice)
+template <class T>
+__host__ __device__ inline T pmc_diag_extra(const Grid &g, const T *lx, const T *ly, const T *lz,
+                                            int comp, int i, int j, int k, int64_t p) {
+    if (!g.pmc) return T(0);
+    T e = T(0);
+    if ((g.pmc & 1) && i == 0) e += comp == 1 ? lz[p] : (comp == 2 ? ly[p] : T(0));
+    if ((g.pmc & 2) && j == 0) e += comp == 0 ? lz[p] : (comp == 2 ? lx[p] : T(0));
+    if ((g.pmc & 4) && k == 0) e += comp == 0 ? ly[p] : (comp == 1 ? lx[p] : T(0));
+    return e;
 }
 
 enum { CAX = 0, CAY, CAZ, CLX, CLY, CLZ, CVINV, NCOEF };
@@ -145,6 +242,12 @@ void launch_coarse_solve(int n, const double *inv, const int64_t *idx, const T *
 void launch_apply_A(const Grid &g, const double *coef, const double *x, double *y, hipStream_t s);
 template <class T>
 void launch_apply_A_t(const Grid &g, const T *coef, const T *x, T *y, hipStream_t s);
+
+// PMC ghost layers of a face / cell vector from the adjacent values (no-op
+// without PMC planes)
+template <class T>
+void launch_mirror_faces(const Grid &g, T *x, hipStream_t s);
+void launch_mirror_cells(const Grid &g, double *x, hipStream_t s);
 
 // scalar (cell-centred) Laplacian S = D A D^T with per-level weight `w`
 void launch_div_DA(const Grid &g, const double *coef, const double *b, double *gout,

@@ -82,6 +82,8 @@ double integrate_smooth(const std::function<double(double)> &f, double a, double
     return s * L;
 }
 
+}  // namespace
+
 double integrate_pieces(const std::function<double(double)> &f, double a, double b,
                         std::vector<double> cuts) {
     cuts.push_back(a);
@@ -96,6 +98,8 @@ double integrate_pieces(const std::function<double(double)> &f, double a, double
     }
     return s;
 }
+
+namespace {
 
 // antiderivative of sqrt(rho^2 - t^2), t clamped to [-rho, rho]
 inline double arc_prim(double t, double rho) {
@@ -293,6 +297,34 @@ void compute_fractions(const Body &body, const Grid &g, const int bc_lo[3],
         th.emplace_back(work, k0, k1);
     }
     for (auto &t : th) t.join();
+}
+
+// PMC ghost layer of the fraction blocks: the mirror image of the cavity
+// across each low-side PMC plane (planes in the order x, y, z so corners
+// get both mirrors).  Across the plane normal to a, a node-centred quantity
+// (face normal to a, edge across a) at -1 mirrors +1; a cell-centred one
+// (other faces, edge along a, cell) at -1 mirrors 0.
+void mirror_fraction_ghosts(const Grid &g, std::vector<double> &fr) {
+    if (!g.pmc) return;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int64_t stride[3] = {1, g.sy, g.sz};
+    for (int a = 0; a < 3; ++a) {
+        if (!((g.pmc >> a) & 1)) continue;
+        const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
+        for (int u = -1; u <= n[b]; ++u)
+            for (int v = -1; v <= n[d]; ++v) {
+                int idx[3];
+                idx[a] = -1;
+                idx[b] = u;
+                idx[d] = v;
+                const int64_t pg = pidx(g, idx[0], idx[1], idx[2]);
+                for (int blk = 0; blk < 7; ++blk) {
+                    // node-centred along a: face blk==a, edges 3+e with e != a
+                    const bool node = (blk < 3 && blk == a) || (blk >= 3 && blk < 6 && blk - 3 != a);
+                    fr[blk * g.P + pg] = fr[blk * g.P + pg + (node ? 2 : 1) * stride[a]];
+                }
+            }
+    }
 }
 
 // Face neglect (Sec. 3): faces with 0 < a < a_min lose their b (a := 0) and

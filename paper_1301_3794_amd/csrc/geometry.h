@@ -1,6 +1,7 @@
 // Host-side cavity geometries and cut-fraction arrays (setup step).
 #pragma once
 
+#include <functional>
 #include <memory>
 #include <vector>
 
@@ -25,9 +26,14 @@ struct Body {
 
 std::unique_ptr<Body> make_body(const dm_geometry &g);
 double disk_rect_area(double rho, double x0, double x1, double y0, double y1);
+// integral of f over [a, b], split at `cuts` (kinks of f), each piece by
+// Gauss--Legendre after a map that flattens endpoint (x - a)^{1/2..3/2} terms
+double integrate_pieces(const std::function<double(double)> &f, double a, double b,
+                        std::vector<double> cuts);
 void compute_fractions(const Body &body, const Grid &g, const int bc_lo[3],
                        std::vector<double> &out);
 void neglect_faces(const Grid &g, double a_min, std::vector<double> &fr);
+void mirror_fraction_ghosts(const Grid &g, std::vector<double> &fr);
 void coarsen_fractions(const Grid &gf, const std::vector<double> &ff, const Grid &gc,
                        std::vector<double> &fc);
 

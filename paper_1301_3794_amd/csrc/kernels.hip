@@ -78,9 +78,9 @@ k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restric
             yz = f[2 * P + p] - yz;
         }
     }
-    y[p] = c.ax[p] != T(0) ? yx : T(0);
-    y[P + p] = c.ay[p] != T(0) ? yy : T(0);
-    y[2 * P + p] = c.az[p] != T(0) ? yz : T(0);
+    put_face<T>(g, y, 0, i, j, k, p, c.ax[p] != T(0) ? yx : T(0));
+    put_face<T>(g, y + P, 1, i, j, k, p, c.ay[p] != T(0) ? yy : T(0));
+    put_face<T>(g, y + 2 * P, 2, i, j, k, p, c.az[p] != T(0) ? yz : T(0));
 }
 
 // y = A x
@@ -90,14 +90,16 @@ k_apply_A(Grid g, Coefs<T> c, const T *__restrict__ x, T *__restrict__ y) {
     int i, j, k;
     if (!cell_of(g, xcd_item(), i, j, k)) return;
     const int64_t P = g.P, p = pidx(g, i, j, k);
-    y[p] = c.ax[p] * x[p];
-    y[P + p] = c.ay[p] * x[P + p];
-    y[2 * P + p] = c.az[p] * x[2 * P + p];
+    put_face<T>(g, y, 0, i, j, k, p, c.ax[p] * x[p]);
+    put_face<T>(g, y + P, 1, i, j, k, p, c.ay[p] * x[P + p]);
+    put_face<T>(g, y + 2 * P, 2, i, j, k, p, c.az[p] * x[2 * P + p]);
 }
 
 // ---------------------------------------------------------------------------
 // Red-black Gauss--Seidel: one (component, colour) class, colour = (i+j+k)&1.
 // Threads cover half the cells of each row: i = 2*ih + ((j+k+colour)&1).
+// A thread also refreshes the PMC ghost images of the value it updates; no
+// row of the same class reads those images except its own.
 // ---------------------------------------------------------------------------
 template <class T, int COMP>
 __global__ void __launch_bounds__(kThreads)
@@ -122,8 +124,9 @@ k_smooth(Grid g, Coefs<T> c, T sigma, int colour, const T *__restrict__ f, T *__
     else if (COMP == 1) row = row_y<T, true>(c, X, Y, Z, p, dy, dz);
     else row = row_z<T, true>(c, X, Y, Z, p, dy, dz);
     row = ih2 * row - sigma * a[p] * xc[p];
-    const T d = diag_of<T>(c, COMP, p, dy, dz, ih2, sigma);
-    xc[p] += (f[COMP * P + p] - row) / d;
+    const T d = diag_of<T>(c, COMP, p, dy, dz, ih2, sigma) +
+                ih2 * pmc_diag_extra<T>(g, c.lx, c.ly, c.lz, COMP, i, j, k, p);
+    put_face<T>(g, xc, COMP, i, j, k, p, xc[p] + (f[COMP * P + p] - row) / d);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,9 +155,9 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
             sz += RZ[qz] + T(0.5) * (RZ[qz - fz] + RZ[qz + fz]);
         }
     const T e = T(0.125);
-    fc[pc] = cc.ax[pc] != T(0) ? e * sx : T(0);
-    fc[Pc + pc] = cc.ay[pc] != T(0) ? e * sy : T(0);
-    fc[2 * Pc + pc] = cc.az[pc] != T(0) ? e * sz : T(0);
+    put_face<T>(gc, fc, 0, I, J, K, pc, cc.ax[pc] != T(0) ? e * sx : T(0));
+    put_face<T>(gc, fc + Pc, 1, I, J, K, pc, cc.ay[pc] != T(0) ? e * sy : T(0));
+    put_face<T>(gc, fc + 2 * Pc, 2, I, J, K, pc, cc.az[pc] != T(0) ? e * sz : T(0));
 }
 
 template <class T>
@@ -166,9 +169,12 @@ k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, const T *__restrict__ xc, T *__rest
     const int64_t p = pidx(gf, i, j, k);
     const int64_t q = pidx(gc, i >> 1, j >> 1, k >> 1);
     const T *CX = xc, *CY = xc + Pc, *CZ = xc + 2 * Pc;
-    if (cf.ax[p] != T(0)) x[p] += (i & 1) ? T(0.5) * (CX[q] + CX[q + 1]) : CX[q];
-    if (cf.ay[p] != T(0)) x[Pf + p] += (j & 1) ? T(0.5) * (CY[q] + CY[q + cy]) : CY[q];
-    if (cf.az[p] != T(0)) x[2 * Pf + p] += (k & 1) ? T(0.5) * (CZ[q] + CZ[q + cz]) : CZ[q];
+    if (cf.ax[p] != T(0))
+        put_face<T>(gf, x, 0, i, j, k, p, x[p] + ((i & 1) ? T(0.5) * (CX[q] + CX[q + 1]) : CX[q]));
+    if (cf.ay[p] != T(0))
+        put_face<T>(gf, x + Pf, 1, i, j, k, p, x[Pf + p] + ((j & 1) ? T(0.5) * (CY[q] + CY[q + cy]) : CY[q]));
+    if (cf.az[p] != T(0))
+        put_face<T>(gf, x + 2 * Pf, 2, i, j, k, p, x[2 * Pf + p] + ((k & 1) ? T(0.5) * (CZ[q] + CZ[q + cz]) : CZ[q]));
 }
 
 template <class TI, class TO>
@@ -198,6 +204,42 @@ k_coarse_solve(int n, const double *__restrict__ inv, const int64_t *__restrict_
     }
 }
 
+// PMC ghost layer of one plane (axis a) from the values next to it; planes
+// are filled in the order x, y, z so corner ghosts get both mirrors.
+template <class T>
+__global__ void k_mirror_faces(Grid g, int a, T *__restrict__ x) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
+    const int nb = n[b] + 2, nd = n[d] + 2;
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= (int64_t)nb * nd) return;
+    int idx[3];
+    idx[b] = (int)(t % nb) - 1;
+    idx[d] = (int)(t / nb) - 1;
+    idx[a] = -1;
+    const int64_t stride[3] = {1, g.sy, g.sz};
+    const int64_t pg = pidx(g, idx[0], idx[1], idx[2]);
+    for (int comp = 0; comp < 3; ++comp) {
+        T *arr = x + comp * g.P;
+        arr[pg] = comp == a ? arr[pg + 2 * stride[a]] : -arr[pg + stride[a]];
+    }
+}
+
+__global__ void k_mirror_cells(Grid g, int a, double *__restrict__ x) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
+    const int nb = n[b] + 2, nd = n[d] + 2;
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= (int64_t)nb * nd) return;
+    int idx[3];
+    idx[b] = (int)(t % nb) - 1;
+    idx[d] = (int)(t / nb) - 1;
+    idx[a] = -1;
+    const int64_t stride[3] = {1, g.sy, g.sz};
+    const int64_t pg = pidx(g, idx[0], idx[1], idx[2]);
+    x[pg] = -x[pg + stride[a]];
+}
+
 // ---------------------------------------------------------------------------
 // Scalar problem: g = D A b, b -= D^T psi, S = D A D^T (weight w per level)
 // ---------------------------------------------------------------------------
@@ -209,7 +251,7 @@ k_div_DA(Grid g, Coefs<double> c, const double *__restrict__ b, double *__restri
     const double *X = b, *Y = b + P, *Z = b + 2 * P;
     const double s = c.ax[p + 1] * X[p + 1] - c.ax[p] * X[p] + c.ay[p + dy] * Y[p + dy] -
                      c.ay[p] * Y[p] + c.az[p + dz] * Z[p + dz] - c.az[p] * Z[p];
-    out[p] = c.vinv[p] != 0.0 ? s / g.h : 0.0;
+    put_cell<double>(g, out, i, j, k, p, c.vinv[p] != 0.0 ? s / g.h : 0.0);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -220,9 +262,12 @@ k_grad_sub(Grid g, Coefs<double> c, const double *__restrict__ psi, const double
     const int64_t P = g.P, dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
     const double s = scale / g.h;
     const double pp = psi[p];
-    bout[p] = c.ax[p] != 0.0 ? bin[p] - s * (psi[p - 1] - pp) : 0.0;
-    bout[P + p] = c.ay[p] != 0.0 ? bin[P + p] - s * (psi[p - dy] - pp) : 0.0;
-    bout[2 * P + p] = c.az[p] != 0.0 ? bin[2 * P + p] - s * (psi[p - dz] - pp) : 0.0;
+    const double vx = c.ax[p] != 0.0 ? bin[p] - s * (psi[p - 1] - pp) : 0.0;
+    const double vy = c.ay[p] != 0.0 ? bin[P + p] - s * (psi[p - dy] - pp) : 0.0;
+    const double vz = c.az[p] != 0.0 ? bin[2 * P + p] - s * (psi[p - dz] - pp) : 0.0;
+    put_face<double>(g, bout, 0, i, j, k, p, vx);
+    put_face<double>(g, bout + P, 1, i, j, k, p, vy);
+    put_face<double>(g, bout + 2 * P, 2, i, j, k, p, vz);
 }
 
 __device__ inline double s_row(const Coefs<double> &c, const double *x, int64_t p, int64_t dy,
@@ -241,7 +286,7 @@ k_s_apply(Grid g, Coefs<double> c, double w, int resid, const double *__restrict
     const int64_t p = pidx(g, i, j, k);
     double v = w * s_row(c, x, p, g.sy, g.sz);
     if (resid) v = f[p] - v;
-    y[p] = c.vinv[p] != 0.0 ? v : 0.0;
+    put_cell<double>(g, y, i, j, k, p, c.vinv[p] != 0.0 ? v : 0.0);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -257,9 +302,14 @@ k_s_smooth(Grid g, Coefs<double> c, double w, int colour, const double *__restri
     if (i >= g.nx) return;
     const int64_t dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
     if (c.vinv[p] == 0.0) return;
-    const double d = w * (c.ax[p] + c.ax[p + 1] + c.ay[p] + c.ay[p + dy] + c.az[p] + c.az[p + dz]);
+    double d = c.ax[p] + c.ax[p + 1] + c.ay[p] + c.ay[p + dy] + c.az[p] + c.az[p + dz];
+    // odd mirror across a PMC plane: the face in the plane counts twice
+    if ((g.pmc & 1) && i == 0) d += c.ax[p];
+    if ((g.pmc & 2) && j == 0) d += c.ay[p];
+    if ((g.pmc & 4) && k == 0) d += c.az[p];
+    d *= w;
     if (d == 0.0) return;
-    x[p] += (f[p] - w * s_row(c, x, p, dy, dz)) / d;
+    put_cell<double>(g, x, i, j, k, p, x[p] + (f[p] - w * s_row(c, x, p, dy, dz)) / d);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -274,7 +324,7 @@ k_s_restrict(Grid gf, Grid gc, Coefs<double> cc, const double *__restrict__ r,
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) s += r[q + a * fy + b * fz] + r[q + 1 + a * fy + b * fz];
-    fc[pc] = cc.vinv[pc] != 0.0 ? 0.125 * s : 0.0;
+    put_cell<double>(gc, fc, I, J, K, pc, cc.vinv[pc] != 0.0 ? 0.125 * s : 0.0);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -283,7 +333,7 @@ k_s_prolong_add(Grid gf, Grid gc, Coefs<double> cf, const double *__restrict__ x
     int i, j, k;
     if (!cell_of(gf, xcd_item(), i, j, k)) return;
     const int64_t p = pidx(gf, i, j, k);
-    if (cf.vinv[p] != 0.0) x[p] += xc[pidx(gc, i >> 1, j >> 1, k >> 1)];
+    if (cf.vinv[p] != 0.0) put_cell<double>(gf, x, i, j, k, p, x[p] + xc[pidx(gc, i >> 1, j >> 1, k >> 1)]);
 }
 
 // ---------------------------------------------------------------------------
@@ -691,6 +741,30 @@ void launch_s_prolong_add(const Grid &gf, const Grid &gc, const double *coef_f,
     hipLaunchKernelGGL(k_s_prolong_add, xcd_grid(n), dim3(kThreads), 0, s, gf, gc,
                        coefs_of(coef_f, gf.P), xc, x);
 }
+
+template <class T>
+void launch_mirror_faces(const Grid &g, T *x, hipStream_t s) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (!((g.pmc >> a) & 1)) continue;
+        const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
+        const int64_t cnt = (int64_t)(n[b] + 2) * (n[d] + 2);
+        hipLaunchKernelGGL((k_mirror_faces<T>), dim3((unsigned)ceil_div(cnt, kThreads)), dim3(kThreads), 0, s, g, a, x);
+    }
+}
+
+void launch_mirror_cells(const Grid &g, double *x, hipStream_t s) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (!((g.pmc >> a) & 1)) continue;
+        const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
+        const int64_t cnt = (int64_t)(n[b] + 2) * (n[d] + 2);
+        hipLaunchKernelGGL(k_mirror_cells, dim3((unsigned)ceil_div(cnt, kThreads)), dim3(kThreads), 0, s, g, a, x);
+    }
+}
+
+template void launch_mirror_faces<double>(const Grid &, double *, hipStream_t);
+template void launch_mirror_faces<float>(const Grid &, float *, hipStream_t);
 
 void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_axpy, flat_grid(n), dim3(kThreads), 0, s, n, a, x, y);

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 #include "geometry.h"
@@ -11,6 +12,9 @@
 namespace dm {
 
 namespace {
+
+// largest coarsest level factored densely (its inverse is n^2 doubles)
+constexpr int kMaxCoarse = 4000;
 
 // In-place inverse of a dense row-major n x n matrix by Gauss--Jordan with
 // partial pivoting.  Returns the smallest |pivot| / largest |pivot|.
@@ -42,20 +46,54 @@ double invert_dense(std::vector<double> &a, int n) {
             a[(size_t)c * n + k] *= d;
             inv[(size_t)c * n + k] *= d;
         }
-        for (int r = 0; r < n; ++r) {
-            if (r == c) continue;
-            const double m = a[(size_t)r * n + c];
-            if (m == 0.0) continue;
-            double *ar = &a[(size_t)r * n], *ac = &a[(size_t)c * n];
-            double *ir = &inv[(size_t)r * n], *ic = &inv[(size_t)c * n];
-            for (int k = 0; k < n; ++k) {
-                ar[k] -= m * ac[k];
-                ir[k] -= m * ic[k];
+        // eliminate column c from every other row (rows split over threads)
+        auto elim = [&](int r0, int r1) {
+            const double *ac = &a[(size_t)c * n], *ic = &inv[(size_t)c * n];
+            for (int r = r0; r < r1; ++r) {
+                if (r == c) continue;
+                const double m = a[(size_t)r * n + c];
+                if (m == 0.0) continue;
+                double *ar = &a[(size_t)r * n], *ir = &inv[(size_t)r * n];
+                for (int k = 0; k < n; ++k) {
+                    ar[k] -= m * ac[k];
+                    ir[k] -= m * ic[k];
+                }
             }
+        };
+        const int nt = n >= 512 ? std::min(16, (int)std::max(1u, std::thread::hardware_concurrency())) : 1;
+        if (nt == 1) {
+            elim(0, n);
+        } else {
+            std::vector<std::thread> th;
+            for (int t = 0; t < nt; ++t) th.emplace_back(elim, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt));
+            for (auto &t : th) t.join();
         }
     }
     a.swap(inv);
     return pmax > 0.0 ? pmin / pmax : 0.0;
+}
+
+// host version of the PMC ghost fill of a face vector (planes x, y, z in order)
+void mirror_faces_host(const Grid &g, double *x) {
+    if (!g.pmc) return;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int64_t stride[3] = {1, g.sy, g.sz};
+    for (int a = 0; a < 3; ++a) {
+        if (!((g.pmc >> a) & 1)) continue;
+        const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
+        for (int u = -1; u <= n[b]; ++u)
+            for (int v = -1; v <= n[d]; ++v) {
+                int idx[3];
+                idx[a] = -1;
+                idx[b] = u;
+                idx[d] = v;
+                const int64_t pg = pidx(g, idx[0], idx[1], idx[2]);
+                for (int c = 0; c < 3; ++c) {
+                    double *arr = x + c * g.P;
+                    arr[pg] = c == a ? arr[pg + 2 * stride[a]] : -arr[pg + stride[a]];
+                }
+            }
+    }
 }
 
 std::vector<double> to_coefs(const Grid &g, const std::vector<double> &fr) {
@@ -72,7 +110,10 @@ std::vector<double> to_coefs(const Grid &g, const std::vector<double> &fr) {
 
 void build_hierarchy(dm_op *op, const double *user_frac) {
     const int nl = op->opt.levels;
-    Grid g0 = make_grid(op->dims[0], op->dims[1], op->dims[2], op->h);
+    int pmc = 0;
+    for (int a = 0; a < 3; ++a)
+        if (op->geom.bc_lo[a] == DM_BC_PMC) pmc |= 1 << a;
+    Grid g0 = make_grid(op->dims[0], op->dims[1], op->dims[2], op->h, pmc);
     std::vector<double> fr;
     if (op->geom.kind == DM_GEOM_USER) {
         fr.assign(user_frac, user_frac + 7 * g0.P);
@@ -82,14 +123,16 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         compute_fractions(*body, g0, op->geom.bc_lo, fr);
     }
     neglect_faces(g0, op->geom.a_min, fr);
+    mirror_fraction_ghosts(g0, fr);
     op->frac.clear();
     op->frac.push_back(fr);
     std::vector<Grid> grids = {g0};
     for (int l = 1; l < nl; ++l) {
         const Grid &gf = grids.back();
-        Grid gc = make_grid(gf.nx / 2, gf.ny / 2, gf.nz / 2, gf.h * 2.0);
+        Grid gc = make_grid(gf.nx / 2, gf.ny / 2, gf.nz / 2, gf.h * 2.0, pmc);
         std::vector<double> fc;
         coarsen_fractions(gf, op->frac.back(), gc, fc);
+        mirror_fraction_ghosts(gc, fc);
         op->frac.push_back(fc);
         grids.push_back(gc);
     }
@@ -106,9 +149,14 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         DM_HIP(hipMemcpyAsync(L.coef32, c32.data(), 7 * P * sizeof(float), hipMemcpyHostToDevice, op->stream));
         DM_HIP(hipStreamSynchronize(op->stream));
         L.sweight = 1.0 / (std::ldexp(1.0, l) * op->h * op->h);
-        int64_t naf = 0, nac = 0;
-        for (int64_t p = 0; p < 3 * P; ++p) naf += op->frac[l][p] > 0.0;
-        for (int64_t p = 0; p < P; ++p) nac += op->frac[l][6 * P + p] > 0.0;
+        int64_t naf = 0, nac = 0;  // owned entries only (not PMC ghosts)
+        for (int k = 0; k < L.g.nz; ++k)
+            for (int j = 0; j < L.g.ny; ++j)
+                for (int i = 0; i < L.g.nx; ++i) {
+                    const int64_t p = pidx(L.g, i, j, k);
+                    for (int c = 0; c < 3; ++c) naf += op->frac[l][c * P + p] > 0.0;
+                    nac += op->frac[l][6 * P + p] > 0.0;
+                }
         L.n_act_faces = naf;
         L.n_act_cells = nac;
         if (l > 0) {
@@ -123,15 +171,42 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         L.r32 = op->dalloc<float>(3 * P);
         L.sr = op->dalloc<double>(P);
     }
-    // level-0 masks
+    // level-0 masks and weights over the owned (non-ghost) entries:
+    //   fmask  1 on active faces;  cmask 1 on active cells;
+    //   wface  W: 1/2 per PMC plane the face lies in (the face is shared with
+    //          its mirror image), else 1 -- the half-cavity pencil
+    //          (W K, W A) is the symmetric restriction of the full cavity's;
+    //   wa = W a and wainv = W / a (inner product and residual norm weights)
     const Grid &g = op->lv[0].g;
-    std::vector<double> fm(3 * g.P), cm(g.P);
-    for (int64_t p = 0; p < 3 * g.P; ++p) fm[p] = op->frac[0][p] > 0.0 ? 1.0 : 0.0;
-    for (int64_t p = 0; p < g.P; ++p) cm[p] = op->frac[0][6 * g.P + p] > 0.0 ? 1.0 : 0.0;
-    op->fmask = op->dalloc<double>(3 * g.P);
-    op->cmask = op->dalloc<double>(g.P);
+    const int64_t P0 = g.P;
+    std::vector<double> fm(3 * P0, 0.0), cm(P0, 0.0), wf(3 * P0, 0.0), wa(3 * P0, 0.0), wi(3 * P0, 0.0);
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                const int64_t p = pidx(g, i, j, k);
+                const int idx[3] = {i, j, k};
+                cm[p] = op->frac[0][6 * P0 + p] > 0.0 ? 1.0 : 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double a = op->frac[0][c * P0 + p];
+                    if (!(a > 0.0)) continue;
+                    double w = 1.0;
+                    if (((pmc >> c) & 1) && idx[c] == 0) w = 0.5;
+                    fm[c * P0 + p] = 1.0;
+                    wf[c * P0 + p] = w;
+                    wa[c * P0 + p] = w * a;
+                    wi[c * P0 + p] = w / a;
+                }
+            }
+    op->fmask = op->dalloc<double>(3 * P0);
+    op->cmask = op->dalloc<double>(P0);
+    op->wface = op->dalloc<double>(3 * P0);
+    op->wa = op->dalloc<double>(3 * P0);
+    op->wainv = op->dalloc<double>(3 * P0);
     DM_HIP(hipMemcpyAsync(op->fmask, fm.data(), fm.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
     DM_HIP(hipMemcpyAsync(op->cmask, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
+    DM_HIP(hipMemcpyAsync(op->wface, wf.data(), wf.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
+    DM_HIP(hipMemcpyAsync(op->wa, wa.data(), wa.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
+    DM_HIP(hipMemcpyAsync(op->wainv, wi.data(), wi.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
     op->part = op->dalloc<double>((size_t)kReduceBlocks * kMaxDots);
     op->dres = op->dalloc<double>(kMaxDots);
     DM_HIP(hipHostMalloc((void **)&op->hres, kMaxDots * sizeof(double), hipHostMallocDefault));
@@ -167,10 +242,14 @@ void factor_coarse(dm_op *op) {
                     }
                 }
     const int n = (int)idx.size();
+    if (n > kMaxCoarse)
+        throw DmError{DM_EINVAL, "coarsest level has " + std::to_string(n) + " active faces (limit " +
+                                     std::to_string(kMaxCoarse) + "): use more multigrid levels"};
     std::vector<double> Md((size_t)n * n, 0.0), e(3 * P, 0.0);
     for (int col = 0; col < n; ++col) {
         const int64_t pc = idx[col] % P;
         e[idx[col]] = 1.0;
+        mirror_faces_host(g, e.data());
         const int ic = (int)(pc % dy) - 1, jc = (int)((pc / dy) % (g.ny + 2)) - 1,
                   kc = (int)(pc / dz) - 1;
         for (int k = std::max(0, kc - 2); k <= std::min(g.nz - 1, kc + 2); ++k)
@@ -189,6 +268,7 @@ void factor_coarse(dm_op *op) {
                     }
                 }
         e[idx[col]] = 0.0;
+        mirror_faces_host(g, e.data());
     }
     const double ratio = invert_dense(Md, n);
     if (!(ratio > 1e-13))
@@ -224,6 +304,13 @@ void factor_coarse(dm_op *op) {
             d += wt[q];
             auto it = srow.find(nb[q]);
             if (it != srow.end()) Sd[(size_t)r * ns + it->second] -= w * wt[q];
+        }
+        // odd mirror across a PMC plane: the neighbour is -psi, the face counts twice
+        {
+            const int i = (int)(p % dy) - 1, j = (int)((p / dy) % (g.ny + 2)) - 1, kk = (int)(p / dz) - 1;
+            if ((g.pmc & 1) && i == 0) d += wt[0];
+            if ((g.pmc & 2) && j == 0) d += wt[2];
+            if ((g.pmc & 4) && kk == 0) d += wt[4];
         }
         Sd[(size_t)r * ns + r] += w * d;
         dsum += w * d;

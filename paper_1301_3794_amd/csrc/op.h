@@ -63,6 +63,9 @@ struct dm_op {
     // level-0 masks
     double *fmask = nullptr;  // 3P, 1 on active faces
     double *cmask = nullptr;  // P, 1 on active cells
+    double *wface = nullptr;  // 3P, W (1/2 on faces in a PMC plane, 1 else, 0 off)
+    double *wa = nullptr;     // 3P, W a
+    double *wainv = nullptr;  // 3P, W / a
     // reductions
     double *part = nullptr;   // kReduceBlocks * kMaxDots
     double *dres = nullptr;   // kMaxDots device results

@@ -247,7 +247,7 @@ int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_
     const int64_t n = op->n0();
     double *r = op->fg_V, *z = op->fg_V + n, *p = op->fg_V + 2 * n, *q = op->fg_w;
     DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    const double bnorm = std::sqrt(dot1(op, f, f, nullptr, n, s));
+    const double bnorm = std::sqrt(dot1(op, f, f, op->wface, n, s));
     if (bnorm == 0.0) {
         if (info) *info = dm_solve_info{0, 0, 0.0, 0.0};
         return DM_OK;
@@ -255,33 +255,33 @@ int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_
     launch_copy(n, f, r, s);
     vcycle<double>(op, 0, r, z, s);
     launch_copy(n, z, p, s);
-    double rz = dot1(op, r, z, nullptr, n, s);
+    double rz = dot1(op, r, z, op->wface, n, s);
     int it = 0;
     double rel = 1.0;
     bool conv = false;
     while (it < maxit) {
         launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, p, q, s);
-        const double pq = dot1(op, p, q, nullptr, n, s);
+        const double pq = dot1(op, p, q, op->wface, n, s);
         if (!(pq > 0.0)) throw DmError{pq == pq ? DM_EBREAKDOWN : DM_ENAN,
                                        "PCG: operator not positive definite at this shift"};
         const double alpha = rz / pq;
         launch_axpy(n, alpha, p, x, s);
         launch_axpy(n, -alpha, q, r, s);
         ++it;
-        rel = std::sqrt(dot1(op, r, r, nullptr, n, s)) / bnorm;
+        rel = std::sqrt(dot1(op, r, r, op->wface, n, s)) / bnorm;
         if (!std::isfinite(rel)) throw DmError{DM_ENAN, "PCG residual is not finite"};
         if (rel <= rtol) {
             conv = true;
             break;
         }
         vcycle<double>(op, 0, r, z, s);
-        const double rz2 = dot1(op, r, z, nullptr, n, s);
+        const double rz2 = dot1(op, r, z, op->wface, n, s);
         launch_axpby(n, 1.0, z, rz2 / rz, p, s);
         rz = rz2;
     }
     // true residual
     launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, r, s);
-    rel = std::sqrt(dot1(op, r, r, nullptr, n, s)) / bnorm;
+    rel = std::sqrt(dot1(op, r, r, op->wface, n, s)) / bnorm;
     if (info) {
         info->iterations = it;
         info->restarts = 0;
@@ -308,6 +308,7 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
     DM_HIP(hipMemsetAsync(x, 0, 3 * g.P * sizeof(T), s));
     if (l == op->nlev() - 1) {
         launch_coarse_solve<T>(op->nc, op->cinv, op->cidx, f, x, s);
+        launch_mirror_faces<T>(g, x, s);
         return;
     }
     const T *c = Prec<T>::coef(L);
@@ -335,6 +336,7 @@ void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
     DM_HIP(hipMemsetAsync(x, 0, g.P * sizeof(double), s));
     if (l == op->nlev() - 1) {
         launch_coarse_solve<double>(op->ns, op->sinv, op->sidx, f, x, s);
+        launch_mirror_cells(g, x, s);
         return;
     }
     for (int it = 0; it < op->opt.nu_pre; ++it)
@@ -358,11 +360,11 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
            *q = op->pj_q;
     launch_div_DA(g, L.coef64, b, gv, s);
     if (op->s_floating) demean_cells(op, gv, s);
-    const double gnorm = std::sqrt(dot1(op, gv, gv, nullptr, P, s));
+    const double gnorm = std::sqrt(dot1(op, gv, gv, op->cmask, P, s));
     // Stop on the scale of the field, not of its divergence: the gradient
     // left in the output is then at most ~rtol of |b|_A, however nearly
     // divergence-free b already was (the usual case inside the eigensolve).
-    const double stop = rtol * std::sqrt(dot1(op, b, b, L.coef64, op->n0(), s)) / g.h;
+    const double stop = rtol * std::sqrt(dot1(op, b, b, op->wa, op->n0(), s)) / g.h;
     DM_HIP(hipMemsetAsync(psi, 0, P * sizeof(double), s));
     int it = 0;
     if (!std::isfinite(gnorm)) throw DmError{DM_ENAN, "projection input is not finite"};
@@ -371,20 +373,20 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
         svcycle(op, 0, r, z, s);
         if (op->s_floating) demean_cells(op, z, s);
         launch_copy(P, z, p, s);
-        double rz = dot1(op, r, z, nullptr, P, s);
+        double rz = dot1(op, r, z, op->cmask, P, s);
         while (it < maxit) {
             launch_s_apply(g, L.coef64, L.sweight, 0, nullptr, p, q, s);
-            const double pq = dot1(op, p, q, nullptr, P, s);
+            const double pq = dot1(op, p, q, op->cmask, P, s);
             if (!(pq > 0.0)) break;
             const double alpha = rz / pq;
             launch_axpy(P, alpha, p, psi, s);
             launch_axpy(P, -alpha, q, r, s);
             ++it;
-            const double rn = std::sqrt(dot1(op, r, r, nullptr, P, s));
+            const double rn = std::sqrt(dot1(op, r, r, op->cmask, P, s));
             if (rn <= stop) break;
             svcycle(op, 0, r, z, s);
             if (op->s_floating) demean_cells(op, z, s);
-            const double rz2 = dot1(op, r, z, nullptr, P, s);
+            const double rz2 = dot1(op, r, z, op->cmask, P, s);
             launch_axpby(P, 1.0, z, rz2 / rz, p, s);
             rz = rz2;
         }
@@ -429,16 +431,10 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     ensure_krylov(op);
     double *V = op->eg_V, *W = op->eg_W, *t1 = op->eg_T, *t2 = op->eg_T + n, *t3 = op->eg_T + 2 * n;
     double *SCR = V + (size_t)(m + b) * n;   // room for keep_max Ritz vectors
-    const double *a = L.coef64;              // ax|ay|az: the A weights of a face vector
-    // 1/a on active faces (weight of the A^-1 norm)
-    double *ainv = t3;
-    {
-        std::vector<double> hv(n);
-        const std::vector<double> &fr = op->frac[0];
-        for (int64_t p = 0; p < n; ++p) hv[p] = fr[p] > 0.0 ? 1.0 / fr[p] : 0.0;
-        DM_HIP(hipMemcpyAsync(ainv, hv.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
-        DM_HIP(hipStreamSynchronize(s));
-    }
+    // inner products over the owned active faces: (u, v) = u^T W A v
+    // (eq. bInner; W = 1/2 on faces in a PMC plane), K-forms with W, and
+    // the residual norm with W / A
+    const double *a = op->wa, *wk = op->wface, *ainv = op->wainv;
     int inner_its = 0, proj_its = 0, outer = 0, restarts = 0;
     dm_solve_info sinfo;
     auto A_normalize = [&](double *v) -> double {
@@ -467,13 +463,14 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     auto Gat = [&](int r, int c) -> double & { return GK[(size_t)r * cap + c]; };
     auto add_gk = [&](int q) {
         launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, V + (size_t)q * n, t2, s);
-        dots(op, q + 1, V, n, t2, nullptr, n, s);
+        dots(op, q + 1, V, n, t2, wk, n, s);
         for (int i = 0; i <= q; ++i) Gat(i, q) = Gat(q, i) = op->hres[i];
     };
     // start block
     for (int c = 0; c < b; ++c) {
         double *v = V + (size_t)c * n;
         launch_randn(n, seed, (int64_t)c * n, op->fmask, v, s);
+        launch_mirror_faces<double>(L.g, v, s);
         project(op, v, v, opt.proj_rtol, 1000, s, &pj);
         proj_its += pj;
         orth(V, c, v, nullptr);
@@ -560,7 +557,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
             double *bi = SCR + (size_t)(i % std::max(1, keep_max)) * n;
             launch_maxpy(nb, V, n, op->dcoef, t1, n, 1, s);  // t1 = V y
             launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, t1, t2, s);
-            const double bKb = dot1(op, t1, t2, nullptr, n, s);
+            const double bKb = dot1(op, t1, t2, wk, n, s);
             const double bAb = dot1(op, t1, t1, a, n, s);
             const double lr = bKb / bAb;
             // t2 = K b - lr A b
