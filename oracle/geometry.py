@@ -17,7 +17,15 @@ Conventions (this project's readings, stated once):
   only touches Omega along a curve has area fraction 0;
 * a computed fraction below ZERO_FRACTION (1e-12, far below any fraction
   a resolved boundary produces and above the rounding error of the area and
-  volume formulas, ~1e-13) is rounding noise of a tangency and is set to 0.
+  volume formulas, ~1e-13) is rounding noise of a tangency and is set to 0;
+* two consistency rules then restore what holds for exact fractions of an
+  open cavity: a face with area has volume on both sides, and an edge with
+  length has area on all four faces around it.  A face next to a cell of
+  volume 0 gets a = 0 (a tangency sliver whose volume was rounded away but
+  whose area, of lower order in the sliver's thickness, was not: its b would
+  carry a flux with no divergence penalty, a near-null mode of M); then every
+  edge of a face with a = 0 gets l = 0 (as face neglect does, Sec. 3), so that
+  the discrete gradients D^T psi on the active faces stay curl-free.
 
 Array layout: numpy arrays indexed [k, j, i] (x fastest), shapes
     ax (Nz, Ny, Nx+1)   ay (Nz, Ny+1, Nx)   az (Nz+1, Ny, Nx)
@@ -498,15 +506,53 @@ def cell_fractions(geom, n, h) -> np.ndarray:
     return out.reshape(shape)
 
 
-def fractions(geom, n, h) -> dict:
-    """All seven fraction arrays of the grid n = (Nx, Ny, Nz), cell size h."""
+def _either_side(mask, np_axis, pad_value):
+    """For an array of items along np_axis (length N), the items' boundary
+    positions 0..N: True where the item on either side is True."""
+    pad = [(0, 0)] * 3
+    pad[np_axis] = (1, 1)
+    e = np.pad(mask, pad, constant_values=pad_value)
+    lo = np.take(e, np.arange(0, e.shape[np_axis] - 1), axis=np_axis)
+    hi = np.take(e, np.arange(1, e.shape[np_axis]), axis=np_axis)
+    return lo | hi
+
+
+def drop_faces_of_empty_cells(fr: dict) -> dict:
+    """Set a = 0 on every face that has a cell with v = 0 on either side."""
+    out = dict(fr)
+    empty = fr["v"] == 0.0                                  # (Nz, Ny, Nx)
+    for axis, name in enumerate(("ax", "ay", "az")):
+        out[name] = np.where(_either_side(empty, 2 - axis, False), 0.0, fr[name])
+    return out
+
+
+def drop_edges_of_zero_faces(fr: dict) -> dict:
+    """Set l = 0 on every edge with a face of a = 0 around it.  An edge along
+    axis e is bounded by the two faces normal to each other axis b, which lie
+    on either side of it along the third axis d."""
+    out = dict(fr)
+    faces = ("ax", "ay", "az")
+    for e, name in enumerate(("lx", "ly", "lz")):
+        drop = np.zeros(fr[name].shape, bool)
+        for b in range(3):
+            if b == e:
+                continue
+            d = 3 - e - b
+            drop |= _either_side(fr[faces[b]] == 0.0, 2 - d, False)
+        out[name] = np.where(drop, 0.0, fr[name])
+    return out
+
+
+def fractions(geom, n, h, drop_empty=True) -> dict:
+    """All seven fraction arrays of the grid n = (Nx, Ny, Nz), cell size h;
+    with drop_empty, the two consistency rules above are applied."""
     out = {}
     for axis, name in enumerate(("ax", "ay", "az")):
         out[name] = face_fractions(geom, n, h, axis)
     for axis, name in enumerate(("lx", "ly", "lz")):
         out[name] = edge_fractions(geom, n, h, axis)
     out["v"] = cell_fractions(geom, n, h)
-    return out
+    return drop_edges_of_zero_faces(drop_faces_of_empty_cells(out)) if drop_empty else out
 
 
 def count_active_faces(geom, n, h) -> int:

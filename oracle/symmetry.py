@@ -162,7 +162,7 @@ class HalfVCycle(mg.VCycle):
         for lev in range(levels - 1):
             ef, ec = self.exts[lev], self.exts[lev + 1]
             Lf, Lc = self.levels[lev], self.levels[lev + 1]
-            Pfull = mg.prolongation(ef.gf, ec.gf, Lf.op.full.a > 0, Lc.op.full.a > 0)
+            Pfull = mg.prolongation(ef.gf, ec.gf, Lf.op.full.a > 0, Lc.op.full.a > 0, Lc.op.full.a)
             self.P.append((ef.R @ Pfull @ ec.Q).tocsr())
             self.Rt.append((ec.R @ (Pfull.T / 8.0) @ ef.Q).tocsr())
         last = self.levels[-1]

@@ -180,6 +180,7 @@ int dm_compute_fractions(const dm_geometry *geom, const int dims[3], double h, d
         if (!body) return fail(DM_EINVAL, "geometry kind not available");
         std::vector<double> fr;
         compute_fractions(*body, g, geom->bc_lo, fr);
+        enforce_fraction_consistency(g, fr);
         neglect_faces(g, geom->a_min, fr);
         mirror_fraction_ghosts(g, fr);
         std::memcpy(out_host, fr.data(), fr.size() * sizeof(double));
@@ -367,8 +368,8 @@ int dm_prolong_add(dm_op *op, int prec, int level, const void *xc, void *x, void
     return on_device(op, stream, [&](hipStream_t s) -> int {
         const Level &F = op->lv[level], &C = op->lv[level + 1];
         fill_ghosts(F, prec, x, false, s);
-        if (prec == 64) launch_prolong_add<double>(F.g, C.g, F.coef64, (const double *)xc, (double *)x, s);
-        else launch_prolong_add<float>(F.g, C.g, F.coef32, (const float *)xc, (float *)x, s);
+        if (prec == 64) launch_prolong_add<double>(F.g, C.g, F.coef64, C.coef64, (const double *)xc, (double *)x, s);
+        else launch_prolong_add<float>(F.g, C.g, F.coef32, C.coef32, (const float *)xc, (float *)x, s);
         return DM_OK;
     });
 }
@@ -491,8 +492,8 @@ int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double 
                         else launch_restrict<float>(L.g, C.g, C.coef32, (float *)x, (float *)c, s);
                         break;
                     case DM_KERNEL_PROLONG:
-                        if (prec == 64) launch_prolong_add<double>(L.g, C.g, L.coef64, (double *)c, (double *)y, s);
-                        else launch_prolong_add<float>(L.g, C.g, L.coef32, (float *)c, (float *)y, s);
+                        if (prec == 64) launch_prolong_add<double>(L.g, C.g, L.coef64, C.coef64, (double *)c, (double *)y, s);
+                        else launch_prolong_add<float>(L.g, C.g, L.coef32, C.coef32, (float *)c, (float *)y, s);
                         break;
                     case DM_KERNEL_VCYCLE:
                         if (prec == 64) vcycle<double>(op, 0, (double *)f, (double *)y, s);

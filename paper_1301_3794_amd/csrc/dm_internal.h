@@ -232,7 +232,7 @@ template <class T>
 void launch_restrict(const Grid &gf, const Grid &gc, const T *coef_c, const T *r, T *fc,
                      hipStream_t s);
 template <class T>
-void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T *xc, T *x,
+void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, const T *xc, T *x,
                         hipStream_t s);
 template <class TI, class TO>
 void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s);

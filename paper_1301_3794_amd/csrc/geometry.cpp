@@ -327,6 +327,51 @@ void mirror_fraction_ghosts(const Grid &g, std::vector<double> &fr) {
     }
 }
 
+// Consistency of thresholded fractions.  Exact fractions of an open cavity
+// have area on both sides of a face with area and on all four faces around an
+// edge with length; rounding tangencies to 0 can break both.  A face next to
+// a cell without volume (a sliver whose volume fell below kZeroFraction while
+// its area, of lower order in the thickness, did not) would keep a flux with
+// no divergence penalty, a near-null mode of M: it is dropped.  Then every
+// edge of a face without area is dropped too (as face neglect does), so that
+// the gradients D^T psi on the active faces stay curl-free.  Only cells and
+// faces inside the grid are looked at; the ghost images across a PMC plane
+// equal their originals.
+void enforce_fraction_consistency(const Grid &g, std::vector<double> &fr) {
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int64_t stride[3] = {1, g.sy, g.sz};
+    const double *v = &fr[6 * P];
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < n[2] + (a == 2); ++k)
+            for (int j = 0; j < n[1] + (a == 1); ++j)
+                for (int i = 0; i < n[0] + (a == 0); ++i) {
+                    const int64_t p = pidx(g, i, j, k);
+                    if (fr[a * P + p] == 0.0) continue;
+                    const int idx = a == 0 ? i : a == 1 ? j : k;
+                    const bool lo_empty = idx > 0 && v[p - stride[a]] == 0.0;
+                    const bool hi_empty = idx < n[a] && v[p] == 0.0;
+                    if (lo_empty || hi_empty) fr[a * P + p] = 0.0;
+                }
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < n[2] + (a == 2); ++k)
+            for (int j = 0; j < n[1] + (a == 1); ++j)
+                for (int i = 0; i < n[0] + (a == 0); ++i) {
+                    const int64_t p = pidx(g, i, j, k);
+                    if (fr[a * P + p] != 0.0) continue;
+                    if (a == 0) {          // x-face: e_y(p), e_y(p+dz), e_z(p), e_z(p+dy)
+                        fr[4 * P + p] = fr[4 * P + p + dz] = 0.0;
+                        fr[5 * P + p] = fr[5 * P + p + dy] = 0.0;
+                    } else if (a == 1) {   // y-face: e_x(p), e_x(p+dz), e_z(p), e_z(p+1)
+                        fr[3 * P + p] = fr[3 * P + p + dz] = 0.0;
+                        fr[5 * P + p] = fr[5 * P + p + 1] = 0.0;
+                    } else {               // z-face: e_x(p), e_x(p+dy), e_y(p), e_y(p+1)
+                        fr[3 * P + p] = fr[3 * P + p + dy] = 0.0;
+                        fr[4 * P + p] = fr[4 * P + p + 1] = 0.0;
+                    }
+                }
+}
+
 // Face neglect (Sec. 3): faces with 0 < a < a_min lose their b (a := 0) and
 // every edge around such a face its e (l := 0).
 void neglect_faces(const Grid &g, double a_min, std::vector<double> &fr) {

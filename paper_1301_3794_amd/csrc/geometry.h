@@ -32,6 +32,7 @@ double integrate_pieces(const std::function<double(double)> &f, double a, double
                         std::vector<double> cuts);
 void compute_fractions(const Body &body, const Grid &g, const int bc_lo[3],
                        std::vector<double> &out);
+void enforce_fraction_consistency(const Grid &g, std::vector<double> &fr);
 void neglect_faces(const Grid &g, double a_min, std::vector<double> &fr);
 void mirror_fraction_ghosts(const Grid &g, std::vector<double> &fr);
 void coarsen_fractions(const Grid &gf, const std::vector<double> &ff, const Grid &gc,

@@ -141,6 +141,15 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
     const int64_t pc = pidx(gc, I, J, K);
     const T *RX = r, *RY = r + Pf, *RZ = r + 2 * Pf;
     const int64_t q = pidx(gf, 2 * I, 2 * J, 2 * K);
+    // transpose of the area-weighted normal interpolation: the fine face
+    // between coarse faces c and c' gives c the share a_c / (a_c + a_c')
+    const T ax = cc.ax[pc], ay = cc.ay[pc], az = cc.az[pc];
+    const T xm = ax > T(0) ? ax / (ax + cc.ax[pc - 1]) : T(0);
+    const T xp = ax > T(0) ? ax / (ax + cc.ax[pc + 1]) : T(0);
+    const T ym = ay > T(0) ? ay / (ay + cc.ay[pc - gc.sy]) : T(0);
+    const T yp = ay > T(0) ? ay / (ay + cc.ay[pc + gc.sy]) : T(0);
+    const T zm = az > T(0) ? az / (az + cc.az[pc - gc.sz]) : T(0);
+    const T zp = az > T(0) ? az / (az + cc.az[pc + gc.sz]) : T(0);
     T sx = 0, sy = 0, sz = 0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -148,21 +157,29 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
         for (int b = 0; b < 2; ++b) {
             // x: tangential offsets in y (a) and z (b)
             const int64_t qx = q + a * fy + b * fz;
-            sx += RX[qx] + T(0.5) * (RX[qx - 1] + RX[qx + 1]);
+            sx += RX[qx] + xm * RX[qx - 1] + xp * RX[qx + 1];
             const int64_t qy = q + a + b * fz;
-            sy += RY[qy] + T(0.5) * (RY[qy - fy] + RY[qy + fy]);
+            sy += RY[qy] + ym * RY[qy - fy] + yp * RY[qy + fy];
             const int64_t qz = q + a + b * fy;
-            sz += RZ[qz] + T(0.5) * (RZ[qz - fz] + RZ[qz + fz]);
+            sz += RZ[qz] + zm * RZ[qz - fz] + zp * RZ[qz + fz];
         }
     const T e = T(0.125);
-    put_face<T>(gc, fc, 0, I, J, K, pc, cc.ax[pc] != T(0) ? e * sx : T(0));
-    put_face<T>(gc, fc + Pc, 1, I, J, K, pc, cc.ay[pc] != T(0) ? e * sy : T(0));
-    put_face<T>(gc, fc + 2 * Pc, 2, I, J, K, pc, cc.az[pc] != T(0) ? e * sz : T(0));
+    put_face<T>(gc, fc, 0, I, J, K, pc, ax != T(0) ? e * sx : T(0));
+    put_face<T>(gc, fc + Pc, 1, I, J, K, pc, ay != T(0) ? e * sy : T(0));
+    put_face<T>(gc, fc + 2 * Pc, 2, I, J, K, pc, az != T(0) ? e * sz : T(0));
+}
+
+// fine value between coarse faces c0, c1: (a0 x0 + a1 x1) / (a0 + a1)
+template <class T>
+__device__ __forceinline__ T wmean(T a0, T x0, T a1, T x1) {
+    const T t = a0 + a1;
+    return t > T(0) ? (a0 * x0 + a1 * x1) / t : T(0);
 }
 
 template <class T>
 __global__ void __launch_bounds__(kThreads)
-k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, const T *__restrict__ xc, T *__restrict__ x) {
+k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ xc,
+              T *__restrict__ x) {
     int i, j, k;
     if (!cell_of(gf, xcd_item(), i, j, k)) return;
     const int64_t Pf = gf.P, Pc = gc.P, cy = gc.sy, cz = gc.sz;
@@ -170,11 +187,14 @@ k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, const T *__restrict__ xc, T *__rest
     const int64_t q = pidx(gc, i >> 1, j >> 1, k >> 1);
     const T *CX = xc, *CY = xc + Pc, *CZ = xc + 2 * Pc;
     if (cf.ax[p] != T(0))
-        put_face<T>(gf, x, 0, i, j, k, p, x[p] + ((i & 1) ? T(0.5) * (CX[q] + CX[q + 1]) : CX[q]));
+        put_face<T>(gf, x, 0, i, j, k, p,
+                    x[p] + ((i & 1) ? wmean(cc.ax[q], CX[q], cc.ax[q + 1], CX[q + 1]) : CX[q]));
     if (cf.ay[p] != T(0))
-        put_face<T>(gf, x + Pf, 1, i, j, k, p, x[Pf + p] + ((j & 1) ? T(0.5) * (CY[q] + CY[q + cy]) : CY[q]));
+        put_face<T>(gf, x + Pf, 1, i, j, k, p,
+                    x[Pf + p] + ((j & 1) ? wmean(cc.ay[q], CY[q], cc.ay[q + cy], CY[q + cy]) : CY[q]));
     if (cf.az[p] != T(0))
-        put_face<T>(gf, x + 2 * Pf, 2, i, j, k, p, x[2 * Pf + p] + ((k & 1) ? T(0.5) * (CZ[q] + CZ[q + cz]) : CZ[q]));
+        put_face<T>(gf, x + 2 * Pf, 2, i, j, k, p,
+                    x[2 * Pf + p] + ((k & 1) ? wmean(cc.az[q], CZ[q], cc.az[q + cz], CZ[q + cz]) : CZ[q]));
 }
 
 template <class TI, class TO>
@@ -682,11 +702,11 @@ void launch_restrict(const Grid &gf, const Grid &gc, const T *coef_c, const T *r
 }
 
 template <class T>
-void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T *xc, T *x,
-                        hipStream_t s) {
+void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, const T *xc,
+                        T *x, hipStream_t s) {
     const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
     hipLaunchKernelGGL((k_prolong_add<T>), xcd_grid(n), dim3(kThreads), 0, s, gf, gc,
-                       coefs_of(coef_f, gf.P), xc, x);
+                       coefs_of(coef_f, gf.P), coefs_of(coef_c, gc.P), xc, x);
 }
 
 template <class TI, class TO>
@@ -776,7 +796,7 @@ void launch_scale(int64_t n, double a, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_scale, flat_grid(n), dim3(kThreads), 0, s, n, a, x);
 }
 void launch_copy(int64_t n, const double *x, double *y, hipStream_t s) {
-    hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
 }
 
 namespace {
@@ -875,9 +895,9 @@ template void launch_restrict<double>(const Grid &, const Grid &, const double *
                                       double *, hipStream_t);
 template void launch_restrict<float>(const Grid &, const Grid &, const float *, const float *,
                                      float *, hipStream_t);
-template void launch_prolong_add<double>(const Grid &, const Grid &, const double *, const double *,
+template void launch_prolong_add<double>(const Grid &, const Grid &, const double *, const double *, const double *,
                                          double *, hipStream_t);
-template void launch_prolong_add<float>(const Grid &, const Grid &, const float *, const float *,
+template void launch_prolong_add<float>(const Grid &, const Grid &, const float *, const float *, const float *,
                                         float *, hipStream_t);
 template void launch_cast<double, float>(const double *, float *, int64_t, hipStream_t);
 template void launch_cast<float, double>(const float *, double *, int64_t, hipStream_t);

@@ -122,6 +122,7 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         if (!body) throw DmError{DM_EINVAL, "unknown or unsupported geometry kind"};
         compute_fractions(*body, g0, op->geom.bc_lo, fr);
     }
+    enforce_fraction_consistency(g0, fr);
     neglect_faces(g0, op->geom.a_min, fr);
     mirror_fraction_ghosts(g0, fr);
     op->frac.clear();

@@ -321,7 +321,7 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
     T *fc = Prec<T>::f(C), *xc = Prec<T>::x(C);
     launch_restrict<T>(g, C.g, Prec<T>::coef(C), r, fc, s);
     vcycle<T>(op, l + 1, fc, xc, s);
-    launch_prolong_add<T>(g, C.g, c, xc, x, s);
+    launch_prolong_add<T>(g, C.g, c, Prec<T>::coef(C), xc, x, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int comp = 2; comp >= 0; --comp)
             for (int col = 1; col >= 0; --col) launch_smooth<T>(g, c, sig, comp, col, f, x, s);

@@ -71,7 +71,7 @@ def test_sphere_measure_sums(sphere16):
 def test_ellipsoid_measure_sums():
     cen, semi = (0.52, 0.47, 0.5), (0.41, 0.33, 0.27)
     n, h = (12, 12, 12), 1.0 / 12
-    fr = geo.fractions(geo.Ellipsoid(cen, semi), n, h)
+    fr = geo.fractions(geo.Ellipsoid(cen, semi), n, h, drop_empty=False)
     vol = 4 * math.pi * semi[0] * semi[1] * semi[2] / 3
     assert fr["v"].sum() * h ** 3 == pytest.approx(vol, rel=1e-12)
     for i in range(1, 12):
@@ -151,3 +151,16 @@ def test_paper_smallest_area_fraction():
         mins.append(a[a > 0].min())
     assert 5.5e-4 <= min(mins) <= 6.5e-4
     assert round(min(mins), 4) == 6e-4
+
+
+def test_faces_of_empty_cells_are_dropped():
+    """A face with area next to a cell of volume 0 is dropped; nothing else is."""
+    v = np.ones((2, 3, 4))
+    v[1, 2, 3] = 0.0
+    fr = dict(v=v, ax=np.full((2, 3, 5), 0.5), ay=np.full((2, 4, 4), 0.5), az=np.full((3, 3, 4), 0.5))
+    out = geo.drop_faces_of_empty_cells(fr)
+    # the empty cell (i, j, k) = (3, 2, 1) owns x-faces i = 3, 4; y-faces j = 2, 3; z-faces k = 1, 2
+    assert np.argwhere(out["ax"] == 0).tolist() == [[1, 2, 3], [1, 2, 4]]
+    assert np.argwhere(out["ay"] == 0).tolist() == [[1, 2, 3], [1, 3, 3]]
+    assert np.argwhere(out["az"] == 0).tolist() == [[1, 2, 3], [2, 2, 3]]
+    assert out["v"] is fr["v"]

@@ -55,8 +55,9 @@ def test_vcycle_contracts(sphere16_frac):
 
 
 def test_coarse_fractions_are_geometric(sphere16_frac):
-    fr, n, h = sphere16_frac
+    _, n, h = sphere16_frac
+    fr = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), n, h, drop_empty=False)
     coarse = mg.coarsen_fractions(fr)
-    direct = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), (8, 8, 8), 2 * h)
+    direct = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), (8, 8, 8), 2 * h, drop_empty=False)
     for s in coarse:
         assert np.max(abs(coarse[s] - direct[s])) < 1e-13

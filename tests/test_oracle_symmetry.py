@@ -40,7 +40,8 @@ def test_bor_volume_closed_form():
 
 
 def test_bor_measure_sums(full_small):
-    g, n, fr = full_small
+    g, n, _ = full_small
+    fr = geo.fractions(g, n, H, drop_empty=False)
     assert fr["v"].sum() * H ** 3 == pytest.approx(geo.bor_volume(g), rel=1e-12)
     for k in range(1, n[2]):
         r = g.radius(k * H)
