@@ -25,6 +25,11 @@ eigs       dense generalized eigensolve of (K, A) and shift-and-invert
 multigrid  the V-cycle definition the GPU path must reproduce (geometric
            coarsening by exact fraction summation, component x colour
            Gauss--Seidel, staggered transfers, dense coarsest solve).
+symmetry   PMC symmetry planes (Sec. 6.3 quarter cavities) through the
+           full mirrored cavity.
+learned    the learned correction's 3-layer conv network, loss, gradients
+           and Adam step (not in the paper), with optional bfloat16
+           rounding at the points the device stores bfloat16.
 
 Parity status of every function is recorded in its docstring; the only
 "parity unpinned" items are listed in ``UNPINNED`` below.
