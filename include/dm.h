@@ -207,12 +207,18 @@ int dm_project(dm_op *op, const double *b_dev, double *out_dev, double rtol,
                                     the lowest eigenvalue of (K+G, A)) */
 #define DM_SOLVE_FGMRES_MG64  1  /* flexible GMRES, FP64 V-cycle preconditioner */
 #define DM_SOLVE_FGMRES_MG32  2  /* flexible GMRES (FP64), FP32 V-cycle */
+#define DM_SOLVE_FGMRES_MG32_LEARNED 3  /* as MG32, then the attached network's
+                                    correction (dm_net_attach), kept only where it
+                                    lowers the FP64 residual of the V-cycle's answer;
+                                    DM_EINVAL without an attached network */
 
 typedef struct {
     int iterations;          /* preconditioner applications */
     int restarts;
     double rel_residual;     /* ||f - M x||_2 / ||f||_2, recomputed in FP64 */
     double seconds;
+    int learned_accepted;    /* LEARNED mode: corrections kept / rejected */
+    int learned_rejected;
 } dm_solve_info;
 
 /* x = M^-1 f to ||f - M x|| <= rtol ||f||, starting from x = 0.  FP64 in
@@ -258,6 +264,49 @@ typedef struct {
 int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed,
             const dm_eig_options *opt, double *lambda_host, double *vecs_dev,
             double *residuals_host, dm_eig_info *info, void *stream);
+
+/* ---- learned correction (not in the paper) ------------------------------
+ * A 3-D convolutional network on the cell grid corrects the FP32 V-cycle's
+ * answer.  Input per cell (10 channels): the residual r of the V-cycle's
+ * answer at the cell's low x, y, z faces divided by s = ||r||_2 / sqrt(number
+ * of active faces), and the fractions a_x a_y a_z l_x l_y l_z v of the cell.
+ * Layers: conv 3^3 10->16, ReLU, conv 3^3 16->16, ReLU, conv 3^3 16->3, no
+ * bias (12,528 weights); bfloat16 weights and activations on MFMA with FP32
+ * accumulation; zero outside the grid.  Output channel c at a cell, times
+ * s h^2, is the correction of face component c there (0 on inactive faces).
+ * Master weights are FP32, flat, layer by layer, [27 taps][in][out] with tap
+ * = (dz+1)*9 + (dy+1)*3 + (dx+1).  Training minimises, per pair (r, e) with
+ * M e = r, L = sum_active (y - e / (s h^2))^2 / sum_active (e / (s h^2))^2
+ * with Adam (Kingma & Ba) on the FP32 master weights.
+ * A network is used by at most one operator at a time (dm_net_attach);
+ * destroying either side detaches it. */
+#define DM_NET_WEIGHTS 12528
+typedef struct dm_net dm_net;   /* opaque, owned by the library */
+
+/* He-uniform weights from a counter-based generator keyed by seed (last
+ * layer scaled by 0.1).  Errors: DM_ENOMEM, DM_EHIP, DM_ENODEVICE. */
+int dm_net_create(uint64_t seed, dm_net **out);
+void dm_net_destroy(dm_net *net);
+/* DM_NET_WEIGHTS floats, host memory, flat layout above. */
+int dm_net_get_weights(const dm_net *net, float *weights_host);
+int dm_net_set_weights(dm_net *net, const float *weights_host);
+/* Bind net to op (NULL detaches); builds the fraction channels of op's
+ * finest grid.  Both must live on the same device. */
+int dm_net_attach(dm_op *op, dm_net *net);
+/* out = network correction for residual r (face vectors, 3P doubles, device).
+ * scale > 0 is used as s, else s is computed from r. */
+int dm_net_apply(dm_op *op, const double *r_dev, double scale, double *out_dev, void *stream);
+/* Loss L of one pair (r, e) (scale as above) and its gradient with respect
+ * to the master weights (DM_NET_WEIGHTS floats to grad_host, may be NULL). */
+int dm_net_loss_grad(dm_op *op, const double *r_dev, const double *e_dev, double scale,
+                     double *loss_host, float *grad_host, void *stream);
+/* A training pair on op's grid: x* = V(w) for w ~ N(0,1) on active faces
+ * (counter-based, keyed by seed), f = M x*, z = V(f) (FP32 V-cycles), and
+ * r = f - M z, e = x* - z, so that M e = r.  r_dev, e_dev: 3P doubles. */
+int dm_net_make_pair(dm_op *op, uint64_t seed, double *r_dev, double *e_dev, void *stream);
+/* `steps` Adam steps with learning rate lr, one fresh pair (seed + step)
+ * per step; loss_host (may be NULL) receives the loss of every step. */
+int dm_net_train(dm_op *op, int steps, float lr, uint64_t seed, float *loss_host, void *stream);
 
 /* ---- measurement -------------------------------------------------------- */
 #define DM_KERNEL_APPLY     0  /* y = M x on `level` */

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "geometry.h"
+#include "learned.h"
 #include "op.h"
 
 namespace dm {
@@ -117,6 +118,7 @@ using namespace dm;
 
 static void free_op(dm_op *op) {
     if (!op) return;
+    if (op->net) op->net->op = nullptr;
     hipSetDevice(op->device);
     if (op->stream) hipStreamSynchronize(op->stream);
     for (void *p : op->allocs) hipFree(p);
@@ -397,7 +399,9 @@ int dm_project(dm_op *op, const double *b, double *out, double rtol, void *strea
 int dm_solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
              dm_solve_info *info, void *stream) {
     if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
-    if (mode < DM_SOLVE_PCG64 || mode > DM_SOLVE_FGMRES_MG32) return fail(DM_EINVAL, "unknown solve mode");
+    if (mode < DM_SOLVE_PCG64 || mode > DM_SOLVE_FGMRES_MG32_LEARNED) return fail(DM_EINVAL, "unknown solve mode");
+    if (mode == DM_SOLVE_FGMRES_MG32_LEARNED && !op->net)
+        return fail(DM_EINVAL, "learned solve mode without an attached network");
     if (!(rtol > 0.0) || maxit < 1) return fail(DM_EINVAL, "rtol must be positive and maxit >= 1");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         fill_ghosts(op->lv[0], 64, f, false, s);
@@ -415,7 +419,8 @@ int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed, const dm_
     if (opt) o = *opt;
     else dm_default_eig_options(&o);
     if (o.block < 1 || o.max_restarts < 0 || !(o.inner_rtol > 0) || !(o.proj_rtol > 0) ||
-        o.solve_mode < DM_SOLVE_PCG64 || o.solve_mode > DM_SOLVE_FGMRES_MG32)
+        o.solve_mode < DM_SOLVE_PCG64 || o.solve_mode > DM_SOLVE_FGMRES_MG32_LEARNED ||
+        (o.solve_mode == DM_SOLVE_FGMRES_MG32_LEARNED && !op->net))
         return fail(DM_EINVAL, "bad eig options");
     if (sigma != op->sigma) {
         const int rc = dm_set_shift(op, sigma);
@@ -423,6 +428,108 @@ int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed, const dm_
     }
     return on_device(op, stream, [&](hipStream_t s) -> int {
         return eigs(op, k, tol, seed, o, lambda_host, vecs_dev, residuals_host, info, s);
+    });
+}
+
+/* ---- learned correction ------------------------------------------------- */
+
+int dm_net_create(uint64_t seed, dm_net **out) {
+    if (!out) return fail(DM_EINVAL, "NULL argument");
+    *out = nullptr;
+    return guarded([&]() -> int {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(DM_ENODEVICE, "no HIP device");
+        dm_net *net = new dm_net();
+        try {
+            net_init(net, seed);
+        } catch (...) {
+            net_free(net);
+            delete net;
+            throw;
+        }
+        *out = net;
+        return DM_OK;
+    });
+}
+
+void dm_net_destroy(dm_net *net) {
+    if (!net) return;
+    if (net->op) net->op->net = nullptr;
+    net_free(net);
+    delete net;
+}
+
+int dm_net_get_weights(const dm_net *net, float *weights_host) {
+    if (!net || !weights_host) return fail(DM_EINVAL, "NULL argument");
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(net->device));
+        DM_HIP(hipMemcpy(weights_host, net->w32, kNetWeights * sizeof(float), hipMemcpyDeviceToHost));
+        return DM_OK;
+    });
+}
+
+int dm_net_set_weights(dm_net *net, const float *weights_host) {
+    if (!net || !weights_host) return fail(DM_EINVAL, "NULL argument");
+    for (int q = 0; q < kNetWeights; ++q)
+        if (!std::isfinite(weights_host[q])) return fail(DM_ENAN, "non-finite network weight");
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(net->device));
+        net_upload_weights(net, weights_host);
+        net->step = 0;
+        DM_HIP(hipMemset(net->adam_m, 0, kNetWeights * sizeof(float)));
+        DM_HIP(hipMemset(net->adam_v, 0, kNetWeights * sizeof(float)));
+        return DM_OK;
+    });
+}
+
+int dm_net_attach(dm_op *op, dm_net *net) {
+    if (!op) return fail(DM_EINVAL, "NULL operator");
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(op->device));
+        DM_HIP(hipStreamSynchronize(op->stream));
+        net_attach(op, net);
+        DM_HIP(hipDeviceSynchronize());
+        return DM_OK;
+    });
+}
+
+int dm_net_apply(dm_op *op, const double *r_dev, double scale, double *out_dev, void *stream) {
+    if (!op || !r_dev || !out_dev) return fail(DM_EINVAL, "NULL argument");
+    if (!op->net) return fail(DM_EINVAL, "no network attached");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        net_apply(op, r_dev, scale, out_dev, s);
+        return DM_OK;
+    });
+}
+
+int dm_net_loss_grad(dm_op *op, const double *r_dev, const double *e_dev, double scale,
+                     double *loss_host, float *grad_host, void *stream) {
+    if (!op || !r_dev || !e_dev || !loss_host) return fail(DM_EINVAL, "NULL argument");
+    if (!op->net) return fail(DM_EINVAL, "no network attached");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        *loss_host = net_loss_grad(op, r_dev, e_dev, scale, s);
+        if (grad_host)
+            DM_HIP(hipMemcpyAsync(grad_host, op->net->grad, kNetWeights * sizeof(float),
+                                  hipMemcpyDeviceToHost, s));
+        return DM_OK;
+    });
+}
+
+int dm_net_make_pair(dm_op *op, uint64_t seed, double *r_dev, double *e_dev, void *stream) {
+    if (!op || !r_dev || !e_dev) return fail(DM_EINVAL, "NULL argument");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        net_make_pair(op, seed, r_dev, e_dev, s);
+        return DM_OK;
+    });
+}
+
+int dm_net_train(dm_op *op, int steps, float lr, uint64_t seed, float *loss_host, void *stream) {
+    if (!op) return fail(DM_EINVAL, "NULL operator");
+    if (!op->net) return fail(DM_EINVAL, "no network attached");
+    if (steps < 0 || !(lr > 0.f)) return fail(DM_EINVAL, "steps must be >= 0 and lr > 0");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        net_train(op, steps, lr, seed, loss_host, s);
+        return DM_OK;
     });
 }
 

@@ -42,6 +42,8 @@ struct DmError {
 
 }  // namespace dm
 
+struct dm_net;
+
 struct dm_op {
     dm_geometry geom{};
     int dims[3] = {0, 0, 0};
@@ -81,6 +83,10 @@ struct dm_op {
     double *eg_V = nullptr, *eg_W = nullptr, *eg_T = nullptr;
     std::vector<void *> allocs;  // everything to free
     int last_proj_iters = 0;
+    // learned correction: the attached network (not owned) and its scratch
+    dm_net *net = nullptr;
+    double *ln_t1 = nullptr, *ln_t2 = nullptr, *ln_t3 = nullptr, *ln_t4 = nullptr;  // 3P each
+    int ln_accepted = 0, ln_rejected = 0;
 
     template <class T>
     T *dalloc(size_t count) {
@@ -114,7 +120,40 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
             int *iters);
 int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
           dm_solve_info *info, hipStream_t s);
+void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s);
+void ensure_krylov(dm_op *op);
+double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n, hipStream_t s);
 int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt, double *lam,
          double *vecs, double *res, dm_eig_info *info, hipStream_t s);
 
+}  // namespace dm
+
+// The learned correction's network (learned.cpp): FP32 master weights, Adam
+// state, bfloat16 device weights and the activation buffers of the grid of
+// the operator it is attached to.
+struct dm_net {
+    int device = 0;
+    float *w32 = nullptr, *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+    uint16_t *wf = nullptr, *wb = nullptr;   // [3][27][16][16] forward / data-gradient
+    float *part = nullptr;                   // weight-gradient partials
+    double *lpart = nullptr, *hl = nullptr;  // loss partials (device, pinned host)
+    int64_t cap = 0;                         // cells the activation buffers hold
+    uint16_t *x0 = nullptr, *a1 = nullptr, *a2 = nullptr, *dy = nullptr, *d2 = nullptr, *d1 = nullptr;
+    float *y = nullptr;
+    int64_t step = 0;
+    dm_op *op = nullptr;                     // attached operator
+    std::vector<void *> fixed_allocs, act_allocs;
+};
+
+namespace dm {
+// learned.cpp
+void net_init(dm_net *net, uint64_t seed);
+void net_free(dm_net *net);
+void net_upload_weights(dm_net *net, const float *host);
+void net_attach(dm_op *op, dm_net *net);
+void net_apply(dm_op *op, const double *r, double scale, double *out, hipStream_t s);
+double net_loss_grad(dm_op *op, const double *r, const double *e, double scale, hipStream_t s);
+void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s);
+void net_train(dm_op *op, int steps, float lr, uint64_t seed, float *loss, hipStream_t s);
+void net_correct(dm_op *op, const double *v, double *z, hipStream_t s);
 }  // namespace dm

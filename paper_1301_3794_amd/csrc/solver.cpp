@@ -81,12 +81,6 @@ void jacobi_eig(std::vector<double> a, int n, std::vector<double> &w, std::vecto
     for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
 }
 
-double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n,
-            hipStream_t s) {
-    dots(op, 1, x, 0, y, wt, n, s);
-    return op->hres[0];
-}
-
 void to_device_coef(dm_op *op, const double *h, int nv, hipStream_t s) {
     DM_HIP(hipMemcpyAsync(op->dcoef, h, nv * sizeof(double), hipMemcpyHostToDevice, s));
 }
@@ -98,21 +92,6 @@ void demean_cells(dm_op *op, double *x, hipStream_t s) {
     launch_sub_masked(L.g.P, op->cmask, op->dres, 1.0 / (double)std::max<int64_t>(1, L.n_act_cells), x, s);
 }
 
-void ensure_krylov(dm_op *op) {
-    const int64_t n = op->n0();
-    if (!op->fg_V) {
-        const int m = op->opt.fgmres_restart;
-        op->fg_m = m;
-        // at least 3 vectors: PCG borrows r, z, p from this block
-        op->fg_V = op->dalloc<double>((size_t)std::max(m + 1, 3) * n);
-        op->fg_Z = op->dalloc<double>((size_t)m * n);
-        op->fg_w = op->dalloc<double>(n);
-        op->fg_f32 = op->dalloc<float>(n);
-        op->fg_x32 = op->dalloc<float>(n);
-        op->dcoef = op->dalloc<double>(kMaxDots);
-    }
-}
-
 void ensure_proj(dm_op *op) {
     if (!op->pj_g) {
         const int64_t P = op->lv[0].g.P;
@@ -122,17 +101,6 @@ void ensure_proj(dm_op *op) {
         op->pj_z = op->dalloc<double>(P);
         op->pj_p = op->dalloc<double>(P);
         op->pj_q = op->dalloc<double>(P);
-    }
-}
-
-void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s) {
-    const int64_t n = op->n0();
-    if (mode == DM_SOLVE_FGMRES_MG32) {
-        launch_cast<double, float>(v, op->fg_f32, n, s);
-        vcycle<float>(op, 0, op->fg_f32, op->fg_x32, s);
-        launch_cast<float, double>(op->fg_x32, z, n, s);
-    } else {
-        vcycle<double>(op, 0, v, z, s);
     }
 }
 
@@ -148,7 +116,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
     int total = 0, restarts = 0;
     double rel = 0.0;
     if (bnorm == 0.0) {
-        if (info) *info = dm_solve_info{0, 0, 0.0, 0.0};
+        if (info) *info = dm_solve_info{0, 0, 0.0, 0.0, 0, 0};
         return DM_OK;
     }
     if (!std::isfinite(bnorm)) throw DmError{DM_ENAN, "right-hand side is not finite"};
@@ -249,7 +217,7 @@ int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_
     DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
     const double bnorm = std::sqrt(dot1(op, f, f, op->wface, n, s));
     if (bnorm == 0.0) {
-        if (info) *info = dm_solve_info{0, 0, 0.0, 0.0};
+        if (info) *info = dm_solve_info{0, 0, 0.0, 0.0, 0, 0};
         return DM_OK;
     }
     launch_copy(n, f, r, s);
@@ -291,6 +259,41 @@ int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_
 }
 
 }  // namespace
+
+void ensure_krylov(dm_op *op) {
+    const int64_t n = op->n0();
+    if (!op->fg_V) {
+        const int m = op->opt.fgmres_restart;
+        op->fg_m = m;
+        // at least 3 vectors: PCG borrows r, z, p from this block
+        op->fg_V = op->dalloc<double>((size_t)std::max(m + 1, 3) * n);
+        op->fg_Z = op->dalloc<double>((size_t)m * n);
+        op->fg_w = op->dalloc<double>(n);
+        op->fg_f32 = op->dalloc<float>(n);
+        op->fg_x32 = op->dalloc<float>(n);
+        op->dcoef = op->dalloc<double>(kMaxDots);
+    }
+}
+
+
+double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n,
+            hipStream_t s) {
+    dots(op, 1, x, 0, y, wt, n, s);
+    return op->hres[0];
+}
+
+void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s) {
+    const int64_t n = op->n0();
+    if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
+        launch_cast<double, float>(v, op->fg_f32, n, s);
+        vcycle<float>(op, 0, op->fg_f32, op->fg_x32, s);
+        launch_cast<float, double>(op->fg_x32, z, n, s);
+        if (mode == DM_SOLVE_FGMRES_MG32_LEARNED) net_correct(op, v, z, s);
+    } else {
+        vcycle<double>(op, 0, v, z, s);
+    }
+}
+
 
 // ---------------------------------------------------------------------------
 void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const double *wt,
@@ -401,10 +404,15 @@ int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxi
           dm_solve_info *info, hipStream_t s) {
     const double t0 = now_s();
     int rc;
+    op->ln_accepted = op->ln_rejected = 0;
     if (mode == DM_SOLVE_PCG64) rc = pcg(op, f, x, rtol, maxit, info, s);
     else rc = fgmres(op, mode, f, x, rtol, maxit, info, s);
     DM_HIP(hipStreamSynchronize(s));
-    if (info) info->seconds = now_s() - t0;
+    if (info) {
+        info->seconds = now_s() - t0;
+        info->learned_accepted = op->ln_accepted;
+        info->learned_rejected = op->ln_rejected;
+    }
     return rc;
 }
 

@@ -22,14 +22,17 @@ DM_EINVAL, DM_ENOMEM, DM_EHIP, DM_ESINGULAR, DM_EBREAKDOWN, DM_ENAN, DM_ENODEVIC
 GEOM_BOX, GEOM_ELLIPSOID, GEOM_ELLIPTIC_BOR, GEOM_USER = 0, 1, 2, 3
 BC_PEC, BC_PMC = 0, 1
 APPLY_M, APPLY_K, APPLY_A, APPLY_DA, APPLY_DT, APPLY_S = range(6)
-SOLVE_PCG64, SOLVE_FGMRES_MG64, SOLVE_FGMRES_MG32 = range(3)
+SOLVE_PCG64, SOLVE_FGMRES_MG64, SOLVE_FGMRES_MG32, SOLVE_FGMRES_MG32_LEARNED = range(4)
+NET_WEIGHTS = 12528
 
 EXPORTS = (
     "dm_default_options", "dm_build_operator", "dm_destroy", "dm_set_shift",
     "dm_compute_fractions", "dm_field_layout", "dm_get_fractions", "dm_apply",
     "dm_residual", "dm_smooth", "dm_restrict", "dm_prolong_add", "dm_vcycle",
     "dm_project", "dm_solve", "dm_default_eig_options", "dm_eigs", "dm_strerror",
-    "dm_last_error_message", "dm_time_kernel",
+    "dm_last_error_message", "dm_time_kernel", "dm_net_create", "dm_net_destroy",
+    "dm_net_get_weights", "dm_net_set_weights", "dm_net_attach", "dm_net_apply",
+    "dm_net_loss_grad", "dm_net_make_pair", "dm_net_train",
 )
 KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_SMOOTH, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE = range(7)
 
@@ -65,7 +68,8 @@ class Options(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("learned_accepted", ctypes.c_int), ("learned_rejected", ctypes.c_int)]
 
 
 class EigOptions(ctypes.Structure):
@@ -123,6 +127,17 @@ def lib():
     L.dm_strerror.restype = ctypes.c_char_p
     L.dm_last_error_message.argtypes = []
     L.dm_last_error_message.restype = ctypes.c_char_p
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.dm_net_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.dm_net_destroy.argtypes = [vp]
+    L.dm_net_destroy.restype = None
+    L.dm_net_get_weights.argtypes = [vp, fp]
+    L.dm_net_set_weights.argtypes = [vp, fp]
+    L.dm_net_attach.argtypes = [vp, vp]
+    L.dm_net_apply.argtypes = [vp, vp, d, vp, vp]
+    L.dm_net_loss_grad.argtypes = [vp, vp, vp, d, dp, fp, vp]
+    L.dm_net_make_pair.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
+    L.dm_net_train.argtypes = [vp, i, ctypes.c_float, ctypes.c_uint64, fp, vp]
     _lib = L
     return L
 
@@ -225,6 +240,7 @@ class Operator:
         opt.levels, opt.nu_pre, opt.nu_post = levels, nu_pre, nu_post
         opt.fgmres_restart, opt.verbose = fgmres_restart, verbose
         self._op = ctypes.c_void_p()
+        self._net = None
         self.dims = tuple(int(x) for x in dims)
         self.h = float(h)
         self._geom = geom
@@ -320,7 +336,8 @@ class Operator:
         rc = _check(lib().dm_solve(self._op, mode, _ptr(f), _ptr(x), float(rtol), int(maxit),
                                    ctypes.byref(info), _stream(stream)), allow_warning=True)
         return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
-                    rel_residual=info.rel_residual, seconds=info.seconds)
+                    rel_residual=info.rel_residual, seconds=info.seconds,
+                    learned_accepted=info.learned_accepted, learned_rejected=info.learned_rejected)
 
     def time_kernel(self, kernel, prec=32, level=0, reps=50):
         """Milliseconds per launch of a library kernel (HIP events)."""
@@ -351,3 +368,71 @@ class Operator:
                     inner_iterations=info.inner_iterations,
                     projection_iterations=info.projection_iterations,
                     max_residual=info.max_residual, seconds=info.seconds)
+
+
+# ---------------------------------------------------------------------------
+# learned correction
+# ---------------------------------------------------------------------------
+
+class Net:
+    """The learned correction's network (``dm_net_*``)."""
+
+    def __init__(self, seed=0):
+        self._net = ctypes.c_void_p()
+        _check(lib().dm_net_create(ctypes.c_uint64(seed), ctypes.byref(self._net)))
+
+    def close(self):
+        if self._net:
+            lib().dm_net_destroy(self._net)
+            self._net = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(NET_WEIGHTS, dtype=np.float32)
+        _check(lib().dm_net_get_weights(self._net, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != NET_WEIGHTS:
+            raise ValueError(f"expected {NET_WEIGHTS} weights")
+        _check(lib().dm_net_set_weights(self._net, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def attach(self, op: "Operator"):
+        _check(lib().dm_net_attach(op._op, self._net))
+        op._net = self
+
+    @staticmethod
+    def detach(op: "Operator"):
+        _check(lib().dm_net_attach(op._op, None))
+        op._net = None
+
+
+def net_apply(op: "Operator", r, out, scale=0.0, stream=None):
+    _check(lib().dm_net_apply(op._op, _ptr(r), float(scale), _ptr(out), _stream(stream)))
+    return out
+
+
+def net_loss_grad(op: "Operator", r, e, scale=0.0, stream=None):
+    loss = ctypes.c_double()
+    g = np.zeros(NET_WEIGHTS, dtype=np.float32)
+    _check(lib().dm_net_loss_grad(op._op, _ptr(r), _ptr(e), float(scale), ctypes.byref(loss),
+                                  g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+    return loss.value, g
+
+
+def net_make_pair(op: "Operator", seed, r, e, stream=None):
+    _check(lib().dm_net_make_pair(op._op, ctypes.c_uint64(seed), _ptr(r), _ptr(e), _stream(stream)))
+    return r, e
+
+
+def net_train(op: "Operator", steps, lr=1e-3, seed=0, stream=None) -> np.ndarray:
+    loss = np.zeros(max(1, steps), dtype=np.float32)
+    _check(lib().dm_net_train(op._op, int(steps), ctypes.c_float(lr), ctypes.c_uint64(seed),
+                              loss.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+    return loss[:steps]

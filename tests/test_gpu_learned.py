@@ -1,0 +1,145 @@
+"""GPU parity of the learned correction against the NumPy oracle.
+
+An ellipsoid on a 20 x 16 x 24 grid (h = 1/20; x rows of 20 cells leave a
+ragged 4-cell tail after one 16-cell MFMA segment), fractions from the
+oracle.  The library's network (bfloat16 on MFMA, FP32 accumulation) is
+compared with ``oracle.learned`` rounding to bfloat16 at the same points:
+  * forward correction: max error <= 2e-3 of the largest value;
+  * a training pair from the solver satisfies M e = r to 1e-11;
+  * loss to 1e-4 and weight gradient to 2e-3 (relative 2-norm);
+  * Adam training lowers the loss; the learned solve mode converges and
+    its eigenvalues match the oracle's to 1e-9.
+"""
+import numpy as np
+import pytest
+
+from oracle import eigs as oeigs, geometry as geo, learned as ln, operators as ops
+import layout as lay
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = (20, 16, 24)
+H = 1.0 / 20
+SIGMA = 5.0
+
+
+def cells(vec, n, nch):
+    """Padded blocks (nch x P) -> per-cell channels (nz, ny, nx, nch)."""
+    a = np.asarray(vec).reshape(nch, n[2] + 2, n[1] + 2, n[0] + 2)[:, 1:-1, 1:-1, 1:-1]
+    return np.moveaxis(a, 0, -1)
+
+
+def static_channels(fr, n):
+    nx, ny, nz = n
+    ch = [fr["ax"][:, :, :nx], fr["ay"][:, :ny, :], fr["az"][:nz],
+          fr["lx"][:nz, :ny, :], fr["ly"][:nz, :, :nx], fr["lz"][:, :ny, :nx], fr["v"]]
+    return np.stack(ch, axis=-1)
+
+
+@pytest.fixture(scope="module")
+def case():
+    from paper_1301_3794_amd import dm
+    g = geo.Ellipsoid((0.5, 0.4, 0.6), (0.42, 0.33, 0.5))
+    fr = geo.fractions(g, N, H)
+    op = dm.Operator(dm.user_fractions(lay.fractions_to_padded(fr, N)), N, H, SIGMA, levels=3)
+    net = dm.Net(seed=1)
+    w = (np.random.default_rng(11).standard_normal(ln.N_WEIGHTS) * 0.15).astype(np.float32)
+    net.set_weights(w)
+    net.attach(op)
+    stat = static_channels(fr, N)
+    mask = (stat[..., :3] > 0).astype(float)
+    print("[case] learned ellipsoid", N, flush=True)
+    yield dict(dm=dm, op=op, net=net, w=w.astype(np.float64), fr=fr, stat=stat, mask=mask)
+    op.close()
+    net.close()
+
+
+def rms(r_cells, mask):
+    return float(np.sqrt(np.sum((r_cells * mask) ** 2) / mask.sum()))
+
+
+def test_forward_matches_oracle(case):
+    dm, op = case["dm"], case["op"]
+    P = op.layout(0)["P"]
+    rng = np.random.default_rng(5)
+    r = np.zeros(3 * P)
+    act = np.concatenate([case_fr_block(case, c) for c in range(3)]) > 0
+    r[act] = rng.standard_normal(act.sum())
+    rc = cells(r, N, 3)
+    s = rms(rc, case["mask"])
+    out = dm.net_apply(op, torch.tensor(r, device="cuda"), op.face_tensor(), scale=s)
+    got = cells(out.cpu().numpy(), N, 3)
+    x0 = np.concatenate([rc / s, case["stat"]], axis=-1)
+    ref = ln.forward(case["w"], x0, bf16_round=True)["y"] * s * H * H * case["mask"]
+    err = np.max(abs(got - ref)) / np.max(abs(ref))
+    print("forward max rel err", err)
+    assert err <= 2e-3
+
+
+def case_fr_block(case, c):
+    """Face fractions of component c as a padded block (library numbering)."""
+    name = ("ax", "ay", "az")[c]
+    return lay.to_padded(case["fr"][name], N)
+
+
+@pytest.fixture(scope="module")
+def pair(case):
+    dm, op = case["dm"], case["op"]
+    r, e = op.face_tensor(), op.face_tensor()
+    dm.net_make_pair(op, 7, r, e)
+    return r, e
+
+
+def test_pair_satisfies_M_e_equals_r(case, pair):
+    dm, op = case["dm"], case["op"]
+    r, e = pair
+    me = op.apply(dm.APPLY_M, e, op.face_tensor())
+    rel = float((me - r).norm() / r.norm())
+    assert rel <= 1e-11 and float(e.norm()) > 0
+
+
+def test_loss_and_gradient_match_oracle(case, pair):
+    dm, op = case["dm"], case["op"]
+    r, e = pair
+    rc, ec = cells(r.cpu().numpy(), N, 3), cells(e.cpu().numpy(), N, 3)
+    s = rms(rc, case["mask"])
+    L, g = dm.net_loss_grad(op, r, e, scale=s)
+    x0 = np.concatenate([rc / s, case["stat"]], axis=-1)
+    t = ec / (s * H * H)
+    L_ref, g_ref = ln.loss_and_grad(case["w"], x0, t, case["mask"], bf16_round=True)
+    print("loss", L, L_ref, "grad rel", np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
+    assert L == pytest.approx(L_ref, rel=1e-4)
+    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) <= 2e-3
+
+
+def test_training_lowers_the_loss(case):
+    dm, op = case["dm"], case["op"]
+    loss = dm.net_train(op, 300, lr=2e-3, seed=100)
+    assert np.all(np.isfinite(loss))
+    first, last = loss[:30].mean(), loss[-30:].mean()
+    print("loss first/last", first, last)
+    assert last < 0.8 * first
+
+
+def test_learned_solve_and_eigenvalues(case):
+    dm, op = case["dm"], case["op"]
+    f = op.apply(dm.APPLY_A, torch.randn(3 * op.layout(0)["P"], dtype=torch.float64,
+                                         generator=torch.Generator().manual_seed(3)).cuda(),
+                 op.face_tensor())
+    out = op.solve(f, op.face_tensor(), mode=dm.SOLVE_FGMRES_MG32_LEARNED, rtol=1e-10)
+    assert out["status"] == 0
+    assert out["learned_accepted"] + out["learned_rejected"] == out["iterations"]
+    res = op.eigs(4, sigma=SIGMA, tol=1e-10, seed=2, solve_mode=dm.SOLVE_FGMRES_MG32_LEARNED)
+    assert res["status"] == 0
+    o = ops.build(case["fr"], N, H, SIGMA)
+    w_ref = oeigs.lanczos_eigs(o, 4, sigma_o=SIGMA, block=4, tol=1e-11)[0]
+    assert np.max(abs(res["lam"] - w_ref) / w_ref) <= 1e-9
+
+
+def test_learned_mode_needs_a_network(case):
+    dm, op = case["dm"], case["op"]
+    dm.Net.detach(op)
+    with pytest.raises(dm.DMError):
+        op.solve(op.face_tensor(), op.face_tensor(), mode=dm.SOLVE_FGMRES_MG32_LEARNED)
+    case["net"].attach(op)
