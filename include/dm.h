@@ -275,9 +275,12 @@ int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed,
  * accumulation; zero outside the grid.  Output channel c at a cell, times
  * s h^2, is the correction of face component c there (0 on inactive faces).
  * Master weights are FP32, flat, layer by layer, [27 taps][in][out] with tap
- * = (dz+1)*9 + (dy+1)*3 + (dx+1).  Training minimises, per pair (r, e) with
- * M e = r, L = sum_active (y - e / (s h^2))^2 / sum_active (e / (s h^2))^2
- * with Adam (Kingma & Ba) on the FP32 master weights.
+ * = (dz+1)*9 + (dy+1)*3 + (dx+1).  Training runs Adam (Kingma & Ba) on the
+ * FP32 master weights over pairs (r, e) with M e = r, minimising per pair
+ *   DM_NET_LOSS_ERROR:    sum_active (y - e/(s h^2))^2 / sum_active (e/(s h^2))^2
+ *   DM_NET_LOSS_RESIDUAL: ||r - M d||^2 / ||r||^2, d = the correction,
+ * the second being what the learned solve mode judges (M symmetric: PEC
+ * operators without symmetry planes).
  * A network is used by at most one operator at a time (dm_net_attach);
  * destroying either side detaches it. */
 #define DM_NET_WEIGHTS 12528
@@ -296,9 +299,12 @@ int dm_net_attach(dm_op *op, dm_net *net);
 /* out = network correction for residual r (face vectors, 3P doubles, device).
  * scale > 0 is used as s, else s is computed from r. */
 int dm_net_apply(dm_op *op, const double *r_dev, double scale, double *out_dev, void *stream);
-/* Loss L of one pair (r, e) (scale as above) and its gradient with respect
- * to the master weights (DM_NET_WEIGHTS floats to grad_host, may be NULL). */
-int dm_net_loss_grad(dm_op *op, const double *r_dev, const double *e_dev, double scale,
+#define DM_NET_LOSS_ERROR    0
+#define DM_NET_LOSS_RESIDUAL 1
+/* Loss of one pair (r, e) (scale as above; e may be NULL for the residual
+ * loss) and its gradient with respect to the master weights (DM_NET_WEIGHTS
+ * floats to grad_host, may be NULL). */
+int dm_net_loss_grad(dm_op *op, int kind, const double *r_dev, const double *e_dev, double scale,
                      double *loss_host, float *grad_host, void *stream);
 /* A training pair on op's grid: x* = V(w) for w ~ N(0,1) on active faces
  * (counter-based, keyed by seed), f = M x*, z = V(f) (FP32 V-cycles), and
@@ -306,7 +312,8 @@ int dm_net_loss_grad(dm_op *op, const double *r_dev, const double *e_dev, double
 int dm_net_make_pair(dm_op *op, uint64_t seed, double *r_dev, double *e_dev, void *stream);
 /* `steps` Adam steps with learning rate lr, one fresh pair (seed + step)
  * per step; loss_host (may be NULL) receives the loss of every step. */
-int dm_net_train(dm_op *op, int steps, float lr, uint64_t seed, float *loss_host, void *stream);
+int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss_host,
+                 void *stream);
 
 /* ---- measurement -------------------------------------------------------- */
 #define DM_KERNEL_APPLY     0  /* y = M x on `level` */

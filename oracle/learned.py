@@ -8,8 +8,12 @@ Network (on the cell grid, channels per cell, zero outside the grid):
              -> conv 3^3, 16->3 -> Y
   conv:  out[p, o] = sum_{tap, c} in[p + off(tap), c] * W[tap, c, o],
          tap = (dz+1)*9 + (dy+1)*3 + (dx+1), off(tap) = (dx, dy, dz); no bias.
-Loss of one pair (target T, mask m on the 3 output channels):
-  L = sum m (Y - T)^2 / sum m T^2.
+Losses of one pair (mask m on the 3 output channels):
+  error loss     L = sum m (Y - T)^2 / sum m T^2 for a target T;
+  residual loss  L = |r - M d|^2 / |r|^2 with the correction d = m * Y * c
+                 (c the output scale) and M the symmetric operator, given
+                 as a callable on per-cell channel arrays; dL/dd =
+                 -2 M (r - M d) / |r|^2.
 
 ``bf16=True`` rounds, to bfloat16 with round-to-nearest-even, exactly the
 quantities the device stores in bfloat16: the input X0, the weights, the
@@ -99,18 +103,36 @@ def loss(y, t, m):
 
 
 def loss_and_grad(w, x0, t, m, bf16_round=False):
-    """Loss of one pair and its gradient w.r.t. the flat weight vector."""
+    """Error loss of one pair and its gradient w.r.t. the flat weight vector."""
     R = bf16 if bf16_round else (lambda v: np.asarray(v, dtype=np.float64))
     f = forward(w, x0, bf16_round)
-    W1, W2, W3 = f["W"]
     L = loss(f["y"], t, m)
     dy = R(2.0 * m * (f["y"] - t) / np.sum(m * t * t))
+    return L, _backward(f, dy, R)
+
+
+def _backward(f, dy, R):
+    W1, W2, W3 = f["W"]
     g3 = conv_weight_grad(f["a2"], dy)
     d2 = R(conv_data_grad(dy, W3) * (f["a2"] > 0))
     g2 = conv_weight_grad(f["a1"], d2)
     d1 = R(conv_data_grad(d2, W2) * (f["a1"] > 0))
     g1 = conv_weight_grad(f["x0"], d1)
-    return L, np.concatenate([g1.ravel(), g2.ravel(), g3.ravel()])
+    return np.concatenate([g1.ravel(), g2.ravel(), g3.ravel()])
+
+
+def residual_loss_and_grad(w, x0, r, M, m, c, bf16_round=False):
+    """Residual loss of one pair and its gradient w.r.t. the weights; r and
+    M(.) live on per-cell channel arrays (nz, ny, nx, 3)."""
+    R = bf16 if bf16_round else (lambda v: np.asarray(v, dtype=np.float64))
+    f = forward(w, x0, bf16_round)
+    d = m * f["y"] * c
+    r3 = r - M(d)
+    rr = float(np.sum(r * r))
+    L = float(np.sum(r3 * r3)) / rr
+    dd = -2.0 * M(r3) / rr
+    dy = R(dd * m * c)
+    return L, _backward(f, dy, R)
 
 
 def adam(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -502,12 +502,14 @@ int dm_net_apply(dm_op *op, const double *r_dev, double scale, double *out_dev, 
     });
 }
 
-int dm_net_loss_grad(dm_op *op, const double *r_dev, const double *e_dev, double scale,
+int dm_net_loss_grad(dm_op *op, int kind, const double *r_dev, const double *e_dev, double scale,
                      double *loss_host, float *grad_host, void *stream) {
-    if (!op || !r_dev || !e_dev || !loss_host) return fail(DM_EINVAL, "NULL argument");
+    if (!op || !r_dev || !loss_host) return fail(DM_EINVAL, "NULL argument");
+    if (kind != DM_NET_LOSS_ERROR && kind != DM_NET_LOSS_RESIDUAL) return fail(DM_EINVAL, "unknown loss");
+    if (kind == DM_NET_LOSS_ERROR && !e_dev) return fail(DM_EINVAL, "error loss needs e");
     if (!op->net) return fail(DM_EINVAL, "no network attached");
     return on_device(op, stream, [&](hipStream_t s) -> int {
-        *loss_host = net_loss_grad(op, r_dev, e_dev, scale, s);
+        *loss_host = net_loss_grad(op, kind, r_dev, e_dev, scale, s);
         if (grad_host)
             DM_HIP(hipMemcpyAsync(grad_host, op->net->grad, kNetWeights * sizeof(float),
                                   hipMemcpyDeviceToHost, s));
@@ -523,12 +525,13 @@ int dm_net_make_pair(dm_op *op, uint64_t seed, double *r_dev, double *e_dev, voi
     });
 }
 
-int dm_net_train(dm_op *op, int steps, float lr, uint64_t seed, float *loss_host, void *stream) {
+int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss_host, void *stream) {
     if (!op) return fail(DM_EINVAL, "NULL operator");
+    if (kind != DM_NET_LOSS_ERROR && kind != DM_NET_LOSS_RESIDUAL) return fail(DM_EINVAL, "unknown loss");
     if (!op->net) return fail(DM_EINVAL, "no network attached");
     if (steps < 0 || !(lr > 0.f)) return fail(DM_EINVAL, "steps must be >= 0 and lr > 0");
     return on_device(op, stream, [&](hipStream_t s) -> int {
-        net_train(op, steps, lr, seed, loss_host, s);
+        net_train(op, kind, steps, lr, seed, loss_host, s);
         return DM_OK;
     });
 }

@@ -186,23 +186,43 @@ void net_correct(dm_op *op, const double *v, double *z, hipStream_t s) {
     }
 }
 
-double net_loss_grad(dm_op *op, const double *r, const double *e, double scale, hipStream_t s) {
+double net_loss_grad(dm_op *op, int kind, const double *r, const double *e, double scale, hipStream_t s) {
     dm_net *net = attached(op);
     const Level &L = op->lv[0];
     const Grid &g = L.g;
+    const int64_t n = op->n0();
     const double sc = scale > 0.0 ? scale : rms_of(op, r, s);
     if (!(sc > 0.0) || !std::isfinite(sc)) throw DmError{DM_EINVAL, "training pair with a zero residual"};
     launch_net_pack_r<double>(g, r, 1.0 / sc, net->x0, s);
     forward(net, g, s);
-    const double t_scale = 1.0 / (sc * g.h * g.h);
-    // pass 0: sum t^2; pass 1: dy and sum (y - t)^2
-    launch_net_loss(g, L.coef64, net->y, e, t_scale, 0.0, net->dy, net->lpart, kLossBlocks, 0, s);
-    DM_HIP(hipMemcpyAsync(net->hl, net->lpart, 2 * kLossBlocks * sizeof(double), hipMemcpyDeviceToHost, s));
-    DM_HIP(hipStreamSynchronize(s));
-    double st = 0.0;
-    for (int q = 0; q < kLossBlocks; ++q) st += net->hl[2 * q + 1];
-    if (!(st > 0.0)) throw DmError{DM_EINVAL, "training pair with a zero target"};
-    launch_net_loss(g, L.coef64, net->y, e, t_scale, 1.0 / st, net->dy, net->lpart, kLossBlocks, 1, s);
+    const double c = sc * g.h * g.h;   // output scale
+    double loss = 0.0;
+    if (kind == DM_NET_LOSS_ERROR) {
+        if (!e) throw DmError{DM_EINVAL, "error loss needs the error e"};
+        // pass 0: sum t^2; pass 1: dy and sum (y - t)^2, t = e / c
+        launch_net_loss(g, L.coef64, net->y, e, 1.0 / c, 0.0, net->dy, net->lpart, kLossBlocks, 0, s);
+        DM_HIP(hipMemcpyAsync(net->hl, net->lpart, 2 * kLossBlocks * sizeof(double), hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        double st = 0.0;
+        for (int q = 0; q < kLossBlocks; ++q) st += net->hl[2 * q + 1];
+        if (!(st > 0.0)) throw DmError{DM_EINVAL, "training pair with a zero target"};
+        launch_net_loss(g, L.coef64, net->y, e, 1.0 / c, 1.0 / st, net->dy, net->lpart, kLossBlocks, 1, s);
+        DM_HIP(hipMemcpyAsync(net->hl, net->lpart, 2 * kLossBlocks * sizeof(double), hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        double se = 0.0;
+        for (int q = 0; q < kLossBlocks; ++q) se += net->hl[2 * q];
+        loss = se / st;
+    } else {
+        // d = correction, r3 = r - M d, L = |r3|^2 / |r|^2, dL/dd = -2 M r3 / |r|^2
+        double *d = op->ln_t3, *r3 = op->ln_t4;
+        launch_net_unpack<double>(g, L.coef64, net->y, c, d, s);
+        launch_apply<double>(g, L.coef64, op->sigma, AK_RESID, r, d, r3, s);
+        const double rr = dot1(op, r, r, op->wface, n, s);
+        const double r33 = dot1(op, r3, r3, op->wface, n, s);
+        launch_apply<double>(g, L.coef64, op->sigma, AK_M, nullptr, r3, d, s);
+        launch_net_dy_from_face(g, L.coef64, d, -2.0 * c / rr, net->dy, s);
+        loss = r33 / rr;
+    }
     // layer 3: weights from a2 and dy; data gradient into d2 (masked by a2 > 0)
     launch_net_wgrad(g, net->a2, net->dy, net->part, s);
     launch_net_wgrad_reduce(net->part, kNetIn[2], kNetOut[2], net->grad + net_offset(2), s);
@@ -215,11 +235,7 @@ double net_loss_grad(dm_op *op, const double *r, const double *e, double scale, 
     launch_net_wgrad(g, net->x0, net->d1, net->part, s);
     launch_net_wgrad_reduce(net->part, kNetIn[0], kNetOut[0], net->grad, s);
     DM_HIP(hipGetLastError());
-    DM_HIP(hipMemcpyAsync(net->hl, net->lpart, 2 * kLossBlocks * sizeof(double), hipMemcpyDeviceToHost, s));
-    DM_HIP(hipStreamSynchronize(s));
-    double se = 0.0;
-    for (int q = 0; q < kLossBlocks; ++q) se += net->hl[2 * q];
-    return se / st;
+    return loss;
 }
 
 void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s) {
@@ -237,13 +253,13 @@ void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s
     DM_HIP(hipGetLastError());
 }
 
-void net_train(dm_op *op, int steps, float lr, uint64_t seed, float *loss, hipStream_t s) {
+void net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss, hipStream_t s) {
     dm_net *net = attached(op);
     ensure_scratch(op);
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     for (int it = 0; it < steps; ++it) {
         net_make_pair(op, seed + (uint64_t)it, op->ln_t1, op->ln_t2, s);
-        const double L = net_loss_grad(op, op->ln_t1, op->ln_t2, 0.0, s);
+        const double L = net_loss_grad(op, kind, op->ln_t1, op->ln_t2, 0.0, s);
         if (loss) loss[it] = (float)L;
         ++net->step;
         const float c1 = 1.f - std::pow(b1, (float)net->step), c2 = 1.f - std::pow(b2, (float)net->step);

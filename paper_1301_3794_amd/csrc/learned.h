@@ -64,6 +64,9 @@ void launch_net_unpack(const Grid &g, const T *coef, const float *y, double scal
 void launch_net_loss(const Grid &g, const double *coef, const float *y, const double *e,
                      double t_scale, double inv_norm, uint16_t *dy, double *part, int nblocks,
                      int pass, hipStream_t s);
+// dy [P][16] channels 0..2 = bf16(g_c * factor) on active faces (a_c > 0), else 0
+void launch_net_dy_from_face(const Grid &g, const double *coef, const double *gv, double factor, uint16_t *dy,
+                             hipStream_t s);
 // FP32 master -> bf16 forward weights of all layers; and the transposed,
 // tap-flipped weights of layers 2 and 3 for the data gradient
 void launch_net_pack_weights(const float *w32, uint16_t *wf, uint16_t *wb, hipStream_t s);

@@ -218,6 +218,22 @@ k_net_loss(Grid g, const double *__restrict__ coef, const float *__restrict__ y,
     }
 }
 
+// dy channel c = bf16(g_c * factor) on active faces, 0 elsewhere
+__global__ void __launch_bounds__(kT)
+k_net_dy_from_face(Grid g, const double *__restrict__ coef, const double *__restrict__ gv, double factor,
+                   uint16_t *__restrict__ dy) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= n) return;
+    const int i = (int)(t % g.nx);
+    const int64_t q = t / g.nx;
+    const int j = (int)(q % g.ny), k = (int)(q / g.ny);
+    const int64_t p = pidx(g, i, j, k);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        dy[p * kNetCh + c] = coef[c * g.P + p] != 0.0 ? f2bf((float)(gv[c * g.P + p] * factor)) : (uint16_t)0;
+}
+
 // wf[l][t][o][c] = bf16(W_l[t][c][o]);  wb[l][t][c][o] = bf16(W_l[26 - t][c][o])
 // (the data gradient is the forward conv of d with the flipped taps and the
 // roles of in and out channels exchanged); zero-padded to 16 x 16.
@@ -287,6 +303,12 @@ void launch_net_unpack(const Grid &g, const T *coef, const float *y, double scal
 void launch_net_loss(const Grid &g, const double *coef, const float *y, const double *e, double t_scale,
                      double inv_norm, uint16_t *dy, double *part, int nblocks, int pass, hipStream_t s) {
     hipLaunchKernelGGL(k_net_loss, dim3(nblocks), dim3(kT), 0, s, g, coef, y, e, t_scale, inv_norm, dy, part, pass);
+}
+
+void launch_net_dy_from_face(const Grid &g, const double *coef, const double *gv, double factor, uint16_t *dy,
+                             hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_net_dy_from_face, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, g, coef, gv, factor, dy);
 }
 
 void launch_net_pack_weights(const float *w32, uint16_t *wf, uint16_t *wb, hipStream_t s) {

@@ -24,6 +24,7 @@ BC_PEC, BC_PMC = 0, 1
 APPLY_M, APPLY_K, APPLY_A, APPLY_DA, APPLY_DT, APPLY_S = range(6)
 SOLVE_PCG64, SOLVE_FGMRES_MG64, SOLVE_FGMRES_MG32, SOLVE_FGMRES_MG32_LEARNED = range(4)
 NET_WEIGHTS = 12528
+NET_LOSS_ERROR, NET_LOSS_RESIDUAL = 0, 1
 
 EXPORTS = (
     "dm_default_options", "dm_build_operator", "dm_destroy", "dm_set_shift",
@@ -135,9 +136,9 @@ def lib():
     L.dm_net_set_weights.argtypes = [vp, fp]
     L.dm_net_attach.argtypes = [vp, vp]
     L.dm_net_apply.argtypes = [vp, vp, d, vp, vp]
-    L.dm_net_loss_grad.argtypes = [vp, vp, vp, d, dp, fp, vp]
+    L.dm_net_loss_grad.argtypes = [vp, i, vp, vp, d, dp, fp, vp]
     L.dm_net_make_pair.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
-    L.dm_net_train.argtypes = [vp, i, ctypes.c_float, ctypes.c_uint64, fp, vp]
+    L.dm_net_train.argtypes = [vp, i, i, ctypes.c_float, ctypes.c_uint64, fp, vp]
     _lib = L
     return L
 
@@ -418,10 +419,11 @@ def net_apply(op: "Operator", r, out, scale=0.0, stream=None):
     return out
 
 
-def net_loss_grad(op: "Operator", r, e, scale=0.0, stream=None):
+def net_loss_grad(op: "Operator", r, e, scale=0.0, kind=NET_LOSS_ERROR, stream=None):
     loss = ctypes.c_double()
     g = np.zeros(NET_WEIGHTS, dtype=np.float32)
-    _check(lib().dm_net_loss_grad(op._op, _ptr(r), _ptr(e), float(scale), ctypes.byref(loss),
+    _check(lib().dm_net_loss_grad(op._op, int(kind), _ptr(r), _ptr(e) if e is not None else None,
+                                  float(scale), ctypes.byref(loss),
                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
     return loss.value, g
 
@@ -431,8 +433,8 @@ def net_make_pair(op: "Operator", seed, r, e, stream=None):
     return r, e
 
 
-def net_train(op: "Operator", steps, lr=1e-3, seed=0, stream=None) -> np.ndarray:
+def net_train(op: "Operator", steps, lr=1e-3, seed=0, kind=NET_LOSS_RESIDUAL, stream=None) -> np.ndarray:
     loss = np.zeros(max(1, steps), dtype=np.float32)
-    _check(lib().dm_net_train(op._op, int(steps), ctypes.c_float(lr), ctypes.c_uint64(seed),
+    _check(lib().dm_net_train(op._op, int(kind), int(steps), ctypes.c_float(lr), ctypes.c_uint64(seed),
                               loss.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
     return loss[:steps]

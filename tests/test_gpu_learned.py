@@ -6,7 +6,8 @@ oracle.  The library's network (bfloat16 on MFMA, FP32 accumulation) is
 compared with ``oracle.learned`` rounding to bfloat16 at the same points:
   * forward correction: max error <= 2e-3 of the largest value;
   * a training pair from the solver satisfies M e = r to 1e-11;
-  * loss to 1e-4 and weight gradient to 2e-3 (relative 2-norm);
+  * error and residual losses to 1e-4, their weight gradients to 2e-3
+    (relative 2-norm), the residual loss with the oracle's sparse M;
   * Adam training lowers the loss; the learned solve mode converges and
     its eigenvalues match the oracle's to 1e-9.
 """
@@ -109,6 +110,31 @@ def test_loss_and_gradient_match_oracle(case, pair):
     t = ec / (s * H * H)
     L_ref, g_ref = ln.loss_and_grad(case["w"], x0, t, case["mask"], bf16_round=True)
     print("loss", L, L_ref, "grad rel", np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
+    assert L == pytest.approx(L_ref, rel=1e-4)
+    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) <= 2e-3
+
+
+def test_residual_loss_and_gradient_match_oracle(case, pair):
+    dm, op = case["dm"], case["op"]
+    r, _ = pair
+    rc = cells(r.cpu().numpy(), N, 3)
+    s = rms(rc, case["mask"])
+    L, g = dm.net_loss_grad(op, r, None, scale=s, kind=dm.NET_LOSS_RESIDUAL)
+    o = ops.build(case["fr"], N, H, SIGMA)
+    nx, ny, nz = N
+
+    def M(d):
+        fam = {"ax": np.zeros((nz, ny, nx + 1)), "ay": np.zeros((nz, ny + 1, nx)),
+               "az": np.zeros((nz + 1, ny, nx))}
+        fam["ax"][:, :, :nx] = d[..., 0]
+        fam["ay"][:, :ny, :] = d[..., 1]
+        fam["az"][:nz] = d[..., 2]
+        ax, ay, az = o.grid.split_faces(o.M @ o.grid.face_vector(fam))
+        return np.stack([ax[:, :, :nx], ay[:, :ny, :], az[:nz]], axis=-1)
+
+    x0 = np.concatenate([rc / s, case["stat"]], axis=-1)
+    L_ref, g_ref = ln.residual_loss_and_grad(case["w"], x0, rc, M, case["mask"], s * H * H, bf16_round=True)
+    print("residual loss", L, L_ref, "grad rel", np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
     assert L == pytest.approx(L_ref, rel=1e-4)
     assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) <= 2e-3
 

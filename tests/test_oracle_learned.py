@@ -65,3 +65,27 @@ def test_bf16_rounding():
     w, x0, t, m = rand_case(3)
     a = ln.forward(w, x0, bf16_round=False)
     assert np.array_equal(a["x0"], x0)
+
+
+def test_residual_loss_gradient_matches_finite_differences():
+    """Residual loss with a small SPD stand-in for M (a 7-point stencil)."""
+    w, x0, t, m = rand_case(4)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(t.shape)
+
+    def M(d):
+        out = 7.0 * d
+        for ax in range(3):
+            out -= np.roll(d, 1, axis=ax) * 0.5 + np.roll(d, -1, axis=ax) * 0.5
+        return out
+
+    c = 0.3
+    L, g = ln.residual_loss_and_grad(w, x0, r, M, m, c)
+    for idx in rng.choice(w.size, 20, replace=False):
+        eps = 1e-6
+        wp, wm = w.copy(), w.copy()
+        wp[idx] += eps
+        wm[idx] -= eps
+        fd = (ln.residual_loss_and_grad(wp, x0, r, M, m, c)[0]
+              - ln.residual_loss_and_grad(wm, x0, r, M, m, c)[0]) / (2 * eps)
+        assert g[idx] == pytest.approx(fd, rel=1e-5, abs=1e-9)
