@@ -41,12 +41,18 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"residual": 16 * 4, "apply": 13 * 4, "sweep": 16 * 4}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the plain FP64 form")
+    ap.add_argument("--skip-learned", action="store_true", help="do not train and time the learned form")
+    ap.add_argument("--skip-c3", action="store_true", help="do not run the 9-cell quarter cavity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
@@ -73,6 +79,40 @@ def cpu_baseline():
                 max_residual=float(np.max(info["residuals"])))
 
 
+def run_c3(dm, torch):
+    """Secondary figures on the 9-cell quarter cavity (96 x 96 x 1024, PMC
+    planes x = 0 and y = 0): the FP32 red-black sweep's bandwidth where the
+    fine-level working set (about 630 MB) exceeds the 256 MB Infinity Cache,
+    and the 9 lowest modes at sigma = 632 (0.9 x the lowest eigenvalue of a
+    48 x 48 x 512 run) with the FP32-multigrid form."""
+    nxy, nz = 96, 1024
+    h = 1.235 / nz
+    geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
+                           bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
+    t0 = time.perf_counter()
+    op = dm.Operator(geom, (nxy, nxy, nz), h, 632.0, levels=0, fgmres_restart=50)
+    setup = time.perf_counter() - t0
+    try:
+        ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=20)
+        cells = nxy * nxy * nz
+        gbs = BYTES_PER_CELL["sweep"] * cells / (ms_sweep * 1e-3) / 1e9
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = op.eigs(9, sigma=632.0, tol=TOL, seed=3, solve_mode=dm.SOLVE_FGMRES_MG32, block=4,
+                      max_basis=48, max_restarts=30)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        lay = op.layout(0)
+        return {"grid": [nxy, nxy, nz], "levels": lay["levels"], "active_faces": lay["active_faces"],
+                "setup_s": round(setup, 2), "sweep_ms": ms_sweep, "sweep_GBps": round(gbs, 1),
+                "sweep_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                "status": out["status"], "s_per_eigenpair": dt / 9, "lam": out["lam"].tolist(),
+                "max_residual": out["max_residual"], "outer_iterations": out["outer_iterations"],
+                "inner_iterations": out["inner_iterations"], "restarts": out["restarts"]}
+    finally:
+        op.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -97,8 +137,10 @@ def main():
             raise RuntimeError(f"eigensolve did not converge: {out}")
         return out
 
+    log(f"setup {setup_s:.2f}s; warmup")
     for _ in range(args.warmup):
         solve(dm.SOLVE_FGMRES_MG32)
+    log("timed steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     outs = []
@@ -115,6 +157,7 @@ def main():
                             inner_iterations=main_out["inner_iterations"],
                             outer_iterations=main_out["outer_iterations"])}
     if not args.skip_fp64:
+        log("fp64 form")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         o64 = solve(dm.SOLVE_FGMRES_MG64)
@@ -125,6 +168,26 @@ def main():
                              inner_iterations=o64["inner_iterations"],
                              outer_iterations=o64["outer_iterations"],
                              rel_diff_vs_fp32mg=float(np.max(abs(o64["lam"] - main_out["lam"]) / o64["lam"])))
+    if not args.skip_learned:
+        log("learned form: training")
+        from paper_1301_3794_amd import train
+        net = dm.Net(seed=0)
+        hist = train.train_on_ellipsoids(net, n=64, count=6, steps=200, rounds=5, lr=1e-3, sigma=SIGMA)
+        net.attach(op)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ol = solve(dm.SOLVE_FGMRES_MG32_LEARNED)
+        torch.cuda.synchronize()
+        dl = time.perf_counter() - t1
+        forms["learned"] = dict(s_per_eigenpair=dl / K_EIG, lam=ol["lam"].tolist(),
+                                max_residual=ol["max_residual"],
+                                inner_iterations=ol["inner_iterations"],
+                                outer_iterations=ol["outer_iterations"],
+                                training={"pairs": hist["pairs"], "seconds": round(hist["train_s"], 2),
+                                          "cavities": "6 ellipsoids at 64^3, sigma=36",
+                                          "loss_per_round": [round(x, 4) for x in hist["loss_per_round"]]})
+        dm.Net.detach(op)
+        net.close()
     golden = os.path.join(ROOT, "tests", "golden", "sphere128_oracle.json")
     if os.path.exists(golden):
         ref = np.array(json.load(open(golden))["lam"][:K_EIG])
@@ -144,8 +207,14 @@ def main():
                 "vcycle_ms": ms_vc, "residual_ms": ms_res,
                 "residual_GBps": BYTES_PER_CELL["residual"] * cells / (ms_res * 1e-3) / 1e9}
 
+    c3 = None
+    if not args.skip_c3:
+        log("9-cell quarter cavity")
+        c3 = run_c3(dm, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         cb = cpu_baseline()
         scale = lay["active_faces"] / cb["sample_active_faces"]
         cpu = {"value": cb["sample_seconds"] / K_EIG * scale, "unit": "s/eigenpair", "cores": 1,
@@ -166,6 +235,7 @@ def main():
         "forms": forms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "c3_9cell_quarter": c3,
     }
     print(json.dumps(line))
     op.close()
