@@ -191,7 +191,10 @@ int dm_prolong_add(dm_op *op, int prec, int level, const void *x_coarse_dev,
 /* One multigrid V-cycle x = B f for M on level 0, zero initial guess:
  * nu_pre sweeps, residual, restriction, recursion, prolongation, nu_post
  * reverse sweeps; exact dense FP64 solve on the coarsest level.  prec 64
- * (all FP64) or 32 (FP32 smoothing/transfers, FP64 coarsest solve). */
+ * (all FP64) or 32 (FP32 smoothing/transfers, FP64 coarsest solve).
+ * Runs the same captured HIP graph the solvers use (f and x are copied to
+ * and from the op's own buffers); the graph is recorded on first use and
+ * re-recorded after dm_set_shift. */
 int dm_vcycle(dm_op *op, int prec, const void *f_dev, void *x_dev, void *stream);
 
 /* Divergence projection b_out = P_DM b (eq. proj); the scalar system
@@ -322,7 +325,8 @@ int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float 
 #define DM_KERNEL_SWEEP     3  /* the six class updates of one red-black sweep */
 #define DM_KERNEL_RESTRICT  4  /* `level` -> `level`+1 */
 #define DM_KERNEL_PROLONG   5  /* `level`+1 -> `level` */
-#define DM_KERNEL_VCYCLE    6  /* one whole V-cycle (level must be 0) */
+#define DM_KERNEL_VCYCLE    6  /* one whole V-cycle, replayed from the solver's
+                                  captured graph (level must be 0) */
 
 /* Average duration of one launch of `kernel` (prec 64 or 32) on seeded
  * N(0,1) data in library-owned buffers: 2 untimed launches, then `reps`

@@ -119,6 +119,7 @@ using namespace dm;
 static void free_op(dm_op *op) {
     if (!op) return;
     if (op->net) op->net->op = nullptr;
+    invalidate_graphs(op);
     hipSetDevice(op->device);
     if (op->stream) hipStreamSynchronize(op->stream);
     for (void *p : op->allocs) hipFree(p);
@@ -242,6 +243,7 @@ int dm_set_shift(dm_op *op, double sigma) {
         DM_HIP(hipSetDevice(op->device));
         const double old = op->sigma;
         op->sigma = sigma;
+        invalidate_graphs(op);
         try {
             factor_coarse(op);
         } catch (...) {
@@ -381,8 +383,15 @@ int dm_vcycle(dm_op *op, int prec, const void *f, void *x, void *stream) {
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         fill_ghosts(op->lv[0], prec, f, false, s);
-        if (prec == 64) vcycle<double>(op, 0, (const double *)f, (double *)x, s);
-        else vcycle<float>(op, 0, (const float *)f, (float *)x, s);
+        // through the solver's captured V-cycle graph, between its fixed buffers
+        ensure_krylov(op);
+        const int64_t n = op->n0();
+        const size_t bytes = n * (prec == 64 ? sizeof(double) : sizeof(float));
+        void *fin = prec == 64 ? (void *)op->gv_f64 : (void *)op->fg_f32;
+        void *xout = prec == 64 ? (void *)op->gv_x64 : (void *)op->fg_x32;
+        DM_HIP(hipMemcpyAsync(fin, f, bytes, hipMemcpyDeviceToDevice, s));
+        vcycle_graphed(op, prec, s);
+        DM_HIP(hipMemcpyAsync(x, xout, bytes, hipMemcpyDeviceToDevice, s));
         return DM_OK;
     });
 }
@@ -605,9 +614,8 @@ int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double 
                         if (prec == 64) launch_prolong_add<double>(L.g, C.g, L.coef64, C.coef64, (double *)c, (double *)y, s);
                         else launch_prolong_add<float>(L.g, C.g, L.coef32, C.coef32, (float *)c, (float *)y, s);
                         break;
-                    case DM_KERNEL_VCYCLE:
-                        if (prec == 64) vcycle<double>(op, 0, (double *)f, (double *)y, s);
-                        else vcycle<float>(op, 0, (float *)f, (float *)y, s);
+                    case DM_KERNEL_VCYCLE:   // the solver's graph, between its own buffers
+                        vcycle_graphed(op, prec, s);
                         break;
                 }
             };

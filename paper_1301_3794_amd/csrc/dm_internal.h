@@ -142,6 +142,9 @@ enum { CAX = 0, CAY, CAZ, CLX, CLY, CLZ, CVINV, NCOEF };
 template <class T>
 struct Coefs {
     const T *ax, *ay, *az, *lx, *ly, *lz, *vinv;
+    // per-cell row classes (device coefficient blocks only, see kFaceActive):
+    // P bytes stored right after the 7 coefficient blocks
+    const uint8_t *flags;
 };
 
 template <class T>
@@ -150,8 +153,18 @@ inline Coefs<T> coefs_of(const T *base, int64_t P) {
     c.ax = base; c.ay = base + P; c.az = base + 2 * P;
     c.lx = base + 3 * P; c.ly = base + 4 * P; c.lz = base + 5 * P;
     c.vinv = base + 6 * P;
+    c.flags = reinterpret_cast<const uint8_t *>(base + 7 * P);
     return c;
 }
+
+// Row classes of the faces of a cell, one byte per cell: bit c (kFaceActive
+// << c) is set when face component c is active (a > 0); bit 3 + c
+// (kFaceVacuum << c) when every coefficient in the 3^3 block of cells around
+// is that of vacuum (a = l = v = 1) and the cell touches no PMC plane.  On a
+// vacuum row the curl-curl and grad-div cross terms cancel and M is the
+// 7-point Laplacian of the face's own component:
+//     (M x)_f = (6 x_f - sum of the 6 same-component neighbours) / h^2 - sigma x_f.
+constexpr uint8_t kFaceActive = 1, kFaceVacuum = 8;
 
 // ---------------------------------------------------------------------------
 // Stencil rows of M (Sec. 2 eq. farInt for C L C^T, Sec. 5.1 eq. divBInt for
@@ -267,6 +280,8 @@ void launch_s_prolong_add(const Grid &gf, const Grid &gc, const double *coef_f,
 void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 void launch_scale(int64_t n, double a, double *x, hipStream_t s);
+template <class T>
+void launch_zero(int64_t n, T *x, hipStream_t s);
 void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
 // out[i] = sum_n V_i[n] w[n] (wt[n]) for i < nv; V_i = V + i*ld; results left in
 // device buffer `dout` (nv doubles); `part` scratch of nv * kReduceBlocks doubles

@@ -53,6 +53,12 @@ __device__ inline T inv_h2_of(const Grid &g) {
 // ---------------------------------------------------------------------------
 // y = M x, y = K x, or r = f - M x
 // ---------------------------------------------------------------------------
+// 7-point vacuum row of component array C at p (no 1/h^2)
+template <class T>
+__device__ inline T vac_row(const T *C, int64_t p, int64_t dy, int64_t dz) {
+    return T(6) * C[p] - (C[p - 1] + C[p + 1]) - (C[p - dy] + C[p + dy]) - (C[p - dz] + C[p + dz]);
+}
+
 template <class T, int KIND>
 __global__ void __launch_bounds__(kThreads)
 k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restrict__ x,
@@ -63,24 +69,32 @@ k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restric
     const int64_t p = pidx(g, i, j, k);
     const T *X = x, *Y = x + P, *Z = x + 2 * P;
     const T ih2 = inv_h2_of<T>(g);
-    T yx, yy, yz;
+    const uint8_t fl = c.flags[p];
+    T yx = T(0), yy = T(0), yz = T(0);
     if (KIND == AK_K) {
-        yx = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
-        yy = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
-        yz = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 0)) yx = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 1)) yy = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 2)) yz = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
     } else {
-        yx = ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
-        yy = ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
-        yz = ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
-        if (KIND == AK_RESID) {
-            yx = f[p] - yx;
-            yy = f[P + p] - yy;
-            yz = f[2 * P + p] - yz;
+        if (fl & (kFaceActive << 0)) {
+            yx = (fl & (kFaceVacuum << 0)) ? ih2 * vac_row(X, p, dy, dz) - sigma * X[p]
+                                           : ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
+            if (KIND == AK_RESID) yx = f[p] - yx;
+        }
+        if (fl & (kFaceActive << 1)) {
+            yy = (fl & (kFaceVacuum << 1)) ? ih2 * vac_row(Y, p, dy, dz) - sigma * Y[p]
+                                           : ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
+            if (KIND == AK_RESID) yy = f[P + p] - yy;
+        }
+        if (fl & (kFaceActive << 2)) {
+            yz = (fl & (kFaceVacuum << 2)) ? ih2 * vac_row(Z, p, dy, dz) - sigma * Z[p]
+                                           : ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
+            if (KIND == AK_RESID) yz = f[2 * P + p] - yz;
         }
     }
-    put_face<T>(g, y, 0, i, j, k, p, c.ax[p] != T(0) ? yx : T(0));
-    put_face<T>(g, y + P, 1, i, j, k, p, c.ay[p] != T(0) ? yy : T(0));
-    put_face<T>(g, y + 2 * P, 2, i, j, k, p, c.az[p] != T(0) ? yz : T(0));
+    put_face<T>(g, y, 0, i, j, k, p, yx);
+    put_face<T>(g, y + P, 1, i, j, k, p, yy);
+    put_face<T>(g, y + 2 * P, 2, i, j, k, p, yz);
 }
 
 // y = A x
@@ -116,9 +130,17 @@ k_smooth(Grid g, Coefs<T> c, T sigma, int colour, const T *__restrict__ f, T *__
     const int64_t p = pidx(g, i, j, k);
     T *X = x, *Y = x + P, *Z = x + 2 * P;
     const T ih2 = inv_h2_of<T>(g);
-    const T *a = COMP == 0 ? c.ax : (COMP == 1 ? c.ay : c.az);
     T *xc = COMP == 0 ? X : (COMP == 1 ? Y : Z);
-    if (a[p] == T(0)) return;
+    const uint8_t fl = c.flags[p];
+    if (!(fl & (kFaceActive << COMP))) return;
+    if (fl & (kFaceVacuum << COMP)) {
+        const T xp = xc[p];
+        const T row = ih2 * vac_row<T>(xc, p, dy, dz) - sigma * xp;
+        const T d = T(6) * ih2 - sigma;
+        put_face<T>(g, xc, COMP, i, j, k, p, xp + (f[COMP * P + p] - row) / d);
+        return;
+    }
+    const T *a = COMP == 0 ? c.ax : (COMP == 1 ? c.ay : c.az);
     T row;
     if (COMP == 0) row = row_x<T, true>(c, X, Y, Z, p, dy, dz);
     else if (COMP == 1) row = row_y<T, true>(c, X, Y, Z, p, dy, dz);
@@ -195,6 +217,13 @@ k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ 
     if (cf.az[p] != T(0))
         put_face<T>(gf, x + 2 * Pf, 2, i, j, k, p,
                     x[2 * Pf + p] + ((k & 1) ? wmean(cc.az[q], CZ[q], cc.az[q + cz], CZ[q + cz]) : CZ[q]));
+}
+
+// x = 0 (a kernel, not a memset: it may be recorded into a HIP graph)
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_zero(int64_t n, T *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
+        x[e] = T(0);
 }
 
 template <class TI, class TO>
@@ -792,6 +821,13 @@ void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, flat_grid(n), dim3(kThreads), 0, s, n, a, x, b, y);
 }
+template <class T>
+void launch_zero(int64_t n, T *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero<T>, flat_grid(n), dim3(kThreads), 0, s, n, x);
+}
+template void launch_zero<double>(int64_t, double *, hipStream_t);
+template void launch_zero<float>(int64_t, float *, hipStream_t);
+
 void launch_scale(int64_t n, double a, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_scale, flat_grid(n), dim3(kThreads), 0, s, n, a, x);
 }

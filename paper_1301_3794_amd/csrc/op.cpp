@@ -108,6 +108,34 @@ std::vector<double> to_coefs(const Grid &g, const std::vector<double> &fr) {
 
 }  // namespace
 
+// row classes of every cell (kFaceActive / kFaceVacuum bits) from the
+// coefficient blocks ax ay az lx ly lz vinv of one level
+std::vector<uint8_t> row_flags(const Grid &g, const std::vector<double> &c) {
+    const int64_t P = g.P;
+    std::vector<uint8_t> fl(P, 0);
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                const int64_t p = pidx(g, i, j, k);
+                const int idx[3] = {i, j, k};
+                bool vac = true;
+                for (int a = 0; a < 3; ++a)
+                    if (((g.pmc >> a) & 1) && idx[a] == 0) vac = false;
+                for (int dz = -1; dz <= 1 && vac; ++dz)
+                    for (int dy = -1; dy <= 1 && vac; ++dy)
+                        for (int dx = -1; dx <= 1 && vac; ++dx) {
+                            const int64_t q = p + dx + (int64_t)dy * g.sy + (int64_t)dz * g.sz;
+                            for (int b = 0; b < 7; ++b)
+                                if (c[b * P + q] != 1.0) { vac = false; break; }
+                        }
+                uint8_t f = 0;
+                for (int a = 0; a < 3; ++a)
+                    if (c[a * P + p] != 0.0) f |= (uint8_t)((kFaceActive << a) | (vac ? (kFaceVacuum << a) : 0));
+                fl[p] = f;
+            }
+    return fl;
+}
+
 void build_hierarchy(dm_op *op, const double *user_frac) {
     const int nl = op->opt.levels;
     int pmc = 0;
@@ -144,10 +172,14 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         const int64_t P = L.g.P;
         std::vector<double> c = to_coefs(L.g, op->frac[l]);
         std::vector<float> c32(c.begin(), c.end());
-        L.coef64 = op->dalloc<double>(7 * P);
-        L.coef32 = op->dalloc<float>(7 * P);
+        const std::vector<uint8_t> fl = row_flags(L.g, c);
+        // coefficient blocks followed by the P row-class bytes
+        L.coef64 = op->dalloc<double>(7 * P + (P + 7) / 8);
+        L.coef32 = op->dalloc<float>(7 * P + (P + 3) / 4);
         DM_HIP(hipMemcpyAsync(L.coef64, c.data(), 7 * P * sizeof(double), hipMemcpyHostToDevice, op->stream));
         DM_HIP(hipMemcpyAsync(L.coef32, c32.data(), 7 * P * sizeof(float), hipMemcpyHostToDevice, op->stream));
+        DM_HIP(hipMemcpyAsync(L.coef64 + 7 * P, fl.data(), P, hipMemcpyHostToDevice, op->stream));
+        DM_HIP(hipMemcpyAsync(L.coef32 + 7 * P, fl.data(), P, hipMemcpyHostToDevice, op->stream));
         DM_HIP(hipStreamSynchronize(op->stream));
         L.sweight = 1.0 / (std::ldexp(1.0, l) * op->h * op->h);
         int64_t naf = 0, nac = 0;  // owned entries only (not PMC ghosts)

@@ -76,6 +76,8 @@ struct dm_op {
     int fg_m = 0;
     double *fg_V = nullptr, *fg_Z = nullptr, *fg_w = nullptr, *dcoef = nullptr;
     float *fg_f32 = nullptr, *fg_x32 = nullptr;
+    double *gv_f64 = nullptr, *gv_x64 = nullptr;       // fixed in/out of the FP64 V-cycle graph
+    hipGraphExec_t g_vc32 = nullptr, g_vc64 = nullptr, g_svc = nullptr;
     double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
     double *pj_g = nullptr, *pj_psi = nullptr, *pj_r = nullptr, *pj_z = nullptr,
            *pj_p = nullptr, *pj_q = nullptr;
@@ -122,6 +124,12 @@ int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxi
           dm_solve_info *info, hipStream_t s);
 void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s);
 void ensure_krylov(dm_op *op);
+void ensure_proj(dm_op *op);
+void invalidate_graphs(dm_op *op);
+// V-cycle graphs: prec 32 runs fg_f32 -> fg_x32, prec 64 gv_f64 -> gv_x64;
+// the scalar one pj_r -> pj_z
+void vcycle_graphed(dm_op *op, int prec, hipStream_t s);
+void svcycle_graphed(dm_op *op, hipStream_t s);
 double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n, hipStream_t s);
 int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt, double *lam,
          double *vecs, double *res, dm_eig_info *info, hipStream_t s);

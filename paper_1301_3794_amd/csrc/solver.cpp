@@ -92,17 +92,6 @@ void demean_cells(dm_op *op, double *x, hipStream_t s) {
     launch_sub_masked(L.g.P, op->cmask, op->dres, 1.0 / (double)std::max<int64_t>(1, L.n_act_cells), x, s);
 }
 
-void ensure_proj(dm_op *op) {
-    if (!op->pj_g) {
-        const int64_t P = op->lv[0].g.P;
-        op->pj_g = op->dalloc<double>(P);
-        op->pj_psi = op->dalloc<double>(P);
-        op->pj_r = op->dalloc<double>(P);
-        op->pj_z = op->dalloc<double>(P);
-        op->pj_p = op->dalloc<double>(P);
-        op->pj_q = op->dalloc<double>(P);
-    }
-}
 
 int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
            dm_solve_info *info, hipStream_t s) {
@@ -260,6 +249,18 @@ int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_
 
 }  // namespace
 
+void ensure_proj(dm_op *op) {
+    if (!op->pj_g) {
+        const int64_t P = op->lv[0].g.P;
+        op->pj_g = op->dalloc<double>(P);
+        op->pj_psi = op->dalloc<double>(P);
+        op->pj_r = op->dalloc<double>(P);
+        op->pj_z = op->dalloc<double>(P);
+        op->pj_p = op->dalloc<double>(P);
+        op->pj_q = op->dalloc<double>(P);
+    }
+}
+
 void ensure_krylov(dm_op *op) {
     const int64_t n = op->n0();
     if (!op->fg_V) {
@@ -271,6 +272,8 @@ void ensure_krylov(dm_op *op) {
         op->fg_w = op->dalloc<double>(n);
         op->fg_f32 = op->dalloc<float>(n);
         op->fg_x32 = op->dalloc<float>(n);
+        op->gv_f64 = op->dalloc<double>(n);
+        op->gv_x64 = op->dalloc<double>(n);
         op->dcoef = op->dalloc<double>(kMaxDots);
     }
 }
@@ -286,11 +289,13 @@ void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s
     const int64_t n = op->n0();
     if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
         launch_cast<double, float>(v, op->fg_f32, n, s);
-        vcycle<float>(op, 0, op->fg_f32, op->fg_x32, s);
+        vcycle_graphed(op, 32, s);
         launch_cast<float, double>(op->fg_x32, z, n, s);
         if (mode == DM_SOLVE_FGMRES_MG32_LEARNED) net_correct(op, v, z, s);
     } else {
-        vcycle<double>(op, 0, v, z, s);
+        launch_copy(n, v, op->gv_f64, s);
+        vcycle_graphed(op, 64, s);
+        launch_copy(n, op->gv_x64, z, s);
     }
 }
 
@@ -308,7 +313,7 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
     Level &L = op->lv[l];
     const Grid &g = L.g;
     const T sig = (T)op->sigma;
-    DM_HIP(hipMemsetAsync(x, 0, 3 * g.P * sizeof(T), s));
+    launch_zero<T>(3 * g.P, x, s);
     if (l == op->nlev() - 1) {
         launch_coarse_solve<T>(op->nc, op->cinv, op->cidx, f, x, s);
         launch_mirror_faces<T>(g, x, s);
@@ -336,7 +341,7 @@ template void vcycle<float>(dm_op *, int, const float *, float *, hipStream_t);
 void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
     Level &L = op->lv[l];
     const Grid &g = L.g;
-    DM_HIP(hipMemsetAsync(x, 0, g.P * sizeof(double), s));
+    launch_zero<double>(g.P, x, s);
     if (l == op->nlev() - 1) {
         launch_coarse_solve<double>(op->ns, op->sinv, op->sidx, f, x, s);
         launch_mirror_cells(g, x, s);
@@ -351,6 +356,64 @@ void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
     launch_s_prolong_add(g, C.g, L.coef64, C.sx, x, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int col = 1; col >= 0; --col) launch_s_smooth(g, L.coef64, L.sweight, col, f, x, s);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycles replayed from captured HIP graphs.  A V-cycle is a fixed sequence
+// of ~27 launches per level, short on the coarse levels, so per-launch
+// overhead dominates its time; the graph is recorded once per operator (on
+// the op's own stream) between fixed buffers and launched on the caller's
+// stream.  The captured sequence holds kernels only (no memsets).  Graphs
+// bake in the shift and the coarsest inverse, so a change of shift drops them.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class F>
+hipGraphExec_t capture(dm_op *op, F &&record) {
+    hipGraph_t gph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DM_HIP(hipStreamBeginCapture(op->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        record(op->stream);
+    } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(op->stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        throw;
+    }
+    DM_HIP(hipStreamEndCapture(op->stream, &gph));
+    const hipError_t e = hipGraphInstantiate(&exec, gph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gph);
+    DM_HIP(e);
+    return exec;
+}
+
+}  // namespace
+
+void invalidate_graphs(dm_op *op) {
+    for (hipGraphExec_t *e : {&op->g_vc32, &op->g_vc64, &op->g_svc}) {
+        if (*e) (void)hipGraphExecDestroy(*e);
+        *e = nullptr;
+    }
+}
+
+void vcycle_graphed(dm_op *op, int prec, hipStream_t s) {
+    ensure_krylov(op);
+    if (prec == 32) {
+        if (!op->g_vc32)
+            op->g_vc32 = capture(op, [&](hipStream_t cs) { vcycle<float>(op, 0, op->fg_f32, op->fg_x32, cs); });
+        DM_HIP(hipGraphLaunch(op->g_vc32, s));
+    } else {
+        if (!op->g_vc64)
+            op->g_vc64 = capture(op, [&](hipStream_t cs) { vcycle<double>(op, 0, op->gv_f64, op->gv_x64, cs); });
+        DM_HIP(hipGraphLaunch(op->g_vc64, s));
+    }
+}
+
+void svcycle_graphed(dm_op *op, hipStream_t s) {
+    if (!op->g_svc)
+        op->g_svc = capture(op, [&](hipStream_t cs) { svcycle(op, 0, op->pj_r, op->pj_z, cs); });
+    DM_HIP(hipGraphLaunch(op->g_svc, s));
 }
 
 int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hipStream_t s,
@@ -373,7 +436,7 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
     if (!std::isfinite(gnorm)) throw DmError{DM_ENAN, "projection input is not finite"};
     if (gnorm > stop) {
         launch_copy(P, gv, r, s);
-        svcycle(op, 0, r, z, s);
+        svcycle_graphed(op, s);            // r -> z
         if (op->s_floating) demean_cells(op, z, s);
         launch_copy(P, z, p, s);
         double rz = dot1(op, r, z, op->cmask, P, s);
@@ -387,7 +450,7 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
             ++it;
             const double rn = std::sqrt(dot1(op, r, r, op->cmask, P, s));
             if (rn <= stop) break;
-            svcycle(op, 0, r, z, s);
+            svcycle_graphed(op, s);        // r -> z
             if (op->s_floating) demean_cells(op, z, s);
             const double rz2 = dot1(op, r, z, op->cmask, P, s);
             launch_axpby(P, 1.0, z, rz2 / rz, p, s);
