@@ -268,6 +268,48 @@ int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed,
             const dm_eig_options *opt, double *lambda_host, double *vecs_dev,
             double *residuals_host, dm_eig_info *info, void *stream);
 
+/* ---- batched cavities (one fused V-cycle for many operators) -------------
+ * A batch owns `count` operators (cavities of their own grids and cell
+ * sizes, no PMC planes).  Their FP32 V-cycles are merged level by level into
+ * shared launches -- one launch per smoothing class, residual, transfer and
+ * coarsest solve for all members -- recorded in one HIP graph; the block size
+ * of those launches (64, 128 or 256 threads) is picked at creation by timing
+ * each (autotuner).  Each member's values are exactly those of its own
+ * V-cycle. */
+typedef struct dm_batch dm_batch;   /* opaque, owned by the library */
+
+typedef struct {
+    int count;
+    int threads_per_block;      /* chosen by the autotuner */
+    double tuned_ms[3];         /* fused V-cycle at 64, 128, 256 threads per block */
+    int launches_per_vcycle;
+    int64_t cells;              /* finest cells over all members */
+    int64_t active_faces;
+} dm_batch_stats;
+
+/* geoms[count], dims[3*count], h[count]; every member gets sigma and opt.
+ * Errors as dm_build_operator; DM_EINVAL for PMC planes or mixed smoothing
+ * counts. */
+int dm_batch_create(int count, const dm_geometry *geoms, const int *dims, const double *h, double sigma,
+                    const dm_options *opt, dm_batch **out);
+void dm_batch_destroy(dm_batch *b);
+/* the i-th member (owned by the batch; use it like any operator) */
+int dm_batch_member(dm_batch *b, int i, dm_op **op);
+int dm_batch_info(const dm_batch *b, dm_batch_stats *stats);
+/* One fused FP32 V-cycle: x_i = B_i f_i for every member i (host arrays of
+ * device pointers to FP32 face vectors of the members' finest grids). */
+int dm_batch_vcycle(dm_batch *b, const float *const *f_dev, float *const *x_dev, void *stream);
+/* Average milliseconds of one fused V-cycle (graph replay, HIP events). */
+int dm_batch_time_vcycle(dm_batch *b, int reps, double *ms);
+/* dm_eigs on every member (k pairs each, FP32-multigrid solve mode forced),
+ * each on its own host thread and stream; every preconditioner application
+ * of all running members is one fused V-cycle.  lambda_host: count*k,
+ * residuals_host: count*k or NULL, info_host: count or NULL, seconds: wall
+ * time or NULL.  Returns the worst member status (an error names the
+ * member). */
+int dm_batch_eigs(dm_batch *b, int k, double sigma, double tol, uint64_t seed, const dm_eig_options *opt,
+                  double *lambda_host, double *residuals_host, dm_eig_info *info_host, double *seconds);
+
 /* ---- learned correction (not in the paper) ------------------------------
  * A 3-D convolutional network on the cell grid corrects the FP32 V-cycle's
  * answer.  Input per cell (10 channels): the residual r of the V-cycle's

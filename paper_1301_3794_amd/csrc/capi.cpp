@@ -6,6 +6,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <thread>
 
 #include "geometry.h"
 #include "learned.h"
@@ -438,6 +439,182 @@ int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed, const dm_
     return on_device(op, stream, [&](hipStream_t s) -> int {
         return eigs(op, k, tol, seed, o, lambda_host, vecs_dev, residuals_host, info, s);
     });
+}
+
+/* ---- batched cavities ---------------------------------------------------- */
+
+static void free_batch(dm_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    batch_release(b);
+    for (dm_op *op : b->ops) {
+        op->batch = nullptr;
+        dm_destroy(op);
+    }
+    for (hipEvent_t e : b->ev_in) (void)hipEventDestroy(e);
+    if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int dm_batch_create(int count, const dm_geometry *geoms, const int *dims, const double *h, double sigma,
+                    const dm_options *opt, dm_batch **out) {
+    if (!out) return fail(DM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !geoms || !dims || !h) return fail(DM_EINVAL, "bad batch arguments");
+    dm_batch *b = new dm_batch();
+    for (int i = 0; i < count; ++i) {
+        dm_op *op = nullptr;
+        const int rc = dm_build_operator(&geoms[i], dims + 3 * i, h[i], sigma, opt, &op);
+        if (rc != DM_OK) {
+            free_batch(b);
+            return rc;
+        }
+        op->batch_index = i;
+        b->ops.push_back(op);
+    }
+    const int rc = guarded([&]() -> int {
+        DM_HIP(hipGetDevice(&b->device));
+        DM_HIP(hipStreamCreate(&b->stream));
+        b->ev_in.resize(count, nullptr);
+        for (int i = 0; i < count; ++i) DM_HIP(hipEventCreateWithFlags(&b->ev_in[i], hipEventDisableTiming));
+        DM_HIP(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+        b->pending.assign(count, 0);
+        batch_setup(b);
+        return DM_OK;
+    });
+    if (rc != DM_OK) {
+        free_batch(b);
+        return rc;
+    }
+    *out = b;
+    return DM_OK;
+}
+
+void dm_batch_destroy(dm_batch *b) { free_batch(b); }
+
+int dm_batch_member(dm_batch *b, int i, dm_op **op) {
+    if (!b || !op || i < 0 || i >= (int)b->ops.size()) return fail(DM_EINVAL, "bad batch member");
+    *op = b->ops[i];
+    return DM_OK;
+}
+
+int dm_batch_info(const dm_batch *b, dm_batch_stats *st) {
+    if (!b || !st) return fail(DM_EINVAL, "NULL argument");
+    st->count = (int)b->ops.size();
+    st->threads_per_block = b->tpb;
+    for (int q = 0; q < 3; ++q) st->tuned_ms[q] = b->tuned_ms[q];
+    st->launches_per_vcycle = b->nsteps;
+    int64_t c = 0, a = 0;
+    for (const dm_op *op : b->ops) {
+        const dm::Grid &g = op->lv[0].g;
+        c += (int64_t)g.nx * g.ny * g.nz;
+        a += op->lv[0].n_act_faces;
+    }
+    st->cells = c;
+    st->active_faces = a;
+    return DM_OK;
+}
+
+int dm_batch_vcycle(dm_batch *b, const float *const *f_dev, float *const *x_dev, void *stream) {
+    if (!b || !f_dev || !x_dev) return fail(DM_EINVAL, "NULL argument");
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(b->device));
+        hipStream_t s = stream ? (hipStream_t)stream : b->stream;
+        for (size_t i = 0; i < b->ops.size(); ++i) {
+            if (!f_dev[i] || !x_dev[i]) return fail(DM_EINVAL, "NULL member vector");
+            DM_HIP(hipMemcpyAsync(b->ops[i]->fg_f32, f_dev[i], b->ops[i]->n0() * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s));
+        }
+        DM_HIP(hipGraphLaunch(b->graph, s));
+        for (size_t i = 0; i < b->ops.size(); ++i)
+            DM_HIP(hipMemcpyAsync(x_dev[i], b->ops[i]->fg_x32, b->ops[i]->n0() * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s));
+        DM_HIP(hipStreamSynchronize(s));
+        return DM_OK;
+    });
+}
+
+int dm_batch_time_vcycle(dm_batch *b, int reps, double *ms) {
+    if (!b || !ms || reps < 1) return fail(DM_EINVAL, "bad arguments");
+    return guarded([&]() -> int {
+        DM_HIP(hipSetDevice(b->device));
+        hipEvent_t e0, e1;
+        DM_HIP(hipEventCreate(&e0));
+        DM_HIP(hipEventCreate(&e1));
+        DM_HIP(hipGraphLaunch(b->graph, b->stream));
+        DM_HIP(hipEventRecord(e0, b->stream));
+        for (int r = 0; r < reps; ++r) DM_HIP(hipGraphLaunch(b->graph, b->stream));
+        DM_HIP(hipEventRecord(e1, b->stream));
+        DM_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        DM_HIP(hipEventElapsedTime(&t, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms = t / reps;
+        return DM_OK;
+    });
+}
+
+int dm_batch_eigs(dm_batch *b, int k, double sigma, double tol, uint64_t seed, const dm_eig_options *opt,
+                  double *lambda_host, double *residuals_host, dm_eig_info *info_host, double *seconds) {
+    if (!b || !lambda_host) return fail(DM_EINVAL, "NULL argument");
+    if (k < 1 || !(tol > 0.0)) return fail(DM_EINVAL, "bad k or tol");
+    dm_eig_options o;
+    if (opt) o = *opt;
+    else dm_default_eig_options(&o);
+    o.solve_mode = DM_SOLVE_FGMRES_MG32;
+    const int n = (int)b->ops.size();
+    // a change of shift re-factors every member and re-records the fused V-cycle
+    bool reshift = false;
+    for (dm_op *op : b->ops)
+        if (op->sigma != sigma) {
+            const int rc = dm_set_shift(op, sigma);
+            if (rc != DM_OK) return rc;
+            reshift = true;
+        }
+    if (reshift) {
+        const int rc = guarded([&]() -> int {
+            DM_HIP(hipSetDevice(b->device));
+            batch_setup(b);
+            return DM_OK;
+        });
+        if (rc != DM_OK) return rc;
+    }
+    std::vector<int> codes(n, DM_OK);
+    std::vector<std::string> msgs(n);
+    std::vector<dm_eig_info> infos(n);
+    b->active = n;
+    b->submitted = 0;
+    std::fill(b->pending.begin(), b->pending.end(), 0);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::thread> th;
+    for (int i = 0; i < n; ++i)
+        th.emplace_back([&, i]() {
+            dm_op *op = b->ops[i];
+            op->batch = b;
+            codes[i] = guarded([&]() -> int {
+                DM_HIP(hipSetDevice(op->device));
+                const int rc = eigs(op, k, tol, seed, o, lambda_host + (size_t)i * k, nullptr,
+                                    residuals_host ? residuals_host + (size_t)i * k : nullptr, &infos[i],
+                                    op->stream);
+                DM_HIP(hipStreamSynchronize(op->stream));
+                return rc;
+            });
+            if (codes[i] < 0) msgs[i] = dm_last_error_message();
+            op->batch = nullptr;
+            batch_leave(b);
+        });
+    for (auto &t : th) t.join();
+    if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info_host)
+        for (int i = 0; i < n; ++i) info_host[i] = infos[i];
+    int worst = DM_OK;
+    for (int i = 0; i < n; ++i) {
+        if (codes[i] < 0) return fail(codes[i], "member " + std::to_string(i) + ": " + msgs[i]);
+        worst = std::max(worst, codes[i]);
+    }
+    return worst;
 }
 
 /* ---- learned correction ------------------------------------------------- */

@@ -148,7 +148,7 @@ struct Coefs {
 };
 
 template <class T>
-inline Coefs<T> coefs_of(const T *base, int64_t P) {
+__host__ __device__ inline Coefs<T> coefs_of(const T *base, int64_t P) {
     Coefs<T> c;
     c.ax = base; c.ay = base + P; c.az = base + 2 * P;
     c.lx = base + 3 * P; c.ly = base + 4 * P; c.lz = base + 5 * P;
@@ -229,6 +229,34 @@ __host__ __device__ inline T diag_of(const Coefs<T> &c, int comp, int64_t p, int
     return inv_h2 * (c.lx[p] + c.lx[p + dy] + c.ly[p] + c.ly[p + 1] +
                      c.az[p] * c.az[p] * (c.vinv[p - dz] + c.vinv[p])) - sigma * c.az[p];
 }
+
+// ---------------------------------------------------------------------------
+// Batched launches: one launch performs the same V-cycle step for several
+// operators (cavities), each its own grid, coefficients and buffers.  A job
+// is one operator's share; its work items occupy blocks [block0, block0 +
+// its block count) of the launch.  Used only without PMC planes.
+// ---------------------------------------------------------------------------
+struct BJob {
+    Grid g, gc;           // the job's level (and the next coarser one)
+    const void *c;        // coefficient base of g (7 blocks + row classes)
+    const void *cc;       // coefficient base of gc
+    const void *in;       // f (smooth, residual), r (restrict), xc (prolong), f (coarse)
+    const void *aux;      // x (residual)
+    void *out;            // x (smooth, prolong, zero, coarse), r (residual), fc (restrict)
+    const double *inv;    // coarsest dense inverse (coarse)
+    const int64_t *idx;   // its active-face index (coarse)
+    int64_t items;        // work items of the job
+    int ncoarse;          // coarsest active faces (coarse)
+    double sigma;
+    int64_t block0;
+};
+
+enum BatchStep { BS_ZERO = 0, BS_SMOOTH, BS_RESID, BS_RESTRICT, BS_PROLONG, BS_COARSE };
+
+// one batched launch of `step` over `njobs` jobs (device array) covering
+// `nblocks` blocks of `tpb` threads (tpb <= 256; the coarse step uses 256)
+void launch_batched(int step, int comp, int colour, const BJob *jobs, int njobs, int64_t nblocks, int tpb,
+                    hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All take a stream; none synchronise.

@@ -60,11 +60,10 @@ __device__ inline T vac_row(const T *C, int64_t p, int64_t dy, int64_t dz) {
 }
 
 template <class T, int KIND>
-__global__ void __launch_bounds__(kThreads)
-k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restrict__ x,
-        T *__restrict__ y) {
+__device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T sigma, const T *__restrict__ f,
+                                           const T *__restrict__ x, T *__restrict__ y, int64_t item) {
     int i, j, k;
-    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    if (!cell_of(g, item, i, j, k)) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
     const int64_t p = pidx(g, i, j, k);
     const T *X = x, *Y = x + P, *Z = x + 2 * P;
@@ -97,6 +96,13 @@ k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restric
     put_face<T>(g, y + 2 * P, 2, i, j, k, p, yz);
 }
 
+template <class T, int KIND>
+__global__ void __launch_bounds__(kThreads)
+k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restrict__ x,
+        T *__restrict__ y) {
+    apply_body<T, KIND>(g, c, sigma, f, x, y, xcd_item());
+}
+
 // y = A x
 template <class T>
 __global__ void __launch_bounds__(kThreads)
@@ -116,10 +122,9 @@ k_apply_A(Grid g, Coefs<T> c, const T *__restrict__ x, T *__restrict__ y) {
 // row of the same class reads those images except its own.
 // ---------------------------------------------------------------------------
 template <class T, int COMP>
-__global__ void __launch_bounds__(kThreads)
-k_smooth(Grid g, Coefs<T> c, T sigma, int colour, const T *__restrict__ f, T *__restrict__ x) {
+__device__ __forceinline__ void smooth_body(const Grid &g, const Coefs<T> &c, T sigma, int colour,
+                                            const T *__restrict__ f, T *__restrict__ x, int64_t t) {
     const int nxh = (g.nx + 1) >> 1;
-    const int64_t t = xcd_item();
     if (t >= (int64_t)nxh * g.ny * g.nz) return;
     const int ih = (int)(t % nxh);
     const int64_t r = t / nxh;
@@ -151,14 +156,20 @@ k_smooth(Grid g, Coefs<T> c, T sigma, int colour, const T *__restrict__ f, T *__
     put_face<T>(g, xc, COMP, i, j, k, p, xc[p] + (f[COMP * P + p] - row) / d);
 }
 
+template <class T, int COMP>
+__global__ void __launch_bounds__(kThreads)
+k_smooth(Grid g, Coefs<T> c, T sigma, int colour, const T *__restrict__ f, T *__restrict__ x) {
+    smooth_body<T, COMP>(g, c, sigma, colour, f, x, xcd_item());
+}
+
 // ---------------------------------------------------------------------------
 // Staggered transfers.  P: linear along the normal, constant across; R = P^T/8.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(kThreads)
-k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict__ fc) {
+__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
+                                              const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
     int I, J, K;
-    if (!cell_of(gc, xcd_item(), I, J, K)) return;
+    if (!cell_of(gc, item, I, J, K)) return;
     const int64_t Pf = gf.P, Pc = gc.P, fy = gf.sy, fz = gf.sz;
     const int64_t pc = pidx(gc, I, J, K);
     const T *RX = r, *RY = r + Pf, *RZ = r + 2 * Pf;
@@ -191,6 +202,12 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
     put_face<T>(gc, fc + 2 * Pc, 2, I, J, K, pc, az != T(0) ? e * sz : T(0));
 }
 
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict__ fc) {
+    restrict_body<T>(gf, gc, cc, r, fc, xcd_item());
+}
+
 // fine value between coarse faces c0, c1: (a0 x0 + a1 x1) / (a0 + a1)
 template <class T>
 __device__ __forceinline__ T wmean(T a0, T x0, T a1, T x1) {
@@ -199,11 +216,10 @@ __device__ __forceinline__ T wmean(T a0, T x0, T a1, T x1) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(kThreads)
-k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ xc,
-              T *__restrict__ x) {
+__device__ __forceinline__ void prolong_body(const Grid &gf, const Grid &gc, const Coefs<T> &cf, const Coefs<T> &cc,
+                                             const T *__restrict__ xc, T *__restrict__ x, int64_t item) {
     int i, j, k;
-    if (!cell_of(gf, xcd_item(), i, j, k)) return;
+    if (!cell_of(gf, item, i, j, k)) return;
     const int64_t Pf = gf.P, Pc = gc.P, cy = gc.sy, cz = gc.sz;
     const int64_t p = pidx(gf, i, j, k);
     const int64_t q = pidx(gc, i >> 1, j >> 1, k >> 1);
@@ -217,6 +233,13 @@ k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ 
     if (cf.az[p] != T(0))
         put_face<T>(gf, x + 2 * Pf, 2, i, j, k, p,
                     x[2 * Pf + p] + ((k & 1) ? wmean(cc.az[q], CZ[q], cc.az[q + cz], CZ[q + cz]) : CZ[q]));
+}
+
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ xc,
+              T *__restrict__ x) {
+    prolong_body<T>(gf, gc, cf, cc, xc, x, xcd_item());
 }
 
 // x = 0 (a kernel, not a memset: it may be recorded into a HIP graph)
@@ -235,10 +258,8 @@ __global__ void k_cast(const TI *__restrict__ in, TO *__restrict__ out, int64_t 
 
 // Coarsest level: x[idx[r]] = sum_c inv[r, c] f[idx[c]] (FP64 arithmetic)
 template <class T>
-__global__ void __launch_bounds__(kThreads)
-k_coarse_solve(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx,
-               const T *__restrict__ f, T *__restrict__ x) {
-    const int row = blockIdx.x;
+__device__ __forceinline__ void coarse_body(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx,
+                                            const T *__restrict__ f, T *__restrict__ x, int row) {
     double s = 0.0;
     for (int col = threadIdx.x; col < n; col += kThreads)
         s += inv[(int64_t)row * n + col] * (double)f[idx[col]];
@@ -251,6 +272,13 @@ k_coarse_solve(int n, const double *__restrict__ inv, const int64_t *__restrict_
         for (int w = 0; w < kThreads / 64; ++w) t += sh[w];
         x[idx[row]] = (T)t;
     }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+k_coarse_solve(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx,
+               const T *__restrict__ f, T *__restrict__ x) {
+    coarse_body<T>(n, inv, idx, f, x, blockIdx.x);
 }
 
 // PMC ghost layer of one plane (axis a) from the values next to it; planes
@@ -673,6 +701,66 @@ __global__ void k_randn(int64_t n, uint64_t seed, int64_t offset, const double *
         x[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
     }
 }
+
+// ---------------------------------------------------------------------------
+// Batched V-cycle steps (see BJob): the same bodies as the single-operator
+// kernels, the job found from the block index.
+// ---------------------------------------------------------------------------
+__device__ inline int find_job(const BJob *__restrict__ jobs, int nj, int64_t b) {
+    int lo = 0, hi = nj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int STEP, int COMP>
+__global__ void __launch_bounds__(kThreads)
+kb_step(const BJob *__restrict__ jobs, int nj, int colour) {
+    const BJob &J = jobs[find_job(jobs, nj, blockIdx.x)];
+    const int64_t lb = (int64_t)blockIdx.x - J.block0;
+    const int64_t item = lb * blockDim.x + threadIdx.x;
+    using T = float;
+    if (STEP == BS_ZERO) {
+        if (item < J.items) ((T *)J.out)[item] = T(0);
+    } else if (STEP == BS_SMOOTH) {
+        smooth_body<T, COMP>(J.g, coefs_of((const T *)J.c, J.g.P), (T)J.sigma, colour, (const T *)J.in, (T *)J.out,
+                             item);
+    } else if (STEP == BS_RESID) {
+        apply_body<T, AK_RESID>(J.g, coefs_of((const T *)J.c, J.g.P), (T)J.sigma, (const T *)J.in,
+                                (const T *)J.aux, (T *)J.out, item);
+    } else if (STEP == BS_RESTRICT) {
+        restrict_body<T>(J.g, J.gc, coefs_of((const T *)J.cc, J.gc.P), (const T *)J.in, (T *)J.out, item);
+    } else if (STEP == BS_PROLONG) {
+        prolong_body<T>(J.g, J.gc, coefs_of((const T *)J.c, J.g.P), coefs_of((const T *)J.cc, J.gc.P),
+                        (const T *)J.in, (T *)J.out, item);
+    } else {
+        coarse_body<T>(J.ncoarse, J.inv, J.idx, (const T *)J.in, (T *)J.out, (int)lb);
+    }
+}
+
+}  // namespace
+
+void launch_batched(int step, int comp, int colour, const BJob *jobs, int njobs, int64_t nblocks, int tpb,
+                    hipStream_t s) {
+    const dim3 grid((unsigned)nblocks), block((unsigned)(step == BS_COARSE ? kThreads : tpb));
+    switch (step) {
+        case BS_ZERO: hipLaunchKernelGGL((kb_step<BS_ZERO, 0>), grid, block, 0, s, jobs, njobs, colour); break;
+        case BS_SMOOTH:
+            if (comp == 0) hipLaunchKernelGGL((kb_step<BS_SMOOTH, 0>), grid, block, 0, s, jobs, njobs, colour);
+            else if (comp == 1) hipLaunchKernelGGL((kb_step<BS_SMOOTH, 1>), grid, block, 0, s, jobs, njobs, colour);
+            else hipLaunchKernelGGL((kb_step<BS_SMOOTH, 2>), grid, block, 0, s, jobs, njobs, colour);
+            break;
+        case BS_RESID: hipLaunchKernelGGL((kb_step<BS_RESID, 0>), grid, block, 0, s, jobs, njobs, colour); break;
+        case BS_RESTRICT: hipLaunchKernelGGL((kb_step<BS_RESTRICT, 0>), grid, block, 0, s, jobs, njobs, colour); break;
+        case BS_PROLONG: hipLaunchKernelGGL((kb_step<BS_PROLONG, 0>), grid, block, 0, s, jobs, njobs, colour); break;
+        default: hipLaunchKernelGGL((kb_step<BS_COARSE, 0>), grid, block, 0, s, jobs, njobs, colour); break;
+    }
+}
+
+namespace {
 
 inline dim3 flat_grid(int64_t n) {
     int64_t nb = ceil_div(n, kThreads);

@@ -2,7 +2,9 @@
 // coarsest-level dense inverses and Krylov workspaces.
 #pragma once
 
+#include <condition_variable>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +45,7 @@ struct DmError {
 }  // namespace dm
 
 struct dm_net;
+struct dm_batch;
 
 struct dm_op {
     dm_geometry geom{};
@@ -89,6 +92,10 @@ struct dm_op {
     dm_net *net = nullptr;
     double *ln_t1 = nullptr, *ln_t2 = nullptr, *ln_t3 = nullptr, *ln_t4 = nullptr;  // 3P each
     int ln_accepted = 0, ln_rejected = 0;
+    // batched runs: the batch whose fused V-cycle serves this op's FP32
+    // preconditioner while dm_batch_eigs runs (not owned), and the op's index
+    dm_batch *batch = nullptr;
+    int batch_index = -1;
 
     template <class T>
     T *dalloc(size_t count) {
@@ -164,4 +171,33 @@ double net_loss_grad(dm_op *op, int kind, const double *r, const double *e, doub
 void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s);
 void net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss, hipStream_t s);
 void net_correct(dm_op *op, const double *v, double *z, hipStream_t s);
+}  // namespace dm
+
+// A batch of operators (cavities) whose FP32 V-cycles run as one fused
+// sequence of batched launches recorded in one HIP graph (batch.cpp).
+struct dm_batch {
+    std::vector<dm_op *> ops;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t graph = nullptr;   // fused V-cycle: every op's fg_f32 -> fg_x32
+    int tpb = 256;                    // threads per block chosen by the autotuner
+    double tuned_ms[3] = {0, 0, 0};   // graph time for 64, 128, 256 threads per block
+    int nsteps = 0;                   // batched launches per fused V-cycle
+    std::vector<void *> tables;       // device job tables of the current graph
+    // lockstep: threads of dm_batch_eigs meet at every preconditioner call
+    std::mutex mu;
+    std::condition_variable cv;
+    int active = 0, submitted = 0;
+    uint64_t round = 0;
+    std::vector<char> pending;
+    std::vector<hipEvent_t> ev_in;
+    hipEvent_t ev_done = nullptr;
+};
+
+namespace dm {
+// batch.cpp
+void batch_setup(dm_batch *b);                   // schedule, autotune, capture
+void batch_release(dm_batch *b);
+void batch_vcycle_lockstep(dm_op *op, hipStream_t s);   // op->fg_f32 -> op->fg_x32
+void batch_leave(dm_batch *b);
 }  // namespace dm

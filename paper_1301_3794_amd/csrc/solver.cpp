@@ -289,7 +289,8 @@ void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s
     const int64_t n = op->n0();
     if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
         launch_cast<double, float>(v, op->fg_f32, n, s);
-        vcycle_graphed(op, 32, s);
+        if (op->batch && mode == DM_SOLVE_FGMRES_MG32) batch_vcycle_lockstep(op, s);
+        else vcycle_graphed(op, 32, s);
         launch_cast<float, double>(op->fg_x32, z, n, s);
         if (mode == DM_SOLVE_FGMRES_MG32_LEARNED) net_correct(op, v, z, s);
     } else {

@@ -33,7 +33,8 @@ EXPORTS = (
     "dm_project", "dm_solve", "dm_default_eig_options", "dm_eigs", "dm_strerror",
     "dm_last_error_message", "dm_time_kernel", "dm_net_create", "dm_net_destroy",
     "dm_net_get_weights", "dm_net_set_weights", "dm_net_attach", "dm_net_apply",
-    "dm_net_loss_grad", "dm_net_make_pair", "dm_net_train",
+    "dm_net_loss_grad", "dm_net_make_pair", "dm_net_train", "dm_batch_create", "dm_batch_destroy",
+    "dm_batch_member", "dm_batch_info", "dm_batch_vcycle", "dm_batch_time_vcycle", "dm_batch_eigs",
 )
 KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_SMOOTH, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE = range(7)
 
@@ -78,6 +79,12 @@ class EigOptions(ctypes.Structure):
                 ("proj_rtol", ctypes.c_double), ("block", ctypes.c_int),
                 ("max_basis", ctypes.c_int), ("max_restarts", ctypes.c_int),
                 ("verbose", ctypes.c_int)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("threads_per_block", ctypes.c_int),
+                ("tuned_ms", ctypes.c_double * 3), ("launches_per_vcycle", ctypes.c_int),
+                ("cells", ctypes.c_int64), ("active_faces", ctypes.c_int64)]
 
 
 class EigInfo(ctypes.Structure):
@@ -139,6 +146,16 @@ def lib():
     L.dm_net_loss_grad.argtypes = [vp, i, vp, vp, d, dp, fp, vp]
     L.dm_net_make_pair.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
     L.dm_net_train.argtypes = [vp, i, i, ctypes.c_float, ctypes.c_uint64, fp, vp]
+    L.dm_batch_create.argtypes = [i, ctypes.POINTER(Geometry), ctypes.POINTER(ctypes.c_int), dp, d,
+                                  ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.dm_batch_destroy.argtypes = [vp]
+    L.dm_batch_destroy.restype = None
+    L.dm_batch_member.argtypes = [vp, i, ctypes.POINTER(vp)]
+    L.dm_batch_info.argtypes = [vp, ctypes.POINTER(BatchStats)]
+    L.dm_batch_vcycle.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.dm_batch_time_vcycle.argtypes = [vp, i, dp]
+    L.dm_batch_eigs.argtypes = [vp, i, d, d, ctypes.c_uint64, ctypes.POINTER(EigOptions), dp, dp,
+                                ctypes.POINTER(EigInfo), dp]
     _lib = L
     return L
 
@@ -438,3 +455,100 @@ def net_train(op: "Operator", steps, lr=1e-3, seed=0, kind=NET_LOSS_RESIDUAL, st
     _check(lib().dm_net_train(op._op, int(kind), int(steps), ctypes.c_float(lr), ctypes.c_uint64(seed),
                               loss.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
     return loss[:steps]
+
+
+# ---------------------------------------------------------------------------
+# batched cavities
+# ---------------------------------------------------------------------------
+
+class _Member(Operator):
+    """A batch member: an operator owned by its batch (never destroyed here)."""
+
+    def __init__(self, handle, dims, h, sigma):   # noqa: D401 - no build
+        self._op = handle
+        self._net = None
+        self.dims = tuple(int(x) for x in dims)
+        self.h = float(h)
+        self.sigma = float(sigma)
+
+    def close(self):
+        self._op = ctypes.c_void_p()
+
+
+class Batch:
+    """``dm_batch_*``: cavities whose FP32 V-cycles run as one fused V-cycle."""
+
+    def __init__(self, geoms, dims, hs, sigma, levels=0, nu_pre=2, nu_post=2, fgmres_restart=30):
+        L = lib()
+        n = len(geoms)
+        garr = (Geometry * n)(*geoms)
+        darr = (ctypes.c_int * (3 * n))(*[int(v) for d3 in dims for v in d3])
+        harr = (ctypes.c_double * n)(*[float(x) for x in hs])
+        opt = Options()
+        L.dm_default_options(ctypes.byref(opt))
+        opt.levels, opt.nu_pre, opt.nu_post, opt.fgmres_restart = levels, nu_pre, nu_post, fgmres_restart
+        self._b = ctypes.c_void_p()
+        self._geoms = garr
+        _check(L.dm_batch_create(n, garr, darr, harr, float(sigma), ctypes.byref(opt), ctypes.byref(self._b)))
+        self.members = []
+        for q in range(n):
+            hdl = ctypes.c_void_p()
+            _check(L.dm_batch_member(self._b, q, ctypes.byref(hdl)))
+            self.members.append(_Member(hdl, dims[q], hs[q], sigma))
+        self.sigma = float(sigma)
+
+    def close(self):
+        if self._b:
+            for m in self.members:
+                m.close()
+            lib().dm_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self):
+        st = BatchStats()
+        _check(lib().dm_batch_info(self._b, ctypes.byref(st)))
+        return dict(count=st.count, threads_per_block=st.threads_per_block, tuned_ms=list(st.tuned_ms),
+                    launches_per_vcycle=st.launches_per_vcycle, cells=st.cells, active_faces=st.active_faces)
+
+    def vcycle(self, fs, xs, stream=None):
+        n = len(self.members)
+        fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        _check(lib().dm_batch_vcycle(self._b, fp, xp, _stream(stream)))
+        return xs
+
+    def time_vcycle(self, reps=10):
+        ms = ctypes.c_double()
+        _check(lib().dm_batch_time_vcycle(self._b, int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def eigs(self, k, sigma=None, tol=1e-10, seed=1301, inner_rtol=1e-11, proj_rtol=1e-13, block=4,
+             max_basis=40, max_restarts=20):
+        L = lib()
+        n = len(self.members)
+        o = EigOptions()
+        L.dm_default_eig_options(ctypes.byref(o))
+        o.solve_mode, o.inner_rtol, o.proj_rtol = SOLVE_FGMRES_MG32, inner_rtol, proj_rtol
+        o.block, o.max_basis, o.max_restarts = block, max_basis, max_restarts
+        lam = np.zeros(n * k)
+        res = np.zeros(n * k)
+        infos = (EigInfo * n)()
+        secs = ctypes.c_double()
+        sig = self.sigma if sigma is None else float(sigma)
+        rc = _check(L.dm_batch_eigs(self._b, int(k), sig, float(tol), ctypes.c_uint64(seed), ctypes.byref(o),
+                                    lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), infos,
+                                    ctypes.byref(secs)), allow_warning=True)
+        self.sigma = sig
+        for m in self.members:
+            m.sigma = sig
+        return dict(status=rc, lam=lam.reshape(n, k), residuals=res.reshape(n, k), seconds=secs.value,
+                    n_converged=[infos[q].n_converged for q in range(n)],
+                    inner_iterations=[infos[q].inner_iterations for q in range(n)],
+                    outer_iterations=[infos[q].outer_iterations for q in range(n)])
