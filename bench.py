@@ -39,6 +39,16 @@ HBM_PEAK_GBS = 8000.0
 #   apply   y = M x      : x(3) coef(7) y(3)            = 13 words
 #   red-black sweep (6 class updates): x(3) f(3) coef(7) read, x(3) written = 16 words
 BYTES_PER_CELL = {"residual": 16 * 4, "apply": 13 * 4, "sweep": 16 * 4}
+# FP32 V-cycle, nu = 2/2: on the fine level 4 sweeps + residual + restriction
+# + prolongation = 4*64 + 64 + 13.5 + 25.5 = 359 B per cell, times 8/7 for
+# the coarser levels
+VCYCLE_BYTES_PER_CELL = 359.0 * 8.0 / 7.0
+# HBM bytes per FP32 sweep on the 128^3 sphere's finest level, from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of `bench.py --only
+# traffic`, each counter scaled by its reading for a 256 MiB copy (reads
+# x2.000, writes x1.000): 231,031 KiB.  Valid for the smoother kernel as of
+# those runs; set to None when k_smooth changes.
+SWEEP_TRAFFIC_BYTES = 231031 * 1024
 
 
 def log(msg):
@@ -53,6 +63,11 @@ def parse():
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the plain FP64 form")
     ap.add_argument("--skip-learned", action="store_true", help="do not train and time the learned form")
     ap.add_argument("--skip-c3", action="store_true", help="do not run the 9-cell quarter cavity")
+    ap.add_argument("--skip-c4", action="store_true", help="do not run the 64 batched ellipsoids")
+    ap.add_argument("--only", choices=["c3", "c4", "traffic"], default=None,
+                    help="profiling runs: only the 9-cell cavity, only the batch, or the HBM-traffic "
+                         "probe (a 256 MiB device copy of known size, then 3 FP32 red-black sweeps "
+                         "on the 128^3 sphere's finest level)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
@@ -113,6 +128,41 @@ def run_c3(dm, torch):
         op.close()
 
 
+def run_c4(dm, torch):
+    """Secondary figures on 64 batched ellipsoidal cavities: semi-axes uniform
+    in [0.3, 0.48] (NumPy generator, seed 0), centred in the unit cube, grids
+    N^3 with N drawn from {32, 48, 64, 80, 96} by the same generator, h = 1/N,
+    sigma = 5, the 4 lowest modes of every cavity to rho <= 1e-10; every FP32
+    preconditioner application of all running members is one fused V-cycle."""
+    import numpy as np
+    rng = np.random.default_rng(0)
+    semis = [tuple(float(a) for a in rng.uniform(0.3, 0.48, 3)) for _ in range(64)]
+    ns = [int(n) for n in rng.choice([32, 48, 64, 80, 96], 64)]
+    t0 = time.perf_counter()
+    b = dm.Batch([dm.ellipsoid((0.5, 0.5, 0.5), s) for s in semis], [(n, n, n) for n in ns],
+                 [1.0 / n for n in ns], 5.0)
+    setup = time.perf_counter() - t0
+    try:
+        st = b.stats()
+        fused_ms = b.time_vcycle(reps=10)
+        solo_ms = sum(m.time_kernel(dm.KERNEL_VCYCLE, prec=32, level=0, reps=3) for m in b.members)
+        out = b.eigs(4, sigma=5.0, tol=TOL, seed=SEED)
+        vbytes = VCYCLE_BYTES_PER_CELL * st["cells"]
+        return {"cavities": 64, "grids": {str(n): ns.count(n) for n in (32, 48, 64, 80, 96)},
+                "cells": st["cells"], "active_faces": st["active_faces"], "setup_s": round(setup, 2),
+                "status": out["status"], "seconds": out["seconds"],
+                "s_per_eigenpair": out["seconds"] / (64 * 4),
+                "max_residual": float(np.max(out["residuals"])),
+                "inner_iterations_total": int(sum(out["inner_iterations"])),
+                "fused_vcycle_ms": fused_ms, "sum_of_solo_vcycle_ms": solo_ms,
+                "fused_vcycle_GBps": round(vbytes / (fused_ms * 1e-3) / 1e9, 1),
+                "autotuner": {"threads_per_block": st["threads_per_block"],
+                              "ms_at_64_128_256": [round(x, 4) for x in st["tuned_ms"]],
+                              "launches_per_vcycle": st["launches_per_vcycle"]}}
+    finally:
+        b.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,6 +175,26 @@ def main():
     from paper_1301_3794_amd import dm
 
     torch.cuda.set_device(0)
+    if args.only == "c3":
+        print(json.dumps({"c3_9cell_quarter": run_c3(dm, torch)}))
+        return
+    if args.only == "c4":
+        print(json.dumps({"c4_batched_ellipsoids": run_c4(dm, torch)}))
+        return
+    if args.only == "traffic":
+        # calibration: the counters of a plain copy of known size
+        n = 64 * 1024 * 1024
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        op = dm.Operator(dm.sphere((0.5, 0.5, 0.5), R), (N, N, N), 1.0 / N, SIGMA, levels=LEVELS)
+        ms = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=3)
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "sweep_ms": ms, "sweep_launches": 2 + 3,
+                          "classes_per_sweep": 6, "cells": N ** 3}))
+        op.close()
+        return
     t0 = time.perf_counter()
     op = dm.Operator(dm.sphere((0.5, 0.5, 0.5), R), (N, N, N), 1.0 / N, SIGMA, levels=LEVELS)
     setup_s = time.perf_counter() - t0
@@ -202,7 +272,7 @@ def main():
     ms_res = op.time_kernel(dm.KERNEL_RESIDUAL, prec=32, level=0, reps=50)
     roofline = {"bound": "hbm", "kernel": "red-black sweep (6 class updates), FP32, 128^3",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": SWEEP_TRAFFIC_BYTES,
                 "ms_per_launch": ms_sweep, "bytes_per_launch": BYTES_PER_CELL["sweep"] * cells,
                 "vcycle_ms": ms_vc, "residual_ms": ms_res,
                 "residual_GBps": BYTES_PER_CELL["residual"] * cells / (ms_res * 1e-3) / 1e9}
@@ -211,6 +281,11 @@ def main():
     if not args.skip_c3:
         log("9-cell quarter cavity")
         c3 = run_c3(dm, torch)
+
+    c4 = None
+    if not args.skip_c4:
+        log("64 batched ellipsoids")
+        c4 = run_c4(dm, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -236,6 +311,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "c3_9cell_quarter": c3,
+        "c4_batched_ellipsoids": c4,
     }
     print(json.dumps(line))
     op.close()
