@@ -606,7 +606,10 @@ k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restri
 // One read of the basis (held in registers) serves the update and the dots.
 constexpr int kFuseMax = 32;
 
-template <int VEC, int MAXV>
+// REREAD: the basis values are loaded a second time for the dot products
+// instead of being held in registers (more vectors than registers allow; the
+// second load comes from cache, the basis still crosses HBM once)
+template <int VEC, int MAXV, bool REREAD>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
                   double *__restrict__ w, int64_t n, double *__restrict__ part) {
@@ -620,18 +623,28 @@ k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double
     const int64_t nvec = n / VEC, ldv = ld / VEC;
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
          e += (int64_t)gridDim.x * kThreads) {
-        typename O::T vv[MAXV];
         typename O::T s = O::ld(w, e);
+        if (REREAD) {
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q)
-            if (q < nv) {
-                vv[q] = O::ld(V + (int64_t)q * ldv * VEC, e);
-                s = O::fma(-cs[q], vv[q], s);
-            }
-        O::st(w, e, s);
+            for (int q = 0; q < MAXV; ++q)
+                if (q < nv) s = O::fma(-cs[q], O::ld(V + (int64_t)q * ldv * VEC, e), s);
+            O::st(w, e, s);
 #pragma unroll
-        for (int q = 0; q < MAXV; ++q)
-            if (q < nv) acc[q] += O::dot(vv[q], s);
+            for (int q = 0; q < MAXV; ++q)
+                if (q < nv) acc[q] += O::dot(O::ld(V + (int64_t)q * ldv * VEC, e), s);
+        } else {
+            typename O::T vv[REREAD ? 1 : MAXV];
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q)
+                if (q < nv) {
+                    vv[q] = O::ld(V + (int64_t)q * ldv * VEC, e);
+                    s = O::fma(-cs[q], vv[q], s);
+                }
+            O::st(w, e, s);
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q)
+                if (q < nv) acc[q] += O::dot(vv[q], s);
+        }
         acc[MAXV] += O::dot(s, s);
     }
     if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -963,11 +976,14 @@ void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c
     const bool v2 = vec2_ok(n, ld, {V, w});
     const dim3 g(kReduceBlocks), b(kThreads);
     if (nv <= 8) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8>), g, b, 0, s, nv, V, ld, c, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
     } else if (nv <= 16) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16>), g, b, 0, s, nv, V, ld, c, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
+    } else if (nv <= 32) {
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 32, true>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 32, true>), g, b, 0, s, nv, V, ld, c, w, n, part);
     } else {
         // too many vectors to hold in registers: update w, then a second
         // pass for the dots (the basis is read twice)
