@@ -164,3 +164,23 @@ def test_faces_of_empty_cells_are_dropped():
     assert np.argwhere(out["ay"] == 0).tolist() == [[1, 2, 3], [1, 3, 3]]
     assert np.argwhere(out["az"] == 0).tolist() == [[1, 2, 3], [2, 2, 3]]
     assert out["v"] is fr["v"]
+
+
+@pytest.mark.parametrize("body", ["sphere", "bor"])
+def test_window_origin_reproduces_the_full_grid(body):
+    """fractions(..., origin=o) of a window equal the full grid's fractions
+    on the window's interior (its own boundary is a wall), entry for entry."""
+    if body == "sphere":
+        g, n, h = geo.sphere((0.5, 0.5, 0.5), 0.45), (16, 16, 16), 1.0 / 16
+    else:
+        g, n, h = geo.EllipticCells((0.5, 0.5), 0.03, 2, 0.4, 0.18, 0.5, 0.2), (16, 16, 20), 1.0 / 16
+    o, w = (0, 5, 3), (6, 7, 8)     # a window across the cut surface
+    full = geo.fractions(g, n, h, drop_empty=False)
+    win = geo.fractions(g, w, h, drop_empty=False, origin=o)
+    cut = 0
+    for name in ("ax", "ay", "az", "lx", "ly", "lz", "v"):
+        a = full[name][o[2] + 1:o[2] + w[2], o[1] + 1:o[1] + w[1], o[0] + 1:o[0] + w[0]]
+        b = win[name][1:w[2], 1:w[1], 1:w[0]]
+        assert np.array_equal(a, b), name
+        cut += int(np.sum((a > 0) & (a < 1)))
+    assert cut > 20
