@@ -167,7 +167,9 @@ int dm_get_fractions(const dm_op *op, int level, double *out_host);
 int dm_apply(dm_op *op, int which, int prec, int level, const void *x_dev,
              void *y_dev, void *stream);
 
-/* r = f - M x on `level` (prec 64 or 32). */
+/* r = f - M x on `level` (prec 64 or 32).  M acts on the active faces only:
+ * rows of inactive faces (zero area fraction, ghosts) are written as zero,
+ * whatever f holds there. */
 int dm_residual(dm_op *op, int prec, int level, const void *f_dev,
                 const void *x_dev, void *r_dev, void *stream);
 

@@ -223,6 +223,7 @@ int dm_build_operator(const dm_geometry *geom, const int dims[3], double h, doub
         DM_HIP(hipGetDevice(&op->device));
         DM_HIP(hipStreamCreate(&op->stream));
         build_hierarchy(op, geom->user_fractions_host);
+        if (op->lv[0].n_act_faces == 0) return fail(DM_EINVAL, "the geometry leaves no active face on this grid");
         factor_coarse(op);
         DM_HIP(hipStreamSynchronize(op->stream));
         return DM_OK;

@@ -1,0 +1,214 @@
+"""Parity at the full sizes the benchmark runs, on sampled rows.
+
+The library builds the whole operator (128^3 sphere; 96 x 96 x 1024 quarter
+9-cell cavity, 6 levels) exactly as ``bench.py`` does and applies M (FP64 and
+FP32) and the residual to one seeded random vector.  Sampled 7^3-cell
+windows (on the cut surface, where the coefficients are not those of vacuum,
+in the interior and at random) are checked in two parts:
+  * geometry: the oracle's fractions of the window (a small grid whose cells
+    carry the full grid's coordinates) equal the library's full-grid
+    fractions there to 1e-12;
+  * stencil: the oracle's sparse M, built from the library's fractions of the
+    window, times the window's part of the vector, equals the library's
+    output on the window's interior faces (whose stencils lie inside the
+    window): FP64 1e-12, FP32 2e-5, relative to the largest sampled row.
+(Comparing rows built from two independently computed fraction sets mixes
+the two: a 1e-13 difference in a small cell's volume is amplified by 1/v.
+Shifting the body instead of the cells changes the rounding of the
+coordinates, which moves a fraction by ~1e-12 where r'(z) is large.)
+
+A property at full size: the FP64 V-cycle operator is symmetric,
+<u, B v> = <v, B u> to 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import geometry as geo, operators as ops
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W = 7           # window cells per side
+LO, HI = 2, W - 3   # interior cells of a window whose rows are compared
+
+
+SHAPES = {"ax": (W, W, W + 1), "ay": (W, W + 1, W), "az": (W + 1, W, W),
+          "lx": (W + 1, W + 1, W), "ly": (W + 1, W, W + 1), "lz": (W, W + 1, W + 1), "v": (W, W, W)}
+NAMES = ("ax", "ay", "az", "lx", "ly", "lz", "v")
+
+
+def lib_window_fractions(frac7, n_full, origin):
+    """The library's fractions (7 padded blocks) on a window, oracle shapes."""
+    nx, ny, nz = n_full
+    b = np.asarray(frac7).reshape(7, nz + 2, ny + 2, nx + 2)
+    i0, j0, k0 = origin
+    out = {}
+    for q, name in enumerate(NAMES):
+        sz, sy, sx = SHAPES[name]
+        out[name] = b[q, k0 + 1:k0 + 1 + sz, j0 + 1:j0 + 1 + sy, i0 + 1:i0 + 1 + sx].copy()
+    return out
+
+
+def window_rows(fr, h, sigma, x_full, n_full, origin):
+    """Oracle rows M x on the window's interior faces for window fractions fr,
+    from the global vector x_full (3 padded blocks of the full grid)."""
+    o = ops.build(fr, (W, W, W), h, sigma)
+    nx, ny, nz = n_full
+    xb = np.asarray(x_full).reshape(3, nz + 2, ny + 2, nx + 2)
+    i0, j0, k0 = origin
+    fam = {}
+    for c, name in enumerate(("ax", "ay", "az")):
+        sz, sy, sx = SHAPES[name]
+        fam[name] = xb[c, k0 + 1:k0 + 1 + sz, j0 + 1:j0 + 1 + sy, i0 + 1:i0 + 1 + sx].copy()
+    y = o.grid.split_faces(o.M @ o.grid.face_vector(fam))
+    return [blk[LO:HI + 1, LO:HI + 1, LO:HI + 1] for blk in y]
+
+
+def lib_rows(y_full, n_full, origin):
+    nx, ny, nz = n_full
+    yb = np.asarray(y_full).reshape(3, nz + 2, ny + 2, nx + 2)
+    i0, j0, k0 = origin
+    return [yb[c, k0 + 1 + LO:k0 + 2 + HI, j0 + 1 + LO:j0 + 2 + HI, i0 + 1 + LO:i0 + 2 + HI] for c in range(3)]
+
+
+def compare(windows, frac7, h, sigma, x, y, n):
+    """Relative max difference of the library's rows from the oracle's rows
+    (built from the library's window fractions)."""
+    worst, scale = 0.0, 0.0
+    for o in windows:
+        ref = window_rows(lib_window_fractions(frac7, n, o), h, sigma, x, n, o)
+        got = lib_rows(y, n, o)
+        for a, b in zip(got, ref):
+            worst = max(worst, float(np.max(abs(a - b))))
+            scale = max(scale, float(np.max(abs(b))))
+    assert scale > 0
+    return worst / scale
+
+
+def fraction_gap(windows, geom, frac7, h, n):
+    """Max |oracle - library| over the fractions of the windows' interior
+    (the window's own wall entities are zero by the oracle's convention)."""
+    worst = 0.0
+    for o in windows:
+        ref = geo.fractions(geom, (W, W, W), h, origin=o)
+        got = lib_window_fractions(frac7, n, o)
+        for name in NAMES:
+            sl = (slice(1, -1),) * 3
+            worst = max(worst, float(np.max(abs(ref[name][sl] - got[name][sl]))))
+    return worst
+
+
+def random_vector(P, seed):
+    v = np.random.default_rng(seed).standard_normal(3 * P)
+    return v
+
+
+def surface_windows(n, centre, radius, h, count, seed):
+    """Window origins whose centre cell is cut by a sphere (or a random cell)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        p = np.asarray(centre) + radius * d
+        c = np.floor(p / h).astype(int)
+        o = tuple(int(v) - W // 2 for v in c)
+        if all(0 <= o[a] and o[a] + W <= n[a] for a in range(3)):
+            out.append(o)
+    return out
+
+
+@pytest.fixture(scope="module")
+def sphere128():
+    from paper_1301_3794_amd import dm
+    n, h = (128, 128, 128), 1.0 / 128
+    op = dm.Operator(dm.sphere((0.5, 0.5, 0.5), 0.45), n, h, 36.0, levels=5)
+    P = op.layout(0)["P"]
+    x = random_vector(P, 11)
+    print("[case] full-size sphere 128^3", flush=True)
+    yield dm, op, n, h, x
+    op.close()
+
+
+def test_sphere128_apply_rows(sphere128):
+    dm, op, n, h, x = sphere128
+    xt = torch.tensor(x, device="cuda")
+    y64 = op.apply(dm.APPLY_M, xt, op.face_tensor()).cpu().numpy()
+    y32 = op.apply(dm.APPLY_M, xt.float(), op.face_tensor(dtype=torch.float32)).double().cpu().numpy()
+    wins = surface_windows(n, (0.5, 0.5, 0.5), 0.45, h, 10, 1) + [(60, 60, 60), (20, 90, 50)]
+
+    fr7 = op.fractions(0)
+    assert fraction_gap(wins, geo.sphere((0.5, 0.5, 0.5), 0.45), fr7, h, n) <= 1e-12
+    assert compare(wins, fr7, h, 36.0, x, y64, n) <= 1e-12
+    x32 = np.asarray(xt.float().double().cpu().numpy())
+    assert compare(wins, fr7, h, 36.0, x32, y32, n) <= 2e-5
+
+
+def test_sphere128_residual_rows(sphere128):
+    dm, op, n, h, x = sphere128
+    P = op.layout(0)["P"]
+    # the residual is that of the active faces: f is zero elsewhere
+    fr7 = op.fractions(0)
+    f = random_vector(P, 12) * (fr7[:3].reshape(-1) > 0)
+    r = op.residual(torch.tensor(f, device="cuda"), torch.tensor(x, device="cuda"), op.face_tensor()).cpu().numpy()
+    wins = surface_windows(n, (0.5, 0.5, 0.5), 0.45, h, 6, 2)
+    # r = f - M x  <=>  f - r = M x on the sampled rows
+    fm = np.asarray(f) - r
+    assert compare(wins, fr7, h, 36.0, x, fm, n) <= 1e-12
+
+
+def test_sphere128_vcycle_symmetric(sphere128):
+    dm, op, n, h, _ = sphere128
+    P = op.layout(0)["P"]
+    a = op.apply(dm.APPLY_A, torch.randn(3 * P, dtype=torch.float64, generator=torch.Generator().manual_seed(3)).cuda(),
+                 op.face_tensor())
+    b = op.apply(dm.APPLY_A, torch.randn(3 * P, dtype=torch.float64, generator=torch.Generator().manual_seed(4)).cuda(),
+                 op.face_tensor())
+    Ba = op.vcycle(a, op.face_tensor())
+    Bb = op.vcycle(b, op.face_tensor())
+    u, v = float(torch.dot(b, Ba)), float(torch.dot(a, Bb))
+    assert abs(u - v) <= 1e-12 * max(abs(u), abs(v))
+
+
+@pytest.fixture(scope="module")
+def ninecell():
+    from paper_1301_3794_amd import dm
+    n, h = (96, 96, 1024), 1.235 / 1024
+    geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
+                           bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
+    op = dm.Operator(geom, n, h, 632.0, levels=0)
+    P = op.layout(0)["P"]
+    x = random_vector(P, 21)
+    print("[case] full-size 9-cell quarter 96x96x1024", op.layout(0), flush=True)
+    yield dm, op, n, h, x
+    op.close()
+
+
+def test_ninecell_apply_rows(ninecell):
+    dm, op, n, h, x = ninecell
+    # the stencil reads the PMC ghost layer: give x the mirror images it would hold
+    xt = torch.tensor(x, device="cuda")
+    y = op.apply(dm.APPLY_M, xt, op.face_tensor()).cpu().numpy()
+    g = geo.nine_cell()
+    # windows away from the PMC planes (x, y >= 2): an iris, an equator, a tube
+    # end plate, a cell wall and the tube; each centred on the cut surface
+    zs = [0.1 + 0.115 * 3, 0.1 + 0.115 * 4.5, 0.1, 0.1 + 0.115 * 6.3, 0.05, 1.235 - 0.002]
+    wins = []
+    for z in zs:
+        r = g.radius(z)
+        k = int(z / h)
+        i = int(r / np.sqrt(2) / h)
+        o = (max(2, i - W // 2), max(2, i - W // 2), min(max(0, k - W // 2), n[2] - W))
+        wins.append(o)
+
+    fr7 = op.fractions(0)
+    assert fraction_gap(wins, g, fr7, h, n) <= 1e-12
+    assert compare(wins, fr7, h, 632.0, x, y, n) <= 1e-12
+
+
+def test_empty_geometry_is_rejected():
+    """Degenerate input: a cavity smaller than a cell leaves no active face."""
+    from paper_1301_3794_amd import dm
+    with pytest.raises(dm.DMError) as e:
+        dm.Operator(dm.ellipsoid((0.53, 0.51, 0.52), (0.004, 0.004, 0.004)), (16, 16, 16), 1.0 / 16, 5.0)
+    assert e.value.code == dm.DM_EINVAL
