@@ -199,6 +199,15 @@ int dm_prolong_add(dm_op *op, int prec, int level, const void *x_coarse_dev,
  * re-recorded after dm_set_shift. */
 int dm_vcycle(dm_op *op, int prec, const void *f_dev, void *x_dev, void *stream);
 
+/* The same V-cycle on nrhs (1..4) vectors at once (Sec. 6: the block
+ * eigensolver's inversions of one outer step share M).  Each launch serves
+ * every vector, so each coefficient is read once per block; the values are
+ * those of nrhs calls of dm_vcycle.  f_dev, x_dev: host arrays of nrhs
+ * device pointers (face vectors of level 0, FP64 for prec 64, FP32 for 32).
+ * A graph per (prec, nrhs) is recorded on first use. */
+int dm_vcycle_block(dm_op *op, int prec, int nrhs, const void *const *f_dev, void *const *x_dev,
+                    void *stream);
+
 /* Divergence projection b_out = P_DM b (eq. proj); the scalar system
  * D A D^T psi = D A b is solved by CG preconditioned with a cell-centred
  * multigrid V-cycle until ||D A D^T psi - D A b||_2 <= rtol ||b||_A / h, a
@@ -266,6 +275,18 @@ typedef struct {
  *   vecs_dev     NULL or k face vectors (k * 3P doubles), A-orthonormal.
  *   residuals_host  NULL or k doubles (rho of each pair).
  * Returns DM_NOT_CONVERGED with info->n_converged if max_restarts is hit. */
+/* nrhs (1..4) solves M x_r = f_r at once (the inversions of one block step
+ * of the eigensolver, Sec. 4.3): each system runs its own FGMRES exactly as
+ * dm_solve does, in lockstep, with the preconditioner applications of a step
+ * done as one block V-cycle (dm_vcycle_block) and the products M z as one
+ * block apply.  mode: an FGMRES mode (PCG64 is refused).  f_dev, x_dev: host
+ * arrays of nrhs device pointers (FP64 face vectors); info: nrhs entries or
+ * NULL (seconds and learned counts are those of the whole call).  Returns
+ * DM_NOT_CONVERGED if any system did not reach rtol.  dm_eigs uses this path
+ * for its blocks unless the op is a batch member or the mode is PCG64. */
+int dm_solve_block(dm_op *op, int mode, int nrhs, const double *const *f_dev, double *const *x_dev,
+                   double rtol, int maxit, dm_solve_info *info, void *stream);
+
 int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed,
             const dm_eig_options *opt, double *lambda_host, double *vecs_dev,
             double *residuals_host, dm_eig_info *info, void *stream);

@@ -211,7 +211,7 @@ void batch_setup(dm_batch *b) {
         if (op->lv[0].g.pmc) throw DmError{DM_EINVAL, "batched cavities without PMC planes only"};
         if (op->opt.nu_pre != b->ops[0]->opt.nu_pre || op->opt.nu_post != b->ops[0]->opt.nu_post)
             throw DmError{DM_EINVAL, "batch members need the same smoothing counts"};
-        ensure_krylov(op);   // fg_f32 / fg_x32: the fused V-cycle's level-0 buffers
+        ensure_krylov_small(op);   // fg_f32 / fg_x32: the fused V-cycle's level-0 buffers
     }
     DM_HIP(hipDeviceSynchronize());
     if (b->graph) (void)hipGraphExecDestroy(b->graph);

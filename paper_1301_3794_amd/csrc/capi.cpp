@@ -125,6 +125,7 @@ static void free_op(dm_op *op) {
     if (op->stream) hipStreamSynchronize(op->stream);
     for (void *p : op->allocs) hipFree(p);
     if (op->hres) hipHostFree(op->hres);
+    if (op->bk_hres) hipHostFree(op->bk_hres);
     if (op->stream) hipStreamDestroy(op->stream);
     delete op;
 }
@@ -386,7 +387,7 @@ int dm_vcycle(dm_op *op, int prec, const void *f, void *x, void *stream) {
     return on_device(op, stream, [&](hipStream_t s) -> int {
         fill_ghosts(op->lv[0], prec, f, false, s);
         // through the solver's captured V-cycle graph, between its fixed buffers
-        ensure_krylov(op);
+        ensure_krylov_small(op);
         const int64_t n = op->n0();
         const size_t bytes = n * (prec == 64 ? sizeof(double) : sizeof(float));
         void *fin = prec == 64 ? (void *)op->gv_f64 : (void *)op->fg_f32;
@@ -394,6 +395,29 @@ int dm_vcycle(dm_op *op, int prec, const void *f, void *x, void *stream) {
         DM_HIP(hipMemcpyAsync(fin, f, bytes, hipMemcpyDeviceToDevice, s));
         vcycle_graphed(op, prec, s);
         DM_HIP(hipMemcpyAsync(x, xout, bytes, hipMemcpyDeviceToDevice, s));
+        return DM_OK;
+    });
+}
+
+int dm_vcycle_block(dm_op *op, int prec, int nrhs, const void *const *f, void *const *x, void *stream) {
+    if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
+    if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(DM_EINVAL, "nrhs must be 1..4");
+    for (int q = 0; q < nrhs; ++q)
+        if (!f[q] || !x[q]) return fail(DM_EINVAL, "NULL vector in the block");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        ensure_block(op, prec);
+        const int64_t n = op->n0();
+        const size_t es = prec == 64 ? sizeof(double) : sizeof(float);
+        char *fin = prec == 64 ? (char *)op->lv[0].bf64 : (char *)op->lv[0].bf32;
+        char *xout = prec == 64 ? (char *)op->lv[0].bx64 : (char *)op->lv[0].bx32;
+        for (int q = 0; q < nrhs; ++q) {
+            fill_ghosts(op->lv[0], prec, f[q], false, s);
+            DM_HIP(hipMemcpyAsync(fin + q * n * es, f[q], n * es, hipMemcpyDeviceToDevice, s));
+        }
+        vcycle_block_graphed(op, prec, nrhs, s);
+        for (int q = 0; q < nrhs; ++q)
+            DM_HIP(hipMemcpyAsync(x[q], xout + q * n * es, n * es, hipMemcpyDeviceToDevice, s));
         return DM_OK;
     });
 }
@@ -417,6 +441,23 @@ int dm_solve(dm_op *op, int mode, const double *f, double *x, double rtol, int m
     return on_device(op, stream, [&](hipStream_t s) -> int {
         fill_ghosts(op->lv[0], 64, f, false, s);
         return solve(op, mode, f, x, rtol, maxit, info, s);
+    });
+}
+
+int dm_solve_block(dm_op *op, int mode, int nrhs, const double *const *f, double *const *x, double rtol,
+                   int maxit, dm_solve_info *info, void *stream) {
+    if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(DM_EINVAL, "nrhs must be 1..4");
+    if (mode < DM_SOLVE_FGMRES_MG64 || mode > DM_SOLVE_FGMRES_MG32_LEARNED)
+        return fail(DM_EINVAL, "block solves take the FGMRES modes");
+    if (mode == DM_SOLVE_FGMRES_MG32_LEARNED && !op->net)
+        return fail(DM_EINVAL, "learned solve mode without an attached network");
+    if (!(rtol > 0.0) || maxit < 1) return fail(DM_EINVAL, "rtol must be positive and maxit >= 1");
+    for (int q = 0; q < nrhs; ++q)
+        if (!f[q] || !x[q]) return fail(DM_EINVAL, "NULL vector in the block");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        for (int q = 0; q < nrhs; ++q) fill_ghosts(op->lv[0], 64, f[q], false, s);
+        return solve_block(op, mode, nrhs, f, x, rtol, maxit, info, s);
     });
 }
 

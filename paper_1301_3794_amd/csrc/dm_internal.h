@@ -263,6 +263,44 @@ void launch_batched(int step, int comp, int colour, const BJob *jobs, int njobs,
 // ---------------------------------------------------------------------------
 enum ApplyKind { AK_M = 0, AK_K = 1, AK_RESID = 2 };
 
+// Block solves: up to kMaxRhs vectors of one level, passed by value as an
+// array of device pointers (any subset of a block, no stride assumed).
+constexpr int kMaxRhs = 4;
+template <class T>
+struct VPtr {
+    T *p[kMaxRhs];
+};
+template <class T>
+__host__ __device__ inline VPtr<T> vptr1(T *x) {
+    VPtr<T> v{};
+    v.p[0] = x;
+    return v;
+}
+template <class T>
+__host__ __device__ inline VPtr<const T> as_const(const VPtr<T> &x) {
+    VPtr<const T> v{};
+    for (int q = 0; q < kMaxRhs; ++q) v.p[q] = x.p[q];
+    return v;
+}
+
+// the block forms of the V-cycle's kernels: nr (1..kMaxRhs) vectors per
+// launch, each coefficient loaded once for all of them
+template <class T>
+void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, const VPtr<const T> &f,
+                    const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s);
+template <class T>
+void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour, int nr, const VPtr<const T> &f,
+                     const VPtr<T> &x, hipStream_t s);
+template <class T>
+void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
+                       const VPtr<T> &fc, hipStream_t s);
+template <class T>
+void launch_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, int nr,
+                          const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s);
+template <class T>
+void launch_coarse_solve_b(int n, const double *inv, const int64_t *idx, int nr, const VPtr<const T> &f,
+                           const VPtr<T> &x, hipStream_t s);
+
 template <class T>
 void launch_apply(const Grid &g, const T *coef, T sigma, int kind, const T *f, const T *x, T *y,
                   hipStream_t s);

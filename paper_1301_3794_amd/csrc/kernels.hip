@@ -59,41 +59,56 @@ __device__ inline T vac_row(const T *C, int64_t p, int64_t dy, int64_t dz) {
     return T(6) * C[p] - (C[p - 1] + C[p + 1]) - (C[p - dy] + C[p + dy]) - (C[p - dz] + C[p + dz]);
 }
 
-template <class T, int KIND>
-__device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T sigma, const T *__restrict__ f,
-                                           const T *__restrict__ x, T *__restrict__ y, int64_t item) {
+// NR right-hand sides at once (block solves): the coefficients of a row are
+// loaded once and serve every vector; all rows are formed before any store.
+template <class T, int KIND, int NR>
+__device__ __forceinline__ void apply_body_n(const Grid &g, const Coefs<T> &c, T sigma, const VPtr<const T> &f,
+                                             const VPtr<const T> &x, const VPtr<T> &y, int64_t item) {
     int i, j, k;
     if (!cell_of(g, item, i, j, k)) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
     const int64_t p = pidx(g, i, j, k);
-    const T *X = x, *Y = x + P, *Z = x + 2 * P;
     const T ih2 = inv_h2_of<T>(g);
     const uint8_t fl = c.flags[p];
-    T yx = T(0), yy = T(0), yz = T(0);
-    if (KIND == AK_K) {
-        if (fl & (kFaceActive << 0)) yx = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
-        if (fl & (kFaceActive << 1)) yy = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
-        if (fl & (kFaceActive << 2)) yz = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
-    } else {
-        if (fl & (kFaceActive << 0)) {
-            yx = (fl & (kFaceVacuum << 0)) ? ih2 * vac_row(X, p, dy, dz) - sigma * X[p]
-                                           : ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
-            if (KIND == AK_RESID) yx = f[p] - yx;
-        }
-        if (fl & (kFaceActive << 1)) {
-            yy = (fl & (kFaceVacuum << 1)) ? ih2 * vac_row(Y, p, dy, dz) - sigma * Y[p]
-                                           : ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
-            if (KIND == AK_RESID) yy = f[P + p] - yy;
-        }
-        if (fl & (kFaceActive << 2)) {
-            yz = (fl & (kFaceVacuum << 2)) ? ih2 * vac_row(Z, p, dy, dz) - sigma * Z[p]
-                                           : ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
-            if (KIND == AK_RESID) yz = f[2 * P + p] - yz;
+    T yx[NR], yy[NR], yz[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const T *X = x.p[q], *Y = X + P, *Z = X + 2 * P;
+        yx[q] = T(0), yy[q] = T(0), yz[q] = T(0);
+        if (KIND == AK_K) {
+            if (fl & (kFaceActive << 0)) yx[q] = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
+            if (fl & (kFaceActive << 1)) yy[q] = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
+            if (fl & (kFaceActive << 2)) yz[q] = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
+        } else {
+            if (fl & (kFaceActive << 0)) {
+                yx[q] = (fl & (kFaceVacuum << 0)) ? ih2 * vac_row(X, p, dy, dz) - sigma * X[p]
+                                                  : ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
+                if (KIND == AK_RESID) yx[q] = f.p[q][p] - yx[q];
+            }
+            if (fl & (kFaceActive << 1)) {
+                yy[q] = (fl & (kFaceVacuum << 1)) ? ih2 * vac_row(Y, p, dy, dz) - sigma * Y[p]
+                                                  : ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
+                if (KIND == AK_RESID) yy[q] = f.p[q][P + p] - yy[q];
+            }
+            if (fl & (kFaceActive << 2)) {
+                yz[q] = (fl & (kFaceVacuum << 2)) ? ih2 * vac_row(Z, p, dy, dz) - sigma * Z[p]
+                                                  : ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
+                if (KIND == AK_RESID) yz[q] = f.p[q][2 * P + p] - yz[q];
+            }
         }
     }
-    put_face<T>(g, y, 0, i, j, k, p, yx);
-    put_face<T>(g, y + P, 1, i, j, k, p, yy);
-    put_face<T>(g, y + 2 * P, 2, i, j, k, p, yz);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        put_face<T>(g, y.p[q], 0, i, j, k, p, yx[q]);
+        put_face<T>(g, y.p[q] + P, 1, i, j, k, p, yy[q]);
+        put_face<T>(g, y.p[q] + 2 * P, 2, i, j, k, p, yz[q]);
+    }
+}
+
+template <class T, int KIND>
+__device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T sigma, const T *__restrict__ f,
+                                           const T *__restrict__ x, T *__restrict__ y, int64_t item) {
+    apply_body_n<T, KIND, 1>(g, c, sigma, vptr1(f), vptr1(x), vptr1(y), item);
 }
 
 template <class T, int KIND>
@@ -101,6 +116,12 @@ __global__ void __launch_bounds__(kThreads)
 k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restrict__ x,
         T *__restrict__ y) {
     apply_body<T, KIND>(g, c, sigma, f, x, y, xcd_item());
+}
+
+template <class T, int KIND, int NR>
+__global__ void __launch_bounds__(kThreads)
+k_apply_b(Grid g, Coefs<T> c, T sigma, VPtr<const T> f, VPtr<const T> x, VPtr<T> y) {
+    apply_body_n<T, KIND, NR>(g, c, sigma, f, x, y, xcd_item());
 }
 
 // y = A x
@@ -121,9 +142,9 @@ k_apply_A(Grid g, Coefs<T> c, const T *__restrict__ x, T *__restrict__ y) {
 // A thread also refreshes the PMC ghost images of the value it updates; no
 // row of the same class reads those images except its own.
 // ---------------------------------------------------------------------------
-template <class T, int COMP>
-__device__ __forceinline__ void smooth_body(const Grid &g, const Coefs<T> &c, T sigma, int colour,
-                                            const T *__restrict__ f, T *__restrict__ x, int64_t t) {
+template <class T, int COMP, int NR>
+__device__ __forceinline__ void smooth_body_n(const Grid &g, const Coefs<T> &c, T sigma, int colour,
+                                              const VPtr<const T> &f, const VPtr<T> &x, int64_t t) {
     const int nxh = (g.nx + 1) >> 1;
     if (t >= (int64_t)nxh * g.ny * g.nz) return;
     const int ih = (int)(t % nxh);
@@ -133,27 +154,43 @@ __device__ __forceinline__ void smooth_body(const Grid &g, const Coefs<T> &c, T 
     if (i >= g.nx) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
     const int64_t p = pidx(g, i, j, k);
-    T *X = x, *Y = x + P, *Z = x + 2 * P;
     const T ih2 = inv_h2_of<T>(g);
-    T *xc = COMP == 0 ? X : (COMP == 1 ? Y : Z);
     const uint8_t fl = c.flags[p];
     if (!(fl & (kFaceActive << COMP))) return;
+    T nv[NR];
     if (fl & (kFaceVacuum << COMP)) {
-        const T xp = xc[p];
-        const T row = ih2 * vac_row<T>(xc, p, dy, dz) - sigma * xp;
         const T d = T(6) * ih2 - sigma;
-        put_face<T>(g, xc, COMP, i, j, k, p, xp + (f[COMP * P + p] - row) / d);
-        return;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const T *xc = x.p[q] + COMP * P;
+            const T xp = xc[p];
+            const T row = ih2 * vac_row<T>(xc, p, dy, dz) - sigma * xp;
+            nv[q] = xp + (f.p[q][COMP * P + p] - row) / d;
+        }
+    } else {
+        const T *a = COMP == 0 ? c.ax : (COMP == 1 ? c.ay : c.az);
+        const T d = diag_of<T>(c, COMP, p, dy, dz, ih2, sigma) +
+                    ih2 * pmc_diag_extra<T>(g, c.lx, c.ly, c.lz, COMP, i, j, k, p);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const T *X = x.p[q], *Y = X + P, *Z = X + 2 * P;
+            const T *xc = COMP == 0 ? X : (COMP == 1 ? Y : Z);
+            T row;
+            if (COMP == 0) row = row_x<T, true>(c, X, Y, Z, p, dy, dz);
+            else if (COMP == 1) row = row_y<T, true>(c, X, Y, Z, p, dy, dz);
+            else row = row_z<T, true>(c, X, Y, Z, p, dy, dz);
+            row = ih2 * row - sigma * a[p] * xc[p];
+            nv[q] = xc[p] + (f.p[q][COMP * P + p] - row) / d;
+        }
     }
-    const T *a = COMP == 0 ? c.ax : (COMP == 1 ? c.ay : c.az);
-    T row;
-    if (COMP == 0) row = row_x<T, true>(c, X, Y, Z, p, dy, dz);
-    else if (COMP == 1) row = row_y<T, true>(c, X, Y, Z, p, dy, dz);
-    else row = row_z<T, true>(c, X, Y, Z, p, dy, dz);
-    row = ih2 * row - sigma * a[p] * xc[p];
-    const T d = diag_of<T>(c, COMP, p, dy, dz, ih2, sigma) +
-                ih2 * pmc_diag_extra<T>(g, c.lx, c.ly, c.lz, COMP, i, j, k, p);
-    put_face<T>(g, xc, COMP, i, j, k, p, xc[p] + (f[COMP * P + p] - row) / d);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
+}
+
+template <class T, int COMP>
+__device__ __forceinline__ void smooth_body(const Grid &g, const Coefs<T> &c, T sigma, int colour,
+                                            const T *__restrict__ f, T *__restrict__ x, int64_t t) {
+    smooth_body_n<T, COMP, 1>(g, c, sigma, colour, vptr1(f), vptr1(x), t);
 }
 
 template <class T, int COMP>
@@ -162,17 +199,22 @@ k_smooth(Grid g, Coefs<T> c, T sigma, int colour, const T *__restrict__ f, T *__
     smooth_body<T, COMP>(g, c, sigma, colour, f, x, xcd_item());
 }
 
+template <class T, int COMP, int NR>
+__global__ void __launch_bounds__(kThreads)
+k_smooth_b(Grid g, Coefs<T> c, T sigma, int colour, VPtr<const T> f, VPtr<T> x) {
+    smooth_body_n<T, COMP, NR>(g, c, sigma, colour, f, x, xcd_item());
+}
+
 // ---------------------------------------------------------------------------
 // Staggered transfers.  P: linear along the normal, constant across; R = P^T/8.
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
-                                              const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
+template <class T, int NR>
+__device__ __forceinline__ void restrict_body_n(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
+                                                const VPtr<const T> &r, const VPtr<T> &fc, int64_t item) {
     int I, J, K;
     if (!cell_of(gc, item, I, J, K)) return;
     const int64_t Pf = gf.P, Pc = gc.P, fy = gf.sy, fz = gf.sz;
     const int64_t pc = pidx(gc, I, J, K);
-    const T *RX = r, *RY = r + Pf, *RZ = r + 2 * Pf;
     const int64_t q = pidx(gf, 2 * I, 2 * J, 2 * K);
     // transpose of the area-weighted normal interpolation: the fine face
     // between coarse faces c and c' gives c the share a_c / (a_c + a_c')
@@ -183,29 +225,45 @@ __device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, co
     const T yp = ay > T(0) ? ay / (ay + cc.ay[pc + gc.sy]) : T(0);
     const T zm = az > T(0) ? az / (az + cc.az[pc - gc.sz]) : T(0);
     const T zp = az > T(0) ? az / (az + cc.az[pc + gc.sz]) : T(0);
-    T sx = 0, sy = 0, sz = 0;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            // x: tangential offsets in y (a) and z (b)
-            const int64_t qx = q + a * fy + b * fz;
-            sx += RX[qx] + xm * RX[qx - 1] + xp * RX[qx + 1];
-            const int64_t qy = q + a + b * fz;
-            sy += RY[qy] + ym * RY[qy - fy] + yp * RY[qy + fy];
-            const int64_t qz = q + a + b * fy;
-            sz += RZ[qz] + zm * RZ[qz - fz] + zp * RZ[qz + fz];
-        }
     const T e = T(0.125);
-    put_face<T>(gc, fc, 0, I, J, K, pc, ax != T(0) ? e * sx : T(0));
-    put_face<T>(gc, fc + Pc, 1, I, J, K, pc, ay != T(0) ? e * sy : T(0));
-    put_face<T>(gc, fc + 2 * Pc, 2, I, J, K, pc, az != T(0) ? e * sz : T(0));
+#pragma unroll
+    for (int v = 0; v < NR; ++v) {
+        const T *RX = r.p[v], *RY = RX + Pf, *RZ = RX + 2 * Pf;
+        T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                // x: tangential offsets in y (a) and z (b)
+                const int64_t qx = q + a * fy + b * fz;
+                sx += RX[qx] + xm * RX[qx - 1] + xp * RX[qx + 1];
+                const int64_t qy = q + a + b * fz;
+                sy += RY[qy] + ym * RY[qy - fy] + yp * RY[qy + fy];
+                const int64_t qz = q + a + b * fy;
+                sz += RZ[qz] + zm * RZ[qz - fz] + zp * RZ[qz + fz];
+            }
+        put_face<T>(gc, fc.p[v], 0, I, J, K, pc, ax != T(0) ? e * sx : T(0));
+        put_face<T>(gc, fc.p[v] + Pc, 1, I, J, K, pc, ay != T(0) ? e * sy : T(0));
+        put_face<T>(gc, fc.p[v] + 2 * Pc, 2, I, J, K, pc, az != T(0) ? e * sz : T(0));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
+                                              const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
+    restrict_body_n<T, 1>(gf, gc, cc, vptr1(r), vptr1(fc), item);
 }
 
 template <class T>
 __global__ void __launch_bounds__(kThreads)
 k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict__ fc) {
     restrict_body<T>(gf, gc, cc, r, fc, xcd_item());
+}
+
+template <class T, int NR>
+__global__ void __launch_bounds__(kThreads)
+k_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc) {
+    restrict_body_n<T, NR>(gf, gc, cc, r, fc, xcd_item());
 }
 
 // fine value between coarse faces c0, c1: (a0 x0 + a1 x1) / (a0 + a1)
@@ -215,24 +273,37 @@ __device__ __forceinline__ T wmean(T a0, T x0, T a1, T x1) {
     return t > T(0) ? (a0 * x0 + a1 * x1) / t : T(0);
 }
 
-template <class T>
-__device__ __forceinline__ void prolong_body(const Grid &gf, const Grid &gc, const Coefs<T> &cf, const Coefs<T> &cc,
-                                             const T *__restrict__ xc, T *__restrict__ x, int64_t item) {
+template <class T, int NR>
+__device__ __forceinline__ void prolong_body_n(const Grid &gf, const Grid &gc, const Coefs<T> &cf,
+                                               const Coefs<T> &cc, const VPtr<const T> &xc, const VPtr<T> &x,
+                                               int64_t item) {
     int i, j, k;
     if (!cell_of(gf, item, i, j, k)) return;
     const int64_t Pf = gf.P, Pc = gc.P, cy = gc.sy, cz = gc.sz;
     const int64_t p = pidx(gf, i, j, k);
     const int64_t q = pidx(gc, i >> 1, j >> 1, k >> 1);
-    const T *CX = xc, *CY = xc + Pc, *CZ = xc + 2 * Pc;
-    if (cf.ax[p] != T(0))
-        put_face<T>(gf, x, 0, i, j, k, p,
-                    x[p] + ((i & 1) ? wmean(cc.ax[q], CX[q], cc.ax[q + 1], CX[q + 1]) : CX[q]));
-    if (cf.ay[p] != T(0))
-        put_face<T>(gf, x + Pf, 1, i, j, k, p,
-                    x[Pf + p] + ((j & 1) ? wmean(cc.ay[q], CY[q], cc.ay[q + cy], CY[q + cy]) : CY[q]));
-    if (cf.az[p] != T(0))
-        put_face<T>(gf, x + 2 * Pf, 2, i, j, k, p,
-                    x[2 * Pf + p] + ((k & 1) ? wmean(cc.az[q], CZ[q], cc.az[q + cz], CZ[q + cz]) : CZ[q]));
+    const bool fx = cf.ax[p] != T(0), fy = cf.ay[p] != T(0), fz = cf.az[p] != T(0);
+    const T ax0 = cc.ax[q], ax1 = cc.ax[q + 1], ay0 = cc.ay[q], ay1 = cc.ay[q + cy];
+    const T az0 = cc.az[q], az1 = cc.az[q + cz];
+#pragma unroll
+    for (int v = 0; v < NR; ++v) {
+        const T *CX = xc.p[v], *CY = CX + Pc, *CZ = CX + 2 * Pc;
+        T *X = x.p[v];
+        if (fx)
+            put_face<T>(gf, X, 0, i, j, k, p, X[p] + ((i & 1) ? wmean(ax0, CX[q], ax1, CX[q + 1]) : CX[q]));
+        if (fy)
+            put_face<T>(gf, X + Pf, 1, i, j, k, p,
+                        X[Pf + p] + ((j & 1) ? wmean(ay0, CY[q], ay1, CY[q + cy]) : CY[q]));
+        if (fz)
+            put_face<T>(gf, X + 2 * Pf, 2, i, j, k, p,
+                        X[2 * Pf + p] + ((k & 1) ? wmean(az0, CZ[q], az1, CZ[q + cz]) : CZ[q]));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void prolong_body(const Grid &gf, const Grid &gc, const Coefs<T> &cf, const Coefs<T> &cc,
+                                             const T *__restrict__ xc, T *__restrict__ x, int64_t item) {
+    prolong_body_n<T, 1>(gf, gc, cf, cc, vptr1(xc), vptr1(x), item);
 }
 
 template <class T>
@@ -240,6 +311,12 @@ __global__ void __launch_bounds__(kThreads)
 k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ xc,
               T *__restrict__ x) {
     prolong_body<T>(gf, gc, cf, cc, xc, x, xcd_item());
+}
+
+template <class T, int NR>
+__global__ void __launch_bounds__(kThreads)
+k_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, VPtr<const T> xc, VPtr<T> x) {
+    prolong_body_n<T, NR>(gf, gc, cf, cc, xc, x, xcd_item());
 }
 
 // x = 0 (a kernel, not a memset: it may be recorded into a HIP graph)
@@ -256,22 +333,41 @@ __global__ void k_cast(const TI *__restrict__ in, TO *__restrict__ out, int64_t 
         out[e] = (TO)in[e];
 }
 
-// Coarsest level: x[idx[r]] = sum_c inv[r, c] f[idx[c]] (FP64 arithmetic)
+// Coarsest level: x[idx[r]] = sum_c inv[r, c] f[idx[c]] (FP64 arithmetic);
+// one row of the inverse serves every right-hand side
+template <class T, int NR>
+__device__ __forceinline__ void coarse_body_n(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx,
+                                              const VPtr<const T> &f, const VPtr<T> &x, int row) {
+    double s[NR];
+#pragma unroll
+    for (int v = 0; v < NR; ++v) s[v] = 0.0;
+    for (int col = threadIdx.x; col < n; col += kThreads) {
+        const double w = inv[(int64_t)row * n + col];
+        const int64_t e = idx[col];
+#pragma unroll
+        for (int v = 0; v < NR; ++v) s[v] += w * (double)f.p[v][e];
+    }
+    __shared__ double sh[NR][kThreads / 64];
+#pragma unroll
+    for (int v = 0; v < NR; ++v) {
+        for (int off = 32; off > 0; off >>= 1) s[v] += __shfl_down(s[v], off, 64);
+        if ((threadIdx.x & 63) == 0) sh[v][threadIdx.x >> 6] = s[v];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+            double t = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) t += sh[v][w];
+            x.p[v][idx[row]] = (T)t;
+        }
+    }
+}
+
 template <class T>
 __device__ __forceinline__ void coarse_body(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx,
                                             const T *__restrict__ f, T *__restrict__ x, int row) {
-    double s = 0.0;
-    for (int col = threadIdx.x; col < n; col += kThreads)
-        s += inv[(int64_t)row * n + col] * (double)f[idx[col]];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    __shared__ double sh[kThreads / 64];
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) t += sh[w];
-        x[idx[row]] = (T)t;
-    }
+    coarse_body_n<T, 1>(n, inv, idx, vptr1(f), vptr1(x), row);
 }
 
 template <class T>
@@ -279,6 +375,13 @@ __global__ void __launch_bounds__(kThreads)
 k_coarse_solve(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx,
                const T *__restrict__ f, T *__restrict__ x) {
     coarse_body<T>(n, inv, idx, f, x, blockIdx.x);
+}
+
+template <class T, int NR>
+__global__ void __launch_bounds__(kThreads)
+k_coarse_solve_b(int n, const double *__restrict__ inv, const int64_t *__restrict__ idx, VPtr<const T> f,
+                 VPtr<T> x) {
+    coarse_body_n<T, NR>(n, inv, idx, f, x, blockIdx.x);
 }
 
 // PMC ghost layer of one plane (axis a) from the values next to it; planes
@@ -839,6 +942,73 @@ void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T
                        coefs_of(coef_f, gf.P), coefs_of(coef_c, gc.P), xc, x);
 }
 
+// ---- block forms: dispatch nr (1..kMaxRhs) to the template
+#define DM_NR_SWITCH(nr, CALL)                      \
+    switch (nr) {                                   \
+        case 1: { constexpr int NR = 1; CALL; } break; \
+        case 2: { constexpr int NR = 2; CALL; } break; \
+        case 3: { constexpr int NR = 3; CALL; } break; \
+        case 4: { constexpr int NR = 4; CALL; } break; \
+        default: throw std::runtime_error("block of more than 4 vectors"); \
+    }
+
+template <class T>
+void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, const VPtr<const T> &f,
+                    const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const Coefs<T> c = coefs_of(coef, g.P);
+    if (kind == AK_M)
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_M, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c,
+                                            sigma, f, x, y))
+    else if (kind == AK_RESID)
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_RESID, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c,
+                                            sigma, f, x, y))
+    else
+        throw std::runtime_error("block apply: M or residual only");
+}
+
+template <class T>
+void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour, int nr, const VPtr<const T> &f,
+                     const VPtr<T> &x, hipStream_t s) {
+    const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
+    const Coefs<T> c = coefs_of(coef, g.P);
+    if (comp == 0)
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_b<T, 0, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma,
+                                            colour, f, x))
+    else if (comp == 1)
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_b<T, 1, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma,
+                                            colour, f, x))
+    else
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_b<T, 2, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma,
+                                            colour, f, x))
+}
+
+template <class T>
+void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
+                       const VPtr<T> &fc, hipStream_t s) {
+    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+    const Coefs<T> cc = coefs_of(coef_c, gc.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid(n), dim3(kThreads), 0, s, gf, gc, cc, r, fc))
+}
+
+template <class T>
+void launch_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, int nr,
+                          const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s) {
+    const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
+    const Coefs<T> cf = coefs_of(coef_f, gf.P), cc = coefs_of(coef_c, gc.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_prolong_add_b<T, NR>), xcd_grid(n), dim3(kThreads), 0, s, gf, gc, cf, cc,
+                                        xc, x))
+}
+
+template <class T>
+void launch_coarse_solve_b(int n, const double *inv, const int64_t *idx, int nr, const VPtr<const T> &f,
+                           const VPtr<T> &x, hipStream_t s) {
+    if (n <= 0) return;
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_coarse_solve_b<T, NR>), dim3(n), dim3(kThreads), 0, s, n, inv, idx, f, x))
+}
+
+#undef DM_NR_SWITCH
+
 template <class TI, class TO>
 void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL((k_cast<TI, TO>), flat_grid(n), dim3(kThreads), 0, s, in, out, n);
@@ -1021,6 +1191,20 @@ void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, 
 }
 
 // explicit instantiations
+#define DM_BLOCK_INST(T)                                                                                   \
+    template void launch_apply_b<T>(const Grid &, const T *, T, int, int, const VPtr<const T> &,                 \
+                                    const VPtr<const T> &, const VPtr<T> &, hipStream_t);                         \
+    template void launch_smooth_b<T>(const Grid &, const T *, T, int, int, int, const VPtr<const T> &,           \
+                                     const VPtr<T> &, hipStream_t);                                               \
+    template void launch_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,        \
+                                       const VPtr<T> &, hipStream_t);                                             \
+    template void launch_prolong_add_b<T>(const Grid &, const Grid &, const T *, const T *, int,                 \
+                                          const VPtr<const T> &, const VPtr<T> &, hipStream_t);                   \
+    template void launch_coarse_solve_b<T>(int, const double *, const int64_t *, int, const VPtr<const T> &,     \
+                                           const VPtr<T> &, hipStream_t);
+DM_BLOCK_INST(double)
+DM_BLOCK_INST(float)
+#undef DM_BLOCK_INST
 template void launch_apply<double>(const Grid &, const double *, double, int, const double *,
                                    const double *, double *, hipStream_t);
 template void launch_apply<float>(const Grid &, const float *, float, int, const float *,

@@ -243,7 +243,7 @@ void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s
     const Level &L = op->lv[0];
     const int64_t n = op->n0();
     double *w = op->ln_t3, *f = op->ln_t4;
-    ensure_krylov(op);   // the FP32 V-cycle's cast buffers
+    ensure_krylov_small(op);   // the FP32 V-cycle's cast buffers
     launch_randn(n, seed, 0, op->fmask, w, s);
     precondition(op, DM_SOLVE_FGMRES_MG32, w, e, s);          // e holds x* for now
     launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, e, f, s);

@@ -20,6 +20,9 @@ struct Level {
     double *x64 = nullptr, *f64 = nullptr, *r64 = nullptr;  // 3P each
     float *x32 = nullptr, *f32 = nullptr, *r32 = nullptr;   // 3P each
     double *sx = nullptr, *sf = nullptr, *sr = nullptr;     // P each (scalar MG)
+    // block V-cycle buffers: kMaxRhs vectors of 3P each (allocated on first use)
+    double *bx64 = nullptr, *bf64 = nullptr, *br64 = nullptr;
+    float *bx32 = nullptr, *bf32 = nullptr, *br32 = nullptr;
     int64_t n_act_faces = 0, n_act_cells = 0;
 };
 
@@ -85,7 +88,14 @@ struct dm_op {
     double *pj_g = nullptr, *pj_psi = nullptr, *pj_r = nullptr, *pj_z = nullptr,
            *pj_p = nullptr, *pj_q = nullptr;
     int eg_cap = 0;
-    double *eg_V = nullptr, *eg_W = nullptr, *eg_T = nullptr;
+    double *eg_V = nullptr, *eg_W = nullptr, *eg_T = nullptr, *eg_F = nullptr;
+    // block solves (allocated on first use): FGMRES bases of kMaxRhs systems,
+    // column j of system r at bk_V + (j * nrhs + r) * n0; per-system device
+    // results / coefficients (kMaxDots each) and pinned host results
+    int bk_m = 0;
+    double *bk_V = nullptr, *bk_Z = nullptr, *bk_w = nullptr;
+    double *bk_dres = nullptr, *bk_dcoef = nullptr, *bk_hres = nullptr;
+    hipGraphExec_t g_vb32[dm::kMaxRhs + 1] = {}, g_vb64[dm::kMaxRhs + 1] = {};
     std::vector<void *> allocs;  // everything to free
     int last_proj_iters = 0;
     // learned correction: the attached network (not owned) and its scratch
@@ -129,8 +139,19 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
             int *iters);
 int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
           dm_solve_info *info, hipStream_t s);
+// nrhs (1..kMaxRhs) systems M x_r = f_r in lockstep, FGMRES modes only;
+// info: nrhs entries or NULL; returns the worst status
+int solve_block(dm_op *op, int mode, int nrhs, const double *const *f, double *const *x, double rtol, int maxit,
+                dm_solve_info *info, hipStream_t s);
+// block V-cycle graph: prec 32 runs lv[0].bf32 -> lv[0].bx32 (nrhs slots of
+// 3P), prec 64 lv[0].bf64 -> lv[0].bx64
+void ensure_block(dm_op *op, int prec);
+void vcycle_block_graphed(dm_op *op, int prec, int nrhs, hipStream_t s);
 void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s);
 void ensure_krylov(dm_op *op);
+// the single-vector solver's small buffers (casts, graph in/out, coefficients)
+// without its FGMRES basis
+void ensure_krylov_small(dm_op *op);
 void ensure_proj(dm_op *op);
 void invalidate_graphs(dm_op *op);
 // V-cycle graphs: prec 32 runs fg_f32 -> fg_x32, prec 64 gv_f64 -> gv_x64;

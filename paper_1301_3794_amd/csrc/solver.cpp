@@ -34,6 +34,29 @@ struct Prec<float> {
     static float *r(Level &L) { return L.r32; }
 };
 
+template <class T>
+struct BPrec;
+template <>
+struct BPrec<double> {
+    static double *x(Level &L) { return L.bx64; }
+    static double *f(Level &L) { return L.bf64; }
+    static double *r(Level &L) { return L.br64; }
+};
+template <>
+struct BPrec<float> {
+    static float *x(Level &L) { return L.bx32; }
+    static float *f(Level &L) { return L.bf32; }
+    static float *r(Level &L) { return L.br32; }
+};
+
+// nr consecutive slots of `stride` elements from base
+template <class T>
+VPtr<T> slots(T *base, int64_t stride, int nr) {
+    VPtr<T> v{};
+    for (int q = 0; q < nr; ++q) v.p[q] = base + q * stride;
+    return v;
+}
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -261,7 +284,20 @@ void ensure_proj(dm_op *op) {
     }
 }
 
+void ensure_krylov_small(dm_op *op) {
+    const int64_t n = op->n0();
+    if (!op->fg_w) {
+        op->fg_w = op->dalloc<double>(n);
+        op->fg_f32 = op->dalloc<float>(n);
+        op->fg_x32 = op->dalloc<float>(n);
+        op->gv_f64 = op->dalloc<double>(n);
+        op->gv_x64 = op->dalloc<double>(n);
+        op->dcoef = op->dalloc<double>(kMaxDots);
+    }
+}
+
 void ensure_krylov(dm_op *op) {
+    ensure_krylov_small(op);
     const int64_t n = op->n0();
     if (!op->fg_V) {
         const int m = op->opt.fgmres_restart;
@@ -269,12 +305,6 @@ void ensure_krylov(dm_op *op) {
         // at least 3 vectors: PCG borrows r, z, p from this block
         op->fg_V = op->dalloc<double>((size_t)std::max(m + 1, 3) * n);
         op->fg_Z = op->dalloc<double>((size_t)m * n);
-        op->fg_w = op->dalloc<double>(n);
-        op->fg_f32 = op->dalloc<float>(n);
-        op->fg_x32 = op->dalloc<float>(n);
-        op->gv_f64 = op->dalloc<double>(n);
-        op->gv_x64 = op->dalloc<double>(n);
-        op->dcoef = op->dalloc<double>(kMaxDots);
     }
 }
 
@@ -339,6 +369,38 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
 template void vcycle<double>(dm_op *, int, const double *, double *, hipStream_t);
 template void vcycle<float>(dm_op *, int, const float *, float *, hipStream_t);
 
+// The V-cycle above on nr vectors at once (the level's block slots, f and x
+// of level 0 included): the same operations per vector, each launch serving
+// all of them.
+template <class T>
+void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
+    Level &L = op->lv[l];
+    const Grid &g = L.g;
+    const int64_t n3 = 3 * g.P;
+    const T sig = (T)op->sigma;
+    const VPtr<T> F = slots(BPrec<T>::f(L), n3, nr), X = slots(BPrec<T>::x(L), n3, nr);
+    launch_zero<T>(nr * n3, BPrec<T>::x(L), s);
+    if (l == op->nlev() - 1) {
+        launch_coarse_solve_b<T>(op->nc, op->cinv, op->cidx, nr, as_const(F), X, s);
+        for (int q = 0; q < nr; ++q) launch_mirror_faces<T>(g, X.p[q], s);
+        return;
+    }
+    const T *c = Prec<T>::coef(L);
+    for (int it = 0; it < op->opt.nu_pre; ++it)
+        for (int comp = 0; comp < 3; ++comp)
+            for (int col = 0; col < 2; ++col) launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s);
+    const VPtr<T> R = slots(BPrec<T>::r(L), n3, nr);
+    launch_apply_b<T>(g, c, sig, AK_RESID, nr, as_const(F), as_const(X), R, s);
+    Level &C = op->lv[l + 1];
+    const int64_t c3 = 3 * C.g.P;
+    launch_restrict_b<T>(g, C.g, Prec<T>::coef(C), nr, as_const(R), slots(BPrec<T>::f(C), c3, nr), s);
+    vcycle_b<T>(op, l + 1, nr, s);
+    launch_prolong_add_b<T>(g, C.g, c, Prec<T>::coef(C), nr, as_const(slots(BPrec<T>::x(C), c3, nr)), X, s);
+    for (int it = 0; it < op->opt.nu_post; ++it)
+        for (int comp = 2; comp >= 0; --comp)
+            for (int col = 1; col >= 0; --col) launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s);
+}
+
 void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
     Level &L = op->lv[l];
     const Grid &g = L.g;
@@ -396,10 +458,54 @@ void invalidate_graphs(dm_op *op) {
         if (*e) (void)hipGraphExecDestroy(*e);
         *e = nullptr;
     }
+    for (int q = 0; q <= kMaxRhs; ++q)
+        for (hipGraphExec_t *e : {&op->g_vb32[q], &op->g_vb64[q]}) {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            *e = nullptr;
+        }
+}
+
+void ensure_block(dm_op *op, int prec) {
+    const int64_t n = op->n0();
+    if (!op->bk_V) {
+        const int m = op->opt.fgmres_restart;
+        op->bk_m = m;
+        op->bk_V = op->dalloc<double>((size_t)(m + 1) * kMaxRhs * n);
+        op->bk_Z = op->dalloc<double>((size_t)m * kMaxRhs * n);
+        op->bk_w = op->dalloc<double>((size_t)kMaxRhs * n);
+        op->bk_dres = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
+        op->bk_dcoef = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
+        DM_HIP(hipHostMalloc((void **)&op->bk_hres, kMaxRhs * kMaxDots * sizeof(double), hipHostMallocDefault));
+    }
+    for (Level &L : op->lv) {
+        const size_t cnt = (size_t)kMaxRhs * 3 * L.g.P;
+        if (prec == 32 && !L.bx32) {
+            L.bx32 = op->dalloc<float>(cnt);
+            L.bf32 = op->dalloc<float>(cnt);
+            L.br32 = op->dalloc<float>(cnt);
+        }
+        if (prec == 64 && !L.bx64) {
+            L.bx64 = op->dalloc<double>(cnt);
+            L.bf64 = op->dalloc<double>(cnt);
+            L.br64 = op->dalloc<double>(cnt);
+        }
+    }
+}
+
+void vcycle_block_graphed(dm_op *op, int prec, int nr, hipStream_t s) {
+    if (nr < 1 || nr > kMaxRhs) throw DmError{DM_EINVAL, "block of 1 to 4 vectors"};
+    ensure_block(op, prec);
+    hipGraphExec_t &g = prec == 32 ? op->g_vb32[nr] : op->g_vb64[nr];
+    if (!g)
+        g = capture(op, [&](hipStream_t cs) {
+            if (prec == 32) vcycle_b<float>(op, 0, nr, cs);
+            else vcycle_b<double>(op, 0, nr, cs);
+        });
+    DM_HIP(hipGraphLaunch(g, s));
 }
 
 void vcycle_graphed(dm_op *op, int prec, hipStream_t s) {
-    ensure_krylov(op);
+    ensure_krylov_small(op);
     if (prec == 32) {
         if (!op->g_vc32)
             op->g_vc32 = capture(op, [&](hipStream_t cs) { vcycle<float>(op, 0, op->fg_f32, op->fg_x32, cs); });
@@ -481,6 +587,242 @@ int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxi
 }
 
 // ---------------------------------------------------------------------------
+// Block solves: nr systems M x_r = f_r in lockstep.  Every system runs the
+// FGMRES(m) of fgmres() above step for step; one lockstep step applies the
+// preconditioner of all open systems as one block V-cycle and their matrix
+// products as one block apply (each coefficient read once for all of them),
+// and gathers the dot products of every system before one host sync.
+// ---------------------------------------------------------------------------
+namespace {
+
+void precondition_block(dm_op *op, int mode, int nr, const double *const *v, double *const *z, hipStream_t s) {
+    const int64_t n = op->n0();
+    if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
+        ensure_block(op, 32);
+        for (int q = 0; q < nr; ++q) launch_cast<double, float>(v[q], op->lv[0].bf32 + q * n, n, s);
+        vcycle_block_graphed(op, 32, nr, s);
+        for (int q = 0; q < nr; ++q) launch_cast<float, double>(op->lv[0].bx32 + q * n, z[q], n, s);
+        if (mode == DM_SOLVE_FGMRES_MG32_LEARNED)
+            for (int q = 0; q < nr; ++q) net_correct(op, v[q], z[q], s);
+    } else {
+        ensure_block(op, 64);
+        for (int q = 0; q < nr; ++q) launch_copy(n, v[q], op->lv[0].bf64 + q * n, s);
+        vcycle_block_graphed(op, 64, nr, s);
+        for (int q = 0; q < nr; ++q) launch_copy(n, op->lv[0].bx64 + q * n, z[q], s);
+    }
+}
+
+struct BlockRhs {
+    const double *f = nullptr;
+    double *x = nullptr;
+    double bnorm = 0.0, rel = 0.0;
+    int total = 0, restarts = 0, j = 0;
+    bool open = false, done = false, conv = false;
+    std::vector<double> H, cs, sn, g, y, h, h2;
+};
+
+int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *const *x, double rtol, int maxit,
+                 dm_solve_info *info, hipStream_t s) {
+    ensure_block(op, mode == DM_SOLVE_FGMRES_MG64 ? 64 : 32);
+    const Level &L = op->lv[0];
+    const int64_t n = op->n0();
+    const int m = op->bk_m;
+    const int64_t ld = (int64_t)nb * n;   // stride between the columns of one system
+    auto Vc = [&](int r, int j) { return op->bk_V + (int64_t)j * ld + (int64_t)r * n; };
+    auto Zc = [&](int r, int j) { return op->bk_Z + (int64_t)j * ld + (int64_t)r * n; };
+    auto Wr = [&](int r) { return op->bk_w + (int64_t)r * n; };
+    auto dres = [&](int r) { return op->bk_dres + (int64_t)r * kMaxDots; };
+    auto dcoef = [&](int r) { return op->bk_dcoef + (int64_t)r * kMaxDots; };
+    auto hres = [&](int r) { return op->bk_hres + (int64_t)r * kMaxDots; };
+    // every system's device results to the host, one sync
+    auto fetch = [&]() {
+        DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nb * kMaxDots * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+    };
+    std::vector<BlockRhs> st(nb);
+    for (int r = 0; r < nb; ++r) {
+        BlockRhs &R = st[r];
+        R.f = f[r];
+        R.x = x[r];
+        R.H.assign((size_t)(m + 1) * m, 0.0);
+        R.cs.assign(m, 0.0);
+        R.sn.assign(m, 0.0);
+        R.g.assign(m + 1, 0.0);
+        R.y.assign(m, 0.0);
+        R.h.assign(m + 1, 0.0);
+        R.h2.assign(m + 1, 0.0);
+        DM_HIP(hipMemsetAsync(R.x, 0, n * sizeof(double), s));
+        launch_mdot(1, R.f, 0, R.f, nullptr, n, op->part, dres(r), s);
+    }
+    fetch();
+    for (int r = 0; r < nb; ++r) {
+        BlockRhs &R = st[r];
+        R.bnorm = std::sqrt(hres(r)[0]);
+        if (!std::isfinite(R.bnorm)) throw DmError{DM_ENAN, "right-hand side is not finite"};
+        if (R.bnorm == 0.0) R.done = R.conv = true;
+    }
+    std::vector<int> act;
+    const double *vin[kMaxRhs];
+    double *zout[kMaxRhs];
+    while (true) {
+        // (re)start the systems without an open cycle: r0 = f - M x, beta
+        act.clear();
+        for (int r = 0; r < nb; ++r)
+            if (!st[r].done && !st[r].open) act.push_back(r);
+        if (!act.empty()) {
+            VPtr<const double> bf{}, bx{};
+            VPtr<double> by{};
+            int nres = 0;
+            for (int r : act) {
+                if (st[r].total == 0) {
+                    launch_copy(n, st[r].f, Vc(r, 0), s);
+                } else {
+                    bf.p[nres] = st[r].f;
+                    bx.p[nres] = st[r].x;
+                    by.p[nres] = Vc(r, 0);
+                    ++nres;
+                }
+            }
+            if (nres) launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_RESID, nres, bf, bx, by, s);
+            for (int r : act) launch_mdot(1, Vc(r, 0), 0, Vc(r, 0), nullptr, n, op->part, dres(r), s);
+            fetch();
+            for (int r : act) {
+                BlockRhs &R = st[r];
+                const double beta = std::sqrt(hres(r)[0]);
+                if (!std::isfinite(beta)) throw DmError{DM_ENAN, "FGMRES residual is not finite"};
+                R.rel = beta / R.bnorm;
+                if (beta <= rtol * R.bnorm) {
+                    R.done = R.conv = true;
+                    continue;
+                }
+                if (R.total >= maxit) {
+                    R.done = true;
+                    continue;
+                }
+                launch_scale(n, 1.0 / beta, Vc(r, 0), s);
+                std::fill(R.g.begin(), R.g.end(), 0.0);
+                R.g[0] = beta;
+                std::fill(R.H.begin(), R.H.end(), 0.0);
+                R.j = 0;
+                R.open = true;
+            }
+        }
+        act.clear();
+        for (int r = 0; r < nb; ++r)
+            if (st[r].open) act.push_back(r);
+        if (act.empty()) break;
+        const int na = (int)act.size();
+        // z_j = B v_j and w = M z_j for every open system
+        VPtr<const double> zc{};
+        VPtr<double> wv{};
+        for (int q = 0; q < na; ++q) {
+            const int r = act[q];
+            vin[q] = Vc(r, st[r].j);
+            zout[q] = Zc(r, st[r].j);
+            zc.p[q] = zout[q];
+            wv.p[q] = Wr(r);
+        }
+        precondition_block(op, mode, na, vin, zout, s);
+        launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s);
+        // classical Gram--Schmidt twice, as in fgmres(): (1) h = V^T w
+        for (int r : act) launch_mdot(st[r].j + 1, Vc(r, 0), ld, Wr(r), nullptr, n, op->part, dres(r), s);
+        fetch();
+        // (2) w -= V h, then h2 = V^T w and |w|^2
+        for (int r : act) {
+            BlockRhs &R = st[r];
+            const int j = R.j;
+            std::copy(hres(r), hres(r) + j + 1, R.h.begin());
+            DM_HIP(hipMemcpyAsync(dcoef(r), R.h.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+            if (j + 1 <= 32) {
+                launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dcoef(r), Wr(r), n, op->part, dres(r), s);
+            } else {
+                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), Wr(r), n, 0, s);
+                launch_mdot(j + 1, Vc(r, 0), ld, Wr(r), nullptr, n, op->part, dres(r), s);
+                launch_mdot(1, Wr(r), 0, Wr(r), nullptr, n, op->part, dres(r) + j + 1, s);
+            }
+        }
+        fetch();
+        // (3) v_{j+1} = (w - V h2) / |w - V h2|; Hessenberg column, Givens
+        for (int r : act) {
+            BlockRhs &R = st[r];
+            int j = R.j;
+            std::copy(hres(r), hres(r) + j + 1, R.h2.begin());
+            const double wn2 = hres(r)[j + 1];
+            double c2 = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                R.h[i] += R.h2[i];
+                c2 += R.h2[i] * R.h2[i];
+            }
+            const double hn = std::sqrt(std::max(wn2 - c2, 0.0));
+            if (!std::isfinite(hn)) throw DmError{DM_ENAN, "FGMRES iterate is not finite"};
+            DM_HIP(hipMemcpyAsync(dcoef(r), R.h2.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+            double *H = R.H.data();
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = R.h[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = R.cs[i] * a + R.sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -R.sn[i] * a + R.cs[i] * b;
+            }
+            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            const double rr = std::hypot(a, b);
+            R.cs[j] = rr > 0 ? a / rr : 1.0;
+            R.sn[j] = rr > 0 ? b / rr : 0.0;
+            H[(size_t)j * m + j] = rr;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            R.g[j + 1] = -R.sn[j] * R.g[j];
+            R.g[j] = R.cs[j] * R.g[j];
+            ++R.total;
+            R.j = ++j;
+            if (hn > 0.0) launch_maxpy_scale(j, Vc(r, 0), ld, dcoef(r), Wr(r), 1.0 / hn, Vc(r, j), n, s);
+            const bool close = std::fabs(R.g[j]) <= rtol * R.bnorm || R.total >= maxit || hn == 0.0 || j == m;
+            if (!close) continue;
+            // end of the cycle: x += Z y, y from the triangular system
+            for (int i = j - 1; i >= 0; --i) {
+                double t = R.g[i];
+                for (int c = i + 1; c < j; ++c) t -= H[(size_t)i * m + c] * R.y[c];
+                R.y[i] = t / H[(size_t)i * m + i];
+            }
+            for (int i = 0; i < j; ++i) R.h[i] = -R.y[i];
+            DM_HIP(hipMemcpyAsync(dcoef(r), R.h.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+            launch_maxpy(j, Zc(r, 0), ld, dcoef(r), R.x, n, 0, s);
+            ++R.restarts;
+            R.open = false;
+        }
+    }
+    int rc = DM_OK;
+    for (int r = 0; r < nb; ++r) {
+        if (!st[r].conv) rc = DM_NOT_CONVERGED;
+        if (info) {
+            info[r].iterations = st[r].total;
+            info[r].restarts = st[r].restarts > 0 ? st[r].restarts - 1 : 0;
+            info[r].rel_residual = st[r].rel;
+        }
+    }
+    return rc;
+}
+
+}  // namespace
+
+int solve_block(dm_op *op, int mode, int nrhs, const double *const *f, double *const *x, double rtol, int maxit,
+                dm_solve_info *info, hipStream_t s) {
+    if (nrhs < 1 || nrhs > kMaxRhs) throw DmError{DM_EINVAL, "block of 1 to 4 systems"};
+    if (mode == DM_SOLVE_PCG64) throw DmError{DM_EINVAL, "block solves use FGMRES modes"};
+    const double t0 = now_s();
+    op->ln_accepted = op->ln_rejected = 0;
+    const int rc = fgmres_block(op, mode, nrhs, f, x, rtol, maxit, info, s);
+    DM_HIP(hipStreamSynchronize(s));
+    if (info)
+        for (int r = 0; r < nrhs; ++r) {
+            info[r].seconds = now_s() - t0;
+            info[r].learned_accepted = op->ln_accepted;
+            info[r].learned_rejected = op->ln_rejected;
+        }
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // Block Krylov--Schur (symmetric) on T = P_DM M^-1 A, A-inner product.
 // ---------------------------------------------------------------------------
 int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt, double *lam,
@@ -500,7 +842,12 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
         op->eg_T = op->dalloc<double>((size_t)3 * n);
         op->eg_cap = cap;
     }
-    ensure_krylov(op);
+    // the block's M solves in lockstep (one block V-cycle per step) unless
+    // the op's preconditioner is a batch's fused V-cycle or the mode is PCG
+    const bool blocked = b > 1 && !op->batch && opt.solve_mode != DM_SOLVE_PCG64;
+    if (blocked && !op->eg_F) op->eg_F = op->dalloc<double>((size_t)kMaxRhs * n);
+    if (blocked) ensure_krylov_small(op);
+    else ensure_krylov(op);
     double *V = op->eg_V, *W = op->eg_W, *t1 = op->eg_T, *t2 = op->eg_T + n, *t3 = op->eg_T + 2 * n;
     double *SCR = V + (size_t)(m + b) * n;   // room for keep_max Ritz vectors
     // inner products over the owned active faces: (u, v) = u^T W A v
@@ -562,14 +909,37 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
         // ---- expand by one block: W = T V_last, orthogonalise, append
         {
             const int j0 = cur - b;
-            for (int c = 0; c < b; ++c) {
-                double *w = W + (size_t)c * n;
-                launch_apply_A(L.g, L.coef64, V + (size_t)(j0 + c) * n, t1, s);
-                const int rc = solve(op, opt.solve_mode, t1, w, opt.inner_rtol, 2000, &sinfo, s);
-                if (rc < 0) return rc;
-                inner_its += sinfo.iterations;
-                project(op, w, w, opt.proj_rtol, 1000, s, &pj);
-                proj_its += pj;
+            if (blocked) {
+                // the block's solves in lockstep, kMaxRhs at a time
+                for (int c0 = 0; c0 < b; c0 += kMaxRhs) {
+                    const int nr = std::min(kMaxRhs, b - c0);
+                    const double *fp[kMaxRhs];
+                    double *xp[kMaxRhs];
+                    dm_solve_info bi[kMaxRhs];
+                    for (int q = 0; q < nr; ++q) {
+                        launch_apply_A(L.g, L.coef64, V + (size_t)(j0 + c0 + q) * n, op->eg_F + (size_t)q * n, s);
+                        fp[q] = op->eg_F + (size_t)q * n;
+                        xp[q] = W + (size_t)(c0 + q) * n;
+                    }
+                    const int rc = solve_block(op, opt.solve_mode, nr, fp, xp, opt.inner_rtol, 2000, bi, s);
+                    if (rc < 0) return rc;
+                    for (int q = 0; q < nr; ++q) inner_its += bi[q].iterations;
+                }
+                for (int c = 0; c < b; ++c) {
+                    double *w = W + (size_t)c * n;
+                    project(op, w, w, opt.proj_rtol, 1000, s, &pj);
+                    proj_its += pj;
+                }
+            } else {
+                for (int c = 0; c < b; ++c) {
+                    double *w = W + (size_t)c * n;
+                    launch_apply_A(L.g, L.coef64, V + (size_t)(j0 + c) * n, t1, s);
+                    const int rc = solve(op, opt.solve_mode, t1, w, opt.inner_rtol, 2000, &sinfo, s);
+                    if (rc < 0) return rc;
+                    inner_its += sinfo.iterations;
+                    project(op, w, w, opt.proj_rtol, 1000, s, &pj);
+                    proj_its += pj;
+                }
             }
             ++outer;
             for (int c = 0; c < b; ++c) {

@@ -29,8 +29,8 @@ NET_LOSS_ERROR, NET_LOSS_RESIDUAL = 0, 1
 EXPORTS = (
     "dm_default_options", "dm_build_operator", "dm_destroy", "dm_set_shift",
     "dm_compute_fractions", "dm_field_layout", "dm_get_fractions", "dm_apply",
-    "dm_residual", "dm_smooth", "dm_restrict", "dm_prolong_add", "dm_vcycle",
-    "dm_project", "dm_solve", "dm_default_eig_options", "dm_eigs", "dm_strerror",
+    "dm_residual", "dm_smooth", "dm_restrict", "dm_prolong_add", "dm_vcycle", "dm_vcycle_block",
+    "dm_project", "dm_solve", "dm_solve_block", "dm_default_eig_options", "dm_eigs", "dm_strerror",
     "dm_last_error_message", "dm_time_kernel", "dm_net_create", "dm_net_destroy",
     "dm_net_get_weights", "dm_net_set_weights", "dm_net_attach", "dm_net_apply",
     "dm_net_loss_grad", "dm_net_make_pair", "dm_net_train", "dm_batch_create", "dm_batch_destroy",
@@ -124,8 +124,11 @@ def lib():
     L.dm_restrict.argtypes = [vp, i, i, vp, vp, vp]
     L.dm_prolong_add.argtypes = [vp, i, i, vp, vp, vp]
     L.dm_vcycle.argtypes = [vp, i, vp, vp, vp]
+    L.dm_vcycle_block.argtypes = [vp, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.dm_project.argtypes = [vp, vp, vp, d, vp]
     L.dm_solve.argtypes = [vp, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
+    L.dm_solve_block.argtypes = [vp, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp), d, i,
+                                 ctypes.POINTER(SolveInfo), vp]
     L.dm_default_eig_options.argtypes = [ctypes.POINTER(EigOptions)]
     L.dm_default_eig_options.restype = None
     L.dm_eigs.argtypes = [vp, i, d, d, ctypes.c_uint64, ctypes.POINTER(EigOptions), dp, vp, dp,
@@ -345,6 +348,14 @@ class Operator:
         _check(lib().dm_vcycle(self._op, self._prec(f), _ptr(f), _ptr(x), _stream(stream)))
         return x
 
+    def vcycle_block(self, fs, xs, stream=None):
+        """x_r = B f_r for every pair (1..4 vectors of one precision)."""
+        n = len(fs)
+        fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        _check(lib().dm_vcycle_block(self._op, self._prec(fs[0]), n, fp, xp, _stream(stream)))
+        return xs
+
     def project(self, b, out, rtol=1e-13, stream=None):
         _check(lib().dm_project(self._op, _ptr(b), _ptr(out), float(rtol), _stream(stream)))
         return out
@@ -356,6 +367,17 @@ class Operator:
         return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
                     rel_residual=info.rel_residual, seconds=info.seconds,
                     learned_accepted=info.learned_accepted, learned_rejected=info.learned_rejected)
+
+    def solve_block(self, fs, xs, mode=SOLVE_FGMRES_MG32, rtol=1e-10, maxit=500, stream=None):
+        """M x_r = f_r for 1..4 systems in lockstep; one dict per system."""
+        n = len(fs)
+        fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        info = (SolveInfo * n)()
+        rc = _check(lib().dm_solve_block(self._op, mode, n, fp, xp, float(rtol), int(maxit), info,
+                                         _stream(stream)), allow_warning=True)
+        return [dict(status=rc, iterations=q.iterations, restarts=q.restarts, rel_residual=q.rel_residual,
+                     seconds=q.seconds) for q in info]
 
     def time_kernel(self, kernel, prec=32, level=0, reps=50):
         """Milliseconds per launch of a library kernel (HIP events)."""
