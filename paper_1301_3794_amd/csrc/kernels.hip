@@ -61,54 +61,41 @@ __device__ inline T vac_row(const T *C, int64_t p, int64_t dy, int64_t dz) {
 
 // NR right-hand sides at once (block solves): the coefficients of a row are
 // loaded once and serve every vector; all rows are formed before any store.
-template <class T, int KIND, int NR>
-__device__ __forceinline__ void apply_body_n(const Grid &g, const Coefs<T> &c, T sigma, const VPtr<const T> &f,
-                                             const VPtr<const T> &x, const VPtr<T> &y, int64_t item) {
+template <class T, int KIND>
+__device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T sigma, const T *__restrict__ f,
+                                           const T *__restrict__ x, T *__restrict__ y, int64_t item) {
     int i, j, k;
     if (!cell_of(g, item, i, j, k)) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
     const int64_t p = pidx(g, i, j, k);
+    const T *X = x, *Y = x + P, *Z = x + 2 * P;
     const T ih2 = inv_h2_of<T>(g);
     const uint8_t fl = c.flags[p];
-    T yx[NR], yy[NR], yz[NR];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        const T *X = x.p[q], *Y = X + P, *Z = X + 2 * P;
-        yx[q] = T(0), yy[q] = T(0), yz[q] = T(0);
-        if (KIND == AK_K) {
-            if (fl & (kFaceActive << 0)) yx[q] = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
-            if (fl & (kFaceActive << 1)) yy[q] = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
-            if (fl & (kFaceActive << 2)) yz[q] = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
-        } else {
-            if (fl & (kFaceActive << 0)) {
-                yx[q] = (fl & (kFaceVacuum << 0)) ? ih2 * vac_row(X, p, dy, dz) - sigma * X[p]
-                                                  : ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
-                if (KIND == AK_RESID) yx[q] = f.p[q][p] - yx[q];
-            }
-            if (fl & (kFaceActive << 1)) {
-                yy[q] = (fl & (kFaceVacuum << 1)) ? ih2 * vac_row(Y, p, dy, dz) - sigma * Y[p]
-                                                  : ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
-                if (KIND == AK_RESID) yy[q] = f.p[q][P + p] - yy[q];
-            }
-            if (fl & (kFaceActive << 2)) {
-                yz[q] = (fl & (kFaceVacuum << 2)) ? ih2 * vac_row(Z, p, dy, dz) - sigma * Z[p]
-                                                  : ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
-                if (KIND == AK_RESID) yz[q] = f.p[q][2 * P + p] - yz[q];
-            }
+    T yx = T(0), yy = T(0), yz = T(0);
+    if (KIND == AK_K) {
+        if (fl & (kFaceActive << 0)) yx = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 1)) yy = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 2)) yz = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
+    } else {
+        if (fl & (kFaceActive << 0)) {
+            yx = (fl & (kFaceVacuum << 0)) ? ih2 * vac_row(X, p, dy, dz) - sigma * X[p]
+                                           : ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
+            if (KIND == AK_RESID) yx = f[p] - yx;
+        }
+        if (fl & (kFaceActive << 1)) {
+            yy = (fl & (kFaceVacuum << 1)) ? ih2 * vac_row(Y, p, dy, dz) - sigma * Y[p]
+                                           : ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
+            if (KIND == AK_RESID) yy = f[P + p] - yy;
+        }
+        if (fl & (kFaceActive << 2)) {
+            yz = (fl & (kFaceVacuum << 2)) ? ih2 * vac_row(Z, p, dy, dz) - sigma * Z[p]
+                                           : ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
+            if (KIND == AK_RESID) yz = f[2 * P + p] - yz;
         }
     }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        put_face<T>(g, y.p[q], 0, i, j, k, p, yx[q]);
-        put_face<T>(g, y.p[q] + P, 1, i, j, k, p, yy[q]);
-        put_face<T>(g, y.p[q] + 2 * P, 2, i, j, k, p, yz[q]);
-    }
-}
-
-template <class T, int KIND>
-__device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T sigma, const T *__restrict__ f,
-                                           const T *__restrict__ x, T *__restrict__ y, int64_t item) {
-    apply_body_n<T, KIND, 1>(g, c, sigma, vptr1(f), vptr1(x), vptr1(y), item);
+    put_face<T>(g, y, 0, i, j, k, p, yx);
+    put_face<T>(g, y + P, 1, i, j, k, p, yy);
+    put_face<T>(g, y + 2 * P, 2, i, j, k, p, yz);
 }
 
 template <class T, int KIND>
@@ -118,10 +105,23 @@ k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restric
     apply_body<T, KIND>(g, c, sigma, f, x, y, xcd_item());
 }
 
+// Block forms of apply, restriction and prolongation: NR consecutive lanes
+// take the same cell, one vector each, so their coefficient loads fall on
+// the same cache lines (one fetch from HBM for the block) while every lane
+// keeps the register budget of the one-vector body.  (Looping over the
+// vectors inside a thread instead kept every vector's loads and addresses
+// live at once: 170-240 VGPRs, two waves per SIMD.)
+template <class T, int NR>
+__device__ __forceinline__ int lane_vector(int64_t t) {
+    return (int)(t % NR);
+}
+
 template <class T, int KIND, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_apply_b(Grid g, Coefs<T> c, T sigma, VPtr<const T> f, VPtr<const T> x, VPtr<T> y) {
-    apply_body_n<T, KIND, NR>(g, c, sigma, f, x, y, xcd_item());
+    const int64_t t = xcd_item();
+    const int q = lane_vector<T, NR>(t);
+    apply_body<T, KIND>(g, c, sigma, f.p[q], x.p[q], y.p[q], t / NR);
 }
 
 // y = A x
@@ -208,13 +208,14 @@ k_smooth_b(Grid g, Coefs<T> c, T sigma, int colour, VPtr<const T> f, VPtr<T> x) 
 // ---------------------------------------------------------------------------
 // Staggered transfers.  P: linear along the normal, constant across; R = P^T/8.
 // ---------------------------------------------------------------------------
-template <class T, int NR>
-__device__ __forceinline__ void restrict_body_n(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
-                                                const VPtr<const T> &r, const VPtr<T> &fc, int64_t item) {
+template <class T>
+__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
+                                              const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
     int I, J, K;
     if (!cell_of(gc, item, I, J, K)) return;
     const int64_t Pf = gf.P, Pc = gc.P, fy = gf.sy, fz = gf.sz;
     const int64_t pc = pidx(gc, I, J, K);
+    const T *RX = r, *RY = r + Pf, *RZ = r + 2 * Pf;
     const int64_t q = pidx(gf, 2 * I, 2 * J, 2 * K);
     // transpose of the area-weighted normal interpolation: the fine face
     // between coarse faces c and c' gives c the share a_c / (a_c + a_c')
@@ -225,33 +226,23 @@ __device__ __forceinline__ void restrict_body_n(const Grid &gf, const Grid &gc, 
     const T yp = ay > T(0) ? ay / (ay + cc.ay[pc + gc.sy]) : T(0);
     const T zm = az > T(0) ? az / (az + cc.az[pc - gc.sz]) : T(0);
     const T zp = az > T(0) ? az / (az + cc.az[pc + gc.sz]) : T(0);
+    T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            // x: tangential offsets in y (a) and z (b)
+            const int64_t qx = q + a * fy + b * fz;
+            sx += RX[qx] + xm * RX[qx - 1] + xp * RX[qx + 1];
+            const int64_t qy = q + a + b * fz;
+            sy += RY[qy] + ym * RY[qy - fy] + yp * RY[qy + fy];
+            const int64_t qz = q + a + b * fy;
+            sz += RZ[qz] + zm * RZ[qz - fz] + zp * RZ[qz + fz];
+        }
     const T e = T(0.125);
-#pragma unroll
-    for (int v = 0; v < NR; ++v) {
-        const T *RX = r.p[v], *RY = RX + Pf, *RZ = RX + 2 * Pf;
-        T sx = 0, sy = 0, sz = 0;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                // x: tangential offsets in y (a) and z (b)
-                const int64_t qx = q + a * fy + b * fz;
-                sx += RX[qx] + xm * RX[qx - 1] + xp * RX[qx + 1];
-                const int64_t qy = q + a + b * fz;
-                sy += RY[qy] + ym * RY[qy - fy] + yp * RY[qy + fy];
-                const int64_t qz = q + a + b * fy;
-                sz += RZ[qz] + zm * RZ[qz - fz] + zp * RZ[qz + fz];
-            }
-        put_face<T>(gc, fc.p[v], 0, I, J, K, pc, ax != T(0) ? e * sx : T(0));
-        put_face<T>(gc, fc.p[v] + Pc, 1, I, J, K, pc, ay != T(0) ? e * sy : T(0));
-        put_face<T>(gc, fc.p[v] + 2 * Pc, 2, I, J, K, pc, az != T(0) ? e * sz : T(0));
-    }
-}
-
-template <class T>
-__device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
-                                              const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
-    restrict_body_n<T, 1>(gf, gc, cc, vptr1(r), vptr1(fc), item);
+    put_face<T>(gc, fc, 0, I, J, K, pc, ax != T(0) ? e * sx : T(0));
+    put_face<T>(gc, fc + Pc, 1, I, J, K, pc, ay != T(0) ? e * sy : T(0));
+    put_face<T>(gc, fc + 2 * Pc, 2, I, J, K, pc, az != T(0) ? e * sz : T(0));
 }
 
 template <class T>
@@ -263,7 +254,9 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc) {
-    restrict_body_n<T, NR>(gf, gc, cc, r, fc, xcd_item());
+    const int64_t t = xcd_item();
+    const int q = lane_vector<T, NR>(t);
+    restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t / NR);
 }
 
 // fine value between coarse faces c0, c1: (a0 x0 + a1 x1) / (a0 + a1)
@@ -273,37 +266,24 @@ __device__ __forceinline__ T wmean(T a0, T x0, T a1, T x1) {
     return t > T(0) ? (a0 * x0 + a1 * x1) / t : T(0);
 }
 
-template <class T, int NR>
-__device__ __forceinline__ void prolong_body_n(const Grid &gf, const Grid &gc, const Coefs<T> &cf,
-                                               const Coefs<T> &cc, const VPtr<const T> &xc, const VPtr<T> &x,
-                                               int64_t item) {
+template <class T>
+__device__ __forceinline__ void prolong_body(const Grid &gf, const Grid &gc, const Coefs<T> &cf, const Coefs<T> &cc,
+                                             const T *__restrict__ xc, T *__restrict__ x, int64_t item) {
     int i, j, k;
     if (!cell_of(gf, item, i, j, k)) return;
     const int64_t Pf = gf.P, Pc = gc.P, cy = gc.sy, cz = gc.sz;
     const int64_t p = pidx(gf, i, j, k);
     const int64_t q = pidx(gc, i >> 1, j >> 1, k >> 1);
-    const bool fx = cf.ax[p] != T(0), fy = cf.ay[p] != T(0), fz = cf.az[p] != T(0);
-    const T ax0 = cc.ax[q], ax1 = cc.ax[q + 1], ay0 = cc.ay[q], ay1 = cc.ay[q + cy];
-    const T az0 = cc.az[q], az1 = cc.az[q + cz];
-#pragma unroll
-    for (int v = 0; v < NR; ++v) {
-        const T *CX = xc.p[v], *CY = CX + Pc, *CZ = CX + 2 * Pc;
-        T *X = x.p[v];
-        if (fx)
-            put_face<T>(gf, X, 0, i, j, k, p, X[p] + ((i & 1) ? wmean(ax0, CX[q], ax1, CX[q + 1]) : CX[q]));
-        if (fy)
-            put_face<T>(gf, X + Pf, 1, i, j, k, p,
-                        X[Pf + p] + ((j & 1) ? wmean(ay0, CY[q], ay1, CY[q + cy]) : CY[q]));
-        if (fz)
-            put_face<T>(gf, X + 2 * Pf, 2, i, j, k, p,
-                        X[2 * Pf + p] + ((k & 1) ? wmean(az0, CZ[q], az1, CZ[q + cz]) : CZ[q]));
-    }
-}
-
-template <class T>
-__device__ __forceinline__ void prolong_body(const Grid &gf, const Grid &gc, const Coefs<T> &cf, const Coefs<T> &cc,
-                                             const T *__restrict__ xc, T *__restrict__ x, int64_t item) {
-    prolong_body_n<T, 1>(gf, gc, cf, cc, vptr1(xc), vptr1(x), item);
+    const T *CX = xc, *CY = xc + Pc, *CZ = xc + 2 * Pc;
+    if (cf.ax[p] != T(0))
+        put_face<T>(gf, x, 0, i, j, k, p,
+                    x[p] + ((i & 1) ? wmean(cc.ax[q], CX[q], cc.ax[q + 1], CX[q + 1]) : CX[q]));
+    if (cf.ay[p] != T(0))
+        put_face<T>(gf, x + Pf, 1, i, j, k, p,
+                    x[Pf + p] + ((j & 1) ? wmean(cc.ay[q], CY[q], cc.ay[q + cy], CY[q + cy]) : CY[q]));
+    if (cf.az[p] != T(0))
+        put_face<T>(gf, x + 2 * Pf, 2, i, j, k, p,
+                    x[2 * Pf + p] + ((k & 1) ? wmean(cc.az[q], CZ[q], cc.az[q + cz], CZ[q + cz]) : CZ[q]));
 }
 
 template <class T>
@@ -316,7 +296,9 @@ k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, VPtr<const T> xc, VPtr<T> x) {
-    prolong_body_n<T, NR>(gf, gc, cf, cc, xc, x, xcd_item());
+    const int64_t t = xcd_item();
+    const int q = lane_vector<T, NR>(t);
+    prolong_body<T>(gf, gc, cf, cc, xc.p[q], x.p[q], t / NR);
 }
 
 // x = 0 (a kernel, not a memset: it may be recorded into a HIP graph)
@@ -958,11 +940,11 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
     if (kind == AK_M)
-        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_M, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c,
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_M, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c,
                                             sigma, f, x, y))
     else if (kind == AK_RESID)
-        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_RESID, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c,
-                                            sigma, f, x, y))
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_RESID, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g,
+                                            c, sigma, f, x, y))
     else
         throw std::runtime_error("block apply: M or residual only");
 }
@@ -988,7 +970,8 @@ void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, 
                        const VPtr<T> &fc, hipStream_t s) {
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
     const Coefs<T> cc = coefs_of(coef_c, gc.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid(n), dim3(kThreads), 0, s, gf, gc, cc, r, fc))
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cc, r,
+                                        fc))
 }
 
 template <class T>
@@ -996,8 +979,8 @@ void launch_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, const
                           const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s) {
     const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
     const Coefs<T> cf = coefs_of(coef_f, gf.P), cc = coefs_of(coef_c, gc.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_prolong_add_b<T, NR>), xcd_grid(n), dim3(kThreads), 0, s, gf, gc, cf, cc,
-                                        xc, x))
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_prolong_add_b<T, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cf,
+                                        cc, xc, x))
 }
 
 template <class T>
