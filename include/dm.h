@@ -215,6 +215,13 @@ int dm_vcycle_block(dm_op *op, int prec, int nrhs, const void *const *f_dev, voi
  * divergence-free input costs few iterations.  FP64.  b and b_out may alias. */
 int dm_project(dm_op *op, const double *b_dev, double *out_dev, double rtol,
                void *stream);
+/* dm_project on nrhs (1..4) vectors at once (the projections of one block
+ * step of the eigensolver): each vector runs its own CG on S, in lockstep,
+ * with one block S apply and one block scalar V-cycle per step; the values
+ * are those of nrhs calls of dm_project.  b_dev, out_dev: host arrays of
+ * nrhs device pointers (FP64 face vectors); out may equal b. */
+int dm_project_block(dm_op *op, int nrhs, const double *const *b_dev, double *const *out_dev, double rtol,
+                     void *stream);
 
 /* ---- linear solve of M x = f (Sec. 6: the inner inversion) -------------- */
 #define DM_SOLVE_PCG64        0  /* CG + FP64 V-cycle (M must be SPD: sigma below

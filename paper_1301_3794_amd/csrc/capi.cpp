@@ -431,6 +431,18 @@ int dm_project(dm_op *op, const double *b, double *out, double rtol, void *strea
     });
 }
 
+int dm_project_block(dm_op *op, int nrhs, const double *const *b, double *const *out, double rtol, void *stream) {
+    if (!op || !b || !out) return fail(DM_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(DM_EINVAL, "nrhs must be 1..4");
+    if (!(rtol > 0.0)) return fail(DM_EINVAL, "rtol must be positive");
+    for (int q = 0; q < nrhs; ++q)
+        if (!b[q] || !out[q]) return fail(DM_EINVAL, "NULL vector in the block");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        for (int q = 0; q < nrhs; ++q) fill_ghosts(op->lv[0], 64, b[q], false, s);
+        return project_block(op, nrhs, b, out, rtol, 2000, s, nullptr);
+    });
+}
+
 int dm_solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
              dm_solve_info *info, void *stream) {
     if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");

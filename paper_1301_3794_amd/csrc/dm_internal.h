@@ -322,6 +322,20 @@ void launch_apply_A(const Grid &g, const double *coef, const double *x, double *
 template <class T>
 void launch_apply_A_t(const Grid &g, const T *coef, const T *x, T *y, hipStream_t s);
 
+// block forms of the scalar-Laplacian kernels (projection), nr = 1..kMaxRhs
+void launch_div_DA_b(const Grid &g, const double *coef, int nr, const VPtr<const double> &b,
+                     const VPtr<double> &out, hipStream_t s);
+void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<const double> &psi,
+                       const VPtr<const double> &b_in, const VPtr<double> &b_out, double scale, hipStream_t s);
+void launch_s_apply_b(const Grid &g, const double *coef, double w, int resid, int nr, const VPtr<const double> &f,
+                      const VPtr<const double> &x, const VPtr<double> &y, hipStream_t s);
+void launch_s_smooth_b(const Grid &g, const double *coef, double w, int colour, int nr, const VPtr<const double> &f,
+                       const VPtr<double> &x, hipStream_t s);
+void launch_s_restrict_b(const Grid &gf, const Grid &gc, const double *coef_c, int nr, const VPtr<const double> &r,
+                         const VPtr<double> &fc, hipStream_t s);
+void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const double *coef_f, int nr,
+                            const VPtr<const double> &xc, const VPtr<double> &x, hipStream_t s);
+
 // PMC ghost layers of a face / cell vector from the adjacent values (no-op
 // without PMC planes)
 template <class T>

@@ -405,10 +405,10 @@ __global__ void k_mirror_cells(Grid g, int a, double *__restrict__ x) {
 // ---------------------------------------------------------------------------
 // Scalar problem: g = D A b, b -= D^T psi, S = D A D^T (weight w per level)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads)
-k_div_DA(Grid g, Coefs<double> c, const double *__restrict__ b, double *__restrict__ out) {
+__device__ __forceinline__ void div_DA_body(const Grid &g, const Coefs<double> &c, const double *__restrict__ b,
+                                            double *__restrict__ out, int64_t item) {
     int i, j, k;
-    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    if (!cell_of(g, item, i, j, k)) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
     const double *X = b, *Y = b + P, *Z = b + 2 * P;
     const double s = c.ax[p + 1] * X[p + 1] - c.ax[p] * X[p] + c.ay[p + dy] * Y[p + dy] -
@@ -416,11 +416,10 @@ k_div_DA(Grid g, Coefs<double> c, const double *__restrict__ b, double *__restri
     put_cell<double>(g, out, i, j, k, p, c.vinv[p] != 0.0 ? s / g.h : 0.0);
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_grad_sub(Grid g, Coefs<double> c, const double *__restrict__ psi, const double *bin,
-           double *bout, double scale) {
+__device__ __forceinline__ void grad_sub_body(const Grid &g, const Coefs<double> &c, const double *__restrict__ psi,
+                                              const double *bin, double *bout, double scale, int64_t item) {
     int i, j, k;
-    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    if (!cell_of(g, item, i, j, k)) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
     const double s = scale / g.h;
     const double pp = psi[p];
@@ -440,22 +439,20 @@ __device__ inline double s_row(const Coefs<double> &c, const double *x, int64_t 
            c.az[p] * (xp - x[p - dz]) + c.az[p + dz] * (xp - x[p + dz]);
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_s_apply(Grid g, Coefs<double> c, double w, int resid, const double *__restrict__ f,
-          const double *__restrict__ x, double *__restrict__ y) {
+__device__ __forceinline__ void s_apply_body(const Grid &g, const Coefs<double> &c, double w, int resid,
+                                             const double *__restrict__ f, const double *__restrict__ x,
+                                             double *__restrict__ y, int64_t item) {
     int i, j, k;
-    if (!cell_of(g, xcd_item(), i, j, k)) return;
+    if (!cell_of(g, item, i, j, k)) return;
     const int64_t p = pidx(g, i, j, k);
     double v = w * s_row(c, x, p, g.sy, g.sz);
     if (resid) v = f[p] - v;
     put_cell<double>(g, y, i, j, k, p, c.vinv[p] != 0.0 ? v : 0.0);
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_s_smooth(Grid g, Coefs<double> c, double w, int colour, const double *__restrict__ f,
-           double *__restrict__ x) {
+__device__ __forceinline__ void s_smooth_body(const Grid &g, const Coefs<double> &c, double w, int colour,
+                                              const double *__restrict__ f, double *__restrict__ x, int64_t t) {
     const int nxh = (g.nx + 1) >> 1;
-    const int64_t t = xcd_item();
     if (t >= (int64_t)nxh * g.ny * g.nz) return;
     const int ih = (int)(t % nxh);
     const int64_t r = t / nxh;
@@ -474,11 +471,11 @@ k_s_smooth(Grid g, Coefs<double> c, double w, int colour, const double *__restri
     put_cell<double>(g, x, i, j, k, p, x[p] + (f[p] - w * s_row(c, x, p, dy, dz)) / d);
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_s_restrict(Grid gf, Grid gc, Coefs<double> cc, const double *__restrict__ r,
-             double *__restrict__ fc) {
+__device__ __forceinline__ void s_restrict_body(const Grid &gf, const Grid &gc, const Coefs<double> &cc,
+                                                const double *__restrict__ r, double *__restrict__ fc,
+                                                int64_t item) {
     int I, J, K;
-    if (!cell_of(gc, xcd_item(), I, J, K)) return;
+    if (!cell_of(gc, item, I, J, K)) return;
     const int64_t pc = pidx(gc, I, J, K), q = pidx(gf, 2 * I, 2 * J, 2 * K);
     const int64_t fy = gf.sy, fz = gf.sz;
     double s = 0.0;
@@ -489,13 +486,98 @@ k_s_restrict(Grid gf, Grid gc, Coefs<double> cc, const double *__restrict__ r,
     put_cell<double>(gc, fc, I, J, K, pc, cc.vinv[pc] != 0.0 ? 0.125 * s : 0.0);
 }
 
+__device__ __forceinline__ void s_prolong_body(const Grid &gf, const Grid &gc, const Coefs<double> &cf,
+                                               const double *__restrict__ xc, double *__restrict__ x,
+                                               int64_t item) {
+    int i, j, k;
+    if (!cell_of(gf, item, i, j, k)) return;
+    const int64_t p = pidx(gf, i, j, k);
+    if (cf.vinv[p] != 0.0) put_cell<double>(gf, x, i, j, k, p, x[p] + xc[pidx(gc, i >> 1, j >> 1, k >> 1)]);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_div_DA(Grid g, Coefs<double> c, const double *__restrict__ b, double *__restrict__ out) {
+    div_DA_body(g, c, b, out, xcd_item());
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_grad_sub(Grid g, Coefs<double> c, const double *__restrict__ psi, const double *bin, double *bout, double scale) {
+    grad_sub_body(g, c, psi, bin, bout, scale, xcd_item());
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_s_apply(Grid g, Coefs<double> c, double w, int resid, const double *__restrict__ f,
+          const double *__restrict__ x, double *__restrict__ y) {
+    s_apply_body(g, c, w, resid, f, x, y, xcd_item());
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_s_smooth(Grid g, Coefs<double> c, double w, int colour, const double *__restrict__ f,
+           double *__restrict__ x) {
+    s_smooth_body(g, c, w, colour, f, x, xcd_item());
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_s_restrict(Grid gf, Grid gc, Coefs<double> cc, const double *__restrict__ r,
+             double *__restrict__ fc) {
+    s_restrict_body(gf, gc, cc, r, fc, xcd_item());
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_s_prolong_add(Grid gf, Grid gc, Coefs<double> cf, const double *__restrict__ xc,
                 double *__restrict__ x) {
-    int i, j, k;
-    if (!cell_of(gf, xcd_item(), i, j, k)) return;
-    const int64_t p = pidx(gf, i, j, k);
-    if (cf.vinv[p] != 0.0) put_cell<double>(gf, x, i, j, k, p, x[p] + xc[pidx(gc, i >> 1, j >> 1, k >> 1)]);
+    s_prolong_body(gf, gc, cf, xc, x, xcd_item());
+}
+
+// block forms of the scalar kernels: NR lanes per cell, one vector each
+template <int NR>
+__global__ void __launch_bounds__(kThreads)
+k_div_DA_b(Grid g, Coefs<double> c, VPtr<const double> b, VPtr<double> out) {
+    const int64_t t = xcd_item();
+    const int q = (int)(t % NR);
+    div_DA_body(g, c, b.p[q], out.p[q], t / NR);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kThreads)
+k_grad_sub_b(Grid g, Coefs<double> c, VPtr<const double> psi, VPtr<const double> bin, VPtr<double> bout,
+             double scale) {
+    const int64_t t = xcd_item();
+    const int q = (int)(t % NR);
+    grad_sub_body(g, c, psi.p[q], bin.p[q], bout.p[q], scale, t / NR);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kThreads)
+k_s_apply_b(Grid g, Coefs<double> c, double w, int resid, VPtr<const double> f, VPtr<const double> x,
+            VPtr<double> y) {
+    const int64_t t = xcd_item();
+    const int q = (int)(t % NR);
+    s_apply_body(g, c, w, resid, f.p[q], x.p[q], y.p[q], t / NR);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kThreads)
+k_s_smooth_b(Grid g, Coefs<double> c, double w, int colour, VPtr<const double> f, VPtr<double> x) {
+    const int64_t t = xcd_item();
+    const int q = (int)(t % NR);
+    s_smooth_body(g, c, w, colour, f.p[q], x.p[q], t / NR);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kThreads)
+k_s_restrict_b(Grid gf, Grid gc, Coefs<double> cc, VPtr<const double> r, VPtr<double> fc) {
+    const int64_t t = xcd_item();
+    const int q = (int)(t % NR);
+    s_restrict_body(gf, gc, cc, r.p[q], fc.p[q], t / NR);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kThreads)
+k_s_prolong_add_b(Grid gf, Grid gc, Coefs<double> cf, VPtr<const double> xc, VPtr<double> x) {
+    const int64_t t = xcd_item();
+    const int q = (int)(t % NR);
+    s_prolong_body(gf, gc, cf, xc.p[q], x.p[q], t / NR);
 }
 
 // ---------------------------------------------------------------------------
@@ -988,6 +1070,53 @@ void launch_coarse_solve_b(int n, const double *inv, const int64_t *idx, int nr,
                            const VPtr<T> &x, hipStream_t s) {
     if (n <= 0) return;
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_coarse_solve_b<T, NR>), dim3(n), dim3(kThreads), 0, s, n, inv, idx, f, x))
+}
+
+void launch_div_DA_b(const Grid &g, const double *coef, int nr, const VPtr<const double> &b,
+                     const VPtr<double> &out, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const Coefs<double> c = coefs_of(coef, g.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_div_DA_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, b, out))
+}
+
+void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<const double> &psi,
+                       const VPtr<const double> &b_in, const VPtr<double> &b_out, double scale, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const Coefs<double> c = coefs_of(coef, g.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_grad_sub_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, psi, b_in,
+                                        b_out, scale))
+}
+
+void launch_s_apply_b(const Grid &g, const double *coef, double w, int resid, int nr, const VPtr<const double> &f,
+                      const VPtr<const double> &x, const VPtr<double> &y, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const Coefs<double> c = coefs_of(coef, g.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_apply_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, w, resid,
+                                        f, x, y))
+}
+
+void launch_s_smooth_b(const Grid &g, const double *coef, double w, int colour, int nr, const VPtr<const double> &f,
+                       const VPtr<double> &x, hipStream_t s) {
+    const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
+    const Coefs<double> c = coefs_of(coef, g.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_smooth_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, w, colour,
+                                        f, x))
+}
+
+void launch_s_restrict_b(const Grid &gf, const Grid &gc, const double *coef_c, int nr, const VPtr<const double> &r,
+                         const VPtr<double> &fc, hipStream_t s) {
+    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+    const Coefs<double> cc = coefs_of(coef_c, gc.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_restrict_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cc, r,
+                                        fc))
+}
+
+void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const double *coef_f, int nr,
+                            const VPtr<const double> &xc, const VPtr<double> &x, hipStream_t s) {
+    const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
+    const Coefs<double> cf = coefs_of(coef_f, gf.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_prolong_add_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cf,
+                                        xc, x))
 }
 
 #undef DM_NR_SWITCH

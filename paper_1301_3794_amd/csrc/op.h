@@ -23,6 +23,7 @@ struct Level {
     // block V-cycle buffers: kMaxRhs vectors of 3P each (allocated on first use)
     double *bx64 = nullptr, *bf64 = nullptr, *br64 = nullptr;
     float *bx32 = nullptr, *bf32 = nullptr, *br32 = nullptr;
+    double *bsx = nullptr, *bsf = nullptr, *bsr = nullptr;  // kMaxRhs * P (scalar MG)
     int64_t n_act_faces = 0, n_act_cells = 0;
 };
 
@@ -96,6 +97,9 @@ struct dm_op {
     double *bk_V = nullptr, *bk_Z = nullptr, *bk_w = nullptr;
     double *bk_dres = nullptr, *bk_dcoef = nullptr, *bk_hres = nullptr;
     hipGraphExec_t g_vb32[dm::kMaxRhs + 1] = {}, g_vb64[dm::kMaxRhs + 1] = {};
+    // block projection: per-vector CG state (kMaxRhs * P each) and graphs
+    double *pjb_g = nullptr, *pjb_psi = nullptr, *pjb_p = nullptr, *pjb_q = nullptr;
+    hipGraphExec_t g_svb[dm::kMaxRhs + 1] = {};
     std::vector<void *> allocs;  // everything to free
     int last_proj_iters = 0;
     // learned correction: the attached network (not owned) and its scratch
@@ -137,6 +141,9 @@ void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const
           int64_t n, hipStream_t s);
 int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hipStream_t s,
             int *iters);
+// project() on nr (1..kMaxRhs) vectors in lockstep; iters: nr entries or NULL
+int project_block(dm_op *op, int nr, const double *const *b, double *const *out, double rtol, int maxit,
+                  hipStream_t s, int *iters);
 int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
           dm_solve_info *info, hipStream_t s);
 // nrhs (1..kMaxRhs) systems M x_r = f_r in lockstep, FGMRES modes only;

@@ -421,6 +421,30 @@ void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
         for (int col = 1; col >= 0; --col) launch_s_smooth(g, L.coef64, L.sweight, col, f, x, s);
 }
 
+// svcycle() on nr vectors at once (the level's scalar block slots)
+void svcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
+    Level &L = op->lv[l];
+    const Grid &g = L.g;
+    const int64_t P = g.P;
+    const VPtr<double> F = slots(L.bsf, P, nr), X = slots(L.bsx, P, nr);
+    launch_zero<double>(nr * P, L.bsx, s);
+    if (l == op->nlev() - 1) {
+        launch_coarse_solve_b<double>(op->ns, op->sinv, op->sidx, nr, as_const(F), X, s);
+        for (int q = 0; q < nr; ++q) launch_mirror_cells(g, X.p[q], s);
+        return;
+    }
+    for (int it = 0; it < op->opt.nu_pre; ++it)
+        for (int col = 0; col < 2; ++col) launch_s_smooth_b(g, L.coef64, L.sweight, col, nr, as_const(F), X, s);
+    const VPtr<double> R = slots(L.bsr, P, nr);
+    launch_s_apply_b(g, L.coef64, L.sweight, 1, nr, as_const(F), as_const(X), R, s);
+    Level &C = op->lv[l + 1];
+    launch_s_restrict_b(g, C.g, C.coef64, nr, as_const(R), slots(C.bsf, C.g.P, nr), s);
+    svcycle_b(op, l + 1, nr, s);
+    launch_s_prolong_add_b(g, C.g, L.coef64, nr, as_const(slots(C.bsx, C.g.P, nr)), X, s);
+    for (int it = 0; it < op->opt.nu_post; ++it)
+        for (int col = 1; col >= 0; --col) launch_s_smooth_b(g, L.coef64, L.sweight, col, nr, as_const(F), X, s);
+}
+
 // ---------------------------------------------------------------------------
 // V-cycles replayed from captured HIP graphs.  A V-cycle is a fixed sequence
 // of ~27 launches per level, short on the coarse levels, so per-launch
@@ -459,10 +483,18 @@ void invalidate_graphs(dm_op *op) {
         *e = nullptr;
     }
     for (int q = 0; q <= kMaxRhs; ++q)
-        for (hipGraphExec_t *e : {&op->g_vb32[q], &op->g_vb64[q]}) {
+        for (hipGraphExec_t *e : {&op->g_vb32[q], &op->g_vb64[q], &op->g_svb[q]}) {
             if (*e) (void)hipGraphExecDestroy(*e);
             *e = nullptr;
         }
+}
+
+void ensure_block_results(dm_op *op) {
+    if (!op->bk_dres) {
+        op->bk_dres = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
+        op->bk_dcoef = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
+        DM_HIP(hipHostMalloc((void **)&op->bk_hres, kMaxRhs * kMaxDots * sizeof(double), hipHostMallocDefault));
+    }
 }
 
 void ensure_block(dm_op *op, int prec) {
@@ -473,10 +505,8 @@ void ensure_block(dm_op *op, int prec) {
         op->bk_V = op->dalloc<double>((size_t)(m + 1) * kMaxRhs * n);
         op->bk_Z = op->dalloc<double>((size_t)m * kMaxRhs * n);
         op->bk_w = op->dalloc<double>((size_t)kMaxRhs * n);
-        op->bk_dres = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
-        op->bk_dcoef = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
-        DM_HIP(hipHostMalloc((void **)&op->bk_hres, kMaxRhs * kMaxDots * sizeof(double), hipHostMallocDefault));
     }
+    ensure_block_results(op);
     for (Level &L : op->lv) {
         const size_t cnt = (size_t)kMaxRhs * 3 * L.g.P;
         if (prec == 32 && !L.bx32) {
@@ -567,6 +597,126 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
     launch_grad_sub(g, L.coef64, psi, const_cast<double *>(b), out, 1.0, s);
     if (iters) *iters = it;
     op->last_proj_iters = it;
+    return DM_OK;
+}
+
+// project() on nr vectors in lockstep: the CG iterations of every vector
+// that has not met its stopping test share one block S apply and one block
+// scalar V-cycle per step, and one host sync per inner product.  r and z of
+// vector q live in the level-0 slots of the block scalar V-cycle.
+int project_block(dm_op *op, int nr, const double *const *b, double *const *out, double rtol, int maxit,
+                  hipStream_t s, int *iters) {
+    if (nr < 1 || nr > kMaxRhs) throw DmError{DM_EINVAL, "block of 1 to 4 vectors"};
+    ensure_block_results(op);
+    Level &L = op->lv[0];
+    const Grid &g = L.g;
+    const int64_t P = g.P, n = op->n0();
+    if (!op->pjb_g) {
+        op->pjb_g = op->dalloc<double>((size_t)kMaxRhs * P);
+        op->pjb_psi = op->dalloc<double>((size_t)kMaxRhs * P);
+        op->pjb_p = op->dalloc<double>((size_t)kMaxRhs * P);
+        op->pjb_q = op->dalloc<double>((size_t)kMaxRhs * P);
+    }
+    for (Level &Lv : op->lv)
+        if (!Lv.bsx) {
+            Lv.bsx = op->dalloc<double>((size_t)kMaxRhs * Lv.g.P);
+            Lv.bsf = op->dalloc<double>((size_t)kMaxRhs * Lv.g.P);
+            Lv.bsr = op->dalloc<double>((size_t)kMaxRhs * Lv.g.P);
+        }
+    const VPtr<double> G = slots(op->pjb_g, P, nr), PSI = slots(op->pjb_psi, P, nr), PP = slots(op->pjb_p, P, nr),
+                       Q = slots(op->pjb_q, P, nr), R = slots(L.bsf, P, nr), Z = slots(L.bsx, P, nr);
+    VPtr<const double> B{};
+    for (int q = 0; q < nr; ++q) B.p[q] = b[q];
+    auto dres = [&](int q) { return op->bk_dres + (int64_t)q * kMaxDots; };
+    auto hres = [&](int q) { return op->bk_hres + (int64_t)q * kMaxDots; };
+    auto fetch = [&]() {
+        DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nr * kMaxDots * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+    };
+    auto graph = [&]() {
+        hipGraphExec_t &gx = op->g_svb[nr];
+        if (!gx) gx = capture(op, [&](hipStream_t cs) { svcycle_b(op, 0, nr, cs); });
+        DM_HIP(hipGraphLaunch(gx, s));
+    };
+    launch_div_DA_b(g, L.coef64, nr, B, G, s);
+    for (int q = 0; q < nr; ++q) {
+        if (op->s_floating) demean_cells(op, G.p[q], s);
+        launch_mdot(1, G.p[q], 0, G.p[q], op->cmask, P, op->part, dres(q), s);
+        launch_mdot(1, b[q], 0, b[q], op->wa, n, op->part, dres(q) + 1, s);
+    }
+    fetch();
+    double stop[kMaxRhs], rz[kMaxRhs];
+    bool act[kMaxRhs];
+    int its[kMaxRhs];
+    bool any = false;
+    for (int q = 0; q < nr; ++q) {
+        const double gnorm = std::sqrt(hres(q)[0]);
+        if (!std::isfinite(gnorm)) throw DmError{DM_ENAN, "projection input is not finite"};
+        // stop on the scale of the field, as project() does
+        stop[q] = rtol * std::sqrt(hres(q)[1]) / g.h;
+        act[q] = gnorm > stop[q];
+        its[q] = 0;
+        any = any || act[q];
+    }
+    DM_HIP(hipMemsetAsync(op->pjb_psi, 0, (size_t)nr * P * sizeof(double), s));
+    if (any) {
+        for (int q = 0; q < nr; ++q) launch_copy(P, G.p[q], R.p[q], s);
+        graph();                                   // r -> z, every slot
+        for (int q = 0; q < nr; ++q) {
+            if (op->s_floating) demean_cells(op, Z.p[q], s);
+            launch_copy(P, Z.p[q], PP.p[q], s);
+            launch_mdot(1, R.p[q], 0, Z.p[q], op->cmask, P, op->part, dres(q), s);
+        }
+        fetch();
+        for (int q = 0; q < nr; ++q) rz[q] = hres(q)[0];
+        int it = 0;
+        while (it < maxit) {
+            launch_s_apply_b(g, L.coef64, L.sweight, 0, nr, VPtr<const double>{}, as_const(PP), Q, s);
+            for (int q = 0; q < nr; ++q)
+                if (act[q]) launch_mdot(1, PP.p[q], 0, Q.p[q], op->cmask, P, op->part, dres(q), s);
+            fetch();
+            for (int q = 0; q < nr; ++q) {
+                if (!act[q]) continue;
+                const double pq = hres(q)[0];
+                if (!(pq > 0.0)) {
+                    act[q] = false;
+                    continue;
+                }
+                const double alpha = rz[q] / pq;
+                launch_axpy(P, alpha, PP.p[q], PSI.p[q], s);
+                launch_axpy(P, -alpha, Q.p[q], R.p[q], s);
+                ++its[q];
+                launch_mdot(1, R.p[q], 0, R.p[q], op->cmask, P, op->part, dres(q), s);
+            }
+            ++it;
+            fetch();
+            any = false;
+            for (int q = 0; q < nr; ++q) {
+                if (act[q] && std::sqrt(hres(q)[0]) <= stop[q]) act[q] = false;
+                any = any || act[q];
+            }
+            if (!any) break;
+            graph();                               // r -> z
+            for (int q = 0; q < nr; ++q) {
+                if (!act[q]) continue;
+                if (op->s_floating) demean_cells(op, Z.p[q], s);
+                launch_mdot(1, R.p[q], 0, Z.p[q], op->cmask, P, op->part, dres(q), s);
+            }
+            fetch();
+            for (int q = 0; q < nr; ++q) {
+                if (!act[q]) continue;
+                const double rz2 = hres(q)[0];
+                launch_axpby(P, 1.0, Z.p[q], rz2 / rz[q], PP.p[q], s);
+                rz[q] = rz2;
+            }
+        }
+    }
+    VPtr<double> O{};
+    for (int q = 0; q < nr; ++q) O.p[q] = out[q];
+    launch_grad_sub_b(g, L.coef64, nr, as_const(PSI), B, O, 1.0, s);
+    if (iters)
+        for (int q = 0; q < nr; ++q) iters[q] = its[q];
     return DM_OK;
 }
 
@@ -925,10 +1075,14 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
                     if (rc < 0) return rc;
                     for (int q = 0; q < nr; ++q) inner_its += bi[q].iterations;
                 }
-                for (int c = 0; c < b; ++c) {
-                    double *w = W + (size_t)c * n;
-                    project(op, w, w, opt.proj_rtol, 1000, s, &pj);
-                    proj_its += pj;
+                for (int c0 = 0; c0 < b; c0 += kMaxRhs) {
+                    const int nr = std::min(kMaxRhs, b - c0);
+                    const double *bp[kMaxRhs];
+                    double *op_[kMaxRhs];
+                    int pits[kMaxRhs];
+                    for (int q = 0; q < nr; ++q) bp[q] = op_[q] = W + (size_t)(c0 + q) * n;
+                    project_block(op, nr, bp, op_, opt.proj_rtol, 1000, s, pits);
+                    for (int q = 0; q < nr; ++q) proj_its += pits[q];
                 }
             } else {
                 for (int c = 0; c < b; ++c) {

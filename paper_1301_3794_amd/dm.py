@@ -30,7 +30,7 @@ EXPORTS = (
     "dm_default_options", "dm_build_operator", "dm_destroy", "dm_set_shift",
     "dm_compute_fractions", "dm_field_layout", "dm_get_fractions", "dm_apply",
     "dm_residual", "dm_smooth", "dm_restrict", "dm_prolong_add", "dm_vcycle", "dm_vcycle_block",
-    "dm_project", "dm_solve", "dm_solve_block", "dm_default_eig_options", "dm_eigs", "dm_strerror",
+    "dm_project", "dm_project_block", "dm_solve", "dm_solve_block", "dm_default_eig_options", "dm_eigs", "dm_strerror",
     "dm_last_error_message", "dm_time_kernel", "dm_net_create", "dm_net_destroy",
     "dm_net_get_weights", "dm_net_set_weights", "dm_net_attach", "dm_net_apply",
     "dm_net_loss_grad", "dm_net_make_pair", "dm_net_train", "dm_batch_create", "dm_batch_destroy",
@@ -127,6 +127,7 @@ def lib():
     L.dm_vcycle_block.argtypes = [vp, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.dm_project.argtypes = [vp, vp, vp, d, vp]
     L.dm_solve.argtypes = [vp, i, vp, vp, d, i, ctypes.POINTER(SolveInfo), vp]
+    L.dm_project_block.argtypes = [vp, i, ctypes.POINTER(vp), ctypes.POINTER(vp), d, vp]
     L.dm_solve_block.argtypes = [vp, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp), d, i,
                                  ctypes.POINTER(SolveInfo), vp]
     L.dm_default_eig_options.argtypes = [ctypes.POINTER(EigOptions)]
@@ -367,6 +368,14 @@ class Operator:
         return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
                     rel_residual=info.rel_residual, seconds=info.seconds,
                     learned_accepted=info.learned_accepted, learned_rejected=info.learned_rejected)
+
+    def project_block(self, bs, outs, rtol=1e-13, stream=None):
+        """P_DM b_r for 1..4 vectors in lockstep."""
+        n = len(bs)
+        bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        op_ = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        _check(lib().dm_project_block(self._op, n, bp, op_, float(rtol), _stream(stream)))
+        return outs
 
     def solve_block(self, fs, xs, mode=SOLVE_FGMRES_MG32, rtol=1e-10, maxit=500, stream=None):
         """M x_r = f_r for 1..4 systems in lockstep; one dict per system."""

@@ -13,6 +13,8 @@ coefficient once for all vectors.  Checked through the C ABI:
     direct solve of the oracle's M (1e-9), its reported residual <= rtol,
     iteration counts equal to dm_solve's for the same right-hand side, a
     zero right-hand side (converged at once) inside a block;
+  * dm_project_block, 1..4 vectors: each against the oracle's projection
+    (1e-9) and against dm_project (1e-12), divergence-free to rounding;
   * the eigensolver (which takes the block path for block size 4) still
     matches the oracle's eigenvalues to 1e-10;
   * restarts of FGMRES(4) inside the lockstep, as dm_solve takes them;
@@ -100,6 +102,27 @@ def test_solve_block_matches_direct_and_single(case, mode):
         assert infos[q]["rel_residual"] <= 1e-11
         single = op.solve(fd[q], op.face_tensor(), mode=m, rtol=1e-11, maxit=300)
         assert single["iterations"] == infos[q]["iterations"], (q, single, infos[q])
+
+
+@pytest.mark.parametrize("nr", [1, 3, 4])
+def test_project_block(case, nr):
+    op, oop, n = case["op"], case["oop"], case["n"]
+    bs = [rnd(oop.act, oop.grid.n_faces, 70 + q) for q in range(nr)]
+    if nr == 4:
+        # an already divergence-free vector beside the others (no CG step)
+        bs[3] = np.zeros_like(bs[3])
+        bs[3][oop.act] = oeigs.Projector(oop, tol=1e-14)(bs[0][oop.act])
+    bd = [dev(lay.faces_to_padded(b, n)) for b in bs]
+    outs = op.project_block(bd, [op.face_tensor() for _ in range(nr)], rtol=1e-13)
+    for q in range(nr):
+        got = lay.faces_from_padded(outs[q].cpu().numpy(), n)
+        ref = np.zeros_like(bs[q])
+        ref[oop.act] = oeigs.Projector(oop, tol=1e-13)(bs[q][oop.act])
+        assert rel_inf(got, ref) <= 1e-9, q
+        one = op.project(bd[q], op.face_tensor(), rtol=1e-13)
+        assert rel_inf(got, lay.faces_from_padded(one.cpu().numpy(), n)) <= 1e-12, q
+        div = oop.D @ (oop.a * got)
+        assert np.max(abs(div)) <= 1e-9 * max(np.max(abs(oop.D @ (oop.a * bs[0]))), 1e-300)
 
 
 def test_solve_block_restarts(case):
