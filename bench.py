@@ -41,6 +41,16 @@ MAX_BASIS = 40
 # 9-cell quarter: the PMC planes leave one mode per passband frequency
 # (nondegenerate), so block 2
 C3_BLOCK = 2
+# ... and 4 pre- and post-smoothing sweeps with FGMRES(30): measured 1.45
+# s/pair against 1.79 for 2 sweeps with FGMRES(50) (about 75 inner
+# iterations per inversion there, so orthogonalisation dominated)
+C3_NU = 4
+C3_RESTART = 30
+# The learned form's inner solves stop at 3e-12 instead of 1e-11: with
+# 1e-11 its eigen-residuals of the triplet stalled at 1.1e-10 .. 3.8e-10
+# (block 3 or 4, 20 restarts), while the FP32-multigrid form reaches
+# 5.6e-11 with 1e-11.
+LEARNED_INNER_RTOL = 3e-12
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per cell (3 face unknowns) of the FP32 kernels: every
@@ -49,16 +59,35 @@ HBM_PEAK_GBS = 8000.0
 #   apply   y = M x      : x(3) coef(7) y(3)            = 13 words
 #   red-black sweep (6 class updates): x(3) f(3) coef(7) read, x(3) written = 16 words
 BYTES_PER_CELL = {"residual": 16 * 4, "apply": 13 * 4, "sweep": 16 * 4}
+
+
+def block_sweep_bytes_per_cell(nr):
+    """The block sweep on nr vectors: coef(7) read once, x(3) f(3) read and
+    x(3) written per vector."""
+    return (7 + 9 * nr) * 4
+
+
+# The same counted only where a row needs it (128^3 sphere): 1 B row class
+# per cell; per cell with a cut row (121,284 cells) coef(7) once and 9 words
+# per vector; 12 B per vector for each active component of a vacuum-only
+# cell (2,129,808 components in 709,936 cells).  One vector: 35,417,024 B
+# per sweep against 134,217,728 B for the box count.
+SWEEP_CUT_CELLS = 121284
+SWEEP_VACUUM_COMPONENTS = 2129808
+
+
+def strict_sweep_bytes(nr, cells):
+    return cells + SWEEP_CUT_CELLS * (28 + 36 * nr) + SWEEP_VACUUM_COMPONENTS * 12 * nr
 # FP32 V-cycle, nu = 2/2: on the fine level 4 sweeps + residual + restriction
 # + prolongation = 4*64 + 64 + 13.5 + 25.5 = 359 B per cell, times 8/7 for
 # the coarser levels
 VCYCLE_BYTES_PER_CELL = 359.0 * 8.0 / 7.0
-# HBM bytes per FP32 sweep on the 128^3 sphere's finest level, from
-# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of `bench.py --only
-# traffic`, each counter scaled by its reading for a 256 MiB copy (reads
-# x2.000, writes x1.000): 231,031 KiB.  Valid for the smoother kernel as of
-# those runs; set to None when k_smooth changes.
-SWEEP_TRAFFIC_BYTES = 231031 * 1024
+# HBM bytes per FP32 block sweep (BLOCK = 3 vectors) on the 128^3 sphere's
+# finest level, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of
+# `bench.py --only traffic`, each counter scaled by its reading for a 256 MiB
+# copy (reads x2.000, writes x1.000): 404,336 + 62,242 KiB.  Valid for the
+# smoother kernel as of those runs; set to None when k_smooth_b changes.
+BLOCK_SWEEP_TRAFFIC_BYTES = 466578 * 1024
 
 
 def log(msg):
@@ -115,7 +144,8 @@ def run_c3(dm, torch):
     geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
                            bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
     t0 = time.perf_counter()
-    op = dm.Operator(geom, (nxy, nxy, nz), h, 632.0, levels=0, fgmres_restart=50)
+    op = dm.Operator(geom, (nxy, nxy, nz), h, 632.0, levels=0, fgmres_restart=C3_RESTART, nu_pre=C3_NU,
+                     nu_post=C3_NU)
     setup = time.perf_counter() - t0
     try:
         ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=20)
@@ -131,7 +161,7 @@ def run_c3(dm, torch):
         return {"grid": [nxy, nxy, nz], "levels": lay["levels"], "active_faces": lay["active_faces"],
                 "setup_s": round(setup, 2), "sweep_ms": ms_sweep, "sweep_GBps": round(gbs, 1),
                 "sweep_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-                "block": C3_BLOCK, "status": out["status"], "s_per_eigenpair": dt / 9, "lam": out["lam"].tolist(),
+                "block": C3_BLOCK, "nu": C3_NU, "fgmres_restart": C3_RESTART, "status": out["status"], "s_per_eigenpair": dt / 9, "lam": out["lam"].tolist(),
                 "max_residual": out["max_residual"], "outer_iterations": out["outer_iterations"],
                 "inner_iterations": out["inner_iterations"], "restarts": out["restarts"]}
     finally:
@@ -177,7 +207,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the data-parallel sharding is described in DESIGN.md)", file=sys.stderr)
+              "(one GPU holds the whole grid; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -200,9 +230,9 @@ def main():
         c.copy_(a)
         torch.cuda.synchronize()
         op = dm.Operator(dm.sphere((0.5, 0.5, 0.5), R), (N, N, N), 1.0 / N, SIGMA, levels=LEVELS)
-        ms = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=3)
-        print(json.dumps({"copy_bytes_each_way": 4 * n, "sweep_ms": ms, "sweep_launches": 2 + 3,
-                          "classes_per_sweep": 6, "cells": N ** 3}))
+        ms = op.time_block_kernel(dm.KERNEL_SWEEP, BLOCK, prec=32, level=0, reps=3)
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "block_sweep_ms": ms, "vectors": BLOCK,
+                          "sweep_launches": 2 + 3, "classes_per_sweep": 6, "cells": N ** 3}))
         op.close()
         return
     t0 = time.perf_counter()
@@ -210,9 +240,9 @@ def main():
     setup_s = time.perf_counter() - t0
     lay = op.layout(0)
 
-    def solve(mode):
+    def solve(mode, inner_rtol=1e-11):
         out = op.eigs(K_EIG, sigma=SIGMA, tol=TOL, seed=SEED, solve_mode=mode, block=BLOCK,
-                      max_basis=MAX_BASIS, verbose=int(args.verbose))
+                      max_basis=MAX_BASIS, inner_rtol=inner_rtol, verbose=int(args.verbose))
         if out["status"] != 0:
             raise RuntimeError(f"eigensolve did not converge: {out}")
         return out
@@ -256,10 +286,10 @@ def main():
         net.attach(op)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        ol = solve(dm.SOLVE_FGMRES_MG32_LEARNED)
+        ol = solve(dm.SOLVE_FGMRES_MG32_LEARNED, inner_rtol=LEARNED_INNER_RTOL)
         torch.cuda.synchronize()
         dl = time.perf_counter() - t1
-        forms["learned"] = dict(s_per_eigenpair=dl / K_EIG, lam=ol["lam"].tolist(),
+        forms["learned"] = dict(s_per_eigenpair=dl / K_EIG, lam=ol["lam"].tolist(), inner_rtol=LEARNED_INNER_RTOL,
                                 max_residual=ol["max_residual"],
                                 inner_iterations=ol["inner_iterations"],
                                 outer_iterations=ol["outer_iterations"],
@@ -274,17 +304,27 @@ def main():
         for f in forms.values():
             f["rel_err_vs_oracle"] = (abs(np.array(f["lam"]) - ref) / ref).tolist()
 
-    # roofline of the dominant kernel: the FP32 red-black sweep on the finest level
-    ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=50)
+    # roofline of the dominant kernel: the FP32 block red-black sweep (the
+    # BLOCK vectors of one Krylov-Schur step) on the finest level, timed with
+    # HIP events on the op's stream
     cells = N ** 3
-    achieved = BYTES_PER_CELL["sweep"] * cells / (ms_sweep * 1e-3) / 1e9
+    ms_bsweep = op.time_block_kernel(dm.KERNEL_SWEEP, BLOCK, prec=32, level=0, reps=50)
+    bytes_b = block_sweep_bytes_per_cell(BLOCK) * cells
+    achieved = bytes_b / (ms_bsweep * 1e-3) / 1e9
+    ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=50)
     ms_vc = op.time_kernel(dm.KERNEL_VCYCLE, prec=32, level=0, reps=20)
+    ms_bvc = op.time_block_kernel(dm.KERNEL_VCYCLE, BLOCK, prec=32, level=0, reps=20)
     ms_res = op.time_kernel(dm.KERNEL_RESIDUAL, prec=32, level=0, reps=50)
-    roofline = {"bound": "hbm", "kernel": "red-black sweep (6 class updates), FP32, 128^3",
+    strict_b = strict_sweep_bytes(BLOCK, cells)
+    roofline = {"bound": "hbm", "kernel": f"block red-black sweep (6 class updates, {BLOCK} vectors), FP32, 128^3",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": SWEEP_TRAFFIC_BYTES,
-                "ms_per_launch": ms_sweep, "bytes_per_launch": BYTES_PER_CELL["sweep"] * cells,
-                "vcycle_ms": ms_vc, "residual_ms": ms_res,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": BLOCK_SWEEP_TRAFFIC_BYTES,
+                "ms_per_launch": ms_bsweep, "bytes_per_launch": bytes_b,
+                "strict_bytes_per_launch": strict_b,
+                "strict_frac": round(strict_b / (ms_bsweep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "single_vector_sweep_ms": ms_sweep,
+                "single_vector_sweep_GBps": round(BYTES_PER_CELL["sweep"] * cells / (ms_sweep * 1e-3) / 1e9, 1),
+                "vcycle_ms": ms_vc, "block_vcycle_ms": ms_bvc, "residual_ms": ms_res,
                 "residual_GBps": BYTES_PER_CELL["residual"] * cells / (ms_res * 1e-3) / 1e9}
 
     c3 = None

@@ -407,6 +407,10 @@ int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float 
  * memory.  Errors: DM_EINVAL, DM_ENOMEM, DM_EHIP. */
 int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps,
                    double *ms_per_launch);
+/* The same for the block form of `kernel` on nrhs (1..4) vectors (the
+ * kernels of dm_vcycle_block; DM_KERNEL_VCYCLE replays its graph). */
+int dm_time_block_kernel(dm_op *op, int kernel, int prec, int level, int nrhs, int reps,
+                         double *ms_per_launch);
 
 /* ---- diagnostics -------------------------------------------------------- */
 const char *dm_strerror(int code);

@@ -776,11 +776,14 @@ int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float 
     });
 }
 
-int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double *ms_per_launch) {
+// nrhs == 0: the one-vector kernels; 1..kMaxRhs: their block forms
+static int time_kernel_impl(dm_op *op, int kernel, int prec, int level, int nrhs, int reps,
+                            double *ms_per_launch) {
     if (!op || !ms_per_launch) return fail(DM_EINVAL, "NULL argument");
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
     if (kernel < DM_KERNEL_APPLY || kernel > DM_KERNEL_VCYCLE) return fail(DM_EINVAL, "unknown kernel");
     if (reps < 1) return fail(DM_EINVAL, "reps must be >= 1");
+    if (nrhs < 0 || nrhs > kMaxRhs) return fail(DM_EINVAL, "nrhs must be 1..4");
     const bool pair = kernel == DM_KERNEL_RESTRICT || kernel == DM_KERNEL_PROLONG;
     if (level < 0 || level >= op->nlev() || (pair && level + 1 >= op->nlev()) ||
         (kernel == DM_KERNEL_VCYCLE && level != 0))
@@ -789,6 +792,7 @@ int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double 
         DM_HIP(hipSetDevice(op->device));
         hipStream_t s = op->stream;
         const Level &L = op->lv[level];
+        const int nv = std::max(nrhs, 1);
         const int64_t n = 3 * L.g.P;
         const int64_t nc = pair ? 3 * op->lv[level + 1].g.P : 0;
         const size_t es = prec == 64 ? sizeof(double) : sizeof(float);
@@ -801,7 +805,8 @@ int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double 
         };
         int rc = DM_OK;
         try {
-            void *x = alloc(n), *f = alloc(n), *y = alloc(n), *c = alloc(std::max(nc, (int64_t)1));
+            char *x = (char *)alloc(nv * n), *f = (char *)alloc(nv * n), *y = (char *)alloc(nv * n);
+            char *c = (char *)alloc(std::max(nv * nc, (int64_t)1));
             double *g64 = nullptr;
             DM_HIP(hipMalloc((void **)&g64, n * sizeof(double)));
             tmp.push_back(g64);
@@ -812,16 +817,17 @@ int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double 
             DM_HIP(hipMalloc((void **)&mask, n * sizeof(double)));
             tmp.push_back(mask);
             DM_HIP(hipMemcpyAsync(mask, m.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
-            for (int q = 0; q < 2; ++q) {
-                launch_randn(n, 97 + q, 0, mask, g64, s);
-                void *dst = q == 0 ? x : f;
-                if (prec == 64) launch_copy(n, g64, (double *)dst, s);
-                else launch_cast<double, float>(g64, (float *)dst, n, s);
-            }
-            DM_HIP(hipMemsetAsync(y, 0, n * es, s));
-            DM_HIP(hipMemsetAsync(c, 0, std::max(nc, (int64_t)1) * es, s));
-            auto launch = [&]() {
-                const Level &C = op->lv[std::min(level + 1, op->nlev() - 1)];
+            for (int v = 0; v < nv; ++v)
+                for (int q = 0; q < 2; ++q) {
+                    launch_randn(n, 97 + 2 * v + q, 0, mask, g64, s);
+                    char *dst = (q == 0 ? x : f) + v * n * es;
+                    if (prec == 64) launch_copy(n, g64, (double *)dst, s);
+                    else launch_cast<double, float>(g64, (float *)dst, n, s);
+                }
+            DM_HIP(hipMemsetAsync(y, 0, nv * n * es, s));
+            DM_HIP(hipMemsetAsync(c, 0, std::max(nv * nc, (int64_t)1) * es, s));
+            const Level &C = op->lv[std::min(level + 1, op->nlev() - 1)];
+            auto one = [&]() {
                 switch (kernel) {
                     case DM_KERNEL_APPLY:
                     case DM_KERNEL_RESIDUAL: {
@@ -850,6 +856,44 @@ int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double 
                         break;
                 }
             };
+            auto block = [&](auto tag) {
+                using T = decltype(tag);
+                VPtr<T> X{}, F{}, Y{}, Cc{};
+                for (int v = 0; v < nrhs; ++v) {
+                    X.p[v] = (T *)x + v * n;
+                    F.p[v] = (T *)f + v * n;
+                    Y.p[v] = (T *)y + v * n;
+                    Cc.p[v] = (T *)c + v * nc;
+                }
+                const T *coef = prec == 64 ? (const T *)L.coef64 : (const T *)L.coef32;
+                const T *ccoef = prec == 64 ? (const T *)C.coef64 : (const T *)C.coef32;
+                switch (kernel) {
+                    case DM_KERNEL_APPLY:
+                    case DM_KERNEL_RESIDUAL:
+                        launch_apply_b<T>(L.g, coef, (T)op->sigma, kernel == DM_KERNEL_APPLY ? AK_M : AK_RESID, nrhs,
+                                          as_const(F), as_const(X), Y, s);
+                        break;
+                    case DM_KERNEL_SMOOTH:
+                    case DM_KERNEL_SWEEP:
+                        for (int q = 0; q < (kernel == DM_KERNEL_SMOOTH ? 1 : 6); ++q)
+                            launch_smooth_b<T>(L.g, coef, (T)op->sigma, q / 2, q % 2, nrhs, as_const(F), X, s);
+                        break;
+                    case DM_KERNEL_RESTRICT:
+                        launch_restrict_b<T>(L.g, C.g, ccoef, nrhs, as_const(X), Cc, s);
+                        break;
+                    case DM_KERNEL_PROLONG:
+                        launch_prolong_add_b<T>(L.g, C.g, coef, ccoef, nrhs, as_const(Cc), Y, s);
+                        break;
+                    case DM_KERNEL_VCYCLE:
+                        vcycle_block_graphed(op, prec, nrhs, s);
+                        break;
+                }
+            };
+            auto launch = [&]() {
+                if (nrhs == 0) one();
+                else if (prec == 64) block(double{});
+                else block(float{});
+            };
             launch();
             launch();
             hipEvent_t e0, e1;
@@ -874,6 +918,15 @@ int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double 
         for (void *p : tmp) hipFree(p);
         return rc;
     });
+}
+
+int dm_time_kernel(dm_op *op, int kernel, int prec, int level, int reps, double *ms_per_launch) {
+    return time_kernel_impl(op, kernel, prec, level, 0, reps, ms_per_launch);
+}
+
+int dm_time_block_kernel(dm_op *op, int kernel, int prec, int level, int nrhs, int reps, double *ms_per_launch) {
+    if (nrhs < 1) return fail(DM_EINVAL, "nrhs must be 1..4");
+    return time_kernel_impl(op, kernel, prec, level, nrhs, reps, ms_per_launch);
 }
 
 }  // extern "C"

@@ -31,7 +31,7 @@ EXPORTS = (
     "dm_compute_fractions", "dm_field_layout", "dm_get_fractions", "dm_apply",
     "dm_residual", "dm_smooth", "dm_restrict", "dm_prolong_add", "dm_vcycle", "dm_vcycle_block",
     "dm_project", "dm_project_block", "dm_solve", "dm_solve_block", "dm_default_eig_options", "dm_eigs", "dm_strerror",
-    "dm_last_error_message", "dm_time_kernel", "dm_net_create", "dm_net_destroy",
+    "dm_last_error_message", "dm_time_kernel", "dm_time_block_kernel", "dm_net_create", "dm_net_destroy",
     "dm_net_get_weights", "dm_net_set_weights", "dm_net_attach", "dm_net_apply",
     "dm_net_loss_grad", "dm_net_make_pair", "dm_net_train", "dm_batch_create", "dm_batch_destroy",
     "dm_batch_member", "dm_batch_info", "dm_batch_vcycle", "dm_batch_time_vcycle", "dm_batch_eigs",
@@ -135,6 +135,7 @@ def lib():
     L.dm_eigs.argtypes = [vp, i, d, d, ctypes.c_uint64, ctypes.POINTER(EigOptions), dp, vp, dp,
                           ctypes.POINTER(EigInfo), vp]
     L.dm_time_kernel.argtypes = [vp, i, i, i, i, dp]
+    L.dm_time_block_kernel.argtypes = [vp, i, i, i, i, i, ctypes.POINTER(d)]
     L.dm_strerror.argtypes = [i]
     L.dm_strerror.restype = ctypes.c_char_p
     L.dm_last_error_message.argtypes = []
@@ -387,6 +388,12 @@ class Operator:
                                          _stream(stream)), allow_warning=True)
         return [dict(status=rc, iterations=q.iterations, restarts=q.restarts, rel_residual=q.rel_residual,
                      seconds=q.seconds) for q in info]
+
+    def time_block_kernel(self, kernel, nrhs, prec=32, level=0, reps=50):
+        """Milliseconds per launch of the block form of a kernel on nrhs vectors."""
+        ms = ctypes.c_double()
+        _check(lib().dm_time_block_kernel(self._op, kernel, prec, level, int(nrhs), reps, ctypes.byref(ms)))
+        return ms.value
 
     def time_kernel(self, kernel, prec=32, level=0, reps=50):
         """Milliseconds per launch of a library kernel (HIP events)."""

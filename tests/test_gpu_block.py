@@ -183,3 +183,14 @@ def test_block_pmc_vcycle():
                                  [op.face_tensor(dtype=dt) for _ in range(3)])
             for q in range(3):
                 assert rel_inf(lay.faces_from_padded(xs[q].double().cpu().numpy(), NH), vc(fs[q])) <= tol
+
+
+def test_time_block_kernel(case):
+    dm, op = case["dm"], case["op"]
+    for kernel in (dm.KERNEL_APPLY, dm.KERNEL_RESIDUAL, dm.KERNEL_SMOOTH, dm.KERNEL_SWEEP, dm.KERNEL_RESTRICT,
+                   dm.KERNEL_PROLONG, dm.KERNEL_VCYCLE):
+        for prec in (32, 64):
+            assert op.time_block_kernel(kernel, 3, prec=prec, level=0, reps=2) > 0.0
+    for bad in (0, 5):
+        with pytest.raises(dm.DMError):
+            op.time_block_kernel(dm.KERNEL_SWEEP, bad)
