@@ -52,6 +52,7 @@ C3_RESTART = 30
 # 5.6e-11 with 1e-11.
 LEARNED_INNER_RTOL = 3e-12
 HBM_PEAK_GBS = 8000.0
+CPU_N = 40      # grid of the oracle's timed sample
 
 # Algorithmic bytes per cell (3 face unknowns) of the FP32 kernels: every
 # array the kernel must read or write, each counted once.
@@ -114,15 +115,16 @@ def parse():
 
 def cpu_baseline():
     """The oracle (block shift-invert Lanczos + Jacobi-CG, projection by CG)
-    on a bounded sample of the workload: the same sphere at 32^3, k = 6,
-    rho <= 1e-10, on one host thread.  Scaled to the 128^3 workload by the
-    ratio of active faces (linear: a lower bound, since the oracle's CG
-    iteration count grows with resolution)."""
+    on a bounded sample of the workload: the same sphere at CPU_N^3, k = 6,
+    rho <= 1e-10, on one host thread (about 15-20 s on the GPU host).
+    Scaled to the 128^3 workload by the ratio of active faces (linear: a
+    lower bound, since the oracle's CG iteration count grows with
+    resolution)."""
     import numpy as np  # noqa: F401
     from threadpoolctl import threadpool_limits
 
     from oracle import eigs as oeigs, geometry as geo, operators as ops
-    n = 32
+    n = CPU_N
     with threadpool_limits(1):
         fr = geo.fractions(geo.sphere((0.5, 0.5, 0.5), R), (n, n, n), 1.0 / n)
         op = ops.build(fr, (n, n, n), 1.0 / n, 5.0)
@@ -344,7 +346,7 @@ def main():
         scale = lay["active_faces"] / cb["sample_active_faces"]
         cpu = {"value": cb["sample_seconds"] / K_EIG * scale, "unit": "s/eigenpair", "cores": 1,
                "kind": "oracle",
-               "sample": (f"oracle eigensolve of the same sphere at 32^3 (k={K_EIG}, rho<=1e-10, "
+               "sample": (f"oracle eigensolve of the same sphere at {CPU_N}^3 (k={K_EIG}, rho<=1e-10, "
                           f"{cb['sample_seconds']:.1f} s, {cb['sample_active_faces']} active faces), "
                           f"scaled x{scale:.1f} by active faces to 128^3 (lower bound)")}
 
