@@ -94,7 +94,7 @@ struct dm_op {
     // column j of system r at bk_V + (j * nrhs + r) * n0; per-system device
     // results / coefficients (kMaxDots each) and pinned host results
     int bk_m = 0;
-    double *bk_V = nullptr, *bk_Z = nullptr, *bk_w = nullptr;
+    double *bk_V = nullptr, *bk_Z = nullptr;
     double *bk_dres = nullptr, *bk_dcoef = nullptr, *bk_hres = nullptr;
     hipGraphExec_t g_vb32[dm::kMaxRhs + 1] = {}, g_vb64[dm::kMaxRhs + 1] = {};
     // block projection: per-vector CG state (kMaxRhs * P each) and graphs

@@ -116,13 +116,27 @@ void demean_cells(dm_op *op, double *x, hipStream_t s) {
 }
 
 
+// FGMRES(m), right-preconditioned.  The basis is kept unnormalised: column
+// u_i of V stands for v_i = sc[i] u_i, and the preconditioner output Z_i for
+// z_i = sc[i] Z_i (the V-cycles and the learned correction are equivariant
+// under scaling, and FGMRES accepts any z_i).  The scales are folded into the
+// host-side coefficients, so a step makes two passes over the basis:
+// (1) d = U^T w; (2) w -= U c fused with d2 = U^T w and |w|^2.  The product
+// w = M Z_j is formed in the next column's slot and stays there as u_{j+1}.
+// A third pass (w -= U c2, classical Gram--Schmidt's second correction) runs
+// only when the remaining projection |h2| exceeds kReorth of the new
+// column's norm; otherwise the Arnoldi relation M z_j = V h + hn v_{j+1}
+// holds with the first-pass coefficients and the basis keeps orthogonality
+// to 1e-10.  Convergence is always confirmed by the true residual.
+constexpr double kReorth = 1e-10;
+
 int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
            dm_solve_info *info, hipStream_t s) {
     ensure_krylov(op);
     const Level &L = op->lv[0];
     const int64_t n = op->n0();
     const int m = op->fg_m;
-    double *V = op->fg_V, *Z = op->fg_Z, *w = op->fg_w;
+    double *V = op->fg_V, *Z = op->fg_Z;
     DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
     const double bnorm = std::sqrt(dot1(op, f, f, nullptr, n, s));
     int total = 0, restarts = 0;
@@ -132,7 +146,10 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
         return DM_OK;
     }
     if (!std::isfinite(bnorm)) throw DmError{DM_ENAN, "right-hand side is not finite"};
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1);
+    // c, c3, cx: coefficients of passes (2), (3) and of the update of x, each
+    // in its own host array (a queued copy never reads an overwritten array)
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1), c(m + 1),
+        c3(m + 1), cx(m + 1), sc(m + 1);
     bool conv = false;
     while (true) {
         if (total == 0) launch_copy(n, f, V, s);
@@ -145,43 +162,58 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
             break;
         }
         if (total >= maxit) break;
-        launch_scale(n, 1.0 / beta, V, s);
+        sc[0] = 1.0 / beta;
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         std::fill(H.begin(), H.end(), 0.0);
         int j = 0;
         for (; j < m;) {
-            double *vj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n;
-            precondition(op, mode, vj, zj, s);
+            double *uj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
+            precondition(op, mode, uj, zj, s);
             launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, zj, w, s);
-            // classical Gram--Schmidt twice, in three passes over the basis:
-            // (1) h = V^T w; (2) w -= V h fused with h2 = V^T w, |w|^2;
-            // (3) v_{j+1} = (w - V h2) / |w - V h2|, the norm from Pythagoras
-            // (h2 is the tiny re-orthogonalisation correction)
+            // (1) d = U^T w; true coefficients h_i = sc_i sc_j d_i
             dots(op, j + 1, V, n, w, nullptr, n, s);
-            std::copy(op->hres, op->hres + j + 1, h.begin());
-            to_device_coef(op, h.data(), j + 1, s);
+            for (int i = 0; i <= j; ++i) {
+                h[i] = sc[i] * sc[j] * op->hres[i];
+                c[i] = sc[i] * sc[i] * op->hres[i];
+            }
+            to_device_coef(op, c.data(), j + 1, s);
+            // (2) w -= U c, then d2 = U^T w and |w|^2
             double wn2;
             if (j + 1 <= 32) {
                 launch_maxpy_mdot_norm(j + 1, V, n, op->dcoef, w, n, op->part, op->dres, s);
                 DM_HIP(hipMemcpyAsync(op->hres, op->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
                 DM_HIP(hipStreamSynchronize(s));
-                std::copy(op->hres, op->hres + j + 1, h2.begin());
                 wn2 = op->hres[j + 1];
             } else {
                 launch_maxpy(j + 1, V, n, op->dcoef, w, n, 0, s);
-                dots(op, j + 1, V, n, w, nullptr, n, s);
-                std::copy(op->hres, op->hres + j + 1, h2.begin());
-                wn2 = dot1(op, w, w, nullptr, n, s);
+                launch_mdot(j + 1, V, n, w, nullptr, n, op->part, op->dres, s);
+                launch_mdot(1, w, 0, w, nullptr, n, op->part, op->dres + j + 1, s);
+                DM_HIP(hipMemcpyAsync(op->hres, op->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+                DM_HIP(hipStreamSynchronize(s));
+                wn2 = op->hres[j + 1];
             }
+            wn2 *= sc[j] * sc[j];
             double c2 = 0.0;
             for (int i = 0; i <= j; ++i) {
-                h[i] += h2[i];
+                h2[i] = sc[i] * sc[j] * op->hres[i];
                 c2 += h2[i] * h2[i];
             }
-            const double hn = std::sqrt(std::max(wn2 - c2, 0.0));
+            double hn;
+            if (c2 > kReorth * kReorth * wn2) {
+                // (3) second classical Gram--Schmidt correction
+                for (int i = 0; i <= j; ++i) {
+                    c3[i] = sc[i] * sc[i] * op->hres[i];
+                    h[i] += h2[i];
+                }
+                to_device_coef(op, c3.data(), j + 1, s);
+                launch_maxpy(j + 1, V, n, op->dcoef, w, n, 0, s);
+                hn = std::sqrt(std::max(wn2 - c2, 0.0));
+            } else {
+                hn = std::sqrt(wn2);
+            }
             if (!std::isfinite(hn)) throw DmError{DM_ENAN, "FGMRES iterate is not finite"};
-            to_device_coef(op, h2.data(), j + 1, s);
+            sc[j + 1] = hn > 0.0 ? sc[j] / hn : 0.0;
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
             H[(size_t)(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
@@ -199,16 +231,15 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
             g[j] = cs[j] * g[j];
             ++total;
             ++j;
-            if (hn > 0.0) launch_maxpy_scale(j, V, n, op->dcoef, w, 1.0 / hn, V + (int64_t)j * n, n, s);
             if (std::fabs(g[j]) <= rtol * bnorm || total >= maxit || hn == 0.0) break;
         }
         for (int i = j - 1; i >= 0; --i) {
             double t = g[i];
-            for (int c = i + 1; c < j; ++c) t -= H[(size_t)i * m + c] * y[c];
+            for (int k = i + 1; k < j; ++k) t -= H[(size_t)i * m + k] * y[k];
             y[i] = t / H[(size_t)i * m + i];
         }
-        for (int i = 0; i < j; ++i) h[i] = -y[i];
-        to_device_coef(op, h.data(), j, s);
+        for (int i = 0; i < j; ++i) cx[i] = -y[i] * sc[i];   // x += sum y_i z_i, z_i = sc_i Z_i
+        to_device_coef(op, cx.data(), j, s);
         launch_maxpy(j, Z, n, op->dcoef, x, n, 0, s);
         ++restarts;
     }
@@ -504,7 +535,6 @@ void ensure_block(dm_op *op, int prec) {
         op->bk_m = m;
         op->bk_V = op->dalloc<double>((size_t)(m + 1) * kMaxRhs * n);
         op->bk_Z = op->dalloc<double>((size_t)m * kMaxRhs * n);
-        op->bk_w = op->dalloc<double>((size_t)kMaxRhs * n);
     }
     ensure_block_results(op);
     for (Level &L : op->lv) {
@@ -768,7 +798,7 @@ struct BlockRhs {
     double bnorm = 0.0, rel = 0.0;
     int total = 0, restarts = 0, j = 0;
     bool open = false, done = false, conv = false;
-    std::vector<double> H, cs, sn, g, y, h, h2;
+    std::vector<double> H, cs, sn, g, y, h, h2, c, c3, cx, sc;   // c, c3, cx as in fgmres()
 };
 
 int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *const *x, double rtol, int maxit,
@@ -780,7 +810,6 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
     const int64_t ld = (int64_t)nb * n;   // stride between the columns of one system
     auto Vc = [&](int r, int j) { return op->bk_V + (int64_t)j * ld + (int64_t)r * n; };
     auto Zc = [&](int r, int j) { return op->bk_Z + (int64_t)j * ld + (int64_t)r * n; };
-    auto Wr = [&](int r) { return op->bk_w + (int64_t)r * n; };
     auto dres = [&](int r) { return op->bk_dres + (int64_t)r * kMaxDots; };
     auto dcoef = [&](int r) { return op->bk_dcoef + (int64_t)r * kMaxDots; };
     auto hres = [&](int r) { return op->bk_hres + (int64_t)r * kMaxDots; };
@@ -802,6 +831,10 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         R.y.assign(m, 0.0);
         R.h.assign(m + 1, 0.0);
         R.h2.assign(m + 1, 0.0);
+        R.c.assign(m + 1, 0.0);
+        R.c3.assign(m + 1, 0.0);
+        R.cx.assign(m + 1, 0.0);
+        R.sc.assign(m + 1, 0.0);
         DM_HIP(hipMemsetAsync(R.x, 0, n * sizeof(double), s));
         launch_mdot(1, R.f, 0, R.f, nullptr, n, op->part, dres(r), s);
     }
@@ -850,7 +883,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                     R.done = true;
                     continue;
                 }
-                launch_scale(n, 1.0 / beta, Vc(r, 0), s);
+                R.sc[0] = 1.0 / beta;   // unnormalised basis, as in fgmres()
                 std::fill(R.g.begin(), R.g.end(), 0.0);
                 R.g[0] = beta;
                 std::fill(R.H.begin(), R.H.end(), 0.0);
@@ -871,42 +904,57 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             vin[q] = Vc(r, st[r].j);
             zout[q] = Zc(r, st[r].j);
             zc.p[q] = zout[q];
-            wv.p[q] = Wr(r);
+            wv.p[q] = Vc(r, st[r].j + 1);          // w = M Z_j in the next column's slot
         }
         precondition_block(op, mode, na, vin, zout, s);
         launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s);
-        // classical Gram--Schmidt twice, as in fgmres(): (1) h = V^T w
-        for (int r : act) launch_mdot(st[r].j + 1, Vc(r, 0), ld, Wr(r), nullptr, n, op->part, dres(r), s);
+        // Gram--Schmidt as in fgmres(): (1) d = U^T w
+        for (int r : act) launch_mdot(st[r].j + 1, Vc(r, 0), ld, Vc(r, st[r].j + 1), nullptr, n, op->part, dres(r), s);
         fetch();
-        // (2) w -= V h, then h2 = V^T w and |w|^2
+        // (2) w -= U c, then d2 = U^T w and |w|^2
         for (int r : act) {
             BlockRhs &R = st[r];
             const int j = R.j;
-            std::copy(hres(r), hres(r) + j + 1, R.h.begin());
-            DM_HIP(hipMemcpyAsync(dcoef(r), R.h.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+            double *w = Vc(r, j + 1);
+            for (int i = 0; i <= j; ++i) {
+                R.h[i] = R.sc[i] * R.sc[j] * hres(r)[i];
+                R.c[i] = R.sc[i] * R.sc[i] * hres(r)[i];
+            }
+            DM_HIP(hipMemcpyAsync(dcoef(r), R.c.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
             if (j + 1 <= 32) {
-                launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dcoef(r), Wr(r), n, op->part, dres(r), s);
+                launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dcoef(r), w, n, op->part, dres(r), s);
             } else {
-                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), Wr(r), n, 0, s);
-                launch_mdot(j + 1, Vc(r, 0), ld, Wr(r), nullptr, n, op->part, dres(r), s);
-                launch_mdot(1, Wr(r), 0, Wr(r), nullptr, n, op->part, dres(r) + j + 1, s);
+                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), w, n, 0, s);
+                launch_mdot(j + 1, Vc(r, 0), ld, w, nullptr, n, op->part, dres(r), s);
+                launch_mdot(1, w, 0, w, nullptr, n, op->part, dres(r) + j + 1, s);
             }
         }
         fetch();
-        // (3) v_{j+1} = (w - V h2) / |w - V h2|; Hessenberg column, Givens
+        // (3) the second correction where needed; Hessenberg column, Givens
         for (int r : act) {
             BlockRhs &R = st[r];
             int j = R.j;
-            std::copy(hres(r), hres(r) + j + 1, R.h2.begin());
-            const double wn2 = hres(r)[j + 1];
+            double *w = Vc(r, j + 1);
+            const double wn2 = hres(r)[j + 1] * R.sc[j] * R.sc[j];
             double c2 = 0.0;
             for (int i = 0; i <= j; ++i) {
-                R.h[i] += R.h2[i];
+                R.h2[i] = R.sc[i] * R.sc[j] * hres(r)[i];
                 c2 += R.h2[i] * R.h2[i];
             }
-            const double hn = std::sqrt(std::max(wn2 - c2, 0.0));
+            double hn;
+            if (c2 > kReorth * kReorth * wn2) {
+                for (int i = 0; i <= j; ++i) {
+                    R.c3[i] = R.sc[i] * R.sc[i] * hres(r)[i];
+                    R.h[i] += R.h2[i];
+                }
+                DM_HIP(hipMemcpyAsync(dcoef(r), R.c3.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), w, n, 0, s);
+                hn = std::sqrt(std::max(wn2 - c2, 0.0));
+            } else {
+                hn = std::sqrt(wn2);
+            }
             if (!std::isfinite(hn)) throw DmError{DM_ENAN, "FGMRES iterate is not finite"};
-            DM_HIP(hipMemcpyAsync(dcoef(r), R.h2.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+            R.sc[j + 1] = hn > 0.0 ? R.sc[j] / hn : 0.0;
             double *H = R.H.data();
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = R.h[i];
             H[(size_t)(j + 1) * m + j] = hn;
@@ -925,7 +973,6 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             R.g[j] = R.cs[j] * R.g[j];
             ++R.total;
             R.j = ++j;
-            if (hn > 0.0) launch_maxpy_scale(j, Vc(r, 0), ld, dcoef(r), Wr(r), 1.0 / hn, Vc(r, j), n, s);
             const bool close = std::fabs(R.g[j]) <= rtol * R.bnorm || R.total >= maxit || hn == 0.0 || j == m;
             if (!close) continue;
             // end of the cycle: x += Z y, y from the triangular system
@@ -934,8 +981,8 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                 for (int c = i + 1; c < j; ++c) t -= H[(size_t)i * m + c] * R.y[c];
                 R.y[i] = t / H[(size_t)i * m + i];
             }
-            for (int i = 0; i < j; ++i) R.h[i] = -R.y[i];
-            DM_HIP(hipMemcpyAsync(dcoef(r), R.h.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+            for (int i = 0; i < j; ++i) R.cx[i] = -R.y[i] * R.sc[i];
+            DM_HIP(hipMemcpyAsync(dcoef(r), R.cx.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
             launch_maxpy(j, Zc(r, 0), ld, dcoef(r), R.x, n, 0, s);
             ++R.restarts;
             R.open = false;
