@@ -126,6 +126,8 @@ static void free_op(dm_op *op) {
     for (void *p : op->allocs) hipFree(p);
     if (op->hres) hipHostFree(op->hres);
     if (op->bk_hres) hipHostFree(op->bk_hres);
+    if (op->hres2) hipHostFree(op->hres2);
+    if (op->bk_hres2) hipHostFree(op->bk_hres2);
     if (op->stream) hipStreamDestroy(op->stream);
     delete op;
 }

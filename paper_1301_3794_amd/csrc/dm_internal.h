@@ -368,13 +368,15 @@ void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
 constexpr int kReduceBlocks = 1024;
 void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
                  int64_t n, double *part, double *dout, hipStream_t s);
-// y -= sum_i c[i] V_i  (c on device)  or  y = sum_i c[i] V_i when overwrite
+// y -= sum_i c[i] V_i  (c on device)  or  y = sum_i c[i] V_i when overwrite;
+// with cscale (device, nv values) the coefficients are c[i] * cscale[i]
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
-                  int overwrite, hipStream_t s);
-// fused Gram--Schmidt step (nv <= 32): w -= sum c_i V_i, then dout[0..nv-1] =
-// V_i . w and dout[nv] = |w|^2 (device results)
+                  int overwrite, hipStream_t s, const double *cscale = nullptr);
+// fused Gram--Schmidt step: w -= sum c_i V_i (c_i times cscale_i if given),
+// then dout[0..nv-1] = V_i . w and dout[nv] = |w|^2 (device results); one
+// pass over the basis for nv <= 32, two above
 void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
-                            int64_t n, double *part, double *dout, hipStream_t s);
+                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale = nullptr);
 // out = scale * (w - sum c_i V_i)
 void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,
                         double scale, double *out, int64_t n, hipStream_t s);

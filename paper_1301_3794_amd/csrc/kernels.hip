@@ -744,10 +744,10 @@ k_mdot_final(int nblk, const double *__restrict__ part, double *__restrict__ out
 template <int VEC>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
-        const double *w, double scale, double *y, int64_t n, int overwrite) {
+        const double *__restrict__ cscale, const double *w, double scale, double *y, int64_t n, int overwrite) {
     using O = Vec<VEC>;
     __shared__ double cs[256];
-    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
+    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = cscale ? c[q] * cscale[q] : c[q];
     __syncthreads();
     const int64_t nvec = n / VEC, ldv = ld / VEC;
     for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
@@ -779,10 +779,10 @@ constexpr int kFuseMax = 32;
 template <int VEC, int MAXV, bool REREAD>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
-                  double *__restrict__ w, int64_t n, double *__restrict__ part) {
+                  const double *__restrict__ cscale, double *__restrict__ w, int64_t n, double *__restrict__ part) {
     using O = Vec<VEC>;
     __shared__ double cs[MAXV];
-    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
+    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = cscale ? c[q] * cscale[q] : c[q];
     __syncthreads();
     double acc[MAXV + 1];
 #pragma unroll
@@ -1241,35 +1241,35 @@ void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const dou
 }
 
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
-                  int overwrite, hipStream_t s) {
+                  int overwrite, hipStream_t s, const double *cscale) {
     if (nv <= 0 && !overwrite) return;
     if (nv > 256) throw std::runtime_error("launch_maxpy: more than 256 vectors");
     if (vec2_ok(n, ld, {V, y}))
-        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c,
+        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
                            (const double *)nullptr, 1.0, y, n, overwrite);
     else
-        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c,
+        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
                            (const double *)nullptr, 1.0, y, n, overwrite);
 }
 
 void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
-                            int64_t n, double *part, double *dout, hipStream_t s) {
-    if (nv < 1 || nv > kFuseMax) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
+                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale) {
+    if (nv < 1 || nv + 1 > 256) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
     const bool v2 = vec2_ok(n, ld, {V, w});
     const dim3 g(kReduceBlocks), b(kThreads);
     if (nv <= 8) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
     } else if (nv <= 16) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16, false>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
     } else if (nv <= 32) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 32, true>), g, b, 0, s, nv, V, ld, c, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 32, true>), g, b, 0, s, nv, V, ld, c, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
     } else {
         // too many vectors to hold in registers: update w, then a second
         // pass for the dots (the basis is read twice)
-        launch_maxpy(nv, V, ld, c, w, n, 0, s);
+        launch_maxpy(nv, V, ld, c, w, n, 0, s, cscale);
         if (v2) hipLaunchKernelGGL((k_mdot_norm<2>), g, b, 0, s, nv, V, ld, (const double *)w, n, part);
         else hipLaunchKernelGGL((k_mdot_norm<1>), g, b, 0, s, nv, V, ld, (const double *)w, n, part);
     }
@@ -1281,11 +1281,11 @@ void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, co
                         double scale, double *out, int64_t n, hipStream_t s) {
     if (nv < 0 || nv > 256) throw std::runtime_error("launch_maxpy_scale: nv out of range");
     if (vec2_ok(n, ld, {V, w, out}))
-        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c, w, scale,
-                           out, n, 0);
+        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c,
+                           (const double *)nullptr, w, scale, out, n, 0);
     else
-        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, w, scale,
-                           out, n, 0);
+        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c,
+                           (const double *)nullptr, w, scale, out, n, 0);
 }
 
 void launch_sub_masked(int64_t n, const double *mask, const double *val, double scale, double *x,

@@ -82,6 +82,9 @@ struct dm_op {
     // Krylov workspaces (allocated on first use)
     int fg_m = 0;
     double *fg_V = nullptr, *fg_Z = nullptr, *fg_w = nullptr, *dcoef = nullptr;
+    // second-pass results of FGMRES's Gram--Schmidt (device / pinned host) and
+    // the squared column scales of its unnormalised basis (device)
+    double *dres2 = nullptr, *hres2 = nullptr, *sc2d = nullptr;
     float *fg_f32 = nullptr, *fg_x32 = nullptr;
     double *gv_f64 = nullptr, *gv_x64 = nullptr;       // fixed in/out of the FP64 V-cycle graph
     hipGraphExec_t g_vc32 = nullptr, g_vc64 = nullptr, g_svc = nullptr;
@@ -96,6 +99,7 @@ struct dm_op {
     int bk_m = 0;
     double *bk_V = nullptr, *bk_Z = nullptr;
     double *bk_dres = nullptr, *bk_dcoef = nullptr, *bk_hres = nullptr;
+    double *bk_dres2 = nullptr, *bk_hres2 = nullptr, *bk_sc2 = nullptr;   // as dres2, hres2, sc2d
     hipGraphExec_t g_vb32[dm::kMaxRhs + 1] = {}, g_vb64[dm::kMaxRhs + 1] = {};
     // block projection: per-vector CG state (kMaxRhs * P each) and graphs
     double *pjb_g = nullptr, *pjb_psi = nullptr, *pjb_p = nullptr, *pjb_q = nullptr;

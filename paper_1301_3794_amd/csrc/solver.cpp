@@ -149,7 +149,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
     // c, c3, cx: coefficients of passes (2), (3) and of the update of x, each
     // in its own host array (a queued copy never reads an overwritten array)
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1), c(m + 1),
-        c3(m + 1), cx(m + 1), sc(m + 1);
+        c3(m + 1), cx(m + 1), sc(m + 1), sc2h(m + 1);
     bool conv = false;
     while (true) {
         if (total == 0) launch_copy(n, f, V, s);
@@ -163,6 +163,8 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
         }
         if (total >= maxit) break;
         sc[0] = 1.0 / beta;
+        sc2h[0] = sc[0] * sc[0];
+        DM_HIP(hipMemcpyAsync(op->sc2d, sc2h.data(), sizeof(double), hipMemcpyHostToDevice, s));
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         std::fill(H.begin(), H.end(), 0.0);
@@ -171,39 +173,25 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
             double *uj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
             precondition(op, mode, uj, zj, s);
             launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, zj, w, s);
-            // (1) d = U^T w; true coefficients h_i = sc_i sc_j d_i
-            dots(op, j + 1, V, n, w, nullptr, n, s);
-            for (int i = 0; i <= j; ++i) {
-                h[i] = sc[i] * sc[j] * op->hres[i];
-                c[i] = sc[i] * sc[i] * op->hres[i];
-            }
-            to_device_coef(op, c.data(), j + 1, s);
-            // (2) w -= U c, then d2 = U^T w and |w|^2
-            double wn2;
-            if (j + 1 <= 32) {
-                launch_maxpy_mdot_norm(j + 1, V, n, op->dcoef, w, n, op->part, op->dres, s);
-                DM_HIP(hipMemcpyAsync(op->hres, op->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-                DM_HIP(hipStreamSynchronize(s));
-                wn2 = op->hres[j + 1];
-            } else {
-                launch_maxpy(j + 1, V, n, op->dcoef, w, n, 0, s);
-                launch_mdot(j + 1, V, n, w, nullptr, n, op->part, op->dres, s);
-                launch_mdot(1, w, 0, w, nullptr, n, op->part, op->dres + j + 1, s);
-                DM_HIP(hipMemcpyAsync(op->hres, op->dres, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-                DM_HIP(hipStreamSynchronize(s));
-                wn2 = op->hres[j + 1];
-            }
-            wn2 *= sc[j] * sc[j];
+            // (1) d = U^T w, then (2) w -= U c with c_i = sc_i^2 d_i formed on
+            // the device, fused with d2 = U^T w and |w|^2: one host sync
+            launch_mdot(j + 1, V, n, w, nullptr, n, op->part, op->dres, s);
+            launch_maxpy_mdot_norm(j + 1, V, n, op->dres, w, n, op->part, op->dres2, s, op->sc2d);
+            DM_HIP(hipMemcpyAsync(op->hres, op->dres, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            DM_HIP(hipMemcpyAsync(op->hres2, op->dres2, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+            DM_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) h[i] = sc[i] * sc[j] * op->hres[i];   // true coefficients
+            const double wn2 = op->hres2[j + 1] * sc[j] * sc[j];
             double c2 = 0.0;
             for (int i = 0; i <= j; ++i) {
-                h2[i] = sc[i] * sc[j] * op->hres[i];
+                h2[i] = sc[i] * sc[j] * op->hres2[i];
                 c2 += h2[i] * h2[i];
             }
             double hn;
             if (c2 > kReorth * kReorth * wn2) {
                 // (3) second classical Gram--Schmidt correction
                 for (int i = 0; i <= j; ++i) {
-                    c3[i] = sc[i] * sc[i] * op->hres[i];
+                    c3[i] = sc[i] * sc[i] * op->hres2[i];
                     h[i] += h2[i];
                 }
                 to_device_coef(op, c3.data(), j + 1, s);
@@ -214,6 +202,8 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
             }
             if (!std::isfinite(hn)) throw DmError{DM_ENAN, "FGMRES iterate is not finite"};
             sc[j + 1] = hn > 0.0 ? sc[j] / hn : 0.0;
+            sc2h[j + 1] = sc[j + 1] * sc[j + 1];
+            DM_HIP(hipMemcpyAsync(op->sc2d + j + 1, &sc2h[j + 1], sizeof(double), hipMemcpyHostToDevice, s));
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
             H[(size_t)(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
@@ -324,6 +314,9 @@ void ensure_krylov_small(dm_op *op) {
         op->gv_f64 = op->dalloc<double>(n);
         op->gv_x64 = op->dalloc<double>(n);
         op->dcoef = op->dalloc<double>(kMaxDots);
+        op->dres2 = op->dalloc<double>(kMaxDots);
+        op->sc2d = op->dalloc<double>(kMaxDots);
+        DM_HIP(hipHostMalloc((void **)&op->hres2, kMaxDots * sizeof(double), hipHostMallocDefault));
     }
 }
 
@@ -525,6 +518,9 @@ void ensure_block_results(dm_op *op) {
         op->bk_dres = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
         op->bk_dcoef = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
         DM_HIP(hipHostMalloc((void **)&op->bk_hres, kMaxRhs * kMaxDots * sizeof(double), hipHostMallocDefault));
+        op->bk_dres2 = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
+        op->bk_sc2 = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
+        DM_HIP(hipHostMalloc((void **)&op->bk_hres2, kMaxRhs * kMaxDots * sizeof(double), hipHostMallocDefault));
     }
 }
 
@@ -798,7 +794,7 @@ struct BlockRhs {
     double bnorm = 0.0, rel = 0.0;
     int total = 0, restarts = 0, j = 0;
     bool open = false, done = false, conv = false;
-    std::vector<double> H, cs, sn, g, y, h, h2, c, c3, cx, sc;   // c, c3, cx as in fgmres()
+    std::vector<double> H, cs, sn, g, y, h, h2, c3, cx, sc, sc2;   // as in fgmres()
 };
 
 int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *const *x, double rtol, int maxit,
@@ -813,6 +809,9 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
     auto dres = [&](int r) { return op->bk_dres + (int64_t)r * kMaxDots; };
     auto dcoef = [&](int r) { return op->bk_dcoef + (int64_t)r * kMaxDots; };
     auto hres = [&](int r) { return op->bk_hres + (int64_t)r * kMaxDots; };
+    auto dres2 = [&](int r) { return op->bk_dres2 + (int64_t)r * kMaxDots; };
+    auto hres2 = [&](int r) { return op->bk_hres2 + (int64_t)r * kMaxDots; };
+    auto dsc2 = [&](int r) { return op->bk_sc2 + (int64_t)r * kMaxDots; };
     // every system's device results to the host, one sync
     auto fetch = [&]() {
         DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nb * kMaxDots * sizeof(double),
@@ -831,7 +830,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         R.y.assign(m, 0.0);
         R.h.assign(m + 1, 0.0);
         R.h2.assign(m + 1, 0.0);
-        R.c.assign(m + 1, 0.0);
+        R.sc2.assign(m + 1, 0.0);
         R.c3.assign(m + 1, 0.0);
         R.cx.assign(m + 1, 0.0);
         R.sc.assign(m + 1, 0.0);
@@ -884,6 +883,8 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                     continue;
                 }
                 R.sc[0] = 1.0 / beta;   // unnormalised basis, as in fgmres()
+                R.sc2[0] = R.sc[0] * R.sc[0];
+                DM_HIP(hipMemcpyAsync(dsc2(r), R.sc2.data(), sizeof(double), hipMemcpyHostToDevice, s));
                 std::fill(R.g.begin(), R.g.end(), 0.0);
                 R.g[0] = beta;
                 std::fill(R.H.begin(), R.H.end(), 0.0);
@@ -908,43 +909,34 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         }
         precondition_block(op, mode, na, vin, zout, s);
         launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s);
-        // Gram--Schmidt as in fgmres(): (1) d = U^T w
-        for (int r : act) launch_mdot(st[r].j + 1, Vc(r, 0), ld, Vc(r, st[r].j + 1), nullptr, n, op->part, dres(r), s);
-        fetch();
-        // (2) w -= U c, then d2 = U^T w and |w|^2
+        // Gram--Schmidt as in fgmres(): (1) d = U^T w, (2) w -= U (sc^2 d)
+        // fused with d2 = U^T w and |w|^2, every open system, one sync
         for (int r : act) {
-            BlockRhs &R = st[r];
-            const int j = R.j;
-            double *w = Vc(r, j + 1);
-            for (int i = 0; i <= j; ++i) {
-                R.h[i] = R.sc[i] * R.sc[j] * hres(r)[i];
-                R.c[i] = R.sc[i] * R.sc[i] * hres(r)[i];
-            }
-            DM_HIP(hipMemcpyAsync(dcoef(r), R.c.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
-            if (j + 1 <= 32) {
-                launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dcoef(r), w, n, op->part, dres(r), s);
-            } else {
-                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), w, n, 0, s);
-                launch_mdot(j + 1, Vc(r, 0), ld, w, nullptr, n, op->part, dres(r), s);
-                launch_mdot(1, w, 0, w, nullptr, n, op->part, dres(r) + j + 1, s);
-            }
+            const int j = st[r].j;
+            launch_mdot(j + 1, Vc(r, 0), ld, Vc(r, j + 1), nullptr, n, op->part, dres(r), s);
+            launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dres(r), Vc(r, j + 1), n, op->part, dres2(r), s, dsc2(r));
         }
-        fetch();
+        DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nb * kMaxDots * sizeof(double), hipMemcpyDeviceToHost,
+                              s));
+        DM_HIP(hipMemcpyAsync(op->bk_hres2, op->bk_dres2, (size_t)nb * kMaxDots * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
         // (3) the second correction where needed; Hessenberg column, Givens
         for (int r : act) {
             BlockRhs &R = st[r];
             int j = R.j;
             double *w = Vc(r, j + 1);
-            const double wn2 = hres(r)[j + 1] * R.sc[j] * R.sc[j];
+            for (int i = 0; i <= j; ++i) R.h[i] = R.sc[i] * R.sc[j] * hres(r)[i];   // true coefficients
+            const double wn2 = hres2(r)[j + 1] * R.sc[j] * R.sc[j];
             double c2 = 0.0;
             for (int i = 0; i <= j; ++i) {
-                R.h2[i] = R.sc[i] * R.sc[j] * hres(r)[i];
+                R.h2[i] = R.sc[i] * R.sc[j] * hres2(r)[i];
                 c2 += R.h2[i] * R.h2[i];
             }
             double hn;
             if (c2 > kReorth * kReorth * wn2) {
                 for (int i = 0; i <= j; ++i) {
-                    R.c3[i] = R.sc[i] * R.sc[i] * hres(r)[i];
+                    R.c3[i] = R.sc[i] * R.sc[i] * hres2(r)[i];
                     R.h[i] += R.h2[i];
                 }
                 DM_HIP(hipMemcpyAsync(dcoef(r), R.c3.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
@@ -955,6 +947,8 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             }
             if (!std::isfinite(hn)) throw DmError{DM_ENAN, "FGMRES iterate is not finite"};
             R.sc[j + 1] = hn > 0.0 ? R.sc[j] / hn : 0.0;
+            R.sc2[j + 1] = R.sc[j + 1] * R.sc[j + 1];
+            DM_HIP(hipMemcpyAsync(dsc2(r) + j + 1, &R.sc2[j + 1], sizeof(double), hipMemcpyHostToDevice, s));
             double *H = R.H.data();
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = R.h[i];
             H[(size_t)(j + 1) * m + j] = hn;
