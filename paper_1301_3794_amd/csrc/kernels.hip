@@ -35,6 +35,24 @@ __device__ inline int64_t xcd_item() {
     return logical * kThreads + threadIdx.x;
 }
 
+// Block kernels over nr vectors: a workgroup of 64 * nr threads takes 64
+// consecutive items, wave q the vector q (coalesced loads per wave; the waves
+// of a workgroup share the coefficient lines of their cells in the CU's
+// cache).  Grid: ceil(items / 64) workgroups, padded to a multiple of 8.
+inline dim3 xcd_grid_waves(int64_t items) {
+    int64_t nb = ceil_div(items, 64);
+    int64_t per = ceil_div(nb, kXcd);
+    return dim3((unsigned)(per * kXcd));
+}
+
+__device__ inline int64_t wave_item(int &q) {
+    const int64_t per = gridDim.x / kXcd;
+    const int64_t b = blockIdx.x;
+    const int64_t logical = (b % kXcd) * per + b / kXcd;
+    q = threadIdx.x >> 6;
+    return logical * 64 + (threadIdx.x & 63);
+}
+
 __device__ inline bool cell_of(const Grid &g, int64_t t, int &i, int &j, int &k) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     if (t >= n) return false;
@@ -105,23 +123,19 @@ k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restric
     apply_body<T, KIND>(g, c, sigma, f, x, y, xcd_item());
 }
 
-// Block forms of apply, restriction and prolongation: NR consecutive lanes
-// take the same cell, one vector each, so their coefficient loads fall on
-// the same cache lines (one fetch from HBM for the block) while every lane
-// keeps the register budget of the one-vector body.  (Looping over the
-// vectors inside a thread instead kept every vector's loads and addresses
-// live at once: 170-240 VGPRs, two waves per SIMD.)
-template <class T, int NR>
-__device__ __forceinline__ int lane_vector(int64_t t) {
-    return (int)(t % NR);
-}
+// Block forms of apply, restriction and prolongation: wave q of a workgroup
+// applies the one-vector body to vector q of the workgroup's 64 cells (see
+// wave_item), so every lane keeps the register budget of the one-vector
+// body.  (Looping over the vectors inside a thread kept every vector's loads
+// and addresses live at once: 170-240 VGPRs, two waves per SIMD; giving the
+// vectors to neighbouring lanes split every load of a wave over NR arrays.)
 
 template <class T, int KIND, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_apply_b(Grid g, Coefs<T> c, T sigma, VPtr<const T> f, VPtr<const T> x, VPtr<T> y) {
-    const int64_t t = xcd_item();
-    const int q = lane_vector<T, NR>(t);
-    apply_body<T, KIND>(g, c, sigma, f.p[q], x.p[q], y.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    apply_body<T, KIND>(g, c, sigma, f.p[q], x.p[q], y.p[q], t);
 }
 
 // y = A x
@@ -254,9 +268,9 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc) {
-    const int64_t t = xcd_item();
-    const int q = lane_vector<T, NR>(t);
-    restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t);
 }
 
 // fine value between coarse faces c0, c1: (a0 x0 + a1 x1) / (a0 + a1)
@@ -296,9 +310,9 @@ k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, VPtr<const T> xc, VPtr<T> x) {
-    const int64_t t = xcd_item();
-    const int q = lane_vector<T, NR>(t);
-    prolong_body<T>(gf, gc, cf, cc, xc.p[q], x.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    prolong_body<T>(gf, gc, cf, cc, xc.p[q], x.p[q], t);
 }
 
 // x = 0 (a kernel, not a memset: it may be recorded into a HIP graph)
@@ -533,51 +547,51 @@ k_s_prolong_add(Grid gf, Grid gc, Coefs<double> cf, const double *__restrict__ x
 template <int NR>
 __global__ void __launch_bounds__(kThreads)
 k_div_DA_b(Grid g, Coefs<double> c, VPtr<const double> b, VPtr<double> out) {
-    const int64_t t = xcd_item();
-    const int q = (int)(t % NR);
-    div_DA_body(g, c, b.p[q], out.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    div_DA_body(g, c, b.p[q], out.p[q], t);
 }
 
 template <int NR>
 __global__ void __launch_bounds__(kThreads)
 k_grad_sub_b(Grid g, Coefs<double> c, VPtr<const double> psi, VPtr<const double> bin, VPtr<double> bout,
              double scale) {
-    const int64_t t = xcd_item();
-    const int q = (int)(t % NR);
-    grad_sub_body(g, c, psi.p[q], bin.p[q], bout.p[q], scale, t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    grad_sub_body(g, c, psi.p[q], bin.p[q], bout.p[q], scale, t);
 }
 
 template <int NR>
 __global__ void __launch_bounds__(kThreads)
 k_s_apply_b(Grid g, Coefs<double> c, double w, int resid, VPtr<const double> f, VPtr<const double> x,
             VPtr<double> y) {
-    const int64_t t = xcd_item();
-    const int q = (int)(t % NR);
-    s_apply_body(g, c, w, resid, f.p[q], x.p[q], y.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    s_apply_body(g, c, w, resid, f.p[q], x.p[q], y.p[q], t);
 }
 
 template <int NR>
 __global__ void __launch_bounds__(kThreads)
 k_s_smooth_b(Grid g, Coefs<double> c, double w, int colour, VPtr<const double> f, VPtr<double> x) {
-    const int64_t t = xcd_item();
-    const int q = (int)(t % NR);
-    s_smooth_body(g, c, w, colour, f.p[q], x.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    s_smooth_body(g, c, w, colour, f.p[q], x.p[q], t);
 }
 
 template <int NR>
 __global__ void __launch_bounds__(kThreads)
 k_s_restrict_b(Grid gf, Grid gc, Coefs<double> cc, VPtr<const double> r, VPtr<double> fc) {
-    const int64_t t = xcd_item();
-    const int q = (int)(t % NR);
-    s_restrict_body(gf, gc, cc, r.p[q], fc.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    s_restrict_body(gf, gc, cc, r.p[q], fc.p[q], t);
 }
 
 template <int NR>
 __global__ void __launch_bounds__(kThreads)
 k_s_prolong_add_b(Grid gf, Grid gc, Coefs<double> cf, VPtr<const double> xc, VPtr<double> x) {
-    const int64_t t = xcd_item();
-    const int q = (int)(t % NR);
-    s_prolong_body(gf, gc, cf, xc.p[q], x.p[q], t / NR);
+    int q;
+    const int64_t t = wave_item(q);
+    s_prolong_body(gf, gc, cf, xc.p[q], x.p[q], t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1022,10 +1036,10 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
     if (kind == AK_M)
-        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_M, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c,
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_M, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c,
                                             sigma, f, x, y))
     else if (kind == AK_RESID)
-        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_RESID, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g,
+        DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_RESID, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g,
                                             c, sigma, f, x, y))
     else
         throw std::runtime_error("block apply: M or residual only");
@@ -1052,7 +1066,7 @@ void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, 
                        const VPtr<T> &fc, hipStream_t s) {
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
     const Coefs<T> cc = coefs_of(coef_c, gc.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cc, r,
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc, r,
                                         fc))
 }
 
@@ -1061,7 +1075,7 @@ void launch_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, const
                           const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s) {
     const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
     const Coefs<T> cf = coefs_of(coef_f, gf.P), cc = coefs_of(coef_c, gc.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_prolong_add_b<T, NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cf,
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_prolong_add_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cf,
                                         cc, xc, x))
 }
 
@@ -1076,14 +1090,14 @@ void launch_div_DA_b(const Grid &g, const double *coef, int nr, const VPtr<const
                      const VPtr<double> &out, hipStream_t s) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<double> c = coefs_of(coef, g.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_div_DA_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, b, out))
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_div_DA_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, b, out))
 }
 
 void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<const double> &psi,
                        const VPtr<const double> &b_in, const VPtr<double> &b_out, double scale, hipStream_t s) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<double> c = coefs_of(coef, g.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_grad_sub_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, psi, b_in,
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_grad_sub_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, psi, b_in,
                                         b_out, scale))
 }
 
@@ -1091,7 +1105,7 @@ void launch_s_apply_b(const Grid &g, const double *coef, double w, int resid, in
                       const VPtr<const double> &x, const VPtr<double> &y, hipStream_t s) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<double> c = coefs_of(coef, g.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_apply_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, w, resid,
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_apply_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, w, resid,
                                         f, x, y))
 }
 
@@ -1099,7 +1113,7 @@ void launch_s_smooth_b(const Grid &g, const double *coef, double w, int colour, 
                        const VPtr<double> &x, hipStream_t s) {
     const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
     const Coefs<double> c = coefs_of(coef, g.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_smooth_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, g, c, w, colour,
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_smooth_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, w, colour,
                                         f, x))
 }
 
@@ -1107,7 +1121,7 @@ void launch_s_restrict_b(const Grid &gf, const Grid &gc, const double *coef_c, i
                          const VPtr<double> &fc, hipStream_t s) {
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
     const Coefs<double> cc = coefs_of(coef_c, gc.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_restrict_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cc, r,
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_restrict_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc, r,
                                         fc))
 }
 
@@ -1115,7 +1129,7 @@ void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const double *coef_f
                             const VPtr<const double> &xc, const VPtr<double> &x, hipStream_t s) {
     const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
     const Coefs<double> cf = coefs_of(coef_f, gf.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_prolong_add_b<NR>), xcd_grid(n * NR), dim3(kThreads), 0, s, gf, gc, cf,
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_prolong_add_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cf,
                                         xc, x))
 }
 
