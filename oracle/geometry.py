@@ -36,11 +36,13 @@ Every routine here is the plain definition: the area of a rectangle inside a
 disk is the integral of the chord length (integrated piece by piece with the
 antiderivative of sqrt(rho^2 - t^2)), a volume is the integral of the
 cross-section area (SciPy adaptive quadrature with the kinks as
-breakpoints).  For the bodies of revolution the integrals along z are taken
-piece by piece between the kinks with the substitution z = end +- s^2 at
-both ends of every piece: at an iris two elliptic arcs meet with a vertical
-tangent, so r(z) - r_iris grows like sqrt|z - z_iris| and an adaptive rule
-applied to z directly stalls near 1e-11 in the cells holding an iris.  Pinned in tests against: measure sums (plane sums of areas
+breakpoints).  The integrals along the axis are taken piece by piece between
+the kinks with the substitution t = end +- s^2 at both ends of every piece:
+at an iris two elliptic arcs meet with a vertical tangent (r(z) - r_iris
+grows like sqrt|z - z_iris|), and at a pole of an ellipsoid the section
+radius grows like the square root of the distance; an adaptive rule applied
+to the axis coordinate directly stalled near 1e-11 (iris cells) and 5e-11
+(cells touching a pole) in cell units.  Pinned in tests against: measure sums (plane sums of areas
 equal the disk area, line sums of lengths equal the chord, the volume sum
 equals the ball volume), direct 2-D / 3-D SciPy quadrature of the
 indicator on individual faces and cells, the octahedral symmetry of a
@@ -237,8 +239,10 @@ class Ellipsoid:
         def area(ux):
             return self._section_area_u(0, ux, (ulo[1], ulo[2]), (uhi[1], uhi[2]))
 
-        val, _ = integrate.quad(area, ulo[0], uhi[0], points=sorted(pts) or None,
-                                epsabs=1e-17, epsrel=1e-13, limit=400)
+        # the section radius has a square-root end behaviour at the poles
+        # (ux -> +-1) and where it meets a distance: integrated piecewise with
+        # the end substitution of quad_pieces
+        val = quad_pieces(area, ulo[0], uhi[0], pts)
         return val * self.semi[0] * self.semi[1] * self.semi[2]
 
 

@@ -184,3 +184,25 @@ def test_window_origin_reproduces_the_full_grid(body):
         assert np.array_equal(a, b), name
         cut += int(np.sum((a > 0) & (a < 1)))
     assert cut > 20
+
+
+def test_cell_touching_a_pole_vs_chord_integral():
+    """A 40^3 cell whose face x = 0.95 touches the sphere's pole: the section
+    radius grows like the square root of the distance to the pole there.
+    Independent value: the 2-D integral over (y, z) of the chord length in
+    x inside the cell (the old adaptive integration in x was off by 5e-11)."""
+    n, h = (40, 40, 40), 1.0 / 40
+    g = geo.sphere((0.5, 0.5, 0.5), 0.45)
+    i, j, k = 37, 20, 20
+    x0, x1 = i * h, (i + 1) * h
+
+    def chord(z, y):
+        r2 = 0.45 ** 2 - (y - 0.5) ** 2 - (z - 0.5) ** 2
+        if r2 <= 0.0:
+            return 0.0
+        s = math.sqrt(r2)
+        return max(0.0, min(x1, 0.5 + s) - max(x0, 0.5 - s))
+
+    ref, err = integrate.dblquad(chord, j * h, (j + 1) * h, k * h, (k + 1) * h, epsabs=1e-19, epsrel=1e-14)
+    assert err / h ** 3 <= 1e-12
+    assert geo.cell_fraction(g, n, h, i, j, k) == pytest.approx(ref / h ** 3, abs=2e-12)
