@@ -86,9 +86,8 @@ VCYCLE_BYTES_PER_CELL = 359.0 * 8.0 / 7.0
 # HBM bytes per FP32 block sweep (BLOCK = 3 vectors) on the 128^3 sphere's
 # finest level, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of
 # `bench.py --only traffic`, each counter scaled by its reading for a 256 MiB
-# copy (reads x2.000, writes x1.000): 404,336 + 62,242 KiB.  Valid for the
-# smoother kernel as of those runs; set to None when k_smooth_b changes.
-BLOCK_SWEEP_TRAFFIC_BYTES = 466578 * 1024
+# copy; None until measured for the current smoother kernel (k_smooth_split).
+BLOCK_SWEEP_TRAFFIC_BYTES = None
 
 
 def log(msg):

@@ -295,9 +295,11 @@ int dm_apply(dm_op *op, int which, int prec, int level, const void *x, void *y, 
             case DM_APPLY_K: {
                 const int kind = which == DM_APPLY_M ? AK_M : AK_K;
                 if (prec == 64)
-                    launch_apply<double>(L.g, L.coef64, op->sigma, kind, nullptr, (const double *)x, (double *)y, s);
+                    launch_apply<double>(L.g, L.coef64, op->sigma, kind, nullptr, (const double *)x, (double *)y, s,
+                                         L.cut_cells());
                 else
-                    launch_apply<float>(L.g, L.coef32, (float)op->sigma, kind, nullptr, (const float *)x, (float *)y, s);
+                    launch_apply<float>(L.g, L.coef32, (float)op->sigma, kind, nullptr, (const float *)x, (float *)y, s,
+                                        L.cut_cells());
                 break;
             }
             case DM_APPLY_A:
@@ -328,9 +330,11 @@ int dm_residual(dm_op *op, int prec, int level, const void *f, const void *x, vo
         const Level &L = op->lv[level];
         fill_ghosts(L, prec, x, false, s);
         if (prec == 64)
-            launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, (const double *)f, (const double *)x, (double *)r, s);
+            launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, (const double *)f, (const double *)x, (double *)r, s,
+                                 L.cut_cells());
         else
-            launch_apply<float>(L.g, L.coef32, (float)op->sigma, AK_RESID, (const float *)f, (const float *)x, (float *)r, s);
+            launch_apply<float>(L.g, L.coef32, (float)op->sigma, AK_RESID, (const float *)f, (const float *)x, (float *)r, s,
+                                L.cut_cells());
         return DM_OK;
     });
 }
@@ -349,9 +353,11 @@ int dm_smooth(dm_op *op, int prec, int level, int n_sweeps, int reverse, const v
                 const int cls = reverse ? 5 - q : q;
                 const int comp = cls / 2, col = cls % 2;
                 if (prec == 64)
-                    launch_smooth<double>(L.g, L.coef64, op->sigma, comp, col, (const double *)f, (double *)x, s);
+                    launch_smooth<double>(L.g, L.coef64, op->sigma, comp, col, (const double *)f, (double *)x, s,
+                                          L.cut_list(comp, col));
                 else
-                    launch_smooth<float>(L.g, L.coef32, (float)op->sigma, comp, col, (const float *)f, (float *)x, s);
+                    launch_smooth<float>(L.g, L.coef32, (float)op->sigma, comp, col, (const float *)f, (float *)x, s,
+                                         L.cut_list(comp, col));
             }
         return DM_OK;
     });
@@ -834,15 +840,15 @@ static int time_kernel_impl(dm_op *op, int kernel, int prec, int level, int nrhs
                     case DM_KERNEL_APPLY:
                     case DM_KERNEL_RESIDUAL: {
                         const int kind = kernel == DM_KERNEL_APPLY ? AK_M : AK_RESID;
-                        if (prec == 64) launch_apply<double>(L.g, L.coef64, op->sigma, kind, (double *)f, (double *)x, (double *)y, s);
-                        else launch_apply<float>(L.g, L.coef32, (float)op->sigma, kind, (float *)f, (float *)x, (float *)y, s);
+                        if (prec == 64) launch_apply<double>(L.g, L.coef64, op->sigma, kind, (double *)f, (double *)x, (double *)y, s, L.cut_cells());
+                        else launch_apply<float>(L.g, L.coef32, (float)op->sigma, kind, (float *)f, (float *)x, (float *)y, s, L.cut_cells());
                         break;
                     }
                     case DM_KERNEL_SMOOTH:
                     case DM_KERNEL_SWEEP:
                         for (int q = 0; q < (kernel == DM_KERNEL_SMOOTH ? 1 : 6); ++q) {
-                            if (prec == 64) launch_smooth<double>(L.g, L.coef64, op->sigma, q / 2, q % 2, (double *)f, (double *)x, s);
-                            else launch_smooth<float>(L.g, L.coef32, (float)op->sigma, q / 2, q % 2, (float *)f, (float *)x, s);
+                            if (prec == 64) launch_smooth<double>(L.g, L.coef64, op->sigma, q / 2, q % 2, (double *)f, (double *)x, s, L.cut_list(q / 2, q % 2));
+                            else launch_smooth<float>(L.g, L.coef32, (float)op->sigma, q / 2, q % 2, (float *)f, (float *)x, s, L.cut_list(q / 2, q % 2));
                         }
                         break;
                     case DM_KERNEL_RESTRICT:
@@ -873,12 +879,12 @@ static int time_kernel_impl(dm_op *op, int kernel, int prec, int level, int nrhs
                     case DM_KERNEL_APPLY:
                     case DM_KERNEL_RESIDUAL:
                         launch_apply_b<T>(L.g, coef, (T)op->sigma, kernel == DM_KERNEL_APPLY ? AK_M : AK_RESID, nrhs,
-                                          as_const(F), as_const(X), Y, s);
+                                          as_const(F), as_const(X), Y, s, L.cut_cells());
                         break;
                     case DM_KERNEL_SMOOTH:
                     case DM_KERNEL_SWEEP:
                         for (int q = 0; q < (kernel == DM_KERNEL_SMOOTH ? 1 : 6); ++q)
-                            launch_smooth_b<T>(L.g, coef, (T)op->sigma, q / 2, q % 2, nrhs, as_const(F), X, s);
+                            launch_smooth_b<T>(L.g, coef, (T)op->sigma, q / 2, q % 2, nrhs, as_const(F), X, s, L.cut_list(q / 2, q % 2));
                         break;
                     case DM_KERNEL_RESTRICT:
                         launch_restrict_b<T>(L.g, C.g, ccoef, nrhs, as_const(X), Cc, s);

@@ -283,14 +283,23 @@ __host__ __device__ inline VPtr<const T> as_const(const VPtr<T> &x) {
     return v;
 }
 
+// The non-vacuum (cut) rows of one smoother class as padded indices; with a
+// list the class update runs as two parts (see k_smooth_split).
+struct ClassList {
+    const int32_t *idx = nullptr;
+    int64_t n = 0;
+};
+
 // the block forms of the V-cycle's kernels: nr (1..kMaxRhs) vectors per
 // launch, each coefficient loaded once for all of them
+// with a cut-cell list (cells with an active non-vacuum row) the launch runs
+// as two parts, the listed cells and the vacuum-only rest (M and residual)
 template <class T>
 void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, const VPtr<const T> &f,
-                    const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s);
+                    const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s, ClassList cut = {});
 template <class T>
 void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour, int nr, const VPtr<const T> &f,
-                     const VPtr<T> &x, hipStream_t s);
+                     const VPtr<T> &x, hipStream_t s, ClassList cut = {});
 template <class T>
 void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
                        const VPtr<T> &fc, hipStream_t s);
@@ -303,10 +312,10 @@ void launch_coarse_solve_b(int n, const double *inv, const int64_t *idx, int nr,
 
 template <class T>
 void launch_apply(const Grid &g, const T *coef, T sigma, int kind, const T *f, const T *x, T *y,
-                  hipStream_t s);
+                  hipStream_t s, ClassList cut = {});
 template <class T>
 void launch_smooth(const Grid &g, const T *coef, T sigma, int comp, int colour, const T *f, T *x,
-                   hipStream_t s);
+                   hipStream_t s, ClassList cut = {});
 template <class T>
 void launch_restrict(const Grid &gf, const Grid &gc, const T *coef_c, const T *r, T *fc,
                      hipStream_t s);

@@ -116,6 +116,37 @@ __device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T s
     put_face<T>(g, y + 2 * P, 2, i, j, k, p, yz);
 }
 
+// apply_body of M or the residual for the cells whose active rows are all
+// vacuum rows (the other cells are listed and run the full body): the same
+// values, written the same way, zeros on the inactive components included.
+// (K alone has no vacuum shortcut: its rows keep the cross terms.)
+template <class T, int KIND>
+__device__ __forceinline__ void apply_vac_body(const Grid &g, T sigma, uint8_t fl, const T *__restrict__ f,
+                                               const T *__restrict__ x, T *__restrict__ y, int i, int j, int k,
+                                               int64_t p) {
+    static_assert(KIND == AK_M || KIND == AK_RESID, "vacuum rows of M only");
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    const T ih2 = inv_h2_of<T>(g);
+    T v[3];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const T *C = x + comp * P;
+        v[comp] = T(0);
+        if (fl & (kFaceActive << comp)) {
+            v[comp] = ih2 * vac_row(C, p, dy, dz) - sigma * C[p];
+            if (KIND == AK_RESID) v[comp] = f[comp * P + p] - v[comp];
+        }
+    }
+    put_face<T>(g, y, 0, i, j, k, p, v[0]);
+    put_face<T>(g, y + P, 1, i, j, k, p, v[1]);
+    put_face<T>(g, y + 2 * P, 2, i, j, k, p, v[2]);
+}
+
+// cells with an active non-vacuum row (those in the cut-cell list)
+__device__ inline bool has_cut_row(uint8_t fl) {
+    return ((fl & 7) & ~(fl >> 3)) != 0;
+}
+
 template <class T, int KIND>
 __global__ void __launch_bounds__(kThreads)
 k_apply(Grid g, Coefs<T> c, T sigma, const T *__restrict__ f, const T *__restrict__ x,
@@ -136,6 +167,35 @@ k_apply_b(Grid g, Coefs<T> c, T sigma, VPtr<const T> f, VPtr<const T> x, VPtr<T>
     int q;
     const int64_t t = wave_item(q);
     apply_body<T, KIND>(g, c, sigma, f.p[q], x.p[q], y.p[q], t);
+}
+
+// The block apply in two parts, as the smoother's class updates: the first
+// ncb workgroups (a multiple of 8) take the cut-cell list (full body), the
+// rest all cells, skipping listed ones (vacuum rows only); wave q of a
+// workgroup takes vector q of 64 entries in either part.
+template <class T, int KIND, int NR>
+__global__ void __launch_bounds__(kThreads)
+k_apply_split(Grid g, Coefs<T> c, T sigma, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
+              VPtr<const T> f, VPtr<const T> x, VPtr<T> y) {
+    const int64_t b = blockIdx.x;
+    const int q = threadIdx.x >> 6;
+    if (b < ncb) {
+        const int64_t e = ((b % kXcd) * (ncb / kXcd) + b / kXcd) * 64 + (threadIdx.x & 63);
+        if (e >= ncut) return;
+        const int64_t p = cut[e], dy = g.sy, dz = g.sz;
+        const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
+        const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
+        apply_body<T, KIND>(g, c, sigma, f.p[q], x.p[q], y.p[q], ((int64_t)k * g.ny + j) * g.nx + i);
+    } else {
+        const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
+        const int64_t t = ((bv % kXcd) * (nvb / kXcd) + bv / kXcd) * 64 + (threadIdx.x & 63);
+        int i, j, k;
+        if (!cell_of(g, t, i, j, k)) return;
+        const int64_t p = pidx(g, i, j, k);
+        const uint8_t fl = c.flags[p];
+        if (has_cut_row(fl)) return;
+        apply_vac_body<T, KIND>(g, sigma, fl, f.p[q], x.p[q], y.p[q], i, j, k, p);
+    }
 }
 
 // y = A x
@@ -201,6 +261,69 @@ __device__ __forceinline__ void smooth_body_n(const Grid &g, const Coefs<T> &c, 
     for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
 }
 
+// The two parts of a class update when the class's cut rows are listed:
+// smooth_vac_n updates the vacuum rows of the colour sweep and skips every
+// other row; smooth_cut_n updates entry e of the list of the class's
+// non-vacuum rows.  Rows of one class do not read each other, so the parts
+// may run in any order; separating them keeps the waves of the colour sweep
+// on the short vacuum path (a cut row in a wave made the whole wave take
+// the long path as well).
+template <class T, int COMP, int NR>
+__device__ __forceinline__ void smooth_vac_n(const Grid &g, const Coefs<T> &c, T sigma, int colour,
+                                             const VPtr<const T> &f, const VPtr<T> &x, int64_t t) {
+    const int nxh = (g.nx + 1) >> 1;
+    if (t >= (int64_t)nxh * g.ny * g.nz) return;
+    const int ih = (int)(t % nxh);
+    const int64_t r = t / nxh;
+    const int j = (int)(r % g.ny), k = (int)(r / g.ny);
+    const int i = 2 * ih + ((j + k + colour) & 1);
+    if (i >= g.nx) return;
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    const int64_t p = pidx(g, i, j, k);
+    if (!(c.flags[p] & (kFaceVacuum << COMP))) return;
+    const T ih2 = inv_h2_of<T>(g);
+    const T d = T(6) * ih2 - sigma;
+    T nv[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const T *xc = x.p[q] + COMP * P;
+        const T xp = xc[p];
+        const T row = ih2 * vac_row<T>(xc, p, dy, dz) - sigma * xp;
+        nv[q] = xp + (f.p[q][COMP * P + p] - row) / d;
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
+}
+
+template <class T, int COMP, int NR>
+__device__ __forceinline__ void smooth_cut_n(const Grid &g, const Coefs<T> &c, T sigma,
+                                             const int32_t *__restrict__ cut, int64_t ncut, const VPtr<const T> &f,
+                                             const VPtr<T> &x, int64_t e) {
+    if (e >= ncut) return;
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    const int64_t p = cut[e];
+    const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
+    const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
+    const T ih2 = inv_h2_of<T>(g);
+    const T *a = COMP == 0 ? c.ax : (COMP == 1 ? c.ay : c.az);
+    const T d = diag_of<T>(c, COMP, p, dy, dz, ih2, sigma) +
+                ih2 * pmc_diag_extra<T>(g, c.lx, c.ly, c.lz, COMP, i, j, k, p);
+    T nv[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const T *X = x.p[q], *Y = X + P, *Z = X + 2 * P;
+        const T *xc = COMP == 0 ? X : (COMP == 1 ? Y : Z);
+        T row;
+        if (COMP == 0) row = row_x<T, true>(c, X, Y, Z, p, dy, dz);
+        else if (COMP == 1) row = row_y<T, true>(c, X, Y, Z, p, dy, dz);
+        else row = row_z<T, true>(c, X, Y, Z, p, dy, dz);
+        row = ih2 * row - sigma * a[p] * xc[p];
+        nv[q] = xc[p] + (f.p[q][COMP * P + p] - row) / d;
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
+}
+
 template <class T, int COMP>
 __device__ __forceinline__ void smooth_body(const Grid &g, const Coefs<T> &c, T sigma, int colour,
                                             const T *__restrict__ f, T *__restrict__ x, int64_t t) {
@@ -217,6 +340,35 @@ template <class T, int COMP, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_smooth_b(Grid g, Coefs<T> c, T sigma, int colour, VPtr<const T> f, VPtr<T> x) {
     smooth_body_n<T, COMP, NR>(g, c, sigma, colour, f, x, xcd_item());
+}
+
+// A class update from its two parts: the first ncb workgroups (a multiple of
+// 8) take the cut-row list, the rest the vacuum rows of the colour sweep;
+// each part maps its workgroups to the XCDs as xcd_item does.  With several
+// vectors and a short list (wave_split) a cut workgroup takes 64 rows, wave
+// q the vector q: the cut rows are latency-bound, and one thread per row and
+// vector keeps more of them in flight (the waves share the rows' coefficient
+// lines in cache); a long list fills the GPU with one thread per row looping
+// over the vectors, which reuses the coefficients in registers.
+template <class T, int COMP, int NR>
+__global__ void __launch_bounds__(kThreads)
+k_smooth_split(Grid g, Coefs<T> c, T sigma, int colour, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
+               int wave_split, VPtr<const T> f, VPtr<T> x) {
+    const int64_t b = blockIdx.x;
+    if (b < ncb) {
+        const int64_t L = (b % kXcd) * (ncb / kXcd) + b / kXcd;
+        if (!wave_split) {
+            smooth_cut_n<T, COMP, NR>(g, c, sigma, cut, ncut, f, x, L * kThreads + threadIdx.x);
+        } else {
+            const int q = threadIdx.x >> 6;
+            if (q >= NR) return;
+            smooth_cut_n<T, COMP, 1>(g, c, sigma, cut, ncut, vptr1(f.p[q]), vptr1(x.p[q]), L * 64 + (threadIdx.x & 63));
+        }
+    } else {
+        const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
+        const int64_t L = (bv % kXcd) * (nvb / kXcd) + bv / kXcd;
+        smooth_vac_n<T, COMP, NR>(g, c, sigma, colour, f, x, L * kThreads + threadIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -970,7 +1122,11 @@ inline dim3 flat_grid(int64_t n) {
 // ---------------------------------------------------------------------------
 template <class T>
 void launch_apply(const Grid &g, const T *coef, T sigma, int kind, const T *f, const T *x, T *y,
-                  hipStream_t s) {
+                  hipStream_t s, ClassList cut) {
+    if (cut.idx && (kind == AK_M || kind == AK_RESID)) {
+        launch_apply_b<T>(g, coef, sigma, kind, 1, vptr1(f), vptr1(x), vptr1(y), s, cut);
+        return;
+    }
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     Coefs<T> c = coefs_of(coef, g.P);
     if (kind == AK_M)
@@ -993,7 +1149,15 @@ void launch_apply_A(const Grid &g, const double *coef, const double *x, double *
 
 template <class T>
 void launch_smooth(const Grid &g, const T *coef, T sigma, int comp, int colour, const T *f, T *x,
-                   hipStream_t s) {
+                   hipStream_t s, ClassList cut) {
+    if (cut.idx) {
+        VPtr<const T> F{};
+        VPtr<T> X{};
+        F.p[0] = f;
+        X.p[0] = x;
+        launch_smooth_b<T>(g, coef, sigma, comp, colour, 1, F, X, s, cut);
+        return;
+    }
     const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
     Coefs<T> c = coefs_of(coef, g.P);
     if (comp == 0)
@@ -1020,6 +1184,11 @@ void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T
                        coefs_of(coef_f, gf.P), coefs_of(coef_c, gc.P), xc, x);
 }
 
+// cut rows of a class below which the block smoother gives each vector its
+// own wave (measured on the 128^3 sphere: ~60k rows per class on the finest
+// level favour the in-thread loop, ~15k rows on the next the waves)
+constexpr int64_t kCutWaveSplit = 32768;
+
 // ---- block forms: dispatch nr (1..kMaxRhs) to the template
 #define DM_NR_SWITCH(nr, CALL)                      \
     switch (nr) {                                   \
@@ -1032,9 +1201,21 @@ void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T
 
 template <class T>
 void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, const VPtr<const T> &f,
-                    const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s) {
+                    const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s, ClassList cut) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
+    if (cut.idx && (kind == AK_M || kind == AK_RESID)) {
+        const int64_t ncb = ceil_div(ceil_div(cut.n, 64), kXcd) * kXcd;
+        const int64_t nvb = ceil_div(ceil_div(n, 64), kXcd) * kXcd;
+        const dim3 grid((unsigned)(ncb + nvb));
+        if (kind == AK_M)
+            DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<T, AK_M, NR>), grid, dim3(64 * NR), 0, s, g, c, sigma,
+                                                cut.idx, cut.n, ncb, f, x, y))
+        else
+            DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<T, AK_RESID, NR>), grid, dim3(64 * NR), 0, s, g, c,
+                                                sigma, cut.idx, cut.n, ncb, f, x, y))
+        return;
+    }
     if (kind == AK_M)
         DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_b<T, AK_M, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c,
                                             sigma, f, x, y))
@@ -1047,9 +1228,25 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
 
 template <class T>
 void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour, int nr, const VPtr<const T> &f,
-                     const VPtr<T> &x, hipStream_t s) {
+                     const VPtr<T> &x, hipStream_t s, ClassList cut) {
     const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
+    if (cut.idx) {
+        const int wave_split = nr > 1 && cut.n < kCutWaveSplit;
+        const int64_t ncb = ceil_div(ceil_div(cut.n, wave_split ? 64 : kThreads), kXcd) * kXcd;
+        const int64_t nvb = ceil_div(ceil_div(n, kThreads), kXcd) * kXcd;
+        const dim3 grid((unsigned)(ncb + nvb));
+        if (comp == 0)
+            DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 0, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
+                                                colour, cut.idx, cut.n, ncb, wave_split, f, x))
+        else if (comp == 1)
+            DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 1, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
+                                                colour, cut.idx, cut.n, ncb, wave_split, f, x))
+        else
+            DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 2, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
+                                                colour, cut.idx, cut.n, ncb, wave_split, f, x))
+        return;
+    }
     if (comp == 0)
         DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_b<T, 0, NR>), xcd_grid(n), dim3(kThreads), 0, s, g, c, sigma,
                                             colour, f, x))
@@ -1319,9 +1516,9 @@ void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, 
 // explicit instantiations
 #define DM_BLOCK_INST(T)                                                                                   \
     template void launch_apply_b<T>(const Grid &, const T *, T, int, int, const VPtr<const T> &,                 \
-                                    const VPtr<const T> &, const VPtr<T> &, hipStream_t);                         \
+                                    const VPtr<const T> &, const VPtr<T> &, hipStream_t, ClassList);              \
     template void launch_smooth_b<T>(const Grid &, const T *, T, int, int, int, const VPtr<const T> &,           \
-                                     const VPtr<T> &, hipStream_t);                                               \
+                                     const VPtr<T> &, hipStream_t, ClassList);                                    \
     template void launch_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,        \
                                        const VPtr<T> &, hipStream_t);                                             \
     template void launch_prolong_add_b<T>(const Grid &, const Grid &, const T *, const T *, int,                 \
@@ -1332,15 +1529,15 @@ DM_BLOCK_INST(double)
 DM_BLOCK_INST(float)
 #undef DM_BLOCK_INST
 template void launch_apply<double>(const Grid &, const double *, double, int, const double *,
-                                   const double *, double *, hipStream_t);
+                                   const double *, double *, hipStream_t, ClassList);
 template void launch_apply<float>(const Grid &, const float *, float, int, const float *,
-                                  const float *, float *, hipStream_t);
+                                  const float *, float *, hipStream_t, ClassList);
 template void launch_apply_A_t<float>(const Grid &, const float *, const float *, float *, hipStream_t);
 template void launch_apply_A_t<double>(const Grid &, const double *, const double *, double *, hipStream_t);
 template void launch_smooth<double>(const Grid &, const double *, double, int, int, const double *,
-                                    double *, hipStream_t);
+                                    double *, hipStream_t, ClassList);
 template void launch_smooth<float>(const Grid &, const float *, float, int, int, const float *,
-                                   float *, hipStream_t);
+                                   float *, hipStream_t, ClassList);
 template void launch_restrict<double>(const Grid &, const Grid &, const double *, const double *,
                                       double *, hipStream_t);
 template void launch_restrict<float>(const Grid &, const Grid &, const float *, const float *,

@@ -180,6 +180,38 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         DM_HIP(hipMemcpyAsync(L.coef32, c32.data(), 7 * P * sizeof(float), hipMemcpyHostToDevice, op->stream));
         DM_HIP(hipMemcpyAsync(L.coef64 + 7 * P, fl.data(), P, hipMemcpyHostToDevice, op->stream));
         DM_HIP(hipMemcpyAsync(L.coef32 + 7 * P, fl.data(), P, hipMemcpyHostToDevice, op->stream));
+        // the cut (non-vacuum) rows of every smoother class, in index order
+        std::vector<int32_t> cut;
+        for (int comp = 0; comp < 3; ++comp)
+            for (int col = 0; col < 2; ++col) {
+                L.cut_off[2 * comp + col] = (int64_t)cut.size();
+                for (int k = 0; k < L.g.nz; ++k)
+                    for (int j = 0; j < L.g.ny; ++j)
+                        for (int i = ((j + k + col) & 1); i < L.g.nx; i += 2) {
+                            const int64_t p = pidx(L.g, i, j, k);
+                            if ((fl[p] & (kFaceActive << comp)) && !(fl[p] & (kFaceVacuum << comp)))
+                                cut.push_back((int32_t)p);
+                        }
+            }
+        L.cut_off[6] = (int64_t)cut.size();
+        std::vector<int32_t> cutc;
+        for (int k = 0; k < L.g.nz; ++k)
+            for (int j = 0; j < L.g.ny; ++j)
+                for (int i = 0; i < L.g.nx; ++i) {
+                    const int64_t p = pidx(L.g, i, j, k);
+                    if ((fl[p] & 7) & ~(fl[p] >> 3)) cutc.push_back((int32_t)p);
+                }
+        L.ncutc = (int64_t)cutc.size();
+        if (!cutc.empty()) {
+            L.cutc = op->dalloc<int32_t>(cutc.size());
+            DM_HIP(hipMemcpyAsync(L.cutc, cutc.data(), cutc.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  op->stream));
+        }
+        if (P > INT32_MAX) throw DmError{DM_EINVAL, "grid too large for 32-bit row lists"};
+        if (!cut.empty()) {
+            L.cut = op->dalloc<int32_t>(cut.size());
+            DM_HIP(hipMemcpyAsync(L.cut, cut.data(), cut.size() * sizeof(int32_t), hipMemcpyHostToDevice, op->stream));
+        }
         DM_HIP(hipStreamSynchronize(op->stream));
         L.sweight = 1.0 / (std::ldexp(1.0, l) * op->h * op->h);
         int64_t naf = 0, nac = 0;  // owned entries only (not PMC ghosts)

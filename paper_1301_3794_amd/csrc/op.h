@@ -25,6 +25,18 @@ struct Level {
     float *bx32 = nullptr, *bf32 = nullptr, *br32 = nullptr;
     double *bsx = nullptr, *bsf = nullptr, *bsr = nullptr;  // kMaxRhs * P (scalar MG)
     int64_t n_act_faces = 0, n_act_cells = 0;
+    // non-vacuum rows of each smoother class (component c, colour col) as
+    // padded indices: class 2c+col is cut[cut_off[2c+col] .. cut_off[2c+col+1])
+    int32_t *cut = nullptr;
+    int64_t cut_off[7] = {};
+    // cells with an active non-vacuum row (any component), padded indices
+    int32_t *cutc = nullptr;
+    int64_t ncutc = 0;
+    ClassList cut_cells() const { return ClassList{cutc, ncutc}; }
+    ClassList cut_list(int comp, int colour) const {
+        const int q = 2 * comp + colour;
+        return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q]};
+    }
 };
 
 // thread-local error reporting

@@ -153,7 +153,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
     bool conv = false;
     while (true) {
         if (total == 0) launch_copy(n, f, V, s);
-        else launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, V, s);
+        else launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, V, s, L.cut_cells());
         const double beta = std::sqrt(dot1(op, V, V, nullptr, n, s));
         if (!std::isfinite(beta)) throw DmError{DM_ENAN, "FGMRES residual is not finite"};
         rel = beta / bnorm;
@@ -172,7 +172,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
         for (; j < m;) {
             double *uj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
             precondition(op, mode, uj, zj, s);
-            launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, zj, w, s);
+            launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, zj, w, s, L.cut_cells());
             // (1) d = U^T w, then (2) w -= U c with c_i = sc_i^2 d_i formed on
             // the device, fused with d2 = U^T w and |w|^2: one host sync
             launch_mdot(j + 1, V, n, w, nullptr, n, op->part, op->dres, s);
@@ -377,9 +377,9 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
     const T *c = Prec<T>::coef(L);
     for (int it = 0; it < op->opt.nu_pre; ++it)
         for (int comp = 0; comp < 3; ++comp)
-            for (int col = 0; col < 2; ++col) launch_smooth<T>(g, c, sig, comp, col, f, x, s);
+            for (int col = 0; col < 2; ++col) launch_smooth<T>(g, c, sig, comp, col, f, x, s, L.cut_list(comp, col));
     T *r = Prec<T>::r(L);
-    launch_apply<T>(g, c, sig, AK_RESID, f, x, r, s);
+    launch_apply<T>(g, c, sig, AK_RESID, f, x, r, s, L.cut_cells());
     Level &C = op->lv[l + 1];
     T *fc = Prec<T>::f(C), *xc = Prec<T>::x(C);
     launch_restrict<T>(g, C.g, Prec<T>::coef(C), r, fc, s);
@@ -387,7 +387,7 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
     launch_prolong_add<T>(g, C.g, c, Prec<T>::coef(C), xc, x, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int comp = 2; comp >= 0; --comp)
-            for (int col = 1; col >= 0; --col) launch_smooth<T>(g, c, sig, comp, col, f, x, s);
+            for (int col = 1; col >= 0; --col) launch_smooth<T>(g, c, sig, comp, col, f, x, s, L.cut_list(comp, col));
 }
 
 template void vcycle<double>(dm_op *, int, const double *, double *, hipStream_t);
@@ -412,9 +412,10 @@ void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     const T *c = Prec<T>::coef(L);
     for (int it = 0; it < op->opt.nu_pre; ++it)
         for (int comp = 0; comp < 3; ++comp)
-            for (int col = 0; col < 2; ++col) launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s);
+            for (int col = 0; col < 2; ++col)
+                launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s, L.cut_list(comp, col));
     const VPtr<T> R = slots(BPrec<T>::r(L), n3, nr);
-    launch_apply_b<T>(g, c, sig, AK_RESID, nr, as_const(F), as_const(X), R, s);
+    launch_apply_b<T>(g, c, sig, AK_RESID, nr, as_const(F), as_const(X), R, s, L.cut_cells());
     Level &C = op->lv[l + 1];
     const int64_t c3 = 3 * C.g.P;
     launch_restrict_b<T>(g, C.g, Prec<T>::coef(C), nr, as_const(R), slots(BPrec<T>::f(C), c3, nr), s);
@@ -422,7 +423,8 @@ void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     launch_prolong_add_b<T>(g, C.g, c, Prec<T>::coef(C), nr, as_const(slots(BPrec<T>::x(C), c3, nr)), X, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int comp = 2; comp >= 0; --comp)
-            for (int col = 1; col >= 0; --col) launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s);
+            for (int col = 1; col >= 0; --col)
+                launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s, L.cut_list(comp, col));
 }
 
 void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
@@ -866,7 +868,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                     ++nres;
                 }
             }
-            if (nres) launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_RESID, nres, bf, bx, by, s);
+            if (nres) launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_RESID, nres, bf, bx, by, s, L.cut_cells());
             for (int r : act) launch_mdot(1, Vc(r, 0), 0, Vc(r, 0), nullptr, n, op->part, dres(r), s);
             fetch();
             for (int r : act) {
@@ -908,7 +910,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             wv.p[q] = Vc(r, st[r].j + 1);          // w = M Z_j in the next column's slot
         }
         precondition_block(op, mode, na, vin, zout, s);
-        launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s);
+        launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s, L.cut_cells());
         // Gram--Schmidt as in fgmres(): (1) d = U^T w, (2) w -= U (sc^2 d)
         // fused with d2 = U^T w and |w|^2, every open system, one sync
         for (int r : act) {
