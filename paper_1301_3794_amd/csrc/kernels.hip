@@ -905,6 +905,103 @@ k_mdot_final(int nblk, const double *__restrict__ part, double *__restrict__ out
     }
 }
 
+// Block forms for the eigensolver's basis work (NW <= 8 vectors at once):
+// part[(i*NW + q)][block] = partial sums of V_i . (W_q * wt) for i < nv; the
+// basis is read once, W once per chunk of CH basis vectors (CH * NW ~ 16
+// accumulators per thread)
+
+template <int VEC, int NW, int CH>
+__global__ void __launch_bounds__(kThreads)
+k_mdot_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ W, int64_t ldw,
+             const double *__restrict__ wt, int64_t n, double *__restrict__ part) {
+    using O = Vec<VEC>;
+    const int64_t nvec = n / VEC, ldv = ld / VEC, ldwv = ldw / VEC;
+    __shared__ double sh[kThreads / 64][CH * NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < nv; c0 += CH) {
+        const int cn = min(CH, nv - c0);
+        double acc[CH][NW];
+#pragma unroll
+        for (int a = 0; a < CH; ++a)
+#pragma unroll
+            for (int q = 0; q < NW; ++q) acc[a][q] = 0.0;
+        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
+             e += (int64_t)gridDim.x * kThreads) {
+            typename O::T wv[NW];
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                wv[q] = O::ld(W + (int64_t)q * ldwv * VEC, e);
+                if (wt) wv[q] = O::mul(wv[q], O::ld(wt, e));
+            }
+#pragma unroll
+            for (int a = 0; a < CH; ++a)
+                if (a < cn) {
+                    const typename O::T v = O::ld(V + (int64_t)(c0 + a) * ldv * VEC, e);
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) acc[a][q] += O::dot(v, wv[q]);
+                }
+        }
+        if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double tv = wt ? wt[n - 1] : 1.0;
+            for (int a = 0; a < cn; ++a)
+                for (int q = 0; q < NW; ++q)
+                    acc[a][q] += V[(int64_t)(c0 + a) * ld + n - 1] * W[(int64_t)q * ldw + n - 1] * tv;
+        }
+#pragma unroll
+        for (int a = 0; a < CH; ++a)
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                double v = acc[a][q];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                if (lane == 0) sh[wave][a * NW + q] = v;
+            }
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn * NW; t += kThreads) {
+            double v = 0.0;
+            for (int u = 0; u < kThreads / 64; ++u) v += sh[u][t];
+            part[(int64_t)(c0 * NW + t) * gridDim.x + blockIdx.x] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Y_q = sum_i C[i][q] V_i (overwrite) or Y_q -= sum_i C[i][q] V_i for q < NW;
+// C row-major (nv x NW, device); one read of the basis
+template <int VEC, int NW>
+__global__ void __launch_bounds__(kThreads)
+k_maxpy_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ C,
+              double *__restrict__ Y, int64_t ldy, int64_t n, int overwrite) {
+    using O = Vec<VEC>;
+    __shared__ double cs[256 * NW];
+    for (int t = threadIdx.x; t < nv * NW; t += kThreads) cs[t] = C[t];
+    __syncthreads();
+    const int64_t nvec = n / VEC, ldv = ld / VEC, ldyv = ldy / VEC;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
+         e += (int64_t)gridDim.x * kThreads) {
+        typename O::T acc[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) acc[q] = O::zero();
+        for (int i = 0; i < nv; ++i) {
+            const typename O::T v = O::ld(V + (int64_t)i * ldv * VEC, e);
+#pragma unroll
+            for (int q = 0; q < NW; ++q) acc[q] = O::fma(cs[i * NW + q], v, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            double *y = Y + (int64_t)q * ldyv * VEC;
+            O::st(y, e, overwrite ? acc[q] : O::fma(-1.0, acc[q], O::ld(y, e)));
+        }
+    }
+    if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int q = 0; q < NW; ++q) {
+            double sacc = 0.0;
+            for (int i = 0; i < nv; ++i) sacc += cs[i * NW + q] * V[(int64_t)i * ld + n - 1];
+            double *y = Y + (int64_t)q * ldy;
+            y[n - 1] = overwrite ? sacc : y[n - 1] - sacc;
+        }
+    }
+}
+
 // y = sum_i c_i V_i (overwrite) or y -= sum_i c_i V_i; w: optional input
 // (out = scale * (w - sum c_i V_i) when w != nullptr)
 template <int VEC>
@@ -1450,6 +1547,44 @@ void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const dou
     hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout);
 }
+
+#define DM_NW_SWITCH(nw, CALL)                                   \
+    switch (nw) {                                                \
+        case 1: { constexpr int NW = 1, CH = 16; CALL; } break;  \
+        case 2: { constexpr int NW = 2, CH = 8; CALL; } break;   \
+        case 3: { constexpr int NW = 3, CH = 5; CALL; } break;   \
+        case 4: { constexpr int NW = 4, CH = 4; CALL; } break;   \
+        case 5: { constexpr int NW = 5, CH = 2; CALL; } break;   \
+        case 6: { constexpr int NW = 6, CH = 2; CALL; } break;   \
+        case 7: { constexpr int NW = 7, CH = 2; CALL; } break;   \
+        default: { constexpr int NW = 8, CH = 2; CALL; } break;  \
+    }
+
+void launch_mdot_multi(int nv, const double *V, int64_t ld, const double *W, int64_t ldw, int nw,
+                       const double *wt, int64_t n, double *part, double *dout, hipStream_t s) {
+    if (nv <= 0 || nw <= 0) return;
+    if (nw > kMultiMax || nv * nw > 256) throw std::runtime_error("launch_mdot_multi: too many products");
+    const bool v2 = vec2_ok(n, ld, {V, W, wt}) && (ldw % 2 == 0);
+    const dim3 g(kReduceBlocks), b(kThreads);
+    if (v2) DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_mdot_multi<2, NW, CH>), g, b, 0, s, nv, V, ld, W, ldw, wt, n, part))
+    else DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_mdot_multi<1, NW, CH>), g, b, 0, s, nv, V, ld, W, ldw, wt, n, part))
+    hipLaunchKernelGGL(k_mdot_final, dim3(nv * nw), dim3(kThreads), 0, s, (int)kReduceBlocks,
+                       (const double *)part, dout);
+}
+
+void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, int nw, double *Y, int64_t ldy,
+                        int64_t n, int overwrite, hipStream_t s) {
+    if (nw <= 0 || (nv <= 0 && !overwrite)) return;
+    if (nw > kMultiMax || nv > 256) throw std::runtime_error("launch_maxpy_multi: too many vectors");
+    if (vec2_ok(n, ld, {V, Y}) && ldy % 2 == 0)
+        DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_maxpy_multi<2, NW>), flat_grid(n / 2), dim3(kThreads), 0, s, nv, V,
+                                            ld, C, Y, ldy, n, overwrite))
+    else
+        DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_maxpy_multi<1, NW>), flat_grid(n), dim3(kThreads), 0, s, nv, V, ld,
+                                            C, Y, ldy, n, overwrite))
+}
+
+#undef DM_NW_SWITCH
 
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
                   int overwrite, hipStream_t s, const double *cscale) {

@@ -105,6 +105,10 @@ struct dm_op {
            *pj_p = nullptr, *pj_q = nullptr;
     int eg_cap = 0;
     double *eg_V = nullptr, *eg_W = nullptr, *eg_T = nullptr, *eg_F = nullptr;
+    // block basis work: coefficients (256 x 8, device), K of the new block,
+    // Ritz vectors with their K and A images
+    double *eg_C = nullptr, *eg_KV = nullptr, *eg_R = nullptr;
+    int eg_kv_cap = 0, eg_r_cap = 0;
     // block solves (allocated on first use): FGMRES bases of kMaxRhs systems,
     // column j of system r at bk_V + (j * nrhs + r) * n0; per-system device
     // results / coefficients (kMaxDots each) and pinned host results

@@ -1041,8 +1041,48 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     if (blocked && !op->eg_F) op->eg_F = op->dalloc<double>((size_t)kMaxRhs * n);
     if (blocked) ensure_krylov_small(op);
     else ensure_krylov(op);
+    if (b > kMultiMax) throw DmError{DM_EINVAL, "eigs: block size above 8"};
+    if (!op->eg_C) op->eg_C = op->dalloc<double>((size_t)256 * kMultiMax);
+    if (op->eg_kv_cap < b) {
+        op->eg_KV = op->dalloc<double>((size_t)b * n);
+        op->eg_kv_cap = b;
+    }
+    if (op->eg_r_cap < k) {
+        op->eg_R = op->dalloc<double>((size_t)3 * k * n);
+        op->eg_r_cap = k;
+    }
     double *V = op->eg_V, *W = op->eg_W, *t1 = op->eg_T, *t2 = op->eg_T + n, *t3 = op->eg_T + 2 * n;
     double *SCR = V + (size_t)(m + b) * n;   // room for keep_max Ritz vectors
+    double *RB = op->eg_R, *RK = op->eg_R + (size_t)k * n, *RA = op->eg_R + (size_t)2 * k * n;
+    // block basis work: every product of nv basis vectors with up to
+    // kMultiMax vectors reads the basis once (launch_mdot_multi /
+    // launch_maxpy_multi); results through op->dres / hres, coefficients
+    // through eg_C (a host array of its own per upload)
+    std::vector<double> cbuf((size_t)256 * kMultiMax), mres((size_t)cap * kMultiMax);
+    // mres[i*nw + q] = V_i . (W_q * wt), i < nv (chunks of basis columns whose
+    // products fit the kMaxDots result buffer)
+    auto multi_dots = [&](int nv, const double *W0, int nw, const double *wt) {
+        const int rows = kMaxDots / nw;
+        for (int i0 = 0; i0 < nv; i0 += rows) {
+            const int cnt = std::min(rows, nv - i0);
+            launch_mdot_multi(cnt, V + (size_t)i0 * n, n, W0, n, nw, wt, n, op->part, op->dres, s);
+            DM_HIP(hipMemcpyAsync(op->hres, op->dres, (size_t)cnt * nw * sizeof(double), hipMemcpyDeviceToHost, s));
+            DM_HIP(hipStreamSynchronize(s));
+            std::copy(op->hres, op->hres + (size_t)cnt * nw, mres.begin() + (size_t)i0 * nw);
+        }
+    };
+    // Y_q = sum_r coefficient(r, q) V_r for q < nq, in chunks of kMultiMax
+    auto combine = [&](int nv, int nq, double *Y0, auto coefficient) {
+        for (int q0 = 0; q0 < nq; q0 += kMultiMax) {
+            const int nw = std::min(kMultiMax, nq - q0);
+            std::vector<double> c((size_t)nv * nw);
+            for (int r = 0; r < nv; ++r)
+                for (int q = 0; q < nw; ++q) c[(size_t)r * nw + q] = coefficient(r, q0 + q);
+            DM_HIP(hipMemcpyAsync(op->eg_C, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            launch_maxpy_multi(nv, V, n, op->eg_C, nw, Y0 + (size_t)q0 * n, n, n, 1, s);
+            DM_HIP(hipStreamSynchronize(s));   // c goes out of scope
+        }
+    };
     // inner products over the owned active faces: (u, v) = u^T W A v
     // (eq. bInner; W = 1/2 on faces in a PMC plane), K-forms with W, and
     // the residual norm with W / A
@@ -1139,18 +1179,41 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
                 }
             }
             ++outer;
+            double *Vn = V + (size_t)cur * n;
+            DM_HIP(hipMemcpyAsync(Vn, W, (size_t)b * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            // block classical Gram--Schmidt twice against the cur old columns
+            // (one read of the basis per pass for the whole block) ...
+            std::vector<double> cb((size_t)cur * b, 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                multi_dots(cur, Vn, b, a);
+                for (int t = 0; t < cur * b; ++t) {
+                    cbuf[t] = mres[t];
+                    cb[t] += mres[t];
+                }
+                DM_HIP(hipMemcpyAsync(op->eg_C, cbuf.data(), (size_t)cur * b * sizeof(double), hipMemcpyHostToDevice,
+                                      s));
+                launch_maxpy_multi(cur, V, n, op->eg_C, b, Vn, n, n, 0, s);
+                DM_HIP(hipStreamSynchronize(s));   // cbuf is reused
+            }
+            // ... then within the block, column by column
             for (int c = 0; c < b; ++c) {
-                double *v = V + (size_t)(cur + c) * n;
-                launch_copy(n, W + (size_t)c * n, v, s);
+                double *v = Vn + (size_t)c * n;
                 std::fill(coef.begin(), coef.end(), 0.0);
-                orth(V, cur + c, v, coef.data());
-                for (int i = 0; i < cur + c; ++i) Hat(i, j0 + c) += coef[i];
+                orth(Vn, c, v, coef.data());
+                for (int i = 0; i < cur; ++i) Hat(i, j0 + c) += cb[(size_t)i * b + c];
+                for (int i = 0; i < c; ++i) Hat(cur + i, j0 + c) += coef[i];
                 const double nrm = A_normalize(v);
                 if (!std::isfinite(nrm)) throw DmError{DM_ENAN, "eigs: basis vector not finite"};
                 Hat(cur + c, j0 + c) = nrm;
                 if (nrm <= 1e-300) throw DmError{DM_EBREAKDOWN, "eigs: Krylov breakdown"};
-                add_gk(cur + c);
             }
+            // V^T K V: the block's K images against the whole basis, one pass
+            for (int c = 0; c < b; ++c)
+                launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, Vn + (size_t)c * n, op->eg_KV + (size_t)c * n,
+                                     s);
+            multi_dots(cur + b, op->eg_KV, b, wk);
+            for (int c = 0; c < b; ++c)
+                for (int i = 0; i < cur + b; ++i) Gat(i, cur + c) = Gat(cur + c, i) = mres[(size_t)i * b + c];
             cur += b;
         }
         const bool full = cur >= m + b;
@@ -1186,25 +1249,34 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
             for (int i = 0; w < k && i < nb; ++i)
                 if (!(mu[ord[i]] > 1e-10 * gmax)) wanted[w++] = ord[i];
         }
-        // ---- explicit residuals of the k wanted Ritz pairs on (K, A)
+        // ---- explicit residuals of the k wanted Ritz pairs on (K, A): the
+        // k Ritz vectors b_i = V y_i from one read of the basis (per chunk of
+        // kMultiMax), their K and A images, and two host syncs for all
         nconv = 0;
         double maxres = 0.0;
         std::vector<double> yk(std::max(mm, nb));
+        combine(nb, k, RB, [&](int r, int i) { return Z[(size_t)r * nb + wanted[i]]; });
         for (int i = 0; i < k; ++i) {
-            for (int r = 0; r < nb; ++r) yk[r] = Z[(size_t)r * nb + wanted[i]];
-            to_device_coef(op, yk.data(), nb, s);
-            double *bi = SCR + (size_t)(i % std::max(1, keep_max)) * n;
-            launch_maxpy(nb, V, n, op->dcoef, t1, n, 1, s);  // t1 = V y
-            launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, t1, t2, s);
-            const double bKb = dot1(op, t1, t2, wk, n, s);
-            const double bAb = dot1(op, t1, t1, a, n, s);
-            const double lr = bKb / bAb;
-            // t2 = K b - lr A b
-            launch_apply_A(L.g, L.coef64, t1, bi, s);
-            launch_axpy(n, -lr, bi, t2, s);
-            const double rr = dot1(op, t2, t2, ainv, n, s);
-            const double rho = std::sqrt(rr) / (std::fabs(lr) * std::sqrt(bAb));
-            lam_h[i] = lr;
+            launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, RB + (size_t)i * n, RK + (size_t)i * n, s);
+            launch_apply_A(L.g, L.coef64, RB + (size_t)i * n, RA + (size_t)i * n, s);
+            launch_mdot(1, RB + (size_t)i * n, 0, RK + (size_t)i * n, wk, n, op->part, op->dres + 2 * i, s);
+            launch_mdot(1, RB + (size_t)i * n, 0, RB + (size_t)i * n, a, n, op->part, op->dres + 2 * i + 1, s);
+        }
+        DM_HIP(hipMemcpyAsync(op->hres, op->dres, (size_t)2 * k * sizeof(double), hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        std::vector<double> bKb(k), bAb(k);
+        for (int i = 0; i < k; ++i) {
+            bKb[i] = op->hres[2 * i];
+            bAb[i] = op->hres[2 * i + 1];
+            lam_h[i] = bKb[i] / bAb[i];
+            // K b - lr A b
+            launch_axpy(n, -lam_h[i], RA + (size_t)i * n, RK + (size_t)i * n, s);
+            launch_mdot(1, RK + (size_t)i * n, 0, RK + (size_t)i * n, ainv, n, op->part, op->dres + i, s);
+        }
+        DM_HIP(hipMemcpyAsync(op->hres, op->dres, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < k; ++i) {
+            const double rho = std::sqrt(op->hres[i]) / (std::fabs(lam_h[i]) * std::sqrt(bAb[i]));
             res_h[i] = rho;
             maxres = std::max(maxres, rho);
             if (rho <= tol) ++nconv;
@@ -1222,12 +1294,8 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
                 const int i = idx[q];
                 lam[q] = lam_h[i];
                 if (res_out) res_out[q] = res_h[i];
-                if (vecs) {
-                    for (int r = 0; r < nb; ++r) yk[r] = Z[(size_t)r * nb + wanted[i]];
-                    to_device_coef(op, yk.data(), nb, s);
-                    launch_maxpy(nb, V, n, op->dcoef, vecs + (size_t)q * n, n, 1, s);
-                }
             }
+            if (vecs) combine(nb, k, vecs, [&](int r, int q) { return Z[(size_t)r * nb + wanted[idx[q]]]; });
             if (info) {
                 info->n_converged = nconv;
                 info->outer_iterations = outer;
@@ -1243,11 +1311,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
         if (!full) continue;
         // ---- thick restart: keep the keep_max leading Ritz vectors
         const int keep = keep_max;
-        for (int i = 0; i < keep; ++i) {
-            for (int r = 0; r < mm; ++r) yk[r] = Y[(size_t)r * mm + order[i]];
-            to_device_coef(op, yk.data(), mm, s);
-            launch_maxpy(mm, V, n, op->dcoef, SCR + (size_t)i * n, n, 1, s);
-        }
+        combine(mm, keep, SCR, [&](int r, int i) { return Y[(size_t)r * mm + order[i]]; });
         std::vector<double> Bc((size_t)b * keep, 0.0);  // coupling of the last block
         for (int r = 0; r < b; ++r)
             for (int i = 0; i < keep; ++i) {
