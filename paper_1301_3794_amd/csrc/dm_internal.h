@@ -290,6 +290,18 @@ struct ClassList {
     int64_t n = 0;
 };
 
+// Units of kSpanUnit consecutive doubles (one 128-byte line) of a level-0
+// face vector that can hold a nonzero entry: an active face, or a PMC ghost
+// image of one.  The Krylov reductions and multi-axpys visit only the listed
+// units (ascending indices); every vector they read is zero elsewhere and
+// what they write is left untouched there.  An empty span means the whole
+// vector.
+constexpr int kSpanUnit = 16;
+struct Span {
+    const int32_t *u = nullptr;
+    int64_t n = 0;
+};
+
 // the block forms of the V-cycle's kernels: nr (1..kMaxRhs) vectors per
 // launch, each coefficient loaded once for all of them
 // with a cut-cell list (cells with an active non-vacuum row) the launch runs
@@ -376,7 +388,7 @@ void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
 // device buffer `dout` (nv doubles); `part` scratch of nv * kReduceBlocks doubles
 constexpr int kReduceBlocks = 1024;
 void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
-                 int64_t n, double *part, double *dout, hipStream_t s);
+                 int64_t n, double *part, double *dout, hipStream_t s, Span sp = {});
 constexpr int kMultiMax = 8;   // vectors per launch of the two kernels below
 // dout[i*nw + q] = V_i . (W_q * wt) for i < nv, q < nw (nw <= 8, nv*nw <= 256;
 // W_q = W + q*ldw); the basis is read once
@@ -389,12 +401,13 @@ void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, in
 // y -= sum_i c[i] V_i  (c on device)  or  y = sum_i c[i] V_i when overwrite;
 // with cscale (device, nv values) the coefficients are c[i] * cscale[i]
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
-                  int overwrite, hipStream_t s, const double *cscale = nullptr);
+                  int overwrite, hipStream_t s, const double *cscale = nullptr, Span sp = {});
 // fused Gram--Schmidt step: w -= sum c_i V_i (c_i times cscale_i if given),
 // then dout[0..nv-1] = V_i . w and dout[nv] = |w|^2 (device results); one
 // pass over the basis for nv <= 32, two above
 void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
-                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale = nullptr);
+                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale = nullptr,
+                            Span sp = {});
 // out = scale * (w - sum c_i V_i)
 void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,
                         double scale, double *out, int64_t n, hipStream_t s);

@@ -798,20 +798,35 @@ struct Vec<2> {
     __device__ static T zero() { return make_double2(0.0, 0.0); }
 };
 
+// Index i of a grid-stride loop -> element (in VEC units) of the listed
+// units; the whole vector without a list.  Elements past nvec (a partial
+// last unit) are skipped by the caller.
+template <int VEC>
+__device__ __forceinline__ int64_t span_count(const Span &sp, int64_t nvec) {
+    return sp.u ? sp.n * (kSpanUnit / VEC) : nvec;
+}
+template <int VEC>
+__device__ __forceinline__ int64_t span_elem(const Span &sp, int64_t i) {
+    constexpr int per = kSpanUnit / VEC;
+    return sp.u ? (int64_t)sp.u[i / per] * per + (i % per) : i;
+}
+
 // part[i][block] = partial sums of V_i . (w * wt) over the block's elements
 template <int VEC>
 __global__ void __launch_bounds__(kThreads)
 k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
-       const double *__restrict__ wt, int64_t n, double *__restrict__ part) {
+       const double *__restrict__ wt, int64_t n, double *__restrict__ part, Span sp) {
     using O = Vec<VEC>;
-    const int64_t nvec = n / VEC, ldv = ld / VEC;
+    const int64_t nvec = n / VEC, ldv = ld / VEC, cnt = span_count<VEC>(sp, nvec);
     for (int c0 = 0; c0 < nv; c0 += kChunk) {
         const int cn = min(kChunk, nv - c0);
         double acc[kChunk];
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) acc[q] = 0.0;
-        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
-             e += (int64_t)gridDim.x * kThreads) {
+        for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt;
+             it += (int64_t)gridDim.x * kThreads) {
+            const int64_t e = span_elem<VEC>(sp, it);
+            if (e >= nvec) continue;
             typename O::T wv = O::ld(w, e);
             if (wt) wv = O::mul(wv, O::ld(wt, e));
 #pragma unroll
@@ -846,9 +861,9 @@ k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restric
 template <int VEC>
 __global__ void __launch_bounds__(kThreads)
 k_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
-            int64_t n, double *__restrict__ part) {
+            int64_t n, double *__restrict__ part, Span sp) {
     using O = Vec<VEC>;
-    const int64_t nvec = n / VEC, ldv = ld / VEC;
+    const int64_t nvec = n / VEC, ldv = ld / VEC, cnt = span_count<VEC>(sp, nvec);
     __shared__ double sh[kThreads / 64][kChunk + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c0 = 0; c0 < nv; c0 += kChunk) {
@@ -857,8 +872,10 @@ k_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__re
         double acc[kChunk + 1];
 #pragma unroll
         for (int q = 0; q <= kChunk; ++q) acc[q] = 0.0;
-        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
-             e += (int64_t)gridDim.x * kThreads) {
+        for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt;
+             it += (int64_t)gridDim.x * kThreads) {
+            const int64_t e = span_elem<VEC>(sp, it);
+            if (e >= nvec) continue;
             const typename O::T wv = O::ld(w, e);
 #pragma unroll
             for (int q = 0; q < kChunk; ++q)
@@ -1007,14 +1024,17 @@ k_maxpy_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__
 template <int VEC>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
-        const double *__restrict__ cscale, const double *w, double scale, double *y, int64_t n, int overwrite) {
+        const double *__restrict__ cscale, const double *w, double scale, double *y, int64_t n, int overwrite,
+        Span sp) {
     using O = Vec<VEC>;
     __shared__ double cs[256];
     for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = cscale ? c[q] * cscale[q] : c[q];
     __syncthreads();
-    const int64_t nvec = n / VEC, ldv = ld / VEC;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
-         e += (int64_t)gridDim.x * kThreads) {
+    const int64_t nvec = n / VEC, ldv = ld / VEC, cnt = span_count<VEC>(sp, nvec);
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt;
+         it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = span_elem<VEC>(sp, it);
+        if (e >= nvec) continue;
         typename O::T s = O::zero();
         for (int q = 0; q < nv; ++q) s = O::fma(cs[q], O::ld(V + (int64_t)q * ldv * VEC, e), s);
         typename O::T r;
@@ -1042,7 +1062,8 @@ constexpr int kFuseMax = 32;
 template <int VEC, int MAXV, bool REREAD>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
-                  const double *__restrict__ cscale, double *__restrict__ w, int64_t n, double *__restrict__ part) {
+                  const double *__restrict__ cscale, double *__restrict__ w, int64_t n, double *__restrict__ part,
+                  Span sp) {
     using O = Vec<VEC>;
     __shared__ double cs[MAXV];
     for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = cscale ? c[q] * cscale[q] : c[q];
@@ -1050,9 +1071,11 @@ k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double
     double acc[MAXV + 1];
 #pragma unroll
     for (int q = 0; q <= MAXV; ++q) acc[q] = 0.0;
-    const int64_t nvec = n / VEC, ldv = ld / VEC;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
-         e += (int64_t)gridDim.x * kThreads) {
+    const int64_t nvec = n / VEC, ldv = ld / VEC, cnt = span_count<VEC>(sp, nvec);
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt;
+         it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = span_elem<VEC>(sp, it);
+        if (e >= nvec) continue;
         typename O::T s = O::ld(w, e);
         if (REREAD) {
 #pragma unroll
@@ -1537,13 +1560,13 @@ inline bool vec2_ok(int64_t n, int64_t ld, std::initializer_list<const void *> p
 }  // namespace
 
 void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
-                 int64_t n, double *part, double *dout, hipStream_t s) {
+                 int64_t n, double *part, double *dout, hipStream_t s, Span sp) {
     if (nv <= 0) return;
     if (nv > 256) throw std::runtime_error("launch_mdot: more than 256 vectors");
     if (vec2_ok(n, ld, {V, w, wt}))
-        hipLaunchKernelGGL(k_mdot<2>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part);
+        hipLaunchKernelGGL(k_mdot<2>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
     else
-        hipLaunchKernelGGL(k_mdot<1>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part);
+        hipLaunchKernelGGL(k_mdot<1>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
     hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout);
 }
@@ -1587,37 +1610,39 @@ void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, in
 #undef DM_NW_SWITCH
 
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
-                  int overwrite, hipStream_t s, const double *cscale) {
+                  int overwrite, hipStream_t s, const double *cscale, Span sp) {
     if (nv <= 0 && !overwrite) return;
     if (nv > 256) throw std::runtime_error("launch_maxpy: more than 256 vectors");
+    const int64_t cnt = sp.u ? sp.n * kSpanUnit : n;
     if (vec2_ok(n, ld, {V, y}))
-        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
-                           (const double *)nullptr, 1.0, y, n, overwrite);
+        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(cnt / 2), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
+                           (const double *)nullptr, 1.0, y, n, overwrite, sp);
     else
-        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
-                           (const double *)nullptr, 1.0, y, n, overwrite);
+        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(cnt), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
+                           (const double *)nullptr, 1.0, y, n, overwrite, sp);
 }
 
 void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
-                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale) {
+                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale,
+                            Span sp) {
     if (nv < 1 || nv + 1 > 256) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
     const bool v2 = vec2_ok(n, ld, {V, w});
     const dim3 g(kReduceBlocks), b(kThreads);
     if (nv <= 8) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
     } else if (nv <= 16) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
     } else if (nv <= 32) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part);
+        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
+        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
     } else {
         // too many vectors to hold in registers: update w, then a second
         // pass for the dots (the basis is read twice)
-        launch_maxpy(nv, V, ld, c, w, n, 0, s, cscale);
-        if (v2) hipLaunchKernelGGL((k_mdot_norm<2>), g, b, 0, s, nv, V, ld, (const double *)w, n, part);
-        else hipLaunchKernelGGL((k_mdot_norm<1>), g, b, 0, s, nv, V, ld, (const double *)w, n, part);
+        launch_maxpy(nv, V, ld, c, w, n, 0, s, cscale, sp);
+        if (v2) hipLaunchKernelGGL((k_mdot_norm<2>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
+        else hipLaunchKernelGGL((k_mdot_norm<1>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
     }
     hipLaunchKernelGGL(k_mdot_final, dim3(nv + 1), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout);
@@ -1628,10 +1653,10 @@ void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, co
     if (nv < 0 || nv > 256) throw std::runtime_error("launch_maxpy_scale: nv out of range");
     if (vec2_ok(n, ld, {V, w, out}))
         hipLaunchKernelGGL(k_maxpy<2>, flat_grid(n / 2), dim3(kThreads), 0, s, nv, V, ld, c,
-                           (const double *)nullptr, w, scale, out, n, 0);
+                           (const double *)nullptr, w, scale, out, n, 0, Span{});
     else
         hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c,
-                           (const double *)nullptr, w, scale, out, n, 0);
+                           (const double *)nullptr, w, scale, out, n, 0, Span{});
 }
 
 void launch_sub_masked(int64_t n, const double *mask, const double *val, double scale, double *x,

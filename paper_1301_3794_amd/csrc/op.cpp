@@ -212,6 +212,35 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
             L.cut = op->dalloc<int32_t>(cut.size());
             DM_HIP(hipMemcpyAsync(L.cut, cut.data(), cut.size() * sizeof(int32_t), hipMemcpyHostToDevice, op->stream));
         }
+        if (l == 0) {
+            // units of 16 doubles of a face vector holding an active face or
+            // a PMC ghost image (rows of a mirrored plane at index -1)
+            const int64_t n = 3 * P, nu = (n + kSpanUnit - 1) / kSpanUnit;
+            std::vector<uint8_t> live(nu, 0);
+            const int nn[3] = {L.g.nx, L.g.ny, L.g.nz};
+            for (int k = -1; k <= L.g.nz; ++k)
+                for (int j = -1; j <= L.g.ny; ++j)
+                    for (int i = -1; i <= L.g.nx; ++i) {
+                        const int idx[3] = {i, j, k};
+                        const int64_t p = pidx(L.g, i, j, k);
+                        bool owned = true, ghost = false;
+                        for (int a = 0; a < 3; ++a) {
+                            if (idx[a] < 0 || idx[a] >= nn[a]) owned = false;
+                            if (idx[a] == -1 && ((L.g.pmc >> a) & 1)) ghost = true;
+                        }
+                        for (int a = 0; a < 3; ++a)
+                            if (ghost || (owned && (fl[p] & (kFaceActive << a)))) live[(a * P + p) / kSpanUnit] = 1;
+                    }
+            std::vector<int32_t> units;
+            for (int64_t u = 0; u < nu; ++u)
+                if (live[u]) units.push_back((int32_t)u);
+            op->nvunit = (int64_t)units.size();
+            if (!units.empty()) {
+                op->vunit = op->dalloc<int32_t>(units.size());
+                DM_HIP(hipMemcpyAsync(op->vunit, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                      op->stream));
+            }
+        }
         DM_HIP(hipStreamSynchronize(op->stream));
         L.sweight = 1.0 / (std::ldexp(1.0, l) * op->h * op->h);
         int64_t naf = 0, nac = 0;  // owned entries only (not PMC ghosts)

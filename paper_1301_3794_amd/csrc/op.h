@@ -130,6 +130,10 @@ struct dm_op {
     // preconditioner while dm_batch_eigs runs (not owned), and the op's index
     dm_batch *batch = nullptr;
     int batch_index = -1;
+    // units of a level-0 face vector the Krylov solvers' reductions visit
+    int32_t *vunit = nullptr;
+    int64_t nvunit = 0;
+    dm::Span vspan() const { return dm::Span{vunit, nvunit}; }
 
     template <class T>
     T *dalloc(size_t count) {
@@ -158,7 +162,7 @@ void vcycle(dm_op *op, int level, const T *f, T *x, hipStream_t s);
 void svcycle(dm_op *op, int level, const double *f, double *x, hipStream_t s);
 // device dots; results copied to op->hres (synchronises the stream)
 void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const double *wt,
-          int64_t n, hipStream_t s);
+          int64_t n, hipStream_t s, Span sp = {});
 int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hipStream_t s,
             int *iters);
 // project() on nr (1..kMaxRhs) vectors in lockstep; iters: nr entries or NULL
@@ -185,7 +189,8 @@ void invalidate_graphs(dm_op *op);
 // the scalar one pj_r -> pj_z
 void vcycle_graphed(dm_op *op, int prec, hipStream_t s);
 void svcycle_graphed(dm_op *op, hipStream_t s);
-double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n, hipStream_t s);
+double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n, hipStream_t s,
+            Span sp = {});
 int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt, double *lam,
          double *vecs, double *res, dm_eig_info *info, hipStream_t s);
 

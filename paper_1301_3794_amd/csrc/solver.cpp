@@ -137,8 +137,9 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
     const int64_t n = op->n0();
     const int m = op->fg_m;
     double *V = op->fg_V, *Z = op->fg_Z;
+    const Span sp = op->vspan();
     DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    const double bnorm = std::sqrt(dot1(op, f, f, nullptr, n, s));
+    const double bnorm = std::sqrt(dot1(op, f, f, nullptr, n, s, sp));
     int total = 0, restarts = 0;
     double rel = 0.0;
     if (bnorm == 0.0) {
@@ -154,7 +155,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
     while (true) {
         if (total == 0) launch_copy(n, f, V, s);
         else launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, V, s, L.cut_cells());
-        const double beta = std::sqrt(dot1(op, V, V, nullptr, n, s));
+        const double beta = std::sqrt(dot1(op, V, V, nullptr, n, s, sp));
         if (!std::isfinite(beta)) throw DmError{DM_ENAN, "FGMRES residual is not finite"};
         rel = beta / bnorm;
         if (beta <= rtol * bnorm) {
@@ -175,8 +176,8 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
             launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, zj, w, s, L.cut_cells());
             // (1) d = U^T w, then (2) w -= U c with c_i = sc_i^2 d_i formed on
             // the device, fused with d2 = U^T w and |w|^2: one host sync
-            launch_mdot(j + 1, V, n, w, nullptr, n, op->part, op->dres, s);
-            launch_maxpy_mdot_norm(j + 1, V, n, op->dres, w, n, op->part, op->dres2, s, op->sc2d);
+            launch_mdot(j + 1, V, n, w, nullptr, n, op->part, op->dres, s, sp);
+            launch_maxpy_mdot_norm(j + 1, V, n, op->dres, w, n, op->part, op->dres2, s, op->sc2d, sp);
             DM_HIP(hipMemcpyAsync(op->hres, op->dres, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
             DM_HIP(hipMemcpyAsync(op->hres2, op->dres2, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
             DM_HIP(hipStreamSynchronize(s));
@@ -195,7 +196,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
                     h[i] += h2[i];
                 }
                 to_device_coef(op, c3.data(), j + 1, s);
-                launch_maxpy(j + 1, V, n, op->dcoef, w, n, 0, s);
+                launch_maxpy(j + 1, V, n, op->dcoef, w, n, 0, s, nullptr, sp);
                 hn = std::sqrt(std::max(wn2 - c2, 0.0));
             } else {
                 hn = std::sqrt(wn2);
@@ -230,7 +231,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
         }
         for (int i = 0; i < j; ++i) cx[i] = -y[i] * sc[i];   // x += sum y_i z_i, z_i = sc_i Z_i
         to_device_coef(op, cx.data(), j, s);
-        launch_maxpy(j, Z, n, op->dcoef, x, n, 0, s);
+        launch_maxpy(j, Z, n, op->dcoef, x, n, 0, s, nullptr, sp);
         ++restarts;
     }
     if (info) {
@@ -334,8 +335,8 @@ void ensure_krylov(dm_op *op) {
 
 
 double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64_t n,
-            hipStream_t s) {
-    dots(op, 1, x, 0, y, wt, n, s);
+            hipStream_t s, Span sp) {
+    dots(op, 1, x, 0, y, wt, n, s, sp);
     return op->hres[0];
 }
 
@@ -357,8 +358,8 @@ void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s
 
 // ---------------------------------------------------------------------------
 void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const double *wt,
-          int64_t n, hipStream_t s) {
-    launch_mdot(nv, V, ld, w, wt, n, op->part, op->dres, s);
+          int64_t n, hipStream_t s, Span sp) {
+    launch_mdot(nv, V, ld, w, wt, n, op->part, op->dres, s, sp);
     DM_HIP(hipMemcpyAsync(op->hres, op->dres, nv * sizeof(double), hipMemcpyDeviceToHost, s));
     DM_HIP(hipStreamSynchronize(s));
 }
@@ -806,6 +807,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
     const int64_t n = op->n0();
     const int m = op->bk_m;
     const int64_t ld = (int64_t)nb * n;   // stride between the columns of one system
+    const Span sp = op->vspan();
     auto Vc = [&](int r, int j) { return op->bk_V + (int64_t)j * ld + (int64_t)r * n; };
     auto Zc = [&](int r, int j) { return op->bk_Z + (int64_t)j * ld + (int64_t)r * n; };
     auto dres = [&](int r) { return op->bk_dres + (int64_t)r * kMaxDots; };
@@ -837,7 +839,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         R.cx.assign(m + 1, 0.0);
         R.sc.assign(m + 1, 0.0);
         DM_HIP(hipMemsetAsync(R.x, 0, n * sizeof(double), s));
-        launch_mdot(1, R.f, 0, R.f, nullptr, n, op->part, dres(r), s);
+        launch_mdot(1, R.f, 0, R.f, nullptr, n, op->part, dres(r), s, sp);
     }
     fetch();
     for (int r = 0; r < nb; ++r) {
@@ -869,7 +871,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                 }
             }
             if (nres) launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_RESID, nres, bf, bx, by, s, L.cut_cells());
-            for (int r : act) launch_mdot(1, Vc(r, 0), 0, Vc(r, 0), nullptr, n, op->part, dres(r), s);
+            for (int r : act) launch_mdot(1, Vc(r, 0), 0, Vc(r, 0), nullptr, n, op->part, dres(r), s, sp);
             fetch();
             for (int r : act) {
                 BlockRhs &R = st[r];
@@ -915,8 +917,9 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         // fused with d2 = U^T w and |w|^2, every open system, one sync
         for (int r : act) {
             const int j = st[r].j;
-            launch_mdot(j + 1, Vc(r, 0), ld, Vc(r, j + 1), nullptr, n, op->part, dres(r), s);
-            launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dres(r), Vc(r, j + 1), n, op->part, dres2(r), s, dsc2(r));
+            launch_mdot(j + 1, Vc(r, 0), ld, Vc(r, j + 1), nullptr, n, op->part, dres(r), s, sp);
+            launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dres(r), Vc(r, j + 1), n, op->part, dres2(r), s, dsc2(r),
+                                   sp);
         }
         DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nb * kMaxDots * sizeof(double), hipMemcpyDeviceToHost,
                               s));
@@ -942,7 +945,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                     R.h[i] += R.h2[i];
                 }
                 DM_HIP(hipMemcpyAsync(dcoef(r), R.c3.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
-                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), w, n, 0, s);
+                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), w, n, 0, s, nullptr, sp);
                 hn = std::sqrt(std::max(wn2 - c2, 0.0));
             } else {
                 hn = std::sqrt(wn2);
@@ -979,7 +982,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             }
             for (int i = 0; i < j; ++i) R.cx[i] = -R.y[i] * R.sc[i];
             DM_HIP(hipMemcpyAsync(dcoef(r), R.cx.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-            launch_maxpy(j, Zc(r, 0), ld, dcoef(r), R.x, n, 0, s);
+            launch_maxpy(j, Zc(r, 0), ld, dcoef(r), R.x, n, 0, s, nullptr, sp);
             ++R.restarts;
             R.open = false;
         }
