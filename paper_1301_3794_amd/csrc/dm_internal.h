@@ -334,8 +334,10 @@ void launch_restrict(const Grid &gf, const Grid &gc, const T *coef_c, const T *r
 template <class T>
 void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, const T *xc, T *x,
                         hipStream_t s);
+// out = (TO) in; with a span, over its listed units only (out is left
+// untouched elsewhere)
 template <class TI, class TO>
-void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s);
+void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s, Span sp = {});
 template <class T>
 void launch_coarse_solve(int n, const double *inv, const int64_t *idx, const T *f, T *x,
                          hipStream_t s);

@@ -481,6 +481,18 @@ __global__ void k_cast(const TI *__restrict__ in, TO *__restrict__ out, int64_t 
         out[e] = (TO)in[e];
 }
 
+// the cast over the listed units of a face vector (see Span)
+template <class TI, class TO>
+__global__ void k_cast_units(const TI *__restrict__ in, TO *__restrict__ out, int64_t n,
+                             const int32_t *__restrict__ units, int64_t nunits) {
+    const int64_t cnt = nunits * kSpanUnit;
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt;
+         it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = (int64_t)units[it / kSpanUnit] * kSpanUnit + it % kSpanUnit;
+        if (e < n) out[e] = (TO)in[e];
+    }
+}
+
 // Coarsest level: x[idx[r]] = sum_c inv[r, c] f[idx[c]] (FP64 arithmetic);
 // one row of the inverse serves every right-hand side
 template <class T, int NR>
@@ -1453,8 +1465,12 @@ void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const double *coef_f
 #undef DM_NR_SWITCH
 
 template <class TI, class TO>
-void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL((k_cast<TI, TO>), flat_grid(n), dim3(kThreads), 0, s, in, out, n);
+void launch_cast(const TI *in, TO *out, int64_t n, hipStream_t s, Span sp) {
+    if (sp.u)
+        hipLaunchKernelGGL((k_cast_units<TI, TO>), flat_grid(sp.n * kSpanUnit), dim3(kThreads), 0, s, in, out, n,
+                           sp.u, sp.n);
+    else
+        hipLaunchKernelGGL((k_cast<TI, TO>), flat_grid(n), dim3(kThreads), 0, s, in, out, n);
 }
 
 template <class T>
@@ -1706,8 +1722,8 @@ template void launch_prolong_add<double>(const Grid &, const Grid &, const doubl
                                          double *, hipStream_t);
 template void launch_prolong_add<float>(const Grid &, const Grid &, const float *, const float *, const float *,
                                         float *, hipStream_t);
-template void launch_cast<double, float>(const double *, float *, int64_t, hipStream_t);
-template void launch_cast<float, double>(const float *, double *, int64_t, hipStream_t);
+template void launch_cast<double, float>(const double *, float *, int64_t, hipStream_t, Span);
+template void launch_cast<float, double>(const float *, double *, int64_t, hipStream_t, Span);
 template void launch_coarse_solve<double>(int, const double *, const int64_t *, const double *,
                                           double *, hipStream_t);
 template void launch_coarse_solve<float>(int, const double *, const int64_t *, const float *,

@@ -343,10 +343,11 @@ double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64
 void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s) {
     const int64_t n = op->n0();
     if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
-        launch_cast<double, float>(v, op->fg_f32, n, s);
+        // as in precondition_block: casts over the listed units only
+        launch_cast<double, float>(v, op->fg_f32, n, s, op->vspan());
         if (op->batch && mode == DM_SOLVE_FGMRES_MG32) batch_vcycle_lockstep(op, s);
         else vcycle_graphed(op, 32, s);
-        launch_cast<float, double>(op->fg_x32, z, n, s);
+        launch_cast<float, double>(op->fg_x32, z, n, s, op->vspan());
         if (mode == DM_SOLVE_FGMRES_MG32_LEARNED) net_correct(op, v, z, s);
     } else {
         launch_copy(n, v, op->gv_f64, s);
@@ -778,9 +779,12 @@ void precondition_block(dm_op *op, int mode, int nr, const double *const *v, dou
     const int64_t n = op->n0();
     if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
         ensure_block(op, 32);
-        for (int q = 0; q < nr; ++q) launch_cast<double, float>(v[q], op->lv[0].bf32 + q * n, n, s);
+        // the V-cycle reads f on active rows only, and z is zero outside the
+        // listed units (written only here)
+        const Span sp = op->vspan();
+        for (int q = 0; q < nr; ++q) launch_cast<double, float>(v[q], op->lv[0].bf32 + q * n, n, s, sp);
         vcycle_block_graphed(op, 32, nr, s);
-        for (int q = 0; q < nr; ++q) launch_cast<float, double>(op->lv[0].bx32 + q * n, z[q], n, s);
+        for (int q = 0; q < nr; ++q) launch_cast<float, double>(op->lv[0].bx32 + q * n, z[q], n, s, sp);
         if (mode == DM_SOLVE_FGMRES_MG32_LEARNED)
             for (int q = 0; q < nr; ++q) net_correct(op, v[q], z[q], s);
     } else {
