@@ -413,6 +413,26 @@ void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c
 // out = scale * (w - sum c_i V_i)
 void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,
                         double scale, double *out, int64_t n, hipStream_t s);
+// Per-vector scalars of a block launch, passed by value
+struct Coef4 {
+    double v[kMaxRhs] = {};
+};
+// Block forms for the conjugate-gradient solves of the projection; each acts
+// on the vector slots q < nr whose first pointer is set, results to
+// dout[q * dstride] (device), `part` scratch of kMaxRhs * kReduceBlocks doubles:
+//   dot_pairs: dout[q] = X_q . (Y_q * wt)     (wt optional, read once)
+//   cg_update: psi_q += a_q p_q, r_q -= a_q q_q, dout[q] = r_q . (r_q * wt)
+//   xpby_b:    Y_q = X_q + b_q Y_q
+//   sub_masked_b: X_q -= scale * val[q * stride] where mask != 0
+void launch_dot_pairs(int nr, const VPtr<const double> &X, const VPtr<const double> &Y, const double *wt,
+                      int64_t n, double *part, double *dout, int64_t dstride, hipStream_t s);
+void launch_cg_update(int nr, const VPtr<const double> &Pv, const VPtr<const double> &Qv, const VPtr<double> &Psi,
+                      const VPtr<double> &R, const Coef4 &a, const double *wt, int64_t n, double *part, double *dout,
+                      int64_t dstride, hipStream_t s);
+void launch_xpby_b(int nr, const VPtr<const double> &X, const Coef4 &b, const VPtr<double> &Y, int64_t n,
+                   hipStream_t s);
+void launch_sub_masked_b(int nr, int64_t n, const double *mask, const double *val, int64_t stride, double scale,
+                         const VPtr<double> &X, hipStream_t s);
 // masked shift: x[n] -= scale * val[0] where mask[n] != 0 (val on device)
 void launch_sub_masked(int64_t n, const double *mask, const double *val, double scale, double *x,
                        hipStream_t s);

@@ -934,6 +934,124 @@ k_mdot_final(int nblk, const double *__restrict__ part, double *__restrict__ out
     }
 }
 
+// Dot products of up to kMaxRhs pairs in one pass:
+//   part[q][block] = partial sum of X_q . (Y_q * wt) for the pairs with X_q set
+// (wt, when given, is read once for all pairs)
+template <int VEC>
+__global__ void __launch_bounds__(kThreads)
+k_dot_pairs(VPtr<const double> X, VPtr<const double> Y, const double *__restrict__ wt, int64_t n,
+            double *__restrict__ part) {
+    using O = Vec<VEC>;
+    const int64_t nvec = n / VEC;
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec; e += (int64_t)gridDim.x * kThreads) {
+        const typename O::T w = wt ? O::ld(wt, e) : typename O::T{};
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (X.p[q]) {
+                const typename O::T x = O::ld(X.p[q], e);
+                acc[q] += O::dot(wt ? O::mul(x, w) : x, O::ld(Y.p[q], e));
+            }
+    }
+    if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double w = wt ? wt[n - 1] : 1.0;
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (X.p[q]) acc[q] += X.p[q][n - 1] * w * Y.p[q][n - 1];
+    }
+    __shared__ double sh[kThreads / 64][kMaxRhs];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) {
+        double v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxRhs) {
+        double t = 0.0;
+        for (int u = 0; u < kThreads / 64; ++u) t += sh[u][threadIdx.x];
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// out[v * stride] = sum of part row v (rows of nblk partial sums)
+__global__ void __launch_bounds__(kThreads)
+k_mdot_final_strided(int nblk, const double *__restrict__ part, double *__restrict__ out, int64_t stride) {
+    const int v = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(int64_t)v * nblk + b];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double sh[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int u = 0; u < kThreads / 64; ++u) t += sh[u];
+        out[(int64_t)v * stride] = t;
+    }
+}
+
+// One conjugate-gradient update of the vectors with Pv_q set:
+//   psi_q += a_q p_q,  r_q -= a_q q_q,  part[q][block] = partial of r_q . (r_q * wt)
+__global__ void __launch_bounds__(kThreads)
+k_cg_update(VPtr<const double> Pv, VPtr<const double> Qv, VPtr<double> Psi, VPtr<double> R, Coef4 a,
+            const double *__restrict__ wt, int64_t n, double *__restrict__ part) {
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+        const double w = wt[e];
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (Pv.p[q]) {
+                Psi.p[q][e] += a.v[q] * Pv.p[q][e];
+                const double r = R.p[q][e] - a.v[q] * Qv.p[q][e];
+                R.p[q][e] = r;
+                acc[q] += r * r * w;
+            }
+    }
+    __shared__ double sh[kThreads / 64][kMaxRhs];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) {
+        double v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxRhs) {
+        double t = 0.0;
+        for (int u = 0; u < kThreads / 64; ++u) t += sh[u][threadIdx.x];
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// Y_q = X_q + b_q Y_q for the vectors with Y_q set
+__global__ void __launch_bounds__(kThreads)
+k_xpby_b(VPtr<const double> X, Coef4 b, VPtr<double> Y, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (Y.p[q]) Y.p[q][e] = X.p[q][e] + b.v[q] * Y.p[q][e];
+}
+
+// X_q -= scale * val[q * stride] where mask != 0, for the vectors with X_q set
+__global__ void __launch_bounds__(kThreads)
+k_sub_masked_b(int64_t n, const double *__restrict__ mask, const double *__restrict__ val, int64_t stride,
+               double scale, VPtr<double> X) {
+    double m[kMaxRhs];
+#pragma unroll
+    for (int q = 0; q < kMaxRhs; ++q) m[q] = X.p[q] ? val[q * stride] * scale : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
+        if (mask[e] != 0.0)
+#pragma unroll
+            for (int q = 0; q < kMaxRhs; ++q)
+                if (X.p[q]) X.p[q][e] -= m[q];
+}
+
 // Block forms for the eigensolver's basis work (NW <= 8 vectors at once):
 // part[(i*NW + q)][block] = partial sums of V_i . (W_q * wt) for i < nv; the
 // basis is read once, W once per chunk of CH basis vectors (CH * NW ~ 16
@@ -1673,6 +1791,47 @@ void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, co
     else
         hipLaunchKernelGGL(k_maxpy<1>, flat_grid(n), dim3(kThreads), 0, s, nv, V, ld, c,
                            (const double *)nullptr, w, scale, out, n, 0, Span{});
+}
+
+void launch_dot_pairs(int nr, const VPtr<const double> &X, const VPtr<const double> &Y, const double *wt,
+                      int64_t n, double *part, double *dout, int64_t dstride, hipStream_t s) {
+    if (nr < 1 || nr > kMaxRhs) throw std::runtime_error("launch_dot_pairs: 1 to 4 pairs");
+    VPtr<const double> x{}, y{};
+    for (int q = 0; q < nr; ++q) {
+        x.p[q] = X.p[q];
+        y.p[q] = X.p[q] ? Y.p[q] : nullptr;
+    }
+    bool v2 = vec2_ok(n, 0, {wt});
+    for (int q = 0; q < nr; ++q) v2 = v2 && vec2_ok(n, 0, {x.p[q], y.p[q]});
+    if (v2) hipLaunchKernelGGL(k_dot_pairs<2>, dim3(kReduceBlocks), dim3(kThreads), 0, s, x, y, wt, n, part);
+    else hipLaunchKernelGGL(k_dot_pairs<1>, dim3(kReduceBlocks), dim3(kThreads), 0, s, x, y, wt, n, part);
+    hipLaunchKernelGGL(k_mdot_final_strided, dim3(nr), dim3(kThreads), 0, s, (int)kReduceBlocks,
+                       (const double *)part, dout, dstride);
+}
+
+void launch_cg_update(int nr, const VPtr<const double> &Pv, const VPtr<const double> &Qv, const VPtr<double> &Psi,
+                      const VPtr<double> &R, const Coef4 &a, const double *wt, int64_t n, double *part, double *dout,
+                      int64_t dstride, hipStream_t s) {
+    if (nr < 1 || nr > kMaxRhs) throw std::runtime_error("launch_cg_update: 1 to 4 vectors");
+    VPtr<const double> pv{};
+    for (int q = 0; q < nr; ++q) pv.p[q] = Pv.p[q];
+    hipLaunchKernelGGL(k_cg_update, dim3(kReduceBlocks), dim3(kThreads), 0, s, pv, Qv, Psi, R, a, wt, n, part);
+    hipLaunchKernelGGL(k_mdot_final_strided, dim3(nr), dim3(kThreads), 0, s, (int)kReduceBlocks,
+                       (const double *)part, dout, dstride);
+}
+
+void launch_xpby_b(int nr, const VPtr<const double> &X, const Coef4 &b, const VPtr<double> &Y, int64_t n,
+                   hipStream_t s) {
+    VPtr<double> y{};
+    for (int q = 0; q < nr && q < kMaxRhs; ++q) y.p[q] = Y.p[q];
+    hipLaunchKernelGGL(k_xpby_b, flat_grid(n), dim3(kThreads), 0, s, X, b, y, n);
+}
+
+void launch_sub_masked_b(int nr, int64_t n, const double *mask, const double *val, int64_t stride, double scale,
+                         const VPtr<double> &X, hipStream_t s) {
+    VPtr<double> x{};
+    for (int q = 0; q < nr && q < kMaxRhs; ++q) x.p[q] = X.p[q];
+    hipLaunchKernelGGL(k_sub_masked_b, flat_grid(n), dim3(kThreads), 0, s, n, mask, val, stride, scale, x);
 }
 
 void launch_sub_masked(int64_t n, const double *mask, const double *val, double scale, double *x,

@@ -669,15 +669,28 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
         if (!gx) gx = capture(op, [&](hipStream_t cs) { svcycle_b(op, 0, nr, cs); });
         DM_HIP(hipGraphLaunch(gx, s));
     };
+    // the vectors of the slots whose flag is set (the rest left out of a launch)
+    auto pick = [&](const VPtr<double> &X, const bool *on) {
+        VPtr<double> v{};
+        for (int q = 0; q < nr; ++q) v.p[q] = on[q] ? X.p[q] : nullptr;
+        return v;
+    };
+    // x_q -= its mean over the active cells (a floating scalar problem)
+    const double inv_cells = 1.0 / (double)std::max<int64_t>(1, L.n_act_cells);
+    auto demean = [&](const VPtr<double> &X) {
+        if (!op->s_floating) return;
+        VPtr<const double> M{};
+        for (int q = 0; q < nr; ++q) M.p[q] = op->cmask;
+        launch_dot_pairs(nr, as_const(X), M, nullptr, P, op->part, op->bk_dres + 2, kMaxDots, s);
+        launch_sub_masked_b(nr, P, op->cmask, op->bk_dres + 2, kMaxDots, inv_cells, X, s);
+    };
     launch_div_DA_b(g, L.coef64, nr, B, G, s);
-    for (int q = 0; q < nr; ++q) {
-        if (op->s_floating) demean_cells(op, G.p[q], s);
-        launch_mdot(1, G.p[q], 0, G.p[q], op->cmask, P, op->part, dres(q), s);
-        launch_mdot(1, b[q], 0, b[q], op->wa, n, op->part, dres(q) + 1, s);
-    }
+    demean(G);
+    launch_dot_pairs(nr, as_const(G), as_const(G), op->cmask, P, op->part, op->bk_dres, kMaxDots, s);
+    launch_dot_pairs(nr, B, B, op->wa, n, op->part, op->bk_dres + 1, kMaxDots, s);
     fetch();
     double stop[kMaxRhs], rz[kMaxRhs];
-    bool act[kMaxRhs];
+    bool act[kMaxRhs] = {};
     int its[kMaxRhs];
     bool any = false;
     for (int q = 0; q < nr; ++q) {
@@ -691,21 +704,20 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
     }
     DM_HIP(hipMemsetAsync(op->pjb_psi, 0, (size_t)nr * P * sizeof(double), s));
     if (any) {
-        for (int q = 0; q < nr; ++q) launch_copy(P, G.p[q], R.p[q], s);
+        launch_copy((int64_t)nr * P, G.p[0], R.p[0], s);   // the slots are consecutive
         graph();                                   // r -> z, every slot
-        for (int q = 0; q < nr; ++q) {
-            if (op->s_floating) demean_cells(op, Z.p[q], s);
-            launch_copy(P, Z.p[q], PP.p[q], s);
-            launch_mdot(1, R.p[q], 0, Z.p[q], op->cmask, P, op->part, dres(q), s);
-        }
+        demean(Z);
+        launch_copy((int64_t)nr * P, Z.p[0], PP.p[0], s);
+        launch_dot_pairs(nr, as_const(R), as_const(Z), op->cmask, P, op->part, op->bk_dres, kMaxDots, s);
         fetch();
         for (int q = 0; q < nr; ++q) rz[q] = hres(q)[0];
         int it = 0;
         while (it < maxit) {
             launch_s_apply_b(g, L.coef64, L.sweight, 0, nr, VPtr<const double>{}, as_const(PP), Q, s);
-            for (int q = 0; q < nr; ++q)
-                if (act[q]) launch_mdot(1, PP.p[q], 0, Q.p[q], op->cmask, P, op->part, dres(q), s);
+            launch_dot_pairs(nr, as_const(pick(PP, act)), as_const(Q), op->cmask, P, op->part, op->bk_dres,
+                             kMaxDots, s);
             fetch();
+            Coef4 alpha;
             for (int q = 0; q < nr; ++q) {
                 if (!act[q]) continue;
                 const double pq = hres(q)[0];
@@ -713,12 +725,15 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
                     act[q] = false;
                     continue;
                 }
-                const double alpha = rz[q] / pq;
-                launch_axpy(P, alpha, PP.p[q], PSI.p[q], s);
-                launch_axpy(P, -alpha, Q.p[q], R.p[q], s);
+                alpha.v[q] = rz[q] / pq;
                 ++its[q];
-                launch_mdot(1, R.p[q], 0, R.p[q], op->cmask, P, op->part, dres(q), s);
             }
+            bool upd = false;
+            for (int q = 0; q < nr; ++q) upd = upd || act[q];
+            if (!upd) break;
+            // psi += alpha p, r -= alpha q and |r|^2, every active system
+            launch_cg_update(nr, as_const(pick(PP, act)), as_const(Q), PSI, R, alpha, op->cmask, P, op->part,
+                             op->bk_dres, kMaxDots, s);
             ++it;
             fetch();
             any = false;
@@ -728,18 +743,18 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
             }
             if (!any) break;
             graph();                               // r -> z
-            for (int q = 0; q < nr; ++q) {
-                if (!act[q]) continue;
-                if (op->s_floating) demean_cells(op, Z.p[q], s);
-                launch_mdot(1, R.p[q], 0, Z.p[q], op->cmask, P, op->part, dres(q), s);
-            }
+            demean(pick(Z, act));
+            launch_dot_pairs(nr, as_const(pick(R, act)), as_const(Z), op->cmask, P, op->part, op->bk_dres,
+                             kMaxDots, s);
             fetch();
+            Coef4 beta;
             for (int q = 0; q < nr; ++q) {
                 if (!act[q]) continue;
                 const double rz2 = hres(q)[0];
-                launch_axpby(P, 1.0, Z.p[q], rz2 / rz[q], PP.p[q], s);
+                beta.v[q] = rz2 / rz[q];
                 rz[q] = rz2;
             }
+            launch_xpby_b(nr, as_const(Z), beta, pick(PP, act), P, s);   // p = z + beta p
         }
     }
     VPtr<double> O{};
@@ -1125,13 +1140,30 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
         dots(op, q + 1, V, n, t2, wk, n, s);
         for (int i = 0; i <= q; ++i) Gat(i, q) = Gat(q, i) = op->hres[i];
     };
-    // start block
+    // start block: random vectors, projected together where the block path
+    // runs (the projections are independent), then A-orthonormalised
     for (int c = 0; c < b; ++c) {
         double *v = V + (size_t)c * n;
         launch_randn(n, seed, (int64_t)c * n, op->fmask, v, s);
         launch_mirror_faces<double>(L.g, v, s);
-        project(op, v, v, opt.proj_rtol, 1000, s, &pj);
-        proj_its += pj;
+    }
+    if (blocked) {
+        for (int c0 = 0; c0 < b; c0 += kMaxRhs) {
+            const int nr = std::min(kMaxRhs, b - c0);
+            const double *bp[kMaxRhs];
+            double *op_[kMaxRhs];
+            int pits[kMaxRhs];
+            for (int q = 0; q < nr; ++q) bp[q] = op_[q] = V + (size_t)(c0 + q) * n;
+            project_block(op, nr, bp, op_, opt.proj_rtol, 1000, s, pits);
+            for (int q = 0; q < nr; ++q) proj_its += pits[q];
+        }
+    }
+    for (int c = 0; c < b; ++c) {
+        double *v = V + (size_t)c * n;
+        if (!blocked) {
+            project(op, v, v, opt.proj_rtol, 1000, s, &pj);
+            proj_its += pj;
+        }
         orth(V, c, v, nullptr);
         if (!(A_normalize(v) > 0)) throw DmError{DM_EBREAKDOWN, "eigs: zero start vector"};
         add_gk(c);
