@@ -7,6 +7,7 @@
 // The stencil path is memory bound: no MFMA here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <stdexcept>
 
 #include "dm_internal.h"
@@ -1756,30 +1757,55 @@ void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *
                            (const double *)nullptr, 1.0, y, n, overwrite, sp);
 }
 
+// Workgroups of a grid-stride reduction kernel: as many as are resident at
+// once (its occupancy times the CUs), at most kReduceBlocks.  Every
+// workgroup carries the same share of the work, so a grid beyond what is
+// resident leaves a partial second round (1024 workgroups of a kernel with
+// three resident per CU ran as 768 + 256).  Computed once per kernel.
+template <auto KERN>
+int reduce_blocks() {
+    static const int nb = [] {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, KERN, kThreads, 0) != hipSuccess || cus <= 0 ||
+            per <= 0)
+            return kReduceBlocks;
+        return std::min(kReduceBlocks, cus * per);
+    }();
+    return nb;
+}
+
 void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
                             int64_t n, double *part, double *dout, hipStream_t s, const double *cscale,
                             Span sp) {
     if (nv < 1 || nv + 1 > 256) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
     const bool v2 = vec2_ok(n, ld, {V, w});
-    const dim3 g(kReduceBlocks), b(kThreads);
+    const dim3 b(kThreads);
+    int nb = kReduceBlocks;
+    // one fused kernel for nv <= 32 (the basis held in registers)
+    auto fused = [&](auto kern, int blocks) {
+        nb = blocks;
+        hipLaunchKernelGGL(kern, dim3(nb), b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
+    };
     if (nv <= 8) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 8, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
+        if (v2) fused(k_maxpy_mdot_norm<2, 8, false>, reduce_blocks<k_maxpy_mdot_norm<2, 8, false>>());
+        else fused(k_maxpy_mdot_norm<1, 8, false>, reduce_blocks<k_maxpy_mdot_norm<1, 8, false>>());
     } else if (nv <= 16) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 16, false>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
+        if (v2) fused(k_maxpy_mdot_norm<2, 16, false>, reduce_blocks<k_maxpy_mdot_norm<2, 16, false>>());
+        else fused(k_maxpy_mdot_norm<1, 16, false>, reduce_blocks<k_maxpy_mdot_norm<1, 16, false>>());
     } else if (nv <= 32) {
-        if (v2) hipLaunchKernelGGL((k_maxpy_mdot_norm<2, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
-        else hipLaunchKernelGGL((k_maxpy_mdot_norm<1, 32, true>), g, b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
+        if (v2) fused(k_maxpy_mdot_norm<2, 32, true>, reduce_blocks<k_maxpy_mdot_norm<2, 32, true>>());
+        else fused(k_maxpy_mdot_norm<1, 32, true>, reduce_blocks<k_maxpy_mdot_norm<1, 32, true>>());
     } else {
         // too many vectors to hold in registers: update w, then a second
         // pass for the dots (the basis is read twice)
         launch_maxpy(nv, V, ld, c, w, n, 0, s, cscale, sp);
+        const dim3 g(kReduceBlocks);
         if (v2) hipLaunchKernelGGL((k_mdot_norm<2>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
         else hipLaunchKernelGGL((k_mdot_norm<1>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
     }
-    hipLaunchKernelGGL(k_mdot_final, dim3(nv + 1), dim3(kThreads), 0, s, (int)kReduceBlocks,
-                       (const double *)part, dout);
+    hipLaunchKernelGGL(k_mdot_final, dim3(nv + 1), dim3(kThreads), 0, s, nb, (const double *)part, dout);
 }
 
 void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,
