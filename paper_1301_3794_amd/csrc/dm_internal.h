@@ -350,20 +350,27 @@ void launch_div_DA_b(const Grid &g, const double *coef, int nr, const VPtr<const
                      const VPtr<double> &out, hipStream_t s);
 void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<const double> &psi,
                        const VPtr<const double> &b_in, const VPtr<double> &b_out, double scale, hipStream_t s);
-void launch_s_apply_b(const Grid &g, const double *coef, double w, int resid, int nr, const VPtr<const double> &f,
-                      const VPtr<const double> &x, const VPtr<double> &y, hipStream_t s);
-void launch_s_smooth_b(const Grid &g, const double *coef, double w, int colour, int nr, const VPtr<const double> &f,
-                       const VPtr<double> &x, hipStream_t s);
-void launch_s_restrict_b(const Grid &gf, const Grid &gc, const double *coef_c, int nr, const VPtr<const double> &r,
-                         const VPtr<double> &fc, hipStream_t s);
-void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const double *coef_f, int nr,
-                            const VPtr<const double> &xc, const VPtr<double> &x, hipStream_t s);
+// (FP64, or FP32 with the FP32 coefficient blocks: the preconditioner of the
+// projection's conjugate gradients)
+template <class T>
+void launch_s_apply_b(const Grid &g, const T *coef, double w, int resid, int nr, const VPtr<const T> &f,
+                      const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s);
+template <class T>
+void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int nr, const VPtr<const T> &f,
+                       const VPtr<T> &x, hipStream_t s);
+template <class T>
+void launch_s_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
+                         const VPtr<T> &fc, hipStream_t s);
+template <class T>
+void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, int nr, const VPtr<const T> &xc,
+                            const VPtr<T> &x, hipStream_t s);
 
 // PMC ghost layers of a face / cell vector from the adjacent values (no-op
 // without PMC planes)
 template <class T>
 void launch_mirror_faces(const Grid &g, T *x, hipStream_t s);
-void launch_mirror_cells(const Grid &g, double *x, hipStream_t s);
+template <class T>
+void launch_mirror_cells(const Grid &g, T *x, hipStream_t s);
 
 // scalar (cell-centred) Laplacian S = D A D^T with per-level weight `w`
 void launch_div_DA(const Grid &g, const double *coef, const double *b, double *gout,

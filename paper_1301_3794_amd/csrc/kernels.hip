@@ -566,7 +566,8 @@ __global__ void k_mirror_faces(Grid g, int a, T *__restrict__ x) {
     }
 }
 
-__global__ void k_mirror_cells(Grid g, int a, double *__restrict__ x) {
+template <class T>
+__global__ void k_mirror_cells(Grid g, int a, T *__restrict__ x) {
     const int n[3] = {g.nx, g.ny, g.nz};
     const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
     const int nb = n[b] + 2, nd = n[d] + 2;
@@ -610,27 +611,29 @@ __device__ __forceinline__ void grad_sub_body(const Grid &g, const Coefs<double>
     put_face<double>(g, bout + 2 * P, 2, i, j, k, p, vz);
 }
 
-__device__ inline double s_row(const Coefs<double> &c, const double *x, int64_t p, int64_t dy,
-                               int64_t dz) {
-    const double xp = x[p];
+template <class T>
+__device__ inline T s_row(const Coefs<T> &c, const T *x, int64_t p, int64_t dy, int64_t dz) {
+    const T xp = x[p];
     return c.ax[p] * (xp - x[p - 1]) + c.ax[p + 1] * (xp - x[p + 1]) +
            c.ay[p] * (xp - x[p - dy]) + c.ay[p + dy] * (xp - x[p + dy]) +
            c.az[p] * (xp - x[p - dz]) + c.az[p + dz] * (xp - x[p + dz]);
 }
 
-__device__ __forceinline__ void s_apply_body(const Grid &g, const Coefs<double> &c, double w, int resid,
-                                             const double *__restrict__ f, const double *__restrict__ x,
-                                             double *__restrict__ y, int64_t item) {
+template <class T>
+__device__ __forceinline__ void s_apply_body(const Grid &g, const Coefs<T> &c, T w, int resid,
+                                             const T *__restrict__ f, const T *__restrict__ x, T *__restrict__ y,
+                                             int64_t item) {
     int i, j, k;
     if (!cell_of(g, item, i, j, k)) return;
     const int64_t p = pidx(g, i, j, k);
-    double v = w * s_row(c, x, p, g.sy, g.sz);
+    T v = w * s_row<T>(c, x, p, g.sy, g.sz);
     if (resid) v = f[p] - v;
-    put_cell<double>(g, y, i, j, k, p, c.vinv[p] != 0.0 ? v : 0.0);
+    put_cell<T>(g, y, i, j, k, p, c.vinv[p] != T(0) ? v : T(0));
 }
 
-__device__ __forceinline__ void s_smooth_body(const Grid &g, const Coefs<double> &c, double w, int colour,
-                                              const double *__restrict__ f, double *__restrict__ x, int64_t t) {
+template <class T>
+__device__ __forceinline__ void s_smooth_body(const Grid &g, const Coefs<T> &c, T w, int colour,
+                                              const T *__restrict__ f, T *__restrict__ x, int64_t t) {
     const int nxh = (g.nx + 1) >> 1;
     if (t >= (int64_t)nxh * g.ny * g.nz) return;
     const int ih = (int)(t % nxh);
@@ -639,39 +642,39 @@ __device__ __forceinline__ void s_smooth_body(const Grid &g, const Coefs<double>
     const int i = 2 * ih + ((j + k + colour) & 1);
     if (i >= g.nx) return;
     const int64_t dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
-    if (c.vinv[p] == 0.0) return;
-    double d = c.ax[p] + c.ax[p + 1] + c.ay[p] + c.ay[p + dy] + c.az[p] + c.az[p + dz];
+    if (c.vinv[p] == T(0)) return;
+    T d = c.ax[p] + c.ax[p + 1] + c.ay[p] + c.ay[p + dy] + c.az[p] + c.az[p + dz];
     // odd mirror across a PMC plane: the face in the plane counts twice
     if ((g.pmc & 1) && i == 0) d += c.ax[p];
     if ((g.pmc & 2) && j == 0) d += c.ay[p];
     if ((g.pmc & 4) && k == 0) d += c.az[p];
     d *= w;
-    if (d == 0.0) return;
-    put_cell<double>(g, x, i, j, k, p, x[p] + (f[p] - w * s_row(c, x, p, dy, dz)) / d);
+    if (d == T(0)) return;
+    put_cell<T>(g, x, i, j, k, p, x[p] + (f[p] - w * s_row<T>(c, x, p, dy, dz)) / d);
 }
 
-__device__ __forceinline__ void s_restrict_body(const Grid &gf, const Grid &gc, const Coefs<double> &cc,
-                                                const double *__restrict__ r, double *__restrict__ fc,
-                                                int64_t item) {
+template <class T>
+__device__ __forceinline__ void s_restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
+                                                const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
     int I, J, K;
     if (!cell_of(gc, item, I, J, K)) return;
     const int64_t pc = pidx(gc, I, J, K), q = pidx(gf, 2 * I, 2 * J, 2 * K);
     const int64_t fy = gf.sy, fz = gf.sz;
-    double s = 0.0;
+    T s = T(0);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) s += r[q + a * fy + b * fz] + r[q + 1 + a * fy + b * fz];
-    put_cell<double>(gc, fc, I, J, K, pc, cc.vinv[pc] != 0.0 ? 0.125 * s : 0.0);
+    put_cell<T>(gc, fc, I, J, K, pc, cc.vinv[pc] != T(0) ? T(0.125) * s : T(0));
 }
 
-__device__ __forceinline__ void s_prolong_body(const Grid &gf, const Grid &gc, const Coefs<double> &cf,
-                                               const double *__restrict__ xc, double *__restrict__ x,
-                                               int64_t item) {
+template <class T>
+__device__ __forceinline__ void s_prolong_body(const Grid &gf, const Grid &gc, const Coefs<T> &cf,
+                                               const T *__restrict__ xc, T *__restrict__ x, int64_t item) {
     int i, j, k;
     if (!cell_of(gf, item, i, j, k)) return;
     const int64_t p = pidx(gf, i, j, k);
-    if (cf.vinv[p] != 0.0) put_cell<double>(gf, x, i, j, k, p, x[p] + xc[pidx(gc, i >> 1, j >> 1, k >> 1)]);
+    if (cf.vinv[p] != T(0)) put_cell<T>(gf, x, i, j, k, p, x[p] + xc[pidx(gc, i >> 1, j >> 1, k >> 1)]);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -687,25 +690,25 @@ k_grad_sub(Grid g, Coefs<double> c, const double *__restrict__ psi, const double
 __global__ void __launch_bounds__(kThreads)
 k_s_apply(Grid g, Coefs<double> c, double w, int resid, const double *__restrict__ f,
           const double *__restrict__ x, double *__restrict__ y) {
-    s_apply_body(g, c, w, resid, f, x, y, xcd_item());
+    s_apply_body<double>(g, c, w, resid, f, x, y, xcd_item());
 }
 
 __global__ void __launch_bounds__(kThreads)
 k_s_smooth(Grid g, Coefs<double> c, double w, int colour, const double *__restrict__ f,
            double *__restrict__ x) {
-    s_smooth_body(g, c, w, colour, f, x, xcd_item());
+    s_smooth_body<double>(g, c, w, colour, f, x, xcd_item());
 }
 
 __global__ void __launch_bounds__(kThreads)
 k_s_restrict(Grid gf, Grid gc, Coefs<double> cc, const double *__restrict__ r,
              double *__restrict__ fc) {
-    s_restrict_body(gf, gc, cc, r, fc, xcd_item());
+    s_restrict_body<double>(gf, gc, cc, r, fc, xcd_item());
 }
 
 __global__ void __launch_bounds__(kThreads)
 k_s_prolong_add(Grid gf, Grid gc, Coefs<double> cf, const double *__restrict__ xc,
                 double *__restrict__ x) {
-    s_prolong_body(gf, gc, cf, xc, x, xcd_item());
+    s_prolong_body<double>(gf, gc, cf, xc, x, xcd_item());
 }
 
 // block forms of the scalar kernels: NR lanes per cell, one vector each
@@ -726,37 +729,36 @@ k_grad_sub_b(Grid g, Coefs<double> c, VPtr<const double> psi, VPtr<const double>
     grad_sub_body(g, c, psi.p[q], bin.p[q], bout.p[q], scale, t);
 }
 
-template <int NR>
+template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_apply_b(Grid g, Coefs<double> c, double w, int resid, VPtr<const double> f, VPtr<const double> x,
-            VPtr<double> y) {
+k_s_apply_b(Grid g, Coefs<T> c, T w, int resid, VPtr<const T> f, VPtr<const T> x, VPtr<T> y) {
     int q;
     const int64_t t = wave_item(q);
-    s_apply_body(g, c, w, resid, f.p[q], x.p[q], y.p[q], t);
+    s_apply_body<T>(g, c, w, resid, f.p[q], x.p[q], y.p[q], t);
 }
 
-template <int NR>
+template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_smooth_b(Grid g, Coefs<double> c, double w, int colour, VPtr<const double> f, VPtr<double> x) {
+k_s_smooth_b(Grid g, Coefs<T> c, T w, int colour, VPtr<const T> f, VPtr<T> x) {
     int q;
     const int64_t t = wave_item(q);
-    s_smooth_body(g, c, w, colour, f.p[q], x.p[q], t);
+    s_smooth_body<T>(g, c, w, colour, f.p[q], x.p[q], t);
 }
 
-template <int NR>
+template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_restrict_b(Grid gf, Grid gc, Coefs<double> cc, VPtr<const double> r, VPtr<double> fc) {
+k_s_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc) {
     int q;
     const int64_t t = wave_item(q);
-    s_restrict_body(gf, gc, cc, r.p[q], fc.p[q], t);
+    s_restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t);
 }
 
-template <int NR>
+template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_prolong_add_b(Grid gf, Grid gc, Coefs<double> cf, VPtr<const double> xc, VPtr<double> x) {
+k_s_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, VPtr<const T> xc, VPtr<T> x) {
     int q;
     const int64_t t = wave_item(q);
-    s_prolong_body(gf, gc, cf, xc.p[q], x.p[q], t);
+    s_prolong_body<T>(gf, gc, cf, xc.p[q], x.p[q], t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1549,37 +1551,54 @@ void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<con
                                         b_out, scale))
 }
 
-void launch_s_apply_b(const Grid &g, const double *coef, double w, int resid, int nr, const VPtr<const double> &f,
-                      const VPtr<const double> &x, const VPtr<double> &y, hipStream_t s) {
+template <class T>
+void launch_s_apply_b(const Grid &g, const T *coef, double w, int resid, int nr, const VPtr<const T> &f,
+                      const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    const Coefs<double> c = coefs_of(coef, g.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_apply_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, w, resid,
-                                        f, x, y))
+    const Coefs<T> c = coefs_of(coef, g.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_apply_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, (T)w,
+                                        resid, f, x, y))
 }
 
-void launch_s_smooth_b(const Grid &g, const double *coef, double w, int colour, int nr, const VPtr<const double> &f,
-                       const VPtr<double> &x, hipStream_t s) {
+template <class T>
+void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int nr, const VPtr<const T> &f,
+                       const VPtr<T> &x, hipStream_t s) {
     const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
-    const Coefs<double> c = coefs_of(coef, g.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_smooth_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, w, colour,
-                                        f, x))
+    const Coefs<T> c = coefs_of(coef, g.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_smooth_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, (T)w,
+                                        colour, f, x))
 }
 
-void launch_s_restrict_b(const Grid &gf, const Grid &gc, const double *coef_c, int nr, const VPtr<const double> &r,
-                         const VPtr<double> &fc, hipStream_t s) {
+template <class T>
+void launch_s_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
+                         const VPtr<T> &fc, hipStream_t s) {
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
-    const Coefs<double> cc = coefs_of(coef_c, gc.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_restrict_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc, r,
-                                        fc))
+    const Coefs<T> cc = coefs_of(coef_c, gc.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_restrict_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc,
+                                        r, fc))
 }
 
-void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const double *coef_f, int nr,
-                            const VPtr<const double> &xc, const VPtr<double> &x, hipStream_t s) {
+template <class T>
+void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, int nr, const VPtr<const T> &xc,
+                            const VPtr<T> &x, hipStream_t s) {
     const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
-    const Coefs<double> cf = coefs_of(coef_f, gf.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_prolong_add_b<NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cf,
-                                        xc, x))
+    const Coefs<T> cf = coefs_of(coef_f, gf.P);
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_prolong_add_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc,
+                                        cf, xc, x))
 }
+
+#define DM_SCALAR_BLOCK(T)                                                                                        \
+    template void launch_s_apply_b<T>(const Grid &, const T *, double, int, int, const VPtr<const T> &,           \
+                                      const VPtr<const T> &, const VPtr<T> &, hipStream_t);                       \
+    template void launch_s_smooth_b<T>(const Grid &, const T *, double, int, int, const VPtr<const T> &,          \
+                                       const VPtr<T> &, hipStream_t);                                             \
+    template void launch_s_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,       \
+                                         const VPtr<T> &, hipStream_t);                                           \
+    template void launch_s_prolong_add_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,    \
+                                            const VPtr<T> &, hipStream_t);
+DM_SCALAR_BLOCK(double)
+DM_SCALAR_BLOCK(float)
+#undef DM_SCALAR_BLOCK
 
 #undef DM_NR_SWITCH
 
@@ -1651,15 +1670,18 @@ void launch_mirror_faces(const Grid &g, T *x, hipStream_t s) {
     }
 }
 
-void launch_mirror_cells(const Grid &g, double *x, hipStream_t s) {
+template <class T>
+void launch_mirror_cells(const Grid &g, T *x, hipStream_t s) {
     const int n[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a) {
         if (!((g.pmc >> a) & 1)) continue;
         const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;
         const int64_t cnt = (int64_t)(n[b] + 2) * (n[d] + 2);
-        hipLaunchKernelGGL(k_mirror_cells, dim3((unsigned)ceil_div(cnt, kThreads)), dim3(kThreads), 0, s, g, a, x);
+        hipLaunchKernelGGL(k_mirror_cells<T>, dim3((unsigned)ceil_div(cnt, kThreads)), dim3(kThreads), 0, s, g, a, x);
     }
 }
+template void launch_mirror_cells<double>(const Grid &, double *, hipStream_t);
+template void launch_mirror_cells<float>(const Grid &, float *, hipStream_t);
 
 template void launch_mirror_faces<double>(const Grid &, double *, hipStream_t);
 template void launch_mirror_faces<float>(const Grid &, float *, hipStream_t);

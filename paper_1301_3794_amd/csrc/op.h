@@ -24,6 +24,7 @@ struct Level {
     double *bx64 = nullptr, *bf64 = nullptr, *br64 = nullptr;
     float *bx32 = nullptr, *bf32 = nullptr, *br32 = nullptr;
     double *bsx = nullptr, *bsf = nullptr, *bsr = nullptr;  // kMaxRhs * P (scalar MG)
+    float *bsx32 = nullptr, *bsf32 = nullptr, *bsr32 = nullptr;  // the same, FP32 scalar MG
     int64_t n_act_faces = 0, n_act_cells = 0;
     // non-vacuum rows of each smoother class (component c, colour col) as
     // padded indices: class 2c+col is cut[cut_off[2c+col] .. cut_off[2c+col+1])
@@ -120,6 +121,7 @@ struct dm_op {
     // block projection: per-vector CG state (kMaxRhs * P each) and graphs
     double *pjb_g = nullptr, *pjb_psi = nullptr, *pjb_p = nullptr, *pjb_q = nullptr;
     hipGraphExec_t g_svb[dm::kMaxRhs + 1] = {};
+    hipGraphExec_t g_svb32[dm::kMaxRhs + 1] = {};  // FP32 scalar block V-cycle with its casts
     std::vector<void *> allocs;  // everything to free
     int last_proj_iters = 0;
     // learned correction: the attached network (not owned) and its scratch
@@ -165,9 +167,11 @@ void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const
           int64_t n, hipStream_t s, Span sp = {});
 int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hipStream_t s,
             int *iters);
-// project() on nr (1..kMaxRhs) vectors in lockstep; iters: nr entries or NULL
+// project() on nr (1..kMaxRhs) vectors in lockstep; iters: nr entries or NULL;
+// prec: precision of the scalar V-cycle preconditioning the conjugate
+// gradients (64 or 32; the gradients themselves run in FP64 either way)
 int project_block(dm_op *op, int nr, const double *const *b, double *const *out, double rtol, int maxit,
-                  hipStream_t s, int *iters);
+                  hipStream_t s, int *iters, int prec = 64);
 int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
           dm_solve_info *info, hipStream_t s);
 // nrhs (1..kMaxRhs) systems M x_r = f_r in lockstep, FGMRES modes only;

@@ -49,6 +49,24 @@ struct BPrec<float> {
     static float *r(Level &L) { return L.br32; }
 };
 
+// the scalar block V-cycle's buffers and coefficients per precision
+template <class T>
+struct SPrec;
+template <>
+struct SPrec<double> {
+    static const double *coef(const Level &L) { return L.coef64; }
+    static double *x(Level &L) { return L.bsx; }
+    static double *f(Level &L) { return L.bsf; }
+    static double *r(Level &L) { return L.bsr; }
+};
+template <>
+struct SPrec<float> {
+    static const float *coef(const Level &L) { return L.coef32; }
+    static float *x(Level &L) { return L.bsx32; }
+    static float *f(Level &L) { return L.bsf32; }
+    static float *r(Level &L) { return L.bsr32; }
+};
+
 // nr consecutive slots of `stride` elements from base
 template <class T>
 VPtr<T> slots(T *base, int64_t stride, int nr) {
@@ -449,28 +467,32 @@ void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
         for (int col = 1; col >= 0; --col) launch_s_smooth(g, L.coef64, L.sweight, col, f, x, s);
 }
 
-// svcycle() on nr vectors at once (the level's scalar block slots)
+// svcycle() on nr vectors at once (the level's scalar block slots), in FP64
+// or in FP32 (FP32 coefficient blocks and slots)
+template <class T>
 void svcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
+    using S = SPrec<T>;
     Level &L = op->lv[l];
     const Grid &g = L.g;
     const int64_t P = g.P;
-    const VPtr<double> F = slots(L.bsf, P, nr), X = slots(L.bsx, P, nr);
-    launch_zero<double>(nr * P, L.bsx, s);
+    const T *c = S::coef(L);
+    const VPtr<T> F = slots(S::f(L), P, nr), X = slots(S::x(L), P, nr);
+    launch_zero<T>(nr * P, S::x(L), s);
     if (l == op->nlev() - 1) {
-        launch_coarse_solve_b<double>(op->ns, op->sinv, op->sidx, nr, as_const(F), X, s);
-        for (int q = 0; q < nr; ++q) launch_mirror_cells(g, X.p[q], s);
+        launch_coarse_solve_b<T>(op->ns, op->sinv, op->sidx, nr, as_const(F), X, s);
+        for (int q = 0; q < nr; ++q) launch_mirror_cells<T>(g, X.p[q], s);
         return;
     }
     for (int it = 0; it < op->opt.nu_pre; ++it)
-        for (int col = 0; col < 2; ++col) launch_s_smooth_b(g, L.coef64, L.sweight, col, nr, as_const(F), X, s);
-    const VPtr<double> R = slots(L.bsr, P, nr);
-    launch_s_apply_b(g, L.coef64, L.sweight, 1, nr, as_const(F), as_const(X), R, s);
+        for (int col = 0; col < 2; ++col) launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s);
+    const VPtr<T> R = slots(S::r(L), P, nr);
+    launch_s_apply_b<T>(g, c, L.sweight, 1, nr, as_const(F), as_const(X), R, s);
     Level &C = op->lv[l + 1];
-    launch_s_restrict_b(g, C.g, C.coef64, nr, as_const(R), slots(C.bsf, C.g.P, nr), s);
-    svcycle_b(op, l + 1, nr, s);
-    launch_s_prolong_add_b(g, C.g, L.coef64, nr, as_const(slots(C.bsx, C.g.P, nr)), X, s);
+    launch_s_restrict_b<T>(g, C.g, S::coef(C), nr, as_const(R), slots(S::f(C), C.g.P, nr), s);
+    svcycle_b<T>(op, l + 1, nr, s);
+    launch_s_prolong_add_b<T>(g, C.g, c, nr, as_const(slots(S::x(C), C.g.P, nr)), X, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
-        for (int col = 1; col >= 0; --col) launch_s_smooth_b(g, L.coef64, L.sweight, col, nr, as_const(F), X, s);
+        for (int col = 1; col >= 0; --col) launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -511,7 +533,7 @@ void invalidate_graphs(dm_op *op) {
         *e = nullptr;
     }
     for (int q = 0; q <= kMaxRhs; ++q)
-        for (hipGraphExec_t *e : {&op->g_vb32[q], &op->g_vb64[q], &op->g_svb[q]}) {
+        for (hipGraphExec_t *e : {&op->g_vb32[q], &op->g_vb64[q], &op->g_svb[q], &op->g_svb32[q]}) {
             if (*e) (void)hipGraphExecDestroy(*e);
             *e = nullptr;
         }
@@ -635,8 +657,9 @@ int project(dm_op *op, const double *b, double *out, double rtol, int maxit, hip
 // scalar V-cycle per step, and one host sync per inner product.  r and z of
 // vector q live in the level-0 slots of the block scalar V-cycle.
 int project_block(dm_op *op, int nr, const double *const *b, double *const *out, double rtol, int maxit,
-                  hipStream_t s, int *iters) {
+                  hipStream_t s, int *iters, int prec) {
     if (nr < 1 || nr > kMaxRhs) throw DmError{DM_EINVAL, "block of 1 to 4 vectors"};
+    if (prec != 64 && prec != 32) throw DmError{DM_EINVAL, "scalar V-cycle precision must be 64 or 32"};
     ensure_block_results(op);
     Level &L = op->lv[0];
     const Grid &g = L.g;
@@ -653,6 +676,13 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
             Lv.bsf = op->dalloc<double>((size_t)kMaxRhs * Lv.g.P);
             Lv.bsr = op->dalloc<double>((size_t)kMaxRhs * Lv.g.P);
         }
+    if (prec == 32)
+        for (Level &Lv : op->lv)
+            if (!Lv.bsx32) {
+                Lv.bsx32 = op->dalloc<float>((size_t)kMaxRhs * Lv.g.P);
+                Lv.bsf32 = op->dalloc<float>((size_t)kMaxRhs * Lv.g.P);
+                Lv.bsr32 = op->dalloc<float>((size_t)kMaxRhs * Lv.g.P);
+            }
     const VPtr<double> G = slots(op->pjb_g, P, nr), PSI = slots(op->pjb_psi, P, nr), PP = slots(op->pjb_p, P, nr),
                        Q = slots(op->pjb_q, P, nr), R = slots(L.bsf, P, nr), Z = slots(L.bsx, P, nr);
     VPtr<const double> B{};
@@ -664,9 +694,20 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
                               hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
     };
+    // z = B r for every slot: the FP64 V-cycle on the slots themselves, or
+    // the FP32 one between two casts (the slots are consecutive)
     auto graph = [&]() {
-        hipGraphExec_t &gx = op->g_svb[nr];
-        if (!gx) gx = capture(op, [&](hipStream_t cs) { svcycle_b(op, 0, nr, cs); });
+        hipGraphExec_t &gx = prec == 64 ? op->g_svb[nr] : op->g_svb32[nr];
+        if (!gx)
+            gx = capture(op, [&](hipStream_t cs) {
+                if (prec == 64) {
+                    svcycle_b<double>(op, 0, nr, cs);
+                } else {
+                    launch_cast<double, float>(L.bsf, L.bsf32, (int64_t)nr * P, cs);
+                    svcycle_b<float>(op, 0, nr, cs);
+                    launch_cast<float, double>(L.bsx32, L.bsx, (int64_t)nr * P, cs);
+                }
+            });
         DM_HIP(hipGraphLaunch(gx, s));
     };
     // the vectors of the slots whose flag is set (the rest left out of a launch)
@@ -1060,6 +1101,9 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     // the block's M solves in lockstep (one block V-cycle per step) unless
     // the op's preconditioner is a batch's fused V-cycle or the mode is PCG
     const bool blocked = b > 1 && !op->batch && opt.solve_mode != DM_SOLVE_PCG64;
+    // the projection's scalar V-cycle follows the inner solves' V-cycle: FP32
+    // with the FP32-multigrid forms, FP64 with the FP64 one
+    const int sprec = opt.solve_mode == DM_SOLVE_FGMRES_MG64 ? 64 : 32;
     if (blocked && !op->eg_F) op->eg_F = op->dalloc<double>((size_t)kMaxRhs * n);
     if (blocked) ensure_krylov_small(op);
     else ensure_krylov(op);
@@ -1154,7 +1198,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
             double *op_[kMaxRhs];
             int pits[kMaxRhs];
             for (int q = 0; q < nr; ++q) bp[q] = op_[q] = V + (size_t)(c0 + q) * n;
-            project_block(op, nr, bp, op_, opt.proj_rtol, 1000, s, pits);
+            project_block(op, nr, bp, op_, opt.proj_rtol, 1000, s, pits, sprec);
             for (int q = 0; q < nr; ++q) proj_its += pits[q];
         }
     }
@@ -1203,7 +1247,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
                     double *op_[kMaxRhs];
                     int pits[kMaxRhs];
                     for (int q = 0; q < nr; ++q) bp[q] = op_[q] = W + (size_t)(c0 + q) * n;
-                    project_block(op, nr, bp, op_, opt.proj_rtol, 1000, s, pits);
+                    project_block(op, nr, bp, op_, opt.proj_rtol, 1000, s, pits, sprec);
                     for (int q = 0; q < nr; ++q) proj_its += pits[q];
                 }
             } else {
