@@ -402,11 +402,11 @@ constexpr int kMultiMax = 8;   // vectors per launch of the two kernels below
 // dout[i*nw + q] = V_i . (W_q * wt) for i < nv, q < nw (nw <= 8, nv*nw <= 256;
 // W_q = W + q*ldw); the basis is read once
 void launch_mdot_multi(int nv, const double *V, int64_t ld, const double *W, int64_t ldw, int nw,
-                       const double *wt, int64_t n, double *part, double *dout, hipStream_t s);
+                       const double *wt, int64_t n, double *part, double *dout, hipStream_t s, Span sp = {});
 // Y_q = sum_i C[i*nw + q] V_i (overwrite) or Y_q -= ... for q < nw (nw <= 8;
 // C on device; Y_q = Y + q*ldy); the basis is read once
 void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, int nw, double *Y, int64_t ldy,
-                        int64_t n, int overwrite, hipStream_t s);
+                        int64_t n, int overwrite, hipStream_t s, Span sp = {});
 // y -= sum_i c[i] V_i  (c on device)  or  y = sum_i c[i] V_i when overwrite;
 // with cscale (device, nv values) the coefficients are c[i] * cscale[i]
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,

@@ -1063,9 +1063,9 @@ k_sub_masked_b(int64_t n, const double *__restrict__ mask, const double *__restr
 template <int VEC, int NW, int CH>
 __global__ void __launch_bounds__(kThreads)
 k_mdot_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ W, int64_t ldw,
-             const double *__restrict__ wt, int64_t n, double *__restrict__ part) {
+             const double *__restrict__ wt, int64_t n, double *__restrict__ part, Span sp) {
     using O = Vec<VEC>;
-    const int64_t nvec = n / VEC, ldv = ld / VEC, ldwv = ldw / VEC;
+    const int64_t nvec = n / VEC, ldv = ld / VEC, ldwv = ldw / VEC, cnt = span_count<VEC>(sp, nvec);
     __shared__ double sh[kThreads / 64][CH * NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c0 = 0; c0 < nv; c0 += CH) {
@@ -1075,8 +1075,10 @@ k_mdot_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__r
         for (int a = 0; a < CH; ++a)
 #pragma unroll
             for (int q = 0; q < NW; ++q) acc[a][q] = 0.0;
-        for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
-             e += (int64_t)gridDim.x * kThreads) {
+        for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt;
+             it += (int64_t)gridDim.x * kThreads) {
+            const int64_t e = span_elem<VEC>(sp, it);
+            if (e >= nvec) continue;
             typename O::T wv[NW];
 #pragma unroll
             for (int q = 0; q < NW; ++q) {
@@ -1120,14 +1122,16 @@ k_mdot_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__r
 template <int VEC, int NW>
 __global__ void __launch_bounds__(kThreads)
 k_maxpy_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ C,
-              double *__restrict__ Y, int64_t ldy, int64_t n, int overwrite) {
+              double *__restrict__ Y, int64_t ldy, int64_t n, int overwrite, Span sp) {
     using O = Vec<VEC>;
     __shared__ double cs[256 * NW];
     for (int t = threadIdx.x; t < nv * NW; t += kThreads) cs[t] = C[t];
     __syncthreads();
-    const int64_t nvec = n / VEC, ldv = ld / VEC, ldyv = ldy / VEC;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec;
-         e += (int64_t)gridDim.x * kThreads) {
+    const int64_t nvec = n / VEC, ldv = ld / VEC, ldyv = ldy / VEC, cnt = span_count<VEC>(sp, nvec);
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt;
+         it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = span_elem<VEC>(sp, it);
+        if (e >= nvec) continue;
         typename O::T acc[NW];
 #pragma unroll
         for (int q = 0; q < NW; ++q) acc[q] = O::zero();
@@ -1741,27 +1745,29 @@ void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const dou
     }
 
 void launch_mdot_multi(int nv, const double *V, int64_t ld, const double *W, int64_t ldw, int nw,
-                       const double *wt, int64_t n, double *part, double *dout, hipStream_t s) {
+                       const double *wt, int64_t n, double *part, double *dout, hipStream_t s, Span sp) {
     if (nv <= 0 || nw <= 0) return;
     if (nw > kMultiMax || nv * nw > 256) throw std::runtime_error("launch_mdot_multi: too many products");
     const bool v2 = vec2_ok(n, ld, {V, W, wt}) && (ldw % 2 == 0);
     const dim3 g(kReduceBlocks), b(kThreads);
-    if (v2) DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_mdot_multi<2, NW, CH>), g, b, 0, s, nv, V, ld, W, ldw, wt, n, part))
-    else DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_mdot_multi<1, NW, CH>), g, b, 0, s, nv, V, ld, W, ldw, wt, n, part))
+    if (v2) DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_mdot_multi<2, NW, CH>), g, b, 0, s, nv, V, ld, W, ldw, wt, n, part,
+                                                sp))
+    else DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_mdot_multi<1, NW, CH>), g, b, 0, s, nv, V, ld, W, ldw, wt, n, part, sp))
     hipLaunchKernelGGL(k_mdot_final, dim3(nv * nw), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout);
 }
 
 void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, int nw, double *Y, int64_t ldy,
-                        int64_t n, int overwrite, hipStream_t s) {
+                        int64_t n, int overwrite, hipStream_t s, Span sp) {
     if (nw <= 0 || (nv <= 0 && !overwrite)) return;
     if (nw > kMultiMax || nv > 256) throw std::runtime_error("launch_maxpy_multi: too many vectors");
+    const int64_t cnt = sp.u ? sp.n * kSpanUnit : n;
     if (vec2_ok(n, ld, {V, Y}) && ldy % 2 == 0)
-        DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_maxpy_multi<2, NW>), flat_grid(n / 2), dim3(kThreads), 0, s, nv, V,
-                                            ld, C, Y, ldy, n, overwrite))
+        DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_maxpy_multi<2, NW>), flat_grid(cnt / 2), dim3(kThreads), 0, s, nv, V,
+                                            ld, C, Y, ldy, n, overwrite, sp))
     else
-        DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_maxpy_multi<1, NW>), flat_grid(n), dim3(kThreads), 0, s, nv, V, ld,
-                                            C, Y, ldy, n, overwrite))
+        DM_NW_SWITCH(nw, hipLaunchKernelGGL((k_maxpy_multi<1, NW>), flat_grid(cnt), dim3(kThreads), 0, s, nv, V, ld,
+                                            C, Y, ldy, n, overwrite, sp))
 }
 
 #undef DM_NW_SWITCH

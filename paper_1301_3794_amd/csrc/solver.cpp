@@ -1125,27 +1125,33 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     // launch_maxpy_multi); results through op->dres / hres, coefficients
     // through eg_C (a host array of its own per upload)
     std::vector<double> cbuf((size_t)256 * kMultiMax), mres((size_t)cap * kMultiMax);
+    // every basis, Ritz and work vector of the eigensolver is zero outside
+    // the listed units of the face vectors (solves, projections, A and K
+    // products and random starts all write zeros there)
+    const Span vsp = op->vspan();
     // mres[i*nw + q] = V_i . (W_q * wt), i < nv (chunks of basis columns whose
     // products fit the kMaxDots result buffer)
     auto multi_dots = [&](int nv, const double *W0, int nw, const double *wt) {
         const int rows = kMaxDots / nw;
         for (int i0 = 0; i0 < nv; i0 += rows) {
             const int cnt = std::min(rows, nv - i0);
-            launch_mdot_multi(cnt, V + (size_t)i0 * n, n, W0, n, nw, wt, n, op->part, op->dres, s);
+            launch_mdot_multi(cnt, V + (size_t)i0 * n, n, W0, n, nw, wt, n, op->part, op->dres, s, vsp);
             DM_HIP(hipMemcpyAsync(op->hres, op->dres, (size_t)cnt * nw * sizeof(double), hipMemcpyDeviceToHost, s));
             DM_HIP(hipStreamSynchronize(s));
             std::copy(op->hres, op->hres + (size_t)cnt * nw, mres.begin() + (size_t)i0 * nw);
         }
     };
-    // Y_q = sum_r coefficient(r, q) V_r for q < nq, in chunks of kMultiMax
-    auto combine = [&](int nv, int nq, double *Y0, auto coefficient) {
+    // Y_q = sum_r coefficient(r, q) V_r for q < nq, in chunks of kMultiMax;
+    // with the span (internal buffers, zero outside it) only its units are
+    // written, without it (a caller's buffer) every element
+    auto combine = [&](int nv, int nq, double *Y0, auto coefficient, Span csp) {
         for (int q0 = 0; q0 < nq; q0 += kMultiMax) {
             const int nw = std::min(kMultiMax, nq - q0);
             std::vector<double> c((size_t)nv * nw);
             for (int r = 0; r < nv; ++r)
                 for (int q = 0; q < nw; ++q) c[(size_t)r * nw + q] = coefficient(r, q0 + q);
             DM_HIP(hipMemcpyAsync(op->eg_C, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, s));
-            launch_maxpy_multi(nv, V, n, op->eg_C, nw, Y0 + (size_t)q0 * n, n, n, 1, s);
+            launch_maxpy_multi(nv, V, n, op->eg_C, nw, Y0 + (size_t)q0 * n, n, n, 1, s, csp);
             DM_HIP(hipStreamSynchronize(s));   // c goes out of scope
         }
     };
@@ -1156,7 +1162,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     int inner_its = 0, proj_its = 0, outer = 0, restarts = 0;
     dm_solve_info sinfo;
     auto A_normalize = [&](double *v) -> double {
-        const double nrm = std::sqrt(dot1(op, v, v, a, n, s));
+        const double nrm = std::sqrt(dot1(op, v, v, a, n, s, vsp));
         if (nrm > 0) launch_scale(n, 1.0 / nrm, v, s);
         return nrm;
     };
@@ -1166,12 +1172,12 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     auto orth = [&](const double *B, int cnt, double *v, double *coef) {
         if (cnt <= 0) return;
         for (int pass = 0; pass < 2; ++pass) {
-            dots(op, cnt, B, n, v, a, n, s);
+            dots(op, cnt, B, n, v, a, n, s, vsp);
             std::copy(op->hres, op->hres + cnt, hc.begin());
             if (coef)
                 for (int i = 0; i < cnt; ++i) coef[i] += hc[i];
             to_device_coef(op, hc.data(), cnt, s);
-            launch_maxpy(cnt, B, n, op->dcoef, v, n, 0, s);
+            launch_maxpy(cnt, B, n, op->dcoef, v, n, 0, s, nullptr, vsp);
         }
     };
     int pj;
@@ -1181,7 +1187,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     auto Gat = [&](int r, int c) -> double & { return GK[(size_t)r * cap + c]; };
     auto add_gk = [&](int q) {
         launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, V + (size_t)q * n, t2, s);
-        dots(op, q + 1, V, n, t2, wk, n, s);
+        dots(op, q + 1, V, n, t2, wk, n, s, vsp);
         for (int i = 0; i <= q; ++i) Gat(i, q) = Gat(q, i) = op->hres[i];
     };
     // start block: random vectors, projected together where the block path
@@ -1275,7 +1281,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
                 }
                 DM_HIP(hipMemcpyAsync(op->eg_C, cbuf.data(), (size_t)cur * b * sizeof(double), hipMemcpyHostToDevice,
                                       s));
-                launch_maxpy_multi(cur, V, n, op->eg_C, b, Vn, n, n, 0, s);
+                launch_maxpy_multi(cur, V, n, op->eg_C, b, Vn, n, n, 0, s, vsp);
                 DM_HIP(hipStreamSynchronize(s));   // cbuf is reused
             }
             // ... then within the block, column by column
@@ -1338,12 +1344,12 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
         nconv = 0;
         double maxres = 0.0;
         std::vector<double> yk(std::max(mm, nb));
-        combine(nb, k, RB, [&](int r, int i) { return Z[(size_t)r * nb + wanted[i]]; });
+        combine(nb, k, RB, [&](int r, int i) { return Z[(size_t)r * nb + wanted[i]]; }, vsp);
         for (int i = 0; i < k; ++i) {
             launch_apply<double>(L.g, L.coef64, 0.0, AK_K, nullptr, RB + (size_t)i * n, RK + (size_t)i * n, s);
             launch_apply_A(L.g, L.coef64, RB + (size_t)i * n, RA + (size_t)i * n, s);
-            launch_mdot(1, RB + (size_t)i * n, 0, RK + (size_t)i * n, wk, n, op->part, op->dres + 2 * i, s);
-            launch_mdot(1, RB + (size_t)i * n, 0, RB + (size_t)i * n, a, n, op->part, op->dres + 2 * i + 1, s);
+            launch_mdot(1, RB + (size_t)i * n, 0, RK + (size_t)i * n, wk, n, op->part, op->dres + 2 * i, s, vsp);
+            launch_mdot(1, RB + (size_t)i * n, 0, RB + (size_t)i * n, a, n, op->part, op->dres + 2 * i + 1, s, vsp);
         }
         DM_HIP(hipMemcpyAsync(op->hres, op->dres, (size_t)2 * k * sizeof(double), hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
@@ -1354,7 +1360,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
             lam_h[i] = bKb[i] / bAb[i];
             // K b - lr A b
             launch_axpy(n, -lam_h[i], RA + (size_t)i * n, RK + (size_t)i * n, s);
-            launch_mdot(1, RK + (size_t)i * n, 0, RK + (size_t)i * n, ainv, n, op->part, op->dres + i, s);
+            launch_mdot(1, RK + (size_t)i * n, 0, RK + (size_t)i * n, ainv, n, op->part, op->dres + i, s, vsp);
         }
         DM_HIP(hipMemcpyAsync(op->hres, op->dres, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
@@ -1378,7 +1384,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
                 lam[q] = lam_h[i];
                 if (res_out) res_out[q] = res_h[i];
             }
-            if (vecs) combine(nb, k, vecs, [&](int r, int q) { return Z[(size_t)r * nb + wanted[idx[q]]]; });
+            if (vecs) combine(nb, k, vecs, [&](int r, int q) { return Z[(size_t)r * nb + wanted[idx[q]]]; }, Span{});
             if (info) {
                 info->n_converged = nconv;
                 info->outer_iterations = outer;
@@ -1394,7 +1400,7 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
         if (!full) continue;
         // ---- thick restart: keep the keep_max leading Ritz vectors
         const int keep = keep_max;
-        combine(mm, keep, SCR, [&](int r, int i) { return Y[(size_t)r * mm + order[i]]; });
+        combine(mm, keep, SCR, [&](int r, int i) { return Y[(size_t)r * mm + order[i]]; }, vsp);
         std::vector<double> Bc((size_t)b * keep, 0.0);  // coupling of the last block
         for (int r = 0; r < b; ++r)
             for (int i = 0; i < keep; ++i) {
