@@ -243,8 +243,12 @@ typedef struct {
 } dm_solve_info;
 
 /* x = M^-1 f to ||f - M x|| <= rtol ||f||, starting from x = 0.  FP64 in
- * and out.  Returns DM_NOT_CONVERGED if maxit preconditioner applications
- * did not reach rtol (x holds the best iterate). */
+ * and out.  The system is that of the active faces, so f should vanish on
+ * inactive faces (M x does).  In the FGMRES modes the entries of f outside
+ * the 128-byte lines that hold an active face (or a PMC ghost image of one)
+ * are ignored, and x is zero there.  Returns
+ * DM_NOT_CONVERGED if maxit preconditioner applications did not reach rtol
+ * (x holds the best iterate). */
 int dm_solve(dm_op *op, int mode, const double *f_dev, double *x_dev,
              double rtol, int maxit, dm_solve_info *info, void *stream);
 
