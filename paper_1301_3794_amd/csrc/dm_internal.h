@@ -288,6 +288,10 @@ __host__ __device__ inline VPtr<const T> as_const(const VPtr<T> &x) {
 struct ClassList {
     const int32_t *idx = nullptr;
     int64_t n = 0;
+    // for the smoother's vacuum part: the grid rows (k * ny + j) holding a
+    // vacuum row of any component; the colour sweep visits only these
+    const int32_t *rows = nullptr;
+    int64_t nrows = 0;
 };
 
 // Units of kSpanUnit consecutive doubles (one 128-byte line) of a level-0

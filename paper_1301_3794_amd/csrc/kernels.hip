@@ -271,11 +271,12 @@ __device__ __forceinline__ void smooth_body_n(const Grid &g, const Coefs<T> &c, 
 // the long path as well).
 template <class T, int COMP, int NR>
 __device__ __forceinline__ void smooth_vac_n(const Grid &g, const Coefs<T> &c, T sigma, int colour,
-                                             const VPtr<const T> &f, const VPtr<T> &x, int64_t t) {
+                                             const VPtr<const T> &f, const VPtr<T> &x, int64_t t,
+                                             const int32_t *__restrict__ rows, int64_t nrows) {
     const int nxh = (g.nx + 1) >> 1;
-    if (t >= (int64_t)nxh * g.ny * g.nz) return;
+    if (t >= (rows ? nrows : (int64_t)g.ny * g.nz) * nxh) return;
     const int ih = (int)(t % nxh);
-    const int64_t r = t / nxh;
+    const int64_t r = rows ? (int64_t)rows[t / nxh] : t / nxh;
     const int j = (int)(r % g.ny), k = (int)(r / g.ny);
     const int i = 2 * ih + ((j + k + colour) & 1);
     if (i >= g.nx) return;
@@ -354,7 +355,7 @@ k_smooth_b(Grid g, Coefs<T> c, T sigma, int colour, VPtr<const T> f, VPtr<T> x) 
 template <class T, int COMP, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_smooth_split(Grid g, Coefs<T> c, T sigma, int colour, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
-               int wave_split, VPtr<const T> f, VPtr<T> x) {
+               int wave_split, const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f, VPtr<T> x) {
     const int64_t b = blockIdx.x;
     if (b < ncb) {
         const int64_t L = (b % kXcd) * (ncb / kXcd) + b / kXcd;
@@ -368,7 +369,7 @@ k_smooth_split(Grid g, Coefs<T> c, T sigma, int colour, const int32_t *__restric
     } else {
         const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
         const int64_t L = (bv % kXcd) * (nvb / kXcd) + bv / kXcd;
-        smooth_vac_n<T, COMP, NR>(g, c, sigma, colour, f, x, L * kThreads + threadIdx.x);
+        smooth_vac_n<T, COMP, NR>(g, c, sigma, colour, f, x, L * kThreads + threadIdx.x, rows, nrows);
     }
 }
 
@@ -1491,17 +1492,19 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
     if (cut.idx) {
         const int wave_split = nr > 1 && cut.n < kCutWaveSplit;
         const int64_t ncb = ceil_div(ceil_div(cut.n, wave_split ? 64 : kThreads), kXcd) * kXcd;
-        const int64_t nvb = ceil_div(ceil_div(n, kThreads), kXcd) * kXcd;
+        // the vacuum part sweeps the listed rows (every row without a list)
+        const int64_t nvac = cut.rows ? cut.nrows * ((g.nx + 1) >> 1) : n;
+        const int64_t nvb = ceil_div(ceil_div(nvac, kThreads), kXcd) * kXcd;
         const dim3 grid((unsigned)(ncb + nvb));
         if (comp == 0)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 0, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut.rows, cut.nrows, f, x))
         else if (comp == 1)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 1, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut.rows, cut.nrows, f, x))
         else
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 2, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut.rows, cut.nrows, f, x))
         return;
     }
     if (comp == 0)

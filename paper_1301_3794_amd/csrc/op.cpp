@@ -202,6 +202,19 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
                     if ((fl[p] & 7) & ~(fl[p] >> 3)) cutc.push_back((int32_t)p);
                 }
         L.ncutc = (int64_t)cutc.size();
+        std::vector<int32_t> vrows;
+        for (int k = 0; k < L.g.nz; ++k)
+            for (int j = 0; j < L.g.ny; ++j) {
+                bool any = false;
+                for (int i = 0; i < L.g.nx && !any; ++i) any = (fl[pidx(L.g, i, j, k)] >> 3) & 7;
+                if (any) vrows.push_back((int32_t)(k * L.g.ny + j));
+            }
+        L.nvrows = (int64_t)vrows.size();
+        if (!vrows.empty()) {
+            L.vrows = op->dalloc<int32_t>(vrows.size());
+            DM_HIP(hipMemcpyAsync(L.vrows, vrows.data(), vrows.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  op->stream));
+        }
         if (!cutc.empty()) {
             L.cutc = op->dalloc<int32_t>(cutc.size());
             DM_HIP(hipMemcpyAsync(L.cutc, cutc.data(), cutc.size() * sizeof(int32_t), hipMemcpyHostToDevice,

@@ -34,9 +34,12 @@ struct Level {
     int32_t *cutc = nullptr;
     int64_t ncutc = 0;
     ClassList cut_cells() const { return ClassList{cutc, ncutc}; }
+    // grid rows (k * ny + j) with a vacuum row of any component
+    int32_t *vrows = nullptr;
+    int64_t nvrows = 0;
     ClassList cut_list(int comp, int colour) const {
         const int q = 2 * comp + colour;
-        return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q]};
+        return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows};
     }
 };
 

@@ -184,3 +184,31 @@ def test_solve(case, mode):
     ref[oop.act] = sla.spsolve(oop.M_a.tocsc(), f[oop.act])
     assert rel_inf(lay.faces_from_padded(x.cpu().numpy(), n), ref) <= 1e-9
     assert info["rel_residual"] <= 1e-11
+
+
+@pytest.mark.parametrize("mode", ["fgmres64", "fgmres32"])
+def test_solve_reads_only_lines_with_active_faces(case, mode):
+    """The FGMRES reductions, updates and preconditioner casts visit only the
+    128-byte lines (16 doubles) of a face vector that hold an active face:
+    values of f in the other lines change nothing, and x stays zero there."""
+    dm, op, oop, n = case["dm"], case["op"], case["oop"], case["n"]
+    m = dm.SOLVE_FGMRES_MG64 if mode == "fgmres64" else dm.SOLVE_FGMRES_MG32
+    active = np.asarray(op.fractions(0))[:3].reshape(-1) != 0.0
+    nline = (active.size + 15) // 16
+    padded = np.zeros(nline * 16, dtype=bool)
+    padded[:active.size] = active
+    empty = np.flatnonzero(~padded.reshape(nline, 16).any(axis=1))
+    assert empty.size > 0
+    f = lay.faces_to_padded(full_random(oop, 16), n)
+    junk = f.copy()
+    for line in empty[:: max(1, empty.size // 40)]:
+        junk[line * 16:min(active.size, line * 16 + 16)] = 1e3
+    x1, x2 = op.face_tensor(), op.face_tensor()
+    i1 = op.solve(dev(f), x1, mode=m, rtol=1e-11, maxit=200)
+    i2 = op.solve(dev(junk), x2, mode=m, rtol=1e-11, maxit=200)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert i1["iterations"] == i2["iterations"]
+    a, b = x1.cpu().numpy(), x2.cpu().numpy()
+    assert np.array_equal(a, b)
+    outside = np.repeat(~padded.reshape(nline, 16).any(axis=1), 16)[:active.size]
+    assert np.all(b[outside] == 0.0)
