@@ -359,9 +359,11 @@ void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<con
 template <class T>
 void launch_s_apply_b(const Grid &g, const T *coef, double w, int resid, int nr, const VPtr<const T> &f,
                       const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s);
+// (rows: optional list of the grid rows, k * ny + j, holding an active cell;
+// the colour sweep then visits only those)
 template <class T>
 void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int nr, const VPtr<const T> &f,
-                       const VPtr<T> &x, hipStream_t s);
+                       const VPtr<T> &x, hipStream_t s, const int32_t *rows = nullptr, int64_t nrows = 0);
 template <class T>
 void launch_s_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
                          const VPtr<T> &fc, hipStream_t s);

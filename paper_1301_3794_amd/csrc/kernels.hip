@@ -632,13 +632,16 @@ __device__ __forceinline__ void s_apply_body(const Grid &g, const Coefs<T> &c, T
     put_cell<T>(g, y, i, j, k, p, c.vinv[p] != T(0) ? v : T(0));
 }
 
+// rows: optional list of the grid rows (k * ny + j) holding an active cell;
+// the colour sweep then visits only those
 template <class T>
 __device__ __forceinline__ void s_smooth_body(const Grid &g, const Coefs<T> &c, T w, int colour,
-                                              const T *__restrict__ f, T *__restrict__ x, int64_t t) {
+                                              const T *__restrict__ f, T *__restrict__ x, int64_t t,
+                                              const int32_t *__restrict__ rows = nullptr, int64_t nrows = 0) {
     const int nxh = (g.nx + 1) >> 1;
-    if (t >= (int64_t)nxh * g.ny * g.nz) return;
+    if (t >= (rows ? nrows : (int64_t)g.ny * g.nz) * nxh) return;
     const int ih = (int)(t % nxh);
-    const int64_t r = t / nxh;
+    const int64_t r = rows ? (int64_t)rows[t / nxh] : t / nxh;
     const int j = (int)(r % g.ny), k = (int)(r / g.ny);
     const int i = 2 * ih + ((j + k + colour) & 1);
     if (i >= g.nx) return;
@@ -740,10 +743,11 @@ k_s_apply_b(Grid g, Coefs<T> c, T w, int resid, VPtr<const T> f, VPtr<const T> x
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_smooth_b(Grid g, Coefs<T> c, T w, int colour, VPtr<const T> f, VPtr<T> x) {
+k_s_smooth_b(Grid g, Coefs<T> c, T w, int colour, const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f,
+             VPtr<T> x) {
     int q;
     const int64_t t = wave_item(q);
-    s_smooth_body<T>(g, c, w, colour, f.p[q], x.p[q], t);
+    s_smooth_body<T>(g, c, w, colour, f.p[q], x.p[q], t, rows, nrows);
 }
 
 template <class T, int NR>
@@ -1569,11 +1573,11 @@ void launch_s_apply_b(const Grid &g, const T *coef, double w, int resid, int nr,
 
 template <class T>
 void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int nr, const VPtr<const T> &f,
-                       const VPtr<T> &x, hipStream_t s) {
-    const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
+                       const VPtr<T> &x, hipStream_t s, const int32_t *rows, int64_t nrows) {
+    const int64_t n = (int64_t)((g.nx + 1) >> 1) * (rows ? nrows : (int64_t)g.ny * g.nz);
     const Coefs<T> c = coefs_of(coef, g.P);
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_smooth_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, (T)w,
-                                        colour, f, x))
+                                        colour, rows, nrows, f, x))
 }
 
 template <class T>
@@ -1598,7 +1602,7 @@ void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, int
     template void launch_s_apply_b<T>(const Grid &, const T *, double, int, int, const VPtr<const T> &,           \
                                       const VPtr<const T> &, const VPtr<T> &, hipStream_t);                       \
     template void launch_s_smooth_b<T>(const Grid &, const T *, double, int, int, const VPtr<const T> &,          \
-                                       const VPtr<T> &, hipStream_t);                                             \
+                                       const VPtr<T> &, hipStream_t, const int32_t *, int64_t);                   \
     template void launch_s_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,       \
                                          const VPtr<T> &, hipStream_t);                                           \
     template void launch_s_prolong_add_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,    \

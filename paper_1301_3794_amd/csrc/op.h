@@ -37,6 +37,9 @@ struct Level {
     // grid rows (k * ny + j) with a vacuum row of any component
     int32_t *vrows = nullptr;
     int64_t nvrows = 0;
+    // grid rows (k * ny + j) with an active cell (the scalar problem's unknowns)
+    int32_t *arows = nullptr;
+    int64_t narows = 0;
     ClassList cut_list(int comp, int colour) const {
         const int q = 2 * comp + colour;
         return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows};

@@ -484,7 +484,8 @@ void svcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
         return;
     }
     for (int it = 0; it < op->opt.nu_pre; ++it)
-        for (int col = 0; col < 2; ++col) launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s);
+        for (int col = 0; col < 2; ++col)
+            launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s, L.arows, L.narows);
     const VPtr<T> R = slots(S::r(L), P, nr);
     launch_s_apply_b<T>(g, c, L.sweight, 1, nr, as_const(F), as_const(X), R, s);
     Level &C = op->lv[l + 1];
@@ -492,7 +493,8 @@ void svcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     svcycle_b<T>(op, l + 1, nr, s);
     launch_s_prolong_add_b<T>(g, C.g, c, nr, as_const(slots(S::x(C), C.g.P, nr)), X, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
-        for (int col = 1; col >= 0; --col) launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s);
+        for (int col = 1; col >= 0; --col)
+            launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s, L.arows, L.narows);
 }
 
 // ---------------------------------------------------------------------------
