@@ -86,9 +86,9 @@ VCYCLE_BYTES_PER_CELL = 359.0 * 8.0 / 7.0
 # HBM bytes per FP32 block sweep (BLOCK = 3 vectors) on the 128^3 sphere's
 # finest level, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of
 # `bench.py --only traffic`, each counter scaled by its reading for a 256 MiB
-# copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000): reads 463,948 KiB + writes
-# 69,009 KiB per sweep of the six k_smooth_split class kernels.
-BLOCK_SWEEP_TRAFFIC_BYTES = 545748324
+# copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000): reads 471,511 KiB + writes
+# 69,327 KiB per sweep of the six k_smooth_split class kernels.
+BLOCK_SWEEP_TRAFFIC_BYTES = 553818144
 
 
 def log(msg):
