@@ -1224,6 +1224,9 @@ k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double
             for (int q = 0; q < MAXV; ++q)
                 if (q < nv) s = O::fma(-cs[q], O::ld(V + (int64_t)q * ldv * VEC, e), s);
             O::st(w, e, s);
+            // keep the compiler from holding the first loads in registers
+            // for the second use (that costs 200+ VGPRs, 2 waves per SIMD)
+            asm volatile("" ::: "memory");
 #pragma unroll
             for (int q = 0; q < MAXV; ++q)
                 if (q < nv) acc[q] += O::dot(O::ld(V + (int64_t)q * ldv * VEC, e), s);
