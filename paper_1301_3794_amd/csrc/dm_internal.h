@@ -172,47 +172,52 @@ constexpr uint8_t kFaceActive = 1, kFaceVacuum = 8;
 // Shared by the GPU kernels and by the host assembly of the coarsest matrix.
 // ---------------------------------------------------------------------------
 
+// The vectors may be stored in a narrower type TX than the arithmetic type T
+// (FP32 preconditioned vectors in an FP64 product): every loaded value is
+// converted to T before any arithmetic, so the result equals that of the
+// widened vector.
+
 // flux divergence of cell q (times vinv, no 1/h)
-template <class T>
-__host__ __device__ inline T cell_div(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+template <class T, class TX = T>
+__host__ __device__ inline T cell_div(const Coefs<T> &c, const TX *X, const TX *Y, const TX *Z,
                                       int64_t q, int64_t dy, int64_t dz) {
-    return c.vinv[q] * (c.ax[q + 1] * X[q + 1] - c.ax[q] * X[q] + c.ay[q + dy] * Y[q + dy] -
-                        c.ay[q] * Y[q] + c.az[q + dz] * Z[q + dz] - c.az[q] * Z[q]);
+    return c.vinv[q] * (c.ax[q + 1] * T(X[q + 1]) - c.ax[q] * T(X[q]) + c.ay[q + dy] * T(Y[q + dy]) -
+                        c.ay[q] * T(Y[q]) + c.az[q + dz] * T(Z[q + dz]) - c.az[q] * T(Z[q]));
 }
 
-template <class T, bool GD>
-__host__ __device__ inline T row_x(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+template <class T, bool GD, class TX = T>
+__host__ __device__ inline T row_x(const Coefs<T> &c, const TX *X, const TX *Y, const TX *Z,
                                    int64_t p, int64_t dy, int64_t dz) {
-    const T wy0 = c.ly[p] * (X[p] - X[p - dz] - Z[p] + Z[p - 1]);
-    const T wyz = c.ly[p + dz] * (X[p + dz] - X[p] - Z[p + dz] + Z[p + dz - 1]);
-    const T wz0 = c.lz[p] * (Y[p] - Y[p - 1] - X[p] + X[p - dy]);
-    const T wzy = c.lz[p + dy] * (Y[p + dy] - Y[p + dy - 1] - X[p + dy] + X[p]);
+    const T wy0 = c.ly[p] * (T(X[p]) - T(X[p - dz]) - T(Z[p]) + T(Z[p - 1]));
+    const T wyz = c.ly[p + dz] * (T(X[p + dz]) - T(X[p]) - T(Z[p + dz]) + T(Z[p + dz - 1]));
+    const T wz0 = c.lz[p] * (T(Y[p]) - T(Y[p - 1]) - T(X[p]) + T(X[p - dy]));
+    const T wzy = c.lz[p + dy] * (T(Y[p + dy]) - T(Y[p + dy - 1]) - T(X[p + dy]) + T(X[p]));
     T s = wy0 - wyz + wzy - wz0;
-    if (GD) s += c.ax[p] * (cell_div(c, X, Y, Z, p - 1, dy, dz) - cell_div(c, X, Y, Z, p, dy, dz));
+    if (GD) s += c.ax[p] * (cell_div<T, TX>(c, X, Y, Z, p - 1, dy, dz) - cell_div<T, TX>(c, X, Y, Z, p, dy, dz));
     return s;
 }
 
-template <class T, bool GD>
-__host__ __device__ inline T row_y(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+template <class T, bool GD, class TX = T>
+__host__ __device__ inline T row_y(const Coefs<T> &c, const TX *X, const TX *Y, const TX *Z,
                                    int64_t p, int64_t dy, int64_t dz) {
-    const T wx0 = c.lx[p] * (Z[p] - Z[p - dy] - Y[p] + Y[p - dz]);
-    const T wxz = c.lx[p + dz] * (Z[p + dz] - Z[p + dz - dy] - Y[p + dz] + Y[p]);
-    const T wz0 = c.lz[p] * (Y[p] - Y[p - 1] - X[p] + X[p - dy]);
-    const T wzx = c.lz[p + 1] * (Y[p + 1] - Y[p] - X[p + 1] + X[p + 1 - dy]);
+    const T wx0 = c.lx[p] * (T(Z[p]) - T(Z[p - dy]) - T(Y[p]) + T(Y[p - dz]));
+    const T wxz = c.lx[p + dz] * (T(Z[p + dz]) - T(Z[p + dz - dy]) - T(Y[p + dz]) + T(Y[p]));
+    const T wz0 = c.lz[p] * (T(Y[p]) - T(Y[p - 1]) - T(X[p]) + T(X[p - dy]));
+    const T wzx = c.lz[p + 1] * (T(Y[p + 1]) - T(Y[p]) - T(X[p + 1]) + T(X[p + 1 - dy]));
     T s = -wx0 + wxz + wz0 - wzx;
-    if (GD) s += c.ay[p] * (cell_div(c, X, Y, Z, p - dy, dy, dz) - cell_div(c, X, Y, Z, p, dy, dz));
+    if (GD) s += c.ay[p] * (cell_div<T, TX>(c, X, Y, Z, p - dy, dy, dz) - cell_div<T, TX>(c, X, Y, Z, p, dy, dz));
     return s;
 }
 
-template <class T, bool GD>
-__host__ __device__ inline T row_z(const Coefs<T> &c, const T *X, const T *Y, const T *Z,
+template <class T, bool GD, class TX = T>
+__host__ __device__ inline T row_z(const Coefs<T> &c, const TX *X, const TX *Y, const TX *Z,
                                    int64_t p, int64_t dy, int64_t dz) {
-    const T wx0 = c.lx[p] * (Z[p] - Z[p - dy] - Y[p] + Y[p - dz]);
-    const T wxy = c.lx[p + dy] * (Z[p + dy] - Z[p] - Y[p + dy] + Y[p + dy - dz]);
-    const T wy0 = c.ly[p] * (X[p] - X[p - dz] - Z[p] + Z[p - 1]);
-    const T wyx = c.ly[p + 1] * (X[p + 1] - X[p + 1 - dz] - Z[p + 1] + Z[p]);
+    const T wx0 = c.lx[p] * (T(Z[p]) - T(Z[p - dy]) - T(Y[p]) + T(Y[p - dz]));
+    const T wxy = c.lx[p + dy] * (T(Z[p + dy]) - T(Z[p]) - T(Y[p + dy]) + T(Y[p + dy - dz]));
+    const T wy0 = c.ly[p] * (T(X[p]) - T(X[p - dz]) - T(Z[p]) + T(Z[p - 1]));
+    const T wyx = c.ly[p + 1] * (T(X[p + 1]) - T(X[p + 1 - dz]) - T(Z[p + 1]) + T(Z[p]));
     T s = wx0 - wxy - wy0 + wyx;
-    if (GD) s += c.az[p] * (cell_div(c, X, Y, Z, p - dz, dy, dz) - cell_div(c, X, Y, Z, p, dy, dz));
+    if (GD) s += c.az[p] * (cell_div<T, TX>(c, X, Y, Z, p - dz, dy, dz) - cell_div<T, TX>(c, X, Y, Z, p, dy, dz));
     return s;
 }
 
@@ -394,6 +399,11 @@ void launch_s_prolong_add(const Grid &gf, const Grid &gc, const double *coef_f,
 
 // BLAS-1 style FP64 helpers on flat arrays
 void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
+// y = M x (FP64 arithmetic and output) for FP32-stored x: each value of x is
+// widened before use, so y equals the product with the widened x; needs the
+// cut-cell list of the level (the split form)
+void launch_apply_m_f32in(const Grid &g, const double *coef, double sigma, int nr, const VPtr<const float> &x,
+                          const VPtr<double> &y, hipStream_t s, ClassList cut);
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 void launch_scale(int64_t n, double a, double *x, hipStream_t s);
 template <class T>
@@ -417,6 +427,9 @@ void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, in
 // with cscale (device, nv values) the coefficients are c[i] * cscale[i]
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
                   int overwrite, hipStream_t s, const double *cscale = nullptr, Span sp = {});
+// y -= sum_i c[i] V_i for FP32 columns V_i (c on device; FP64 arithmetic)
+void launch_maxpy_f32(int nv, const float *V, int64_t ld, const double *c, double *y, int64_t n, hipStream_t s,
+                      Span sp = {});
 // fused Gram--Schmidt step: w -= sum c_i V_i (c_i times cscale_i if given),
 // then dout[0..nv-1] = V_i . w and dout[nv] = |w|^2 (device results); one
 // pass over the basis for nv <= 32, two above

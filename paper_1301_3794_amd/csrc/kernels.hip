@@ -73,42 +73,46 @@ __device__ inline T inv_h2_of(const Grid &g) {
 // y = M x, y = K x, or r = f - M x
 // ---------------------------------------------------------------------------
 // 7-point vacuum row of component array C at p (no 1/h^2)
-template <class T>
-__device__ inline T vac_row(const T *C, int64_t p, int64_t dy, int64_t dz) {
-    return T(6) * C[p] - (C[p - 1] + C[p + 1]) - (C[p - dy] + C[p + dy]) - (C[p - dz] + C[p + dz]);
+template <class T, class TX = T>
+__device__ inline T vac_row(const TX *C, int64_t p, int64_t dy, int64_t dz) {
+    return T(6) * T(C[p]) - (T(C[p - 1]) + T(C[p + 1])) - (T(C[p - dy]) + T(C[p + dy])) -
+           (T(C[p - dz]) + T(C[p + dz]));
 }
 
 // NR right-hand sides at once (block solves): the coefficients of a row are
 // loaded once and serve every vector; all rows are formed before any store.
-template <class T, int KIND>
+template <class T, int KIND, class TX = T>
 __device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T sigma, const T *__restrict__ f,
-                                           const T *__restrict__ x, T *__restrict__ y, int64_t item) {
+                                           const TX *__restrict__ x, T *__restrict__ y, int64_t item) {
     int i, j, k;
     if (!cell_of(g, item, i, j, k)) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
     const int64_t p = pidx(g, i, j, k);
-    const T *X = x, *Y = x + P, *Z = x + 2 * P;
+    const TX *X = x, *Y = x + P, *Z = x + 2 * P;
     const T ih2 = inv_h2_of<T>(g);
     const uint8_t fl = c.flags[p];
     T yx = T(0), yy = T(0), yz = T(0);
     if (KIND == AK_K) {
-        if (fl & (kFaceActive << 0)) yx = ih2 * row_x<T, false>(c, X, Y, Z, p, dy, dz);
-        if (fl & (kFaceActive << 1)) yy = ih2 * row_y<T, false>(c, X, Y, Z, p, dy, dz);
-        if (fl & (kFaceActive << 2)) yz = ih2 * row_z<T, false>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 0)) yx = ih2 * row_x<T, false, TX>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 1)) yy = ih2 * row_y<T, false, TX>(c, X, Y, Z, p, dy, dz);
+        if (fl & (kFaceActive << 2)) yz = ih2 * row_z<T, false, TX>(c, X, Y, Z, p, dy, dz);
     } else {
         if (fl & (kFaceActive << 0)) {
-            yx = (fl & (kFaceVacuum << 0)) ? ih2 * vac_row(X, p, dy, dz) - sigma * X[p]
-                                           : ih2 * row_x<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * X[p];
+            yx = (fl & (kFaceVacuum << 0))
+                     ? ih2 * vac_row<T, TX>(X, p, dy, dz) - sigma * T(X[p])
+                     : ih2 * row_x<T, true, TX>(c, X, Y, Z, p, dy, dz) - sigma * c.ax[p] * T(X[p]);
             if (KIND == AK_RESID) yx = f[p] - yx;
         }
         if (fl & (kFaceActive << 1)) {
-            yy = (fl & (kFaceVacuum << 1)) ? ih2 * vac_row(Y, p, dy, dz) - sigma * Y[p]
-                                           : ih2 * row_y<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * Y[p];
+            yy = (fl & (kFaceVacuum << 1))
+                     ? ih2 * vac_row<T, TX>(Y, p, dy, dz) - sigma * T(Y[p])
+                     : ih2 * row_y<T, true, TX>(c, X, Y, Z, p, dy, dz) - sigma * c.ay[p] * T(Y[p]);
             if (KIND == AK_RESID) yy = f[P + p] - yy;
         }
         if (fl & (kFaceActive << 2)) {
-            yz = (fl & (kFaceVacuum << 2)) ? ih2 * vac_row(Z, p, dy, dz) - sigma * Z[p]
-                                           : ih2 * row_z<T, true>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * Z[p];
+            yz = (fl & (kFaceVacuum << 2))
+                     ? ih2 * vac_row<T, TX>(Z, p, dy, dz) - sigma * T(Z[p])
+                     : ih2 * row_z<T, true, TX>(c, X, Y, Z, p, dy, dz) - sigma * c.az[p] * T(Z[p]);
             if (KIND == AK_RESID) yz = f[2 * P + p] - yz;
         }
     }
@@ -121,9 +125,9 @@ __device__ __forceinline__ void apply_body(const Grid &g, const Coefs<T> &c, T s
 // vacuum rows (the other cells are listed and run the full body): the same
 // values, written the same way, zeros on the inactive components included.
 // (K alone has no vacuum shortcut: its rows keep the cross terms.)
-template <class T, int KIND>
+template <class T, int KIND, class TX = T>
 __device__ __forceinline__ void apply_vac_body(const Grid &g, T sigma, uint8_t fl, const T *__restrict__ f,
-                                               const T *__restrict__ x, T *__restrict__ y, int i, int j, int k,
+                                               const TX *__restrict__ x, T *__restrict__ y, int i, int j, int k,
                                                int64_t p) {
     static_assert(KIND == AK_M || KIND == AK_RESID, "vacuum rows of M only");
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
@@ -131,10 +135,10 @@ __device__ __forceinline__ void apply_vac_body(const Grid &g, T sigma, uint8_t f
     T v[3];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
-        const T *C = x + comp * P;
+        const TX *C = x + comp * P;
         v[comp] = T(0);
         if (fl & (kFaceActive << comp)) {
-            v[comp] = ih2 * vac_row(C, p, dy, dz) - sigma * C[p];
+            v[comp] = ih2 * vac_row<T, TX>(C, p, dy, dz) - sigma * T(C[p]);
             if (KIND == AK_RESID) v[comp] = f[comp * P + p] - v[comp];
         }
     }
@@ -174,10 +178,10 @@ k_apply_b(Grid g, Coefs<T> c, T sigma, VPtr<const T> f, VPtr<const T> x, VPtr<T>
 // ncb workgroups (a multiple of 8) take the cut-cell list (full body), the
 // rest all cells, skipping listed ones (vacuum rows only); wave q of a
 // workgroup takes vector q of 64 entries in either part.
-template <class T, int KIND, int NR>
+template <class T, int KIND, int NR, class TX = T>
 __global__ void __launch_bounds__(kThreads)
 k_apply_split(Grid g, Coefs<T> c, T sigma, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
-              VPtr<const T> f, VPtr<const T> x, VPtr<T> y) {
+              VPtr<const T> f, VPtr<const TX> x, VPtr<T> y) {
     const int64_t b = blockIdx.x;
     const int q = threadIdx.x >> 6;
     if (b < ncb) {
@@ -186,7 +190,7 @@ k_apply_split(Grid g, Coefs<T> c, T sigma, const int32_t *__restrict__ cut, int6
         const int64_t p = cut[e], dy = g.sy, dz = g.sz;
         const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
         const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
-        apply_body<T, KIND>(g, c, sigma, f.p[q], x.p[q], y.p[q], ((int64_t)k * g.ny + j) * g.nx + i);
+        apply_body<T, KIND, TX>(g, c, sigma, f.p[q], x.p[q], y.p[q], ((int64_t)k * g.ny + j) * g.nx + i);
     } else {
         const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
         const int64_t t = ((bv % kXcd) * (nvb / kXcd) + bv / kXcd) * 64 + (threadIdx.x & 63);
@@ -195,7 +199,7 @@ k_apply_split(Grid g, Coefs<T> c, T sigma, const int32_t *__restrict__ cut, int6
         const int64_t p = pidx(g, i, j, k);
         const uint8_t fl = c.flags[p];
         if (has_cut_row(fl)) return;
-        apply_vac_body<T, KIND>(g, sigma, fl, f.p[q], x.p[q], y.p[q], i, j, k, p);
+        apply_vac_body<T, KIND, TX>(g, sigma, fl, f.p[q], x.p[q], y.p[q], i, j, k, p);
     }
 }
 
@@ -1192,6 +1196,34 @@ k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restri
     }
 }
 
+// y -= sum_i c_i V_i for FP32 columns V_i, in FP64 (each value widened
+// before use: the same result as with the widened columns), over the
+// listed units of the span
+__global__ void __launch_bounds__(kThreads)
+k_maxpy_f32(int nv, const float *__restrict__ V, int64_t ld, const double *__restrict__ c, double *y, int64_t n,
+            Span sp) {
+    __shared__ double cs[256];
+    for (int q = threadIdx.x; q < nv; q += kThreads) cs[q] = c[q];
+    __syncthreads();
+    const int64_t nvec = n / 2, cnt = span_count<2>(sp, nvec);
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt; it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = span_elem<2>(sp, it);
+        if (e >= nvec) continue;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int q = 0; q < nv; ++q) {
+            const float2 v = reinterpret_cast<const float2 *>(V + (int64_t)q * ld)[e];
+            acc = Vec<2>::fma(cs[q], make_double2((double)v.x, (double)v.y), acc);
+        }
+        double2 *yy = reinterpret_cast<double2 *>(y);
+        yy[e] = Vec<2>::fma(-1.0, acc, yy[e]);
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int q = 0; q < nv; ++q) acc += cs[q] * (double)V[(int64_t)q * ld + n - 1];
+        y[n - 1] -= acc;
+    }
+}
+
 // Fused Gram--Schmidt step for nv <= MAXV basis vectors:
 //   w' = w - sum_i c_i V_i      (written back to w)
 //   part rows 0..nv-1: V_i . w', row nv: |w'|^2
@@ -1492,6 +1524,20 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
                                             c, sigma, f, x, y))
     else
         throw std::runtime_error("block apply: M or residual only");
+}
+
+void launch_apply_m_f32in(const Grid &g, const double *coef, double sigma, int nr, const VPtr<const float> &x,
+                         const VPtr<double> &y, hipStream_t s, ClassList cut) {
+    // the split form; without cut cells (no list) every cell takes the vacuum part
+    if (!cut.idx && cut.n != 0) throw std::runtime_error("apply with FP32 input: cut-cell list missing");
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const Coefs<double> c = coefs_of(coef, g.P);
+    const int64_t ncb = cut.idx ? ceil_div(ceil_div(cut.n, 64), kXcd) * kXcd : 0;
+    const int64_t nvb = ceil_div(ceil_div(n, 64), kXcd) * kXcd;
+    const dim3 grid((unsigned)(ncb + nvb));
+    const VPtr<const double> f{};
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<double, AK_M, NR, float>), grid, dim3(64 * NR), 0, s, g, c,
+                                        sigma, cut.idx, cut.n, ncb, f, x, y))
 }
 
 template <class T>
@@ -1798,6 +1844,16 @@ void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *
                            (const double *)nullptr, 1.0, y, n, overwrite, sp);
 }
 
+void launch_maxpy_f32(int nv, const float *V, int64_t ld, const double *c, double *y, int64_t n, hipStream_t s,
+                      Span sp) {
+    if (nv <= 0) return;
+    if (nv > 256) throw std::runtime_error("launch_maxpy_f32: more than 256 vectors");
+    if ((ld & 1) || ((uintptr_t)V & 7) || ((uintptr_t)y & 15))
+        throw std::runtime_error("launch_maxpy_f32: columns must be 8-byte and y 16-byte aligned, ld even");
+    const int64_t cnt = sp.u ? sp.n * kSpanUnit : n;
+    hipLaunchKernelGGL(k_maxpy_f32, flat_grid(cnt / 2), dim3(kThreads), 0, s, nv, V, ld, c, y, n, sp);
+}
+
 // Workgroups of a grid-stride reduction kernel: as many as are resident at
 // once (its occupancy times the CUs), at most kReduceBlocks.  Every
 // workgroup carries the same share of the work, so a grid beyond what is
@@ -1950,6 +2006,7 @@ template void launch_prolong_add<float>(const Grid &, const Grid &, const float 
                                         float *, hipStream_t);
 template void launch_cast<double, float>(const double *, float *, int64_t, hipStream_t, Span);
 template void launch_cast<float, double>(const float *, double *, int64_t, hipStream_t, Span);
+template void launch_cast<float, float>(const float *, float *, int64_t, hipStream_t, Span);
 template void launch_coarse_solve<double>(int, const double *, const int64_t *, const double *,
                                           double *, hipStream_t);
 template void launch_coarse_solve<float>(int, const double *, const int64_t *, const float *,

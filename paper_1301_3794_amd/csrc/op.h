@@ -121,6 +121,7 @@ struct dm_op {
     // results / coefficients (kMaxDots each) and pinned host results
     int bk_m = 0;
     double *bk_V = nullptr, *bk_Z = nullptr;
+    float *bk_Z32 = nullptr;   // FP32 preconditioned columns (plain FP32-multigrid mode)
     double *bk_dres = nullptr, *bk_dcoef = nullptr, *bk_hres = nullptr;
     double *bk_dres2 = nullptr, *bk_hres2 = nullptr, *bk_sc2 = nullptr;   // as dres2, hres2, sc2d
     hipGraphExec_t g_vb32[dm::kMaxRhs + 1] = {}, g_vb64[dm::kMaxRhs + 1] = {};

@@ -558,7 +558,6 @@ void ensure_block(dm_op *op, int prec) {
         const int m = op->opt.fgmres_restart;
         op->bk_m = m;
         op->bk_V = op->dalloc<double>((size_t)(m + 1) * kMaxRhs * n);
-        op->bk_Z = op->dalloc<double>((size_t)m * kMaxRhs * n);
     }
     ensure_block_results(op);
     for (Level &L : op->lv) {
@@ -853,6 +852,19 @@ void precondition_block(dm_op *op, int mode, int nr, const double *const *v, dou
     }
 }
 
+// The plain FP32-multigrid preconditioner with FP32 answers: the V-cycle's
+// output is FP32 already, so the Z columns keep it as it is (half the bytes
+// of the widened copy).  The products M z and the update of x read them
+// widened to FP64, so every value equals that of the FP64 columns.
+void precondition_block_f32(dm_op *op, int nr, const double *const *v, float *const *z, hipStream_t s) {
+    const int64_t n = op->n0();
+    ensure_block(op, 32);
+    const Span sp = op->vspan();
+    for (int q = 0; q < nr; ++q) launch_cast<double, float>(v[q], op->lv[0].bf32 + q * n, n, s, sp);
+    vcycle_block_graphed(op, 32, nr, s);
+    for (int q = 0; q < nr; ++q) launch_cast<float, float>(op->lv[0].bx32 + q * n, z[q], n, s, sp);
+}
+
 struct BlockRhs {
     const double *f = nullptr;
     double *x = nullptr;
@@ -871,7 +883,13 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
     const int64_t ld = (int64_t)nb * n;   // stride between the columns of one system
     const Span sp = op->vspan();
     auto Vc = [&](int r, int j) { return op->bk_V + (int64_t)j * ld + (int64_t)r * n; };
+    // FP32 Z columns in the plain FP32-multigrid mode (even lengths: pairs of
+    // floats per load), FP64 ones otherwise
+    const bool z32 = mode == DM_SOLVE_FGMRES_MG32 && n % 2 == 0;
+    if (z32 && !op->bk_Z32) op->bk_Z32 = op->dalloc<float>((size_t)m * kMaxRhs * n);
+    if (!z32 && !op->bk_Z) op->bk_Z = op->dalloc<double>((size_t)m * kMaxRhs * n);
     auto Zc = [&](int r, int j) { return op->bk_Z + (int64_t)j * ld + (int64_t)r * n; };
+    auto Zc32 = [&](int r, int j) { return op->bk_Z32 + (int64_t)j * ld + (int64_t)r * n; };
     auto dres = [&](int r) { return op->bk_dres + (int64_t)r * kMaxDots; };
     auto dcoef = [&](int r) { return op->bk_dcoef + (int64_t)r * kMaxDots; };
     auto hres = [&](int r) { return op->bk_hres + (int64_t)r * kMaxDots; };
@@ -965,16 +983,29 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         const int na = (int)act.size();
         // z_j = B v_j and w = M z_j for every open system
         VPtr<const double> zc{};
+        VPtr<const float> zc32{};
         VPtr<double> wv{};
+        float *zout32[kMaxRhs];
         for (int q = 0; q < na; ++q) {
             const int r = act[q];
             vin[q] = Vc(r, st[r].j);
-            zout[q] = Zc(r, st[r].j);
-            zc.p[q] = zout[q];
+            if (z32) {
+                zout32[q] = Zc32(r, st[r].j);
+                zc32.p[q] = zout32[q];
+            } else {
+                zout[q] = Zc(r, st[r].j);
+                zc.p[q] = zout[q];
+            }
             wv.p[q] = Vc(r, st[r].j + 1);          // w = M Z_j in the next column's slot
         }
-        precondition_block(op, mode, na, vin, zout, s);
-        launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s, L.cut_cells());
+        if (z32) {
+            precondition_block_f32(op, na, vin, zout32, s);
+            launch_apply_m_f32in(L.g, L.coef64, op->sigma, na, zc32, wv, s, L.cut_cells());
+        } else {
+            precondition_block(op, mode, na, vin, zout, s);
+            launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s,
+                                   L.cut_cells());
+        }
         // Gram--Schmidt as in fgmres(): (1) d = U^T w, (2) w -= U (sc^2 d)
         // fused with d2 = U^T w and |w|^2, every open system, one sync
         for (int r : act) {
@@ -1044,7 +1075,8 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             }
             for (int i = 0; i < j; ++i) R.cx[i] = -R.y[i] * R.sc[i];
             DM_HIP(hipMemcpyAsync(dcoef(r), R.cx.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-            launch_maxpy(j, Zc(r, 0), ld, dcoef(r), R.x, n, 0, s, nullptr, sp);
+            if (z32) launch_maxpy_f32(j, Zc32(r, 0), ld, dcoef(r), R.x, n, s, sp);
+            else launch_maxpy(j, Zc(r, 0), ld, dcoef(r), R.x, n, 0, s, nullptr, sp);
             ++R.restarts;
             R.open = false;
         }
