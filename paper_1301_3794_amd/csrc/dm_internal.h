@@ -321,9 +321,10 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
 template <class T>
 void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour, int nr, const VPtr<const T> &f,
                      const VPtr<T> &x, hipStream_t s, ClassList cut = {});
+// xz (optional, one coarse iterate per vector): set to zero in the same pass
 template <class T>
 void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                       const VPtr<T> &fc, hipStream_t s);
+                       const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz = {});
 template <class T>
 void launch_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, int nr,
                           const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s);
@@ -369,9 +370,10 @@ void launch_s_apply_b(const Grid &g, const T *coef, double w, int resid, int nr,
 template <class T>
 void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int nr, const VPtr<const T> &f,
                        const VPtr<T> &x, hipStream_t s, const int32_t *rows = nullptr, int64_t nrows = 0);
+// (xz: optional coarse iterates, set to zero in the same pass)
 template <class T>
 void launch_s_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                         const VPtr<T> &fc, hipStream_t s);
+                         const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz = {});
 template <class T>
 void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, int nr, const VPtr<const T> &xc,
                             const VPtr<T> &x, hipStream_t s);

@@ -381,8 +381,12 @@ k_smooth_split(Grid g, Coefs<T> c, T sigma, int colour, const int32_t *__restric
 // Staggered transfers.  P: linear along the normal, constant across; R = P^T/8.
 // ---------------------------------------------------------------------------
 template <class T>
+// xz (optional): the coarse iterate, set to zero on the cell's faces (and
+// their PMC ghost images) in the same pass, as the coarse V-cycle starts
+// from zero
 __device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
-                                              const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
+                                              const T *__restrict__ r, T *__restrict__ fc, int64_t item,
+                                              T *__restrict__ xz = nullptr) {
     int I, J, K;
     if (!cell_of(gc, item, I, J, K)) return;
     const int64_t Pf = gf.P, Pc = gc.P, fy = gf.sy, fz = gf.sz;
@@ -415,6 +419,11 @@ __device__ __forceinline__ void restrict_body(const Grid &gf, const Grid &gc, co
     put_face<T>(gc, fc, 0, I, J, K, pc, ax != T(0) ? e * sx : T(0));
     put_face<T>(gc, fc + Pc, 1, I, J, K, pc, ay != T(0) ? e * sy : T(0));
     put_face<T>(gc, fc + 2 * Pc, 2, I, J, K, pc, az != T(0) ? e * sz : T(0));
+    if (xz) {
+        put_face<T>(gc, xz, 0, I, J, K, pc, T(0));
+        put_face<T>(gc, xz + Pc, 1, I, J, K, pc, T(0));
+        put_face<T>(gc, xz + 2 * Pc, 2, I, J, K, pc, T(0));
+    }
 }
 
 template <class T>
@@ -425,10 +434,10 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc) {
+k_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc, VPtr<T> xz) {
     int q;
     const int64_t t = wave_item(q);
-    restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t);
+    restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t, xz.p[q]);
 }
 
 // fine value between coarse faces c0, c1: (a0 x0 + a1 x1) / (a0 + a1)
@@ -663,7 +672,8 @@ __device__ __forceinline__ void s_smooth_body(const Grid &g, const Coefs<T> &c, 
 
 template <class T>
 __device__ __forceinline__ void s_restrict_body(const Grid &gf, const Grid &gc, const Coefs<T> &cc,
-                                                const T *__restrict__ r, T *__restrict__ fc, int64_t item) {
+                                                const T *__restrict__ r, T *__restrict__ fc, int64_t item,
+                                                T *__restrict__ xz = nullptr) {
     int I, J, K;
     if (!cell_of(gc, item, I, J, K)) return;
     const int64_t pc = pidx(gc, I, J, K), q = pidx(gf, 2 * I, 2 * J, 2 * K);
@@ -674,6 +684,7 @@ __device__ __forceinline__ void s_restrict_body(const Grid &gf, const Grid &gc, 
 #pragma unroll
         for (int b = 0; b < 2; ++b) s += r[q + a * fy + b * fz] + r[q + 1 + a * fy + b * fz];
     put_cell<T>(gc, fc, I, J, K, pc, cc.vinv[pc] != T(0) ? T(0.125) * s : T(0));
+    if (xz) put_cell<T>(gc, xz, I, J, K, pc, T(0));   // the coarse iterate starts at zero
 }
 
 template <class T>
@@ -756,10 +767,10 @@ k_s_smooth_b(Grid g, Coefs<T> c, T w, int colour, const int32_t *__restrict__ ro
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc) {
+k_s_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc, VPtr<T> xz) {
     int q;
     const int64_t t = wave_item(q);
-    s_restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t);
+    s_restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t, xz.p[q]);
 }
 
 template <class T, int NR>
@@ -1576,11 +1587,11 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
 
 template <class T>
 void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                       const VPtr<T> &fc, hipStream_t s) {
+                       const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz) {
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
     const Coefs<T> cc = coefs_of(coef_c, gc.P);
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc, r,
-                                        fc))
+                                        fc, xz))
 }
 
 template <class T>
@@ -1634,11 +1645,11 @@ void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int n
 
 template <class T>
 void launch_s_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                         const VPtr<T> &fc, hipStream_t s) {
+                         const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz) {
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
     const Coefs<T> cc = coefs_of(coef_c, gc.P);
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_restrict_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc,
-                                        r, fc))
+                                        r, fc, xz))
 }
 
 template <class T>
@@ -1656,7 +1667,7 @@ void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, int
     template void launch_s_smooth_b<T>(const Grid &, const T *, double, int, int, const VPtr<const T> &,          \
                                        const VPtr<T> &, hipStream_t, const int32_t *, int64_t);                   \
     template void launch_s_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,       \
-                                         const VPtr<T> &, hipStream_t);                                           \
+                                         const VPtr<T> &, hipStream_t, const VPtr<T> &);                          \
     template void launch_s_prolong_add_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,    \
                                             const VPtr<T> &, hipStream_t);
 DM_SCALAR_BLOCK(double)
@@ -1978,7 +1989,7 @@ void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, 
     template void launch_smooth_b<T>(const Grid &, const T *, T, int, int, int, const VPtr<const T> &,           \
                                      const VPtr<T> &, hipStream_t, ClassList);                                    \
     template void launch_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,        \
-                                       const VPtr<T> &, hipStream_t);                                             \
+                                       const VPtr<T> &, hipStream_t, const VPtr<T> &);                                             \
     template void launch_prolong_add_b<T>(const Grid &, const Grid &, const T *, const T *, int,                 \
                                           const VPtr<const T> &, const VPtr<T> &, hipStream_t);                   \
     template void launch_coarse_solve_b<T>(int, const double *, const int64_t *, int, const VPtr<const T> &,     \

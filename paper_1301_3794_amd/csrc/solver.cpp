@@ -423,7 +423,9 @@ void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     const int64_t n3 = 3 * g.P;
     const T sig = (T)op->sigma;
     const VPtr<T> F = slots(BPrec<T>::f(L), n3, nr), X = slots(BPrec<T>::x(L), n3, nr);
-    launch_zero<T>(nr * n3, BPrec<T>::x(L), s);
+    // the iterate starts at zero: here on the finest level, on the coarser
+    // ones in the restriction that forms their right-hand side
+    if (l == 0) launch_zero<T>(nr * n3, BPrec<T>::x(L), s);
     if (l == op->nlev() - 1) {
         launch_coarse_solve_b<T>(op->nc, op->cinv, op->cidx, nr, as_const(F), X, s);
         for (int q = 0; q < nr; ++q) launch_mirror_faces<T>(g, X.p[q], s);
@@ -438,7 +440,8 @@ void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     launch_apply_b<T>(g, c, sig, AK_RESID, nr, as_const(F), as_const(X), R, s, L.cut_cells());
     Level &C = op->lv[l + 1];
     const int64_t c3 = 3 * C.g.P;
-    launch_restrict_b<T>(g, C.g, Prec<T>::coef(C), nr, as_const(R), slots(BPrec<T>::f(C), c3, nr), s);
+    launch_restrict_b<T>(g, C.g, Prec<T>::coef(C), nr, as_const(R), slots(BPrec<T>::f(C), c3, nr), s,
+                         slots(BPrec<T>::x(C), c3, nr));
     vcycle_b<T>(op, l + 1, nr, s);
     launch_prolong_add_b<T>(g, C.g, c, Prec<T>::coef(C), nr, as_const(slots(BPrec<T>::x(C), c3, nr)), X, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
@@ -477,7 +480,7 @@ void svcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     const int64_t P = g.P;
     const T *c = S::coef(L);
     const VPtr<T> F = slots(S::f(L), P, nr), X = slots(S::x(L), P, nr);
-    launch_zero<T>(nr * P, S::x(L), s);
+    if (l == 0) launch_zero<T>(nr * P, S::x(L), s);   // coarser levels: zeroed by the restriction
     if (l == op->nlev() - 1) {
         launch_coarse_solve_b<T>(op->ns, op->sinv, op->sidx, nr, as_const(F), X, s);
         for (int q = 0; q < nr; ++q) launch_mirror_cells<T>(g, X.p[q], s);
@@ -489,7 +492,8 @@ void svcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     const VPtr<T> R = slots(S::r(L), P, nr);
     launch_s_apply_b<T>(g, c, L.sweight, 1, nr, as_const(F), as_const(X), R, s);
     Level &C = op->lv[l + 1];
-    launch_s_restrict_b<T>(g, C.g, S::coef(C), nr, as_const(R), slots(S::f(C), C.g.P, nr), s);
+    launch_s_restrict_b<T>(g, C.g, S::coef(C), nr, as_const(R), slots(S::f(C), C.g.P, nr), s,
+                           slots(S::x(C), C.g.P, nr));
     svcycle_b<T>(op, l + 1, nr, s);
     launch_s_prolong_add_b<T>(g, C.g, c, nr, as_const(slots(S::x(C), C.g.P, nr)), X, s);
     for (int it = 0; it < op->opt.nu_post; ++it)
