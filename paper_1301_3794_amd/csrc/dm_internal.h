@@ -321,13 +321,17 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
 template <class T>
 void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour, int nr, const VPtr<const T> &f,
                      const VPtr<T> &x, hipStream_t s, ClassList cut = {});
-// xz (optional, one coarse iterate per vector): set to zero in the same pass
+// xz (optional, one coarse iterate per vector): set to zero in the same pass;
+// rows (optional): the coarse grid rows (k * ny + j) to visit, those holding
+// an active face (fc and xz stay zero on the others)
 template <class T>
 void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                       const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz = {});
+                       const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz = {}, const int32_t *rows = nullptr,
+                       int64_t nrows = 0);
 template <class T>
 void launch_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, int nr,
-                          const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s);
+                          const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s, const int32_t *rows = nullptr,
+                          int64_t nrows = 0);
 template <class T>
 void launch_coarse_solve_b(int n, const double *inv, const int64_t *idx, int nr, const VPtr<const T> &f,
                            const VPtr<T> &x, hipStream_t s);

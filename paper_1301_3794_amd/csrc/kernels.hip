@@ -64,6 +64,15 @@ __device__ inline bool cell_of(const Grid &g, int64_t t, int &i, int &j, int &k)
     return true;
 }
 
+// Item t of a launch over listed grid rows (k * ny + j, ascending) -> the
+// cell item of the whole grid (past its end for t past the listed rows);
+// without a list the item itself
+__device__ inline int64_t listed_item(const Grid &g, const int32_t *rows, int64_t nrows, int64_t t) {
+    if (!rows) return t;
+    if (t >= nrows * g.nx) return (int64_t)g.nx * g.ny * g.nz;
+    return (int64_t)rows[t / g.nx] * g.nx + t % g.nx;
+}
+
 template <class T>
 __device__ inline T inv_h2_of(const Grid &g) {
     return (T)(1.0 / (g.h * g.h));
@@ -181,7 +190,7 @@ k_apply_b(Grid g, Coefs<T> c, T sigma, VPtr<const T> f, VPtr<const T> x, VPtr<T>
 template <class T, int KIND, int NR, class TX = T>
 __global__ void __launch_bounds__(kThreads)
 k_apply_split(Grid g, Coefs<T> c, T sigma, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
-              VPtr<const T> f, VPtr<const TX> x, VPtr<T> y) {
+              const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f, VPtr<const TX> x, VPtr<T> y) {
     const int64_t b = blockIdx.x;
     const int q = threadIdx.x >> 6;
     if (b < ncb) {
@@ -195,7 +204,7 @@ k_apply_split(Grid g, Coefs<T> c, T sigma, const int32_t *__restrict__ cut, int6
         const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
         const int64_t t = ((bv % kXcd) * (nvb / kXcd) + bv / kXcd) * 64 + (threadIdx.x & 63);
         int i, j, k;
-        if (!cell_of(g, t, i, j, k)) return;
+        if (!cell_of(g, listed_item(g, rows, nrows, t), i, j, k)) return;
         const int64_t p = pidx(g, i, j, k);
         const uint8_t fl = c.flags[p];
         if (has_cut_row(fl)) return;
@@ -434,10 +443,11 @@ k_restrict(Grid gf, Grid gc, Coefs<T> cc, const T *__restrict__ r, T *__restrict
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc, VPtr<T> xz) {
+k_restrict_b(Grid gf, Grid gc, Coefs<T> cc, const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> r,
+             VPtr<T> fc, VPtr<T> xz) {
     int q;
     const int64_t t = wave_item(q);
-    restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t, xz.p[q]);
+    restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], listed_item(gc, rows, nrows, t), xz.p[q]);
 }
 
 // fine value between coarse faces c0, c1: (a0 x0 + a1 x1) / (a0 + a1)
@@ -476,10 +486,11 @@ k_prolong_add(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const T *__restrict__ 
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, VPtr<const T> xc, VPtr<T> x) {
+k_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, Coefs<T> cc, const int32_t *__restrict__ rows, int64_t nrows,
+                VPtr<const T> xc, VPtr<T> x) {
     int q;
     const int64_t t = wave_item(q);
-    prolong_body<T>(gf, gc, cf, cc, xc.p[q], x.p[q], t);
+    prolong_body<T>(gf, gc, cf, cc, xc.p[q], x.p[q], listed_item(gf, rows, nrows, t));
 }
 
 // x = 0 (a kernel, not a memset: it may be recorded into a HIP graph)
@@ -1516,15 +1527,17 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
     if (cut.idx && (kind == AK_M || kind == AK_RESID)) {
+        // the vacuum part visits the listed grid rows (every row without a list)
         const int64_t ncb = ceil_div(ceil_div(cut.n, 64), kXcd) * kXcd;
-        const int64_t nvb = ceil_div(ceil_div(n, 64), kXcd) * kXcd;
+        const int64_t nvac = cut.rows ? cut.nrows * g.nx : n;
+        const int64_t nvb = ceil_div(ceil_div(nvac, 64), kXcd) * kXcd;
         const dim3 grid((unsigned)(ncb + nvb));
         if (kind == AK_M)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<T, AK_M, NR>), grid, dim3(64 * NR), 0, s, g, c, sigma,
-                                                cut.idx, cut.n, ncb, f, x, y))
+                                                cut.idx, cut.n, ncb, cut.rows, cut.nrows, f, x, y))
         else
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<T, AK_RESID, NR>), grid, dim3(64 * NR), 0, s, g, c,
-                                                sigma, cut.idx, cut.n, ncb, f, x, y))
+                                                sigma, cut.idx, cut.n, ncb, cut.rows, cut.nrows, f, x, y))
         return;
     }
     if (kind == AK_M)
@@ -1547,8 +1560,9 @@ void launch_apply_m_f32in(const Grid &g, const double *coef, double sigma, int n
     const int64_t nvb = ceil_div(ceil_div(n, 64), kXcd) * kXcd;
     const dim3 grid((unsigned)(ncb + nvb));
     const VPtr<const double> f{};
+    const int32_t *norows = nullptr;   // every row: M z is written on every row
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<double, AK_M, NR, float>), grid, dim3(64 * NR), 0, s, g, c,
-                                        sigma, cut.idx, cut.n, ncb, f, x, y))
+                                        sigma, cut.idx, cut.n, ncb, norows, (int64_t)0, f, x, y))
 }
 
 template <class T>
@@ -1587,20 +1601,21 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
 
 template <class T>
 void launch_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                       const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz) {
-    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+                       const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz, const int32_t *rows, int64_t nrows) {
+    const int64_t n = rows ? nrows * gc.nx : (int64_t)gc.nx * gc.ny * gc.nz;
     const Coefs<T> cc = coefs_of(coef_c, gc.P);
-    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc, r,
-                                        fc, xz))
+    DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_restrict_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc,
+                                        rows, nrows, r, fc, xz))
 }
 
 template <class T>
 void launch_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, const T *coef_c, int nr,
-                          const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s) {
-    const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
+                          const VPtr<const T> &xc, const VPtr<T> &x, hipStream_t s, const int32_t *rows,
+                          int64_t nrows) {
+    const int64_t n = rows ? nrows * gf.nx : (int64_t)gf.nx * gf.ny * gf.nz;
     const Coefs<T> cf = coefs_of(coef_f, gf.P), cc = coefs_of(coef_c, gc.P);
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_prolong_add_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cf,
-                                        cc, xc, x))
+                                        cc, rows, nrows, xc, x))
 }
 
 template <class T>
@@ -1989,9 +2004,10 @@ void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, 
     template void launch_smooth_b<T>(const Grid &, const T *, T, int, int, int, const VPtr<const T> &,           \
                                      const VPtr<T> &, hipStream_t, ClassList);                                    \
     template void launch_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,        \
-                                       const VPtr<T> &, hipStream_t, const VPtr<T> &);                                             \
+                                       const VPtr<T> &, hipStream_t, const VPtr<T> &, const int32_t *, int64_t);                                             \
     template void launch_prolong_add_b<T>(const Grid &, const Grid &, const T *, const T *, int,                 \
-                                          const VPtr<const T> &, const VPtr<T> &, hipStream_t);                   \
+                                          const VPtr<const T> &, const VPtr<T> &, hipStream_t, const int32_t *,   \
+                                          int64_t);                   \
     template void launch_coarse_solve_b<T>(int, const double *, const int64_t *, int, const VPtr<const T> &,     \
                                            const VPtr<T> &, hipStream_t);
 DM_BLOCK_INST(double)

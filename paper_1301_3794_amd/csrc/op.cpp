@@ -216,6 +216,19 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
                 for (int i = 0; i < L.g.nx && !any; ++i) any = c[6 * P + pidx(L.g, i, j, k)] != 0.0;
                 if (any) arows.push_back((int32_t)(k * L.g.ny + j));
             }
+        std::vector<int32_t> frows;
+        for (int k = 0; k < L.g.nz; ++k)
+            for (int j = 0; j < L.g.ny; ++j) {
+                bool any = false;
+                for (int i = 0; i < L.g.nx && !any; ++i) any = fl[pidx(L.g, i, j, k)] & 7;
+                if (any) frows.push_back((int32_t)(k * L.g.ny + j));
+            }
+        L.nfrows = (int64_t)frows.size();
+        if (!frows.empty()) {
+            L.frows = op->dalloc<int32_t>(frows.size());
+            DM_HIP(hipMemcpyAsync(L.frows, frows.data(), frows.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  op->stream));
+        }
         L.narows = (int64_t)arows.size();
         if (!arows.empty()) {
             L.arows = op->dalloc<int32_t>(arows.size());

@@ -40,6 +40,12 @@ struct Level {
     // grid rows (k * ny + j) with an active cell (the scalar problem's unknowns)
     int32_t *arows = nullptr;
     int64_t narows = 0;
+    // grid rows (k * ny + j) with an active face
+    int32_t *frows = nullptr;
+    int64_t nfrows = 0;
+    // the cut-cell list with the rows holding an active face: for outputs
+    // that stay zero on the other rows (the block V-cycle's residual)
+    ClassList cut_cells_rows() const { return ClassList{cutc, ncutc, frows, nfrows}; }
     ClassList cut_list(int comp, int colour) const {
         const int q = 2 * comp + colour;
         return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows};

@@ -437,13 +437,17 @@ void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
             for (int col = 0; col < 2; ++col)
                 launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s, L.cut_list(comp, col));
     const VPtr<T> R = slots(BPrec<T>::r(L), n3, nr);
-    launch_apply_b<T>(g, c, sig, AK_RESID, nr, as_const(F), as_const(X), R, s, L.cut_cells());
+    // the residual, restriction and prolongation visit only the grid rows
+    // holding an active face: the residual slots, the coarse right-hand
+    // sides and iterates stay zero on the others (written only here)
+    launch_apply_b<T>(g, c, sig, AK_RESID, nr, as_const(F), as_const(X), R, s, L.cut_cells_rows());
     Level &C = op->lv[l + 1];
     const int64_t c3 = 3 * C.g.P;
     launch_restrict_b<T>(g, C.g, Prec<T>::coef(C), nr, as_const(R), slots(BPrec<T>::f(C), c3, nr), s,
-                         slots(BPrec<T>::x(C), c3, nr));
+                         slots(BPrec<T>::x(C), c3, nr), C.frows, C.nfrows);
     vcycle_b<T>(op, l + 1, nr, s);
-    launch_prolong_add_b<T>(g, C.g, c, Prec<T>::coef(C), nr, as_const(slots(BPrec<T>::x(C), c3, nr)), X, s);
+    launch_prolong_add_b<T>(g, C.g, c, Prec<T>::coef(C), nr, as_const(slots(BPrec<T>::x(C), c3, nr)), X, s,
+                            L.frows, L.nfrows);
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int comp = 2; comp >= 0; --comp)
             for (int col = 1; col >= 0; --col)
