@@ -366,9 +366,12 @@ void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<con
                        const VPtr<const double> &b_in, const VPtr<double> &b_out, double scale, hipStream_t s);
 // (FP64, or FP32 with the FP32 coefficient blocks: the preconditioner of the
 // projection's conjugate gradients)
+// (rows, optional: the grid rows, k * ny + j, to visit -- those holding an
+// active cell; y, fc, xz and x stay as they are on the other rows)
 template <class T>
 void launch_s_apply_b(const Grid &g, const T *coef, double w, int resid, int nr, const VPtr<const T> &f,
-                      const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s);
+                      const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s, const int32_t *rows = nullptr,
+                      int64_t nrows = 0);
 // (rows: optional list of the grid rows, k * ny + j, holding an active cell;
 // the colour sweep then visits only those)
 template <class T>
@@ -377,10 +380,11 @@ void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int n
 // (xz: optional coarse iterates, set to zero in the same pass)
 template <class T>
 void launch_s_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                         const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz = {});
+                         const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz = {}, const int32_t *rows = nullptr,
+                         int64_t nrows = 0);
 template <class T>
 void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, int nr, const VPtr<const T> &xc,
-                            const VPtr<T> &x, hipStream_t s);
+                            const VPtr<T> &x, hipStream_t s, const int32_t *rows = nullptr, int64_t nrows = 0);
 
 // PMC ghost layers of a face / cell vector from the adjacent values (no-op
 // without PMC planes)

@@ -761,10 +761,11 @@ k_grad_sub_b(Grid g, Coefs<double> c, VPtr<const double> psi, VPtr<const double>
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_apply_b(Grid g, Coefs<T> c, T w, int resid, VPtr<const T> f, VPtr<const T> x, VPtr<T> y) {
+k_s_apply_b(Grid g, Coefs<T> c, T w, int resid, const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f,
+            VPtr<const T> x, VPtr<T> y) {
     int q;
     const int64_t t = wave_item(q);
-    s_apply_body<T>(g, c, w, resid, f.p[q], x.p[q], y.p[q], t);
+    s_apply_body<T>(g, c, w, resid, f.p[q], x.p[q], y.p[q], listed_item(g, rows, nrows, t));
 }
 
 template <class T, int NR>
@@ -778,18 +779,20 @@ k_s_smooth_b(Grid g, Coefs<T> c, T w, int colour, const int32_t *__restrict__ ro
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_restrict_b(Grid gf, Grid gc, Coefs<T> cc, VPtr<const T> r, VPtr<T> fc, VPtr<T> xz) {
+k_s_restrict_b(Grid gf, Grid gc, Coefs<T> cc, const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> r,
+               VPtr<T> fc, VPtr<T> xz) {
     int q;
     const int64_t t = wave_item(q);
-    s_restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], t, xz.p[q]);
+    s_restrict_body<T>(gf, gc, cc, r.p[q], fc.p[q], listed_item(gc, rows, nrows, t), xz.p[q]);
 }
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kThreads)
-k_s_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, VPtr<const T> xc, VPtr<T> x) {
+k_s_prolong_add_b(Grid gf, Grid gc, Coefs<T> cf, const int32_t *__restrict__ rows, int64_t nrows,
+                  VPtr<const T> xc, VPtr<T> x) {
     int q;
     const int64_t t = wave_item(q);
-    s_prolong_body<T>(gf, gc, cf, xc.p[q], x.p[q], t);
+    s_prolong_body<T>(gf, gc, cf, xc.p[q], x.p[q], listed_item(gf, rows, nrows, t));
 }
 
 // ---------------------------------------------------------------------------
@@ -1642,11 +1645,11 @@ void launch_grad_sub_b(const Grid &g, const double *coef, int nr, const VPtr<con
 
 template <class T>
 void launch_s_apply_b(const Grid &g, const T *coef, double w, int resid, int nr, const VPtr<const T> &f,
-                      const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s) {
-    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+                      const VPtr<const T> &x, const VPtr<T> &y, hipStream_t s, const int32_t *rows, int64_t nrows) {
+    const int64_t n = rows ? nrows * g.nx : (int64_t)g.nx * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_apply_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, g, c, (T)w,
-                                        resid, f, x, y))
+                                        resid, rows, nrows, f, x, y))
 }
 
 template <class T>
@@ -1660,31 +1663,33 @@ void launch_s_smooth_b(const Grid &g, const T *coef, double w, int colour, int n
 
 template <class T>
 void launch_s_restrict_b(const Grid &gf, const Grid &gc, const T *coef_c, int nr, const VPtr<const T> &r,
-                         const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz) {
-    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+                         const VPtr<T> &fc, hipStream_t s, const VPtr<T> &xz, const int32_t *rows, int64_t nrows) {
+    const int64_t n = rows ? nrows * gc.nx : (int64_t)gc.nx * gc.ny * gc.nz;
     const Coefs<T> cc = coefs_of(coef_c, gc.P);
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_restrict_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc, cc,
-                                        r, fc, xz))
+                                        rows, nrows, r, fc, xz))
 }
 
 template <class T>
 void launch_s_prolong_add_b(const Grid &gf, const Grid &gc, const T *coef_f, int nr, const VPtr<const T> &xc,
-                            const VPtr<T> &x, hipStream_t s) {
-    const int64_t n = (int64_t)gf.nx * gf.ny * gf.nz;
+                            const VPtr<T> &x, hipStream_t s, const int32_t *rows, int64_t nrows) {
+    const int64_t n = rows ? nrows * gf.nx : (int64_t)gf.nx * gf.ny * gf.nz;
     const Coefs<T> cf = coefs_of(coef_f, gf.P);
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_s_prolong_add_b<T, NR>), xcd_grid_waves(n), dim3(64 * NR), 0, s, gf, gc,
-                                        cf, xc, x))
+                                        cf, rows, nrows, xc, x))
 }
 
 #define DM_SCALAR_BLOCK(T)                                                                                        \
     template void launch_s_apply_b<T>(const Grid &, const T *, double, int, int, const VPtr<const T> &,           \
-                                      const VPtr<const T> &, const VPtr<T> &, hipStream_t);                       \
+                                      const VPtr<const T> &, const VPtr<T> &, hipStream_t, const int32_t *,       \
+                                      int64_t);                                                                   \
     template void launch_s_smooth_b<T>(const Grid &, const T *, double, int, int, const VPtr<const T> &,          \
                                        const VPtr<T> &, hipStream_t, const int32_t *, int64_t);                   \
     template void launch_s_restrict_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,       \
-                                         const VPtr<T> &, hipStream_t, const VPtr<T> &);                          \
+                                         const VPtr<T> &, hipStream_t, const VPtr<T> &, const int32_t *,          \
+                                         int64_t);                                                                \
     template void launch_s_prolong_add_b<T>(const Grid &, const Grid &, const T *, int, const VPtr<const T> &,    \
-                                            const VPtr<T> &, hipStream_t);
+                                            const VPtr<T> &, hipStream_t, const int32_t *, int64_t);
 DM_SCALAR_BLOCK(double)
 DM_SCALAR_BLOCK(float)
 #undef DM_SCALAR_BLOCK

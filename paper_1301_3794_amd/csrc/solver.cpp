@@ -494,12 +494,14 @@ void svcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
         for (int col = 0; col < 2; ++col)
             launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s, L.arows, L.narows);
     const VPtr<T> R = slots(S::r(L), P, nr);
-    launch_s_apply_b<T>(g, c, L.sweight, 1, nr, as_const(F), as_const(X), R, s);
+    // residual and transfers on the grid rows holding an active cell (the
+    // slots stay zero on the others)
+    launch_s_apply_b<T>(g, c, L.sweight, 1, nr, as_const(F), as_const(X), R, s, L.arows, L.narows);
     Level &C = op->lv[l + 1];
     launch_s_restrict_b<T>(g, C.g, S::coef(C), nr, as_const(R), slots(S::f(C), C.g.P, nr), s,
-                           slots(S::x(C), C.g.P, nr));
+                           slots(S::x(C), C.g.P, nr), C.arows, C.narows);
     svcycle_b<T>(op, l + 1, nr, s);
-    launch_s_prolong_add_b<T>(g, C.g, c, nr, as_const(slots(S::x(C), C.g.P, nr)), X, s);
+    launch_s_prolong_add_b<T>(g, C.g, c, nr, as_const(slots(S::x(C), C.g.P, nr)), X, s, L.arows, L.narows);
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int col = 1; col >= 0; --col)
             launch_s_smooth_b<T>(g, c, L.sweight, col, nr, as_const(F), X, s, L.arows, L.narows);
@@ -763,7 +765,9 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
         for (int q = 0; q < nr; ++q) rz[q] = hres(q)[0];
         int it = 0;
         while (it < maxit) {
-            launch_s_apply_b(g, L.coef64, L.sweight, 0, nr, VPtr<const double>{}, as_const(PP), Q, s);
+            // q = S p on the rows holding an active cell (q is zero elsewhere)
+            launch_s_apply_b(g, L.coef64, L.sweight, 0, nr, VPtr<const double>{}, as_const(PP), Q, s, L.arows,
+                             L.narows);
             launch_dot_pairs(nr, as_const(pick(PP, act)), as_const(Q), op->cmask, P, op->part, op->bk_dres,
                              kMaxDots, s);
             fetch();
