@@ -410,8 +410,9 @@ void launch_s_prolong_add(const Grid &gf, const Grid &gc, const double *coef_f,
 // BLAS-1 style FP64 helpers on flat arrays
 void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 // y = M x (FP64 arithmetic and output) for FP32-stored x: each value of x is
-// widened before use, so y equals the product with the widened x; needs the
-// cut-cell list of the level (the split form)
+// widened before use, so y equals the product with the widened x; takes the
+// cut-cell list of the level (the split form), and with its rows leaves y
+// untouched on the other rows
 void launch_apply_m_f32in(const Grid &g, const double *coef, double sigma, int nr, const VPtr<const float> &x,
                           const VPtr<double> &y, hipStream_t s, ClassList cut);
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);

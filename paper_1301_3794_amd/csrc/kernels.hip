@@ -1560,12 +1560,12 @@ void launch_apply_m_f32in(const Grid &g, const double *coef, double sigma, int n
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<double> c = coefs_of(coef, g.P);
     const int64_t ncb = cut.idx ? ceil_div(ceil_div(cut.n, 64), kXcd) * kXcd : 0;
-    const int64_t nvb = ceil_div(ceil_div(n, 64), kXcd) * kXcd;
+    const int64_t nvac = cut.rows ? cut.nrows * g.nx : n;
+    const int64_t nvb = ceil_div(ceil_div(nvac, 64), kXcd) * kXcd;
     const dim3 grid((unsigned)(ncb + nvb));
     const VPtr<const double> f{};
-    const int32_t *norows = nullptr;   // every row: M z is written on every row
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<double, AK_M, NR, float>), grid, dim3(64 * NR), 0, s, g, c,
-                                        sigma, cut.idx, cut.n, ncb, norows, (int64_t)0, f, x, y))
+                                        sigma, cut.idx, cut.n, ncb, cut.rows, cut.nrows, f, x, y))
 }
 
 template <class T>

@@ -1010,13 +1010,16 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             }
             wv.p[q] = Vc(r, st[r].j + 1);          // w = M Z_j in the next column's slot
         }
+        // w = M z on the rows holding an active face: the slots of columns
+        // 1..m are zero on the others (written only here and, within the
+        // listed units, by the Gram--Schmidt updates of zero entries)
         if (z32) {
             precondition_block_f32(op, na, vin, zout32, s);
-            launch_apply_m_f32in(L.g, L.coef64, op->sigma, na, zc32, wv, s, L.cut_cells());
+            launch_apply_m_f32in(L.g, L.coef64, op->sigma, na, zc32, wv, s, L.cut_cells_rows());
         } else {
             precondition_block(op, mode, na, vin, zout, s);
             launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s,
-                                   L.cut_cells());
+                                   L.cut_cells_rows());
         }
         // Gram--Schmidt as in fgmres(): (1) d = U^T w, (2) w -= U (sc^2 d)
         // fused with d2 = U^T w and |w|^2, every open system, one sync
