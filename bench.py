@@ -208,8 +208,8 @@ def run_c4(dm, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(one GPU holds the whole grid; sharding across GPUs is not built)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(one GPU holds the whole grid; sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
