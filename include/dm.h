@@ -111,6 +111,11 @@ typedef struct {
     int nu_post;         /* red-black sweeps after (2) */
     int fgmres_restart;  /* FGMRES restart length (30) */
     int verbose;         /* 0 silent, 1 per-solve lines on stderr */
+    int cut_wave_split;  /* block smoother (2..4 vectors): a class whose list of
+                            non-vacuum rows is shorter than this gives each vector
+                            its own wavefront; a longer list takes one thread per
+                            row looping over the vectors (32768; 0 always takes
+                            the loop).  Both give the same values. */
 } dm_options;
 
 /* Fills `opt` with the defaults listed above. */
@@ -261,6 +266,12 @@ typedef struct {
     int max_basis;       /* basis size before a thick restart (40) */
     int max_restarts;    /* (20) */
     int verbose;
+    /* NULL, or `block` face vectors (block * 3P doubles, device) taken as the
+       start block instead of the seeded random one (a warm start from earlier
+       eigenvectors); they are projected and A-orthonormalised like the
+       random block.  A block that vanishes there (all zero, or gradients
+       only) gives DM_EBREAKDOWN. */
+    const double *start_dev;
 } dm_eig_options;
 
 void dm_default_eig_options(dm_eig_options *opt);
@@ -279,7 +290,11 @@ typedef struct {
  * Krylov--Schur in the A-inner product (eq. bInner) on T = P_DM M^-1 A with
  * shift sigma, stopping when every pair has
  *     rho = ||K b - lambda A b||_{A^-1} / (lambda ||b||_A) <= tol.
- *   sigma        shift (M is re-factored if it differs from the op's).
+ *   sigma        shift (M is re-factored if it differs from the op's); it
+ *                may lie above some of the wanted eigenvalues (Sec. 4.1 puts
+ *                it near the wanted ones): thick restarts keep the Ritz pairs
+ *                whose estimate lambda = sigma + 1/theta is smallest and
+ *                positive, below the shift as well as above it.
  *   seed         start block: N(0,1) on active faces from a counter-based
  *                generator keyed by seed.
  *   lambda_host  k doubles, ascending.
@@ -335,7 +350,8 @@ int dm_batch_info(const dm_batch *b, dm_batch_stats *stats);
 int dm_batch_vcycle(dm_batch *b, const float *const *f_dev, float *const *x_dev, void *stream);
 /* Average milliseconds of one fused V-cycle (graph replay, HIP events). */
 int dm_batch_time_vcycle(dm_batch *b, int reps, double *ms);
-/* dm_eigs on every member (k pairs each, FP32-multigrid solve mode forced),
+/* dm_eigs on every member (k pairs each, FP32-multigrid solve mode forced;
+ * opt->start_dev must be NULL),
  * each on its own host thread and stream; every preconditioner application
  * of all running members is one fused V-cycle.  lambda_host: count*k,
  * residuals_host: count*k or NULL, info_host: count or NULL, seconds: wall
@@ -393,6 +409,14 @@ int dm_net_make_pair(dm_op *op, uint64_t seed, double *r_dev, double *e_dev, voi
  * per step; loss_host (may be NULL) receives the loss of every step. */
 int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss_host,
                  void *stream);
+/* `npairs` Adam steps on caller-given pairs, one pair per step in order:
+ * r_dev[i] (and e_dev[i] for the error loss; e_dev may be NULL for the
+ * residual loss) are host arrays of device face vectors (3P doubles) on
+ * op's finest grid, s computed from r.  Continues the network's Adam state
+ * (step count and moments, reset by dm_net_set_weights), as dm_net_train
+ * does.  loss_host (may be NULL): the loss of every step. */
+int dm_net_train_pairs(dm_op *op, int kind, int npairs, const double *const *r_dev, const double *const *e_dev,
+                       float lr, float *loss_host, void *stream);
 
 /* ---- measurement -------------------------------------------------------- */
 #define DM_KERNEL_APPLY     0  /* y = M x on `level` */

@@ -184,3 +184,54 @@ class HalfVCycle(mg.VCycle):
         for _ in range(self.nu2):
             self._smooth(L, x, f, self.ORDER[::-1])
         return x
+
+
+class SymmetricPencil:
+    """The symmetric half-cavity problem in the form ``eigs.augmented_eigs``
+    takes (Sec. 6.3 quarter runs with the grad-div augmented pencil of
+    Sec. 5.1): on the active half faces,
+
+        K_a = Q^T K Q,  G_a = Q^T G Q,  A = Q^T A Q = diag(mult * a),
+        M_a = K_a + G_a - sigma A,
+
+    and the divergence of a half field b is that of its symmetric extension,
+    D A Q b, over the full cavity's active cells (``D_a``, ``v_a``: the
+    divergence check ||V^-1/2 D A (Q b)|| / ||b||_A of ``eigs.div_residual``
+    with A Q b = Q (a b) written as D_a (a_a b), D_a = D Q diag(1/mult)).
+    Its eigenpairs with lambda > 0 are the full cavity's eigenpairs that are
+    symmetric under the mirrors (pinned against ``sym_dense_eigs``)."""
+
+    def __init__(self, hop: HalfOperators, sigma=None):
+        self.hop = hop
+        self.sigma = hop.sigma if sigma is None else sigma
+        ext, full = hop.ext, hop.full
+        sel = hop.act
+        Q = ext.Q[:, sel]
+        self.Q_a = Q.tocsr()
+        self.mult_a = ext.mult[sel]
+        self.K_a = (Q.T @ full.K @ Q).tocsr()
+        self.G_a = (Q.T @ full.G @ Q).tocsr()
+        self.a_a = self.mult_a * hop.a[sel]
+        self.M_a = (self.K_a + self.G_a - self.sigma * sp.diags(self.a_a)).tocsr()
+        self.D_a = (full.D[full.cact] @ Q @ sp.diags(1.0 / self.mult_a)).tocsr()
+        self.v_a = full.v[full.cact]
+        self.act = sel
+
+    def with_shift(self, sigma):
+        return SymmetricPencil(self.hop, sigma)
+
+
+def half_vcycle_preconditioner(vc: HalfVCycle, pencil: SymmetricPencil):
+    """M_a^-1 ~ B_h diag(1/mult) on active half faces.  B_h approximates
+    (R M Q)^-1 = (diag(1/mult) Q^T M Q)^-1, so B_h diag(1/mult) approximates
+    (Q^T M Q)^-1; it is symmetric because diag(mult) B_h is (pinned)."""
+    L0 = vc.levels[0]
+    n = L0.op.grid.n_faces
+    sel = pencil.act
+    inv_mult = 1.0 / pencil.mult_a
+
+    def apply(r_act):
+        full = np.zeros(n)
+        full[sel] = inv_mult * r_act
+        return vc(full)[sel]
+    return apply

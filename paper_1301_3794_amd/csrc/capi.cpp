@@ -141,6 +141,7 @@ void dm_default_options(dm_options *opt) {
     opt->nu_post = 2;
     opt->fgmres_restart = 30;
     opt->verbose = 0;
+    opt->cut_wave_split = 32768;
 }
 
 void dm_default_eig_options(dm_eig_options *opt) {
@@ -152,6 +153,7 @@ void dm_default_eig_options(dm_eig_options *opt) {
     opt->max_basis = 40;
     opt->max_restarts = 20;
     opt->verbose = 0;
+    opt->start_dev = nullptr;
 }
 
 const char *dm_strerror(int code) {
@@ -217,8 +219,8 @@ int dm_build_operator(const dm_geometry *geom, const int dims[3], double h, doub
         else dm_default_options(&op->opt);
         if (op->opt.levels <= 0) op->opt.levels = auto_levels(dims);
         if (op->opt.nu_pre < 0 || op->opt.nu_post < 0 || op->opt.fgmres_restart < 1 ||
-            op->opt.fgmres_restart > kMaxDots - 2)
-            return fail(DM_EINVAL, "bad smoothing or restart option");
+            op->opt.fgmres_restart > kMaxDots - 2 || op->opt.cut_wave_split < 0)
+            return fail(DM_EINVAL, "bad smoothing, restart or wave-split option");
         const int div = 1 << (op->opt.levels - 1);
         for (int a = 0; a < 3; ++a)
             if (dims[a] % div != 0 || dims[a] / div < 1)
@@ -625,6 +627,7 @@ int dm_batch_eigs(dm_batch *b, int k, double sigma, double tol, uint64_t seed, c
     dm_eig_options o;
     if (opt) o = *opt;
     else dm_default_eig_options(&o);
+    if (o.start_dev) return fail(DM_EINVAL, "batched eigensolves draw their own start blocks");
     o.solve_mode = DM_SOLVE_FGMRES_MG32;
     const int n = (int)b->ops.size();
     // a change of shift re-factors every member and re-records the fused V-cycle
@@ -780,6 +783,21 @@ int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float 
     if (steps < 0 || !(lr > 0.f)) return fail(DM_EINVAL, "steps must be >= 0 and lr > 0");
     return on_device(op, stream, [&](hipStream_t s) -> int {
         net_train(op, kind, steps, lr, seed, loss_host, s);
+        return DM_OK;
+    });
+}
+
+int dm_net_train_pairs(dm_op *op, int kind, int npairs, const double *const *r_dev, const double *const *e_dev,
+                       float lr, float *loss_host, void *stream) {
+    if (!op || (npairs > 0 && !r_dev)) return fail(DM_EINVAL, "NULL argument");
+    if (kind != DM_NET_LOSS_ERROR && kind != DM_NET_LOSS_RESIDUAL) return fail(DM_EINVAL, "unknown loss");
+    if (kind == DM_NET_LOSS_ERROR && !e_dev) return fail(DM_EINVAL, "error loss needs e");
+    if (!op->net) return fail(DM_EINVAL, "no network attached");
+    if (npairs < 0 || !(lr > 0.f)) return fail(DM_EINVAL, "npairs must be >= 0 and lr > 0");
+    for (int i = 0; i < npairs; ++i)
+        if (!r_dev[i] || (kind == DM_NET_LOSS_ERROR && !e_dev[i])) return fail(DM_EINVAL, "NULL pair vector");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        net_train_pairs(op, kind, npairs, r_dev, e_dev, lr, loss_host, s);
         return DM_OK;
     });
 }

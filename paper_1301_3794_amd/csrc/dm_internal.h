@@ -297,6 +297,9 @@ struct ClassList {
     // vacuum row of any component; the colour sweep visits only these
     const int32_t *rows = nullptr;
     int64_t nrows = 0;
+    // block smoother: below this many listed rows each vector gets its own
+    // wavefront, else one thread per row loops over the vectors
+    int64_t wave_split_max = 32768;
 };
 
 // Units of kSpanUnit consecutive doubles (one 128-byte line) of a level-0
@@ -476,5 +479,7 @@ void launch_sub_masked(int64_t n, const double *mask, const double *val, double 
 void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, double *x,
                   hipStream_t s);
 void launch_mask_mul(int64_t n, const double *mask, double *x, hipStream_t s);
+// x = in on the mask's nonzero entries, 0 elsewhere
+void launch_copy_masked(int64_t n, const double *in, const double *mask, double *x, hipStream_t s);
 
 }  // namespace dm

@@ -1373,6 +1373,13 @@ __global__ void k_randn(int64_t n, uint64_t seed, int64_t offset, const double *
     }
 }
 
+// x = in where mask != 0, else 0
+__global__ void k_copy_masked(int64_t n, const double *__restrict__ in, const double *__restrict__ mask,
+                              double *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
+        x[e] = mask[e] != 0.0 ? in[e] : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Batched V-cycle steps (see BJob): the same bodies as the single-operator
 // kernels, the job found from the block index.
@@ -1510,9 +1517,9 @@ void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T
 }
 
 // cut rows of a class below which the block smoother gives each vector its
-// own wave (measured on the 128^3 sphere: ~60k rows per class on the finest
-// level favour the in-thread loop, ~15k rows on the next the waves)
-constexpr int64_t kCutWaveSplit = 32768;
+// own wave: ClassList::wave_split_max, an operator option (default 32768,
+// measured on the 128^3 sphere: ~60k rows per class on the finest level
+// favour the in-thread loop, ~15k rows on the next the waves)
 
 // ---- block forms: dispatch nr (1..kMaxRhs) to the template
 #define DM_NR_SWITCH(nr, CALL)                      \
@@ -1574,7 +1581,7 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
     const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
     if (cut.idx) {
-        const int wave_split = nr > 1 && cut.n < kCutWaveSplit;
+        const int wave_split = nr > 1 && cut.n < cut.wave_split_max;
         const int64_t ncb = ceil_div(ceil_div(cut.n, wave_split ? 64 : kThreads), kXcd) * kXcd;
         // the vacuum part sweeps the listed rows (every row without a list)
         const int64_t nvac = cut.rows ? cut.nrows * ((g.nx + 1) >> 1) : n;
@@ -2000,6 +2007,10 @@ void launch_mask_mul(int64_t n, const double *mask, double *x, hipStream_t s) {
 void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, double *x,
                   hipStream_t s) {
     hipLaunchKernelGGL(k_randn, flat_grid(n), dim3(kThreads), 0, s, n, seed, offset, mask, x);
+}
+
+void launch_copy_masked(int64_t n, const double *in, const double *mask, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_masked, flat_grid(n), dim3(kThreads), 0, s, n, in, mask, x);
 }
 
 // explicit instantiations

@@ -253,18 +253,40 @@ void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s
     DM_HIP(hipGetLastError());
 }
 
+namespace {
+
+// one Adam step (Kingma & Ba) of the FP32 master weights from net->grad
+void adam_step(dm_net *net, float lr, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    ++net->step;
+    const float c1 = 1.f - std::pow(b1, (float)net->step), c2 = 1.f - std::pow(b2, (float)net->step);
+    launch_net_adam(net->grad, net->w32, net->adam_m, net->adam_v, kNetWeights, lr, b1, b2, eps, c1, c2, s);
+    launch_net_pack_weights(net->w32, net->wf, net->wb, s);
+}
+
+}  // namespace
+
 void net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss, hipStream_t s) {
     dm_net *net = attached(op);
     ensure_scratch(op);
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     for (int it = 0; it < steps; ++it) {
         net_make_pair(op, seed + (uint64_t)it, op->ln_t1, op->ln_t2, s);
         const double L = net_loss_grad(op, kind, op->ln_t1, op->ln_t2, 0.0, s);
         if (loss) loss[it] = (float)L;
-        ++net->step;
-        const float c1 = 1.f - std::pow(b1, (float)net->step), c2 = 1.f - std::pow(b2, (float)net->step);
-        launch_net_adam(net->grad, net->w32, net->adam_m, net->adam_v, kNetWeights, lr, b1, b2, eps, c1, c2, s);
-        launch_net_pack_weights(net->w32, net->wf, net->wb, s);
+        adam_step(net, lr, s);
+    }
+    DM_HIP(hipGetLastError());
+    DM_HIP(hipStreamSynchronize(s));
+}
+
+void net_train_pairs(dm_op *op, int kind, int npairs, const double *const *r, const double *const *e, float lr,
+                     float *loss, hipStream_t s) {
+    dm_net *net = attached(op);
+    ensure_scratch(op);
+    for (int it = 0; it < npairs; ++it) {
+        const double L = net_loss_grad(op, kind, r[it], e ? e[it] : nullptr, 0.0, s);
+        if (loss) loss[it] = (float)L;
+        adam_step(net, lr, s);
     }
     DM_HIP(hipGetLastError());
     DM_HIP(hipStreamSynchronize(s));

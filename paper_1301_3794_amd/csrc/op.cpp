@@ -169,6 +169,7 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
     for (int l = 0; l < nl; ++l) {
         Level &L = op->lv[l];
         L.g = grids[l];
+        L.cut_wave_split = op->opt.cut_wave_split;
         const int64_t P = L.g.P;
         std::vector<double> c = to_coefs(L.g, op->frac[l]);
         std::vector<float> c32(c.begin(), c.end());

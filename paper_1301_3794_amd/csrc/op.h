@@ -46,9 +46,12 @@ struct Level {
     // the cut-cell list with the rows holding an active face: for outputs
     // that stay zero on the other rows (the block V-cycle's residual)
     ClassList cut_cells_rows() const { return ClassList{cutc, ncutc, frows, nfrows}; }
+    // the block smoother's threshold for one wave per vector (dm_options)
+    int64_t cut_wave_split = 32768;
     ClassList cut_list(int comp, int colour) const {
         const int q = 2 * comp + colour;
-        return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows};
+        return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows,
+                         cut_wave_split};
     }
 };
 
@@ -240,6 +243,8 @@ void net_apply(dm_op *op, const double *r, double scale, double *out, hipStream_
 double net_loss_grad(dm_op *op, int kind, const double *r, const double *e, double scale, hipStream_t s);
 void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s);
 void net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss, hipStream_t s);
+void net_train_pairs(dm_op *op, int kind, int npairs, const double *const *r, const double *const *e, float lr,
+                     float *loss, hipStream_t s);
 void net_correct(dm_op *op, const double *v, double *z, hipStream_t s);
 }  // namespace dm
 

@@ -260,13 +260,13 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
     return conv ? DM_OK : DM_NOT_CONVERGED;
 }
 
-int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_info *info,
-        hipStream_t s) {
-    ensure_krylov(op);
+// CG preconditioned by the FP64 V-cycle (direct launches, the op's level
+// buffers), with the work vectors r, z, p, q (n = 3P doubles each) given
+int pcg_work(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_info *info,
+             hipStream_t s, double *r, double *z, double *p, double *q) {
     const Level &L = op->lv[0];
     const int64_t n = op->n0();
-    double *r = op->fg_V, *z = op->fg_V + n, *p = op->fg_V + 2 * n, *q = op->fg_w;
-    DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    launch_zero<double>(n, x, s);
     const double bnorm = std::sqrt(dot1(op, f, f, op->wface, n, s));
     if (bnorm == 0.0) {
         if (info) *info = dm_solve_info{0, 0, 0.0, 0.0, 0, 0};
@@ -308,6 +308,13 @@ int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_
         info->rel_residual = rel;
     }
     return conv ? DM_OK : DM_NOT_CONVERGED;
+}
+
+int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_info *info,
+        hipStream_t s) {
+    ensure_krylov(op);
+    const int64_t n = op->n0();
+    return pcg_work(op, f, x, rtol, maxit, info, s, op->fg_V, op->fg_V + n, op->fg_V + 2 * n, op->fg_w);
 }
 
 }  // namespace
@@ -1241,10 +1248,19 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
     };
     // start block: random vectors, projected together where the block path
     // runs (the projections are independent), then A-orthonormalised
+    // A-norms of the start vectors before the projection: a vector that the
+    // projection and orthogonalisation reduce to rounding noise (zero, or
+    // gradients only) is a breakdown
+    std::vector<double> nrm0(b);
     for (int c = 0; c < b; ++c) {
         double *v = V + (size_t)c * n;
-        launch_randn(n, seed, (int64_t)c * n, op->fmask, v, s);
+        if (opt.start_dev) {   // caller's start block (warm start), active faces only
+            launch_copy_masked(n, opt.start_dev + (size_t)c * n, op->fmask, v, s);
+        } else {
+            launch_randn(n, seed, (int64_t)c * n, op->fmask, v, s);
+        }
         launch_mirror_faces<double>(L.g, v, s);
+        nrm0[c] = std::sqrt(dot1(op, v, v, a, n, s, vsp));
     }
     if (blocked) {
         for (int c0 = 0; c0 < b; c0 += kMaxRhs) {
@@ -1264,7 +1280,9 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
             proj_its += pj;
         }
         orth(V, c, v, nullptr);
-        if (!(A_normalize(v) > 0)) throw DmError{DM_EBREAKDOWN, "eigs: zero start vector"};
+        if (!(A_normalize(v) > 1e-10 * nrm0[c]) || !(nrm0[c] > 0.0))
+            throw DmError{DM_EBREAKDOWN, "eigs: start vector " + std::to_string(c) +
+                                             " is zero, or gradients only, or dependent on the others"};
         add_gk(c);
     }
     const int HR = m + b;  // rows of H
@@ -1362,9 +1380,23 @@ int eigs(dm_op *op, int k, double tol, uint64_t seed, const dm_eig_options &opt,
         for (int i = 0; i < mm; ++i)
             for (int j = 0; j < mm; ++j) Hs[(size_t)i * mm + j] = 0.5 * (Hat(i, j) + Hat(j, i));
         jacobi_eig(Hs, mm, theta, Y);
+        // restart order: the wanted pairs are the smallest lambda > 0, and
+        // theta = 1 / (lambda - sigma), so rank each Ritz value by its
+        // lambda = sigma + 1/theta, ascending over lambda > 0 (theta > 0 for
+        // lambda above the shift, theta < 0 below it), then the rest by
+        // |theta| descending.  With sigma below every wanted eigenvalue this
+        // is theta descending.
         std::vector<int> order(mm);
         for (int i = 0; i < mm; ++i) order[i] = i;
-        std::sort(order.begin(), order.end(), [&](int x, int y) { return theta[x] > theta[y]; });
+        const double sig_r = op->sigma;
+        auto lam_of = [&](int x) { return theta[x] != 0.0 ? sig_r + 1.0 / theta[x] : -1.0; };
+        std::sort(order.begin(), order.end(), [&](int x, int y) {
+            const double lx = lam_of(x), ly = lam_of(y);
+            const bool px = lx > 0.0, py = ly > 0.0;
+            if (px != py) return px;
+            if (px) return lx < ly;
+            return std::fabs(theta[x]) > std::fabs(theta[y]);
+        });
         // ---- Rayleigh--Ritz on (K, A) over the whole basis (answers): the
         // basis is A-orthonormal, so the projected pencil is (V^T K V, I)
         const int nb = cur;

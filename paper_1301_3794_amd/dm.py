@@ -65,7 +65,8 @@ class Geometry(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
-                ("fgmres_restart", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("fgmres_restart", ctypes.c_int), ("verbose", ctypes.c_int),
+                ("cut_wave_split", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -78,7 +79,7 @@ class EigOptions(ctypes.Structure):
     _fields_ = [("solve_mode", ctypes.c_int), ("inner_rtol", ctypes.c_double),
                 ("proj_rtol", ctypes.c_double), ("block", ctypes.c_int),
                 ("max_basis", ctypes.c_int), ("max_restarts", ctypes.c_int),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("start_dev", ctypes.c_void_p)]
 
 
 class BatchStats(ctypes.Structure):
@@ -151,6 +152,7 @@ def lib():
     L.dm_net_loss_grad.argtypes = [vp, i, vp, vp, d, dp, fp, vp]
     L.dm_net_make_pair.argtypes = [vp, ctypes.c_uint64, vp, vp, vp]
     L.dm_net_train.argtypes = [vp, i, i, ctypes.c_float, ctypes.c_uint64, fp, vp]
+    L.dm_net_train_pairs.argtypes = [vp, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_float, fp, vp]
     L.dm_batch_create.argtypes = [i, ctypes.POINTER(Geometry), ctypes.POINTER(ctypes.c_int), dp, d,
                                   ctypes.POINTER(Options), ctypes.POINTER(vp)]
     L.dm_batch_destroy.argtypes = [vp]
@@ -256,12 +258,14 @@ class Operator:
     """A built operator hierarchy (``dm_build_operator``)."""
 
     def __init__(self, geom: Geometry, dims, h, sigma, levels=0, nu_pre=2, nu_post=2,
-                 fgmres_restart=30, verbose=0):
+                 fgmres_restart=30, verbose=0, cut_wave_split=None):
         L = lib()
         opt = Options()
         L.dm_default_options(ctypes.byref(opt))
         opt.levels, opt.nu_pre, opt.nu_post = levels, nu_pre, nu_post
         opt.fgmres_restart, opt.verbose = fgmres_restart, verbose
+        if cut_wave_split is not None:
+            opt.cut_wave_split = int(cut_wave_split)
         self._op = ctypes.c_void_p()
         self._net = None
         self.dims = tuple(int(x) for x in dims)
@@ -403,12 +407,19 @@ class Operator:
 
     def eigs(self, k, sigma=None, tol=1e-10, seed=1301, vecs=None, solve_mode=SOLVE_FGMRES_MG64,
              inner_rtol=1e-11, proj_rtol=1e-13, block=4, max_basis=40, max_restarts=20,
-             verbose=0, stream=None):
+             verbose=0, stream=None, start=None):
+        """``start``: None, or a tensor of block face vectors (FP64, device)
+        used as the start block."""
         L = lib()
         o = EigOptions()
         L.dm_default_eig_options(ctypes.byref(o))
         o.solve_mode, o.inner_rtol, o.proj_rtol = solve_mode, inner_rtol, proj_rtol
         o.block, o.max_basis, o.max_restarts, o.verbose = block, max_basis, max_restarts, verbose
+        if start is not None:
+            if start.dtype.is_floating_point is False or start.element_size() != 8 or \
+                    start.numel() != block * 3 * self.layout(0)["P"]:
+                raise ValueError("start block: block x 3P float64 values")
+            o.start_dev = start.data_ptr()
         lam = np.zeros(k)
         res = np.zeros(k)
         info = EigInfo()
@@ -493,6 +504,17 @@ def net_train(op: "Operator", steps, lr=1e-3, seed=0, kind=NET_LOSS_RESIDUAL, st
     _check(lib().dm_net_train(op._op, int(kind), int(steps), ctypes.c_float(lr), ctypes.c_uint64(seed),
                               loss.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
     return loss[:steps]
+
+
+def net_train_pairs(op: "Operator", rs, es=None, lr=1e-3, kind=NET_LOSS_RESIDUAL, stream=None) -> np.ndarray:
+    """One Adam step per given pair (r, e): device face vectors (float64)."""
+    n = len(rs)
+    loss = np.zeros(max(1, n), dtype=np.float32)
+    rp = (ctypes.c_void_p * max(1, n))(*[r.data_ptr() for r in rs])
+    ep = (ctypes.c_void_p * max(1, n))(*[e.data_ptr() for e in es]) if es is not None else None
+    _check(lib().dm_net_train_pairs(op._op, int(kind), n, rp, ep, ctypes.c_float(lr),
+                                    loss.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)))
+    return loss[:n]
 
 
 # ---------------------------------------------------------------------------

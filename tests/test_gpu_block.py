@@ -18,6 +18,10 @@ coefficient once for all vectors.  Checked through the C ABI:
   * the eigensolver (which takes the block path for block size 4) still
     matches the oracle's eigenvalues to 1e-10;
   * restarts of FGMRES(4) inside the lockstep, as dm_solve takes them;
+  * both forms of the block smoother's cut-row part (one wavefront per
+    vector, and one thread per row looping over the vectors, which the
+    full-size grids take) against the oracle's V-cycle, by forcing the loop
+    with the operator option cut_wave_split = 0;
   * argument errors: 5 vectors, the PCG mode.
 """
 import numpy as np
@@ -78,6 +82,27 @@ def test_vcycle_block(case, prec, nr):
         assert rel_inf(got, vc(fs[q])) <= (1e-12 if prec == 64 else 5e-5), q
         one = op.vcycle(fd[q], op.face_tensor(dtype=dt))
         assert rel_inf(got, lay.faces_from_padded(one.double().cpu().numpy(), n)) <= (1e-14 if prec == 64 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("nr", [2, 3, 4])
+def test_vcycle_block_row_loop(case, prec, nr):
+    """The block smoother's cut rows by one thread per row looping over the
+    vectors (forced: cut_wave_split = 0), the path the 128^3 and 96 x 96 x
+    1024 grids take on their finest levels."""
+    dm, vc, n, oop = case["dm"], case["vc"], case["n"], case["oop"]
+    dt = torch.float64 if prec == 64 else torch.float32
+    with dm.Operator(dm.user_fractions(lay.fractions_to_padded(case["fr"], n)), n, case["h"], case["sigma"],
+                     levels=case["levels"], cut_wave_split=0) as op:
+        fs = [rnd(oop.act, oop.grid.n_faces, 80 + q) for q in range(nr)]
+        fd = [dev(lay.faces_to_padded(f, n), dt) for f in fs]
+        xs = op.vcycle_block(fd, [op.face_tensor(dtype=dt) for _ in range(nr)])
+        for q in range(nr):
+            got = lay.faces_from_padded(xs[q].double().cpu().numpy(), n)
+            assert rel_inf(got, vc(fs[q])) <= (1e-12 if prec == 64 else 5e-5), q
+            one = op.vcycle(fd[q], op.face_tensor(dtype=dt))
+            assert rel_inf(got, lay.faces_from_padded(one.double().cpu().numpy(), n)) <= \
+                (1e-14 if prec == 64 else 1e-6)
 
 
 @pytest.mark.parametrize("mode", ["fgmres64", "fgmres32"])
@@ -174,15 +199,16 @@ def test_block_pmc_vcycle():
     ext = sym.MirrorExtension(NH, H, (0, 1))
     vc = sym.HalfVCycle(fr_full, NH, H, SIGMA, (0, 1), 3)
     fr7 = lay.fractions_to_padded(ext.half_fractions(fr_full), NH)
-    with dm.Operator(dm.user_fractions(fr7, bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC)), NH, H, SIGMA,
-                     levels=3) as op:
-        hop = vc.levels[0].op
-        for prec, dt, tol in ((64, torch.float64, 1e-12), (32, torch.float32, 5e-5)):
-            fs = [rnd(hop.act, hop.grid.n_faces, 60 + q) for q in range(3)]
-            xs = op.vcycle_block([dev(lay.faces_to_padded(f, NH), dt) for f in fs],
-                                 [op.face_tensor(dtype=dt) for _ in range(3)])
-            for q in range(3):
-                assert rel_inf(lay.faces_from_padded(xs[q].double().cpu().numpy(), NH), vc(fs[q])) <= tol
+    for split in (32768, 0):    # cut rows: one wavefront per vector / one thread per row
+        with dm.Operator(dm.user_fractions(fr7, bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC)), NH, H, SIGMA,
+                         levels=3, cut_wave_split=split) as op:
+            hop = vc.levels[0].op
+            for prec, dt, tol in ((64, torch.float64, 1e-12), (32, torch.float32, 5e-5)):
+                fs = [rnd(hop.act, hop.grid.n_faces, 60 + q) for q in range(3)]
+                xs = op.vcycle_block([dev(lay.faces_to_padded(f, NH), dt) for f in fs],
+                                     [op.face_tensor(dtype=dt) for _ in range(3)])
+                for q in range(3):
+                    assert rel_inf(lay.faces_from_padded(xs[q].double().cpu().numpy(), NH), vc(fs[q])) <= tol
 
 
 def test_time_block_kernel(case):

@@ -1,0 +1,192 @@
+"""Failure detection through the C ABI: every documented error code is driven
+by a real input and ends in a normal return (no kernel is made to fault).
+
+* DM_ENAN: a right-hand side with a NaN on an active face, for dm_solve (all
+  modes), dm_solve_block and dm_project; the operator stays usable and the
+  next solve matches a sparse direct solve of the oracle's M.
+* DM_ESINGULAR: a shift equal to an eigenvalue of the coarsest operator.  On
+  the PEC unit box the coarse operator is three decoupled 7-point
+  Laplacians (vacuum: the grad-div term turns the curl-curl into the vector
+  Laplacian, Sec. 4.2 eq. discLaplB), whose lowest eigenvalue on 4^3 cells
+  of size 1/4 is (2 sin(pi/8) / (1/4))^2 = 64 sin^2(pi/8); build and
+  dm_set_shift both refuse it and the op keeps its old shift.
+* DM_NOT_CONVERGED: maxit = 2 at rtol 1e-13 returns the warning, 2
+  iterations, and the best iterate, whose residual the oracle recomputes.
+* DM_EBREAKDOWN: an eigensolve started from a zero block, and from a block
+  of pure gradients D^T psi (removed by the projection P_DM, eq. proj).
+* The warm start: started from the oracle's own eigenvectors the eigensolve
+  converges in its first outer step.
+* A shift above the lowest eigenvalues (Sec. 4.1: the shift sits near the
+  wanted modes): sigma = 50 on the 16^3 sphere, between the TM11 triplet
+  (~37) and TM21 (~74); the 4 smallest eigenvalues still match the oracle.
+* An eigensolve out of restarts returns DM_NOT_CONVERGED with the pairs it
+  has.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+
+from oracle import eigs as oeigs, geometry as geo, operators as ops
+import layout as lay
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 16
+H = 1.0 / N
+SHAPE = (N, N, N)
+
+
+@pytest.fixture(scope="module")
+def small():
+    from paper_1301_3794_amd import dm
+    fr = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), SHAPE, H)
+    oop = ops.build(fr, SHAPE, H, 5.0)
+    op = dm.Operator(dm.sphere((0.5, 0.5, 0.5), 0.45), SHAPE, H, 5.0, levels=3)
+    print("[case] errors: sphere 16^3", flush=True)
+    yield dm, op, oop
+    op.close()
+
+
+def rhs(oop, seed):
+    f = np.zeros(oop.grid.n_faces)
+    f[oop.act] = np.random.default_rng(seed).standard_normal(oop.act.size)
+    return f
+
+
+def dev(x):
+    return torch.tensor(lay.faces_to_padded(x, SHAPE), dtype=torch.float64, device="cuda")
+
+
+def check_solution(oop, f, x_dev, tol):
+    x = lay.faces_from_padded(x_dev.cpu().numpy(), SHAPE)
+    ref = sla.spsolve(oop.M_a.tocsc(), f[oop.act])
+    assert np.max(abs(x[oop.act] - ref)) <= tol * np.max(abs(ref))
+
+
+@pytest.mark.parametrize("mode", ["pcg64", "fgmres64", "fgmres32"])
+def test_nan_rhs(small, mode):
+    dm, op, oop = small
+    m = {"pcg64": dm.SOLVE_PCG64, "fgmres64": dm.SOLVE_FGMRES_MG64, "fgmres32": dm.SOLVE_FGMRES_MG32}[mode]
+    f = rhs(oop, 1)
+    bad = f.copy()
+    bad[oop.act[oop.act.size // 2]] = np.nan
+    with pytest.raises(dm.DMError) as e:
+        op.solve(dev(bad), op.face_tensor(), mode=m, rtol=1e-10, maxit=200)
+    assert e.value.code == dm.DM_ENAN
+    # the op is still usable
+    x = op.face_tensor()
+    out = op.solve(dev(f), x, mode=m, rtol=1e-11, maxit=300)
+    assert out["status"] == 0
+    check_solution(oop, f, x, 1e-9)
+
+
+def test_nan_rhs_block_and_projection(small):
+    dm, op, oop = small
+    fs = [rhs(oop, 2 + q) for q in range(3)]
+    fs[1][oop.act[7]] = np.inf
+    with pytest.raises(dm.DMError) as e:
+        op.solve_block([dev(f) for f in fs], [op.face_tensor() for _ in range(3)], mode=dm.SOLVE_FGMRES_MG32,
+                       rtol=1e-10, maxit=200)
+    assert e.value.code == dm.DM_ENAN
+    with pytest.raises(dm.DMError) as e:
+        op.project(dev(fs[1]), op.face_tensor())
+    assert e.value.code == dm.DM_ENAN
+    x = op.face_tensor()
+    assert op.solve(dev(fs[0]), x, mode=dm.SOLVE_FGMRES_MG32, rtol=1e-11, maxit=300)["status"] == 0
+    check_solution(oop, fs[0], x, 1e-9)
+
+
+def test_singular_shift():
+    from paper_1301_3794_amd import dm
+    lam_c = 64.0 * math.sin(math.pi / 8) ** 2     # lowest eigenvalue of the 4^3 coarse box
+    with pytest.raises(dm.DMError) as e:
+        dm.Operator(dm.box(), (8, 8, 8), 1.0 / 8, lam_c, levels=2)
+    assert e.value.code == dm.DM_ESINGULAR
+    # a shift beside it is fine; moving onto it is refused and changes nothing
+    fr = geo.fractions(geo.Box(), (8, 8, 8), 1.0 / 8)
+    oop = ops.build(fr, (8, 8, 8), 1.0 / 8, 5.0)
+    with dm.Operator(dm.box(), (8, 8, 8), 1.0 / 8, 5.0, levels=2) as op:
+        with pytest.raises(dm.DMError) as e:
+            op.set_shift(lam_c)
+        assert e.value.code == dm.DM_ESINGULAR
+        f = np.zeros(oop.grid.n_faces)
+        f[oop.act] = np.random.default_rng(9).standard_normal(oop.act.size)
+        x = torch.zeros(3 * op.layout(0)["P"], dtype=torch.float64, device="cuda")
+        fd = torch.tensor(lay.faces_to_padded(f, (8, 8, 8)), device="cuda")
+        assert op.solve(fd, x, mode=dm.SOLVE_FGMRES_MG64, rtol=1e-11, maxit=200)["status"] == 0
+        got = lay.faces_from_padded(x.cpu().numpy(), (8, 8, 8))[oop.act]
+        ref = sla.spsolve(oop.M_a.tocsc(), f[oop.act])
+        assert np.max(abs(got - ref)) <= 1e-9 * np.max(abs(ref))
+
+
+@pytest.mark.parametrize("mode", ["pcg64", "fgmres64"])
+def test_not_converged_returns_best_iterate(small, mode):
+    dm, op, oop = small
+    m = dm.SOLVE_PCG64 if mode == "pcg64" else dm.SOLVE_FGMRES_MG64
+    f = rhs(oop, 4)
+    x = op.face_tensor()
+    out = op.solve(dev(f), x, mode=m, rtol=1e-13, maxit=2)
+    assert out["status"] == dm.DM_NOT_CONVERGED
+    assert out["iterations"] == 2
+    xa = lay.faces_from_padded(x.cpu().numpy(), SHAPE)[oop.act]
+    r = f[oop.act] - oop.M_a @ xa
+    rel = np.linalg.norm(r) / np.linalg.norm(f[oop.act])
+    assert 1e-13 < rel < 1.0
+    assert abs(rel - out["rel_residual"]) <= 1e-9 * rel
+
+
+def test_breakdown_zero_and_gradient_start(small):
+    dm, op, oop = small
+    P = op.layout(0)["P"]
+    zero = torch.zeros(4 * 3 * P, dtype=torch.float64, device="cuda")
+    with pytest.raises(dm.DMError) as e:
+        op.eigs(4, tol=1e-10, block=4, start=zero)
+    assert e.value.code == dm.DM_EBREAKDOWN
+    # gradients D^T psi of random cell values: P_DM removes them entirely
+    rng = np.random.default_rng(5)
+    grads = []
+    for _ in range(4):
+        psi = np.zeros(oop.grid.n_cells)
+        psi[oop.cact] = rng.standard_normal(oop.cact.size)
+        g = oop.D.T @ psi
+        g[oop.a == 0] = 0.0
+        grads.append(lay.faces_to_padded(g, SHAPE))
+    start = torch.tensor(np.concatenate(grads), device="cuda")
+    with pytest.raises(dm.DMError) as e:
+        op.eigs(4, tol=1e-10, block=4, start=start)
+    assert e.value.code == dm.DM_EBREAKDOWN
+    # the op is still usable
+    assert op.eigs(4, tol=1e-10, block=4)["status"] == 0
+
+
+def test_warm_start_from_oracle_vectors(small):
+    dm, op, oop = small
+    lam, B, _ = oeigs.lanczos_eigs(oop, 4, sigma_o=5.0, block=4, tol=1e-12)
+    start = np.concatenate([lay.faces_to_padded(oop.full_face(B[:, c]), SHAPE) for c in range(4)])
+    out = op.eigs(4, tol=1e-10, block=4, start=torch.tensor(start, device="cuda"))
+    assert out["status"] == 0
+    assert out["outer_iterations"] == 1
+    assert np.max(abs(out["lam"] - lam) / lam) <= 1e-10
+
+
+@pytest.mark.parametrize("mode", ["fgmres64", "fgmres32"])
+def test_shift_above_lowest_eigenvalues(small, mode):
+    dm, op, oop = small
+    m = dm.SOLVE_FGMRES_MG64 if mode == "fgmres64" else dm.SOLVE_FGMRES_MG32
+    lam_ref = oeigs.lanczos_eigs(oop, 6, sigma_o=5.0, block=4, tol=1e-12)[0]
+    assert lam_ref[2] < 50.0 < lam_ref[3]
+    with dm.Operator(dm.sphere((0.5, 0.5, 0.5), 0.45), SHAPE, H, 50.0, levels=3) as op50:
+        out = op50.eigs(6, sigma=50.0, tol=1e-10, block=4, solve_mode=m, max_restarts=40)
+    assert out["status"] == 0, out
+    assert np.max(abs(out["lam"] - lam_ref) / lam_ref) <= 1e-10
+
+
+def test_eigs_out_of_restarts(small):
+    dm, op, oop = small
+    out = op.eigs(4, tol=1e-10, block=2, max_basis=6, max_restarts=0)
+    assert out["status"] == dm.DM_NOT_CONVERGED
+    assert out["n_converged"] < 4
+    assert out["lam"].shape == (4,) and np.all(np.isfinite(out["lam"]))

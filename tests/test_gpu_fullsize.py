@@ -17,8 +17,13 @@ the two: a 1e-13 difference in a small cell's volume is amplified by 1/v.
 Shifting the body instead of the cells changes the rounding of the
 coordinates, which moves a fraction by ~1e-12 where r'(z) is large.)
 
-A property at full size: the FP64 V-cycle operator is symmetric,
-<u, B v> = <v, B u> to 1e-12.
+Properties at full size: the FP64 V-cycle operator is symmetric,
+<u, B v> = <v, B u> to 1e-12; the block V-cycle on the benchmarks' block
+sizes (3 vectors on the sphere, 2 on the 9-cell quarter) equals the
+single-vector V-cycle on every vector (FP64 1e-14, FP32 1e-6).  At these
+sizes the finest level's lists of non-vacuum rows exceed the block
+smoother's wave split, so this covers its one-thread-per-row path (the
+small grids of the block tests reach it only when it is forced).
 """
 import numpy as np
 import pytest
@@ -170,6 +175,26 @@ def test_sphere128_vcycle_symmetric(sphere128):
     assert abs(u - v) <= 1e-12 * max(abs(u), abs(v))
 
 
+def block_equals_single(op, nr, prec, seed):
+    P = op.layout(0)["P"]
+    dt = torch.float64 if prec == 64 else torch.float32
+    gen = torch.Generator().manual_seed(seed)
+    mask = torch.tensor(op.fractions(0)[:3].reshape(-1) > 0)
+    fs = [(torch.randn(3 * P, dtype=torch.float64, generator=gen) * mask).to(dt).cuda() for _ in range(nr)]
+    xs = op.vcycle_block(fs, [op.face_tensor(dtype=dt) for _ in range(nr)])
+    worst = 0.0
+    for q in range(nr):
+        one = op.vcycle(fs[q], op.face_tensor(dtype=dt))
+        worst = max(worst, float((xs[q] - one).abs().max() / one.abs().max()))
+    return worst
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_sphere128_vcycle_block_equals_single(sphere128, prec):
+    dm, op, n, h, _ = sphere128
+    assert block_equals_single(op, 3, prec, 5) <= (1e-14 if prec == 64 else 1e-6)
+
+
 @pytest.fixture(scope="module")
 def ninecell():
     from paper_1301_3794_amd import dm
@@ -204,6 +229,11 @@ def test_ninecell_apply_rows(ninecell):
     fr7 = op.fractions(0)
     assert fraction_gap(wins, g, fr7, h, n) <= 1e-12
     assert compare(wins, fr7, h, 632.0, x, y, n) <= 1e-12
+
+
+def test_ninecell_vcycle_block_equals_single(ninecell):
+    dm, op, n, h, _ = ninecell
+    assert block_equals_single(op, 2, 32, 6) <= 1e-6
 
 
 def test_empty_geometry_is_rejected():

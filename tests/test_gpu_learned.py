@@ -7,7 +7,10 @@ compared with ``oracle.learned`` rounding to bfloat16 at the same points:
   * forward correction: max error <= 2e-3 of the largest value;
   * a training pair from the solver satisfies M e = r to 1e-11;
   * error and residual losses to 1e-4, their weight gradients to 2e-3
-    (relative 2-norm), the residual loss with the oracle's sparse M;
+    (relative 2-norm), the residual loss with the oracle's sparse M, on
+    seeded N(0,1) pairs (r, e) on the active faces;
+  * two Adam steps (dm_net_train_pairs) against the oracle's Adam step
+    (Kingma & Ba) applied to the oracle's own gradients, weight by weight;
   * Adam training lowers the loss; the learned solve mode converges and
     its eigenvalues match the oracle's to 1e-9.
 """
@@ -86,15 +89,23 @@ def case_fr_block(case, c):
 
 @pytest.fixture(scope="module")
 def pair(case):
+    """A seeded pair (r, e): N(0,1) on the active faces (the losses and
+    gradients are defined for any pair)."""
+    return seeded_face_vector(case, 7), seeded_face_vector(case, 8)
+
+
+def seeded_face_vector(case, seed):
+    P = case["op"].layout(0)["P"]
+    act = np.concatenate([case_fr_block(case, c) for c in range(3)]) > 0
+    x = np.zeros(3 * P)
+    x[act] = np.random.default_rng(seed).standard_normal(act.sum())
+    return torch.tensor(x, device="cuda")
+
+
+def test_pair_satisfies_M_e_equals_r(case):
     dm, op = case["dm"], case["op"]
     r, e = op.face_tensor(), op.face_tensor()
     dm.net_make_pair(op, 7, r, e)
-    return r, e
-
-
-def test_pair_satisfies_M_e_equals_r(case, pair):
-    dm, op = case["dm"], case["op"]
-    r, e = pair
     me = op.apply(dm.APPLY_M, e, op.face_tensor())
     rel = float((me - r).norm() / r.norm())
     assert rel <= 1e-11 and float(e.norm()) > 0
@@ -120,6 +131,16 @@ def test_residual_loss_and_gradient_match_oracle(case, pair):
     rc = cells(r.cpu().numpy(), N, 3)
     s = rms(rc, case["mask"])
     L, g = dm.net_loss_grad(op, r, None, scale=s, kind=dm.NET_LOSS_RESIDUAL)
+    M = cell_operator(case)
+    x0 = np.concatenate([rc / s, case["stat"]], axis=-1)
+    L_ref, g_ref = ln.residual_loss_and_grad(case["w"], x0, rc, M, case["mask"], s * H * H, bf16_round=True)
+    print("residual loss", L, L_ref, "grad rel", np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
+    assert L == pytest.approx(L_ref, rel=1e-4)
+    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) <= 2e-3
+
+
+def cell_operator(case):
+    """The oracle's sparse M acting on per-cell channel arrays (nz, ny, nx, 3)."""
     o = ops.build(case["fr"], N, H, SIGMA)
     nx, ny, nz = N
 
@@ -131,12 +152,46 @@ def test_residual_loss_and_gradient_match_oracle(case, pair):
         fam["az"][:nz] = d[..., 2]
         ax, ay, az = o.grid.split_faces(o.M @ o.grid.face_vector(fam))
         return np.stack([ax[:, :, :nx], ay[:, :ny, :], az[:nz]], axis=-1)
+    return M
 
-    x0 = np.concatenate([rc / s, case["stat"]], axis=-1)
-    L_ref, g_ref = ln.residual_loss_and_grad(case["w"], x0, rc, M, case["mask"], s * H * H, bf16_round=True)
-    print("residual loss", L, L_ref, "grad rel", np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref))
-    assert L == pytest.approx(L_ref, rel=1e-4)
-    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) <= 2e-3
+
+def test_adam_steps_match_oracle(case):
+    """Two Adam steps on two seeded pairs (residual loss) from seeded
+    weights: the device's FP32 master weights against the oracle's Adam step
+    on the oracle's own gradients.  Step 1 moves each weight by lr sign(g),
+    so the bar applies where the gradients are well above the device/oracle
+    gradient difference (|g| >= 5e-2 of their RMS in both steps, at least
+    90% of the weights): |w_dev - w_ref| <= 5e-2 lr; every weight stays
+    within 8 lr."""
+    dm, op, net = case["dm"], case["op"], case["net"]
+    lr = 1e-3
+    w0 = (np.random.default_rng(21).standard_normal(ln.N_WEIGHTS) * 0.15).astype(np.float32)
+    net.set_weights(w0)                     # also resets the Adam state
+    rs = [seeded_face_vector(case, 31), seeded_face_vector(case, 32)]
+    try:
+        loss = dm.net_train_pairs(op, rs, lr=lr, kind=dm.NET_LOSS_RESIDUAL)
+        w_dev = net.weights().astype(np.float64)
+    finally:
+        net.set_weights(case["w"].astype(np.float32))
+    M = cell_operator(case)
+    w, m, v = w0.astype(np.float64), np.zeros(ln.N_WEIGHTS), np.zeros(ln.N_WEIGHTS)
+    grads = []
+    for step, r in enumerate(rs, 1):
+        rc = cells(r.cpu().numpy(), N, 3)
+        s = rms(rc, case["mask"])
+        x0 = np.concatenate([rc / s, case["stat"]], axis=-1)
+        L_ref, g = ln.residual_loss_and_grad(w, x0, rc, M, case["mask"], s * H * H, bf16_round=True)
+        assert loss[step - 1] == pytest.approx(L_ref, rel=1e-4)
+        grads.append(g)
+        w, m, v = ln.adam(w, g, m, v, step, lr)
+    good = np.ones(ln.N_WEIGHTS, bool)
+    for g in grads:
+        good &= np.abs(g) >= 5e-2 * np.sqrt(np.mean(g * g))
+    d = np.abs(w_dev - w)
+    print("adam: well-conditioned fraction", good.mean(), "max dev there / lr", d[good].max() / lr)
+    assert good.mean() >= 0.9
+    assert d[good].max() <= 5e-2 * lr
+    assert d.max() <= 8 * lr
 
 
 def test_training_lowers_the_loss(case):

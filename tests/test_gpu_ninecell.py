@@ -1,0 +1,51 @@
+"""Eigenvalues of the 9-cell quarter cavity against stored oracle values.
+
+The 96 x 96 x 1024 workload's cavity (Sec. 6.3 quarter with perfect
+magnetic conductor planes x = 0 and y = 0; 9 elliptic cells, cusp irises,
+tubes) at coarser resolutions that the oracle solves on the CPU:
+24 x 24 x 256 (h = 1.235/256) and, when its file exists, 48 x 48 x 512.
+``tests/golden/make_ninecell_quarter.py`` (oracle only: full mirrored
+cavity, symmetric half pencil, block Lanczos) wrote the 9 smallest
+eigenvalues; the library computes its own fractions and runs the workload's
+eigensolver settings (shift 632, block 2, basis 48, FGMRES(30), 4 + 4
+sweeps).  Bars: 1e-10 relative for the FP64 form, 1e-9 for the
+FP32-multigrid form (the spec bars), and every returned rho <= 1e-10.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def golden(nz):
+    path = os.path.join(HERE, "golden", f"ninecell_quarter_{nz}_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle values for nz={nz}")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("nz,mode", [(256, "fgmres64"), (256, "fgmres32"), (512, "fgmres32")])
+def test_ninecell_quarter_eigenvalues(nz, mode):
+    from paper_1301_3794_amd import dm
+    ref = golden(nz)
+    nxy = ref["grid"][0]
+    h = 1.235 / nz
+    m = dm.SOLVE_FGMRES_MG64 if mode == "fgmres64" else dm.SOLVE_FGMRES_MG32
+    print(f"[case] 9-cell quarter {nxy}x{nxy}x{nz} {mode}", flush=True)
+    geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1, bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
+    with dm.Operator(geom, (nxy, nxy, nz), h, 632.0, levels=0, fgmres_restart=30, nu_pre=4, nu_post=4) as op:
+        assert op.layout(0)["active_faces"] == ref["active_faces"]
+        out = op.eigs(9, sigma=632.0, tol=1e-10, seed=3, solve_mode=m, block=2, max_basis=48, max_restarts=30)
+    assert out["status"] == 0, out
+    lam_ref = np.array(ref["lam"])
+    err = np.max(abs(out["lam"] - lam_ref) / lam_ref)
+    print(f"[result] max rel err {err:.2e} outer {out['outer_iterations']} inner {out['inner_iterations']}",
+          flush=True)
+    assert err <= (1e-10 if mode == "fgmres64" else 1e-9)
+    assert np.max(out["residuals"]) <= 1e-10

@@ -117,3 +117,26 @@ def test_eig_residual_definition():
     w, V = eigs.dense_eigs(op, 2)
     assert eigs.eig_residual(op, w[0], 3.7 * V[:, 0]) < 1e-12
     assert eigs.eig_residual(op, w[0] * (1 + 1e-6), V[:, 0]) == pytest.approx(1e-6 / (1 + 1e-6), rel=1e-6)
+
+
+def test_div_residual_known_values():
+    """||V^-1/2 D A b|| / ||b||_A (Sec. 5.1) on the PEC box, where a = v = 1:
+    for b = D^T psi with psi a Neumann eigenvector of the cell Laplacian,
+    psi = prod cos(pi m_a (i_a + 1/2) / N), D D^T psi = mu psi with
+    mu = sum (2 sin(pi m_a / 2N) / h)^2, so the value is sqrt(mu); for a
+    curl b = C e it is zero (D C = 0)."""
+    n, h = (6, 5, 4), 0.2
+    fr = geo.fractions(geo.Box(), n, h)
+    op = ops.build(fr, n, h, 0.0)
+    g = op.grid
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    for m in ((1, 0, 0), (0, 2, 1), (3, 1, 2)):
+        psi = (np.cos(math.pi * m[0] * (i + 0.5) / n[0]) * np.cos(math.pi * m[1] * (j + 0.5) / n[1])
+               * np.cos(math.pi * m[2] * (k + 0.5) / n[2])).ravel()
+        mu = sum((2.0 * math.sin(math.pi * m[a] / (2 * n[a])) / h) ** 2 for a in range(3))
+        b = (op.D.T @ psi)[op.act]
+        assert eigs.div_residual(op, b) == pytest.approx(math.sqrt(mu), rel=1e-12)
+    # tangential e vanishes on the conducting walls (l = 0 there)
+    e = np.random.default_rng(0).standard_normal(g.n_edges) * (op.l > 0)
+    b = (op.Ct.T @ e)[op.act]
+    assert eigs.div_residual(op, b) <= 1e-13 / h

@@ -89,3 +89,44 @@ def test_residual_loss_gradient_matches_finite_differences():
         fd = (ln.residual_loss_and_grad(wp, x0, r, M, m, c)[0]
               - ln.residual_loss_and_grad(wm, x0, r, M, m, c)[0]) / (2 * eps)
         assert g[idx] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_adam_closed_forms():
+    """Adam (Kingma & Ba, Algorithm 1) in closed form, not by retyping it:
+    * step 1: the bias-corrected moments are g and g^2, so the step is
+      lr g / (|g| + eps) -> lr sign(g) as eps -> 0, whatever b1, b2;
+    * a constant gradient keeps m_hat = g and v_hat = g^2 at every step
+      (bias correction is exact), so every step is the same;
+    * gradients g then -g: m_hat_2 = -g (1 - b1) / (1 + b1), v_hat_2 = g^2,
+      so the second step is -lr sign(g) (1 - b1) / (1 + b1);
+    * with eps = 0 the update is invariant to scaling all gradients by c > 0.
+    A missing bias correction, a swapped b1/b2 or a wrong square root fails
+    one of these."""
+    rng = np.random.default_rng(0)
+    g = rng.standard_normal(50) * np.logspace(-3, 3, 50)
+    w0 = rng.standard_normal(50)
+    z = np.zeros(50)
+    lr = 1e-3
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.9)):
+        w1, m1, v1 = ln.adam(w0, g, z, z, 1, lr, b1, b2, eps=0.0)
+        assert np.allclose(w0 - w1, lr * np.sign(g), rtol=1e-12, atol=0)
+        # constant gradient: the same step every time
+        w, m, v = w0, z, z
+        for step in range(1, 6):
+            w_new, m, v = ln.adam(w, g, m, v, step, lr, b1, b2, eps=0.0)
+            assert np.allclose(w - w_new, lr * np.sign(g), rtol=1e-10, atol=0)
+            w = w_new
+        # g then -g
+        w1, m1, v1 = ln.adam(w0, g, z, z, 1, lr, b1, b2, eps=0.0)
+        w2, _, _ = ln.adam(w1, -g, m1, v1, 2, lr, b1, b2, eps=0.0)
+        assert np.allclose(w2 - w1, lr * np.sign(g) * (1 - b1) / (1 + b1), rtol=1e-10, atol=0)
+        # scale invariance
+        wa, ma, va = ln.adam(w0, g, z, z, 1, lr, b1, b2, eps=0.0)
+        wb, mb, vb = ln.adam(w0, 37.0 * g, z, z, 1, lr, b1, b2, eps=0.0)
+        g2 = rng.standard_normal(50)
+        wa2, _, _ = ln.adam(wa, g2, ma, va, 2, lr, b1, b2, eps=0.0)
+        wb2, _, _ = ln.adam(wb, 37.0 * g2, mb, vb, 2, lr, b1, b2, eps=0.0)
+        assert np.allclose(wa2, wb2, rtol=1e-12, atol=1e-15)
+    # eps enters only beside sqrt(v_hat): a tiny gradient moves by lr g / eps
+    w1, _, _ = ln.adam(w0, 1e-12 * np.ones(50), z, z, 1, lr, eps=1e-8)
+    assert np.allclose(w0 - w1, lr * 1e-12 / (1e-12 + 1e-8), rtol=1e-10)
