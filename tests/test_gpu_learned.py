@@ -160,9 +160,9 @@ def test_adam_steps_match_oracle(case):
     weights: the device's FP32 master weights against the oracle's Adam step
     on the oracle's own gradients.  Step 1 moves each weight by lr sign(g),
     so the bar applies where the gradients are well above the device/oracle
-    gradient difference (|g| >= 5e-2 of their RMS in both steps, at least
-    90% of the weights): |w_dev - w_ref| <= 5e-2 lr; every weight stays
-    within 8 lr."""
+    gradient difference (|g| >= 5e-2 of their RMS in both steps; the
+    gradients are heavy-tailed, so that is about two thirds of the
+    weights): |w_dev - w_ref| <= 1e-2 lr; every weight stays within 8 lr."""
     dm, op, net = case["dm"], case["op"], case["net"]
     lr = 1e-3
     w0 = (np.random.default_rng(21).standard_normal(ln.N_WEIGHTS) * 0.15).astype(np.float32)
@@ -189,8 +189,8 @@ def test_adam_steps_match_oracle(case):
         good &= np.abs(g) >= 5e-2 * np.sqrt(np.mean(g * g))
     d = np.abs(w_dev - w)
     print("adam: well-conditioned fraction", good.mean(), "max dev there / lr", d[good].max() / lr)
-    assert good.mean() >= 0.9
-    assert d[good].max() <= 5e-2 * lr
+    assert good.mean() >= 0.6
+    assert d[good].max() <= 1e-2 * lr
     assert d.max() <= 8 * lr
 
 
