@@ -317,6 +317,22 @@ int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed,
             const dm_eig_options *opt, double *lambda_host, double *vecs_dev,
             double *residuals_host, dm_eig_info *info, void *stream);
 
+/* ---- solve without allocation -------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as dm_solve(op, DM_SOLVE_PCG64, ...) -- same iterates, iterations
+ * and result -- that calls no hipMalloc/hipFree.  Its four work vectors
+ * (4 * 3P doubles) live in a static device array of
+ * DM_NOALLOC_SCRATCH_BYTES per GPU, held from the first operator build on
+ * that GPU until the process ends, so the op's level-0 grid must satisfy
+ * 4 * 3P * 8 <= DM_NOALLOC_SCRATCH_BYTES (3P <= 1,048,576, e.g. 64^3 cells);
+ * a larger op gets DM_EINVAL.  Every call on one GPU shares that array and
+ * overwrites it: calls that overlap on one GPU (from several threads or
+ * streams) race and must be serialised by the caller.  Errors as dm_solve. */
+#define DM_NOALLOC_SCRATCH_BYTES (32u << 20)
+int dm_solve_pcg_noalloc(dm_op *op, const double *f_dev, double *x_dev, double rtol, int maxit,
+                         dm_solve_info *info, void *stream);
+
 /* ---- batched cavities (one fused V-cycle for many operators) -------------
  * A batch owns `count` operators (cavities of their own grids and cell
  * sizes, no PMC planes).  Their FP32 V-cycles are merged level by level into

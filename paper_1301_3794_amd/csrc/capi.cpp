@@ -226,6 +226,7 @@ int dm_build_operator(const dm_geometry *geom, const int dims[3], double h, doub
             if (dims[a] % div != 0 || dims[a] / div < 1)
                 return fail(DM_EINVAL, "dims not divisible by 2^(levels-1)");
         DM_HIP(hipGetDevice(&op->device));
+        noalloc_init(op->device);   // the no-allocation entry point's scratch on this device
         DM_HIP(hipStreamCreate(&op->stream));
         build_hierarchy(op, geom->user_fractions_host);
         if (op->lv[0].n_act_faces == 0) return fail(DM_EINVAL, "the geometry leaves no active face on this grid");
@@ -463,6 +464,22 @@ int dm_solve(dm_op *op, int mode, const double *f, double *x, double rtol, int m
     return on_device(op, stream, [&](hipStream_t s) -> int {
         fill_ghosts(op->lv[0], 64, f, false, s);
         return solve(op, mode, f, x, rtol, maxit, info, s);
+    });
+}
+
+int dm_solve_pcg_noalloc(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_info *info,
+                         void *stream) {
+    if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
+    if (!(rtol > 0.0) || maxit < 1) return fail(DM_EINVAL, "rtol must be positive and maxit >= 1");
+    const int64_t n = op->n0();
+    if ((uint64_t)4 * (uint64_t)n * sizeof(double) > (uint64_t)DM_NOALLOC_SCRATCH_BYTES)
+        return fail(DM_EINVAL, "grid too large for the no-allocation scratch (4 * 3P doubles > " +
+                                   std::to_string(DM_NOALLOC_SCRATCH_BYTES) + " bytes)");
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        double *work = noalloc_scratch(op->device);
+        if (!work) throw DmError{DM_EHIP, "no-allocation scratch not set up on this device"};
+        fill_ghosts(op->lv[0], 64, f, false, s);
+        return solve_pcg_with(op, f, x, rtol, maxit, info, s, work);
     });
 }
 

@@ -177,6 +177,15 @@ double host_dot_sync(dm_op *op, hipStream_t s);
 // solver.cpp
 template <class T>
 void vcycle(dm_op *op, int level, const T *f, T *x, hipStream_t s);
+// dm_solve in the PCG64 mode with caller-provided work memory (4 * 3P
+// doubles): r, z, p, q; allocates nothing
+int solve_pcg_with(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_info *info,
+                   hipStream_t s, double *work);
+// the no-allocation entry point's scratch array (noalloc.hip): looked up once
+// per device, with that device current; the device address, or NULL if the
+// lookup failed (then the failure is thrown as DM_EHIP by noalloc_init)
+void noalloc_init(int device);
+double *noalloc_scratch(int device);
 void svcycle(dm_op *op, int level, const double *f, double *x, hipStream_t s);
 // device dots; results copied to op->hres (synchronises the stream)
 void dots(dm_op *op, int nv, const double *V, int64_t ld, const double *w, const double *wt,

@@ -319,6 +319,19 @@ int pcg(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_
 
 }  // namespace
 
+int solve_pcg_with(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_solve_info *info,
+                   hipStream_t s, double *work) {
+    const double t0 = now_s();
+    const int64_t n = op->n0();
+    const int rc = pcg_work(op, f, x, rtol, maxit, info, s, work, work + n, work + 2 * n, work + 3 * n);
+    DM_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->seconds = now_s() - t0;
+        info->learned_accepted = info->learned_rejected = 0;
+    }
+    return rc;
+}
+
 void ensure_proj(dm_op *op) {
     if (!op->pj_g) {
         const int64_t P = op->lv[0].g.P;
