@@ -104,10 +104,11 @@ def parse():
     ap.add_argument("--skip-learned", action="store_true", help="do not train and time the learned form")
     ap.add_argument("--skip-c3", action="store_true", help="do not run the 9-cell quarter cavity")
     ap.add_argument("--skip-c4", action="store_true", help="do not run the 64 batched ellipsoids")
-    ap.add_argument("--only", choices=["c3", "c4", "traffic"], default=None,
-                    help="profiling runs: only the 9-cell cavity, only the batch, or the HBM-traffic "
+    ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep"], default=None,
+                    help="profiling runs: only the 9-cell cavity, only the batch, the HBM-traffic "
                          "probe (a 256 MiB device copy of known size, then 3 FP32 red-black sweeps "
-                         "on the 128^3 sphere's finest level)")
+                         "on the 128^3 sphere's finest level), or the same probe on the 9-cell "
+                         "quarter's finest level (3 one-vector and 3 two-vector sweeps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
@@ -135,6 +136,16 @@ def cpu_baseline():
                 max_residual=float(np.max(info["residuals"])))
 
 
+def c3_operator(dm):
+    """The 9-cell quarter cavity: 96 x 96 x 1024 cells, h = 1.235 / 1024, PMC
+    planes x = 0 and y = 0, shift 632, the workload's smoothing counts."""
+    nxy, nz = 96, 1024
+    geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
+                           bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
+    return dm.Operator(geom, (nxy, nxy, nz), 1.235 / nz, 632.0, levels=0, fgmres_restart=C3_RESTART,
+                       nu_pre=C3_NU, nu_post=C3_NU)
+
+
 def run_c3(dm, torch):
     """Secondary figures on the 9-cell quarter cavity (96 x 96 x 1024, PMC
     planes x = 0 and y = 0): the FP32 red-black sweep's bandwidth where the
@@ -142,12 +153,8 @@ def run_c3(dm, torch):
     and the 9 lowest modes at sigma = 632 (0.9 x the lowest eigenvalue of a
     48 x 48 x 512 run) with the FP32-multigrid form."""
     nxy, nz = 96, 1024
-    h = 1.235 / nz
-    geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
-                           bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
     t0 = time.perf_counter()
-    op = dm.Operator(geom, (nxy, nxy, nz), h, 632.0, levels=0, fgmres_restart=C3_RESTART, nu_pre=C3_NU,
-                     nu_post=C3_NU)
+    op = c3_operator(dm)
     setup = time.perf_counter() - t0
     try:
         ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=20)
@@ -222,6 +229,21 @@ def main():
         return
     if args.only == "c4":
         print(json.dumps({"c4_batched_ellipsoids": run_c4(dm, torch)}))
+        return
+    if args.only == "c3sweep":
+        n = 64 * 1024 * 1024
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
+        op = c3_operator(dm)
+        ms1 = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=3)
+        ms2 = op.time_block_kernel(dm.KERNEL_SWEEP, C3_BLOCK, prec=32, level=0, reps=3)
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "sweep_ms_1": ms1, f"sweep_ms_{C3_BLOCK}": ms2,
+                          "cells": 96 * 96 * 1024}))
+        op.close()
         return
     if args.only == "traffic":
         # calibration: the counters of a plain copy of known size

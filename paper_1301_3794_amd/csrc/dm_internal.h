@@ -236,6 +236,42 @@ __host__ __device__ inline T diag_of(const Coefs<T> &c, int comp, int64_t p, int
 }
 
 // ---------------------------------------------------------------------------
+// Tabulated cut rows of the smoother.  The row of M at a face of component
+// c reads 15 stored entries (PMC ghost images counted as entries of their
+// own): 7 of its own component and 4 of each other one, at fixed offsets
+// (cut_term).  For every listed cut row the operator stores kCutW values,
+// term-major over the class's list: the 15 weights w_t of the row of
+// K + G (with 1/h^2), the face's area fraction a, and the diagonal d0 of
+// K + G at the face including the PMC self-coupling; a class update is
+//     x_f += (f_f - sum_t w_t x_t + sigma a x_f) / (d0 - sigma a),
+// the same update as from the fractions (the shift stays out of the table).
+// ---------------------------------------------------------------------------
+constexpr int kCutTerms = 15, kCutW = kCutTerms + 2;
+struct CutTerm {
+    int comp, di, dj, dk;
+};
+__host__ __device__ constexpr CutTerm cut_term(int comp, int t) {
+    // own component: the face, its neighbours -z +z -y +y -x +x (reordered
+    // per component so that t = 0 is the face itself), then the other two
+    // components' four entries each
+    return comp == 0 ? (t == 0 ? CutTerm{0, 0, 0, 0} : t == 1 ? CutTerm{0, 0, 0, -1} : t == 2 ? CutTerm{0, 0, 0, 1}
+                        : t == 3 ? CutTerm{0, 0, -1, 0} : t == 4 ? CutTerm{0, 0, 1, 0} : t == 5 ? CutTerm{0, -1, 0, 0}
+                        : t == 6 ? CutTerm{0, 1, 0, 0} : t == 7 ? CutTerm{1, 0, 0, 0} : t == 8 ? CutTerm{1, -1, 0, 0}
+                        : t == 9 ? CutTerm{1, 0, 1, 0} : t == 10 ? CutTerm{1, -1, 1, 0} : t == 11 ? CutTerm{2, 0, 0, 0}
+                        : t == 12 ? CutTerm{2, -1, 0, 0} : t == 13 ? CutTerm{2, 0, 0, 1} : CutTerm{2, -1, 0, 1})
+         : comp == 1 ? (t == 0 ? CutTerm{1, 0, 0, 0} : t == 1 ? CutTerm{1, 0, 0, -1} : t == 2 ? CutTerm{1, 0, 0, 1}
+                        : t == 3 ? CutTerm{1, -1, 0, 0} : t == 4 ? CutTerm{1, 1, 0, 0} : t == 5 ? CutTerm{1, 0, -1, 0}
+                        : t == 6 ? CutTerm{1, 0, 1, 0} : t == 7 ? CutTerm{0, 0, 0, 0} : t == 8 ? CutTerm{0, 0, -1, 0}
+                        : t == 9 ? CutTerm{0, 1, 0, 0} : t == 10 ? CutTerm{0, 1, -1, 0} : t == 11 ? CutTerm{2, 0, 0, 0}
+                        : t == 12 ? CutTerm{2, 0, -1, 0} : t == 13 ? CutTerm{2, 0, 0, 1} : CutTerm{2, 0, -1, 1})
+                     : (t == 0 ? CutTerm{2, 0, 0, 0} : t == 1 ? CutTerm{2, 0, -1, 0} : t == 2 ? CutTerm{2, 0, 1, 0}
+                        : t == 3 ? CutTerm{2, -1, 0, 0} : t == 4 ? CutTerm{2, 1, 0, 0} : t == 5 ? CutTerm{2, 0, 0, -1}
+                        : t == 6 ? CutTerm{2, 0, 0, 1} : t == 7 ? CutTerm{0, 0, 0, 0} : t == 8 ? CutTerm{0, 0, 0, -1}
+                        : t == 9 ? CutTerm{0, 1, 0, 0} : t == 10 ? CutTerm{0, 1, 0, -1} : t == 11 ? CutTerm{1, 0, 0, 0}
+                        : t == 12 ? CutTerm{1, 0, 0, -1} : t == 13 ? CutTerm{1, 0, 1, 0} : CutTerm{1, 0, 1, -1});
+}
+
+// ---------------------------------------------------------------------------
 // Batched launches: one launch performs the same V-cycle step for several
 // operators (cavities), each its own grid, coefficients and buffers.  A job
 // is one operator's share; its work items occupy blocks [block0, block0 +
@@ -300,7 +336,17 @@ struct ClassList {
     // block smoother: below this many listed rows each vector gets its own
     // wavefront, else one thread per row loops over the vectors
     int64_t wave_split_max = 32768;
+    // the tabulated rows of the listed cut rows (kCutW x n, term-major), per
+    // precision (see cut_term)
+    const double *w64 = nullptr;
+    const float *w32 = nullptr;
 };
+template <class T>
+inline const T *cut_weights(const ClassList &cl);
+template <>
+inline const double *cut_weights<double>(const ClassList &cl) { return cl.w64; }
+template <>
+inline const float *cut_weights<float>(const ClassList &cl) { return cl.w32; }
 
 // Units of kSpanUnit consecutive doubles (one 128-byte line) of a level-0
 // face vector that can hold a nonzero entry: an active face, or a PMC ghost

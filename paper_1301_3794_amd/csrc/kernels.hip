@@ -187,19 +187,47 @@ k_apply_b(Grid g, Coefs<T> c, T sigma, VPtr<const T> f, VPtr<const T> x, VPtr<T>
 // ncb workgroups (a multiple of 8) take the cut-cell list (full body), the
 // rest all cells, skipping listed ones (vacuum rows only); wave q of a
 // workgroup takes vector q of 64 entries in either part.
+// M x or f - M x at listed cell e (padded index p) from the cell's tabulated
+// rows W (3 x kCutW x ncut; see cut_term); inactive faces (a = 0) get 0
+template <class T, int KIND, class TX>
+__device__ __forceinline__ void apply_cut_tab(const Grid &g, T sigma, const T *__restrict__ W, int64_t ncut,
+                                              int64_t e, int64_t p, const T *__restrict__ f,
+                                              const TX *__restrict__ x, T *__restrict__ y) {
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    T v[3];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const T *Wc = W + (int64_t)comp * kCutW * ncut;
+        const T a = Wc[kCutTerms * ncut + e];
+        v[comp] = T(0);
+        if (a != T(0)) {
+            T row = -sigma * a * T(x[comp * P + p]);
+#pragma unroll
+            for (int t = 0; t < kCutTerms; ++t) {
+                const CutTerm ct = cut_term(comp, t);
+                row += Wc[t * ncut + e] * T(x[ct.comp * P + p + ct.di + ct.dj * dy + ct.dk * dz]);
+            }
+            v[comp] = KIND == AK_RESID ? f[comp * P + p] - row : row;
+        }
+    }
+    const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
+    const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
+    put_face<T>(g, y, 0, i, j, k, p, v[0]);
+    put_face<T>(g, y + P, 1, i, j, k, p, v[1]);
+    put_face<T>(g, y + 2 * P, 2, i, j, k, p, v[2]);
+}
+
 template <class T, int KIND, int NR, class TX = T>
 __global__ void __launch_bounds__(kThreads)
 k_apply_split(Grid g, Coefs<T> c, T sigma, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
-              const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f, VPtr<const TX> x, VPtr<T> y) {
+              const T *__restrict__ W, const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f,
+              VPtr<const TX> x, VPtr<T> y) {
     const int64_t b = blockIdx.x;
     const int q = threadIdx.x >> 6;
     if (b < ncb) {
         const int64_t e = ((b % kXcd) * (ncb / kXcd) + b / kXcd) * 64 + (threadIdx.x & 63);
         if (e >= ncut) return;
-        const int64_t p = cut[e], dy = g.sy, dz = g.sz;
-        const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
-        const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
-        apply_body<T, KIND, TX>(g, c, sigma, f.p[q], x.p[q], y.p[q], ((int64_t)k * g.ny + j) * g.nx + i);
+        apply_cut_tab<T, KIND, TX>(g, sigma, W, ncut, e, cut[e], f.p[q], x.p[q], y.p[q]);
     } else {
         const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
         const int64_t t = ((bv % kXcd) * (nvb / kXcd) + bv / kXcd) * 64 + (threadIdx.x & 63);
@@ -310,31 +338,35 @@ __device__ __forceinline__ void smooth_vac_n(const Grid &g, const Coefs<T> &c, T
     for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
 }
 
+// entry e of the class's cut list from its tabulated row W (kCutW x ncut,
+// term-major; see cut_term): the weights are loaded once for the NR vectors
 template <class T, int COMP, int NR>
-__device__ __forceinline__ void smooth_cut_n(const Grid &g, const Coefs<T> &c, T sigma,
-                                             const int32_t *__restrict__ cut, int64_t ncut, const VPtr<const T> &f,
-                                             const VPtr<T> &x, int64_t e) {
+__device__ __forceinline__ void smooth_cut_n(const Grid &g, T sigma, const int32_t *__restrict__ cut, int64_t ncut,
+                                             const T *__restrict__ W, const VPtr<const T> &f, const VPtr<T> &x,
+                                             int64_t e) {
     if (e >= ncut) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
     const int64_t p = cut[e];
-    const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
-    const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
-    const T ih2 = inv_h2_of<T>(g);
-    const T *a = COMP == 0 ? c.ax : (COMP == 1 ? c.ay : c.az);
-    const T d = diag_of<T>(c, COMP, p, dy, dz, ih2, sigma) +
-                ih2 * pmc_diag_extra<T>(g, c.lx, c.ly, c.lz, COMP, i, j, k, p);
+    T w[kCutTerms];
+#pragma unroll
+    for (int t = 0; t < kCutTerms; ++t) w[t] = W[t * ncut + e];
+    const T a = W[kCutTerms * ncut + e];
+    const T d = W[(kCutTerms + 1) * ncut + e] - sigma * a;
     T nv[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        const T *X = x.p[q], *Y = X + P, *Z = X + 2 * P;
-        const T *xc = COMP == 0 ? X : (COMP == 1 ? Y : Z);
-        T row;
-        if (COMP == 0) row = row_x<T, true>(c, X, Y, Z, p, dy, dz);
-        else if (COMP == 1) row = row_y<T, true>(c, X, Y, Z, p, dy, dz);
-        else row = row_z<T, true>(c, X, Y, Z, p, dy, dz);
-        row = ih2 * row - sigma * a[p] * xc[p];
-        nv[q] = xc[p] + (f.p[q][COMP * P + p] - row) / d;
+        const T *X = x.p[q];
+        const T xs = X[COMP * P + p];
+        T row = -sigma * a * xs;
+#pragma unroll
+        for (int t = 0; t < kCutTerms; ++t) {
+            const CutTerm ct = cut_term(COMP, t);
+            row += w[t] * X[ct.comp * P + p + ct.di + ct.dj * dy + ct.dk * dz];
+        }
+        nv[q] = xs + (f.p[q][COMP * P + p] - row) / d;
     }
+    const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
+    const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
 #pragma unroll
     for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
 }
@@ -368,16 +400,17 @@ k_smooth_b(Grid g, Coefs<T> c, T sigma, int colour, VPtr<const T> f, VPtr<T> x) 
 template <class T, int COMP, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_smooth_split(Grid g, Coefs<T> c, T sigma, int colour, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
-               int wave_split, const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f, VPtr<T> x) {
+               int wave_split, const T *__restrict__ W, const int32_t *__restrict__ rows, int64_t nrows,
+               VPtr<const T> f, VPtr<T> x) {
     const int64_t b = blockIdx.x;
     if (b < ncb) {
         const int64_t L = (b % kXcd) * (ncb / kXcd) + b / kXcd;
         if (!wave_split) {
-            smooth_cut_n<T, COMP, NR>(g, c, sigma, cut, ncut, f, x, L * kThreads + threadIdx.x);
+            smooth_cut_n<T, COMP, NR>(g, sigma, cut, ncut, W, f, x, L * kThreads + threadIdx.x);
         } else {
             const int q = threadIdx.x >> 6;
             if (q >= NR) return;
-            smooth_cut_n<T, COMP, 1>(g, c, sigma, cut, ncut, vptr1(f.p[q]), vptr1(x.p[q]), L * 64 + (threadIdx.x & 63));
+            smooth_cut_n<T, COMP, 1>(g, sigma, cut, ncut, W, vptr1(f.p[q]), vptr1(x.p[q]), L * 64 + (threadIdx.x & 63));
         }
     } else {
         const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
@@ -1537,6 +1570,7 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
     if (cut.idx && (kind == AK_M || kind == AK_RESID)) {
+        if (cut.n > 0 && !cut_weights<T>(cut)) throw std::runtime_error("apply: cut-cell list without its row table");
         // the vacuum part visits the listed grid rows (every row without a list)
         const int64_t ncb = ceil_div(ceil_div(cut.n, 64), kXcd) * kXcd;
         const int64_t nvac = cut.rows ? cut.nrows * g.nx : n;
@@ -1544,10 +1578,10 @@ void launch_apply_b(const Grid &g, const T *coef, T sigma, int kind, int nr, con
         const dim3 grid((unsigned)(ncb + nvb));
         if (kind == AK_M)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<T, AK_M, NR>), grid, dim3(64 * NR), 0, s, g, c, sigma,
-                                                cut.idx, cut.n, ncb, cut.rows, cut.nrows, f, x, y))
+                                                cut.idx, cut.n, ncb, cut_weights<T>(cut), cut.rows, cut.nrows, f, x, y))
         else
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<T, AK_RESID, NR>), grid, dim3(64 * NR), 0, s, g, c,
-                                                sigma, cut.idx, cut.n, ncb, cut.rows, cut.nrows, f, x, y))
+                                                sigma, cut.idx, cut.n, ncb, cut_weights<T>(cut), cut.rows, cut.nrows, f, x, y))
         return;
     }
     if (kind == AK_M)
@@ -1564,6 +1598,7 @@ void launch_apply_m_f32in(const Grid &g, const double *coef, double sigma, int n
                          const VPtr<double> &y, hipStream_t s, ClassList cut) {
     // the split form; without cut cells (no list) every cell takes the vacuum part
     if (!cut.idx && cut.n != 0) throw std::runtime_error("apply with FP32 input: cut-cell list missing");
+    if (cut.n > 0 && !cut.w64) throw std::runtime_error("apply: cut-cell list without its row table");
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const Coefs<double> c = coefs_of(coef, g.P);
     const int64_t ncb = cut.idx ? ceil_div(ceil_div(cut.n, 64), kXcd) * kXcd : 0;
@@ -1572,7 +1607,7 @@ void launch_apply_m_f32in(const Grid &g, const double *coef, double sigma, int n
     const dim3 grid((unsigned)(ncb + nvb));
     const VPtr<const double> f{};
     DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_apply_split<double, AK_M, NR, float>), grid, dim3(64 * NR), 0, s, g, c,
-                                        sigma, cut.idx, cut.n, ncb, cut.rows, cut.nrows, f, x, y))
+                                        sigma, cut.idx, cut.n, ncb, cut_weights<double>(cut), cut.rows, cut.nrows, f, x, y))
 }
 
 template <class T>
@@ -1581,6 +1616,7 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
     const int64_t n = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
     const Coefs<T> c = coefs_of(coef, g.P);
     if (cut.idx) {
+        if (cut.n > 0 && !cut_weights<T>(cut)) throw std::runtime_error("smoother: cut list without its row table");
         const int wave_split = nr > 1 && cut.n < cut.wave_split_max;
         const int64_t ncb = ceil_div(ceil_div(cut.n, wave_split ? 64 : kThreads), kXcd) * kXcd;
         // the vacuum part sweeps the listed rows (every row without a list)
@@ -1589,13 +1625,13 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
         const dim3 grid((unsigned)(ncb + nvb));
         if (comp == 0)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 0, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, cut.rows, cut.nrows, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.rows, cut.nrows, f, x))
         else if (comp == 1)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 1, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, cut.rows, cut.nrows, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.rows, cut.nrows, f, x))
         else
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 2, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, cut.rows, cut.nrows, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.rows, cut.nrows, f, x))
         return;
     }
     if (comp == 0)

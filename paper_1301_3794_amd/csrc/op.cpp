@@ -11,6 +11,10 @@
 
 namespace dm {
 
+// grid rows (in y) per strip of the launch order of listed rows (see
+// build_hierarchy)
+constexpr int kStripRows = 16;
+
 namespace {
 
 // largest coarsest level factored densely (its inverse is n^2 doubles)
@@ -136,6 +140,75 @@ std::vector<uint8_t> row_flags(const Grid &g, const std::vector<double> &c) {
     return fl;
 }
 
+// One tabulated row (see cut_term): the weights of the row of K + G at the
+// face of component comp in cell p for its 15 stored entries, read off by
+// evaluating the row on unit vectors in a 3^3 window of cells around the
+// face (local strides 3 and 9), then a and the diagonal d0; written to
+// dst[t * stride], t = 0 .. kCutW - 1.  An inactive face gets zeros.
+static void tab_row(const Grid &g, const std::vector<double> &c, const Coefs<double> &cg, int comp, int64_t p,
+                    double *dst, int64_t stride) {
+    const int64_t P = g.P, dy = g.sy, dz = g.sz;
+    const double ih2 = 1.0 / (g.h * g.h);
+    if (!(c[comp * P + p] > 0.0)) {
+        for (int t = 0; t < kCutW; ++t) dst[t * stride] = 0.0;
+        return;
+    }
+    double cw[7 * 27], xw[3 * 27];
+    Coefs<double> cl;
+    cl.ax = cw; cl.ay = cw + 27; cl.az = cw + 54; cl.lx = cw + 81; cl.ly = cw + 108; cl.lz = cw + 135;
+    cl.vinv = cw + 162;
+    cl.flags = nullptr;
+    for (int a = 0; a < 7; ++a)
+        for (int dk = -1; dk <= 1; ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di)
+                    cw[a * 27 + 13 + di + 3 * dj + 9 * dk] = c[a * P + p + di + dj * dy + dk * dz];
+    std::fill(xw, xw + 3 * 27, 0.0);
+    for (int t = 0; t < kCutTerms; ++t) {
+        const CutTerm ct = cut_term(comp, t);
+        double &slot = xw[ct.comp * 27 + 13 + ct.di + 3 * ct.dj + 9 * ct.dk];
+        slot = 1.0;
+        double v;
+        if (comp == 0) v = row_x<double, true>(cl, xw, xw + 27, xw + 54, 13, 3, 9);
+        else if (comp == 1) v = row_y<double, true>(cl, xw, xw + 27, xw + 54, 13, 3, 9);
+        else v = row_z<double, true>(cl, xw, xw + 27, xw + 54, 13, 3, 9);
+        dst[t * stride] = ih2 * v;
+        slot = 0.0;
+    }
+    const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
+    const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
+    dst[kCutTerms * stride] = c[comp * P + p];
+    dst[(kCutTerms + 1) * stride] = diag_of<double>(cg, comp, p, dy, dz, ih2, 0.0) +
+                                    ih2 * pmc_diag_extra<double>(g, cg.lx, cg.ly, cg.lz, comp, i, j, k, p);
+}
+
+// The tables of a level: its smoother classes' cut lists (class q's rows of
+// component q / 2, term-major, starting at kCutW * cut_off[q]) and its list
+// of cells with a cut row (the three components' rows of each cell: entry
+// (comp, t) of cell e at (comp * kCutW + t) * ncells + e).  Threaded.
+static void cut_tables(const Grid &g, const std::vector<double> &c, const std::vector<int32_t> &cut,
+                       const int64_t cut_off[7], const std::vector<int32_t> &cells, std::vector<double> &rows_tab,
+                       std::vector<double> &cells_tab) {
+    const Coefs<double> cg = coefs_of(c.data(), g.P);
+    rows_tab.assign((size_t)kCutW * cut.size(), 0.0);
+    cells_tab.assign((size_t)3 * kCutW * cells.size(), 0.0);
+    const int64_t nc = (int64_t)cells.size();
+    auto work = [&](int part) {
+        if (part < 6) {
+            const int64_t n = cut_off[part + 1] - cut_off[part];
+            double *T = rows_tab.data() + (size_t)kCutW * cut_off[part];
+            for (int64_t e = 0; e < n; ++e) tab_row(g, c, cg, part / 2, cut[cut_off[part] + e], T + e, n);
+        } else {
+            const int comp = part - 6;
+            for (int64_t e = 0; e < nc; ++e)
+                tab_row(g, c, cg, comp, cells[e], cells_tab.data() + (size_t)comp * kCutW * nc + e, nc);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int q = 0; q < 9; ++q) th.emplace_back(work, q);
+    for (auto &t : th) t.join();
+}
+
 void build_hierarchy(dm_op *op, const double *user_frac) {
     const int nl = op->opt.levels;
     int pmc = 0;
@@ -224,6 +297,56 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
                 for (int i = 0; i < L.g.nx && !any; ++i) any = fl[pidx(L.g, i, j, k)] & 7;
                 if (any) frows.push_back((int32_t)(k * L.g.ny + j));
             }
+        // Launch order of the listed rows and cut rows: strips of kStripRows
+        // grid rows in y, and within a strip plane after plane in z.  The
+        // rows a GPU works on at one time then span many planes of a narrow
+        // strip, so a row's k-1 and k+1 neighbours are fetched by the same
+        // XCD at about the same time and stay in its L2; in plain (k, j)
+        // order they lie a whole plane apart (3.5 MB of one component at
+        // 96 x 96, more than the L2 holds next to the other arrays) and
+        // every line was fetched again for each neighbour plane.  Rows of one
+        // launch are independent, so the order changes no value.
+        {
+            const int ny = L.g.ny;
+            auto row_key = [&](int32_t r) {
+                const int64_t k = r / ny, j = r % ny;
+                return ((j / kStripRows) * (int64_t)L.g.nz + k) * kStripRows + j % kStripRows;
+            };
+            auto by_strip = [&](std::vector<int32_t> &v) {
+                std::stable_sort(v.begin(), v.end(),
+                                 [&](int32_t a, int32_t b) { return row_key(a) < row_key(b); });
+            };
+            by_strip(vrows);
+            by_strip(frows);
+            by_strip(arows);
+            // padded cell indices: the same order over their grid rows, x inside a row
+            const int64_t sy = L.g.sy, sz = L.g.sz;
+            auto cell_key = [&](int32_t p) {
+                const int64_t k = p / sz - 1, j = (p % sz) / sy - 1, i = p % sy;
+                return row_key((int32_t)(k * ny + j)) * sy + i;
+            };
+            auto cells_by_strip = [&](std::vector<int32_t>::iterator b, std::vector<int32_t>::iterator e) {
+                std::stable_sort(b, e, [&](int32_t a, int32_t c) { return cell_key(a) < cell_key(c); });
+            };
+            for (int q = 0; q < 6; ++q) cells_by_strip(cut.begin() + L.cut_off[q], cut.begin() + L.cut_off[q + 1]);
+            cells_by_strip(cutc.begin(), cutc.end());
+        }
+        // tabulated rows of the cut lists and of the cells with a cut row
+        {
+            std::vector<double> tab, ctab;
+            cut_tables(L.g, c, cut, L.cut_off, cutc, tab, ctab);
+            auto upload = [&](const std::vector<double> &t, double *&d64, float *&d32) {
+                if (t.empty()) return;
+                std::vector<float> t32(t.begin(), t.end());
+                d64 = op->dalloc<double>(t.size());
+                d32 = op->dalloc<float>(t.size());
+                DM_HIP(hipMemcpyAsync(d64, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
+                DM_HIP(hipMemcpyAsync(d32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice, op->stream));
+                DM_HIP(hipStreamSynchronize(op->stream));
+            };
+            upload(tab, L.cutw64, L.cutw32);
+            upload(ctab, L.cellw64, L.cellw32);
+        }
         L.nfrows = (int64_t)frows.size();
         if (!frows.empty()) {
             L.frows = op->dalloc<int32_t>(frows.size());

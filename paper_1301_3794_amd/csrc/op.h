@@ -33,7 +33,15 @@ struct Level {
     // cells with an active non-vacuum row (any component), padded indices
     int32_t *cutc = nullptr;
     int64_t ncutc = 0;
-    ClassList cut_cells() const { return ClassList{cutc, ncutc}; }
+    // tabulated rows of the cells in cutc (3 components x kCutW per cell)
+    double *cellw64 = nullptr;
+    float *cellw32 = nullptr;
+    ClassList cut_cells() const {
+        ClassList cl{cutc, ncutc};
+        cl.w64 = cellw64;
+        cl.w32 = cellw32;
+        return cl;
+    }
     // grid rows (k * ny + j) with a vacuum row of any component
     int32_t *vrows = nullptr;
     int64_t nvrows = 0;
@@ -45,13 +53,24 @@ struct Level {
     int64_t nfrows = 0;
     // the cut-cell list with the rows holding an active face: for outputs
     // that stay zero on the other rows (the block V-cycle's residual)
-    ClassList cut_cells_rows() const { return ClassList{cutc, ncutc, frows, nfrows}; }
+    ClassList cut_cells_rows() const {
+        ClassList cl = cut_cells();
+        cl.rows = frows;
+        cl.nrows = nfrows;
+        return cl;
+    }
     // the block smoother's threshold for one wave per vector (dm_options)
     int64_t cut_wave_split = 32768;
+    // tabulated rows of the cut lists (kCutW values per row, term-major per
+    // class: class q's table starts at kCutW * cut_off[q])
+    double *cutw64 = nullptr;
+    float *cutw32 = nullptr;
     ClassList cut_list(int comp, int colour) const {
         const int q = 2 * comp + colour;
-        return ClassList{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows,
-                         cut_wave_split};
+        ClassList cl{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows, cut_wave_split};
+        if (cutw64) cl.w64 = cutw64 + kCutW * cut_off[q];
+        if (cutw32) cl.w32 = cutw32 + kCutW * cut_off[q];
+        return cl;
     }
 };
 
