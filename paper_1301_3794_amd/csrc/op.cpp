@@ -11,10 +11,6 @@
 
 namespace dm {
 
-// grid rows (in y) per strip of the launch order of listed rows (see
-// build_hierarchy)
-constexpr int kStripRows = 16;
-
 namespace {
 
 // largest coarsest level factored densely (its inverse is n^2 doubles)
@@ -297,40 +293,6 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
                 for (int i = 0; i < L.g.nx && !any; ++i) any = fl[pidx(L.g, i, j, k)] & 7;
                 if (any) frows.push_back((int32_t)(k * L.g.ny + j));
             }
-        // Launch order of the listed rows and cut rows: strips of kStripRows
-        // grid rows in y, and within a strip plane after plane in z.  The
-        // rows a GPU works on at one time then span many planes of a narrow
-        // strip, so a row's k-1 and k+1 neighbours are fetched by the same
-        // XCD at about the same time and stay in its L2; in plain (k, j)
-        // order they lie a whole plane apart (3.5 MB of one component at
-        // 96 x 96, more than the L2 holds next to the other arrays) and
-        // every line was fetched again for each neighbour plane.  Rows of one
-        // launch are independent, so the order changes no value.
-        {
-            const int ny = L.g.ny;
-            auto row_key = [&](int32_t r) {
-                const int64_t k = r / ny, j = r % ny;
-                return ((j / kStripRows) * (int64_t)L.g.nz + k) * kStripRows + j % kStripRows;
-            };
-            auto by_strip = [&](std::vector<int32_t> &v) {
-                std::stable_sort(v.begin(), v.end(),
-                                 [&](int32_t a, int32_t b) { return row_key(a) < row_key(b); });
-            };
-            by_strip(vrows);
-            by_strip(frows);
-            by_strip(arows);
-            // padded cell indices: the same order over their grid rows, x inside a row
-            const int64_t sy = L.g.sy, sz = L.g.sz;
-            auto cell_key = [&](int32_t p) {
-                const int64_t k = p / sz - 1, j = (p % sz) / sy - 1, i = p % sy;
-                return row_key((int32_t)(k * ny + j)) * sy + i;
-            };
-            auto cells_by_strip = [&](std::vector<int32_t>::iterator b, std::vector<int32_t>::iterator e) {
-                std::stable_sort(b, e, [&](int32_t a, int32_t c) { return cell_key(a) < cell_key(c); });
-            };
-            for (int q = 0; q < 6; ++q) cells_by_strip(cut.begin() + L.cut_off[q], cut.begin() + L.cut_off[q + 1]);
-            cells_by_strip(cutc.begin(), cutc.end());
-        }
         // tabulated rows of the cut lists and of the cells with a cut row
         {
             std::vector<double> tab, ctab;
