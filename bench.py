@@ -68,31 +68,71 @@ def block_sweep_bytes_per_cell(nr):
     return (7 + 9 * nr) * 4
 
 
-# The same counted only where a row needs it (128^3 sphere): 1 B row class
-# per cell; per cell with a cut row (121,284 cells) coef(7) once and 9 words
-# per vector; 12 B per vector for each active component of a vacuum-only
-# cell (2,129,808 components in 709,936 cells).  One vector: 35,417,024 B
-# per sweep against 134,217,728 B for the box count.
-SWEEP_CUT_CELLS = 121284
-SWEEP_VACUUM_COMPONENTS = 2129808
-
-
-def strict_sweep_bytes(nr, cells):
-    return cells + SWEEP_CUT_CELLS * (28 + 36 * nr) + SWEEP_VACUUM_COMPONENTS * 12 * nr
 # FP32 V-cycle, nu = 2/2: on the fine level 4 sweeps + residual + restriction
 # + prolongation = 4*64 + 64 + 13.5 + 25.5 = 359 B per cell, times 8/7 for
 # the coarser levels
 VCYCLE_BYTES_PER_CELL = 359.0 * 8.0 / 7.0
-# HBM bytes per FP32 block sweep (BLOCK = 3 vectors) on the 128^3 sphere's
-# finest level, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of
-# `bench.py --only traffic`, each counter scaled by its reading for a 256 MiB
-# copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000): reads 471,511 KiB + writes
-# 69,327 KiB per sweep of the six k_smooth_split class kernels.
-BLOCK_SWEEP_TRAFFIC_BYTES = 553818144
+# HBM traffic of the FP32 block sweep from rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE, each run on its own, scaled by the counters' readings for a
+# 256 MiB device copy): bytes per sweep of the six class launches, per
+# workload and block size, for the kernels as they are now (None where no
+# counter run of the current kernels exists).  Summaries under profiles/.
+SWEEP_TRAFFIC_BYTES = {"sphere128_3": 456438973,   # profiles/block_sweep_sphere128_hbm_traffic.md
+                       "ninecell_1": 943020447,    # profiles/sweep_ninecell_96x96x1024_hbm_traffic.md
+                       "ninecell_2": 1750226183}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sweep_bytes(nr, cells):
+    """Algorithmic bytes of one FP32 red-black sweep on nr vectors over
+    `cells` cells: the 7 coefficient words once, and per vector x(3) and
+    f(3) read and x(3) written.  Counted over the active cells (v > 0) this
+    is the method's own count; over the box it is the dense-box count."""
+    return (7 + 9 * nr) * 4 * cells
+
+
+def measure_copy_gbps(torch, nbytes=1 << 30, reps=10):
+    """HBM bandwidth of a plain device-to-device copy of `nbytes` (read +
+    write bytes per second), timed with events on the current stream."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def sweep_roofline(dm, op, nr, copy_gbps, traffic, reps=50):
+    """Roofline figures of the FP32 sweep on nr vectors on the finest level:
+    its average launch time (six class launches, HIP events on the op's
+    stream), the method's bytes over the active cells against the vendor HBM
+    peak and the measured copy bandwidth, and the dense-box count beside."""
+    lay = op.layout(0)
+    nx, ny, nz = lay["dims"]
+    if nr == 1:
+        ms = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=reps)
+    else:
+        ms = op.time_block_kernel(dm.KERNEL_SWEEP, nr, prec=32, level=0, reps=reps)
+    method = sweep_bytes(nr, lay["active_cells"])
+    box = sweep_bytes(nr, nx * ny * nz)
+    ach = method / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "ms_per_launch": ms, "bytes_per_launch": method, "active_cells": lay["active_cells"],
+            "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(ach / copy_gbps, 4),
+            "box_bytes_per_launch": box,
+            "box_frac": round(box / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic_over_method_bytes": round(traffic / method, 2) if traffic else None}
 
 
 def parse():
@@ -132,8 +172,20 @@ def cpu_baseline():
         t0 = time.perf_counter()
         lam, _, info = oeigs.lanczos_eigs(op, K_EIG, sigma_o=5.0, block=4, tol=TOL)
         dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    from threadpoolctl import threadpool_info
+    blas = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()]
+    host = {"os_cpu_count": os.cpu_count(), "cpu_model": model, "blas_outside_sample": blas,
+            "threads_in_sample": 1}
     return dict(sample_seconds=dt, sample_active_faces=int(op.act.size), lam=lam.tolist(),
-                max_residual=float(np.max(info["residuals"])))
+                max_residual=float(np.max(info["residuals"])), host=host)
 
 
 def c3_operator(dm):
@@ -146,20 +198,23 @@ def c3_operator(dm):
                        nu_pre=C3_NU, nu_post=C3_NU)
 
 
-def run_c3(dm, torch):
+def run_c3(dm, torch, copy_gbps):
     """Secondary figures on the 9-cell quarter cavity (96 x 96 x 1024, PMC
     planes x = 0 and y = 0): the FP32 red-black sweep's bandwidth where the
     fine-level working set (about 630 MB) exceeds the 256 MB Infinity Cache,
     and the 9 lowest modes at sigma = 632 (0.9 x the lowest eigenvalue of a
-    48 x 48 x 512 run) with the FP32-multigrid form."""
+    48 x 48 x 512 run) with the FP32-multigrid form; then the same cavity at
+    the coarser grids whose eigenvalues the oracle stored, with the error of
+    every mode."""
+    import numpy as np
     nxy, nz = 96, 1024
     t0 = time.perf_counter()
     op = c3_operator(dm)
     setup = time.perf_counter() - t0
     try:
-        ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=20)
-        cells = nxy * nxy * nz
-        gbs = BYTES_PER_CELL["sweep"] * cells / (ms_sweep * 1e-3) / 1e9
+        roof = {f"sweep_{nr}_vectors": sweep_roofline(dm, op, nr, copy_gbps, SWEEP_TRAFFIC_BYTES[f"ninecell_{nr}"],
+                                                      reps=20)
+                for nr in (1, C3_BLOCK)}
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         out = op.eigs(9, sigma=632.0, tol=TOL, seed=3, solve_mode=dm.SOLVE_FGMRES_MG32, block=C3_BLOCK,
@@ -167,14 +222,57 @@ def run_c3(dm, torch):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         lay = op.layout(0)
-        return {"grid": [nxy, nxy, nz], "levels": lay["levels"], "active_faces": lay["active_faces"],
-                "setup_s": round(setup, 2), "sweep_ms": ms_sweep, "sweep_GBps": round(gbs, 1),
-                "sweep_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-                "block": C3_BLOCK, "nu": C3_NU, "fgmres_restart": C3_RESTART, "status": out["status"], "s_per_eigenpair": dt / 9, "lam": out["lam"].tolist(),
-                "max_residual": out["max_residual"], "outer_iterations": out["outer_iterations"],
-                "inner_iterations": out["inner_iterations"], "restarts": out["restarts"]}
+        res = {"grid": [nxy, nxy, nz], "levels": lay["levels"], "active_faces": lay["active_faces"],
+               "active_cells": lay["active_cells"], "setup_s": round(setup, 2), "roofline": roof,
+               "block": C3_BLOCK, "nu": C3_NU, "fgmres_restart": C3_RESTART, "status": out["status"],
+               "s_per_eigenpair": dt / 9, "lam": out["lam"].tolist(),
+               "max_residual": out["max_residual"], "outer_iterations": out["outer_iterations"],
+               "inner_iterations": out["inner_iterations"], "restarts": out["restarts"]}
     finally:
         op.close()
+    # the coarser grids with stored oracle eigenvalues (tests/golden)
+    res["vs_oracle"] = []
+    for nzc in (256, 512):
+        path = os.path.join(ROOT, "tests", "golden", f"ninecell_quarter_{nzc}_oracle.json")
+        if not os.path.exists(path):
+            continue
+        ref = json.load(open(path))
+        n = ref["grid"]
+        geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
+                               bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
+        with dm.Operator(geom, tuple(n), 1.235 / nzc, 632.0, levels=0, fgmres_restart=C3_RESTART,
+                         nu_pre=C3_NU, nu_post=C3_NU) as opc:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            o = opc.eigs(9, sigma=632.0, tol=TOL, seed=3, solve_mode=dm.SOLVE_FGMRES_MG32, block=C3_BLOCK,
+                         max_basis=48, max_restarts=30)
+            torch.cuda.synchronize()
+            dtc = time.perf_counter() - t1
+        lr = np.array(ref["lam"])
+        res["vs_oracle"].append({"grid": n, "status": o["status"], "s_per_eigenpair": dtc / 9,
+                                 "max_residual": o["max_residual"],
+                                 "rel_err_vs_oracle": (abs(o["lam"] - lr) / lr).tolist()})
+    return res
+
+
+def run_c1(dm, torch, reps=5):
+    """The small configuration: sphere R = 0.45 at 16^3 (h = 1/16), sigma =
+    5, 3-level V-cycle, the 4 lowest pairs to rho <= 1e-10 in the
+    FP32-multigrid form; median over `reps` timed eigensolves after one
+    untimed.  Launch-bound: reported as seconds per eigenpair only."""
+    import numpy as np
+    with dm.Operator(dm.sphere((0.5, 0.5, 0.5), R), (16, 16, 16), 1.0 / 16, 5.0, levels=3) as op:
+        op.eigs(4, tol=TOL, seed=SEED, solve_mode=dm.SOLVE_FGMRES_MG32)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = op.eigs(4, tol=TOL, seed=SEED, solve_mode=dm.SOLVE_FGMRES_MG32)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) / 4)
+    return {"grid": [16, 16, 16], "sigma": 5.0, "k": 4, "s_per_eigenpair_median": float(np.median(ts)),
+            "status": out["status"], "lam": out["lam"].tolist(), "max_residual": out["max_residual"],
+            "outer_iterations": out["outer_iterations"], "inner_iterations": out["inner_iterations"]}
 
 
 def run_c4(dm, torch):
@@ -225,7 +323,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.only == "c3":
-        print(json.dumps({"c3_9cell_quarter": run_c3(dm, torch)}))
+        print(json.dumps({"c3_9cell_quarter": run_c3(dm, torch, measure_copy_gbps(torch))}))
         return
     if args.only == "c4":
         print(json.dumps({"c4_batched_ellipsoids": run_c4(dm, torch)}))
@@ -329,32 +427,25 @@ def main():
             f["rel_err_vs_oracle"] = (abs(np.array(f["lam"]) - ref) / ref).tolist()
 
     # roofline of the dominant kernel: the FP32 block red-black sweep (the
-    # BLOCK vectors of one Krylov-Schur step) on the finest level, timed with
+    # BLOCK vectors of one Krylov--Schur step) on the finest level, timed with
     # HIP events on the op's stream
-    cells = N ** 3
-    ms_bsweep = op.time_block_kernel(dm.KERNEL_SWEEP, BLOCK, prec=32, level=0, reps=50)
-    bytes_b = block_sweep_bytes_per_cell(BLOCK) * cells
-    achieved = bytes_b / (ms_bsweep * 1e-3) / 1e9
-    ms_sweep = op.time_kernel(dm.KERNEL_SWEEP, prec=32, level=0, reps=50)
-    ms_vc = op.time_kernel(dm.KERNEL_VCYCLE, prec=32, level=0, reps=20)
-    ms_bvc = op.time_block_kernel(dm.KERNEL_VCYCLE, BLOCK, prec=32, level=0, reps=20)
-    ms_res = op.time_kernel(dm.KERNEL_RESIDUAL, prec=32, level=0, reps=50)
-    strict_b = strict_sweep_bytes(BLOCK, cells)
-    roofline = {"bound": "hbm", "kernel": f"block red-black sweep (6 class updates, {BLOCK} vectors), FP32, 128^3",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": BLOCK_SWEEP_TRAFFIC_BYTES,
-                "ms_per_launch": ms_bsweep, "bytes_per_launch": bytes_b,
-                "strict_bytes_per_launch": strict_b,
-                "strict_frac": round(strict_b / (ms_bsweep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "single_vector_sweep_ms": ms_sweep,
-                "single_vector_sweep_GBps": round(BYTES_PER_CELL["sweep"] * cells / (ms_sweep * 1e-3) / 1e9, 1),
-                "vcycle_ms": ms_vc, "block_vcycle_ms": ms_bvc, "residual_ms": ms_res,
-                "residual_GBps": BYTES_PER_CELL["residual"] * cells / (ms_res * 1e-3) / 1e9}
+    log("roofline")
+    copy_gbps = measure_copy_gbps(torch)
+    roofline = sweep_roofline(dm, op, BLOCK, copy_gbps, SWEEP_TRAFFIC_BYTES[f"sphere128_{BLOCK}"])
+    roofline["kernel"] = f"block red-black sweep (6 class updates, {BLOCK} vectors), FP32, 128^3 sphere"
+    roofline["single_vector_sweep"] = {k: v for k, v in sweep_roofline(dm, op, 1, copy_gbps, None).items()
+                                       if k in ("ms_per_launch", "achieved", "frac", "frac_of_copy")}
+    roofline["vcycle_ms"] = op.time_kernel(dm.KERNEL_VCYCLE, prec=32, level=0, reps=20)
+    roofline["block_vcycle_ms"] = op.time_block_kernel(dm.KERNEL_VCYCLE, BLOCK, prec=32, level=0, reps=20)
+    roofline["residual_ms"] = op.time_kernel(dm.KERNEL_RESIDUAL, prec=32, level=0, reps=50)
+
+    log("small configuration (16^3)")
+    c1 = run_c1(dm, torch)
 
     c3 = None
     if not args.skip_c3:
         log("9-cell quarter cavity")
-        c3 = run_c3(dm, torch)
+        c3 = run_c3(dm, torch, copy_gbps)
 
     c4 = None
     if not args.skip_c4:
@@ -370,7 +461,16 @@ def main():
                "kind": "oracle",
                "sample": (f"oracle eigensolve of the same sphere at {CPU_N}^3 (k={K_EIG}, rho<=1e-10, "
                           f"{cb['sample_seconds']:.1f} s, {cb['sample_active_faces']} active faces), "
-                          f"scaled x{scale:.1f} by active faces to 128^3 (lower bound)")}
+                          f"scaled x{scale:.1f} by active faces to 128^3 (lower bound)"),
+               "host": cb["host"]}
+        if os.path.exists(golden):
+            g = json.load(open(golden))
+            cpu["measured_full_size"] = {
+                "s_per_eigenpair": g["seconds"] / len(g["lam"]),
+                "what": (f"the oracle's own 128^3 run that wrote tests/golden/sphere128_oracle.json: "
+                         f"{len(g['lam'])} pairs to rho <= 1e-11 in {g['seconds']:.0f} s (augmented block "
+                         "Lanczos, CG preconditioned by the oracle V-cycle), on the 8-core build host, "
+                         "not on this machine")}
 
     line = {
         "metric": "s per eigenpair at 1e-10 residual (FP64 vs FP32-MG vs learned); V-cycle HBM GB/s",
@@ -385,6 +485,7 @@ def main():
         "forms": forms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "c1_small": c1,
         "c3_9cell_quarter": c3,
         "c4_batched_ellipsoids": c4,
     }
