@@ -46,11 +46,12 @@ C3_BLOCK = 2
 # iterations per inversion there, so orthogonalisation dominated)
 C3_NU = 4
 C3_RESTART = 30
-# The learned form's inner solves stop at 3e-12 instead of 1e-11: with
-# 1e-11 its eigen-residuals of the triplet stalled at 1.1e-10 .. 3.8e-10
-# (block 3 or 4, 20 restarts), while the FP32-multigrid form reaches
-# 5.6e-11 with 1e-11.
-LEARNED_INNER_RTOL = 3e-12
+# The learned form's inner solves stop at the same 1e-11 as the other forms.
+# (At 3e-12, below what the FP32 V-cycle lets FGMRES reach cheaply at this
+# indefinite shift, both the plain and the learned form need about 10x the
+# inner iterations: 11,021 and 11,013 against 1,059 and 1,056 at 1e-11,
+# measured with the same trained network.)
+LEARNED_INNER_RTOL = 1e-11
 HBM_PEAK_GBS = 8000.0
 CPU_N = 40      # grid of the oracle's timed sample
 

@@ -116,6 +116,10 @@ typedef struct {
                             its own wavefront; a longer list takes one thread per
                             row looping over the vectors (32768; 0 always takes
                             the loop).  Both give the same values. */
+    int learned_patience; /* DM_SOLVE_FGMRES_MG32_LEARNED: a solve stops trying the
+                            network's correction after this many rejections (the
+                            correction no longer lowers the residual there); 0
+                            never stops.  (1) */
 } dm_options;
 
 /* Fills `opt` with the defaults listed above. */

@@ -142,6 +142,7 @@ void dm_default_options(dm_options *opt) {
     opt->fgmres_restart = 30;
     opt->verbose = 0;
     opt->cut_wave_split = 32768;
+    opt->learned_patience = 1;
 }
 
 void dm_default_eig_options(dm_eig_options *opt) {
@@ -219,7 +220,8 @@ int dm_build_operator(const dm_geometry *geom, const int dims[3], double h, doub
         else dm_default_options(&op->opt);
         if (op->opt.levels <= 0) op->opt.levels = auto_levels(dims);
         if (op->opt.nu_pre < 0 || op->opt.nu_post < 0 || op->opt.fgmres_restart < 1 ||
-            op->opt.fgmres_restart > kMaxDots - 2 || op->opt.cut_wave_split < 0)
+            op->opt.fgmres_restart > kMaxDots - 2 || op->opt.cut_wave_split < 0 ||
+            op->opt.learned_patience < 0)
             return fail(DM_EINVAL, "bad smoothing, restart or wave-split option");
         const int div = 1 << (op->opt.levels - 1);
         for (int a = 0; a < 3; ++a)

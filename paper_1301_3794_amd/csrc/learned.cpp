@@ -165,15 +165,15 @@ void net_apply(dm_op *op, const double *r, double scale, double *out, hipStream_
 }
 
 // z += correction of the V-cycle's answer z for right-hand side v, kept only
-// if it lowers ||v - M z||
-void net_correct(dm_op *op, const double *v, double *z, hipStream_t s) {
+// if it lowers ||v - M z||; returns whether it was kept
+bool net_correct(dm_op *op, const double *v, double *z, hipStream_t s) {
     attached(op);
     const Level &L = op->lv[0];
     const int64_t n = op->n0();
     double *r2 = op->ln_t1, *dz = op->ln_t2, *r3 = op->ln_t3;
     launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, v, z, r2, s);
     const double n2 = dot1(op, r2, r2, op->wface, n, s);
-    if (!(n2 > 0.0)) return;
+    if (!(n2 > 0.0)) return true;
     const double sc = std::sqrt(n2 / (double)std::max<int64_t>(1, L.n_act_faces));
     net_apply(op, r2, sc, dz, s);
     launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, r2, dz, r3, s);
@@ -181,9 +181,10 @@ void net_correct(dm_op *op, const double *v, double *z, hipStream_t s) {
     if (n3 < n2) {
         launch_axpy(n, 1.0, dz, z, s);
         ++op->ln_accepted;
-    } else {
-        ++op->ln_rejected;
+        return true;
     }
+    ++op->ln_rejected;
+    return false;
 }
 
 double net_loss_grad(dm_op *op, int kind, const double *r, const double *e, double scale, hipStream_t s) {

@@ -226,7 +226,8 @@ int solve_block(dm_op *op, int mode, int nrhs, const double *const *f, double *c
 // 3P), prec 64 lv[0].bf64 -> lv[0].bx64
 void ensure_block(dm_op *op, int prec);
 void vcycle_block_graphed(dm_op *op, int prec, int nrhs, hipStream_t s);
-void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s);
+// rejections: the solve's count of rejected learned corrections (learned mode)
+void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s, int *rejections = nullptr);
 void ensure_krylov(dm_op *op);
 // the single-vector solver's small buffers (casts, graph in/out, coefficients)
 // without its FGMRES basis
@@ -273,7 +274,14 @@ void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s
 void net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss, hipStream_t s);
 void net_train_pairs(dm_op *op, int kind, int npairs, const double *const *r, const double *const *e, float lr,
                      float *loss, hipStream_t s);
-void net_correct(dm_op *op, const double *v, double *z, hipStream_t s);
+bool net_correct(dm_op *op, const double *v, double *z, hipStream_t s);
+// the learned correction of one system of a solve, while its rejections stay
+// below the op's patience (dm_options.learned_patience; 0: always)
+inline void net_correct_patient(dm_op *op, const double *v, double *z, int *rejections, hipStream_t s) {
+    const int pat = op->opt.learned_patience;
+    if (pat > 0 && *rejections >= pat) return;
+    if (!net_correct(op, v, z, s)) ++*rejections;
+}
 }  // namespace dm
 
 // A batch of operators (cavities) whose FP32 V-cycles run as one fused

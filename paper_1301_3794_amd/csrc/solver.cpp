@@ -159,6 +159,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
     DM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
     const double bnorm = std::sqrt(dot1(op, f, f, nullptr, n, s, sp));
     int total = 0, restarts = 0;
+    int learned_rejections = 0;   // learned mode: rejected corrections in this solve
     double rel = 0.0;
     if (bnorm == 0.0) {
         if (info) *info = dm_solve_info{0, 0, 0.0, 0.0, 0, 0};
@@ -190,7 +191,7 @@ int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int max
         int j = 0;
         for (; j < m;) {
             double *uj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
-            precondition(op, mode, uj, zj, s);
+            precondition(op, mode, uj, zj, s, &learned_rejections);
             launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, zj, w, s, L.cut_cells());
             // (1) d = U^T w, then (2) w -= U c with c_i = sc_i^2 d_i formed on
             // the device, fused with d2 = U^T w and |w|^2: one host sync
@@ -378,7 +379,7 @@ double dot1(dm_op *op, const double *x, const double *y, const double *wt, int64
     return op->hres[0];
 }
 
-void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s) {
+void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s, int *rejections) {
     const int64_t n = op->n0();
     if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
         // as in precondition_block: casts over the listed units only
@@ -386,7 +387,10 @@ void precondition(dm_op *op, int mode, const double *v, double *z, hipStream_t s
         if (op->batch && mode == DM_SOLVE_FGMRES_MG32) batch_vcycle_lockstep(op, s);
         else vcycle_graphed(op, 32, s);
         launch_cast<float, double>(op->fg_x32, z, n, s, op->vspan());
-        if (mode == DM_SOLVE_FGMRES_MG32_LEARNED) net_correct(op, v, z, s);
+        if (mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
+            int none = 0;
+            net_correct_patient(op, v, z, rejections ? rejections : &none, s);
+        }
     } else {
         launch_copy(n, v, op->gv_f64, s);
         vcycle_graphed(op, 64, s);
@@ -864,7 +868,8 @@ int solve(dm_op *op, int mode, const double *f, double *x, double rtol, int maxi
 // ---------------------------------------------------------------------------
 namespace {
 
-void precondition_block(dm_op *op, int mode, int nr, const double *const *v, double *const *z, hipStream_t s) {
+void precondition_block(dm_op *op, int mode, int nr, const double *const *v, double *const *z, hipStream_t s,
+                        int *const *rejections = nullptr) {
     const int64_t n = op->n0();
     if (mode == DM_SOLVE_FGMRES_MG32 || mode == DM_SOLVE_FGMRES_MG32_LEARNED) {
         ensure_block(op, 32);
@@ -875,7 +880,10 @@ void precondition_block(dm_op *op, int mode, int nr, const double *const *v, dou
         vcycle_block_graphed(op, 32, nr, s);
         for (int q = 0; q < nr; ++q) launch_cast<float, double>(op->lv[0].bx32 + q * n, z[q], n, s, sp);
         if (mode == DM_SOLVE_FGMRES_MG32_LEARNED)
-            for (int q = 0; q < nr; ++q) net_correct(op, v[q], z[q], s);
+            for (int q = 0; q < nr; ++q) {
+                int none = 0;
+                net_correct_patient(op, v[q], z[q], rejections ? rejections[q] : &none, s);
+            }
     } else {
         ensure_block(op, 64);
         for (int q = 0; q < nr; ++q) launch_copy(n, v[q], op->lv[0].bf64 + q * n, s);
@@ -902,6 +910,7 @@ struct BlockRhs {
     double *x = nullptr;
     double bnorm = 0.0, rel = 0.0;
     int total = 0, restarts = 0, j = 0;
+    int learned_rejections = 0;   // learned mode: rejected corrections in this solve
     bool open = false, done = false, conv = false;
     std::vector<double> H, cs, sn, g, y, h, h2, c3, cx, sc, sc2;   // as in fgmres()
 };
@@ -1018,9 +1027,11 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         VPtr<const float> zc32{};
         VPtr<double> wv{};
         float *zout32[kMaxRhs];
+        int *rej[kMaxRhs];
         for (int q = 0; q < na; ++q) {
             const int r = act[q];
             vin[q] = Vc(r, st[r].j);
+            rej[q] = &st[r].learned_rejections;
             if (z32) {
                 zout32[q] = Zc32(r, st[r].j);
                 zc32.p[q] = zout32[q];
@@ -1037,7 +1048,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             precondition_block_f32(op, na, vin, zout32, s);
             launch_apply_m_f32in(L.g, L.coef64, op->sigma, na, zc32, wv, s, L.cut_cells_rows());
         } else {
-            precondition_block(op, mode, na, vin, zout, s);
+            precondition_block(op, mode, na, vin, zout, s, rej);
             launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_M, na, VPtr<const double>{}, zc, wv, s,
                                    L.cut_cells_rows());
         }

@@ -7,7 +7,11 @@ at 128^3, sigma = 5, the 4 lowest eigenpairs to rho <= 1e-10 with the
 FP32-multigrid solve mode and with the learned one; same seed, same
 tolerance.  Checked: both converge to the same eigenvalues (1e-9), most
 corrections are kept by the residual judge, and the learned mode needs
-fewer inner iterations.  Printed: inner iterations and wall times of both.
+fewer inner iterations.  Recorded beside them: the wall time of both
+eigensolves.  The learned form loses there: each correction costs three
+convolution launches and two FP64 residuals, more than the V-cycles it
+saves (measured 0.47 against 0.23 s per pair for 14% fewer inner
+iterations), so the wall-time ratio is printed, not asserted.
 """
 import numpy as np
 import pytest
@@ -37,6 +41,9 @@ def test_learned_gain_on_unseen_sphere():
     print("plain   inner its", plain["inner_iterations"], "s", round(plain["seconds"], 3))
     print("learned inner its", learned["inner_iterations"], "s", round(learned["seconds"], 3),
           "kept", s["learned_accepted"], "of", s["iterations"])
+    print("[result] wall-time ratio learned / plain", round(learned["seconds"] / plain["seconds"], 3),
+          "inner-iteration ratio", round(learned["inner_iterations"] / plain["inner_iterations"], 3), flush=True)
+    assert plain["seconds"] > 0 and learned["seconds"] > 0
     assert plain["status"] == 0 and learned["status"] == 0
     assert np.max(abs(learned["lam"] - plain["lam"]) / plain["lam"]) <= 1e-9
     assert s["learned_accepted"] >= 0.5 * s["iterations"]
