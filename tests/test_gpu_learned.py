@@ -46,7 +46,7 @@ def case():
     from paper_1301_3794_amd import dm
     g = geo.Ellipsoid((0.5, 0.4, 0.6), (0.42, 0.33, 0.5))
     fr = geo.fractions(g, N, H)
-    op = dm.Operator(dm.user_fractions(lay.fractions_to_padded(fr, N)), N, H, SIGMA, levels=3)
+    op = dm.Operator(dm.user_fractions(lay.fractions_to_padded(fr, N)), N, H, SIGMA, levels=3, learned_patience=0)
     net = dm.Net(seed=1)
     w = (np.random.default_rng(11).standard_normal(ln.N_WEIGHTS) * 0.15).astype(np.float32)
     net.set_weights(w)
@@ -216,6 +216,32 @@ def test_learned_solve_and_eigenvalues(case):
     o = ops.build(case["fr"], N, H, SIGMA)
     w_ref = oeigs.lanczos_eigs(o, 4, sigma_o=SIGMA, block=4, tol=1e-11)[0]
     assert np.max(abs(res["lam"] - w_ref) / w_ref) <= 1e-9
+
+
+def test_learned_patience_stops_rejected_corrections(case):
+    """With learned_patience = 1 a solve stops trying the correction after its
+    first rejection; an untrained network (its corrections are mostly
+    rejected) then leaves the solve to the plain V-cycle.  Same solution as
+    the plain FP32-multigrid mode (1e-9)."""
+    dm = case["dm"]
+    net = dm.Net(seed=5)
+    with dm.Operator(dm.user_fractions(lay.fractions_to_padded(case["fr"], N)), N, H, SIGMA, levels=3,
+                     learned_patience=1) as op:
+        net.attach(op)
+        f = op.apply(dm.APPLY_A, seeded_face_vector(case, 41), op.face_tensor())
+        x = op.face_tensor()
+        out = op.solve(f, x, mode=dm.SOLVE_FGMRES_MG32_LEARNED, rtol=1e-11, maxit=300)
+        ref = op.face_tensor()
+        op.solve(f, ref, mode=dm.SOLVE_FGMRES_MG32, rtol=1e-11, maxit=300)
+        dm.Net.detach(op)
+    net.close()
+    print("patience 1: accepted", out["learned_accepted"], "rejected", out["learned_rejected"], "its",
+          out["iterations"])
+    assert out["status"] == 0
+    assert out["learned_rejected"] <= 1
+    if out["learned_rejected"] == 1:
+        assert out["learned_accepted"] + out["learned_rejected"] < out["iterations"] or out["iterations"] <= 1
+    assert float((x - ref).abs().max() / ref.abs().max()) <= 1e-9
 
 
 def test_learned_mode_needs_a_network(case):
