@@ -145,11 +145,12 @@ def parse():
     ap.add_argument("--skip-learned", action="store_true", help="do not train and time the learned form")
     ap.add_argument("--skip-c3", action="store_true", help="do not run the 9-cell quarter cavity")
     ap.add_argument("--skip-c4", action="store_true", help="do not run the 64 batched ellipsoids")
-    ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep"], default=None,
+    ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep", "studies"], default=None,
                     help="profiling runs: only the 9-cell cavity, only the batch, the HBM-traffic "
                          "probe (a 256 MiB device copy of known size, then 3 FP32 red-black sweeps "
                          "on the 128^3 sphere's finest level), or the same probe on the 9-cell "
-                         "quarter's finest level (3 one-vector and 3 two-vector sweeps)")
+                         "quarter's finest level (3 one-vector and 3 two-vector sweeps), or only "
+                         "the accuracy and solver-sensitivity studies")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
@@ -276,6 +277,20 @@ def run_c1(dm, torch, reps=5):
             "outer_iterations": out["outer_iterations"], "inner_iterations": out["inner_iterations"]}
 
 
+def run_studies(dm):
+    """The paper's accuracy study (Sec. 6.2, Fig. freqErr3d): relative
+    frequency error of the sphere octant's lowest mode against resolution,
+    every cut face kept and faces below a_min = 0.1 neglected."""
+    from paper_1301_3794_amd import studies
+    fc = studies.frequency_convergence(ns=(16, 24, 32, 48, 64), a_mins=(0.0, 0.1))
+    return {"f1_frequency_convergence": {
+        "workload": "sphere R=0.45 octant, n^3 cells of [0,0.5]^3, conducting symmetry planes, lowest mode "
+                    "(TM, degree 3, x y z angular part)",
+        "k0": fc["k0"], "orders_finest3": fc["orders_finest3"],
+        "rows": [{k: r[k] for k in ("a_min", "n", "wavelengths_per_cell", "lam", "rel_freq_err", "residual")}
+                 for r in fc["rows"]]}}
+
+
 def run_c4(dm, torch):
     """Secondary figures on 64 batched ellipsoidal cavities: semi-axes uniform
     in [0.3, 0.48] (NumPy generator, seed 0), centred in the unit cube, grids
@@ -328,6 +343,9 @@ def main():
         return
     if args.only == "c4":
         print(json.dumps({"c4_batched_ellipsoids": run_c4(dm, torch)}))
+        return
+    if args.only == "studies":
+        print(json.dumps(run_studies(dm)))
         return
     if args.only == "c3sweep":
         n = 64 * 1024 * 1024
@@ -448,6 +466,9 @@ def main():
         log("9-cell quarter cavity")
         c3 = run_c3(dm, torch, copy_gbps)
 
+    log("studies")
+    st = run_studies(dm)
+
     c4 = None
     if not args.skip_c4:
         log("64 batched ellipsoids")
@@ -489,6 +510,7 @@ def main():
         "c1_small": c1,
         "c3_9cell_quarter": c3,
         "c4_batched_ellipsoids": c4,
+        "studies": st,
     }
     print(json.dumps(line))
     op.close()

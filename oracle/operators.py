@@ -190,7 +190,10 @@ def build(fr, n, h, sigma=0.0) -> DMOperators:
 
 def apply_face_neglect(fr: dict, a_min: float) -> dict:
     """Face neglect of Sec. 3: faces with 0 < a < a_min are set to zero
-    (their b is removed) and every edge of such a face gets l = 0."""
+    (their b is removed) and every edge of such a face gets l = 0.  A cell
+    left without any open face holds no field; its volume is set to zero
+    too (reading: otherwise its scalar unknown would be an isolated island
+    of the projection's D A D^T)."""
     out = {k: v.copy() for k, v in fr.items()}
     nz, ny, nxp = fr["ax"].shape
     n = (nxp - 1, ny, nz)
@@ -206,6 +209,11 @@ def apply_face_neglect(fr: dict, a_min: float) -> dict:
     l[edges] = 0.0
     for s, arr in zip(("ax", "ay", "az"), g.split_faces(a)):
         out[s] = arr.copy()
+    # cells with no open face among their six
+    open_faces = abs(div(g)) @ (a > 0.0).astype(float)
+    v = out["v"].ravel().copy()
+    v[open_faces == 0.0] = 0.0
+    out["v"] = v.reshape(fr["v"].shape)
     eoff = g.edge_off
     for ax, s in enumerate(("lx", "ly", "lz")):
         out[s] = l[eoff[ax]:eoff[ax + 1]].reshape(g.edge_shapes[ax]).copy()

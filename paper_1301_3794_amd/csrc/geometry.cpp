@@ -397,6 +397,17 @@ void neglect_faces(const Grid &g, double a_min, std::vector<double> &fr) {
                 fr[4 * P + p] = fr[4 * P + p + 1] = 0.0;
             }
         }
+    // a cell left without any open face holds no field: its volume goes too
+    // (else its scalar unknown is an island of the projection's D A D^T)
+    for (int k = 0; k < g.nz; ++k)
+        for (int j = 0; j < g.ny; ++j)
+            for (int i = 0; i < g.nx; ++i) {
+                const int64_t p = pidx(g, i, j, k);
+                if (!(fr[6 * P + p] > 0.0)) continue;
+                const bool open = fr[p] > 0.0 || fr[p + 1] > 0.0 || fr[P + p] > 0.0 || fr[P + p + dy] > 0.0 ||
+                                  fr[2 * P + p] > 0.0 || fr[2 * P + p + dz] > 0.0;
+                if (!open) fr[6 * P + p] = 0.0;
+            }
 }
 
 // Coarse fractions: a coarse face is the union of its 4 sub-faces, a coarse

@@ -171,3 +171,22 @@ def test_face_neglect_removes_faces_and_their_edges():
     Ct = ops.curl_t(g)
     edges = np.unique(Ct[:, dropped].tocoo().row)
     assert np.all(g.edge_vector(out)[edges] == 0.0)
+
+
+def test_face_neglect_drops_cells_left_closed():
+    """A cell all of whose six faces are neglected (here a box cell whose
+    faces are made small by hand) gets v = 0; a cell keeping one open face
+    keeps its volume."""
+    n = (4, 4, 4)
+    fr = geo.fractions(geo.Box(), n, 0.25)
+    i, j, k = 1, 2, 1
+    for s, idx in (("ax", [(k, j, i), (k, j, i + 1)]), ("ay", [(k, j, i), (k, j + 1, i)]),
+                   ("az", [(k, j, i), (k + 1, j, i)])):
+        for t in idx:
+            fr[s][t] = 0.05
+    out = ops.apply_face_neglect(fr, 0.1)
+    assert out["v"][k, j, i] == 0.0
+    assert np.count_nonzero(out["v"]) == 63
+    fr["az"][k + 1, j, i] = 0.5          # one face stays open
+    out = ops.apply_face_neglect(fr, 0.1)
+    assert out["v"][k, j, i] == 1.0
