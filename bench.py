@@ -280,15 +280,22 @@ def run_c1(dm, torch, reps=5):
 def run_studies(dm):
     """The paper's accuracy study (Sec. 6.2, Fig. freqErr3d): relative
     frequency error of the sphere octant's lowest mode against resolution,
-    every cut face kept and faces below a_min = 0.1 neglected."""
+    every cut face kept and faces below a_min = 0.1 neglected; and its
+    solver-sensitivity study (Sec. 6.1, Table volPert1; V^-1 left out; the
+    tilde form of eq. fullMat2): average inner iterations.""" 
     from paper_1301_3794_amd import studies
     fc = studies.frequency_convergence(ns=(16, 24, 32, 48, 64), a_mins=(0.0, 0.1))
+    ss = studies.solver_sensitivity(n=32)
     return {"f1_frequency_convergence": {
         "workload": "sphere R=0.45 octant, n^3 cells of [0,0.5]^3, conducting symmetry planes, lowest mode "
                     "(TM, degree 3, x y z angular part)",
         "k0": fc["k0"], "orders_finest3": fc["orders_finest3"],
         "rows": [{k: r[k] for k in ("a_min", "n", "wavelengths_per_cell", "lam", "rel_freq_err", "residual")}
-                 for r in fc["rows"]]}}
+                 for r in fc["rows"]]},
+        "f2_solver_sensitivity": {
+        "workload": "sphere R=0.49 at 32^3, sigma=5, M x = A w for 3 seeded w, FGMRES(40) to 1e-6, FP64 V-cycle; "
+                    "volume errors on cut cells, 3 draws each; iteration cap 2000",
+        "rows": ss["rows"]}}
 
 
 def run_c4(dm, torch):

@@ -120,6 +120,20 @@ typedef struct {
                             network's correction after this many rejections (the
                             correction no longer lowers the residual there); 0
                             never stops.  (1) */
+    /* Solver-sensitivity variants (Sec. 6.1 and Sec. 5.3), not for production
+       runs; they change the operator or the preconditioner, not what the
+       eigensolve converges to: */
+    int grad_div_volume;  /* 1: the grad-div term is A D^T V^-1 D A (the method,
+                            eq. discLaplDM); 0: V^-1 is left out, A D^T D A, on
+                            every level (Sec. 6.1: inversions no longer
+                            converge in reasonable time).  (1) */
+    int tilde_transfers;  /* 0: the V-cycle of M; 1: the same V-cycle built for
+                            the symmetric form of eq. fullMat2, M~ = A^-1/2 M
+                            A^-1/2 (transfers P~ = A_f^-1/2 P A_c^1/2 and
+                            R~ = P~^T / 8 in the variables of M; the smoother
+                            is unchanged by the scaling).  Single-vector
+                            V-cycles only: the block entry points and dm_eigs
+                            refuse it.  (0) */
 } dm_options;
 
 /* Fills `opt` with the defaults listed above. */

@@ -93,8 +93,8 @@ def prolongation(gf: ops.YeeGrid, gc: ops.YeeGrid, mask_f, mask_c, a_c) -> sp.cs
 
 
 class Level:
-    def __init__(self, fr, n, h, sigma):
-        self.op = ops.build(fr, n, h, sigma)
+    def __init__(self, fr, n, h, sigma, grad_div_volume=True):
+        self.op = ops.build(fr, n, h, sigma, grad_div_volume)
         self.fr = fr
         self.n = tuple(n)
         self.h = h
@@ -121,7 +121,13 @@ class VCycle:
 
     ORDER = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (2, 1)]
 
-    def __init__(self, fr, n, h, sigma, levels, nu1=2, nu2=2):
+    def __init__(self, fr, n, h, sigma, levels, nu1=2, nu2=2, grad_div_volume=True, tilde=False):
+        """grad_div_volume=False: every level's M without V^-1 (Sec. 6.1
+        variant).  tilde=True: the V-cycle built for the symmetric form of
+        eq. fullMat2, M~ = A^-1/2 M A^-1/2, written in the variables of M:
+        its transfers become P~ = A_f^-1/2 P A_c^1/2 and R~ = P~^T / 8, and
+        Gauss--Seidel and the coarsest solve are unchanged by the diagonal
+        scaling (Sec. 5.3 variant)."""
         self.nu1, self.nu2 = nu1, nu2
         self.levels = []
         self.P = []
@@ -133,10 +139,15 @@ class VCycle:
                 fr = coarsen_fractions(fr)
                 n = tuple(x // 2 for x in n)
                 h = 2.0 * h
-            self.levels.append(Level(fr, n, h, sigma))
+            self.levels.append(Level(fr, n, h, sigma, grad_div_volume))
         for lev in range(levels - 1):
             f, c = self.levels[lev], self.levels[lev + 1]
-            self.P.append(prolongation(f.op.grid, c.op.grid, f.active, c.active, c.op.a))
+            P = prolongation(f.op.grid, c.op.grid, f.active, c.active, c.op.a)
+            if tilde:
+                sf = np.where(f.active, 1.0 / np.sqrt(np.where(f.active, f.op.a, 1.0)), 0.0)
+                sc = np.sqrt(np.where(c.active, c.op.a, 0.0))
+                P = (sp.diags(sf) @ P @ sp.diags(sc)).tocsr()
+            self.P.append(P)
         last = self.levels[-1]
         sel = last.op.act
         self.coarse_sel = sel

@@ -146,6 +146,9 @@ class DMOperators:
     grid: YeeGrid
     fr: dict
     sigma: float
+    # False: the grad-div term without V^-1, A D^T D A (the solver-sensitivity
+    # variant of Sec. 6.1 that leaves the inverse volumes out)
+    grad_div_volume: bool = True
 
     def __post_init__(self):
         g = self.grid
@@ -157,6 +160,8 @@ class DMOperators:
         self.A = sp.diags(self.a)
         self.L = sp.diags(self.l)
         vinv = np.where(self.v > 0.0, 1.0 / np.where(self.v > 0.0, self.v, 1.0), 0.0)
+        if not self.grad_div_volume:
+            vinv = (self.v > 0.0).astype(float)
         self.Vinv = sp.diags(vinv)
         self.K = (self.Ct.T @ self.L @ self.Ct).tocsr()
         DA = (self.D @ self.A).tocsr()
@@ -175,7 +180,7 @@ class DMOperators:
         self.v_a = self.v[self.cact]
 
     def with_shift(self, sigma):
-        return DMOperators(self.grid, self.fr, sigma)
+        return DMOperators(self.grid, self.fr, sigma, self.grad_div_volume)
 
     def full_face(self, x_active):
         """Scatter an active-face vector into the full face numbering."""
@@ -184,8 +189,8 @@ class DMOperators:
         return out
 
 
-def build(fr, n, h, sigma=0.0) -> DMOperators:
-    return DMOperators(YeeGrid(n, h), fr, sigma)
+def build(fr, n, h, sigma=0.0, grad_div_volume=True) -> DMOperators:
+    return DMOperators(YeeGrid(n, h), fr, sigma, grad_div_volume)
 
 
 def apply_face_neglect(fr: dict, a_min: float) -> dict:

@@ -143,6 +143,8 @@ void dm_default_options(dm_options *opt) {
     opt->verbose = 0;
     opt->cut_wave_split = 32768;
     opt->learned_patience = 1;
+    opt->grad_div_volume = 1;
+    opt->tilde_transfers = 0;
 }
 
 void dm_default_eig_options(dm_eig_options *opt) {
@@ -221,7 +223,8 @@ int dm_build_operator(const dm_geometry *geom, const int dims[3], double h, doub
         if (op->opt.levels <= 0) op->opt.levels = auto_levels(dims);
         if (op->opt.nu_pre < 0 || op->opt.nu_post < 0 || op->opt.fgmres_restart < 1 ||
             op->opt.fgmres_restart > kMaxDots - 2 || op->opt.cut_wave_split < 0 ||
-            op->opt.learned_patience < 0)
+            op->opt.learned_patience < 0 || (op->opt.grad_div_volume != 0 && op->opt.grad_div_volume != 1) ||
+            (op->opt.tilde_transfers != 0 && op->opt.tilde_transfers != 1))
             return fail(DM_EINVAL, "bad smoothing, restart or wave-split option");
         const int div = 1 << (op->opt.levels - 1);
         for (int a = 0; a < 3; ++a)
@@ -413,6 +416,7 @@ int dm_vcycle(dm_op *op, int prec, const void *f, void *x, void *stream) {
 }
 
 int dm_vcycle_block(dm_op *op, int prec, int nrhs, const void *const *f, void *const *x, void *stream) {
+    if (op && op->opt.tilde_transfers) return fail(DM_EINVAL, "tilde transfers: single-vector V-cycles only");
     if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
     if (nrhs < 1 || nrhs > kMaxRhs) return fail(DM_EINVAL, "nrhs must be 1..4");
@@ -487,6 +491,7 @@ int dm_solve_pcg_noalloc(dm_op *op, const double *f, double *x, double rtol, int
 
 int dm_solve_block(dm_op *op, int mode, int nrhs, const double *const *f, double *const *x, double rtol,
                    int maxit, dm_solve_info *info, void *stream) {
+    if (op && op->opt.tilde_transfers) return fail(DM_EINVAL, "tilde transfers: single-vector solves only");
     if (!op || !f || !x) return fail(DM_EINVAL, "NULL argument");
     if (nrhs < 1 || nrhs > kMaxRhs) return fail(DM_EINVAL, "nrhs must be 1..4");
     if (mode < DM_SOLVE_FGMRES_MG64 || mode > DM_SOLVE_FGMRES_MG32_LEARNED)
@@ -505,6 +510,7 @@ int dm_solve_block(dm_op *op, int mode, int nrhs, const double *const *f, double
 int dm_eigs(dm_op *op, int k, double sigma, double tol, uint64_t seed, const dm_eig_options *opt,
             double *lambda_host, double *vecs_dev, double *residuals_host, dm_eig_info *info,
             void *stream) {
+    if (op && op->opt.tilde_transfers) return fail(DM_EINVAL, "tilde transfers: linear solves only (no eigensolve)");
     if (!op || !lambda_host) return fail(DM_EINVAL, "NULL argument");
     if (k < 1) return fail(DM_EINVAL, "k must be >= 1");
     if (!(tol > 0.0)) return fail(DM_EINVAL, "tol must be positive");
@@ -542,6 +548,8 @@ static void free_batch(dm_batch *b) {
 
 int dm_batch_create(int count, const dm_geometry *geoms, const int *dims, const double *h, double sigma,
                     const dm_options *opt, dm_batch **out) {
+    if (opt && (opt->tilde_transfers || !opt->grad_div_volume))
+        return fail(DM_EINVAL, "batched cavities: the solver-sensitivity variants are not supported");
     if (!out) return fail(DM_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 1 || !geoms || !dims || !h) return fail(DM_EINVAL, "bad batch arguments");

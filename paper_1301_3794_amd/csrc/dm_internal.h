@@ -527,5 +527,11 @@ void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, 
 void launch_mask_mul(int64_t n, const double *mask, double *x, hipStream_t s);
 // x = in on the mask's nonzero entries, 0 elsewhere
 void launch_copy_masked(int64_t n, const double *in, const double *mask, double *x, hipStream_t s);
+// tilde-form transfers: x *= a^(power/2) per face (coef: the level's
+// coefficient blocks, whose first 3P entries are ax ay az); x += a^(-1/2) r
+template <class T>
+void launch_scale_a(int64_t n, const T *coef, int power, T *x, hipStream_t s);
+template <class T>
+void launch_add_scaled_a(int64_t n, const T *coef, const T *r, T *x, hipStream_t s);
 
 }  // namespace dm

@@ -1406,6 +1406,27 @@ __global__ void k_randn(int64_t n, uint64_t seed, int64_t offset, const double *
     }
 }
 
+// The transfers of the tilde form (eq. fullMat2): entry e of a face vector
+// scaled by a^(1/2) (power > 0) or a^(-1/2) (power < 0) of its own face,
+// a = coef[e] (the first three coefficient blocks are ax ay az in the face
+// vector's layout); inactive entries become 0
+template <class T>
+__global__ void k_scale_a(int64_t n, const T *__restrict__ a, int power, T *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+        const T ae = a[e];
+        x[e] = ae > T(0) ? (power > 0 ? x[e] * sqrt(ae) : x[e] / sqrt(ae)) : T(0);
+    }
+}
+
+// x += a^(-1/2) r on the active entries
+template <class T>
+__global__ void k_add_scaled_a(int64_t n, const T *__restrict__ a, const T *__restrict__ r, T *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+        const T ae = a[e];
+        if (ae > T(0)) x[e] += r[e] / sqrt(ae);
+    }
+}
+
 // x = in where mask != 0, else 0
 __global__ void k_copy_masked(int64_t n, const double *__restrict__ in, const double *__restrict__ mask,
                               double *__restrict__ x) {
@@ -2048,6 +2069,19 @@ void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, 
 void launch_copy_masked(int64_t n, const double *in, const double *mask, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_masked, flat_grid(n), dim3(kThreads), 0, s, n, in, mask, x);
 }
+
+template <class T>
+void launch_scale_a(int64_t n, const T *coef, int power, T *x, hipStream_t s) {
+    hipLaunchKernelGGL((k_scale_a<T>), flat_grid(n), dim3(kThreads), 0, s, n, coef, power, x);
+}
+template <class T>
+void launch_add_scaled_a(int64_t n, const T *coef, const T *r, T *x, hipStream_t s) {
+    hipLaunchKernelGGL((k_add_scaled_a<T>), flat_grid(n), dim3(kThreads), 0, s, n, coef, r, x);
+}
+template void launch_scale_a<double>(int64_t, const double *, int, double *, hipStream_t);
+template void launch_scale_a<float>(int64_t, const float *, int, float *, hipStream_t);
+template void launch_add_scaled_a<double>(int64_t, const double *, const double *, double *, hipStream_t);
+template void launch_add_scaled_a<float>(int64_t, const float *, const float *, float *, hipStream_t);
 
 // explicit instantiations
 #define DM_BLOCK_INST(T)                                                                                   \

@@ -96,12 +96,13 @@ void mirror_faces_host(const Grid &g, double *x) {
     }
 }
 
-std::vector<double> to_coefs(const Grid &g, const std::vector<double> &fr) {
+// use_v = false: the grad-div term without V^-1 (1 on every cell with v > 0)
+std::vector<double> to_coefs(const Grid &g, const std::vector<double> &fr, bool use_v) {
     std::vector<double> c(fr.begin(), fr.end());
     const int64_t P = g.P;
     for (int64_t p = 0; p < P; ++p) {
         const double v = fr[6 * P + p];
-        c[6 * P + p] = v > 0.0 ? 1.0 / v : 0.0;
+        c[6 * P + p] = v > 0.0 ? (use_v ? 1.0 / v : 1.0) : 0.0;
     }
     return c;
 }
@@ -240,7 +241,7 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         L.g = grids[l];
         L.cut_wave_split = op->opt.cut_wave_split;
         const int64_t P = L.g.P;
-        std::vector<double> c = to_coefs(L.g, op->frac[l]);
+        std::vector<double> c = to_coefs(L.g, op->frac[l], op->opt.grad_div_volume != 0);
         std::vector<float> c32(c.begin(), c.end());
         const std::vector<uint8_t> fl = row_flags(L.g, c);
         // coefficient blocks followed by the P row-class bytes
@@ -444,7 +445,7 @@ void factor_coarse(dm_op *op) {
     Level &L = op->lv.back();
     const Grid &g = L.g;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
-    std::vector<double> c = to_coefs(g, op->frac.back());
+    std::vector<double> c = to_coefs(g, op->frac.back(), op->opt.grad_div_volume != 0);
     Coefs<double> cf = coefs_of(c.data(), P);
     const double ih2 = 1.0 / (g.h * g.h);
     // ---- vector

@@ -426,9 +426,21 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
     launch_apply<T>(g, c, sig, AK_RESID, f, x, r, s, L.cut_cells());
     Level &C = op->lv[l + 1];
     T *fc = Prec<T>::f(C), *xc = Prec<T>::x(C);
-    launch_restrict<T>(g, C.g, Prec<T>::coef(C), r, fc, s);
+    const T *cc = Prec<T>::coef(C);
+    // tilde form (eq. fullMat2): transfers A_c^1/2 R A_f^-1/2 and A_f^-1/2 P A_c^1/2
+    const bool tilde = op->opt.tilde_transfers != 0;
+    if (tilde) launch_scale_a<T>(3 * g.P, c, -1, r, s);
+    launch_restrict<T>(g, C.g, cc, r, fc, s);
+    if (tilde) launch_scale_a<T>(3 * C.g.P, cc, +1, fc, s);
     vcycle<T>(op, l + 1, fc, xc, s);
-    launch_prolong_add<T>(g, C.g, c, Prec<T>::coef(C), xc, x, s);
+    if (tilde) {
+        launch_scale_a<T>(3 * C.g.P, cc, +1, xc, s);
+        launch_zero<T>(3 * g.P, r, s);
+        launch_prolong_add<T>(g, C.g, c, cc, xc, r, s);
+        launch_add_scaled_a<T>(3 * g.P, c, r, x, s);
+    } else {
+        launch_prolong_add<T>(g, C.g, c, cc, xc, x, s);
+    }
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int comp = 2; comp >= 0; --comp)
             for (int col = 1; col >= 0; --col) launch_smooth<T>(g, c, sig, comp, col, f, x, s, L.cut_list(comp, col));

@@ -66,7 +66,8 @@ class Geometry(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("fgmres_restart", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("cut_wave_split", ctypes.c_int), ("learned_patience", ctypes.c_int)]
+                ("cut_wave_split", ctypes.c_int), ("learned_patience", ctypes.c_int),
+                ("grad_div_volume", ctypes.c_int), ("tilde_transfers", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -258,7 +259,8 @@ class Operator:
     """A built operator hierarchy (``dm_build_operator``)."""
 
     def __init__(self, geom: Geometry, dims, h, sigma, levels=0, nu_pre=2, nu_post=2,
-                 fgmres_restart=30, verbose=0, cut_wave_split=None, learned_patience=None):
+                 fgmres_restart=30, verbose=0, cut_wave_split=None, learned_patience=None,
+                 grad_div_volume=None, tilde_transfers=None):
         L = lib()
         opt = Options()
         L.dm_default_options(ctypes.byref(opt))
@@ -268,6 +270,10 @@ class Operator:
             opt.cut_wave_split = int(cut_wave_split)
         if learned_patience is not None:
             opt.learned_patience = int(learned_patience)
+        if grad_div_volume is not None:
+            opt.grad_div_volume = int(grad_div_volume)
+        if tilde_transfers is not None:
+            opt.tilde_transfers = int(tilde_transfers)
         self._op = ctypes.c_void_p()
         self._net = None
         self.dims = tuple(int(x) for x in dims)

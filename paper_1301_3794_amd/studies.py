@@ -72,3 +72,81 @@ def frequency_convergence(ns=(16, 24, 32, 48, 64), a_mins=(0.0, 0.1), radius=0.4
         sel = [r for r in rows if r["a_min"] == a_min][-3:]
         orders[str(a_min)] = fit_order([r["h"] for r in sel], [r["rel_freq_err"] for r in sel])
     return dict(k0=k0, lambda0=k0 * k0, rows=rows, orders_finest3=orders)
+
+
+# ---------------------------------------------------------------------------
+# Solver sensitivity (Sec. 6.1, Table volPert1; Sec. 5.3, eq. fullMat2)
+# ---------------------------------------------------------------------------
+
+def perturb_volumes(frac7: np.ndarray, kind: str, amount: float, seed: int) -> np.ndarray:
+    """The volume-error models of Sec. 6.1 on the cut cells (0 < v < 1) of a
+    padded fraction array (7 blocks, v last), f uniform in [-1, 1] per cell
+    from a NumPy generator keyed by seed:
+      kind 'log'  (eq. volPert1): v~ = 10^(f eps) v,   eps = amount;
+      kind 'add'  (eq. volPert2): v~ = |v + f dv|,      dv = amount (in cell
+                  volumes; the magnitude keeps a volume positive where the
+                  error exceeds the volume itself).
+    Everything else is left as it is."""
+    out = np.array(frac7, dtype=np.float64, copy=True)
+    v = out[6]
+    cut = np.flatnonzero((v > 0.0) & (v < 1.0))
+    f = np.random.default_rng(seed).uniform(-1.0, 1.0, cut.size)
+    if kind == "log":
+        v[cut] = 10.0 ** (f * amount) * v[cut]
+    elif kind == "add":
+        w = np.abs(v[cut] + f * amount)
+        v[cut] = np.where(w > 0.0, w, v[cut])
+    else:
+        raise ValueError(kind)
+    return out
+
+
+def average_inner_iterations(op: dm.Operator, seeds=(1, 2, 3), rtol=1e-6, maxit=2000, mode=None):
+    """Mean FGMRES iterations of M x = A w for w ~ N(0,1) on the active faces
+    (one right-hand side per seed), and whether every solve converged."""
+    import torch
+    mode = dm.SOLVE_FGMRES_MG64 if mode is None else mode
+    mask = torch.tensor(op.fractions(0)[:3].reshape(-1) > 0)
+    its, ok = [], True
+    for sd in seeds:
+        w = (torch.randn(mask.numel(), dtype=torch.float64, generator=torch.Generator().manual_seed(sd)) * mask).cuda()
+        f = op.apply(dm.APPLY_A, w, op.face_tensor())
+        out = op.solve(f, op.face_tensor(), mode=mode, rtol=rtol, maxit=maxit)
+        its.append(out["iterations"])
+        ok &= out["status"] == 0
+    return float(np.mean(its)), bool(ok)
+
+
+def solver_sensitivity(n=32, radius=0.49, sigma=5.0, eps=(0.1, 0.3, 0.5, 1.0, 2.0, 3.0), dv=(1e-5, 1e-4, 1e-3),
+                       trials=3, restart=40, rtol=1e-6, maxit=2000):
+    """Average inner iterations of the sphere (radius 0.49 of the unit box,
+    as in Sec. 6.1) at n^3 for the method and its variants: volume errors of
+    eq. volPert1 (eps) and eq. volPert2 (dv, in cell volumes), `trials`
+    perturbations each; V^-1 left out of the operator; the tilde form's
+    V-cycle (eq. fullMat2).  FGMRES(restart), FP64 V-cycle, tolerance rtol
+    as in the paper (1e-6)."""
+    h = 1.0 / n
+    geom = dm.sphere((0.5, 0.5, 0.5), radius)
+    frac = dm.compute_fractions(geom, (n, n, n), h).reshape(7, -1)
+    rows = []
+
+    def run(label, value, fr7=None, **kw):
+        g = geom if fr7 is None else dm.user_fractions(fr7)
+        with dm.Operator(g, (n, n, n), h, sigma, fgmres_restart=restart, **kw) as op:
+            its, ok = average_inner_iterations(op, rtol=rtol, maxit=maxit)
+        return its, ok
+
+    its, ok = run("method", None)
+    rows.append(dict(variant="method", value=None, avg_iterations=its, converged=ok))
+    for kind, values in (("log", eps), ("add", dv)):
+        for val in values:
+            res = [run(kind, val, perturb_volumes(frac, kind, val, 100 + t)) for t in range(trials)]
+            rows.append(dict(variant="volume error " + ("eq. volPert1, eps" if kind == "log" else
+                                                        "eq. volPert2, dv/v_vac"),
+                             value=val, avg_iterations=float(np.mean([r[0] for r in res])),
+                             converged=all(r[1] for r in res)))
+    its, ok = run("novol", None, grad_div_volume=0)
+    rows.append(dict(variant="V^-1 left out", value=None, avg_iterations=its, converged=ok))
+    its, ok = run("tilde", None, tilde_transfers=1)
+    rows.append(dict(variant="tilde form (eq. fullMat2) V-cycle", value=None, avg_iterations=its, converged=ok))
+    return dict(grid=[n, n, n], radius=radius, sigma=sigma, restart=restart, rtol=rtol, maxit=maxit, rows=rows)

@@ -61,3 +61,57 @@ def test_coarse_fractions_are_geometric(sphere16_frac):
     direct = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), (8, 8, 8), 2 * h, drop_empty=False)
     for s in coarse:
         assert np.max(abs(coarse[s] - direct[s])) < 1e-13
+
+
+def generic_vcycle(levels_M, classes, P, coarse_sel, f, nu=2):
+    """A plain V-cycle for given level matrices: Gauss--Seidel over the given
+    classes (reversed on the way up), restriction P^T / 8, dense coarsest
+    solve -- written out again for the tilde check below."""
+    def cycle(lev, f):
+        M = levels_M[lev]
+        x = np.zeros_like(f)
+        if lev == len(levels_M) - 1:
+            s = coarse_sel
+            x[s] = np.linalg.solve(M[s][:, s].toarray(), f[s])
+            return x
+        d = M.diagonal()
+        order = classes[lev]
+        for _ in range(nu):
+            for ids in order:
+                x[ids] += (f[ids] - M[ids] @ x) / d[ids]
+        r = f - M @ x
+        x += P[lev] @ cycle(lev + 1, (P[lev].T @ r) / 8.0)
+        for _ in range(nu):
+            for ids in order[::-1]:
+                x[ids] += (f[ids] - M[ids] @ x) / d[ids]
+        return x
+    return cycle(0, f)
+
+
+def test_tilde_vcycle_is_the_vcycle_of_the_scaled_operator(sphere16_frac):
+    """Sec. 5.3, eq. fullMat2: the tilde V-cycle (transfers conjugated by
+    A^1/2) equals A^-1/2 B~ A^-1/2, where B~ is the plain V-cycle built on
+    the scaled matrices M~ = A^-1/2 M A^-1/2 of every level with the
+    unscaled transfers P -- constructed independently here."""
+    import scipy.sparse as sp
+    fr, n, h = sphere16_frac
+    vt = mg.VCycle(fr, n, h, 5.0, 3, tilde=True)
+    vp = mg.VCycle(fr, n, h, 5.0, 3)
+    Ms, cls, inv_sqrt = [], [], []
+    for L in vp.levels:
+        s = np.where(L.active, 1.0 / np.sqrt(np.where(L.active, L.op.a, 1.0)), 0.0)
+        inv_sqrt.append(s)
+        Ms.append((sp.diags(s) @ L.M @ sp.diags(s)).tocsr())
+        cls.append([L.classes[c] for c in vp.ORDER])
+    rng = np.random.default_rng(3)
+    f = np.zeros(vp.levels[0].op.grid.n_faces)
+    act = vp.levels[0].op.act
+    f[act] = rng.standard_normal(act.size)
+    ref = inv_sqrt[0] * generic_vcycle(Ms, cls, vp.P, vp.coarse_sel, inv_sqrt[0] * f)
+    got = vt(f)
+    assert np.max(abs(got - ref)) <= 1e-12 * np.max(abs(ref))
+    # symmetric, and a different preconditioner from the method's
+    u = rng.standard_normal(act.size)
+    lhs, rhs = u @ vt.apply_active(f[act]), f[act] @ vt.apply_active(u)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert np.max(abs(got - vp(f))) > 1e-3 * np.max(abs(got))

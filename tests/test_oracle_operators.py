@@ -190,3 +190,24 @@ def test_face_neglect_drops_cells_left_closed():
     fr["az"][k + 1, j, i] = 0.5          # one face stays open
     out = ops.apply_face_neglect(fr, 0.1)
     assert out["v"][k, j, i] == 1.0
+
+
+def test_spectrum_partition_without_volumes_sphere_6():
+    """The Sec. 6.1 variant without V^-1 (G0 = A D^T D A): the EM modes of
+    (K, A) are still untouched, and the gradient branch becomes the nonzero
+    spectrum of S itself (V replaced by the identity), so the variant moves
+    only the gradient modes -- which is why it can change the solver's
+    convergence and not the eigenpairs."""
+    n, h = (6, 6, 6), 1.0 / 6
+    fr = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), n, h)
+    op = ops.build(fr, n, h, 0.0, grad_div_volume=False)
+    a = op.a_a
+    w_all = sl.eigh((op.K_a + op.G_a).toarray(), np.diag(a), eigvals_only=True)
+    wk = sl.eigh(op.K_a.toarray(), np.diag(a), eigvals_only=True)
+    ws = sl.eigvalsh(op.S_a.toarray())
+    union = np.sort(np.concatenate([wk[wk > 1e-9 * wk.max()], ws[ws > 1e-9 * ws.max()]]))
+    assert union.size == w_all.size
+    assert np.max(abs(np.sort(w_all) - union) / union) < 1e-10
+    # and it differs from the method's G exactly where cut cells have v < 1
+    full = ops.build(fr, n, h, 0.0)
+    assert abs(full.G_a - op.G_a).max() > 0.1 * abs(full.G_a).max()
