@@ -282,7 +282,9 @@ def run_studies(dm):
     frequency error of the sphere octant's lowest mode against resolution,
     every cut face kept and faces below a_min = 0.1 neglected; and its
     solver-sensitivity study (Sec. 6.1, Table volPert1; V^-1 left out; the
-    tilde form of eq. fullMat2): average inner iterations.""" 
+    tilde form of eq. fullMat2): average inner iterations; and a general
+    geometry: the sphere as a sampled level set with tetrahedral volumes
+    (Sec. 6.1), converging to the analytic fractions' results."""
     from paper_1301_3794_amd import studies
     fc = studies.frequency_convergence(ns=(16, 24, 32, 48, 64), a_mins=(0.0, 0.1))
     ss = studies.solver_sensitivity(n=32)
@@ -295,7 +297,11 @@ def run_studies(dm):
         "f2_solver_sensitivity": {
         "workload": "sphere R=0.49 at 32^3, sigma=5, M x = A w for 3 seeded w, FGMRES(40) to 1e-6, FP64 V-cycle; "
                     "volume errors on cut cells, 3 draws each; iteration cap 2000",
-        "rows": ss["rows"]}}
+        "rows": ss["rows"]},
+        "f4_general_geometry": dict(
+            workload="sphere R=0.45 at 32^3 as a level set |x-c|-R sampled on the grid refined s times, "
+                     "tetrahedral fractions; lowest 3 eigenvalues against the analytic fractions'",
+            **studies.levelset_convergence(n=32, refinements=(1, 2, 4, 8)))}
 
 
 def run_c4(dm, torch):

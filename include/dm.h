@@ -73,6 +73,9 @@ extern "C" {
                                     y=axis_xy[1]: beam tube, n_cells elliptic cells,
                                     beam tube (see fields below) */
 #define DM_GEOM_USER         3   /* caller-supplied fractions */
+#define DM_GEOM_LEVELSET     4   /* general cavity {phi < 0} from a sampled level set,
+                                    volumes from conforming tetrahedra (Sec. 6.1);
+                                    see levelset_host */
 
 #define DM_BC_PEC 0              /* perfect electric conductor wall */
 #define DM_BC_PMC 1              /* perfect magnetic conductor symmetry plane */
@@ -101,6 +104,18 @@ typedef struct {
        removed together with the edges around them; 0 keeps every cut face
        (the paper's choice for all its timing runs). */
     double a_min;
+    /* DM_GEOM_LEVELSET: phi (< 0 in the cavity, >= 0 in the conductor) on the
+       nodes of the grid refined s = levelset_refine >= 1 times per cell:
+       (s Nx + 1)(s Ny + 1)(s Nz + 1) host doubles, x fastest, node (I, J, K)
+       at (I, J, K) h / s; read at build time.  The cavity is where the
+       piecewise-linear interpolant of phi on the Kuhn tetrahedra of the
+       refined lattice (6 per refined cube, sharing its main diagonal) is
+       negative, a polyhedron whose facets conform to those tetrahedra; cell
+       volumes are sums of tetrahedral subvolumes, face areas and edge
+       lengths those of the same polyhedron, so all three measure one body
+       and converge with the refinement for smooth surfaces. */
+    const double *levelset_host;
+    int levelset_refine;
 } dm_geometry;
 
 /* ---- options ----------------------------------------------------------- */

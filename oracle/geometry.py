@@ -602,3 +602,125 @@ def count_active_faces(geom, n, h) -> int:
         wall = (idx[:, axis] == 0) | (idx[:, axis] == n[axis])
         total += int(np.sum((cls != 0) & ~wall))
     return total
+
+
+# ---------------------------------------------------------------------------
+# General cavities from a sampled level set: tetrahedral cut-cell volumes
+# (Sec. 6.1: volumes from tetrahedral subvolumes conforming to the surface)
+# ---------------------------------------------------------------------------
+
+def _negative_hull_measure(points, values, dim):
+    """Measure (length, area or volume) of the part of a simplex where the
+    linear interpolant of `values` at its vertices `points` is negative: the
+    convex hull of its negative vertices and of the zero crossings on its
+    edges (the negative part of a simplex under a linear function is convex,
+    with exactly those vertices).  Computed by Qhull; a flat hull has
+    measure 0."""
+    from scipy.spatial import ConvexHull, QhullError
+    pts = [p for p, v in zip(points, values) if v < 0.0]
+    k = len(points)
+    for a in range(k):
+        for b in range(a + 1, k):
+            va, vb = values[a], values[b]
+            if (va < 0.0) != (vb < 0.0):
+                t = va / (va - vb)
+                pts.append(points[a] + t * (points[b] - points[a]))
+    if len(pts) < dim + 1:
+        return 0.0
+    pts = np.array(pts)
+    if dim == 1:
+        return float(pts[:, 0].max() - pts[:, 0].min())
+    try:
+        return float(ConvexHull(pts).volume)
+    except QhullError:
+        return 0.0
+
+
+def levelset_fractions(phi, s, n, drop_empty=True) -> dict:
+    """Cut fractions of {phi_lin < 0} for phi sampled on the nodes of the grid
+    n = (Nx, Ny, Nz) refined s times per cell (array [K, J, I] of shape
+    (s Nz + 1, s Ny + 1, s Nx + 1)), phi_lin the linear interpolant on the
+    Kuhn tetrahedra of the refined lattice (6 per refined cube along its
+    main diagonal; each refined square split along the diagonal through its
+    lowest and highest corner).  Units are cells; all walls conduct.  Every
+    cut simplex is measured as a convex hull (``_negative_hull_measure``)."""
+    nx, ny, nz = n
+    out = {name: np.zeros(shape(n)) for name, shape in FACE_SHAPES.items()}
+    out.update({name: np.zeros(shape(n)) for name, shape in EDGE_SHAPES.items()})
+    out["v"] = np.zeros((nz, ny, nx))
+
+    def val(I, J, K):
+        return phi[K, J, I]
+
+    unit = np.eye(3)
+    # cells: 6 tetrahedra per refined cube
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                block = phi[k * s:(k + 1) * s + 1, j * s:(j + 1) * s + 1, i * s:(i + 1) * s + 1]
+                if block.max() < 0.0:
+                    out["v"][k, j, i] = 1.0
+                    continue
+                if block.min() >= 0.0:
+                    continue
+                vol = 0.0
+                for cz in range(s):
+                    for cy in range(s):
+                        for cx in range(s):
+                            corner = np.array([cx, cy, cz], float)
+                            for pm in perms:
+                                verts = [corner, corner + unit[pm[0]], corner + unit[pm[0]] + unit[pm[1]],
+                                         corner + 1.0]
+                                vals = [block[int(v[2]), int(v[1]), int(v[0])] for v in verts]
+                                vol += _negative_hull_measure(verts, vals, 3)
+                out["v"][k, j, i] = vol / s ** 3
+    # faces normal to axis a, over the other two axes b < d
+    for a, name in enumerate(("ax", "ay", "az")):
+        b, d = [x for x in range(3) if x != a]
+        arr = out[name]
+        for idx in np.ndindex(arr.shape):
+            kk, jj, ii = idx
+            cell = (ii, jj, kk)
+            if cell[a] == 0 or cell[a] == n[a]:
+                continue
+            area = 0.0
+            for u in range(s):
+                for w in range(s):
+                    corners = []
+                    for q in range(4):
+                        node = [cell[0] * s, cell[1] * s, cell[2] * s]
+                        node[b] += u + (q & 1)
+                        node[d] += w + (q >> 1)
+                        corners.append((np.array([u + (q & 1), w + (q >> 1)], float), val(*node)))
+                    for tri in ((0, 1, 3), (0, 2, 3)):
+                        area += _negative_hull_measure([corners[t][0] for t in tri], [corners[t][1] for t in tri], 2)
+            arr[idx] = area / s ** 2
+    # edges along axis a
+    for a, name in enumerate(("lx", "ly", "lz")):
+        b, d = [x for x in range(3) if x != a]
+        arr = out[name]
+        for idx in np.ndindex(arr.shape):
+            kk, jj, ii = idx
+            node0 = (ii, jj, kk)
+            if node0[b] in (0, n[b]) or node0[d] in (0, n[d]):
+                continue
+            length = 0.0
+            for u in range(s):
+                p0 = [node0[0] * s, node0[1] * s, node0[2] * s]
+                p1 = list(p0)
+                p0[a] += u
+                p1[a] += u + 1
+                length += _negative_hull_measure([np.array([0.0]), np.array([1.0])], [val(*p0), val(*p1)], 1)
+            arr[idx] = length / s
+    for name in out:
+        out[name] = np.where(out[name] >= 1e-12, out[name], 0.0)
+    return drop_edges_of_zero_faces(drop_faces_of_empty_cells(out)) if drop_empty else out
+
+
+def sample_levelset(fun, n, h, s):
+    """phi on the nodes of the grid refined s times: fun(x, y, z) at
+    (I, J, K) h / s, array [K, J, I]."""
+    nx, ny, nz = n
+    K, J, I = np.meshgrid(np.arange(s * nz + 1), np.arange(s * ny + 1), np.arange(s * nx + 1), indexing="ij")
+    return fun(I * h / s, J * h / s, K * h / s)

@@ -66,7 +66,7 @@ bool valid_geometry(const dm_geometry *g, std::string &why) {
         why = "geometry is NULL";
         return false;
     }
-    if (g->kind < DM_GEOM_BOX || g->kind > DM_GEOM_USER) {
+    if (g->kind < DM_GEOM_BOX || g->kind > DM_GEOM_LEVELSET) {
         why = "unknown geometry kind";
         return false;
     }
@@ -78,6 +78,10 @@ bool valid_geometry(const dm_geometry *g, std::string &why) {
             }
     if (g->kind == DM_GEOM_USER && !g->user_fractions_host) {
         why = "user geometry without fractions";
+        return false;
+    }
+    if (g->kind == DM_GEOM_LEVELSET && (!g->levelset_host || g->levelset_refine < 1 || g->levelset_refine > 64)) {
+        why = "level-set geometry needs levelset_host and levelset_refine in 1..64";
         return false;
     }
     for (int a = 0; a < 3; ++a)
@@ -188,10 +192,14 @@ int dm_compute_fractions(const dm_geometry *geom, const int dims[3], double h, d
         for (int a = 0; a < 3; ++a)
             if (geom->bc_lo[a] == DM_BC_PMC) pmc |= 1 << a;
         Grid g = make_grid(dims[0], dims[1], dims[2], h, pmc);
-        std::unique_ptr<Body> body = make_body(*geom);
-        if (!body) return fail(DM_EINVAL, "geometry kind not available");
         std::vector<double> fr;
-        compute_fractions(*body, g, geom->bc_lo, fr);
+        if (geom->kind == DM_GEOM_LEVELSET) {
+            compute_levelset_fractions(g, geom->levelset_host, geom->levelset_refine, geom->bc_lo, fr);
+        } else {
+            std::unique_ptr<Body> body = make_body(*geom);
+            if (!body) return fail(DM_EINVAL, "geometry kind not available");
+            compute_fractions(*body, g, geom->bc_lo, fr);
+        }
         enforce_fraction_consistency(g, fr);
         neglect_faces(g, geom->a_min, fr);
         mirror_fraction_ghosts(g, fr);

@@ -29,8 +29,6 @@ namespace dm {
 
 namespace {
 
-constexpr double kZeroFraction = 1e-12;
-
 // Gauss--Legendre nodes/weights on [0,1], computed once by Newton iteration
 struct GaussLegendre {
     std::vector<double> x, w;

@@ -9,6 +9,9 @@
 
 namespace dm {
 
+// computed fractions below this are rounding noise of tangencies and set to 0
+constexpr double kZeroFraction = 1e-12;
+
 // A cavity interior Omega (open set).  Coordinates are physical; the grid
 // origin is 0.  Every method answers for the closed box / segment / face given.
 struct Body {
@@ -32,6 +35,11 @@ double integrate_pieces(const std::function<double(double)> &f, double a, double
                         std::vector<double> cuts);
 void compute_fractions(const Body &body, const Grid &g, const int bc_lo[3],
                        std::vector<double> &out);
+// fractions of {phi < 0} for phi sampled on the nodes of the grid refined s
+// times per cell, interpolated linearly on the Kuhn tetrahedra of the
+// refined lattice (geometry_levelset.cpp)
+void compute_levelset_fractions(const Grid &g, const double *phi, int s, const int bc_lo[3],
+                                std::vector<double> &out);
 void enforce_fraction_consistency(const Grid &g, std::vector<double> &fr);
 void neglect_faces(const Grid &g, double a_min, std::vector<double> &fr);
 void mirror_fraction_ghosts(const Grid &g, std::vector<double> &fr);

@@ -215,6 +215,8 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
     std::vector<double> fr;
     if (op->geom.kind == DM_GEOM_USER) {
         fr.assign(user_frac, user_frac + 7 * g0.P);
+    } else if (op->geom.kind == DM_GEOM_LEVELSET) {
+        compute_levelset_fractions(g0, op->geom.levelset_host, op->geom.levelset_refine, op->geom.bc_lo, fr);
     } else {
         std::unique_ptr<Body> body = make_body(op->geom);
         if (!body) throw DmError{DM_EINVAL, "unknown or unsupported geometry kind"};

@@ -19,7 +19,7 @@ DM_OK = 0
 DM_NOT_CONVERGED = 1
 DM_EINVAL, DM_ENOMEM, DM_EHIP, DM_ESINGULAR, DM_EBREAKDOWN, DM_ENAN, DM_ENODEVICE = range(-1, -8, -1)
 
-GEOM_BOX, GEOM_ELLIPSOID, GEOM_ELLIPTIC_BOR, GEOM_USER = 0, 1, 2, 3
+GEOM_BOX, GEOM_ELLIPSOID, GEOM_ELLIPTIC_BOR, GEOM_USER, GEOM_LEVELSET = 0, 1, 2, 3, 4
 BC_PEC, BC_PMC = 0, 1
 APPLY_M, APPLY_K, APPLY_A, APPLY_DA, APPLY_DT, APPLY_S = range(6)
 SOLVE_PCG64, SOLVE_FGMRES_MG64, SOLVE_FGMRES_MG32, SOLVE_FGMRES_MG32_LEARNED = range(4)
@@ -60,6 +60,8 @@ class Geometry(ctypes.Structure):
         ("user_fractions_host", ctypes.POINTER(ctypes.c_double)),
         ("bc_lo", ctypes.c_int * 3),
         ("a_min", ctypes.c_double),
+        ("levelset_host", ctypes.POINTER(ctypes.c_double)),
+        ("levelset_refine", ctypes.c_int),
     ]
 
 
@@ -223,6 +225,22 @@ def user_fractions(frac7: np.ndarray, bc_lo=(BC_PEC,) * 3) -> Geometry:
     g._keep = arr
     g.user_fractions_host = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     g.bc_lo[:] = list(bc_lo)
+    return g
+
+
+def levelset(phi_nodes: np.ndarray, refine: int, bc_lo=(BC_PEC,) * 3, a_min=0.0) -> Geometry:
+    """General cavity {phi < 0} (DM_GEOM_LEVELSET): phi on the nodes of the
+    grid refined `refine` times per cell, an array of shape
+    (refine Nz + 1, refine Ny + 1, refine Nx + 1) (x fastest).  The array must
+    outlive the build call."""
+    g = Geometry()
+    g.kind = GEOM_LEVELSET
+    arr = np.ascontiguousarray(phi_nodes, dtype=np.float64)
+    g._keep = arr
+    g.levelset_host = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    g.levelset_refine = int(refine)
+    g.bc_lo[:] = list(bc_lo)
+    g.a_min = a_min
     return g
 
 
