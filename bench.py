@@ -284,7 +284,10 @@ def run_studies(dm):
     solver-sensitivity study (Sec. 6.1, Table volPert1; V^-1 left out; the
     tilde form of eq. fullMat2): average inner iterations; and a general
     geometry: the sphere as a sampled level set with tetrahedral volumes
-    (Sec. 6.1), converging to the analytic fractions' results."""
+    (Sec. 6.1), converging to the analytic fractions' results; and the
+    surface-field study (Sec. 6.2, eq. errorNorm): the electric field of the
+    octant's lowest mode on a shell inside the wall against the analytic TM
+    field."""
     from paper_1301_3794_amd import studies
     fc = studies.frequency_convergence(ns=(16, 24, 32, 48, 64), a_mins=(0.0, 0.1))
     ss = studies.solver_sensitivity(n=32)
@@ -301,7 +304,11 @@ def run_studies(dm):
         "f4_general_geometry": dict(
             workload="sphere R=0.45 at 32^3 as a level set |x-c|-R sampled on the grid refined s times, "
                      "tetrahedral fractions; lowest 3 eigenvalues against the analytic fractions'",
-            **studies.levelset_convergence(n=32, refinements=(1, 2, 4, 8)))}
+            **studies.levelset_convergence(n=32, refinements=(1, 2, 4, 8))),
+        "f3_surface_fields": dict(
+            workload="sphere R=0.45 octant as for f1, n = 16..64; e = C^T b / k by trilinear interpolation of the "
+                     "edge values on a shell 3 cells inside the wall, relative l2 error after unit-norm scaling",
+            **studies.surface_field_convergence())}
 
 
 def run_c4(dm, torch):

@@ -467,6 +467,20 @@ int dm_net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float 
 int dm_net_train_pairs(dm_op *op, int kind, int npairs, const double *const *r_dev, const double *const *e_dev,
                        float lr, float *loss_host, void *stream);
 
+/* ---- fields of an eigenpair --------------------------------------------- */
+/* Electric field of an eigenpair (b, lambda = k^2) of the op's finest grid at
+ * npts points (Sec. 6.2, surface fields): e = C^T b / k on every edge with
+ * l > 0 and 0 on the others (the Yee scheme's Ampere law in the frequency
+ * domain, whose Faraday law a b = C L e / k closes K b = lambda A b),
+ * interpolated trilinearly from each component's own edge lattice: e_x at
+ * ((i + 1/2) h, j h, k h), e_y at (i h, (j + 1/2) h, k h), e_z likewise.
+ *   b_dev    one face vector (3P doubles, device), e.g. from dm_eigs.
+ *   pts_host npts x 3 coordinates (host); e_host npts x 3 values (host).
+ * A point whose interpolation stencil leaves the grid gets NaN.  Errors:
+ * DM_EINVAL (lambda <= 0, npts < 0, NULL pointers). */
+int dm_sample_e(dm_op *op, const double *b_dev, double lambda, int npts, const double *pts_host,
+                double *e_host, void *stream);
+
 /* ---- measurement -------------------------------------------------------- */
 #define DM_KERNEL_APPLY     0  /* y = M x on `level` */
 #define DM_KERNEL_RESIDUAL  1  /* r = f - M x on `level` */

@@ -497,6 +497,28 @@ int dm_solve_pcg_noalloc(dm_op *op, const double *f, double *x, double rtol, int
     });
 }
 
+int dm_sample_e(dm_op *op, const double *b, double lambda, int npts, const double *pts, double *e, void *stream) {
+    if (!op || !b || (npts > 0 && (!pts || !e))) return fail(DM_EINVAL, "NULL argument");
+    if (!(lambda > 0.0) || npts < 0) return fail(DM_EINVAL, "lambda must be positive and npts >= 0");
+    if (npts == 0) return DM_OK;
+    return on_device(op, stream, [&](hipStream_t s) -> int {
+        const Level &L = op->lv[0];
+        // points and values: a temporary device buffer of this call
+        struct Buf {
+            double *p = nullptr;
+            ~Buf() { if (p) (void)hipFree(p); }
+        } buf;
+        DM_HIP(hipMalloc((void **)&buf.p, (size_t)6 * npts * sizeof(double)));
+        double *dp = buf.p;
+        DM_HIP(hipMemcpyAsync(dp, pts, (size_t)3 * npts * sizeof(double), hipMemcpyHostToDevice, s));
+        fill_ghosts(L, 64, b, false, s);
+        launch_sample_e(L.g, L.coef64, b, std::sqrt(lambda), npts, dp, dp + (size_t)3 * npts, s);
+        DM_HIP(hipMemcpyAsync(e, dp + (size_t)3 * npts, (size_t)3 * npts * sizeof(double), hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        return DM_OK;
+    });
+}
+
 int dm_solve_block(dm_op *op, int mode, int nrhs, const double *const *f, double *const *x, double rtol,
                    int maxit, dm_solve_info *info, void *stream) {
     if (op && op->opt.tilde_transfers) return fail(DM_EINVAL, "tilde transfers: single-vector solves only");

@@ -527,6 +527,9 @@ void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, 
 void launch_mask_mul(int64_t n, const double *mask, double *x, hipStream_t s);
 // x = in on the mask's nonzero entries, 0 elsewhere
 void launch_copy_masked(int64_t n, const double *in, const double *mask, double *x, hipStream_t s);
+// e = C^T b / k at npts points (device arrays pts: 3 per point, out: 3 per point)
+void launch_sample_e(const Grid &g, const double *coef, const double *b, double k, int npts, const double *pts,
+                     double *out, hipStream_t s);
 // tilde-form transfers: x *= a^(power/2) per face (coef: the level's
 // coefficient blocks, whose first 3P entries are ax ay az); x += a^(-1/2) r
 template <class T>

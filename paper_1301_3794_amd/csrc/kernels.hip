@@ -1427,6 +1427,60 @@ __global__ void k_add_scaled_a(int64_t n, const T *__restrict__ a, const T *__re
     }
 }
 
+// Electric field of an eigenvector at sample points: e = C^T b / k on the
+// edges with l > 0 (zero on the others, e.g. the conducting walls), the
+// circulation of b around each edge divided by h (the Yee scheme's Ampere
+// law in the frequency domain), interpolated trilinearly from each
+// component's own edge lattice (e_x at ((i + 1/2) h, j h, k h), ...).  One
+// thread per point; a point whose stencil leaves the grid gets NaN.
+__device__ inline double edge_e(const Grid &g, const Coefs<double> &c, const double *__restrict__ b, int comp, int i,
+                                int j, int k, double inv_kh) {
+    const int64_t P = g.P, dy = g.sy, dz = g.sz, p = pidx(g, i, j, k);
+    const double *X = b, *Y = b + P, *Z = b + 2 * P;
+    if (comp == 0) {
+        if (!(c.lx[p] > 0.0)) return 0.0;
+        return (Z[p] - Z[p - dy] - Y[p] + Y[p - dz]) * inv_kh;
+    }
+    if (comp == 1) {
+        if (!(c.ly[p] > 0.0)) return 0.0;
+        return (X[p] - X[p - dz] - Z[p] + Z[p - 1]) * inv_kh;
+    }
+    if (!(c.lz[p] > 0.0)) return 0.0;
+    return (Y[p] - Y[p - 1] - X[p] + X[p - dy]) * inv_kh;
+}
+
+__global__ void k_sample_e(Grid g, Coefs<double> c, const double *__restrict__ b, double inv_kh, int npts,
+                           const double *__restrict__ pts, double *__restrict__ out) {
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= npts) return;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int comp = 0; comp < 3; ++comp) {
+        int i0[3];
+        double t[3];
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            const double u = pts[3 * q + a] / g.h - (a == comp ? 0.5 : 0.0);
+            const double f = floor(u);
+            i0[a] = (int)f;
+            t[a] = u - f;
+            // edge lattice along comp: 0 .. n-1; across: 0 .. n
+            const int hi = a == comp ? n[a] - 1 : n[a];
+            if (!(f >= 0.0) || i0[a] + 1 > hi) ok = false;
+        }
+        double v = 0.0;
+        if (ok) {
+            for (int corner = 0; corner < 8; ++corner) {
+                const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
+                const double w = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
+                if (w != 0.0) v += w * edge_e(g, c, b, comp, i0[0] + dx, i0[1] + dy, i0[2] + dz, inv_kh);
+            }
+        } else {
+            v = __builtin_nan("");
+        }
+        out[3 * q + comp] = v;
+    }
+}
+
 // x = in where mask != 0, else 0
 __global__ void k_copy_masked(int64_t n, const double *__restrict__ in, const double *__restrict__ mask,
                               double *__restrict__ x) {
@@ -2064,6 +2118,13 @@ void launch_mask_mul(int64_t n, const double *mask, double *x, hipStream_t s) {
 void launch_randn(int64_t n, uint64_t seed, int64_t offset, const double *mask, double *x,
                   hipStream_t s) {
     hipLaunchKernelGGL(k_randn, flat_grid(n), dim3(kThreads), 0, s, n, seed, offset, mask, x);
+}
+
+void launch_sample_e(const Grid &g, const double *coef, const double *b, double k, int npts, const double *pts,
+                     double *out, hipStream_t s) {
+    if (npts <= 0) return;
+    hipLaunchKernelGGL(k_sample_e, dim3((unsigned)ceil_div(npts, kThreads)), dim3(kThreads), 0, s, g,
+                       coefs_of(coef, g.P), b, 1.0 / (k * g.h), npts, pts, out);
 }
 
 void launch_copy_masked(int64_t n, const double *in, const double *mask, double *x, hipStream_t s) {

@@ -139,6 +139,7 @@ def lib():
     L.dm_eigs.argtypes = [vp, i, d, d, ctypes.c_uint64, ctypes.POINTER(EigOptions), dp, vp, dp,
                           ctypes.POINTER(EigInfo), vp]
     L.dm_time_kernel.argtypes = [vp, i, i, i, i, dp]
+    L.dm_sample_e.argtypes = [vp, vp, d, i, dp, dp, vp]
     L.dm_time_block_kernel.argtypes = [vp, i, i, i, i, i, ctypes.POINTER(d)]
     L.dm_strerror.argtypes = [i]
     L.dm_strerror.restype = ctypes.c_char_p
@@ -418,6 +419,16 @@ class Operator:
                                          _stream(stream)), allow_warning=True)
         return [dict(status=rc, iterations=q.iterations, restarts=q.restarts, rel_residual=q.rel_residual,
                      seconds=q.seconds) for q in info]
+
+    def sample_e(self, b, lam, points, stream=None) -> np.ndarray:
+        """Electric field C^T b / k of the eigenpair (b, lam) interpolated at
+        points (n x 3 array of coordinates); NaN where the stencil leaves the grid."""
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros_like(pts)
+        _check(lib().dm_sample_e(self._op, _ptr(b), float(lam), pts.shape[0],
+                                 pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream)))
+        return out
 
     def time_block_kernel(self, kernel, nrhs, prec=32, level=0, reps=50):
         """Milliseconds per launch of the block form of a kernel on nrhs vectors."""

@@ -188,3 +188,90 @@ def levelset_convergence(n=32, refinements=(1, 2, 4, 8), radius=0.45, sigma=5.0,
                          max_rel_diff_vs_analytic=float(np.max(abs(out["lam"] - ref) / ref))))
     return dict(grid=[n, n, n], analytic_volume_rel_err=abs(v_analytic - exact) / exact,
                 lam_analytic=ref.tolist(), rows=rows)
+
+
+# ---------------------------------------------------------------------------
+# Surface fields (Sec. 6.2, eq. errorNorm, Fig. fieldErr3d)
+# ---------------------------------------------------------------------------
+
+def tm3_xyz_field(points, k0):
+    """Electric field (unnormalised) of the sphere's TM mode of degree 3 with
+    angular part x y z / r^3, centred on the origin, wavenumber k0: with
+    psi = j_3(k0 r) Y, Y = x y z / r^3, the TM field is curl (r x grad psi),
+    and curl (r x grad psi) = -grad(d/dr (r psi)) - k0^2 psi r_vec for a
+    Helmholtz solution psi, so E = grad(g Y) + k0^2 f Y r_vec with
+    f = j_3(k0 r) and g = (r f)' = j_3 + k0 r j_3'; it is radial on the wall
+    where g(R) = 0 (the TM condition [x j_3(x)]' = 0)."""
+    from scipy import special
+    p = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    r = np.sqrt(x * x + y * y + z * z)
+    kr = k0 * r
+    j = special.spherical_jn(3, kr)
+    jp = special.spherical_jn(3, kr, derivative=True)
+    # spherical Bessel equation: x^2 j'' + 2 x j' + (x^2 - 12) j = 0
+    jpp = -2.0 / kr * jp - (1.0 - 12.0 / (kr * kr)) * j
+    g = j + kr * jp
+    gp = k0 * (2.0 * jp + kr * jpp)
+    Y = x * y * z / r ** 3
+    grad_y = np.stack([y * z, x * z, x * y], axis=1) / r[:, None] ** 3 - 3.0 * (Y / r ** 2)[:, None] * p
+    return (gp * Y / r)[:, None] * p + g[:, None] * grad_y + (k0 * k0 * j * Y)[:, None] * p
+
+
+def octant_directions(count=400):
+    """Unit vectors spread over the positive octant (a Fibonacci lattice on
+    the sphere, kept where every component is positive)."""
+    m = 8 * count
+    i = np.arange(m) + 0.5
+    phi = np.arccos(1.0 - 2.0 * i / m)
+    theta = np.pi * (1.0 + 5 ** 0.5) * i
+    d = np.stack([np.cos(theta) * np.sin(phi), np.sin(theta) * np.sin(phi), np.cos(phi)], axis=1)
+    return d[(d > 0).all(axis=1)]
+
+
+def surface_field_convergence(ns=(16, 24, 32, 48, 64), a_mins=(0.0, 0.1), radius=0.45, box=0.5, sigma=40.0,
+                              tol=1e-10, shell_cells=3.0):
+    """eq. errorNorm on the sphere octant's lowest mode: the relative l2 error
+    of the computed electric field (dm_sample_e: C^T b / k, trilinear) against
+    the analytic one on a shell shell_cells cells inside the wall, after both
+    are scaled to unit l2 norm over one fixed set of points filling the
+    cavity (and the computed one's sign matched).  Test points lie at least
+    one cell of the coarsest grid from the symmetry planes, where trilinear
+    interpolation needs no mirrored values (a reading: the paper samples the
+    whole shell)."""
+    import torch
+    k0 = tm_root(3, 4.5, 5.5) / radius
+    h_max = box / min(ns)
+    dirs = octant_directions()
+    g = np.arange(h_max, radius, radius / 14.0)
+    vol = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    vol = vol[(np.linalg.norm(vol, axis=1) <= radius - shell_cells * h_max) & (vol >= h_max).all(axis=1)]
+    e_vol = tm3_xyz_field(vol, k0)
+    e_vol /= np.linalg.norm(e_vol)
+    rows = []
+    for a_min in a_mins:
+        for n in ns:
+            h = box / n
+            shell = (radius - shell_cells * h) * dirs
+            shell = shell[(shell >= h_max).all(axis=1)]
+            e_sh = tm3_xyz_field(shell, k0)
+            with octant_operator(n, radius, box, a_min, sigma) as op:
+                P = op.layout(0)["P"]
+                vecs = torch.zeros(3 * P, dtype=torch.float64, device="cuda")
+                out = op.eigs(1, sigma=sigma, tol=tol, seed=1, vecs=vecs, solve_mode=dm.SOLVE_FGMRES_MG32,
+                              block=2, max_basis=24, max_restarts=40)
+                lam = float(out["lam"][0])
+                c_vol = op.sample_e(vecs, lam, vol)
+                c_sh = op.sample_e(vecs, lam, shell)
+            scale = 1.0 / np.linalg.norm(c_vol)
+            sign = 1.0 if np.sum(c_vol * e_vol) >= 0 else -1.0
+            ref_scale = 1.0 / np.linalg.norm(tm3_xyz_field(vol, k0))
+            diff = sign * scale * c_sh - ref_scale * e_sh
+            err = float(np.sqrt(np.sum(diff * diff) / np.sum((ref_scale * e_sh) ** 2)))
+            rows.append(dict(a_min=a_min, n=n, h=h, status=out["status"], lam=lam, shell_points=int(len(shell)),
+                             rel_field_err=err, wavelengths_per_cell=2.0 * math.pi / (k0 * h)))
+    orders = {}
+    for a_min in a_mins:
+        sel = [r for r in rows if r["a_min"] == a_min][-3:]
+        orders[str(a_min)] = fit_order([r["h"] for r in sel], [r["rel_field_err"] for r in sel])
+    return dict(k0=k0, volume_points=int(len(vol)), rows=rows, orders_finest3=orders)
