@@ -289,8 +289,14 @@ def run_studies(dm):
     octant's lowest mode on a shell inside the wall against the analytic TM
     field."""
     from paper_1301_3794_amd import studies
+    log("study f1: frequency convergence")
     fc = studies.frequency_convergence(ns=(16, 24, 32, 48, 64), a_mins=(0.0, 0.1))
+    log("study f2: solver sensitivity")
     ss = studies.solver_sensitivity(n=32)
+    log("study f4: level-set geometry")
+    ls = studies.levelset_convergence(n=32, refinements=(1, 2, 4, 8))
+    log("study f3: surface fields")
+    sf = studies.surface_field_convergence()
     return {"f1_frequency_convergence": {
         "workload": "sphere R=0.45 octant, n^3 cells of [0,0.5]^3, conducting symmetry planes, lowest mode "
                     "(TM, degree 3, x y z angular part)",
@@ -303,12 +309,11 @@ def run_studies(dm):
         "rows": ss["rows"]},
         "f4_general_geometry": dict(
             workload="sphere R=0.45 at 32^3 as a level set |x-c|-R sampled on the grid refined s times, "
-                     "tetrahedral fractions; lowest 3 eigenvalues against the analytic fractions'",
-            **studies.levelset_convergence(n=32, refinements=(1, 2, 4, 8))),
+                     "tetrahedral fractions; lowest 3 eigenvalues against the analytic fractions'", **ls),
         "f3_surface_fields": dict(
             workload="sphere R=0.45 octant as for f1, n = 16..64; e = C^T b / k by trilinear interpolation of the "
                      "edge values on a shell 3 cells inside the wall, relative l2 error after unit-norm scaling",
-            **studies.surface_field_convergence())}
+            **sf)}
 
 
 def run_c4(dm, torch):
