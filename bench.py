@@ -145,6 +145,7 @@ def parse():
     ap.add_argument("--skip-learned", action="store_true", help="do not train and time the learned form")
     ap.add_argument("--skip-c3", action="store_true", help="do not run the 9-cell quarter cavity")
     ap.add_argument("--skip-c4", action="store_true", help="do not run the 64 batched ellipsoids")
+    ap.add_argument("--skip-studies", action="store_true", help="do not run the accuracy and solver studies")
     ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep", "studies"], default=None,
                     help="profiling runs: only the 9-cell cavity, only the batch, the HBM-traffic "
                          "probe (a 256 MiB device copy of known size, then 3 FP32 red-black sweeps "
@@ -491,8 +492,10 @@ def main():
         log("9-cell quarter cavity")
         c3 = run_c3(dm, torch, copy_gbps)
 
-    log("studies")
-    st = run_studies(dm)
+    st = None
+    if not args.skip_studies:
+        log("studies")
+        st = run_studies(dm)
 
     c4 = None
     if not args.skip_c4:

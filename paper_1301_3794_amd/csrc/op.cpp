@@ -179,6 +179,45 @@ static void tab_row(const Grid &g, const std::vector<double> &c, const Coefs<dou
                                     ih2 * pmc_diag_extra<double>(g, cg.lx, cg.ly, cg.lz, comp, i, j, k, p);
 }
 
+// A row that the 3^3 rule of row_flags leaves out can still be a vacuum row:
+// the rule looks at every coefficient of the cells around, the row at the
+// few that enter it.  Every active row without the vacuum bit and away from
+// the PMC planes (where ghost images couple a face to itself) is tabulated;
+// one whose weights are exactly those of the 7-point vacuum stencil (own
+// component 6/h^2 and -1/h^2, no cross terms, a = 1, diagonal 6/h^2) gets
+// the bit, so that it takes the short path (the same matrix row, summed in
+// another order).  Threaded over planes.
+static void refine_vacuum_flags(const Grid &g, const std::vector<double> &c, std::vector<uint8_t> &fl) {
+    const Coefs<double> cg = coefs_of(c.data(), g.P);
+    const double ih2 = 1.0 / (g.h * g.h);
+    auto work = [&](int k0, int k1) {
+        double w[kCutW];
+        for (int k = k0; k < k1; ++k)
+            for (int j = 0; j < g.ny; ++j)
+                for (int i = 0; i < g.nx; ++i) {
+                    const int idx[3] = {i, j, k};
+                    bool pmc = false;
+                    for (int a = 0; a < 3; ++a)
+                        if (((g.pmc >> a) & 1) && idx[a] == 0) pmc = true;
+                    if (pmc) continue;
+                    const int64_t p = pidx(g, i, j, k);
+                    for (int comp = 0; comp < 3; ++comp) {
+                        if (!(fl[p] & (kFaceActive << comp)) || (fl[p] & (kFaceVacuum << comp))) continue;
+                        tab_row(g, c, cg, comp, p, w, 1);
+                        bool vac = w[0] == 6.0 * ih2 && w[kCutTerms] == 1.0 && w[kCutTerms + 1] == 6.0 * ih2;
+                        for (int t = 1; t < 7 && vac; ++t) vac = w[t] == -ih2;
+                        for (int t = 7; t < kCutTerms && vac; ++t) vac = w[t] == 0.0;
+                        if (vac) fl[p] |= (uint8_t)(kFaceVacuum << comp);
+                    }
+                }
+    };
+    const int nt = std::max(1, std::min(16, g.nz));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back(work, (int)((int64_t)g.nz * t / nt), (int)((int64_t)g.nz * (t + 1) / nt));
+    for (auto &t : th) t.join();
+}
+
 // The tables of a level: its smoother classes' cut lists (class q's rows of
 // component q / 2, term-major, starting at kCutW * cut_off[q]) and its list
 // of cells with a cut row (the three components' rows of each cell: entry
@@ -245,7 +284,8 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         const int64_t P = L.g.P;
         std::vector<double> c = to_coefs(L.g, op->frac[l], op->opt.grad_div_volume != 0);
         std::vector<float> c32(c.begin(), c.end());
-        const std::vector<uint8_t> fl = row_flags(L.g, c);
+        std::vector<uint8_t> fl = row_flags(L.g, c);
+        refine_vacuum_flags(L.g, c, fl);
         // coefficient blocks followed by the P row-class bytes
         L.coef64 = op->dalloc<double>(7 * P + (P + 7) / 8);
         L.coef32 = op->dalloc<float>(7 * P + (P + 3) / 4);
