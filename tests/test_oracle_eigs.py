@@ -22,17 +22,17 @@ def tm_root(l, lo, hi):
 
 
 def test_box_lanczos_matches_closed_form():
-    N = 16
+    N = 8
     h = 1.0 / N
     fr = geo.fractions(geo.Box(), (N, N, N), h)
     op = ops.build(fr, (N, N, N), h, 5.0)
     lam, B, info = eigs.lanczos_eigs(op, 5, sigma_o=5.0, block=4, tol=1e-11)
     ref = sorted(sum((2 * math.sin(math.pi * x / (2 * N)) / h) ** 2 for x in m)
                  for m in itertools.product(range(3), repeat=3) if sum(x > 0 for x in m) >= 2)
-    # (1,1,0)x3 then (1,1,1)x2: 19.6758728671 (x3), 29.5138093006 (x2)
+    # (1,1,0)x3 then (1,1,1)x2: 2 (16 sin(pi/16))^2 (x3), 3 (16 sin(pi/16))^2 (x2)
     want = [ref[0]] * 3 + [ref[3]] * 2
-    assert want[0] == pytest.approx(19.6758728671, abs=1e-9)
-    assert want[3] == pytest.approx(29.5138093006, abs=1e-9)
+    assert want[0] == pytest.approx(19.4868396771, abs=1e-9)
+    assert want[3] == pytest.approx(29.2302595157, abs=1e-9)
     assert np.max(abs(lam - want) / np.array(want)) < 1e-10
     assert info["residuals"].max() <= 1e-11
 
@@ -74,7 +74,7 @@ def test_sphere_tm11_second_order_convergence():
     assert x11 == pytest.approx(2.743707, abs=1e-6)
     k2 = (x11 / 0.45) ** 2
     errs = []
-    ns = (8, 12, 16, 24)
+    ns = (8, 12, 16, 20)
     for N in ns:
         h = 1.0 / N
         fr = geo.fractions(geo.sphere((0.5, 0.5, 0.5), 0.45), (N, N, N), h)
@@ -84,7 +84,7 @@ def test_sphere_tm11_second_order_convergence():
         errs.append(abs(lam[0] - k2) / k2)
     p = np.polyfit(np.log(1.0 / np.array(ns)), np.log(errs), 1)[0]
     assert 1.6 <= p <= 2.4
-    assert errs[-1] < 3e-3
+    assert errs[-1] < 4.5e-3
 
 
 def test_projection_properties(sphere16):
