@@ -131,6 +131,7 @@ static void free_op(dm_op *op) {
     if (op->hres) hipHostFree(op->hres);
     if (op->bk_hres) hipHostFree(op->bk_hres);
     if (op->hres2) hipHostFree(op->hres2);
+    if (op->ln_hflag) hipHostFree(op->ln_hflag);
     if (op->bk_hres2) hipHostFree(op->bk_hres2);
     if (op->stream) hipStreamDestroy(op->stream);
     delete op;

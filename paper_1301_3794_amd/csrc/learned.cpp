@@ -60,6 +60,9 @@ void ensure_scratch(dm_op *op) {
         op->ln_t2 = op->dalloc<double>(n);
         op->ln_t3 = op->dalloc<double>(n);
         op->ln_t4 = op->dalloc<double>(n);
+        op->ln_d = op->dalloc<double>(2);
+        op->ln_flag = op->dalloc<int>(1);
+        DM_HIP(hipHostMalloc((void **)&op->ln_hflag, sizeof(int), hipHostMallocDefault));
     }
 }
 
@@ -167,19 +170,24 @@ void net_apply(dm_op *op, const double *r, double scale, double *out, hipStream_
 // z += correction of the V-cycle's answer z for right-hand side v, kept only
 // if it lowers ||v - M z||; returns whether it was kept
 bool net_correct(dm_op *op, const double *v, double *z, hipStream_t s) {
-    attached(op);
+    dm_net *net = attached(op);
     const Level &L = op->lv[0];
     const int64_t n = op->n0();
     double *r2 = op->ln_t1, *dz = op->ln_t2, *r3 = op->ln_t3;
-    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, v, z, r2, s);
-    const double n2 = dot1(op, r2, r2, op->wface, n, s);
-    if (!(n2 > 0.0)) return true;
-    const double sc = std::sqrt(n2 / (double)std::max<int64_t>(1, L.n_act_faces));
-    net_apply(op, r2, sc, dz, s);
-    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, r2, dz, r3, s);
-    const double n3 = dot1(op, r3, r3, op->wface, n, s);
-    if (n3 < n2) {
-        launch_axpy(n, 1.0, dz, z, s);
+    const double inv_cnt = 1.0 / (double)std::max<int64_t>(1, L.n_act_faces);
+    // r' = v - M z and |r'|^2; the input scale s = |r'| / sqrt(active faces)
+    // is read on the device, so nothing waits for the host before the judge
+    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, v, z, r2, s, L.cut_cells());
+    launch_mdot(1, r2, 0, r2, op->wface, n, op->part, op->ln_d, s, op->vspan());
+    launch_net_pack_r_dev(L.g, r2, op->ln_d, inv_cnt, net->x0, s);
+    forward(net, L.g, s);
+    launch_net_unpack_dev(L.g, L.coef64, net->y, L.g.h * L.g.h, op->ln_d, inv_cnt, dz, s);
+    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, r2, dz, r3, s, L.cut_cells());
+    launch_mdot(1, r3, 0, r3, op->wface, n, op->part, op->ln_d + 1, s, op->vspan());
+    launch_net_accept(n, op->ln_d, dz, z, op->ln_flag, s);
+    DM_HIP(hipMemcpyAsync(op->ln_hflag, op->ln_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DM_HIP(hipStreamSynchronize(s));
+    if (*op->ln_hflag) {
         ++op->ln_accepted;
         return true;
     }
@@ -217,10 +225,10 @@ double net_loss_grad(dm_op *op, int kind, const double *r, const double *e, doub
         // d = correction, r3 = r - M d, L = |r3|^2 / |r|^2, dL/dd = -2 M r3 / |r|^2
         double *d = op->ln_t3, *r3 = op->ln_t4;
         launch_net_unpack<double>(g, L.coef64, net->y, c, d, s);
-        launch_apply<double>(g, L.coef64, op->sigma, AK_RESID, r, d, r3, s);
+        launch_apply<double>(g, L.coef64, op->sigma, AK_RESID, r, d, r3, s, L.cut_cells());
         const double rr = dot1(op, r, r, op->wface, n, s);
         const double r33 = dot1(op, r3, r3, op->wface, n, s);
-        launch_apply<double>(g, L.coef64, op->sigma, AK_M, nullptr, r3, d, s);
+        launch_apply<double>(g, L.coef64, op->sigma, AK_M, nullptr, r3, d, s, L.cut_cells());
         launch_net_dy_from_face(g, L.coef64, d, -2.0 * c / rr, net->dy, s);
         loss = r33 / rr;
     }
@@ -247,9 +255,9 @@ void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s
     ensure_krylov_small(op);   // the FP32 V-cycle's cast buffers
     launch_randn(n, seed, 0, op->fmask, w, s);
     precondition(op, DM_SOLVE_FGMRES_MG32, w, e, s);          // e holds x* for now
-    launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, e, f, s);
+    launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, e, f, s, L.cut_cells());
     precondition(op, DM_SOLVE_FGMRES_MG32, f, w, s);          // w = z
-    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, w, r, s);
+    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, w, r, s, L.cut_cells());
     launch_axpy(n, -1.0, w, e, s);                            // e = x* - z
     DM_HIP(hipGetLastError());
 }

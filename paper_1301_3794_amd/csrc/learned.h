@@ -58,6 +58,14 @@ void launch_net_pack_r(const Grid &g, const T *r, double inv_s, uint16_t *x0, hi
 // y [P][4] -> face vector out_comp = (a_comp > 0) ? y[c] * scale : 0 (with PMC ghost images)
 template <class T>
 void launch_net_unpack(const Grid &g, const T *coef, const float *y, double scale, T *out, hipStream_t s);
+// the same with the residual scale s = sqrt(ss[0] * inv_cnt) read on the
+// device (ss: a sum of squares): the input is r / s, the output y * s * h2
+void launch_net_pack_r_dev(const Grid &g, const double *r, const double *ss, double inv_cnt, uint16_t *x0,
+                           hipStream_t s);
+void launch_net_unpack_dev(const Grid &g, const double *coef, const float *y, double h2, const double *ss,
+                           double inv_cnt, double *out, hipStream_t s);
+// z += dz where d[1] < d[0] (or d[0] == 0); *flag = 1 if kept, else 0
+void launch_net_accept(int64_t n, const double *d, const double *dz, double *z, int *flag, hipStream_t s);
 // loss of one pair: target t = e * t_scale on active faces (a > 0);
 // dy [P][16] channels 0..2 = bf16(2 (y - t) / norm); partial sums of
 // (y - t)^2 and t^2 per block into part[2 * nblocks] (FP64)

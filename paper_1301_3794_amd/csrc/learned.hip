@@ -32,50 +32,106 @@ __device__ inline int64_t tap_offset(const Grid &g, int t) {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// A workgroup computes one tile of 16 x kTileY x kTileZ cells: the input
+// cells of the tile and its one-cell halo (18 x (kTileY + 2) x (kTileZ + 2),
+// 16 channels each) are staged in LDS once, so each activation is fetched
+// from memory about twice instead of once per tap; wave w then takes the
+// x-segments of y-row w, one z-plane after another.  Cells outside the padded
+// grid are staged as zeros (the padding layer itself holds zeros).  Each
+// wave keeps the layer's weights for its lanes in registers (27 x 8 bytes),
+// and staged cells sit 48 bytes apart, so that the 8-byte reads of half a
+// wavefront (16 cells x 2 channel groups) fall on 64 distinct banks.
+constexpr int kTileY = 4, kTileZ = 8;
+constexpr int kTileCells = 18 * (kTileY + 2) * (kTileZ + 2);
+constexpr int kCellStride = 3;   // in 16-byte units (32 bytes of data, 16 of padding)
+
 template <int MODE>
 __global__ void __launch_bounds__(kT)
 k_net_conv(Grid g, const uint16_t *__restrict__ in, const uint16_t *__restrict__ w,
            const uint16_t *__restrict__ mask, uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
-    __shared__ uint16_t ws[27 * 256];
-    for (int e = threadIdx.x; e < 27 * 256 / 4; e += kT)
-        reinterpret_cast<uint2 *>(ws)[e] = reinterpret_cast<const uint2 *>(w)[e];
-    __syncthreads();
-    const int nsx = (g.nx + 15) >> 4;
-    const int64_t nseg = (int64_t)nsx * g.ny * g.nz;
-    const int64_t seg = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
-    if (seg >= nseg) return;
-    const int lane = threadIdx.x & 63, col = lane & 15, kg = lane >> 4;
-    const int sx = (int)(seg % nsx);
-    const int64_t rest = seg / nsx;
-    const int j = (int)(rest % g.ny), k = (int)(rest / g.ny);
+    static_assert(kT / 64 == kTileY, "one wave per y-row of the tile");
+    __shared__ uint4 xs[kTileCells * kCellStride];
+    const int nsx = (g.nx + 15) >> 4, nty = (g.ny + kTileY - 1) / kTileY;
+    const int64_t b = blockIdx.x;
+    const int sx = (int)(b % nsx);
+    const int64_t rest = b / nsx;
+    const int j0 = (int)(rest % nty) * kTileY, k0 = (int)(rest / nty) * kTileZ;
     const int i0 = sx * 16;
-    // A operand: cell i0 + col, input channels 4 kg .. 4 kg + 3
+    for (int e = threadIdx.x; e < kTileCells * 2; e += kT) {
+        const int c = e >> 1, half = e & 1;
+        const int xi = c % 18, yi = (c / 18) % (kTileY + 2), zi = c / (18 * (kTileY + 2));
+        // cell (i, j, k) of the grid, padding at -1 and n
+        const int i = i0 - 1 + xi, j = j0 - 1 + yi, k = k0 - 1 + zi;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (i <= g.nx && j <= g.ny && k <= g.nz)
+            v = reinterpret_cast<const uint4 *>(in + pidx(g, i, j, k) * kNetCh)[half];
+        xs[c * kCellStride + half] = v;
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, kg = lane >> 4;
+    // this lane's A operands: output channel col, input channels 4 kg .. 4 kg + 3, every tap
+    uint2 wr[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) wr[t] = *reinterpret_cast<const uint2 *>(w + t * 256 + col * 16 + 4 * kg);
+    __syncthreads();
+    const int j = j0 + wv;
+    if (j >= g.ny) return;
     const int ia = i0 + col;
     const bool va = ia < g.nx;
-    const int64_t pa = pidx(g, va ? ia : 0, j, k);
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
-    for (int t = 0; t < 27; ++t) {
-        bf16x4 a = {0, 0, 0, 0};
-        if (va) {
-            const uint2 raw = *reinterpret_cast<const uint2 *>(in + (pa + tap_offset(g, t)) * kNetCh + 4 * kg);
-            a = *reinterpret_cast<const bf16x4 *>(&raw);
-        }
-        const uint2 wraw = *reinterpret_cast<const uint2 *>(ws + t * 256 + col * 16 + 4 * kg);
-        const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&wraw);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    // D: cell i0 + 4 kg + r, output channel col
+    const uint2 *xs2 = reinterpret_cast<const uint2 *>(xs);
+    // two z-planes at a time: their product chains are independent, so one
+    // hides the other's latency
+    for (int zz = 0; zz < kTileZ; zz += 2) {
+        if (k0 + zz >= g.nz) break;
+        // all 2 x 27 taps from LDS before the first product
+        uint2 raw[2][27];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 4 * kg + r;
-        if (i >= g.nx) continue;
-        const int64_t p = pidx(g, i, j, k);
-        const float v = acc[r];
-        if (MODE == NET_RELU) out_bf[p * kNetCh + col] = f2bf(v > 0.f ? v : 0.f);
-        else if (MODE == NET_MASKED)
-            out_bf[p * kNetCh + col] = f2bf(bf2f(mask[p * kNetCh + col]) > 0.f ? v : 0.f);
-        else if (col < 4) out_f[p * 4 + col] = v;
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int t = 0; t < 27; ++t) {
+                const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                const int c = (col + 1 + dx) + 18 * ((wv + 1 + dy) + (kTileY + 2) * (zz + h + 1 + dz));
+                raw[h][t] = xs2[c * (2 * kCellStride) + kg];
+            }
+        // D = W X: rows the output channels (A = the tap's weights, row = output
+        // channel, k = input channel), columns the 16 cells (B = the inputs,
+        // k = input channel, column = cell); lane (col, kg) ends with output
+        // channels 4 kg .. 4 kg + 3 of cell i0 + col, stored as one 8-byte
+        // write (a wavefront writes the segment's 512 contiguous bytes)
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const bf16x4 aw = *reinterpret_cast<const bf16x4 *>(&wr[t]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint2 xv = va ? raw[h][t] : make_uint2(0u, 0u);
+                const bf16x4 bx = *reinterpret_cast<const bf16x4 *>(&xv);
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw, bx, acc[h], 0, 0, 0);
+            }
+        }
+        if (!va) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = k0 + zz + h;
+            if (k >= g.nz) break;
+            const int64_t p = pidx(g, ia, j, k);
+            if (MODE == NET_LINEAR) {
+                if (kg == 0)
+                    *reinterpret_cast<float4 *>(out_f + p * 4) = make_float4(acc[h][0], acc[h][1], acc[h][2], acc[h][3]);
+                continue;
+            }
+            uint16_t o[4];
+            if (MODE == NET_RELU) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = f2bf(acc[h][r] > 0.f ? acc[h][r] : 0.f);
+            } else {
+                const uint2 mraw = *reinterpret_cast<const uint2 *>(mask + p * kNetCh + 4 * kg);
+                const uint16_t *m = reinterpret_cast<const uint16_t *>(&mraw);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = f2bf(bf2f(m[r]) > 0.f ? acc[h][r] : 0.f);
+            }
+            *reinterpret_cast<uint2 *>(out_bf + p * kNetCh + 4 * kg) =
+                make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+        }
     }
 }
 
@@ -147,10 +203,16 @@ k_net_wgrad_reduce(const float *__restrict__ part, int cin, int cout, float *__r
 
 template <class T>
 __global__ void __launch_bounds__(kT)
-k_net_pack_r(Grid g, const T *__restrict__ r, double inv_s, uint16_t *__restrict__ x0) {
+k_net_pack_r(Grid g, const T *__restrict__ r, double inv_s, const double *__restrict__ ss, double inv_cnt,
+             uint16_t *__restrict__ x0) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (t >= n) return;
+    if (ss) {
+        // the scale from a sum of squares on the device: s = sqrt(ss * inv_cnt)
+        const double sc = sqrt(ss[0] * inv_cnt);
+        inv_s = sc > 0.0 ? 1.0 / sc : 0.0;
+    }
     const int i = (int)(t % g.nx);
     const int64_t q = t / g.nx;
     const int j = (int)(q % g.ny), k = (int)(q / g.ny);
@@ -161,10 +223,12 @@ k_net_pack_r(Grid g, const T *__restrict__ r, double inv_s, uint16_t *__restrict
 
 template <class T>
 __global__ void __launch_bounds__(kT)
-k_net_unpack(Grid g, const T *__restrict__ coef, const float *__restrict__ y, double scale, T *__restrict__ out) {
+k_net_unpack(Grid g, const T *__restrict__ coef, const float *__restrict__ y, double scale,
+             const double *__restrict__ ss, double inv_cnt, T *__restrict__ out) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (t >= n) return;
+    if (ss) scale *= sqrt(ss[0] * inv_cnt);
     const int i = (int)(t % g.nx);
     const int64_t q = t / g.nx;
     const int j = (int)(q % g.ny), k = (int)(q / g.ny);
@@ -270,8 +334,8 @@ k_net_adam(const float *__restrict__ g, float *__restrict__ w, float *__restrict
 
 void launch_net_conv(int mode, const Grid &g, const uint16_t *in, const uint16_t *w, const uint16_t *mask,
                      uint16_t *out_bf, float *out_f, hipStream_t s) {
-    const int64_t nseg = ceil_div(g.nx, 16) * (int64_t)g.ny * g.nz;
-    const dim3 grid((unsigned)ceil_div(nseg, kT / 64));
+    // one workgroup per tile of 16 x kTileY x kTileZ cells
+    const dim3 grid((unsigned)(ceil_div(g.nx, 16) * ceil_div(g.ny, kTileY) * ceil_div(g.nz, kTileZ)));
     if (mode == NET_RELU)
         hipLaunchKernelGGL(k_net_conv<NET_RELU>, grid, dim3(kT), 0, s, g, in, w, mask, out_bf, out_f);
     else if (mode == NET_MASKED)
@@ -291,13 +355,47 @@ void launch_net_wgrad_reduce(const float *part, int cin, int cout, float *grad, 
 template <class T>
 void launch_net_pack_r(const Grid &g, const T *r, double inv_s, uint16_t *x0, hipStream_t s) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_net_pack_r<T>, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, g, r, inv_s, x0);
+    hipLaunchKernelGGL(k_net_pack_r<T>, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, g, r, inv_s,
+                       (const double *)nullptr, 0.0, x0);
+}
+
+void launch_net_pack_r_dev(const Grid &g, const double *r, const double *ss, double inv_cnt, uint16_t *x0,
+                           hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_net_pack_r<double>, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, g, r, 0.0, ss,
+                       inv_cnt, x0);
 }
 
 template <class T>
 void launch_net_unpack(const Grid &g, const T *coef, const float *y, double scale, T *out, hipStream_t s) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_net_unpack<T>, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, g, coef, y, scale, out);
+    hipLaunchKernelGGL(k_net_unpack<T>, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, g, coef, y, scale,
+                       (const double *)nullptr, 0.0, out);
+}
+
+void launch_net_unpack_dev(const Grid &g, const double *coef, const float *y, double h2, const double *ss,
+                           double inv_cnt, double *out, hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_net_unpack<double>, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, g, coef, y, h2, ss,
+                       inv_cnt, out);
+}
+
+// The residual judge on the device: d[0] = |v - M z|^2, d[1] = |v - M (z +
+// dz)|^2; z += dz when the correction lowers the residual (or the residual
+// is already zero, where dz is zero as well); flag = whether it was kept.
+// One workgroup per kThreads entries; every workgroup reads the same two
+// numbers, workgroup 0 writes the flag.
+__global__ void __launch_bounds__(kT)
+k_net_accept(int64_t n, const double *__restrict__ d, const double *__restrict__ dz, double *__restrict__ z,
+             int *__restrict__ flag) {
+    const bool keep = d[1] < d[0] || d[0] == 0.0;
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t == 0) *flag = keep ? 1 : 0;
+    if (keep && t < n) z[t] += dz[t];
+}
+
+void launch_net_accept(int64_t n, const double *d, const double *dz, double *z, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_net_accept, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, n, d, dz, z, flag);
 }
 
 void launch_net_loss(const Grid &g, const double *coef, const float *y, const double *e, double t_scale,

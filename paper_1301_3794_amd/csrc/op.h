@@ -163,6 +163,10 @@ struct dm_op {
     dm_net *net = nullptr;
     double *ln_t1 = nullptr, *ln_t2 = nullptr, *ln_t3 = nullptr, *ln_t4 = nullptr;  // 3P each
     int ln_accepted = 0, ln_rejected = 0;
+    // the residual judge on the device: two sums of squares, the decision
+    // and its pinned host copy
+    double *ln_d = nullptr;
+    int *ln_flag = nullptr, *ln_hflag = nullptr;
     // batched runs: the batch whose fused V-cycle serves this op's FP32
     // preconditioner while dm_batch_eigs runs (not owned), and the op's index
     dm_batch *batch = nullptr;

@@ -281,7 +281,7 @@ int pcg_work(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_s
     double rel = 1.0;
     bool conv = false;
     while (it < maxit) {
-        launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, p, q, s);
+        launch_apply<double>(L.g, L.coef64, op->sigma, AK_M, nullptr, p, q, s, L.cut_cells());
         const double pq = dot1(op, p, q, op->wface, n, s);
         if (!(pq > 0.0)) throw DmError{pq == pq ? DM_EBREAKDOWN : DM_ENAN,
                                        "PCG: operator not positive definite at this shift"};
@@ -301,7 +301,7 @@ int pcg_work(dm_op *op, const double *f, double *x, double rtol, int maxit, dm_s
         rz = rz2;
     }
     // true residual
-    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, r, s);
+    launch_apply<double>(L.g, L.coef64, op->sigma, AK_RESID, f, x, r, s, L.cut_cells());
     rel = std::sqrt(dot1(op, r, r, op->wface, n, s)) / bnorm;
     if (info) {
         info->iterations = it;
