@@ -52,6 +52,11 @@ C3_RESTART = 30
 # inner iterations: 11,021 and 11,013 against 1,059 and 1,056 at 1e-11,
 # measured with the same trained network.)
 LEARNED_INNER_RTOL = 1e-11
+# training set of the learned form: this many random ellipsoids at 64^3, 5
+# rounds of 200 Adam steps each (one new pair per step): 6,000 pairs; a
+# larger set (20 ellipsoids, 20,000 pairs) is trained and evaluated beside it
+LEARNED_CAVITIES = 6
+LEARNED_CAVITIES_LARGE = 20
 HBM_PEAK_GBS = 8000.0
 CPU_N = 40      # grid of the oracle's timed sample
 
@@ -258,6 +263,64 @@ def run_c3(dm, torch, copy_gbps):
     return res
 
 
+def learned_large(dm, torch, op, train):
+    """The network trained on the larger set (LEARNED_CAVITIES_LARGE
+    ellipsoids, 20,000 pairs) on the bench workload, at the common inner
+    tolerance and at 3e-12; reported whether or not it converges."""
+    net = dm.Net(seed=0)
+    try:
+        hist = train.train_on_ellipsoids(net, n=64, count=LEARNED_CAVITIES_LARGE, steps=200, rounds=5, lr=1e-3,
+                                         sigma=SIGMA)
+        net.attach(op)
+        res = {"pairs": hist["pairs"], "train_seconds": round(hist["train_s"], 2),
+               "loss_per_round": [round(x, 4) for x in hist["loss_per_round"]]}
+        for rtol in (LEARNED_INNER_RTOL, 3e-12):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = op.eigs(K_EIG, sigma=SIGMA, tol=TOL, seed=SEED, solve_mode=dm.SOLVE_FGMRES_MG32_LEARNED,
+                        block=BLOCK, max_basis=MAX_BASIS, inner_rtol=rtol)
+            torch.cuda.synchronize()
+            res[f"inner_rtol_{rtol:g}"] = {"status": o["status"], "s_per_eigenpair": (time.perf_counter() - t0) / K_EIG,
+                                           "outer_iterations": o["outer_iterations"],
+                                           "inner_iterations": o["inner_iterations"],
+                                           "restarts": o["restarts"], "max_residual": o["max_residual"]}
+        dm.Net.detach(op)
+    finally:
+        net.close()
+    return res
+
+
+def learned_ninecell(dm, torch, net):
+    """The learned correction on a cavity unlike its training set: the 9-cell
+    quarter at 48 x 48 x 512 (PMC planes, sigma = 632, 9 modes, the 9-cell
+    eigensolver settings), plain FP32-multigrid form and learned form with
+    the same network, with the eigenvalues' errors against the stored oracle
+    values where they exist."""
+    import numpy as np
+    geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1, bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
+    path = os.path.join(ROOT, "tests", "golden", "ninecell_quarter_512_oracle.json")
+    ref = np.array(json.load(open(path))["lam"]) if os.path.exists(path) else None
+    res = {"grid": [48, 48, 512]}
+    with dm.Operator(geom, (48, 48, 512), 1.235 / 512, 632.0, levels=0, fgmres_restart=C3_RESTART,
+                     nu_pre=C3_NU, nu_post=C3_NU) as op:
+        net.attach(op)
+        for name, mode, rtol in (("plain", dm.SOLVE_FGMRES_MG32, 1e-11),
+                                 ("learned", dm.SOLVE_FGMRES_MG32_LEARNED, LEARNED_INNER_RTOL)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = op.eigs(9, sigma=632.0, tol=TOL, seed=3, solve_mode=mode, block=C3_BLOCK, max_basis=48,
+                        max_restarts=30, inner_rtol=rtol)
+            torch.cuda.synchronize()
+            r = {"status": o["status"], "s_per_eigenpair": (time.perf_counter() - t0) / 9,
+                 "inner_iterations": o["inner_iterations"], "outer_iterations": o["outer_iterations"],
+                 "max_residual": o["max_residual"]}
+            if ref is not None:
+                r["max_rel_err_vs_oracle"] = float(np.max(abs(o["lam"] - ref) / ref))
+            res[name] = r
+        dm.Net.detach(op)
+    return res
+
+
 def run_c1(dm, torch, reps=5):
     """The small configuration: sphere R = 0.45 at 16^3 (h = 1/16), sigma =
     5, 3-level V-cycle, the 4 lowest pairs to rho <= 1e-10 in the
@@ -449,7 +512,8 @@ def main():
         log("learned form: training")
         from paper_1301_3794_amd import train
         net = dm.Net(seed=0)
-        hist = train.train_on_ellipsoids(net, n=64, count=6, steps=200, rounds=5, lr=1e-3, sigma=SIGMA)
+        hist = train.train_on_ellipsoids(net, n=64, count=LEARNED_CAVITIES, steps=200, rounds=5, lr=1e-3,
+                                         sigma=SIGMA)
         net.attach(op)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -461,10 +525,14 @@ def main():
                                 inner_iterations=ol["inner_iterations"],
                                 outer_iterations=ol["outer_iterations"],
                                 training={"pairs": hist["pairs"], "seconds": round(hist["train_s"], 2),
-                                          "cavities": "6 ellipsoids at 64^3, sigma=36",
+                                          "cavities": f"{LEARNED_CAVITIES} ellipsoids at 64^3, sigma=36",
                                           "loss_per_round": [round(x, 4) for x in hist["loss_per_round"]]})
         dm.Net.detach(op)
+        log("learned form on the 9-cell quarter at 48x48x512")
+        forms["learned"]["ninecell_48x48x512"] = learned_ninecell(dm, torch, net)
         net.close()
+        log("learned form: the larger training set")
+        forms["learned"]["larger_training_set"] = learned_large(dm, torch, op, train)
     golden = os.path.join(ROOT, "tests", "golden", "sphere128_oracle.json")
     if os.path.exists(golden):
         ref = np.array(json.load(open(golden))["lam"][:K_EIG])
