@@ -58,6 +58,8 @@ LEARNED_INNER_RTOL = 1e-11
 LEARNED_CAVITIES = 6
 LEARNED_CAVITIES_LARGE = 20
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0    # dense bfloat16 MFMA
+NET_FLOP_PER_CELL = 2 * 27 * (10 * 16 + 16 * 16 + 16 * 3)   # the learned network's three convolutions
 CPU_N = 40      # grid of the oracle's timed sample
 
 # Algorithmic bytes per cell (3 face unknowns) of the FP32 kernels: every
@@ -151,12 +153,13 @@ def parse():
     ap.add_argument("--skip-c3", action="store_true", help="do not run the 9-cell quarter cavity")
     ap.add_argument("--skip-c4", action="store_true", help="do not run the 64 batched ellipsoids")
     ap.add_argument("--skip-studies", action="store_true", help="do not run the accuracy and solver studies")
-    ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep", "studies"], default=None,
+    ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep", "studies", "learnediter"], default=None,
                     help="profiling runs: only the 9-cell cavity, only the batch, the HBM-traffic "
                          "probe (a 256 MiB device copy of known size, then 3 FP32 red-black sweeps "
                          "on the 128^3 sphere's finest level), or the same probe on the 9-cell "
                          "quarter's finest level (3 one-vector and 3 two-vector sweeps), or only "
-                         "the accuracy and solver-sensitivity studies")
+                         "the accuracy and solver-sensitivity studies, or 15 FGMRES iterations of the plain "
+                         "and the learned form at 128^3 (untrained network, every correction judged)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
@@ -261,6 +264,36 @@ def run_c3(dm, torch, copy_gbps):
                                  "max_residual": o["max_residual"],
                                  "rel_err_vs_oracle": (abs(o["lam"] - lr) / lr).tolist()})
     return res
+
+
+def learned_iterations(dm, torch, its=15):
+    """One solve M x = A w (w ~ N(0,1) on the active faces, seed 1) on the
+    128^3 sphere, `its` FGMRES iterations of the plain FP32-multigrid form
+    and of the learned form with a freshly initialised network whose every
+    correction is judged (learned_patience = 0): milliseconds per iteration
+    of each, for the kernel profile of a learned iteration."""
+    out = {}
+    with dm.Operator(dm.sphere((0.5, 0.5, 0.5), R), (N, N, N), 1.0 / N, SIGMA, levels=LEVELS,
+                     learned_patience=0) as op:
+        net = dm.Net(seed=0)
+        net.attach(op)
+        mask = torch.tensor(op.fractions(0)[:3].reshape(-1) > 0)
+        w = (torch.randn(mask.numel(), dtype=torch.float64, generator=torch.Generator().manual_seed(1)) * mask).cuda()
+        f = op.apply(dm.APPLY_A, w, op.face_tensor())
+        for mode, name in ((dm.SOLVE_FGMRES_MG32, "plain"), (dm.SOLVE_FGMRES_MG32_LEARNED, "learned")):
+            x = op.face_tensor()
+            op.solve(f, x, mode=mode, rtol=1e-11, maxit=its)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = op.solve(f, x, mode=mode, rtol=1e-11, maxit=its)
+            torch.cuda.synchronize()
+            out[name] = {"ms_per_iteration": 1e3 * (time.perf_counter() - t0) / r["iterations"],
+                         "iterations": r["iterations"], "corrections_kept": r["learned_accepted"],
+                         "corrections_rejected": r["learned_rejected"]}
+        out["network_forward_ms"] = op.time_kernel(dm.KERNEL_NET, prec=32, level=0, reps=20)
+        dm.Net.detach(op)
+        net.close()
+    return out
 
 
 def learned_large(dm, torch, op, train):
@@ -433,6 +466,9 @@ def main():
     if args.only == "c4":
         print(json.dumps({"c4_batched_ellipsoids": run_c4(dm, torch)}))
         return
+    if args.only == "learnediter":
+        print(json.dumps(learned_iterations(dm, torch)))
+        return
     if args.only == "studies":
         print(json.dumps(run_studies(dm)))
         return
@@ -527,6 +563,14 @@ def main():
                                 training={"pairs": hist["pairs"], "seconds": round(hist["train_s"], 2),
                                           "cavities": f"{LEARNED_CAVITIES} ellipsoids at 64^3, sigma=36",
                                           "loss_per_round": [round(x, 4) for x in hist["loss_per_round"]]})
+        # the network's forward pass (three convolutions) on the 128^3 grid:
+        # algorithmic flops per cell 2 * 27 * (10*16 + 16*16 + 16*3)
+        conv_ms = op.time_kernel(dm.KERNEL_NET, prec=32, level=0, reps=20)
+        cells = N ** 3
+        tf = NET_FLOP_PER_CELL * cells / (conv_ms * 1e-3) / 1e12
+        forms["learned"]["network_forward"] = {
+            "bound": "mfma", "ms_per_pass": conv_ms, "flop_per_pass": NET_FLOP_PER_CELL * cells,
+            "achieved": round(tf, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / BF16_PEAK_TFLOPS, 4)}
         dm.Net.detach(op)
         log("learned form on the 9-cell quarter at 48x48x512")
         forms["learned"]["ninecell_48x48x512"] = learned_ninecell(dm, torch, net)

@@ -490,6 +490,10 @@ int dm_sample_e(dm_op *op, const double *b_dev, double lambda, int npts, const d
 #define DM_KERNEL_PROLONG   5  /* `level`+1 -> `level` */
 #define DM_KERNEL_VCYCLE    6  /* one whole V-cycle, replayed from the solver's
                                   captured graph (level must be 0) */
+#define DM_KERNEL_NET       7  /* the attached learned network's forward pass: its
+                                  three convolutions on the finest grid (bfloat16
+                                  MFMA; level 0, prec 32, a network attached
+                                  with dm_net_attach, else DM_EINVAL) */
 
 /* Average duration of one launch of `kernel` (prec 64 or 32) on seeded
  * N(0,1) data in library-owned buffers: 2 untimed launches, then `reps`

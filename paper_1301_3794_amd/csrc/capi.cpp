@@ -865,7 +865,9 @@ static int time_kernel_impl(dm_op *op, int kernel, int prec, int level, int nrhs
                             double *ms_per_launch) {
     if (!op || !ms_per_launch) return fail(DM_EINVAL, "NULL argument");
     if (prec != 64 && prec != 32) return fail(DM_EINVAL, "prec must be 64 or 32");
-    if (kernel < DM_KERNEL_APPLY || kernel > DM_KERNEL_VCYCLE) return fail(DM_EINVAL, "unknown kernel");
+    if (kernel < DM_KERNEL_APPLY || kernel > DM_KERNEL_NET) return fail(DM_EINVAL, "unknown kernel");
+    if (kernel == DM_KERNEL_NET && (!op->net || level != 0 || prec != 32 || nrhs > 1))
+        return fail(DM_EINVAL, "network timing: attach a network; level 0, prec 32, one vector");
     if (reps < 1) return fail(DM_EINVAL, "reps must be >= 1");
     if (nrhs < 0 || nrhs > kMaxRhs) return fail(DM_EINVAL, "nrhs must be 1..4");
     const bool pair = kernel == DM_KERNEL_RESTRICT || kernel == DM_KERNEL_PROLONG;
@@ -934,6 +936,9 @@ static int time_kernel_impl(dm_op *op, int kernel, int prec, int level, int nrhs
                     case DM_KERNEL_PROLONG:
                         if (prec == 64) launch_prolong_add<double>(L.g, C.g, L.coef64, C.coef64, (double *)c, (double *)y, s);
                         else launch_prolong_add<float>(L.g, C.g, L.coef32, C.coef32, (float *)c, (float *)y, s);
+                        break;
+                    case DM_KERNEL_NET:      // the network's own activation buffers
+                        net_forward(op, s);
                         break;
                     case DM_KERNEL_VCYCLE:   // the solver's graph, between its own buffers
                         vcycle_graphed(op, prec, s);

@@ -154,6 +154,11 @@ void net_attach(dm_op *op, dm_net *net) {
     net->op = op;
 }
 
+void net_forward(dm_op *op, hipStream_t s) {
+    dm_net *net = attached(op);
+    forward(net, op->lv[0].g, s);
+}
+
 void net_apply(dm_op *op, const double *r, double scale, double *out, hipStream_t s) {
     dm_net *net = attached(op);
     const Level &L = op->lv[0];

@@ -273,6 +273,8 @@ void net_free(dm_net *net);
 void net_upload_weights(dm_net *net, const float *host);
 void net_attach(dm_op *op, dm_net *net);
 void net_apply(dm_op *op, const double *r, double scale, double *out, hipStream_t s);
+// the attached network's three convolutions on its current activations
+void net_forward(dm_op *op, hipStream_t s);
 double net_loss_grad(dm_op *op, int kind, const double *r, const double *e, double scale, hipStream_t s);
 void net_make_pair(dm_op *op, uint64_t seed, double *r, double *e, hipStream_t s);
 void net_train(dm_op *op, int kind, int steps, float lr, uint64_t seed, float *loss, hipStream_t s);

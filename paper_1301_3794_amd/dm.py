@@ -36,7 +36,8 @@ EXPORTS = (
     "dm_net_loss_grad", "dm_net_make_pair", "dm_net_train", "dm_batch_create", "dm_batch_destroy",
     "dm_batch_member", "dm_batch_info", "dm_batch_vcycle", "dm_batch_time_vcycle", "dm_batch_eigs",
 )
-KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_SMOOTH, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE = range(7)
+(KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_SMOOTH, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE,
+ KERNEL_NET) = range(8)
 
 
 class DMError(RuntimeError):

@@ -249,4 +249,10 @@ def test_learned_mode_needs_a_network(case):
     dm.Net.detach(op)
     with pytest.raises(dm.DMError):
         op.solve(op.face_tensor(), op.face_tensor(), mode=dm.SOLVE_FGMRES_MG32_LEARNED)
+    with pytest.raises(dm.DMError) as e:
+        op.time_kernel(dm.KERNEL_NET, prec=32, level=0, reps=2)
+    assert e.value.code == dm.DM_EINVAL
     case["net"].attach(op)
+    assert op.time_kernel(dm.KERNEL_NET, prec=32, level=0, reps=2) > 0.0
+    with pytest.raises(dm.DMError):
+        op.time_kernel(dm.KERNEL_NET, prec=64, level=0, reps=2)
