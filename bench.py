@@ -153,6 +153,7 @@ def parse():
     ap.add_argument("--skip-c3", action="store_true", help="do not run the 9-cell quarter cavity")
     ap.add_argument("--skip-c4", action="store_true", help="do not run the 64 batched ellipsoids")
     ap.add_argument("--skip-studies", action="store_true", help="do not run the accuracy and solver studies")
+    ap.add_argument("--skip-c1", action="store_true", help="do not run the small 16^3 configuration")
     ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep", "studies", "learnediter"], default=None,
                     help="profiling runs: only the 9-cell cavity, only the batch, the HBM-traffic "
                          "probe (a 256 MiB device copy of known size, then 3 FP32 red-black sweeps "
@@ -596,8 +597,10 @@ def main():
     roofline["block_vcycle_ms"] = op.time_block_kernel(dm.KERNEL_VCYCLE, BLOCK, prec=32, level=0, reps=20)
     roofline["residual_ms"] = op.time_kernel(dm.KERNEL_RESIDUAL, prec=32, level=0, reps=50)
 
-    log("small configuration (16^3)")
-    c1 = run_c1(dm, torch)
+    c1 = None
+    if not args.skip_c1:
+        log("small configuration (16^3)")
+        c1 = run_c1(dm, torch)
 
     c3 = None
     if not args.skip_c3:
