@@ -126,11 +126,12 @@ typedef struct {
     int nu_post;         /* red-black sweeps after (2) */
     int fgmres_restart;  /* FGMRES restart length (30) */
     int verbose;         /* 0 silent, 1 per-solve lines on stderr */
-    int cut_wave_split;  /* block smoother (2..4 vectors): a class whose list of
-                            non-vacuum rows is shorter than this gives each vector
-                            its own wavefront; a longer list takes one thread per
-                            row looping over the vectors (32768; 0 always takes
-                            the loop).  Both give the same values. */
+    int cut_wave_split;  /* block smoother (2..4 vectors): a component whose list
+                            of non-vacuum rows (both colours) is shorter than this
+                            gives each vector its own wavefront; a longer list
+                            takes one thread per row looping over the vectors
+                            (65536; 0 always takes the loop).  Both give the same
+                            values. */
     int learned_patience; /* DM_SOLVE_FGMRES_MG32_LEARNED: a solve stops trying the
                             network's correction after this many rejections (the
                             correction no longer lowers the residual there); 0

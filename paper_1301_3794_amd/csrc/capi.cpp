@@ -146,7 +146,7 @@ void dm_default_options(dm_options *opt) {
     opt->nu_post = 2;
     opt->fgmres_restart = 30;
     opt->verbose = 0;
-    opt->cut_wave_split = 32768;
+    opt->cut_wave_split = 65536;
     opt->learned_patience = 1;
     opt->grad_div_volume = 1;
     opt->tilde_transfers = 0;
@@ -369,12 +369,12 @@ int dm_smooth(dm_op *op, int prec, int level, int n_sweeps, int reverse, const v
             for (int q = 0; q < 6; ++q) {
                 const int cls = reverse ? 5 - q : q;
                 const int comp = cls / 2, col = cls % 2;
+                // the first colour of each component leaves the second's cross sums
+                const ClassList cl = L.cut_list(comp, col, (q % 2) == 0 ? kPairFirst : kPairSecond, op->cut_s);
                 if (prec == 64)
-                    launch_smooth<double>(L.g, L.coef64, op->sigma, comp, col, (const double *)f, (double *)x, s,
-                                          L.cut_list(comp, col));
+                    launch_smooth<double>(L.g, L.coef64, op->sigma, comp, col, (const double *)f, (double *)x, s, cl);
                 else
-                    launch_smooth<float>(L.g, L.coef32, (float)op->sigma, comp, col, (const float *)f, (float *)x, s,
-                                         L.cut_list(comp, col));
+                    launch_smooth<float>(L.g, L.coef32, (float)op->sigma, comp, col, (const float *)f, (float *)x, s, cl);
             }
         return DM_OK;
     });
@@ -925,8 +925,12 @@ static int time_kernel_impl(dm_op *op, int kernel, int prec, int level, int nrhs
                     case DM_KERNEL_SMOOTH:
                     case DM_KERNEL_SWEEP:
                         for (int q = 0; q < (kernel == DM_KERNEL_SMOOTH ? 1 : 6); ++q) {
-                            if (prec == 64) launch_smooth<double>(L.g, L.coef64, op->sigma, q / 2, q % 2, (double *)f, (double *)x, s, L.cut_list(q / 2, q % 2));
-                            else launch_smooth<float>(L.g, L.coef32, (float)op->sigma, q / 2, q % 2, (float *)f, (float *)x, s, L.cut_list(q / 2, q % 2));
+                            // a sweep pairs the two colours of a component as the V-cycle does
+                            const ClassList cl = kernel == DM_KERNEL_SMOOTH
+                                                     ? L.cut_list(0, 0)
+                                                     : L.cut_list(q / 2, q % 2, q % 2 ? kPairSecond : kPairFirst, op->cut_s);
+                            if (prec == 64) launch_smooth<double>(L.g, L.coef64, op->sigma, q / 2, q % 2, (double *)f, (double *)x, s, cl);
+                            else launch_smooth<float>(L.g, L.coef32, (float)op->sigma, q / 2, q % 2, (float *)f, (float *)x, s, cl);
                         }
                         break;
                     case DM_KERNEL_RESTRICT:
@@ -965,7 +969,10 @@ static int time_kernel_impl(dm_op *op, int kernel, int prec, int level, int nrhs
                     case DM_KERNEL_SMOOTH:
                     case DM_KERNEL_SWEEP:
                         for (int q = 0; q < (kernel == DM_KERNEL_SMOOTH ? 1 : 6); ++q)
-                            launch_smooth_b<T>(L.g, coef, (T)op->sigma, q / 2, q % 2, nrhs, as_const(F), X, s, L.cut_list(q / 2, q % 2));
+                            launch_smooth_b<T>(L.g, coef, (T)op->sigma, q / 2, q % 2, nrhs, as_const(F), X, s,
+                                               kernel == DM_KERNEL_SMOOTH
+                                                   ? L.cut_list(q / 2, q % 2)
+                                                   : L.cut_list(q / 2, q % 2, q % 2 ? kPairSecond : kPairFirst, op->cut_s));
                         break;
                     case DM_KERNEL_RESTRICT:
                         launch_restrict_b<T>(L.g, C.g, ccoef, nrhs, as_const(X), Cc, s);

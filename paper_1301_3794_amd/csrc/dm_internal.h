@@ -238,15 +238,16 @@ __host__ __device__ inline T diag_of(const Coefs<T> &c, int comp, int64_t p, int
 // ---------------------------------------------------------------------------
 // Tabulated cut rows of the smoother.  The row of M at a face of component
 // c reads 15 stored entries (PMC ghost images counted as entries of their
-// own): 7 of its own component and 4 of each other one, at fixed offsets
-// (cut_term).  For every listed cut row the operator stores kCutW values,
-// term-major over the class's list: the 15 weights w_t of the row of
-// K + G (with 1/h^2), the face's area fraction a, and the diagonal d0 of
-// K + G at the face including the PMC self-coupling; a class update is
+// own): 7 of its own component (t < kCutOwn) and 4 of each other one, at
+// fixed offsets (cut_term).  For every listed cut row the operator stores
+// kCutW values, term-major over the component's list: the 15 weights w_t of
+// the row of K + G (with 1/h^2), the face's area fraction a, and the
+// diagonal d0 of K + G at the face including the PMC self-coupling; a class
+// update is
 //     x_f += (f_f - sum_t w_t x_t + sigma a x_f) / (d0 - sigma a),
 // the same update as from the fractions (the shift stays out of the table).
 // ---------------------------------------------------------------------------
-constexpr int kCutTerms = 15, kCutW = kCutTerms + 2;
+constexpr int kCutTerms = 15, kCutW = kCutTerms + 2, kCutOwn = 7;
 struct CutTerm {
     int comp, di, dj, dk;
 };
@@ -327,6 +328,8 @@ __host__ __device__ inline VPtr<const T> as_const(const VPtr<T> &x) {
 // The non-vacuum (cut) rows of one smoother class as padded indices; with a
 // list the class update runs as two parts (see k_smooth_split).
 struct ClassList {
+    // smoother: the cut rows of one component, both colours, in index order;
+    // apply and residual: the cells with a cut row
     const int32_t *idx = nullptr;
     int64_t n = 0;
     // for the smoother's vacuum part: the grid rows (k * ny + j) holding a
@@ -335,12 +338,25 @@ struct ClassList {
     int64_t nrows = 0;
     // block smoother: below this many listed rows each vector gets its own
     // wavefront, else one thread per row loops over the vectors
-    int64_t wave_split_max = 32768;
+    int64_t wave_split_max = 65536;
     // the tabulated rows of the listed cut rows (kCutW x n, term-major), per
     // precision (see cut_term)
     const double *w64 = nullptr;
     const float *w32 = nullptr;
+    // smoother only: how the update of the rows of colour `colour` is paired
+    // with the other colour's (the other components do not change between the
+    // two colour updates of a component, so the cross-component part of a
+    // row is the same in both):
+    //   kPairNone   one class update on its own (every term inline);
+    //   kPairFirst  the first of the two: this colour's rows take every term,
+    //               the other colour's rows store the sum of their
+    //               cross-component terms in s (n per vector);
+    //   kPairSecond the second: this colour's rows take their own-component
+    //               terms and the sum stored in s by the first
+    int pair = 0;
+    void *s = nullptr;
 };
+constexpr int kPairNone = 0, kPairFirst = 1, kPairSecond = 2;
 template <class T>
 inline const T *cut_weights(const ClassList &cl);
 template <>

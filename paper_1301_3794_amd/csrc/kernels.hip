@@ -338,18 +338,52 @@ __device__ __forceinline__ void smooth_vac_n(const Grid &g, const Coefs<T> &c, T
     for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
 }
 
-// entry e of the class's cut list from its tabulated row W (kCutW x ncut,
-// term-major; see cut_term): the weights are loaded once for the NR vectors
+// entry e of the component's cut list (both colours, index order) from its
+// tabulated row W (kCutW x ncut, term-major; see cut_term), for the update of
+// colour `colour` paired as `pair` says (see ClassList): the row is
+// -sigma a x_f + (own-component terms) + (cross-component terms), the latter
+// summed first, inline or taken from S (ncut per vector, vector q0 + q);
+// the weights are loaded once for the NR vectors
 template <class T, int COMP, int NR>
 __device__ __forceinline__ void smooth_cut_n(const Grid &g, T sigma, const int32_t *__restrict__ cut, int64_t ncut,
-                                             const T *__restrict__ W, const VPtr<const T> &f, const VPtr<T> &x,
-                                             int64_t e) {
+                                             const T *__restrict__ W, int colour, int pair, T *__restrict__ S,
+                                             int q0, const VPtr<const T> &f, const VPtr<T> &x, int64_t e) {
     if (e >= ncut) return;
     const int64_t P = g.P, dy = g.sy, dz = g.sz;
     const int64_t p = cut[e];
-    T w[kCutTerms];
+    const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
+    const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
+    const bool mine = ((i + j + k) & 1) == colour;
+    // the other colour's rows: nothing, or (first of a pair) their cross sums
+    if (!mine && pair != kPairFirst) return;
+    T cross[NR];
+    if (pair == kPairSecond) {
 #pragma unroll
-    for (int t = 0; t < kCutTerms; ++t) w[t] = W[t * ncut + e];
+        for (int q = 0; q < NR; ++q) cross[q] = S[(int64_t)(q0 + q) * ncut + e];
+    } else {
+        T w[kCutTerms - kCutOwn];
+#pragma unroll
+        for (int t = kCutOwn; t < kCutTerms; ++t) w[t - kCutOwn] = W[t * ncut + e];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const T *X = x.p[q];
+            T c = T(0);
+#pragma unroll
+            for (int t = kCutOwn; t < kCutTerms; ++t) {
+                const CutTerm ct = cut_term(COMP, t);
+                c += w[t - kCutOwn] * X[ct.comp * P + p + ct.di + ct.dj * dy + ct.dk * dz];
+            }
+            cross[q] = c;
+        }
+        if (!mine) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) S[(int64_t)(q0 + q) * ncut + e] = cross[q];
+            return;
+        }
+    }
+    T w[kCutOwn];
+#pragma unroll
+    for (int t = 0; t < kCutOwn; ++t) w[t] = W[t * ncut + e];
     const T a = W[kCutTerms * ncut + e];
     const T d = W[(kCutTerms + 1) * ncut + e] - sigma * a;
     T nv[NR];
@@ -359,14 +393,13 @@ __device__ __forceinline__ void smooth_cut_n(const Grid &g, T sigma, const int32
         const T xs = X[COMP * P + p];
         T row = -sigma * a * xs;
 #pragma unroll
-        for (int t = 0; t < kCutTerms; ++t) {
+        for (int t = 0; t < kCutOwn; ++t) {
             const CutTerm ct = cut_term(COMP, t);
             row += w[t] * X[ct.comp * P + p + ct.di + ct.dj * dy + ct.dk * dz];
         }
+        row += cross[q];
         nv[q] = xs + (f.p[q][COMP * P + p] - row) / d;
     }
-    const int64_t kk = p / dz, rr = p - kk * dz, jj = rr / dy;
-    const int i = (int)(rr - jj * dy) - 1, j = (int)jj - 1, k = (int)kk - 1;
 #pragma unroll
     for (int q = 0; q < NR; ++q) put_face<T>(g, x.p[q] + COMP * P, COMP, i, j, k, p, nv[q]);
 }
@@ -400,17 +433,18 @@ k_smooth_b(Grid g, Coefs<T> c, T sigma, int colour, VPtr<const T> f, VPtr<T> x) 
 template <class T, int COMP, int NR>
 __global__ void __launch_bounds__(kThreads)
 k_smooth_split(Grid g, Coefs<T> c, T sigma, int colour, const int32_t *__restrict__ cut, int64_t ncut, int64_t ncb,
-               int wave_split, const T *__restrict__ W, const int32_t *__restrict__ rows, int64_t nrows,
-               VPtr<const T> f, VPtr<T> x) {
+               int wave_split, const T *__restrict__ W, int pair, T *__restrict__ S,
+               const int32_t *__restrict__ rows, int64_t nrows, VPtr<const T> f, VPtr<T> x) {
     const int64_t b = blockIdx.x;
     if (b < ncb) {
         const int64_t L = (b % kXcd) * (ncb / kXcd) + b / kXcd;
         if (!wave_split) {
-            smooth_cut_n<T, COMP, NR>(g, sigma, cut, ncut, W, f, x, L * kThreads + threadIdx.x);
+            smooth_cut_n<T, COMP, NR>(g, sigma, cut, ncut, W, colour, pair, S, 0, f, x, L * kThreads + threadIdx.x);
         } else {
             const int q = threadIdx.x >> 6;
             if (q >= NR) return;
-            smooth_cut_n<T, COMP, 1>(g, sigma, cut, ncut, W, vptr1(f.p[q]), vptr1(x.p[q]), L * 64 + (threadIdx.x & 63));
+            smooth_cut_n<T, COMP, 1>(g, sigma, cut, ncut, W, colour, pair, S, q, vptr1(f.p[q]), vptr1(x.p[q]),
+                                     L * 64 + (threadIdx.x & 63));
         }
     } else {
         const int64_t bv = b - ncb, nvb = (int64_t)gridDim.x - ncb;
@@ -1624,10 +1658,11 @@ void launch_prolong_add(const Grid &gf, const Grid &gc, const T *coef_f, const T
                        coefs_of(coef_f, gf.P), coefs_of(coef_c, gc.P), xc, x);
 }
 
-// cut rows of a class below which the block smoother gives each vector its
-// own wave: ClassList::wave_split_max, an operator option (default 32768,
-// measured on the 128^3 sphere: ~60k rows per class on the finest level
-// favour the in-thread loop, ~15k rows on the next the waves)
+// cut rows of a component (both colours) below which the block smoother
+// gives each vector its own wave: ClassList::wave_split_max, an operator
+// option (default 65536, measured on the 128^3 sphere: ~60k rows per colour
+// on the finest level favour the in-thread loop, ~15k rows on the next the
+// waves)
 
 // ---- block forms: dispatch nr (1..kMaxRhs) to the template
 #define DM_NR_SWITCH(nr, CALL)                      \
@@ -1692,6 +1727,8 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
     const Coefs<T> c = coefs_of(coef, g.P);
     if (cut.idx) {
         if (cut.n > 0 && !cut_weights<T>(cut)) throw std::runtime_error("smoother: cut list without its row table");
+        if (cut.pair != kPairNone && !cut.s) throw std::runtime_error("smoother: paired update without its sums");
+        T *S = static_cast<T *>(cut.s);
         const int wave_split = nr > 1 && cut.n < cut.wave_split_max;
         const int64_t ncb = ceil_div(ceil_div(cut.n, wave_split ? 64 : kThreads), kXcd) * kXcd;
         // the vacuum part sweeps the listed rows (every row without a list)
@@ -1700,13 +1737,16 @@ void launch_smooth_b(const Grid &g, const T *coef, T sigma, int comp, int colour
         const dim3 grid((unsigned)(ncb + nvb));
         if (comp == 0)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 0, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.rows, cut.nrows, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.pair,
+                                                S, cut.rows, cut.nrows, f, x))
         else if (comp == 1)
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 1, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.rows, cut.nrows, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.pair,
+                                                S, cut.rows, cut.nrows, f, x))
         else
             DM_NR_SWITCH(nr, hipLaunchKernelGGL((k_smooth_split<T, 2, NR>), grid, dim3(kThreads), 0, s, g, c, sigma,
-                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.rows, cut.nrows, f, x))
+                                                colour, cut.idx, cut.n, ncb, wave_split, cut_weights<T>(cut), cut.pair,
+                                                S, cut.rows, cut.nrows, f, x))
         return;
     }
     if (comp == 0)

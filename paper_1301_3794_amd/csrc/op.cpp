@@ -218,30 +218,33 @@ static void refine_vacuum_flags(const Grid &g, const std::vector<double> &c, std
     for (auto &t : th) t.join();
 }
 
-// The tables of a level: its smoother classes' cut lists (class q's rows of
-// component q / 2, term-major, starting at kCutW * cut_off[q]) and its list
-// of cells with a cut row (the three components' rows of each cell: entry
-// (comp, t) of cell e at (comp * kCutW + t) * ncells + e).  Threaded.
+// The tables of a level: its components' cut lists (component c's rows,
+// term-major, starting at kCutW * cut_off[c]) and its list of cells with a
+// cut row (the three components' rows of each cell: entry (comp, t) of cell
+// e at (comp * kCutW + t) * ncells + e).  Threaded.
 static void cut_tables(const Grid &g, const std::vector<double> &c, const std::vector<int32_t> &cut,
-                       const int64_t cut_off[7], const std::vector<int32_t> &cells, std::vector<double> &rows_tab,
+                       const int64_t cut_off[4], const std::vector<int32_t> &cells, std::vector<double> &rows_tab,
                        std::vector<double> &cells_tab) {
     const Coefs<double> cg = coefs_of(c.data(), g.P);
     rows_tab.assign((size_t)kCutW * cut.size(), 0.0);
     cells_tab.assign((size_t)3 * kCutW * cells.size(), 0.0);
     const int64_t nc = (int64_t)cells.size();
+    constexpr int kParts = 4;   // threads per component list
     auto work = [&](int part) {
-        if (part < 6) {
-            const int64_t n = cut_off[part + 1] - cut_off[part];
-            double *T = rows_tab.data() + (size_t)kCutW * cut_off[part];
-            for (int64_t e = 0; e < n; ++e) tab_row(g, c, cg, part / 2, cut[cut_off[part] + e], T + e, n);
+        if (part < 3 * kParts) {
+            const int comp = part / kParts, piece = part % kParts;
+            const int64_t n = cut_off[comp + 1] - cut_off[comp];
+            double *T = rows_tab.data() + (size_t)kCutW * cut_off[comp];
+            for (int64_t e = n * piece / kParts; e < n * (piece + 1) / kParts; ++e)
+                tab_row(g, c, cg, comp, cut[cut_off[comp] + e], T + e, n);
         } else {
-            const int comp = part - 6;
+            const int comp = part - 3 * kParts;
             for (int64_t e = 0; e < nc; ++e)
                 tab_row(g, c, cg, comp, cells[e], cells_tab.data() + (size_t)comp * kCutW * nc + e, nc);
         }
     };
     std::vector<std::thread> th;
-    for (int q = 0; q < 9; ++q) th.emplace_back(work, q);
+    for (int q = 0; q < 3 * kParts + 3; ++q) th.emplace_back(work, q);
     for (auto &t : th) t.join();
 }
 
@@ -293,20 +296,20 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         DM_HIP(hipMemcpyAsync(L.coef32, c32.data(), 7 * P * sizeof(float), hipMemcpyHostToDevice, op->stream));
         DM_HIP(hipMemcpyAsync(L.coef64 + 7 * P, fl.data(), P, hipMemcpyHostToDevice, op->stream));
         DM_HIP(hipMemcpyAsync(L.coef32 + 7 * P, fl.data(), P, hipMemcpyHostToDevice, op->stream));
-        // the cut (non-vacuum) rows of every smoother class, in index order
+        // the cut (non-vacuum) rows of every component, both colours, in
+        // index order
         std::vector<int32_t> cut;
-        for (int comp = 0; comp < 3; ++comp)
-            for (int col = 0; col < 2; ++col) {
-                L.cut_off[2 * comp + col] = (int64_t)cut.size();
-                for (int k = 0; k < L.g.nz; ++k)
-                    for (int j = 0; j < L.g.ny; ++j)
-                        for (int i = ((j + k + col) & 1); i < L.g.nx; i += 2) {
-                            const int64_t p = pidx(L.g, i, j, k);
-                            if ((fl[p] & (kFaceActive << comp)) && !(fl[p] & (kFaceVacuum << comp)))
-                                cut.push_back((int32_t)p);
-                        }
-            }
-        L.cut_off[6] = (int64_t)cut.size();
+        for (int comp = 0; comp < 3; ++comp) {
+            L.cut_off[comp] = (int64_t)cut.size();
+            for (int k = 0; k < L.g.nz; ++k)
+                for (int j = 0; j < L.g.ny; ++j)
+                    for (int i = 0; i < L.g.nx; ++i) {
+                        const int64_t p = pidx(L.g, i, j, k);
+                        if ((fl[p] & (kFaceActive << comp)) && !(fl[p] & (kFaceVacuum << comp)))
+                            cut.push_back((int32_t)p);
+                    }
+        }
+        L.cut_off[3] = (int64_t)cut.size();
         std::vector<int32_t> cutc;
         for (int k = 0; k < L.g.nz; ++k)
             for (int j = 0; j < L.g.ny; ++j)
@@ -432,6 +435,11 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
         L.r64 = op->dalloc<double>(3 * P);
         L.r32 = op->dalloc<float>(3 * P);
         L.sr = op->dalloc<double>(P);
+    }
+    {
+        int64_t m = 1;
+        for (const Level &L : op->lv) m = std::max(m, L.max_cut_rows());
+        op->cut_s = op->dalloc<double>((size_t)m * kMaxRhs);
     }
     // level-0 masks and weights over the owned (non-ghost) entries:
     //   fmask  1 on active faces;  cmask 1 on active cells;

@@ -2,6 +2,7 @@
 // coarsest-level dense inverses and Krylov workspaces.
 #pragma once
 
+#include <algorithm>
 #include <condition_variable>
 #include <cstdio>
 #include <mutex>
@@ -26,10 +27,10 @@ struct Level {
     double *bsx = nullptr, *bsf = nullptr, *bsr = nullptr;  // kMaxRhs * P (scalar MG)
     float *bsx32 = nullptr, *bsf32 = nullptr, *bsr32 = nullptr;  // the same, FP32 scalar MG
     int64_t n_act_faces = 0, n_act_cells = 0;
-    // non-vacuum rows of each smoother class (component c, colour col) as
-    // padded indices: class 2c+col is cut[cut_off[2c+col] .. cut_off[2c+col+1])
+    // non-vacuum rows of each component c (both colours, index order) as
+    // padded indices: cut[cut_off[c] .. cut_off[c+1])
     int32_t *cut = nullptr;
-    int64_t cut_off[7] = {};
+    int64_t cut_off[4] = {};
     // cells with an active non-vacuum row (any component), padded indices
     int32_t *cutc = nullptr;
     int64_t ncutc = 0;
@@ -60,17 +61,27 @@ struct Level {
         return cl;
     }
     // the block smoother's threshold for one wave per vector (dm_options)
-    int64_t cut_wave_split = 32768;
+    int64_t cut_wave_split = 65536;
     // tabulated rows of the cut lists (kCutW values per row, term-major per
-    // class: class q's table starts at kCutW * cut_off[q])
+    // component: component c's table starts at kCutW * cut_off[c])
     double *cutw64 = nullptr;
     float *cutw32 = nullptr;
-    ClassList cut_list(int comp, int colour) const {
-        const int q = 2 * comp + colour;
-        ClassList cl{cut ? cut + cut_off[q] : nullptr, cut_off[q + 1] - cut_off[q], vrows, nvrows, cut_wave_split};
-        if (cutw64) cl.w64 = cutw64 + kCutW * cut_off[q];
-        if (cutw32) cl.w32 = cutw32 + kCutW * cut_off[q];
+    // the smoother's list for class (comp, colour): the component's cut rows,
+    // paired as `pair` says (kPairNone, kPairFirst, kPairSecond) with the
+    // cross sums in s (at least the list's length times the vectors)
+    ClassList cut_list(int comp, int colour, int pair = kPairNone, void *s = nullptr) const {
+        ClassList cl{cut ? cut + cut_off[comp] : nullptr, cut_off[comp + 1] - cut_off[comp], vrows, nvrows,
+                     cut_wave_split};
+        if (cutw64) cl.w64 = cutw64 + kCutW * cut_off[comp];
+        if (cutw32) cl.w32 = cutw32 + kCutW * cut_off[comp];
+        cl.pair = pair;
+        cl.s = s;
         return cl;
+    }
+    int64_t max_cut_rows() const {
+        int64_t m = 0;
+        for (int c = 0; c < 3; ++c) m = std::max(m, cut_off[c + 1] - cut_off[c]);
+        return m;
     }
 };
 
@@ -108,6 +119,10 @@ struct dm_op {
     std::vector<dm::Level> lv;
     std::vector<std::vector<double>> frac;  // host fractions per level (7P, v not vinv)
     // coarsest vector level: dense FP64 inverse over active faces
+    // the smoother's cross-component sums between the two colour updates of
+    // a component (kPairFirst / kPairSecond): the longest cut list of any
+    // level and component times kMaxRhs, in doubles
+    void *cut_s = nullptr;
     int nc = 0;
     double *cinv = nullptr;
     int64_t *cidx = nullptr;

@@ -419,9 +419,13 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
         return;
     }
     const T *c = Prec<T>::coef(L);
+    // the two colour updates of a component are paired: the first leaves the
+    // second colour's cross-component sums in op->cut_s
     for (int it = 0; it < op->opt.nu_pre; ++it)
         for (int comp = 0; comp < 3; ++comp)
-            for (int col = 0; col < 2; ++col) launch_smooth<T>(g, c, sig, comp, col, f, x, s, L.cut_list(comp, col));
+            for (int col = 0; col < 2; ++col)
+                launch_smooth<T>(g, c, sig, comp, col, f, x, s,
+                                 L.cut_list(comp, col, col == 0 ? kPairFirst : kPairSecond, op->cut_s));
     T *r = Prec<T>::r(L);
     launch_apply<T>(g, c, sig, AK_RESID, f, x, r, s, L.cut_cells());
     Level &C = op->lv[l + 1];
@@ -443,7 +447,9 @@ void vcycle(dm_op *op, int l, const T *f, T *x, hipStream_t s) {
     }
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int comp = 2; comp >= 0; --comp)
-            for (int col = 1; col >= 0; --col) launch_smooth<T>(g, c, sig, comp, col, f, x, s, L.cut_list(comp, col));
+            for (int col = 1; col >= 0; --col)
+                launch_smooth<T>(g, c, sig, comp, col, f, x, s,
+                                 L.cut_list(comp, col, col == 1 ? kPairFirst : kPairSecond, op->cut_s));
 }
 
 template void vcycle<double>(dm_op *, int, const double *, double *, hipStream_t);
@@ -471,7 +477,8 @@ void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     for (int it = 0; it < op->opt.nu_pre; ++it)
         for (int comp = 0; comp < 3; ++comp)
             for (int col = 0; col < 2; ++col)
-                launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s, L.cut_list(comp, col));
+                launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s,
+                                   L.cut_list(comp, col, col == 0 ? kPairFirst : kPairSecond, op->cut_s));
     const VPtr<T> R = slots(BPrec<T>::r(L), n3, nr);
     // the residual, restriction and prolongation visit only the grid rows
     // holding an active face: the residual slots, the coarse right-hand
@@ -487,7 +494,8 @@ void vcycle_b(dm_op *op, int l, int nr, hipStream_t s) {
     for (int it = 0; it < op->opt.nu_post; ++it)
         for (int comp = 2; comp >= 0; --comp)
             for (int col = 1; col >= 0; --col)
-                launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s, L.cut_list(comp, col));
+                launch_smooth_b<T>(g, c, sig, comp, col, nr, as_const(F), X, s,
+                                   L.cut_list(comp, col, col == 1 ? kPairFirst : kPairSecond, op->cut_s));
 }
 
 void svcycle(dm_op *op, int l, const double *f, double *x, hipStream_t s) {
