@@ -213,15 +213,23 @@ int dm_residual(dm_op *op, int prec, int level, const void *f_dev,
                 const void *x_dev, void *r_dev, void *stream);
 
 /* n_sweeps red-black Gauss--Seidel sweeps of M x = f on `level`, in place on
- * x.  One sweep updates the six classes (component, colour (i+j+k) mod 2)
- * in the order (x,0)(x,1)(y,0)(y,1)(z,0)(z,1); reverse != 0 uses the
- * reverse order (post-smoothing).  prec 64 or 32. */
+ * x.  Sec. 6 smooths on every level on the way down and up of its
+ * multigrid cycle (its smoother was a polynomial one in algebraic
+ * multigrid); this smoother is a reading of that step for the geometric
+ * V-cycle: one sweep updates the six classes (component, colour
+ * (i+j+k) mod 2) in the order (x,0)(x,1)(y,0)(y,1)(z,0)(z,1); reverse != 0
+ * uses the reverse order (post-smoothing).  prec 64 or 32. */
 int dm_smooth(dm_op *op, int prec, int level, int n_sweeps, int reverse,
               const void *f_dev, void *x_dev, void *stream);
 
-/* Staggered transfers between `level` and `level`+1 (prec 64 or 32).
- * Prolongation P: linear along the face normal, constant across it,
- * inactive faces of either level dropped.  Restriction R = P^T / 8.
+/* Staggered transfers between `level` and `level`+1 (prec 64 or 32), the
+ * grid transfers of the geometric V-cycle that stands in for Sec. 6's
+ * algebraic multigrid (the paper is silent on them; a reading).
+ * Prolongation P: constant across the face normal; along it, a fine face
+ * on a coarse face takes its value and one between two coarse faces takes
+ * their mean weighted by the coarse area fractions, (a0 x0 + a1 x1) /
+ * (a0 + a1); inactive faces of either level dropped.  Restriction
+ * R = P^T / 8.
  *   dm_restrict:    f_coarse = R r_fine
  *   dm_prolong_add: x_fine  += P x_coarse */
 int dm_restrict(dm_op *op, int prec, int level, const void *r_fine_dev,
@@ -229,9 +237,11 @@ int dm_restrict(dm_op *op, int prec, int level, const void *r_fine_dev,
 int dm_prolong_add(dm_op *op, int prec, int level, const void *x_coarse_dev,
                    void *x_fine_dev, void *stream);
 
-/* One multigrid V-cycle x = B f for M on level 0, zero initial guess:
- * nu_pre sweeps, residual, restriction, recursion, prolongation, nu_post
- * reverse sweeps; exact dense FP64 solve on the coarsest level.  prec 64
+/* One multigrid V-cycle x = B f for M on level 0, zero initial guess (the
+ * preconditioner of Sec. 6's inversions of M, eq. discLaplDM, as a
+ * geometric V-cycle: a reading of the paper's algebraic one): nu_pre
+ * sweeps, residual, restriction, recursion, prolongation, nu_post reverse
+ * sweeps; exact dense FP64 solve on the coarsest level.  prec 64
  * (all FP64) or 32 (FP32 smoothing/transfers, FP64 coarsest solve).
  * Runs the same captured HIP graph the solvers use (f and x are copied to
  * and from the op's own buffers); the graph is recorded on first use and
