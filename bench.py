@@ -85,9 +85,9 @@ VCYCLE_BYTES_PER_CELL = 359.0 * 8.0 / 7.0
 # 256 MiB device copy): bytes per sweep of the six class launches, per
 # workload and block size, for the kernels as they are now (None where no
 # counter run of the current kernels exists).  Summaries under profiles/.
-SWEEP_TRAFFIC_BYTES = {"sphere128_3": 430255891,   # profiles/block_sweep_sphere128_hbm_traffic.md
-                       "ninecell_1": 895147839,    # profiles/sweep_ninecell_96x96x1024_hbm_traffic.md
-                       "ninecell_2": 1720074556}
+SWEEP_TRAFFIC_BYTES = {"sphere128_3": 375238954,   # profiles/block_sweep_sphere128_hbm_traffic.md
+                       "ninecell_1": 831521556,    # profiles/sweep_ninecell_96x96x1024_hbm_traffic.md
+                       "ninecell_2": 1549521239}
 
 
 def log(msg):
