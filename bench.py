@@ -552,15 +552,30 @@ def main():
         hist = train.train_on_ellipsoids(net, n=64, count=LEARNED_CAVITIES, steps=200, rounds=5, lr=1e-3,
                                          sigma=SIGMA)
         net.attach(op)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ol = solve(dm.SOLVE_FGMRES_MG32_LEARNED, inner_rtol=LEARNED_INNER_RTOL)
-        torch.cuda.synchronize()
-        dl = time.perf_counter() - t1
-        forms["learned"] = dict(s_per_eigenpair=dl / K_EIG, lam=ol["lam"].tolist(), inner_rtol=LEARNED_INNER_RTOL,
+        # the learned eigensolve at the common inner tolerance and at 3e-12:
+        # with some trained networks the first stalls above rho = 1e-10 (the
+        # corrections leave the inner solves' residual, although below the
+        # tolerance, where the wanted modes amplify it); the form's figures
+        # are those of the common tolerance when it converges, else of 3e-12
+        runs = {}
+        for rtol in (LEARNED_INNER_RTOL, 3e-12):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            o = op.eigs(K_EIG, sigma=SIGMA, tol=TOL, seed=SEED, solve_mode=dm.SOLVE_FGMRES_MG32_LEARNED,
+                        block=BLOCK, max_basis=MAX_BASIS, inner_rtol=rtol)
+            torch.cuda.synchronize()
+            runs[rtol] = (o, (time.perf_counter() - t1) / K_EIG)
+        use = LEARNED_INNER_RTOL if runs[LEARNED_INNER_RTOL][0]["status"] == 0 else 3e-12
+        ol, spp = runs[use]
+        forms["learned"] = dict(s_per_eigenpair=spp, status=ol["status"], lam=ol["lam"].tolist(), inner_rtol=use,
                                 max_residual=ol["max_residual"],
                                 inner_iterations=ol["inner_iterations"],
                                 outer_iterations=ol["outer_iterations"],
+                                by_inner_rtol={f"{r:g}": {"status": o["status"], "s_per_eigenpair": t,
+                                                          "outer_iterations": o["outer_iterations"],
+                                                          "inner_iterations": o["inner_iterations"],
+                                                          "restarts": o["restarts"], "max_residual": o["max_residual"]}
+                                               for r, (o, t) in runs.items()},
                                 training={"pairs": hist["pairs"], "seconds": round(hist["train_s"], 2),
                                           "cavities": f"{LEARNED_CAVITIES} ellipsoids at 64^3, sigma=36",
                                           "loss_per_round": [round(x, 4) for x in hist["loss_per_round"]]})
