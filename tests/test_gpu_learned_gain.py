@@ -10,7 +10,7 @@ corrections are kept by the residual judge, and the learned mode needs
 fewer inner iterations.  Recorded beside them: the wall time of both
 eigensolves.  The learned form loses there: each correction costs three
 convolution launches and two FP64 residuals, more than the V-cycles it
-saves (measured 0.47 against 0.23 s per pair for 14% fewer inner
+saves (measured 1.31 against 0.91 s for the 4 pairs with 14% fewer inner
 iterations), so the wall-time ratio is printed, not asserted.
 """
 import numpy as np
