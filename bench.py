@@ -46,6 +46,13 @@ C3_BLOCK = 2
 # iterations per inversion there, so orthogonalisation dominated)
 C3_NU = 4
 C3_RESTART = 30
+# ... with the FGMRES basis stored in FP32 (operator option
+# krylov_basis_f32): about 56 inner iterations per inversion, so every solve
+# restarts anyway and the Gram--Schmidt passes read half the bytes: 0.742 ->
+# 0.674 s/pair with the same inner iterations (1681).  On the 128^3 sphere
+# (16 per inversion, one cycle) it costs restarts: 1009 -> 1335 inner
+# iterations, 0.122 -> 0.139 s/pair, so the headline keeps the FP64 basis.
+C3_BASIS_F32 = 1
 # The learned form's inner solves stop at the same 1e-11 as the other forms.
 # (At 3e-12, below what the FP32 V-cycle lets FGMRES reach cheaply at this
 # indefinite shift, both the plain and the learned form need about 10x the
@@ -207,7 +214,7 @@ def c3_operator(dm):
     geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
                            bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
     return dm.Operator(geom, (nxy, nxy, nz), 1.235 / nz, 632.0, levels=0, fgmres_restart=C3_RESTART,
-                       nu_pre=C3_NU, nu_post=C3_NU)
+                       nu_pre=C3_NU, nu_post=C3_NU, krylov_basis_f32=C3_BASIS_F32)
 
 
 def run_c3(dm, torch, copy_gbps):
@@ -236,7 +243,8 @@ def run_c3(dm, torch, copy_gbps):
         lay = op.layout(0)
         res = {"grid": [nxy, nxy, nz], "levels": lay["levels"], "active_faces": lay["active_faces"],
                "active_cells": lay["active_cells"], "setup_s": round(setup, 2), "roofline": roof,
-               "block": C3_BLOCK, "nu": C3_NU, "fgmres_restart": C3_RESTART, "status": out["status"],
+               "block": C3_BLOCK, "nu": C3_NU, "fgmres_restart": C3_RESTART, "krylov_basis_f32": C3_BASIS_F32,
+               "status": out["status"],
                "s_per_eigenpair": dt / 9, "lam": out["lam"].tolist(),
                "max_residual": out["max_residual"], "outer_iterations": out["outer_iterations"],
                "inner_iterations": out["inner_iterations"], "restarts": out["restarts"]}
@@ -253,7 +261,7 @@ def run_c3(dm, torch, copy_gbps):
         geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
                                bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
         with dm.Operator(geom, tuple(n), 1.235 / nzc, 632.0, levels=0, fgmres_restart=C3_RESTART,
-                         nu_pre=C3_NU, nu_post=C3_NU) as opc:
+                         nu_pre=C3_NU, nu_post=C3_NU, krylov_basis_f32=C3_BASIS_F32) as opc:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             o = opc.eigs(9, sigma=632.0, tol=TOL, seed=3, solve_mode=dm.SOLVE_FGMRES_MG32, block=C3_BLOCK,

@@ -150,6 +150,21 @@ typedef struct {
                             is unchanged by the scaling).  Single-vector
                             V-cycles only: the block entry points and dm_eigs
                             refuse it.  (0) */
+    int krylov_basis_f32; /* block FGMRES in the plain FP32-multigrid mode
+                            (DM_SOLVE_FGMRES_MG32, dm_solve_block and dm_eigs
+                            with block >= 2; even vector lengths): 1 keeps the
+                            Krylov basis in FP32.  Each new column is still
+                            formed and orthogonalised in FP64, then rounded
+                            for storage, and every sum widens the stored
+                            values, so only the storage is FP32: the
+                            Gram--Schmidt passes read half the bytes.  The
+                            Arnoldi relation then holds to FP32 rounding, so
+                            one cycle lowers the true residual by about 1e-7
+                            at most and a tighter tolerance takes restarts
+                            (which FGMRES checks with the FP64 residual):
+                            a gain for long, restarted solves, a loss where
+                            one cycle would reach the tolerance.  Other modes
+                            and single-vector solves ignore it.  (0) */
 } dm_options;
 
 /* Fills `opt` with the defaults listed above. */

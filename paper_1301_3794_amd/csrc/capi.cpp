@@ -150,6 +150,7 @@ void dm_default_options(dm_options *opt) {
     opt->learned_patience = 1;
     opt->grad_div_volume = 1;
     opt->tilde_transfers = 0;
+    opt->krylov_basis_f32 = 0;
 }
 
 void dm_default_eig_options(dm_eig_options *opt) {
@@ -233,8 +234,9 @@ int dm_build_operator(const dm_geometry *geom, const int dims[3], double h, doub
         if (op->opt.nu_pre < 0 || op->opt.nu_post < 0 || op->opt.fgmres_restart < 1 ||
             op->opt.fgmres_restart > kMaxDots - 2 || op->opt.cut_wave_split < 0 ||
             op->opt.learned_patience < 0 || (op->opt.grad_div_volume != 0 && op->opt.grad_div_volume != 1) ||
-            (op->opt.tilde_transfers != 0 && op->opt.tilde_transfers != 1))
-            return fail(DM_EINVAL, "bad smoothing, restart or wave-split option");
+            (op->opt.tilde_transfers != 0 && op->opt.tilde_transfers != 1) ||
+            (op->opt.krylov_basis_f32 != 0 && op->opt.krylov_basis_f32 != 1))
+            return fail(DM_EINVAL, "bad smoothing, restart, wave-split or variant option");
         const int div = 1 << (op->opt.levels - 1);
         for (int a = 0; a < 3; ++a)
             if (dims[a] % div != 0 || dims[a] / div < 1)

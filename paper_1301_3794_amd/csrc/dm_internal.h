@@ -490,6 +490,9 @@ void launch_copy(int64_t n, const double *x, double *y, hipStream_t s);
 constexpr int kReduceBlocks = 1024;
 void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
                  int64_t n, double *part, double *dout, hipStream_t s, Span sp = {});
+// the same with an FP32 basis (each value widened; FP64 sums)
+void launch_mdot(int nv, const float *V, int64_t ld, const double *w, const double *wt, int64_t n, double *part,
+                 double *dout, hipStream_t s, Span sp = {});
 constexpr int kMultiMax = 8;   // vectors per launch of the two kernels below
 // dout[i*nw + q] = V_i . (W_q * wt) for i < nv, q < nw (nw <= 8, nv*nw <= 256;
 // W_q = W + q*ldw); the basis is read once
@@ -503,6 +506,9 @@ void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, in
 // with cscale (device, nv values) the coefficients are c[i] * cscale[i]
 void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
                   int overwrite, hipStream_t s, const double *cscale = nullptr, Span sp = {});
+// the same with an FP32 basis (each value widened; FP64 arithmetic)
+void launch_maxpy(int nv, const float *V, int64_t ld, const double *c, double *y, int64_t n, int overwrite,
+                  hipStream_t s, const double *cscale = nullptr, Span sp = {});
 // y -= sum_i c[i] V_i for FP32 columns V_i (c on device; FP64 arithmetic)
 void launch_maxpy_f32(int nv, const float *V, int64_t ld, const double *c, double *y, int64_t n, hipStream_t s,
                       Span sp = {});
@@ -511,6 +517,10 @@ void launch_maxpy_f32(int nv, const float *V, int64_t ld, const double *c, doubl
 // pass over the basis for nv <= 32, two above
 void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
                             int64_t n, double *part, double *dout, hipStream_t s, const double *cscale = nullptr,
+                            Span sp = {});
+// the same with an FP32 basis (each value widened; FP64 arithmetic)
+void launch_maxpy_mdot_norm(int nv, const float *V, int64_t ld, const double *c, double *w, int64_t n,
+                            double *part, double *dout, hipStream_t s, const double *cscale = nullptr,
                             Span sp = {});
 // out = scale * (w - sum c_i V_i)
 void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,

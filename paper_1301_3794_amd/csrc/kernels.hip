@@ -914,6 +914,59 @@ struct Vec<2> {
     __device__ static T zero() { return make_double2(0.0, 0.0); }
 };
 
+// Four doubles (two 16-byte loads): the width at which an FP32 basis column
+// is read with 16-byte loads as well (VEC = 4 needs lengths and strides that
+// are multiples of 4 and 16-byte aligned pointers)
+struct D4 {
+    double2 a, b;
+};
+template <>
+struct Vec<4> {
+    using T = D4;
+    __device__ static T ld(const double *p, int64_t e) {
+        const double2 *q = reinterpret_cast<const double2 *>(p) + 2 * e;
+        return {q[0], q[1]};
+    }
+    __device__ static void st(double *p, int64_t e, T v) {
+        double2 *q = reinterpret_cast<double2 *>(p) + 2 * e;
+        q[0] = v.a;
+        q[1] = v.b;
+    }
+    __device__ static double dot(T a, T b) { return Vec<2>::dot(a.a, b.a) + Vec<2>::dot(a.b, b.b); }
+    __device__ static T fma(double c, T a, T b) { return {Vec<2>::fma(c, a.a, b.a), Vec<2>::fma(c, a.b, b.b)}; }
+    __device__ static T mul(T a, T b) { return {Vec<2>::mul(a.a, b.a), Vec<2>::mul(a.b, b.b)}; }
+    __device__ static T scale(double c, T a) { return {Vec<2>::scale(c, a.a), Vec<2>::scale(c, a.b)}; }
+    __device__ static T zero() { return {Vec<2>::zero(), Vec<2>::zero()}; }
+};
+
+// VEC consecutive entries of a Krylov basis column in FP64: FP64 columns
+// as they are, FP32 columns widened (the basis kept in FP32; every sum and
+// update is still FP64)
+template <int VEC, class TV>
+struct BasisLd;
+template <int VEC>
+struct BasisLd<VEC, double> {
+    __device__ static typename Vec<VEC>::T ld(const double *p, int64_t e) { return Vec<VEC>::ld(p, e); }
+};
+template <>
+struct BasisLd<1, float> {
+    __device__ static double ld(const float *p, int64_t e) { return (double)p[e]; }
+};
+template <>
+struct BasisLd<2, float> {
+    __device__ static double2 ld(const float *p, int64_t e) {
+        const float2 v = reinterpret_cast<const float2 *>(p)[e];
+        return make_double2((double)v.x, (double)v.y);
+    }
+};
+template <>
+struct BasisLd<4, float> {
+    __device__ static D4 ld(const float *p, int64_t e) {
+        const float4 v = reinterpret_cast<const float4 *>(p)[e];
+        return {make_double2((double)v.x, (double)v.y), make_double2((double)v.z, (double)v.w)};
+    }
+};
+
 // Index i of a grid-stride loop -> element (in VEC units) of the listed
 // units; the whole vector without a list.  Elements past nvec (a partial
 // last unit) are skipped by the caller.
@@ -928,9 +981,9 @@ __device__ __forceinline__ int64_t span_elem(const Span &sp, int64_t i) {
 }
 
 // part[i][block] = partial sums of V_i . (w * wt) over the block's elements
-template <int VEC>
+template <int VEC, class TV = double>
 __global__ void __launch_bounds__(kThreads)
-k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
+k_mdot(int nv, const TV *__restrict__ V, int64_t ld, const double *__restrict__ w,
        const double *__restrict__ wt, int64_t n, double *__restrict__ part, Span sp) {
     using O = Vec<VEC>;
     const int64_t nvec = n / VEC, ldv = ld / VEC, cnt = span_count<VEC>(sp, nvec);
@@ -947,7 +1000,7 @@ k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restric
             if (wt) wv = O::mul(wv, O::ld(wt, e));
 #pragma unroll
             for (int q = 0; q < kChunk; ++q)
-                if (q < cn) acc[q] += O::dot(O::ld(V + (int64_t)(c0 + q) * ldv * VEC, e), wv);
+                if (q < cn) acc[q] += O::dot(BasisLd<VEC, TV>::ld(V + (int64_t)(c0 + q) * ldv * VEC, e), wv);
         }
         if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
             const double wv = w[n - 1] * (wt ? wt[n - 1] : 1.0);
@@ -974,9 +1027,9 @@ k_mdot(int nv, const double *__restrict__ V, int64_t ld, const double *__restric
 }
 
 // part rows 0..nv-1: V_i . w; row nv: |w|^2  (chunks of kChunk vectors)
-template <int VEC>
+template <int VEC, class TV = double>
 __global__ void __launch_bounds__(kThreads)
-k_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ w,
+k_mdot_norm(int nv, const TV *__restrict__ V, int64_t ld, const double *__restrict__ w,
             int64_t n, double *__restrict__ part, Span sp) {
     using O = Vec<VEC>;
     const int64_t nvec = n / VEC, ldv = ld / VEC, cnt = span_count<VEC>(sp, nvec);
@@ -995,7 +1048,7 @@ k_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__re
             const typename O::T wv = O::ld(w, e);
 #pragma unroll
             for (int q = 0; q < kChunk; ++q)
-                if (q < cn) acc[q] += O::dot(O::ld(V + (int64_t)(c0 + q) * ldv * VEC, e), wv);
+                if (q < cn) acc[q] += O::dot(BasisLd<VEC, TV>::ld(V + (int64_t)(c0 + q) * ldv * VEC, e), wv);
             if (last) acc[kChunk] += O::dot(wv, wv);
         }
         if (VEC == 2 && (n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1259,9 +1312,9 @@ k_maxpy_multi(int nv, const double *__restrict__ V, int64_t ld, const double *__
 
 // y = sum_i c_i V_i (overwrite) or y -= sum_i c_i V_i; w: optional input
 // (out = scale * (w - sum c_i V_i) when w != nullptr)
-template <int VEC>
+template <int VEC, class TV = double>
 __global__ void __launch_bounds__(kThreads)
-k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
+k_maxpy(int nv, const TV *__restrict__ V, int64_t ld, const double *__restrict__ c,
         const double *__restrict__ cscale, const double *w, double scale, double *y, int64_t n, int overwrite,
         Span sp) {
     using O = Vec<VEC>;
@@ -1274,7 +1327,7 @@ k_maxpy(int nv, const double *__restrict__ V, int64_t ld, const double *__restri
         const int64_t e = span_elem<VEC>(sp, it);
         if (e >= nvec) continue;
         typename O::T s = O::zero();
-        for (int q = 0; q < nv; ++q) s = O::fma(cs[q], O::ld(V + (int64_t)q * ldv * VEC, e), s);
+        for (int q = 0; q < nv; ++q) s = O::fma(cs[q], BasisLd<VEC, TV>::ld(V + (int64_t)q * ldv * VEC, e), s);
         typename O::T r;
         if (w) r = O::scale(scale, O::fma(-1.0, s, O::ld(w, e)));
         else if (overwrite) r = s;
@@ -1328,9 +1381,9 @@ constexpr int kFuseMax = 32;
 // vectors holding them took 212 VGPRs (2 waves per SIMD) and rereading 149
 // (3 waves), 3% faster on the 9-cell quarter; for 16 vectors holding them
 // (144 VGPRs) stays faster than rereading (85).
-template <int VEC, int MAXV, bool REREAD>
+template <int VEC, int MAXV, bool REREAD, class TV = double>
 __global__ void __launch_bounds__(kThreads)
-k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double *__restrict__ c,
+k_maxpy_mdot_norm(int nv, const TV *__restrict__ V, int64_t ld, const double *__restrict__ c,
                   const double *__restrict__ cscale, double *__restrict__ w, int64_t n, double *__restrict__ part,
                   Span sp) {
     using O = Vec<VEC>;
@@ -1349,20 +1402,20 @@ k_maxpy_mdot_norm(int nv, const double *__restrict__ V, int64_t ld, const double
         if (REREAD) {
 #pragma unroll
             for (int q = 0; q < MAXV; ++q)
-                if (q < nv) s = O::fma(-cs[q], O::ld(V + (int64_t)q * ldv * VEC, e), s);
+                if (q < nv) s = O::fma(-cs[q], BasisLd<VEC, TV>::ld(V + (int64_t)q * ldv * VEC, e), s);
             O::st(w, e, s);
             // keep the compiler from holding the first loads in registers
             // for the second use (that costs 200+ VGPRs, 2 waves per SIMD)
             asm volatile("" ::: "memory");
 #pragma unroll
             for (int q = 0; q < MAXV; ++q)
-                if (q < nv) acc[q] += O::dot(O::ld(V + (int64_t)q * ldv * VEC, e), s);
+                if (q < nv) acc[q] += O::dot(BasisLd<VEC, TV>::ld(V + (int64_t)q * ldv * VEC, e), s);
         } else {
             typename O::T vv[REREAD ? 1 : MAXV];
 #pragma unroll
             for (int q = 0; q < MAXV; ++q)
                 if (q < nv) {
-                    vv[q] = O::ld(V + (int64_t)q * ldv * VEC, e);
+                    vv[q] = BasisLd<VEC, TV>::ld(V + (int64_t)q * ldv * VEC, e);
                     s = O::fma(-cs[q], vv[q], s);
                 }
             O::st(w, e, s);
@@ -1966,18 +2019,50 @@ inline bool vec2_ok(int64_t n, int64_t ld, std::initializer_list<const void *> p
         if (p && ((uintptr_t)p & 15)) return false;
     return true;
 }
+// the same for a Krylov basis of element type TV with the FP64 vectors in
+// `ptrs`: FP32 columns are read as pairs of floats (8-byte aligned)
+template <class TV>
+inline bool vec2_basis_ok(int64_t n, int64_t ld, const TV *V, std::initializer_list<const void *> ptrs) {
+    if (sizeof(TV) == 8) return vec2_ok(n, ld, {V}) && vec2_ok(n, ld, ptrs);
+    return ((uintptr_t)V & 7) == 0 && vec2_ok(n, ld, ptrs);
+}
+// an FP32 basis read four floats at a time: lengths and strides multiples
+// of 4, every pointer 16-byte aligned
+template <class TV>
+inline bool vec4_basis_ok(int64_t n, int64_t ld, const TV *V, std::initializer_list<const void *> ptrs) {
+    if (sizeof(TV) == 8 || (n & 3) || (ld & 3) || ((uintptr_t)V & 15)) return false;
+    for (const void *p : ptrs)
+        if (p && ((uintptr_t)p & 15)) return false;
+    return true;
+}
+
+template <class TV>
+void launch_mdot_t(int nv, const TV *V, int64_t ld, const double *w, const double *wt, int64_t n, double *part,
+                   double *dout, hipStream_t s, Span sp) {
+    if (nv <= 0) return;
+    if (nv > 256) throw std::runtime_error("launch_mdot: more than 256 vectors");
+    bool done = false;
+    if constexpr (sizeof(TV) == 4)
+        if ((done = vec4_basis_ok(n, ld, V, {w, wt})))
+            hipLaunchKernelGGL((k_mdot<4, TV>), dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part,
+                               sp);
+    if (done) {
+    } else if (vec2_basis_ok(n, ld, V, {w, wt}))
+        hipLaunchKernelGGL((k_mdot<2, TV>), dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
+    else
+        hipLaunchKernelGGL((k_mdot<1, TV>), dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
+    hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kThreads), 0, s, (int)kReduceBlocks,
+                       (const double *)part, dout);
+}
 }  // namespace
 
 void launch_mdot(int nv, const double *V, int64_t ld, const double *w, const double *wt,
                  int64_t n, double *part, double *dout, hipStream_t s, Span sp) {
-    if (nv <= 0) return;
-    if (nv > 256) throw std::runtime_error("launch_mdot: more than 256 vectors");
-    if (vec2_ok(n, ld, {V, w, wt}))
-        hipLaunchKernelGGL(k_mdot<2>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
-    else
-        hipLaunchKernelGGL(k_mdot<1>, dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
-    hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kThreads), 0, s, (int)kReduceBlocks,
-                       (const double *)part, dout);
+    launch_mdot_t<double>(nv, V, ld, w, wt, n, part, dout, s, sp);
+}
+void launch_mdot(int nv, const float *V, int64_t ld, const double *w, const double *wt, int64_t n, double *part,
+                 double *dout, hipStream_t s, Span sp) {
+    launch_mdot_t<float>(nv, V, ld, w, wt, n, part, dout, s, sp);
 }
 
 #define DM_NW_SWITCH(nw, CALL)                                   \
@@ -2020,17 +2105,35 @@ void launch_maxpy_multi(int nv, const double *V, int64_t ld, const double *C, in
 
 #undef DM_NW_SWITCH
 
-void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
-                  int overwrite, hipStream_t s, const double *cscale, Span sp) {
+namespace {
+template <class TV>
+void launch_maxpy_t(int nv, const TV *V, int64_t ld, const double *c, double *y, int64_t n, int overwrite,
+                    hipStream_t s, const double *cscale, Span sp) {
     if (nv <= 0 && !overwrite) return;
     if (nv > 256) throw std::runtime_error("launch_maxpy: more than 256 vectors");
     const int64_t cnt = sp.u ? sp.n * kSpanUnit : n;
-    if (vec2_ok(n, ld, {V, y}))
-        hipLaunchKernelGGL(k_maxpy<2>, flat_grid(cnt / 2), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
+    bool done = false;
+    if constexpr (sizeof(TV) == 4)
+        if ((done = vec4_basis_ok(n, ld, V, {y})))
+            hipLaunchKernelGGL((k_maxpy<4, TV>), flat_grid(cnt / 4), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
+                               (const double *)nullptr, 1.0, y, n, overwrite, sp);
+    if (done) {
+    } else if (vec2_basis_ok(n, ld, V, {y}))
+        hipLaunchKernelGGL((k_maxpy<2, TV>), flat_grid(cnt / 2), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
                            (const double *)nullptr, 1.0, y, n, overwrite, sp);
     else
-        hipLaunchKernelGGL(k_maxpy<1>, flat_grid(cnt), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
+        hipLaunchKernelGGL((k_maxpy<1, TV>), flat_grid(cnt), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
                            (const double *)nullptr, 1.0, y, n, overwrite, sp);
+}
+}  // namespace
+
+void launch_maxpy(int nv, const double *V, int64_t ld, const double *c, double *y, int64_t n,
+                  int overwrite, hipStream_t s, const double *cscale, Span sp) {
+    launch_maxpy_t<double>(nv, V, ld, c, y, n, overwrite, s, cscale, sp);
+}
+void launch_maxpy(int nv, const float *V, int64_t ld, const double *c, double *y, int64_t n, int overwrite,
+                  hipStream_t s, const double *cscale, Span sp) {
+    launch_maxpy_t<float>(nv, V, ld, c, y, n, overwrite, s, cscale, sp);
 }
 
 void launch_maxpy_f32(int nv, const float *V, int64_t ld, const double *c, double *y, int64_t n, hipStream_t s,
@@ -2062,11 +2165,12 @@ int reduce_blocks() {
     return nb;
 }
 
-void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
-                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale,
-                            Span sp) {
+namespace {
+template <class TV>
+void launch_maxpy_mdot_norm_t(int nv, const TV *V, int64_t ld, const double *c, double *w, int64_t n,
+                              double *part, double *dout, hipStream_t s, const double *cscale, Span sp) {
     if (nv < 1 || nv + 1 > 256) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
-    const bool v2 = vec2_ok(n, ld, {V, w});
+    const bool v2 = vec2_basis_ok(n, ld, V, {w});
     const dim3 b(kThreads);
     int nb = kReduceBlocks;
     // one fused kernel for nv <= 32 (the basis held in registers)
@@ -2074,24 +2178,44 @@ void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c
         nb = blocks;
         hipLaunchKernelGGL(kern, dim3(nb), b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
     };
-    if (nv <= 8) {
-        if (v2) fused(k_maxpy_mdot_norm<2, 8, false>, reduce_blocks<k_maxpy_mdot_norm<2, 8, false>>());
-        else fused(k_maxpy_mdot_norm<1, 8, false>, reduce_blocks<k_maxpy_mdot_norm<1, 8, false>>());
+    bool done = false;
+    if constexpr (sizeof(TV) == 4)
+        if ((done = nv <= 32 && vec4_basis_ok(n, ld, V, {w}))) {
+            if (nv <= 8) fused(k_maxpy_mdot_norm<4, 8, false, TV>, reduce_blocks<k_maxpy_mdot_norm<4, 8, false, TV>>());
+            else if (nv <= 16)
+                fused(k_maxpy_mdot_norm<4, 16, false, TV>, reduce_blocks<k_maxpy_mdot_norm<4, 16, false, TV>>());
+            else fused(k_maxpy_mdot_norm<4, 32, true, TV>, reduce_blocks<k_maxpy_mdot_norm<4, 32, true, TV>>());
+        }
+    if (done) {
+    } else if (nv <= 8) {
+        if (v2) fused(k_maxpy_mdot_norm<2, 8, false, TV>, reduce_blocks<k_maxpy_mdot_norm<2, 8, false, TV>>());
+        else fused(k_maxpy_mdot_norm<1, 8, false, TV>, reduce_blocks<k_maxpy_mdot_norm<1, 8, false, TV>>());
     } else if (nv <= 16) {
-        if (v2) fused(k_maxpy_mdot_norm<2, 16, false>, reduce_blocks<k_maxpy_mdot_norm<2, 16, false>>());
-        else fused(k_maxpy_mdot_norm<1, 16, false>, reduce_blocks<k_maxpy_mdot_norm<1, 16, false>>());
+        if (v2) fused(k_maxpy_mdot_norm<2, 16, false, TV>, reduce_blocks<k_maxpy_mdot_norm<2, 16, false, TV>>());
+        else fused(k_maxpy_mdot_norm<1, 16, false, TV>, reduce_blocks<k_maxpy_mdot_norm<1, 16, false, TV>>());
     } else if (nv <= 32) {
-        if (v2) fused(k_maxpy_mdot_norm<2, 32, true>, reduce_blocks<k_maxpy_mdot_norm<2, 32, true>>());
-        else fused(k_maxpy_mdot_norm<1, 32, true>, reduce_blocks<k_maxpy_mdot_norm<1, 32, true>>());
+        if (v2) fused(k_maxpy_mdot_norm<2, 32, true, TV>, reduce_blocks<k_maxpy_mdot_norm<2, 32, true, TV>>());
+        else fused(k_maxpy_mdot_norm<1, 32, true, TV>, reduce_blocks<k_maxpy_mdot_norm<1, 32, true, TV>>());
     } else {
         // too many vectors to hold in registers: update w, then a second
         // pass for the dots (the basis is read twice)
-        launch_maxpy(nv, V, ld, c, w, n, 0, s, cscale, sp);
+        launch_maxpy_t<TV>(nv, V, ld, c, w, n, 0, s, cscale, sp);
         const dim3 g(kReduceBlocks);
-        if (v2) hipLaunchKernelGGL((k_mdot_norm<2>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
-        else hipLaunchKernelGGL((k_mdot_norm<1>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
+        if (v2) hipLaunchKernelGGL((k_mdot_norm<2, TV>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
+        else hipLaunchKernelGGL((k_mdot_norm<1, TV>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
     }
     hipLaunchKernelGGL(k_mdot_final, dim3(nv + 1), dim3(kThreads), 0, s, nb, (const double *)part, dout);
+}
+}  // namespace
+
+void launch_maxpy_mdot_norm(int nv, const double *V, int64_t ld, const double *c, double *w,
+                            int64_t n, double *part, double *dout, hipStream_t s, const double *cscale,
+                            Span sp) {
+    launch_maxpy_mdot_norm_t<double>(nv, V, ld, c, w, n, part, dout, s, cscale, sp);
+}
+void launch_maxpy_mdot_norm(int nv, const float *V, int64_t ld, const double *c, double *w, int64_t n,
+                            double *part, double *dout, hipStream_t s, const double *cscale, Span sp) {
+    launch_maxpy_mdot_norm_t<float>(nv, V, ld, c, w, n, part, dout, s, cscale, sp);
 }
 
 void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, const double *w,

@@ -165,6 +165,10 @@ struct dm_op {
     int bk_m = 0;
     double *bk_V = nullptr, *bk_Z = nullptr;
     float *bk_Z32 = nullptr;   // FP32 preconditioned columns (plain FP32-multigrid mode)
+    // FP32 basis (option krylov_basis_f32; same layout as bk_V) and the FP64
+    // column of each system in which a new basis column is formed
+    float *bk_V32 = nullptr;
+    double *bk_W = nullptr;
     double *bk_dres = nullptr, *bk_dcoef = nullptr, *bk_hres = nullptr;
     double *bk_dres2 = nullptr, *bk_hres2 = nullptr, *bk_sc2 = nullptr;   // as dres2, hres2, sc2d
     hipGraphExec_t g_vb32[dm::kMaxRhs + 1] = {}, g_vb64[dm::kMaxRhs + 1] = {};

@@ -147,6 +147,11 @@ void demean_cells(dm_op *op, double *x, hipStream_t s) {
 // holds with the first-pass coefficients and the basis keeps orthogonality
 // to 1e-10.  Convergence is always confirmed by the true residual.
 constexpr double kReorth = 1e-10;
+// The same threshold for a basis stored in FP32 (krylov_basis_f32): its
+// columns are orthogonal only to FP32 rounding, so the second pass's
+// projection sits near 1e-7 of the first one's whatever is done, and a
+// third pass (which cannot lower it) is taken only well above that level.
+constexpr double kReorthF32 = 1e-5;
 
 int fgmres(dm_op *op, int mode, const double *f, double *x, double rtol, int maxit,
            dm_solve_info *info, hipStream_t s) {
@@ -607,12 +612,7 @@ void ensure_block_results(dm_op *op) {
 }
 
 void ensure_block(dm_op *op, int prec) {
-    const int64_t n = op->n0();
-    if (!op->bk_V) {
-        const int m = op->opt.fgmres_restart;
-        op->bk_m = m;
-        op->bk_V = op->dalloc<double>((size_t)(m + 1) * kMaxRhs * n);
-    }
+    op->bk_m = op->opt.fgmres_restart;   // the bases are allocated by the block FGMRES, in its precision
     ensure_block_results(op);
     for (Level &L : op->lv) {
         const size_t cnt = (size_t)kMaxRhs * 3 * L.g.P;
@@ -915,12 +915,14 @@ void precondition_block(dm_op *op, int mode, int nr, const double *const *v, dou
 // The plain FP32-multigrid preconditioner with FP32 answers: the V-cycle's
 // output is FP32 already, so the Z columns keep it as it is (half the bytes
 // of the widened copy).  The products M z and the update of x read them
-// widened to FP64, so every value equals that of the FP64 columns.
-void precondition_block_f32(dm_op *op, int nr, const double *const *v, float *const *z, hipStream_t s) {
+// widened to FP64, so every value equals that of the FP64 columns.  The
+// inputs are FP64 basis columns, or FP32 ones (krylov_basis_f32).
+template <class TV>
+void precondition_block_f32(dm_op *op, int nr, const TV *const *v, float *const *z, hipStream_t s) {
     const int64_t n = op->n0();
     ensure_block(op, 32);
     const Span sp = op->vspan();
-    for (int q = 0; q < nr; ++q) launch_cast<double, float>(v[q], op->lv[0].bf32 + q * n, n, s, sp);
+    for (int q = 0; q < nr; ++q) launch_cast<TV, float>(v[q], op->lv[0].bf32 + q * n, n, s, sp);
     vcycle_block_graphed(op, 32, nr, s);
     for (int q = 0; q < nr; ++q) launch_cast<float, float>(op->lv[0].bx32 + q * n, z[q], n, s, sp);
 }
@@ -947,6 +949,19 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
     // FP32 Z columns in the plain FP32-multigrid mode (even lengths: pairs of
     // floats per load), FP64 ones otherwise
     const bool z32 = mode == DM_SOLVE_FGMRES_MG32 && n % 2 == 0;
+    // FP32 basis (krylov_basis_f32): each new column is formed and
+    // orthogonalised in the system's FP64 column W_r, then rounded into the
+    // FP32 basis; every dot product and update widens the stored values
+    const bool b32 = z32 && op->opt.krylov_basis_f32 != 0;
+    if (b32) {
+        if (!op->bk_V32) op->bk_V32 = op->dalloc<float>((size_t)(m + 1) * kMaxRhs * n);
+        if (!op->bk_W) op->bk_W = op->dalloc<double>((size_t)kMaxRhs * n);
+    } else if (!op->bk_V) {
+        op->bk_V = op->dalloc<double>((size_t)(m + 1) * kMaxRhs * n);
+    }
+    auto Vc32 = [&](int r, int j) { return op->bk_V32 + (int64_t)j * ld + (int64_t)r * n; };
+    // the FP64 column in which column j of system r is formed
+    auto Fc = [&](int r, int j) { return b32 ? op->bk_W + (int64_t)r * n : Vc(r, j); };
     if (z32 && !op->bk_Z32) op->bk_Z32 = op->dalloc<float>((size_t)m * kMaxRhs * n);
     if (!z32 && !op->bk_Z) op->bk_Z = op->dalloc<double>((size_t)m * kMaxRhs * n);
     auto Zc = [&](int r, int j) { return op->bk_Z + (int64_t)j * ld + (int64_t)r * n; };
@@ -1003,16 +1018,19 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             int nres = 0;
             for (int r : act) {
                 if (st[r].total == 0) {
-                    launch_copy(n, st[r].f, Vc(r, 0), s);
+                    launch_copy(n, st[r].f, Fc(r, 0), s);
                 } else {
                     bf.p[nres] = st[r].f;
                     bx.p[nres] = st[r].x;
-                    by.p[nres] = Vc(r, 0);
+                    by.p[nres] = Fc(r, 0);
                     ++nres;
                 }
             }
             if (nres) launch_apply_b<double>(L.g, L.coef64, op->sigma, AK_RESID, nres, bf, bx, by, s, L.cut_cells());
-            for (int r : act) launch_mdot(1, Vc(r, 0), 0, Vc(r, 0), nullptr, n, op->part, dres(r), s, sp);
+            for (int r : act) {
+                launch_mdot(1, Fc(r, 0), 0, Fc(r, 0), nullptr, n, op->part, dres(r), s, sp);
+                if (b32) launch_cast<double, float>(Fc(r, 0), Vc32(r, 0), n, s, sp);
+            }
             fetch();
             for (int r : act) {
                 BlockRhs &R = st[r];
@@ -1047,10 +1065,12 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         VPtr<const float> zc32{};
         VPtr<double> wv{};
         float *zout32[kMaxRhs];
+        const float *vin32[kMaxRhs];
         int *rej[kMaxRhs];
         for (int q = 0; q < na; ++q) {
             const int r = act[q];
-            vin[q] = Vc(r, st[r].j);
+            if (b32) vin32[q] = Vc32(r, st[r].j);
+            else vin[q] = Vc(r, st[r].j);
             rej[q] = &st[r].learned_rejections;
             if (z32) {
                 zout32[q] = Zc32(r, st[r].j);
@@ -1059,13 +1079,14 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                 zout[q] = Zc(r, st[r].j);
                 zc.p[q] = zout[q];
             }
-            wv.p[q] = Vc(r, st[r].j + 1);          // w = M Z_j in the next column's slot
+            wv.p[q] = Fc(r, st[r].j + 1);          // w = M Z_j in the next column's slot
         }
         // w = M z on the rows holding an active face: the slots of columns
         // 1..m are zero on the others (written only here and, within the
         // listed units, by the Gram--Schmidt updates of zero entries)
         if (z32) {
-            precondition_block_f32(op, na, vin, zout32, s);
+            if (b32) precondition_block_f32<float>(op, na, vin32, zout32, s);
+            else precondition_block_f32<double>(op, na, vin, zout32, s);
             launch_apply_m_f32in(L.g, L.coef64, op->sigma, na, zc32, wv, s, L.cut_cells_rows());
         } else {
             precondition_block(op, mode, na, vin, zout, s, rej);
@@ -1076,9 +1097,15 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         // fused with d2 = U^T w and |w|^2, every open system, one sync
         for (int r : act) {
             const int j = st[r].j;
-            launch_mdot(j + 1, Vc(r, 0), ld, Vc(r, j + 1), nullptr, n, op->part, dres(r), s, sp);
-            launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dres(r), Vc(r, j + 1), n, op->part, dres2(r), s, dsc2(r),
-                                   sp);
+            if (b32) {
+                launch_mdot(j + 1, Vc32(r, 0), ld, Fc(r, j + 1), nullptr, n, op->part, dres(r), s, sp);
+                launch_maxpy_mdot_norm(j + 1, Vc32(r, 0), ld, dres(r), Fc(r, j + 1), n, op->part, dres2(r), s,
+                                       dsc2(r), sp);
+            } else {
+                launch_mdot(j + 1, Vc(r, 0), ld, Vc(r, j + 1), nullptr, n, op->part, dres(r), s, sp);
+                launch_maxpy_mdot_norm(j + 1, Vc(r, 0), ld, dres(r), Vc(r, j + 1), n, op->part, dres2(r), s,
+                                       dsc2(r), sp);
+            }
         }
         DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nb * kMaxDots * sizeof(double), hipMemcpyDeviceToHost,
                               s));
@@ -1089,7 +1116,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         for (int r : act) {
             BlockRhs &R = st[r];
             int j = R.j;
-            double *w = Vc(r, j + 1);
+            double *w = Fc(r, j + 1);
             for (int i = 0; i <= j; ++i) R.h[i] = R.sc[i] * R.sc[j] * hres(r)[i];   // true coefficients
             const double wn2 = hres2(r)[j + 1] * R.sc[j] * R.sc[j];
             double c2 = 0.0;
@@ -1098,13 +1125,15 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                 c2 += R.h2[i] * R.h2[i];
             }
             double hn;
-            if (c2 > kReorth * kReorth * wn2) {
+            const double reorth = b32 ? kReorthF32 : kReorth;
+            if (c2 > reorth * reorth * wn2) {
                 for (int i = 0; i <= j; ++i) {
                     R.c3[i] = R.sc[i] * R.sc[i] * hres2(r)[i];
                     R.h[i] += R.h2[i];
                 }
                 DM_HIP(hipMemcpyAsync(dcoef(r), R.c3.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, s));
-                launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), w, n, 0, s, nullptr, sp);
+                if (b32) launch_maxpy(j + 1, Vc32(r, 0), ld, dcoef(r), w, n, 0, s, nullptr, sp);
+                else launch_maxpy(j + 1, Vc(r, 0), ld, dcoef(r), w, n, 0, s, nullptr, sp);
                 hn = std::sqrt(std::max(wn2 - c2, 0.0));
             } else {
                 hn = std::sqrt(wn2);
@@ -1132,7 +1161,10 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             ++R.total;
             R.j = ++j;
             const bool close = std::fabs(R.g[j]) <= rtol * R.bnorm || R.total >= maxit || hn == 0.0 || j == m;
-            if (!close) continue;
+            if (!close) {
+                if (b32) launch_cast<double, float>(Fc(r, j), Vc32(r, j), n, s, sp);   // store the new column
+                continue;
+            }
             // end of the cycle: x += Z y, y from the triangular system
             for (int i = j - 1; i >= 0; --i) {
                 double t = R.g[i];

@@ -70,7 +70,8 @@ class Options(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("fgmres_restart", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("cut_wave_split", ctypes.c_int), ("learned_patience", ctypes.c_int),
-                ("grad_div_volume", ctypes.c_int), ("tilde_transfers", ctypes.c_int)]
+                ("grad_div_volume", ctypes.c_int), ("tilde_transfers", ctypes.c_int),
+                ("krylov_basis_f32", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -280,7 +281,7 @@ class Operator:
 
     def __init__(self, geom: Geometry, dims, h, sigma, levels=0, nu_pre=2, nu_post=2,
                  fgmres_restart=30, verbose=0, cut_wave_split=None, learned_patience=None,
-                 grad_div_volume=None, tilde_transfers=None):
+                 grad_div_volume=None, tilde_transfers=None, krylov_basis_f32=None):
         L = lib()
         opt = Options()
         L.dm_default_options(ctypes.byref(opt))
@@ -294,6 +295,8 @@ class Operator:
             opt.grad_div_volume = int(grad_div_volume)
         if tilde_transfers is not None:
             opt.tilde_transfers = int(tilde_transfers)
+        if krylov_basis_f32 is not None:
+            opt.krylov_basis_f32 = int(krylov_basis_f32)
         self._op = ctypes.c_void_p()
         self._net = None
         self.dims = tuple(int(x) for x in dims)

@@ -18,6 +18,10 @@ coefficient once for all vectors.  Checked through the C ABI:
   * the eigensolver (which takes the block path for block size 4) still
     matches the oracle's eigenvalues to 1e-10;
   * restarts of FGMRES(4) inside the lockstep, as dm_solve takes them;
+  * the FP32 Krylov basis (operator option krylov_basis_f32, FP32 FGMRES
+    mode): each system against the sparse direct solve (1e-9) with its true
+    residual within the tolerance, under FGMRES(30) and FGMRES(4), and the
+    eigensolver's eigenvalues against the oracle (1e-10);
   * both forms of the block smoother's cut-row part (one wavefront per
     vector, and one thread per row looping over the vectors, which the
     full-size grids take) against the oracle's V-cycle, by forcing the loop
@@ -168,6 +172,45 @@ def test_solve_block_restarts(case):
         r = fs[q][oop.act] - oop.M_a @ lay.faces_from_padded(xs[q].cpu().numpy(), n)[oop.act]
         assert np.linalg.norm(r) <= 2e-13 * np.linalg.norm(fs[q][oop.act])
     op.close()
+
+
+@pytest.mark.parametrize("restart", [30, 4])
+def test_solve_block_fp32_basis(case, restart):
+    """The basis stored in FP32: the Arnoldi relation holds to FP32 rounding,
+    so the solves restart more, but FGMRES confirms each convergence with the
+    FP64 residual: every answer still meets the tolerance."""
+    dm, oop, n = case["dm"], case["oop"], case["n"]
+    op = dm.Operator(dm.user_fractions(lay.fractions_to_padded(case["fr"], n)), n, case["h"], case["sigma"],
+                     levels=case["levels"], fgmres_restart=restart, krylov_basis_f32=1)
+    fs = [rnd(oop.act, oop.grid.n_faces, 60 + q) for q in range(4)]
+    fs[1] = np.zeros_like(fs[1])
+    fd = [dev(lay.faces_to_padded(f, n)) for f in fs]
+    xs = [op.face_tensor() for _ in range(4)]
+    infos = op.solve_block(fd, xs, mode=dm.SOLVE_FGMRES_MG32, rtol=1e-11, maxit=600)
+    lu = sla.splu(oop.M_a.tocsc())
+    for q in range(4):
+        assert infos[q]["status"] == 0, infos[q]
+        got = lay.faces_from_padded(xs[q].cpu().numpy(), n)
+        if q == 1:
+            assert infos[q]["iterations"] == 0 and np.all(got == 0)
+            continue
+        ref = np.zeros_like(fs[q])
+        ref[oop.act] = lu.solve(fs[q][oop.act])
+        assert rel_inf(got, ref) <= 1e-9, q
+        r = fs[q][oop.act] - oop.M_a @ got[oop.act]
+        assert np.linalg.norm(r) <= 1.5e-11 * np.linalg.norm(fs[q][oop.act]), q
+    op.close()
+
+
+def test_block_eigs_fp32_basis(case):
+    dm, oop, n = case["dm"], case["oop"], case["n"]
+    op = dm.Operator(dm.user_fractions(lay.fractions_to_padded(case["fr"], n)), n, case["h"], case["sigma"],
+                     levels=case["levels"], krylov_basis_f32=1)
+    out = op.eigs(4, tol=1e-10, seed=7, block=4, solve_mode=dm.SOLVE_FGMRES_MG32)
+    op.close()
+    assert out["status"] == 0, out
+    lam_ref = oeigs.lanczos_eigs(oop, 4, sigma_o=case["sigma"], block=4, tol=1e-11)[0]
+    assert np.max(abs(out["lam"] - lam_ref) / lam_ref) <= 1e-10
 
 
 @pytest.mark.parametrize("mode", ["fgmres64", "fgmres32"])

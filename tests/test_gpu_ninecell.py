@@ -10,6 +10,8 @@ eigenvalues; the library computes its own fractions and runs the workload's
 eigensolver settings (shift 632, block 2, basis 48, FGMRES(30), 4 + 4
 sweeps).  Bars: 1e-10 relative for the FP64 form, 1e-9 for the
 FP32-multigrid form (the spec bars), and every returned rho <= 1e-10.
+The FP32-multigrid form is also run with its Krylov basis stored in FP32
+(operator option krylov_basis_f32), to the same bar.
 """
 import json
 import os
@@ -30,7 +32,8 @@ def golden(nz):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("nz,mode", [(256, "fgmres64"), (256, "fgmres32"), (512, "fgmres32")])
+@pytest.mark.parametrize("nz,mode", [(256, "fgmres64"), (256, "fgmres32"), (512, "fgmres32"),
+                                     (256, "fgmres32_basis32"), (512, "fgmres32_basis32")])
 def test_ninecell_quarter_eigenvalues(nz, mode):
     from paper_1301_3794_amd import dm
     ref = golden(nz)
@@ -39,7 +42,8 @@ def test_ninecell_quarter_eigenvalues(nz, mode):
     m = dm.SOLVE_FGMRES_MG64 if mode == "fgmres64" else dm.SOLVE_FGMRES_MG32
     print(f"[case] 9-cell quarter {nxy}x{nxy}x{nz} {mode}", flush=True)
     geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1, bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
-    with dm.Operator(geom, (nxy, nxy, nz), h, 632.0, levels=0, fgmres_restart=30, nu_pre=4, nu_post=4) as op:
+    with dm.Operator(geom, (nxy, nxy, nz), h, 632.0, levels=0, fgmres_restart=30, nu_pre=4, nu_post=4,
+                     krylov_basis_f32=int(mode.endswith("basis32"))) as op:
         assert op.layout(0)["active_faces"] == ref["active_faces"]
         out = op.eigs(9, sigma=632.0, tol=1e-10, seed=3, solve_mode=m, block=2, max_basis=48, max_restarts=30)
     assert out["status"] == 0, out
