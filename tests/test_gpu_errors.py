@@ -21,6 +21,8 @@ by a real input and ends in a normal return (no kernel is made to fault).
   (~37) and TM21 (~74); the 4 smallest eigenvalues still match the oracle.
 * An eigensolve out of restarts returns DM_NOT_CONVERGED with the pairs it
   has.
+* DM_EINVAL: an operator option outside its documented range is refused at
+  build time.
 """
 import math
 
@@ -190,3 +192,14 @@ def test_eigs_out_of_restarts(small):
     assert out["status"] == dm.DM_NOT_CONVERGED
     assert out["n_converged"] < 4
     assert out["lam"].shape == (4,) and np.all(np.isfinite(out["lam"]))
+
+
+@pytest.mark.parametrize("bad", [dict(krylov_basis_f32=2), dict(tilde_transfers=-1), dict(grad_div_volume=3),
+                                 dict(cut_wave_split=-1), dict(fgmres_restart=0), dict(nu_pre=-1)])
+def test_bad_options_rejected(bad):
+    """An option outside its documented range is refused at build time with
+    DM_EINVAL (no operator is made)."""
+    from paper_1301_3794_amd import dm
+    with pytest.raises(dm.DMError) as e:
+        dm.Operator(dm.sphere((0.5, 0.5, 0.5), 0.45), (8, 8, 8), 1.0 / 8, 5.0, levels=2, **bad)
+    assert e.value.code == dm.DM_EINVAL
