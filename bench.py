@@ -168,8 +168,9 @@ def parse():
     ap.add_argument("--skip-c4", action="store_true", help="do not run the 64 batched ellipsoids")
     ap.add_argument("--skip-studies", action="store_true", help="do not run the accuracy and solver studies")
     ap.add_argument("--skip-c1", action="store_true", help="do not run the small 16^3 configuration")
-    ap.add_argument("--only", choices=["c3", "c4", "traffic", "c3sweep", "studies", "learnediter"], default=None,
-                    help="profiling runs: only the 9-cell cavity, only the batch, the HBM-traffic "
+    ap.add_argument("--only", choices=["c1", "c3", "c4", "traffic", "c3sweep", "studies", "learnediter"],
+                    default=None,
+                    help="profiling runs: only the 16^3 sphere, only the 9-cell cavity, only the batch, the HBM-traffic "
                          "probe (a 256 MiB device copy of known size, then 3 FP32 red-black sweeps "
                          "on the 128^3 sphere's finest level), or the same probe on the 9-cell "
                          "quarter's finest level (3 one-vector and 3 two-vector sweeps), or only "
@@ -375,22 +376,33 @@ def learned_ninecell(dm, torch, net):
 
 def run_c1(dm, torch, reps=5):
     """The small configuration: sphere R = 0.45 at 16^3 (h = 1/16), sigma =
-    5, 3-level V-cycle, the 4 lowest pairs to rho <= 1e-10 in the
-    FP32-multigrid form; median over `reps` timed eigensolves after one
-    untimed.  Launch-bound: reported as seconds per eigenpair only."""
+    5, 3-level V-cycle with 2 + 2 sweeps, the 4 lowest pairs to rho <= 1e-10
+    in the plain FP64 form (the configuration's) and in the FP32-multigrid
+    form beside it; median over `reps` timed eigensolves after one untimed,
+    and the error of every eigenvalue against the stored oracle values
+    (tests/golden/sphere16_oracle.json: a dense eigensolve of the pencil).
+    Launch-bound: reported as seconds per eigenpair only."""
     import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "sphere16_oracle.json")
+    ref = np.array(json.load(open(path))["lam"][:4]) if os.path.exists(path) else None
+    out = {"grid": [16, 16, 16], "sigma": 5.0, "k": 4, "levels": 3, "nu": 2}
     with dm.Operator(dm.sphere((0.5, 0.5, 0.5), R), (16, 16, 16), 1.0 / 16, 5.0, levels=3) as op:
-        op.eigs(4, tol=TOL, seed=SEED, solve_mode=dm.SOLVE_FGMRES_MG32)
-        ts = []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out = op.eigs(4, tol=TOL, seed=SEED, solve_mode=dm.SOLVE_FGMRES_MG32)
-            torch.cuda.synchronize()
-            ts.append((time.perf_counter() - t0) / 4)
-    return {"grid": [16, 16, 16], "sigma": 5.0, "k": 4, "s_per_eigenpair_median": float(np.median(ts)),
-            "status": out["status"], "lam": out["lam"].tolist(), "max_residual": out["max_residual"],
-            "outer_iterations": out["outer_iterations"], "inner_iterations": out["inner_iterations"]}
+        for name, mode in (("fp64", dm.SOLVE_FGMRES_MG64), ("fp32mg", dm.SOLVE_FGMRES_MG32)):
+            op.eigs(4, tol=TOL, seed=SEED, solve_mode=mode)
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                o = op.eigs(4, tol=TOL, seed=SEED, solve_mode=mode)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) / 4)
+            r = {"s_per_eigenpair_median": float(np.median(ts)), "status": o["status"], "lam": o["lam"].tolist(),
+                 "max_residual": o["max_residual"], "outer_iterations": o["outer_iterations"],
+                 "inner_iterations": o["inner_iterations"]}
+            if ref is not None:
+                r["rel_err_vs_oracle"] = (abs(o["lam"] - ref) / ref).tolist()
+            out[name] = r
+    return out
 
 
 def run_studies(dm):
@@ -479,6 +491,9 @@ def main():
     from paper_1301_3794_amd import dm
 
     torch.cuda.set_device(0)
+    if args.only == "c1":
+        print(json.dumps({"c1_small": run_c1(dm, torch)}))
+        return
     if args.only == "c3":
         print(json.dumps({"c3_9cell_quarter": run_c3(dm, torch, measure_copy_gbps(torch))}))
         return
