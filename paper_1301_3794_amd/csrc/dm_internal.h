@@ -536,13 +536,16 @@ struct Coef4 {
 //   cg_update: psi_q += a_q p_q, r_q -= a_q q_q, dout[q] = r_q . (r_q * wt)
 //   xpby_b:    Y_q = X_q + b_q Y_q
 //   sub_masked_b: X_q -= scale * val[q * stride] where mask != 0
+// The first three visit only the listed units of sp (the whole vectors
+// without a list): every vector they read is zero outside those units, and
+// what they write is left untouched there.
 void launch_dot_pairs(int nr, const VPtr<const double> &X, const VPtr<const double> &Y, const double *wt,
-                      int64_t n, double *part, double *dout, int64_t dstride, hipStream_t s);
+                      int64_t n, double *part, double *dout, int64_t dstride, hipStream_t s, Span sp = {});
 void launch_cg_update(int nr, const VPtr<const double> &Pv, const VPtr<const double> &Qv, const VPtr<double> &Psi,
                       const VPtr<double> &R, const Coef4 &a, const double *wt, int64_t n, double *part, double *dout,
-                      int64_t dstride, hipStream_t s);
+                      int64_t dstride, hipStream_t s, Span sp = {});
 void launch_xpby_b(int nr, const VPtr<const double> &X, const Coef4 &b, const VPtr<double> &Y, int64_t n,
-                   hipStream_t s);
+                   hipStream_t s, Span sp = {});
 void launch_sub_masked_b(int nr, int64_t n, const double *mask, const double *val, int64_t stride, double scale,
                          const VPtr<double> &X, hipStream_t s);
 // masked shift: x[n] -= scale * val[0] where mask[n] != 0 (val on device)

@@ -1093,17 +1093,19 @@ k_mdot_final(int nblk, const double *__restrict__ part, double *__restrict__ out
 
 // Dot products of up to kMaxRhs pairs in one pass:
 //   part[q][block] = partial sum of X_q . (Y_q * wt) for the pairs with X_q set
-// (wt, when given, is read once for all pairs)
+// (wt, when given, is read once for all pairs), over the listed units of sp
 template <int VEC>
 __global__ void __launch_bounds__(kThreads)
 k_dot_pairs(VPtr<const double> X, VPtr<const double> Y, const double *__restrict__ wt, int64_t n,
-            double *__restrict__ part) {
+            double *__restrict__ part, Span sp) {
     using O = Vec<VEC>;
-    const int64_t nvec = n / VEC;
+    const int64_t nvec = n / VEC, cnt = span_count<VEC>(sp, nvec);
     double acc[kMaxRhs];
 #pragma unroll
     for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < nvec; e += (int64_t)gridDim.x * kThreads) {
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt; it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = span_elem<VEC>(sp, it);
+        if (e >= nvec) continue;
         const typename O::T w = wt ? O::ld(wt, e) : typename O::T{};
 #pragma unroll
         for (int q = 0; q < kMaxRhs; ++q)
@@ -1153,13 +1155,17 @@ k_mdot_final_strided(int nblk, const double *__restrict__ part, double *__restri
 
 // One conjugate-gradient update of the vectors with Pv_q set:
 //   psi_q += a_q p_q,  r_q -= a_q q_q,  part[q][block] = partial of r_q . (r_q * wt)
+// over the listed units of sp
 __global__ void __launch_bounds__(kThreads)
 k_cg_update(VPtr<const double> Pv, VPtr<const double> Qv, VPtr<double> Psi, VPtr<double> R, Coef4 a,
-            const double *__restrict__ wt, int64_t n, double *__restrict__ part) {
+            const double *__restrict__ wt, int64_t n, double *__restrict__ part, Span sp) {
     double acc[kMaxRhs];
 #pragma unroll
     for (int q = 0; q < kMaxRhs; ++q) acc[q] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads) {
+    const int64_t cnt = span_count<1>(sp, n);
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt; it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = span_elem<1>(sp, it);
+        if (e >= n) continue;
         const double w = wt[e];
 #pragma unroll
         for (int q = 0; q < kMaxRhs; ++q)
@@ -1186,13 +1192,17 @@ k_cg_update(VPtr<const double> Pv, VPtr<const double> Qv, VPtr<double> Psi, VPtr
     }
 }
 
-// Y_q = X_q + b_q Y_q for the vectors with Y_q set
+// Y_q = X_q + b_q Y_q for the vectors with Y_q set, over the listed units of sp
 __global__ void __launch_bounds__(kThreads)
-k_xpby_b(VPtr<const double> X, Coef4 b, VPtr<double> Y, int64_t n) {
-    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (int64_t)gridDim.x * kThreads)
+k_xpby_b(VPtr<const double> X, Coef4 b, VPtr<double> Y, int64_t n, Span sp) {
+    const int64_t cnt = span_count<1>(sp, n);
+    for (int64_t it = (int64_t)blockIdx.x * kThreads + threadIdx.x; it < cnt; it += (int64_t)gridDim.x * kThreads) {
+        const int64_t e = span_elem<1>(sp, it);
+        if (e >= n) continue;
 #pragma unroll
         for (int q = 0; q < kMaxRhs; ++q)
             if (Y.p[q]) Y.p[q][e] = X.p[q][e] + b.v[q] * Y.p[q][e];
+    }
 }
 
 // X_q -= scale * val[q * stride] where mask != 0, for the vectors with X_q set
@@ -2230,7 +2240,7 @@ void launch_maxpy_scale(int nv, const double *V, int64_t ld, const double *c, co
 }
 
 void launch_dot_pairs(int nr, const VPtr<const double> &X, const VPtr<const double> &Y, const double *wt,
-                      int64_t n, double *part, double *dout, int64_t dstride, hipStream_t s) {
+                      int64_t n, double *part, double *dout, int64_t dstride, hipStream_t s, Span sp) {
     if (nr < 1 || nr > kMaxRhs) throw std::runtime_error("launch_dot_pairs: 1 to 4 pairs");
     VPtr<const double> x{}, y{};
     for (int q = 0; q < nr; ++q) {
@@ -2239,28 +2249,28 @@ void launch_dot_pairs(int nr, const VPtr<const double> &X, const VPtr<const doub
     }
     bool v2 = vec2_ok(n, 0, {wt});
     for (int q = 0; q < nr; ++q) v2 = v2 && vec2_ok(n, 0, {x.p[q], y.p[q]});
-    if (v2) hipLaunchKernelGGL(k_dot_pairs<2>, dim3(kReduceBlocks), dim3(kThreads), 0, s, x, y, wt, n, part);
-    else hipLaunchKernelGGL(k_dot_pairs<1>, dim3(kReduceBlocks), dim3(kThreads), 0, s, x, y, wt, n, part);
+    if (v2) hipLaunchKernelGGL(k_dot_pairs<2>, dim3(kReduceBlocks), dim3(kThreads), 0, s, x, y, wt, n, part, sp);
+    else hipLaunchKernelGGL(k_dot_pairs<1>, dim3(kReduceBlocks), dim3(kThreads), 0, s, x, y, wt, n, part, sp);
     hipLaunchKernelGGL(k_mdot_final_strided, dim3(nr), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout, dstride);
 }
 
 void launch_cg_update(int nr, const VPtr<const double> &Pv, const VPtr<const double> &Qv, const VPtr<double> &Psi,
                       const VPtr<double> &R, const Coef4 &a, const double *wt, int64_t n, double *part, double *dout,
-                      int64_t dstride, hipStream_t s) {
+                      int64_t dstride, hipStream_t s, Span sp) {
     if (nr < 1 || nr > kMaxRhs) throw std::runtime_error("launch_cg_update: 1 to 4 vectors");
     VPtr<const double> pv{};
     for (int q = 0; q < nr; ++q) pv.p[q] = Pv.p[q];
-    hipLaunchKernelGGL(k_cg_update, dim3(kReduceBlocks), dim3(kThreads), 0, s, pv, Qv, Psi, R, a, wt, n, part);
+    hipLaunchKernelGGL(k_cg_update, dim3(kReduceBlocks), dim3(kThreads), 0, s, pv, Qv, Psi, R, a, wt, n, part, sp);
     hipLaunchKernelGGL(k_mdot_final_strided, dim3(nr), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout, dstride);
 }
 
 void launch_xpby_b(int nr, const VPtr<const double> &X, const Coef4 &b, const VPtr<double> &Y, int64_t n,
-                   hipStream_t s) {
+                   hipStream_t s, Span sp) {
     VPtr<double> y{};
     for (int q = 0; q < nr && q < kMaxRhs; ++q) y.p[q] = Y.p[q];
-    hipLaunchKernelGGL(k_xpby_b, flat_grid(n), dim3(kThreads), 0, s, X, b, y, n);
+    hipLaunchKernelGGL(k_xpby_b, flat_grid(sp.u ? sp.n * kSpanUnit : n), dim3(kThreads), 0, s, X, b, y, n, sp);
 }
 
 void launch_sub_masked_b(int nr, int64_t n, const double *mask, const double *val, int64_t stride, double scale,

@@ -477,6 +477,33 @@ void build_hierarchy(dm_op *op, const double *user_frac) {
     DM_HIP(hipMemcpyAsync(op->wface, wf.data(), wf.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
     DM_HIP(hipMemcpyAsync(op->wa, wa.data(), wa.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
     DM_HIP(hipMemcpyAsync(op->wainv, wi.data(), wi.size() * sizeof(double), hipMemcpyHostToDevice, op->stream));
+    // units of kSpanUnit doubles of a level-0 cell vector holding an active
+    // cell or a PMC ghost image (index -1 on a PMC axis)
+    {
+        std::vector<uint8_t> live((P0 + kSpanUnit - 1) / kSpanUnit, 0);
+        const int nn[3] = {g.nx, g.ny, g.nz};
+        for (int k = -1; k <= g.nz; ++k)
+            for (int j = -1; j <= g.ny; ++j)
+                for (int i = -1; i <= g.nx; ++i) {
+                    const int idx[3] = {i, j, k};
+                    const int64_t p = pidx(g, i, j, k);
+                    bool owned = true, ghost = false;
+                    for (int a = 0; a < 3; ++a) {
+                        if (idx[a] < 0 || idx[a] >= nn[a]) owned = false;
+                        if (idx[a] == -1 && ((pmc >> a) & 1)) ghost = true;
+                    }
+                    if (ghost || (owned && cm[p] != 0.0)) live[p / kSpanUnit] = 1;
+                }
+        std::vector<int32_t> units;
+        for (int64_t u = 0; u < (int64_t)live.size(); ++u)
+            if (live[u]) units.push_back((int32_t)u);
+        op->ncunit = (int64_t)units.size();
+        if (!units.empty()) {
+            op->cunit = op->dalloc<int32_t>(units.size());
+            DM_HIP(hipMemcpyAsync(op->cunit, units.data(), units.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  op->stream));
+        }
+    }
     op->part = op->dalloc<double>((size_t)kReduceBlocks * kMaxDots);
     op->dres = op->dalloc<double>(kMaxDots);
     DM_HIP(hipHostMalloc((void **)&op->hres, kMaxDots * sizeof(double), hipHostMallocDefault));

@@ -194,6 +194,11 @@ struct dm_op {
     int32_t *vunit = nullptr;
     int64_t nvunit = 0;
     dm::Span vspan() const { return dm::Span{vunit, nvunit}; }
+    // the same for a level-0 cell vector: units holding an active cell or a
+    // PMC ghost image (the projection's conjugate-gradient vectors)
+    int32_t *cunit = nullptr;
+    int64_t ncunit = 0;
+    dm::Span cspan() const { return dm::Span{cunit, ncunit}; }
 
     template <class T>
     T *dalloc(size_t count) {

@@ -749,6 +749,11 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
                               hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
     };
+    // the CG's reductions and updates visit the units of the cell vectors
+    // that hold an active cell or a PMC ghost image: g = D A b, the V-cycle's
+    // z, S p and every combination of them are zero elsewhere (as is psi,
+    // cleared below), and so stay zero there
+    const Span csp = op->cspan();
     // z = B r for every slot: the FP64 V-cycle on the slots themselves, or
     // the FP32 one between two casts (the slots are consecutive)
     auto graph = [&]() {
@@ -777,12 +782,12 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
         if (!op->s_floating) return;
         VPtr<const double> M{};
         for (int q = 0; q < nr; ++q) M.p[q] = op->cmask;
-        launch_dot_pairs(nr, as_const(X), M, nullptr, P, op->part, op->bk_dres + 2, kMaxDots, s);
+        launch_dot_pairs(nr, as_const(X), M, nullptr, P, op->part, op->bk_dres + 2, kMaxDots, s, csp);
         launch_sub_masked_b(nr, P, op->cmask, op->bk_dres + 2, kMaxDots, inv_cells, X, s);
     };
     launch_div_DA_b(g, L.coef64, nr, B, G, s);
     demean(G);
-    launch_dot_pairs(nr, as_const(G), as_const(G), op->cmask, P, op->part, op->bk_dres, kMaxDots, s);
+    launch_dot_pairs(nr, as_const(G), as_const(G), op->cmask, P, op->part, op->bk_dres, kMaxDots, s, csp);
     launch_dot_pairs(nr, B, B, op->wa, n, op->part, op->bk_dres + 1, kMaxDots, s);
     fetch();
     double stop[kMaxRhs], rz[kMaxRhs];
@@ -804,7 +809,7 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
         graph();                                   // r -> z, every slot
         demean(Z);
         launch_copy((int64_t)nr * P, Z.p[0], PP.p[0], s);
-        launch_dot_pairs(nr, as_const(R), as_const(Z), op->cmask, P, op->part, op->bk_dres, kMaxDots, s);
+        launch_dot_pairs(nr, as_const(R), as_const(Z), op->cmask, P, op->part, op->bk_dres, kMaxDots, s, csp);
         fetch();
         for (int q = 0; q < nr; ++q) rz[q] = hres(q)[0];
         int it = 0;
@@ -813,7 +818,7 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
             launch_s_apply_b(g, L.coef64, L.sweight, 0, nr, VPtr<const double>{}, as_const(PP), Q, s, L.arows,
                              L.narows);
             launch_dot_pairs(nr, as_const(pick(PP, act)), as_const(Q), op->cmask, P, op->part, op->bk_dres,
-                             kMaxDots, s);
+                             kMaxDots, s, csp);
             fetch();
             Coef4 alpha;
             for (int q = 0; q < nr; ++q) {
@@ -831,7 +836,7 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
             if (!upd) break;
             // psi += alpha p, r -= alpha q and |r|^2, every active system
             launch_cg_update(nr, as_const(pick(PP, act)), as_const(Q), PSI, R, alpha, op->cmask, P, op->part,
-                             op->bk_dres, kMaxDots, s);
+                             op->bk_dres, kMaxDots, s, csp);
             ++it;
             fetch();
             any = false;
@@ -843,7 +848,7 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
             graph();                               // r -> z
             demean(pick(Z, act));
             launch_dot_pairs(nr, as_const(pick(R, act)), as_const(Z), op->cmask, P, op->part, op->bk_dres,
-                             kMaxDots, s);
+                             kMaxDots, s, csp);
             fetch();
             Coef4 beta;
             for (int q = 0; q < nr; ++q) {
@@ -852,7 +857,7 @@ int project_block(dm_op *op, int nr, const double *const *b, double *const *out,
                 beta.v[q] = rz2 / rz[q];
                 rz[q] = rz2;
             }
-            launch_xpby_b(nr, as_const(Z), beta, pick(PP, act), P, s);   // p = z + beta p
+            launch_xpby_b(nr, as_const(Z), beta, pick(PP, act), P, s, csp);   // p = z + beta p
         }
     }
     VPtr<double> O{};
