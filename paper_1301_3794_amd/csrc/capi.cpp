@@ -132,7 +132,7 @@ static void free_op(dm_op *op) {
     if (op->bk_hres) hipHostFree(op->bk_hres);
     if (op->hres2) hipHostFree(op->hres2);
     if (op->ln_hflag) hipHostFree(op->ln_hflag);
-    if (op->bk_hres2) hipHostFree(op->bk_hres2);
+    if (op->bk_hsc2) hipHostFree(op->bk_hsc2);   // bk_hres2 lies inside bk_hres
     if (op->stream) hipStreamDestroy(op->stream);
     delete op;
 }

@@ -170,7 +170,9 @@ struct dm_op {
     float *bk_V32 = nullptr;
     double *bk_W = nullptr;
     double *bk_dres = nullptr, *bk_dcoef = nullptr, *bk_hres = nullptr;
-    double *bk_dres2 = nullptr, *bk_hres2 = nullptr, *bk_sc2 = nullptr;   // as dres2, hres2, sc2d
+    // dres2 / hres2 follow dres / hres in the same allocations (one copy
+    // brings both); hsc2 is the pinned host image of sc2
+    double *bk_dres2 = nullptr, *bk_hres2 = nullptr, *bk_sc2 = nullptr, *bk_hsc2 = nullptr;
     hipGraphExec_t g_vb32[dm::kMaxRhs + 1] = {}, g_vb64[dm::kMaxRhs + 1] = {};
     // block projection: per-vector CG state (kMaxRhs * P each) and graphs
     double *pjb_g = nullptr, *pjb_psi = nullptr, *pjb_p = nullptr, *pjb_q = nullptr;

@@ -602,12 +602,14 @@ void invalidate_graphs(dm_op *op) {
 
 void ensure_block_results(dm_op *op) {
     if (!op->bk_dres) {
-        op->bk_dres = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
-        op->bk_dcoef = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
-        DM_HIP(hipHostMalloc((void **)&op->bk_hres, kMaxRhs * kMaxDots * sizeof(double), hipHostMallocDefault));
-        op->bk_dres2 = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
-        op->bk_sc2 = op->dalloc<double>((size_t)kMaxRhs * kMaxDots);
-        DM_HIP(hipHostMalloc((void **)&op->bk_hres2, kMaxRhs * kMaxDots * sizeof(double), hipHostMallocDefault));
+        const size_t nd = (size_t)kMaxRhs * kMaxDots;
+        op->bk_dres = op->dalloc<double>(2 * nd);
+        op->bk_dres2 = op->bk_dres + nd;
+        op->bk_dcoef = op->dalloc<double>(nd);
+        DM_HIP(hipHostMalloc((void **)&op->bk_hres, 2 * nd * sizeof(double), hipHostMallocDefault));
+        op->bk_hres2 = op->bk_hres + nd;
+        op->bk_sc2 = op->dalloc<double>(nd);
+        DM_HIP(hipHostMalloc((void **)&op->bk_hsc2, nd * sizeof(double), hipHostMallocDefault));
     }
 }
 
@@ -977,6 +979,17 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
     auto dres2 = [&](int r) { return op->bk_dres2 + (int64_t)r * kMaxDots; };
     auto hres2 = [&](int r) { return op->bk_hres2 + (int64_t)r * kMaxDots; };
     auto dsc2 = [&](int r) { return op->bk_sc2 + (int64_t)r * kMaxDots; };
+    // the scales sc^2 of every system go to the device in one copy of their
+    // pinned host image; it is written only after a host sync that follows
+    // the previous copy, so no copy in flight reads it
+    auto hsc2 = [&](int r) { return op->bk_hsc2 + (int64_t)r * kMaxDots; };
+    bool put_sc2 = false;
+    auto send_sc2 = [&]() {
+        if (put_sc2)
+            DM_HIP(hipMemcpyAsync(op->bk_sc2, op->bk_hsc2, (size_t)nb * kMaxDots * sizeof(double),
+                                  hipMemcpyHostToDevice, s));
+        put_sc2 = false;
+    };
     // every system's device results to the host, one sync
     auto fetch = [&]() {
         DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nb * kMaxDots * sizeof(double),
@@ -1052,7 +1065,8 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                 }
                 R.sc[0] = 1.0 / beta;   // unnormalised basis, as in fgmres()
                 R.sc2[0] = R.sc[0] * R.sc[0];
-                DM_HIP(hipMemcpyAsync(dsc2(r), R.sc2.data(), sizeof(double), hipMemcpyHostToDevice, s));
+                hsc2(r)[0] = R.sc2[0];
+                put_sc2 = true;
                 std::fill(R.g.begin(), R.g.end(), 0.0);
                 R.g[0] = beta;
                 std::fill(R.H.begin(), R.H.end(), 0.0);
@@ -1100,6 +1114,7 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
         }
         // Gram--Schmidt as in fgmres(): (1) d = U^T w, (2) w -= U (sc^2 d)
         // fused with d2 = U^T w and |w|^2, every open system, one sync
+        send_sc2();
         for (int r : act) {
             const int j = st[r].j;
             if (b32) {
@@ -1112,9 +1127,8 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
                                        dsc2(r), sp);
             }
         }
-        DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)nb * kMaxDots * sizeof(double), hipMemcpyDeviceToHost,
-                              s));
-        DM_HIP(hipMemcpyAsync(op->bk_hres2, op->bk_dres2, (size_t)nb * kMaxDots * sizeof(double),
+        // dres2 follows dres: one copy brings both
+        DM_HIP(hipMemcpyAsync(op->bk_hres, op->bk_dres, (size_t)(kMaxRhs + nb) * kMaxDots * sizeof(double),
                               hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
         // (3) the second correction where needed; Hessenberg column, Givens
@@ -1146,7 +1160,8 @@ int fgmres_block(dm_op *op, int mode, int nb, const double *const *f, double *co
             if (!std::isfinite(hn)) throw DmError{DM_ENAN, "FGMRES iterate is not finite"};
             R.sc[j + 1] = hn > 0.0 ? R.sc[j] / hn : 0.0;
             R.sc2[j + 1] = R.sc[j + 1] * R.sc[j + 1];
-            DM_HIP(hipMemcpyAsync(dsc2(r) + j + 1, &R.sc2[j + 1], sizeof(double), hipMemcpyHostToDevice, s));
+            hsc2(r)[j + 1] = R.sc2[j + 1];
+            put_sc2 = true;
             double *H = R.H.data();
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = R.h[i];
             H[(size_t)(j + 1) * m + j] = hn;
