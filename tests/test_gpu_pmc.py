@@ -6,7 +6,9 @@ y = 0) from the oracle's quarter fractions.  The oracle's half-cavity
 operators are the full cavity's rows on symmetric fields (oracle/symmetry.py):
 apply, residual, smoother, transfers and V-cycle are compared element by
 element (FP64 1e-12, FP32 2e-5 / 5e-5), and the eigenvalues with the
-symmetric pencil's dense eigenvalues (1e-10).
+symmetric pencil's dense eigenvalues (1e-10).  The block projection
+(whose conjugate gradients skip the cell units without an active cell or a
+ghost image) matches the single-vector one to 1e-12.
 """
 import numpy as np
 import pytest
@@ -128,3 +130,16 @@ def test_eigs(case, mode):
         r = K @ b - out["lam"][c] * a * b
         rho = np.sqrt(np.sum(r * r / a)) / (out["lam"][c] * np.sqrt(np.sum(a * b * b)))
         assert rho <= 2e-10
+
+
+def test_project_block_matches_single(case):
+    """The block projection's CG visits only the cell-vector units holding an
+    active cell or a PMC ghost image; with PMC planes it matches the
+    single-vector projection, which visits every cell, to rounding."""
+    op, hop = case["op"], case["hop"]
+    bs = [dev(lay.faces_to_padded(rnd(hop, 30 + q), NH)) for q in range(3)]
+    outs = op.project_block(bs, [op.face_tensor() for _ in range(3)], rtol=1e-13)
+    for q in range(3):
+        one = op.project(bs[q], op.face_tensor(), rtol=1e-13)
+        got, ref = outs[q].cpu().numpy(), one.cpu().numpy()
+        assert rel_inf(got, ref) <= 1e-12, q
