@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <stdexcept>
+#include <type_traits>
 
 #include "dm_internal.h"
 
@@ -2045,22 +2046,25 @@ inline bool vec4_basis_ok(int64_t n, int64_t ld, const TV *V, std::initializer_l
         if (p && ((uintptr_t)p & 15)) return false;
     return true;
 }
+// f(width) with the widest load width (a std::integral_constant) that the
+// basis type and the pointers allow: 4 (FP32 basis only), 2 or 1
+template <class TV, class F>
+inline void with_basis_width(int64_t n, int64_t ld, const TV *V, std::initializer_list<const void *> ptrs, F &&f) {
+    if constexpr (sizeof(TV) == 4)
+        if (vec4_basis_ok(n, ld, V, ptrs)) return f(std::integral_constant<int, 4>{});
+    if (vec2_basis_ok(n, ld, V, ptrs)) return f(std::integral_constant<int, 2>{});
+    f(std::integral_constant<int, 1>{});
+}
 
 template <class TV>
 void launch_mdot_t(int nv, const TV *V, int64_t ld, const double *w, const double *wt, int64_t n, double *part,
                    double *dout, hipStream_t s, Span sp) {
     if (nv <= 0) return;
     if (nv > 256) throw std::runtime_error("launch_mdot: more than 256 vectors");
-    bool done = false;
-    if constexpr (sizeof(TV) == 4)
-        if ((done = vec4_basis_ok(n, ld, V, {w, wt})))
-            hipLaunchKernelGGL((k_mdot<4, TV>), dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part,
-                               sp);
-    if (done) {
-    } else if (vec2_basis_ok(n, ld, V, {w, wt}))
-        hipLaunchKernelGGL((k_mdot<2, TV>), dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
-    else
-        hipLaunchKernelGGL((k_mdot<1, TV>), dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
+    with_basis_width(n, ld, V, {w, wt}, [&](auto width) {
+        constexpr int W = decltype(width)::value;
+        hipLaunchKernelGGL((k_mdot<W, TV>), dim3(kReduceBlocks), dim3(kThreads), 0, s, nv, V, ld, w, wt, n, part, sp);
+    });
     hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kThreads), 0, s, (int)kReduceBlocks,
                        (const double *)part, dout);
 }
@@ -2122,18 +2126,11 @@ void launch_maxpy_t(int nv, const TV *V, int64_t ld, const double *c, double *y,
     if (nv <= 0 && !overwrite) return;
     if (nv > 256) throw std::runtime_error("launch_maxpy: more than 256 vectors");
     const int64_t cnt = sp.u ? sp.n * kSpanUnit : n;
-    bool done = false;
-    if constexpr (sizeof(TV) == 4)
-        if ((done = vec4_basis_ok(n, ld, V, {y})))
-            hipLaunchKernelGGL((k_maxpy<4, TV>), flat_grid(cnt / 4), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
-                               (const double *)nullptr, 1.0, y, n, overwrite, sp);
-    if (done) {
-    } else if (vec2_basis_ok(n, ld, V, {y}))
-        hipLaunchKernelGGL((k_maxpy<2, TV>), flat_grid(cnt / 2), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
+    with_basis_width(n, ld, V, {y}, [&](auto width) {
+        constexpr int W = decltype(width)::value;
+        hipLaunchKernelGGL((k_maxpy<W, TV>), flat_grid(cnt / W), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
                            (const double *)nullptr, 1.0, y, n, overwrite, sp);
-    else
-        hipLaunchKernelGGL((k_maxpy<1, TV>), flat_grid(cnt), dim3(kThreads), 0, s, nv, V, ld, c, cscale,
-                           (const double *)nullptr, 1.0, y, n, overwrite, sp);
+    });
 }
 }  // namespace
 
@@ -2180,7 +2177,6 @@ template <class TV>
 void launch_maxpy_mdot_norm_t(int nv, const TV *V, int64_t ld, const double *c, double *w, int64_t n,
                               double *part, double *dout, hipStream_t s, const double *cscale, Span sp) {
     if (nv < 1 || nv + 1 > 256) throw std::runtime_error("launch_maxpy_mdot_norm: nv out of range");
-    const bool v2 = vec2_basis_ok(n, ld, V, {w});
     const dim3 b(kThreads);
     int nb = kReduceBlocks;
     // one fused kernel for nv <= 32 (the basis held in registers)
@@ -2188,32 +2184,22 @@ void launch_maxpy_mdot_norm_t(int nv, const TV *V, int64_t ld, const double *c, 
         nb = blocks;
         hipLaunchKernelGGL(kern, dim3(nb), b, 0, s, nv, V, ld, c, cscale, w, n, part, sp);
     };
-    bool done = false;
-    if constexpr (sizeof(TV) == 4)
-        if ((done = nv <= 32 && vec4_basis_ok(n, ld, V, {w}))) {
-            if (nv <= 8) fused(k_maxpy_mdot_norm<4, 8, false, TV>, reduce_blocks<k_maxpy_mdot_norm<4, 8, false, TV>>());
-            else if (nv <= 16)
-                fused(k_maxpy_mdot_norm<4, 16, false, TV>, reduce_blocks<k_maxpy_mdot_norm<4, 16, false, TV>>());
-            else fused(k_maxpy_mdot_norm<4, 32, true, TV>, reduce_blocks<k_maxpy_mdot_norm<4, 32, true, TV>>());
+    with_basis_width(n, ld, V, {w}, [&](auto width) {
+        constexpr int W = decltype(width)::value;
+        if (nv <= 8) {
+            fused(k_maxpy_mdot_norm<W, 8, false, TV>, reduce_blocks<k_maxpy_mdot_norm<W, 8, false, TV>>());
+        } else if (nv <= 16) {
+            fused(k_maxpy_mdot_norm<W, 16, false, TV>, reduce_blocks<k_maxpy_mdot_norm<W, 16, false, TV>>());
+        } else if (nv <= 32) {
+            fused(k_maxpy_mdot_norm<W, 32, true, TV>, reduce_blocks<k_maxpy_mdot_norm<W, 32, true, TV>>());
+        } else {
+            // too many vectors to hold in registers: update w, then a second
+            // pass for the dots (the basis is read twice)
+            launch_maxpy_t<TV>(nv, V, ld, c, w, n, 0, s, cscale, sp);
+            hipLaunchKernelGGL((k_mdot_norm<W, TV>), dim3(kReduceBlocks), b, 0, s, nv, V, ld, (const double *)w, n,
+                               part, sp);
         }
-    if (done) {
-    } else if (nv <= 8) {
-        if (v2) fused(k_maxpy_mdot_norm<2, 8, false, TV>, reduce_blocks<k_maxpy_mdot_norm<2, 8, false, TV>>());
-        else fused(k_maxpy_mdot_norm<1, 8, false, TV>, reduce_blocks<k_maxpy_mdot_norm<1, 8, false, TV>>());
-    } else if (nv <= 16) {
-        if (v2) fused(k_maxpy_mdot_norm<2, 16, false, TV>, reduce_blocks<k_maxpy_mdot_norm<2, 16, false, TV>>());
-        else fused(k_maxpy_mdot_norm<1, 16, false, TV>, reduce_blocks<k_maxpy_mdot_norm<1, 16, false, TV>>());
-    } else if (nv <= 32) {
-        if (v2) fused(k_maxpy_mdot_norm<2, 32, true, TV>, reduce_blocks<k_maxpy_mdot_norm<2, 32, true, TV>>());
-        else fused(k_maxpy_mdot_norm<1, 32, true, TV>, reduce_blocks<k_maxpy_mdot_norm<1, 32, true, TV>>());
-    } else {
-        // too many vectors to hold in registers: update w, then a second
-        // pass for the dots (the basis is read twice)
-        launch_maxpy_t<TV>(nv, V, ld, c, w, n, 0, s, cscale, sp);
-        const dim3 g(kReduceBlocks);
-        if (v2) hipLaunchKernelGGL((k_mdot_norm<2, TV>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
-        else hipLaunchKernelGGL((k_mdot_norm<1, TV>), g, b, 0, s, nv, V, ld, (const double *)w, n, part, sp);
-    }
+    });
     hipLaunchKernelGGL(k_mdot_final, dim3(nv + 1), dim3(kThreads), 0, s, nb, (const double *)part, dout);
 }
 }  // namespace
