@@ -9,7 +9,7 @@ cavity, symmetric half pencil, block Lanczos) wrote the 9 smallest
 eigenvalues; the library computes its own fractions and runs the workload's
 eigensolver settings (shift 632, block 2, basis 48, FGMRES(30), 4 + 4
 sweeps).  Bars: 1e-10 relative for the FP64 form, 1e-9 for the
-FP32-multigrid form (the spec bars), and every returned rho <= 1e-10.
+FP32-multigrid form, and every returned rho <= 1e-10.
 The FP32-multigrid form is also run with its Krylov basis stored in FP32
 (operator option krylov_basis_f32), to the same bar.
 """
