@@ -23,7 +23,9 @@ sizes (3 vectors on the sphere, 2 on the 9-cell quarter) equals the
 single-vector V-cycle on every vector (FP64 1e-14, FP32 1e-6).  At these
 sizes the finest level's lists of non-vacuum rows exceed the block
 smoother's wave split, so this covers its one-thread-per-row path (the
-small grids of the block tests reach it only when it is forced).
+small grids of the block tests reach it only when it is forced).  And the
+9-cell quarter's block FGMRES with its Krylov basis in FP32 meets the
+tolerance in the FP64 residual and agrees with the FP64-basis answer.
 """
 import numpy as np
 import pytest
@@ -242,3 +244,36 @@ def test_empty_geometry_is_rejected():
     with pytest.raises(dm.DMError) as e:
         dm.Operator(dm.ellipsoid((0.53, 0.51, 0.52), (0.004, 0.004, 0.004)), (16, 16, 16), 1.0 / 16, 5.0)
     assert e.value.code == dm.DM_EINVAL
+
+
+def test_ninecell_block_solve_fp32_basis():
+    """At full size (96 x 96 x 1024, the 9-cell workload's settings: 4 + 4
+    sweeps, FGMRES(30), two systems in lockstep) the block FGMRES with its
+    Krylov basis stored in FP32 meets the tolerance in the FP64 residual,
+    recomputed here by dm_residual, as the FP64-basis solve does; the two
+    answers agree to the accuracy the tolerance allows."""
+    from paper_1301_3794_amd import dm
+    n, h = (96, 96, 1024), 1.235 / 1024
+    geom = dm.elliptic_bor((0.0, 0.0), 0.0, 9, 0.103, 0.035, 0.115, 0.1,
+                           bc_lo=(dm.BC_PMC, dm.BC_PMC, dm.BC_PEC))
+    rtol = 3e-11
+    answers = []
+    for b32 in (0, 1):
+        print(f"[case] full-size 9-cell quarter block solve, FP32 basis {b32}", flush=True)
+        with dm.Operator(geom, n, h, 632.0, levels=0, fgmres_restart=30, nu_pre=4, nu_post=4,
+                         krylov_basis_f32=b32) as op:
+            P = op.layout(0)["P"]
+            gen = torch.Generator().manual_seed(31)
+            mask = torch.tensor(op.fractions(0)[:3].reshape(-1) > 0)
+            fs = [(torch.randn(3 * P, dtype=torch.float64, generator=gen) * mask).cuda() for _ in range(2)]
+            xs = [op.face_tensor() for _ in range(2)]
+            infos = op.solve_block(fs, xs, mode=dm.SOLVE_FGMRES_MG32, rtol=rtol, maxit=800)
+            for q in range(2):
+                assert infos[q]["status"] == 0, (b32, infos[q])
+                r = op.residual(fs[q], xs[q], op.face_tensor())
+                rel = float(torch.linalg.norm(r) / torch.linalg.norm(fs[q]))
+                assert rel <= 1.5 * rtol, (b32, q, rel)
+            answers.append([x.cpu() for x in xs])
+    for q in range(2):
+        gap = float((answers[0][q] - answers[1][q]).abs().max() / answers[0][q].abs().max())
+        assert gap <= 1e-6, (q, gap)
