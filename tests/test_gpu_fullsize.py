@@ -25,7 +25,9 @@ sizes the finest level's lists of non-vacuum rows exceed the block
 smoother's wave split, so this covers its one-thread-per-row path (the
 small grids of the block tests reach it only when it is forced).  And the
 9-cell quarter's block FGMRES with its Krylov basis in FP32 meets the
-tolerance in the FP64 residual and agrees with the FP64-basis answer.
+tolerance in the FP64 residual and agrees with the FP64-basis answer; the
+128^3 block projection is divergence-free to its tolerance and equals the
+single-vector one.
 """
 import numpy as np
 import pytest
@@ -195,6 +197,32 @@ def block_equals_single(op, nr, prec, seed):
 def test_sphere128_vcycle_block_equals_single(sphere128, prec):
     dm, op, n, h, _ = sphere128
     assert block_equals_single(op, 3, prec, 5) <= (1e-14 if prec == 64 else 1e-6)
+
+
+def test_sphere128_project_block(sphere128):
+    """The block projection of the benchmark's block size (3 vectors; its
+    conjugate gradients over the cell units holding an active cell) at
+    128^3: every output divergence-free to the CG's tolerance on the field's
+    scale, ||V^-1/2 D A b'|| <= 1e-12 ||b||_A / h, and equal to the
+    single-vector projection (which visits every cell) to 1e-12."""
+    dm, op, n, h, _ = sphere128
+    P = op.layout(0)["P"]
+    fr = op.fractions(0)
+    a = torch.tensor(fr[:3].reshape(-1), device="cuda")
+    v = torch.tensor(fr[6], device="cuda")
+    vin = torch.where(v > 0, 1.0 / torch.clamp(v, min=1e-300), torch.zeros_like(v))
+    gen = torch.Generator().manual_seed(41)
+    mask = torch.tensor(fr[:3].reshape(-1) > 0)
+    bs = [(torch.randn(3 * P, dtype=torch.float64, generator=gen) * mask).cuda() for _ in range(3)]
+    outs = op.project_block(bs, [op.face_tensor() for _ in range(3)], rtol=1e-13)
+    g = op.cell_tensor()
+    for q in range(3):
+        op.apply(dm.APPLY_DA, outs[q], g)
+        div = float(torch.sqrt(torch.sum(g * g * vin)))
+        scale = float(torch.sqrt(torch.sum(a * bs[q] * bs[q]))) / h
+        assert div <= 1e-12 * scale, (q, div / scale)
+        one = op.project(bs[q], op.face_tensor(), rtol=1e-13)
+        assert float((outs[q] - one).abs().max() / one.abs().max()) <= 1e-12, q
 
 
 @pytest.fixture(scope="module")
