@@ -27,7 +27,8 @@ small grids of the block tests reach it only when it is forced).  And the
 9-cell quarter's block FGMRES with its Krylov basis in FP32 meets the
 tolerance in the FP64 residual and agrees with the FP64-basis answer; the
 128^3 block projection is divergence-free to its tolerance and equals the
-single-vector one.
+single-vector one; the 128^3 transfers satisfy R = P^T / 8 at every level;
+and the 128^3 block solves meet their tolerance in the FP64 residual.
 """
 import numpy as np
 import pytest
@@ -223,6 +224,42 @@ def test_sphere128_project_block(sphere128):
         assert div <= 1e-12 * scale, (q, div / scale)
         one = op.project(bs[q], op.face_tensor(), rtol=1e-13)
         assert float((outs[q] - one).abs().max() / one.abs().max()) <= 1e-12, q
+
+
+def test_sphere128_transfers_adjoint(sphere128):
+    """R = P^T / 8 at every level of the 128^3 hierarchy (FP64):
+    <R r, x_c> = <r, P x_c> / 8 for seeded random vectors on the active
+    faces, to 1e-12 of the product's scale."""
+    dm, op, n, h, _ = sphere128
+    gen = torch.Generator().manual_seed(43)
+    nlev = op.layout(0)["levels"]
+    for lvl in range(nlev - 1):
+        mf = torch.tensor(op.fractions(lvl)[:3].reshape(-1) > 0)
+        mc = torch.tensor(op.fractions(lvl + 1)[:3].reshape(-1) > 0)
+        r = (torch.randn(mf.numel(), dtype=torch.float64, generator=gen) * mf).cuda()
+        xc = (torch.randn(mc.numel(), dtype=torch.float64, generator=gen) * mc).cuda()
+        rc = op.restrict(r, op.face_tensor(level=lvl + 1), level=lvl)
+        px = op.prolong_add(xc, op.face_tensor(level=lvl), level=lvl)
+        lhs, rhs = float(torch.dot(rc, xc)), float(torch.dot(r, px)) / 8.0
+        scale = float(torch.linalg.norm(rc) * torch.linalg.norm(xc))
+        assert abs(lhs - rhs) <= 1e-12 * scale, (lvl, lhs, rhs)
+
+
+def test_sphere128_block_solve_residual(sphere128):
+    """The benchmark's inner solves at 128^3: three systems in lockstep in the
+    FP32-multigrid mode to 3e-11 meet the tolerance in the FP64 residual
+    recomputed by dm_residual."""
+    dm, op, n, h, _ = sphere128
+    P = op.layout(0)["P"]
+    gen = torch.Generator().manual_seed(47)
+    mask = torch.tensor(op.fractions(0)[:3].reshape(-1) > 0)
+    fs = [(torch.randn(3 * P, dtype=torch.float64, generator=gen) * mask).cuda() for _ in range(3)]
+    xs = [op.face_tensor() for _ in range(3)]
+    infos = op.solve_block(fs, xs, mode=dm.SOLVE_FGMRES_MG32, rtol=3e-11, maxit=400)
+    for q in range(3):
+        assert infos[q]["status"] == 0, infos[q]
+        r = op.residual(fs[q], xs[q], op.face_tensor())
+        assert float(torch.linalg.norm(r) / torch.linalg.norm(fs[q])) <= 4.5e-11, q
 
 
 @pytest.fixture(scope="module")
