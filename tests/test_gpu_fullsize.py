@@ -28,7 +28,8 @@ small grids of the block tests reach it only when it is forced).  And the
 tolerance in the FP64 residual and agrees with the FP64-basis answer; the
 128^3 block projection is divergence-free to its tolerance and equals the
 single-vector one; the 128^3 transfers satisfy R = P^T / 8 at every level;
-and the 128^3 block solves meet their tolerance in the FP64 residual.
+and the 128^3 block solves meet their tolerance in the FP64 residual.  At
+both sizes the FP32 V-cycle equals the FP64 one to 5e-5.
 """
 import numpy as np
 import pytest
@@ -226,6 +227,26 @@ def test_sphere128_project_block(sphere128):
         assert float((outs[q] - one).abs().max() / one.abs().max()) <= 1e-12, q
 
 
+def fp32_vcycle_gap(op, seed):
+    """Largest entry of B32 f - B64 f relative to the largest of B64 f, for a
+    seeded random f on the active faces (the FP32 V-cycle of the
+    mixed-precision form against the FP64 one)."""
+    P = op.layout(0)["P"]
+    gen = torch.Generator().manual_seed(seed)
+    mask = torch.tensor(op.fractions(0)[:3].reshape(-1) > 0)
+    f = (torch.randn(3 * P, dtype=torch.float64, generator=gen) * mask).cuda()
+    x64 = op.vcycle(f, op.face_tensor())
+    x32 = op.vcycle(f.float(), op.face_tensor(dtype=torch.float32))
+    return float((x32.double() - x64).abs().max() / x64.abs().max())
+
+
+def test_sphere128_vcycle_fp32_matches_fp64(sphere128):
+    """The FP32 V-cycle of the benchmark equals the FP64 one to FP32
+    rounding at 128^3 (5e-5, the small-grid bar against the oracle)."""
+    dm, op, n, h, _ = sphere128
+    assert fp32_vcycle_gap(op, 53) <= 5e-5
+
+
 def test_sphere128_transfers_adjoint(sphere128):
     """R = P^T / 8 at every level of the 128^3 hierarchy (FP64):
     <R r, x_c> = <r, P x_c> / 8 for seeded random vectors on the active
@@ -301,6 +322,11 @@ def test_ninecell_apply_rows(ninecell):
 def test_ninecell_vcycle_block_equals_single(ninecell):
     dm, op, n, h, _ = ninecell
     assert block_equals_single(op, 2, 32, 6) <= 1e-6
+
+
+def test_ninecell_vcycle_fp32_matches_fp64(ninecell):
+    dm, op, n, h, _ = ninecell
+    assert fp32_vcycle_gap(op, 59) <= 5e-5
 
 
 def test_empty_geometry_is_rejected():
