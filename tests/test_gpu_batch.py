@@ -7,9 +7,14 @@ at different depths), sigma = 5.  Checked:
     (same kernels and arithmetic; compared to 1e-6 of the largest value);
   * dm_batch_eigs (every member's eigensolve on its own thread, every
     preconditioner application fused) gives each member's 4 lowest
-    eigenvalues as its own solo eigensolve does (1e-10), and the 16^3
-    member's as the oracle (1e-10).
+    eigenvalues as its own solo eigensolve does (1e-10), and every member's
+    as the oracle (1e-10): the 16^3 member's against a live oracle
+    eigensolve, all four against the values that
+    tests/golden/make_batch_members.py stored from the oracle.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -65,3 +70,11 @@ def test_batch_eigs_match_solo_and_oracle(batch):
     o = ops.build(fr, (n, n, n), 1.0 / n, SIGMA)
     w_ref = oeigs.lanczos_eigs(o, 4, sigma_o=SIGMA, block=4, tol=1e-11)[0]
     assert np.max(abs(out["lam"][0] - w_ref) / w_ref) <= 1e-10
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "batch4_oracle.json")))["members"]
+    for q, g in enumerate(gold):
+        assert (g["n"], tuple(g["semi_axes"])) == (NS[q], SEMI[q])
+        ref = np.array(g["lam"])
+        err = float(np.max(abs(out["lam"][q] - ref) / ref))
+        print(f"[result] member {q} ({NS[q]}^3) max rel err vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-10, (q, err)
